@@ -1,0 +1,206 @@
+/*
+ * rsl.h -- resultants of bivariate integer polynomials on MI355X (gfx950).
+ *
+ * Computes R^(y) = res(f, g, y) in Z[x] and R^(x) = res(f, g, x) in Z[y] for
+ * f, g in Z[x, y] by the modular route of the paper's Sec. 4.1 (Collins'
+ * divide-conquer-combine scheme): reduce the coefficients modulo many 31-bit
+ * primes, evaluate at many integer points, take univariate resultants over
+ * Z_p, interpolate in x, and lift the coefficients to Z by Chinese
+ * remaindering.  Every stage after the host-side plan runs in HIP kernels on
+ * the device.  The resultant itself is the determinant of the Sylvester matrix
+ * S^(y)(f, g) of Sec. 3.1 (f rows first, highest power of y first, actual
+ * y-degrees m_y, n_y); the result is exact, bit for bit.
+ *
+ * Conventions where the paper is silent:
+ *   - either input is the zero polynomial          -> R = 0  (deg = -1)
+ *   - m_y = n_y = 0 (both constant in y)           -> R = 1
+ *   - a common factor                              -> R = 0  (not an error;
+ *     the paper assumes none, Sec. 2)
+ *   - zero rows/columns of the input arrays are trimmed: degrees are actual.
+ *
+ * Error convention: every call returns an int; RSL_OK (0) on success, a
+ * negative RSL_E* code otherwise.  rsl_strerror() maps codes to text and
+ * rsl_last_error() returns the context's last detailed message.
+ *
+ * Threading: one rsl_ctx per host thread and stream.  Server calls are
+ * thread-safe.  Inputs and outputs are host memory owned by the caller.
+ */
+#ifndef RSL_H
+#define RSL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ----------------------------------------------------------------- codes */
+#define RSL_OK 0
+#define RSL_EINVAL (-1)   /* null pointer, negative dims, limbs < 1, bad var/mode  */
+#define RSL_ERANGE (-2)   /* output buffer too small: nothing written              */
+#define RSL_ENOMEM (-3)   /* workspace or budget smaller than the footprint        */
+#define RSL_EPRIMES (-4)  /* prime table exhausted (too many bad primes)           */
+#define RSL_EDEVICE (-5)  /* HIP error: the context is poisoned, destroy it        */
+#define RSL_EAGAIN (-6)   /* server queue full, try again later                    */
+#define RSL_ETIMEDOUT (-7)/* rsl_server_wait timed out, request still in flight    */
+
+/* which variable is eliminated */
+#define RSL_Y 0 /* res(f, g, y) in Z[x] */
+#define RSL_X 1 /* res(f, g, x) in Z[y] */
+
+/* rsl_batch modes */
+#define RSL_PLAIN 0   /* one pipeline (reduce, eval+ures, interp, crt) per problem */
+#define RSL_BATCHED 1 /* all problems in one persistent launch                     */
+
+/* point policy (rsl_opts.points) */
+#define RSL_POINTS_REPLACE 0 /* bad points skipped: first D+1 good points of 0..D+s */
+#define RSL_POINTS_FORMAL 1  /* all points 0..D used (formal-degree values)          */
+
+/*
+ * A dense bivariate polynomial f = sum_{i<=dx, j<=dy} c_ij x^i y^j.
+ * coeff holds (dy+1)*(dx+1) coefficients, row-major by the power of y:
+ * coefficient c_ij starts at coeff[(j*(dx+1) + i) * limbs] and is stored as
+ * `limbs` little-endian 32-bit words in two's complement.  Zero padding
+ * (rows/columns) is allowed and trimmed.  Paper Sec. 2, Eq. (2.1).
+ */
+typedef struct {
+  int32_t dx;
+  int32_t dy;
+  int32_t limbs;
+  const uint32_t *coeff;
+} rsl_poly;
+
+/*
+ * Output: coefficient k of R (k = 0..deg) is written to
+ * coeff[k*limbs .. k*limbs+limbs-1], two's complement little-endian words.
+ * cap_deg is the highest degree the buffer holds (coeff has
+ * (cap_deg+1)*limbs words).  deg is set to the actual degree (-1 for R = 0).
+ * If R does not fit (deg > cap_deg or a coefficient needs more limbs) the
+ * call returns RSL_ERANGE, sets deg and needed_limbs, and writes no
+ * coefficient.
+ */
+typedef struct {
+  int32_t cap_deg;
+  int32_t limbs;
+  uint32_t *coeff;
+  int32_t deg;          /* out */
+  int32_t needed_limbs; /* out: limbs of the widest coefficient (signed) */
+} rsl_result;
+
+/* Sizing of one problem, computed on the host without device work. */
+typedef struct {
+  int32_t D;            /* degree bound used for interpolation (paper Sec. 3.1: deg R <= m n) */
+  int32_t bound_bits;   /* bits of the Hadamard bound B with |coeff of R| <= B */
+  int32_t n_primes;     /* number of 31-bit primes, prod p > 2B */
+  int32_t n_points;     /* evaluation points per prime: D + 1 + s */
+  int32_t out_limbs;    /* limbs that always suffice for every coefficient */
+  int32_t my, ny;       /* actual degrees in the eliminated variable */
+  int32_t bad_primes;   /* primes skipped because they divide a leading coefficient */
+  size_t footprint_bytes; /* device workspace one rsl_res call needs */
+} rsl_info;
+
+/* Per-call options (zero-initialise for the defaults). */
+typedef struct {
+  int32_t points;      /* RSL_POINTS_REPLACE (default) or RSL_POINTS_FORMAL */
+  int32_t prime_start; /* skip this many primes of the table (self-consistency tests) */
+  int32_t extra_primes;/* use this many primes beyond the bound (self-consistency tests) */
+  int32_t point_origin;/* evaluate at origin, origin+1, ... instead of 0, 1, ... */
+  int32_t extra_points;/* evaluate at this many points beyond D + s */
+  int32_t prime_limit; /* test hook: treat the prime table as having only this many entries */
+  int32_t reserved[2];
+} rsl_opts;
+
+/* Counters of the last call on a context (or of a server). */
+typedef struct {
+  int64_t problems;
+  int64_t pairs;        /* (prime, point) univariate resultants computed */
+  int64_t bad_pairs;    /* of which had a vanishing leading coefficient */
+  int64_t bad_primes;
+  int64_t slow_primes;  /* primes interpolated on a non-consecutive point set */
+  double ms_device;     /* device time of the last call (HIP events) */
+  double ms_total;      /* host wall time of the last call */
+} rsl_counters;
+
+typedef struct rsl_ctx rsl_ctx;
+
+/*
+ * Create a context on HIP device `device`.  d_workspace/ws_bytes: device
+ * memory owned by the caller (e.g. a torch uint8 tensor) used for all
+ * per-call scratch; it must stay alive until rsl_ctx_destroy.  stream: the
+ * hipStream_t all work is ordered on (NULL = the null stream).  The context
+ * also keeps its own constant tables (primes, Montgomery constants, CRT
+ * tables, factorials, Stirling numbers mod p) in device memory that it
+ * allocates and frees itself.
+ */
+int rsl_ctx_create(int device, void *d_workspace, size_t ws_bytes, void *stream, rsl_ctx **out);
+int rsl_ctx_destroy(rsl_ctx *ctx);
+
+/* Sizing only; no device work, no context needed.  var = RSL_Y or RSL_X. */
+int rsl_query(const rsl_poly *f, const rsl_poly *g, int var, rsl_info *info);
+
+/*
+ * res(f, g, var): synchronous with respect to the context stream (the result
+ * is in `out` when the call returns).  opts may be NULL.
+ */
+int rsl_res(rsl_ctx *ctx, const rsl_poly *f, const rsl_poly *g, int var, const rsl_opts *opts,
+            rsl_result *out);
+int rsl_res_y(rsl_ctx *ctx, const rsl_poly *f, const rsl_poly *g, rsl_result *out);
+int rsl_res_x(rsl_ctx *ctx, const rsl_poly *f, const rsl_poly *g, rsl_result *out);
+
+/*
+ * A batch of n independent problems (f[k], g[k], var[k]) -> out[k].
+ * mode RSL_PLAIN runs one pipeline per problem on the context stream;
+ * RSL_BATCHED plans all problems together and runs them in one persistent
+ * launch.  Both give bit-identical results.  Per-problem status codes go to
+ * status[k] (may be NULL); the call returns the first nonzero one.
+ */
+int rsl_batch(rsl_ctx *ctx, int n, const rsl_poly *f, const rsl_poly *g, const int *var,
+              rsl_result *out, int *status, int mode);
+
+/* Counters of the last rsl_res / rsl_batch on this context. */
+int rsl_last_counters(rsl_ctx *ctx, rsl_counters *c);
+
+/* ---------------------------------------------------------------- serving */
+typedef struct rsl_server rsl_server;
+
+typedef struct {
+  int64_t submitted, completed, rejected, in_flight;
+  double p50_ms, p99_ms, mean_ms; /* submit -> completion latency of completed requests */
+  double throughput;              /* completed requests per second since creation */
+  int64_t admitted_bytes_peak;    /* peak sum of footprints admitted at once */
+  int64_t launches;               /* device iterations run by the scheduler */
+  int64_t max_batch;              /* most requests that shared one device iteration */
+} rsl_stats;
+
+/*
+ * Start a server on a context (the server owns the context's stream and
+ * workspace until rsl_server_destroy).  Requests are admitted in FIFO order
+ * while slots are free and the sum of their device footprints stays within
+ * budget_bytes (<= workspace size); admitted requests run together in one
+ * batched device iteration, and requests arriving while an iteration runs
+ * join the next one (continuous batching).  max_queue bounds the host queue
+ * (RSL_EAGAIN beyond it).
+ */
+int rsl_server_create(rsl_ctx *ctx, size_t budget_bytes, int max_slots, int max_queue,
+                      rsl_server **out);
+/* Copy the inputs and enqueue; `out` must stay valid until completion. */
+int rsl_server_submit(rsl_server *s, const rsl_poly *f, const rsl_poly *g, int var,
+                      rsl_result *out, uint64_t *ticket);
+/* 1 if done (status in *status), 0 if still in flight. */
+int rsl_server_poll(rsl_server *s, uint64_t ticket, int *status);
+/* Wait up to timeout_ms (< 0: forever); returns the request status or RSL_ETIMEDOUT. */
+int rsl_server_wait(rsl_server *s, uint64_t ticket, int timeout_ms);
+int rsl_server_stats(rsl_server *s, rsl_stats *st);
+int rsl_server_destroy(rsl_server *s);
+
+/* ---------------------------------------------------------------- errors */
+const char *rsl_strerror(int code);
+const char *rsl_last_error(rsl_ctx *ctx);
+/* Library version string. */
+const char *rsl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RSL_H */

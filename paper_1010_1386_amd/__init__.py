@@ -1,0 +1,324 @@
+"""Python binding of librsl (resultants of bivariate integer polynomials on MI355X).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``librsl.so``; this module converts Python integers to and from
+the limb arrays of the C-ABI (``include/rsl.h``) and uses PyTorch solely for
+the device workspace tensor and the HIP stream.  If the native library is
+missing, importing this package raises -- there is no CPU fallback.
+
+Polynomials are 2-D arrays ``F[j][i]`` = coefficient of x^i y^j (lists of
+Python ints or numpy integer arrays).  Results are lists of Python ints,
+lowest power first, ``[]`` for the zero polynomial.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "librsl.so")
+
+if not os.path.exists(_LIBPATH):
+    raise ImportError(f"librsl.so not built ({_LIBPATH}); run `python -m paper_1010_1386_amd.build`")
+
+_lib = ctypes.CDLL(_LIBPATH)
+
+RSL_OK, RSL_EINVAL, RSL_ERANGE, RSL_ENOMEM, RSL_EPRIMES, RSL_EDEVICE, RSL_EAGAIN, RSL_ETIMEDOUT = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+RSL_Y, RSL_X = 0, 1
+RSL_PLAIN, RSL_BATCHED = 0, 1
+RSL_POINTS_REPLACE, RSL_POINTS_FORMAL = 0, 1
+
+
+class rsl_poly(ctypes.Structure):
+    _fields_ = [("dx", ctypes.c_int32), ("dy", ctypes.c_int32), ("limbs", ctypes.c_int32),
+                ("coeff", ctypes.POINTER(ctypes.c_uint32))]
+
+
+class rsl_result(ctypes.Structure):
+    _fields_ = [("cap_deg", ctypes.c_int32), ("limbs", ctypes.c_int32),
+                ("coeff", ctypes.POINTER(ctypes.c_uint32)), ("deg", ctypes.c_int32),
+                ("needed_limbs", ctypes.c_int32)]
+
+
+class rsl_info(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_int32), ("bound_bits", ctypes.c_int32), ("n_primes", ctypes.c_int32),
+                ("n_points", ctypes.c_int32), ("out_limbs", ctypes.c_int32), ("my", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("bad_primes", ctypes.c_int32), ("footprint_bytes", ctypes.c_size_t)]
+
+
+class rsl_opts(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_int32), ("prime_start", ctypes.c_int32), ("extra_primes", ctypes.c_int32),
+                ("point_origin", ctypes.c_int32), ("extra_points", ctypes.c_int32),
+                ("prime_limit", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+
+
+class rsl_counters(ctypes.Structure):
+    _fields_ = [("problems", ctypes.c_int64), ("pairs", ctypes.c_int64), ("bad_pairs", ctypes.c_int64),
+                ("bad_primes", ctypes.c_int64), ("slow_primes", ctypes.c_int64),
+                ("ms_device", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+
+class rsl_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("in_flight", ctypes.c_int64), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("throughput", ctypes.c_double),
+                ("admitted_bytes_peak", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("max_batch", ctypes.c_int64)]
+
+
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+_SIGS = {
+    "rsl_ctx_create": (ctypes.c_int, [ctypes.c_int, _vp, ctypes.c_size_t, _vp, _P(_vp)]),
+    "rsl_ctx_destroy": (ctypes.c_int, [_vp]),
+    "rsl_query": (ctypes.c_int, [_P(rsl_poly), _P(rsl_poly), ctypes.c_int, _P(rsl_info)]),
+    "rsl_res": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), ctypes.c_int, _P(rsl_opts), _P(rsl_result)]),
+    "rsl_res_y": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), _P(rsl_result)]),
+    "rsl_res_x": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), _P(rsl_result)]),
+    "rsl_batch": (ctypes.c_int, [_vp, ctypes.c_int, _P(rsl_poly), _P(rsl_poly), _P(ctypes.c_int),
+                                 _P(rsl_result), _P(ctypes.c_int), ctypes.c_int]),
+    "rsl_last_counters": (ctypes.c_int, [_vp, _P(rsl_counters)]),
+    "rsl_server_create": (ctypes.c_int, [_vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, _P(_vp)]),
+    "rsl_server_submit": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), ctypes.c_int, _P(rsl_result),
+                                         _P(ctypes.c_uint64)]),
+    "rsl_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, _P(ctypes.c_int)]),
+    "rsl_server_wait": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_int]),
+    "rsl_server_stats": (ctypes.c_int, [_vp, _P(rsl_stats)]),
+    "rsl_server_destroy": (ctypes.c_int, [_vp]),
+    "rsl_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "rsl_last_error": (ctypes.c_char_p, [_vp]),
+    "rsl_version": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+class RSLError(RuntimeError):
+    def __init__(self, code, msg=""):
+        self.code = code
+        super().__init__(f"{_lib.rsl_strerror(code).decode()} ({code}){': ' + msg if msg else ''}")
+
+
+def library_path():
+    return _LIBPATH
+
+
+def version():
+    return _lib.rsl_version().decode()
+
+
+# ------------------------------------------------------------------ marshalling
+
+
+class Poly:
+    """A bivariate polynomial packed as C-ABI limbs (keeps the buffer alive)."""
+
+    def __init__(self, F):
+        arr = F if isinstance(F, np.ndarray) else None
+        if arr is not None and arr.dtype != object and np.issubdtype(arr.dtype, np.integer):
+            a = np.ascontiguousarray(arr, dtype=np.int64)
+            if a.ndim != 2 or a.size == 0:
+                raise ValueError("polynomial must be a non-empty 2-D array")
+            self.dy, self.dx = a.shape[0] - 1, a.shape[1] - 1
+            self.limbs = 2
+            self.buf = np.ascontiguousarray(a.view(np.uint32))
+        else:
+            rows = [list(r) for r in F]
+            if not rows:
+                rows = [[0]]
+            width = max(1, max(len(r) for r in rows))
+            self.dy, self.dx = len(rows) - 1, width - 1
+            flat = [int(v) for r in rows for v in (list(r) + [0] * (width - len(r)))]
+            bits = max((v.bit_length() + 1 for v in flat), default=1)
+            if bits <= 64:
+                self.limbs = 2
+                self.buf = np.ascontiguousarray(np.array(flat, dtype=np.int64).view(np.uint32))
+            else:
+                self.limbs = (bits + 31) // 32
+                nb = 4 * self.limbs
+                raw = b"".join(v.to_bytes(nb, "little", signed=True) for v in flat)
+                self.buf = np.frombuffer(raw, dtype=np.uint32).copy()
+        self.c = rsl_poly(self.dx, self.dy, self.limbs,
+                          self.buf.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+
+
+def _as_poly(F):
+    return F if isinstance(F, Poly) else Poly(F)
+
+
+def _var_code(var):
+    if var in ("y", RSL_Y):
+        return RSL_Y
+    if var in ("x", RSL_X):
+        return RSL_X
+    raise ValueError("var must be 'y' or 'x'")
+
+
+class _Result:
+    def __init__(self, cap_deg, limbs):
+        self.buf = np.zeros(max(1, (cap_deg + 1) * limbs), dtype=np.uint32)
+        self.c = rsl_result(cap_deg, limbs, self.buf.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), 0, 0)
+
+    def value(self):
+        deg, L = self.c.deg, self.c.limbs
+        if deg < 0:
+            return []
+        w = self.buf[:(deg + 1) * L]
+        if L == 2:
+            return [int(v) for v in w.view(np.int64)]
+        raw = w.tobytes()
+        nb = 4 * L
+        return [int.from_bytes(raw[k * nb:(k + 1) * nb], "little", signed=True) for k in range(deg + 1)]
+
+
+def query(f, g, var="y"):
+    """Sizing of res(f, g, var) without device work (dict of rsl_info fields)."""
+    pf, pg = _as_poly(f), _as_poly(g)
+    info = rsl_info()
+    rc = _lib.rsl_query(ctypes.byref(pf.c), ctypes.byref(pg.c), _var_code(var), ctypes.byref(info))
+    if rc:
+        raise RSLError(rc)
+    return {name: getattr(info, name) for name, _ in rsl_info._fields_}
+
+
+def _opts(points="replace", prime_start=0, extra_primes=0, point_origin=0, extra_points=0, prime_limit=0):
+    o = rsl_opts()
+    o.points = RSL_POINTS_FORMAL if points in ("formal", RSL_POINTS_FORMAL) else RSL_POINTS_REPLACE
+    o.prime_start, o.extra_primes = prime_start, extra_primes
+    o.point_origin, o.extra_points, o.prime_limit = point_origin, extra_points, prime_limit
+    return o
+
+
+# ------------------------------------------------------------------ context
+
+
+class Context:
+    """A device context: a torch workspace tensor on ``cuda:device`` plus a HIP stream."""
+
+    def __init__(self, device=0, workspace_bytes=256 << 20, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: librsl runs only on the device")
+        self.device = device
+        self.workspace = torch.empty(workspace_bytes, dtype=torch.uint8, device=f"cuda:{device}")
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        h = _vp()
+        rc = _lib.rsl_ctx_create(device, ctypes.c_void_p(self.workspace.data_ptr()), workspace_bytes,
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc:
+            raise RSLError(rc, "rsl_ctx_create")
+        self.h = h
+        self.lock = threading.RLock()
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.rsl_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self):
+        return _lib.rsl_last_error(self.h).decode()
+
+    def counters(self):
+        c = rsl_counters()
+        _lib.rsl_last_counters(self.h, ctypes.byref(c))
+        return {name: getattr(c, name) for name, _ in rsl_counters._fields_}
+
+    def _check(self, rc, what):
+        if rc:
+            raise RSLError(rc, f"{what}: {self.last_error()}")
+
+    def res(self, f, g, var="y", **opts):
+        """res(f, g, var) as a list of Python ints (lowest power first)."""
+        pf, pg = _as_poly(f), _as_poly(g)
+        v = _var_code(var)
+        info = rsl_info()
+        rc = _lib.rsl_query(ctypes.byref(pf.c), ctypes.byref(pg.c), v, ctypes.byref(info))
+        self._check(rc, "rsl_query")
+        o = _opts(**opts)
+        lim = info.out_limbs + (1 if o.extra_primes else 0) + o.extra_primes
+        out = _Result(max(info.D, 0), max(1, lim))
+        with self.lock:
+            rc = _lib.rsl_res(self.h, ctypes.byref(pf.c), ctypes.byref(pg.c), v, ctypes.byref(o),
+                              ctypes.byref(out.c))
+        self._check(rc, "rsl_res")
+        return out.value()
+
+    def res_y(self, f, g):
+        return self.res(f, g, "y")
+
+    def res_x(self, f, g):
+        return self.res(f, g, "x")
+
+    def batch(self, problems, mode="batched"):
+        """problems: list of (f, g, var); returns a list of results (lists of ints)."""
+        n = len(problems)
+        polys, outs = [], []
+        fa = (rsl_poly * max(n, 1))()
+        ga = (rsl_poly * max(n, 1))()
+        va = (ctypes.c_int * max(n, 1))()
+        ra = (rsl_result * max(n, 1))()
+        st = (ctypes.c_int * max(n, 1))()
+        for k, (f, g, var) in enumerate(problems):
+            pf, pg = _as_poly(f), _as_poly(g)
+            v = _var_code(var)
+            info = rsl_info()
+            self._check(_lib.rsl_query(ctypes.byref(pf.c), ctypes.byref(pg.c), v, ctypes.byref(info)),
+                        "rsl_query")
+            r = _Result(max(info.D, 0), info.out_limbs)
+            polys.append((pf, pg))
+            outs.append(r)
+            fa[k], ga[k], va[k], ra[k] = pf.c, pg.c, v, r.c
+        code = RSL_BATCHED if mode in ("batched", RSL_BATCHED) else RSL_PLAIN
+        with self.lock:
+            rc = _lib.rsl_batch(self.h, n, fa, ga, va, ra, st, code)
+        self._check(rc, "rsl_batch")
+        res = []
+        for k in range(n):
+            outs[k].c = ra[k]
+            res.append(outs[k].value())
+        return res
+
+
+_default = None
+_default_lock = threading.Lock()
+
+
+def default_context():
+    global _default
+    with _default_lock:
+        if _default is None:
+            _default = Context()
+        return _default
+
+
+def res(f, g, var="y", **opts):
+    return default_context().res(f, g, var, **opts)
+
+
+def res_y(f, g):
+    return res(f, g, "y")
+
+
+def res_x(f, g):
+    return res(f, g, "x")
+
+
+def batch(problems, mode="batched"):
+    return default_context().batch(problems, mode)
+
+
+from .server import Server  # noqa: E402,F401

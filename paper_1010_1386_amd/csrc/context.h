@@ -1,0 +1,86 @@
+// Context state shared by the C-ABI entry points, the batch planner and the server.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/rsl.h"
+#include "device.h"
+#include "plan.h"
+
+struct rsl_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint8_t* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool poisoned = false;
+  std::string err;
+
+  // constant tables (device), indexed by global prime index
+  int npcap = 0, kcap = -1, scap = -1;
+  rsl::PrimeConst* d_pc = nullptr;
+  uint32_t* d_fact = nullptr;
+  uint32_t* d_ifact = nullptr;
+  uint32_t* d_stir = nullptr;
+  int64_t sstride = 0;
+  int kstride = 0;
+  // canonical CRT tables for primes 0..npcap-1
+  uint32_t* d_Tg = nullptr;
+  uint32_t* d_invM = nullptr;
+  uint32_t* d_Plimb = nullptr;
+  int LPg = 0;
+
+  // pinned host staging
+  uint8_t* h_up = nullptr;
+  size_t h_up_bytes = 0;
+  uint8_t* h_down = nullptr;
+  size_t h_down_bytes = 0;
+
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  rsl_counters last{};
+  std::recursive_mutex mu;
+};
+
+namespace rsl {
+
+// Set the context error message and return the code.
+int fail(rsl_ctx* ctx, int code, const std::string& msg);
+// Check a HIP status; on error poison the context.
+int hip_check(rsl_ctx* ctx, hipError_t e, const char* what);
+
+// Make sure the constant tables cover global prime indices < np, factorials up
+// to kneed and Stirling rows up to sneed.
+int ensure_tables(rsl_ctx* ctx, int np, int kneed, int sneed);
+DevTables tables_of(const rsl_ctx* ctx);
+
+// Grow the pinned staging buffers.
+int ensure_staging(rsl_ctx* ctx, size_t up, size_t down);
+
+// Device layout of one planned problem inside a workspace region.
+struct Layout {
+  size_t up_off = 0, up_bytes = 0;     // uploaded inputs (coefficients, tables, zeroed status)
+  size_t resid = 0, zval = 0, zbad = 0, aconv = 0, cres = 0;
+  size_t out = 0, out_bytes = 0;       // output limbs
+  size_t status = 0, status_bytes = 0;
+  size_t total = 0;
+  // offsets inside the upload blob
+  size_t u_coeff = 0, u_rdeg = 0, u_pidx = 0, u_Hm = 0, u_NH = 0, u_Tg = 0, u_invM = 0, u_Plimb = 0;
+  size_t u_status = 0;
+  int L_in = 1;
+};
+
+Layout layout_of(const Plan& P);
+// Fill the upload blob (host) for a plan laid out at device address `base`.
+void fill_upload(const Plan& P, const Layout& L, uint8_t* blob);
+// Device problem descriptor for a plan laid out at device address `base`.
+DevProblem dev_problem(const rsl_ctx* ctx, const Plan& P, const Layout& L, uint8_t* base);
+// Decode the CRT limbs of a problem into the caller's result.
+int decode_result(const Plan& P, const uint32_t* limbs, rsl_result* out);
+
+double now_ms();
+
+}  // namespace rsl

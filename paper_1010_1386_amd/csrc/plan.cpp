@@ -1,0 +1,272 @@
+// Host-side planning (see plan.h).
+#include "plan.h"
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+
+namespace rsl {
+
+namespace {
+
+uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t m) {
+  return static_cast<uint64_t>((static_cast<unsigned __int128>(a) * b) % m);
+}
+uint64_t powmod64(uint64_t a, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  a %= m;
+  while (e) {
+    if (e & 1) r = mulmod64(r, a, m);
+    a = mulmod64(a, a, m);
+    e >>= 1;
+  }
+  return r;
+}
+
+std::mutex g_prime_mu;
+std::vector<uint32_t> g_primes;
+uint32_t g_next_candidate = 0x7FFFFFFFu;  // 2^31 - 1
+
+constexpr size_t kMaxPrimes = 1u << 16;
+
+}  // namespace
+
+// Deterministic Miller-Rabin for n < 4,759,123,141 with bases 2, 7, 61.
+bool is_prime_u32(uint32_t n) {
+  if (n < 2) return false;
+  for (uint32_t q : {2u, 3u, 5u, 7u, 11u, 13u, 17u, 19u, 23u, 29u, 31u, 37u, 41u, 43u, 47u, 53u, 59u, 61u})
+    if (n % q == 0) return n == q;
+  uint32_t d = n - 1;
+  int s = 0;
+  while ((d & 1u) == 0) { d >>= 1; ++s; }
+  for (uint32_t a : {2u, 7u, 61u}) {
+    uint64_t x = powmod64(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int r = 1; r < s; ++r) {
+      x = mulmod64(x, x, n);
+      if (x == n - 1) { comp = false; break; }
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+const std::vector<uint32_t>& prime_table(size_t at_least) {
+  std::lock_guard<std::mutex> lk(g_prime_mu);
+  at_least = std::min(at_least, kMaxPrimes);
+  while (g_primes.size() < at_least) {
+    uint32_t c = g_next_candidate;
+    g_next_candidate -= 2;
+    if (is_prime_u32(c)) g_primes.push_back(c);
+  }
+  return g_primes;
+}
+
+int make_view(const rsl_poly* f, int var, View* v, std::string* err) {
+  if (!f || f->dx < 0 || f->dy < 0 || f->limbs < 1 || f->limbs > 4096) {
+    *err = "invalid polynomial descriptor (null, negative degree or limbs < 1)";
+    return RSL_EINVAL;
+  }
+  const int64_t ncoef = static_cast<int64_t>(f->dx + 1) * (f->dy + 1);
+  if (ncoef > (int64_t(1) << 26)) {
+    *err = "polynomial too large";
+    return RSL_EINVAL;
+  }
+  if (!f->coeff) {
+    *err = "null coefficient pointer";
+    return RSL_EINVAL;
+  }
+  const int L = f->limbs;
+  // In the eliminated variable's view, "y" is the eliminated variable.
+  const int Ydim = (var == RSL_Y) ? f->dy : f->dx;
+  const int Xdim = (var == RSL_Y) ? f->dx : f->dy;
+  auto at = [&](int j, int i) -> const uint32_t* {  // coefficient of X^i Y^j
+    int yi = (var == RSL_Y) ? j : i;   // power of the original y
+    int xi = (var == RSL_Y) ? i : j;   // power of the original x
+    return f->coeff + (static_cast<int64_t>(yi) * (f->dx + 1) + xi) * L;
+  };
+  auto nonzero = [&](const uint32_t* w) {
+    for (int l = 0; l < L; ++l)
+      if (w[l]) return true;
+    return false;
+  };
+  v->L = L;
+  v->dy = -1;
+  v->dx = -1;
+  v->tdeg = -1;
+  std::vector<int> rdeg(Ydim + 1, -1);
+  for (int j = 0; j <= Ydim; ++j)
+    for (int i = 0; i <= Xdim; ++i)
+      if (nonzero(at(j, i))) {
+        rdeg[j] = i;
+        v->dy = j;
+        v->dx = std::max(v->dx, i);
+        v->tdeg = std::max(v->tdeg, i + j);
+      }
+  if (v->dy < 0) {
+    v->rdeg.clear();
+    v->c.clear();
+    return RSL_OK;
+  }
+  rdeg.resize(v->dy + 1);
+  v->rdeg = rdeg;
+  const int row = v->dx + 1;
+  v->c.assign(static_cast<size_t>(v->dy + 1) * row * L, 0u);
+  v->absv.assign(static_cast<size_t>(v->dy + 1) * row, BigU());
+  v->neg.assign(static_cast<size_t>(v->dy + 1) * row, 0);
+  for (int j = 0; j <= v->dy; ++j)
+    for (int i = 0; i <= v->rdeg[j]; ++i) {
+      const uint32_t* w = at(j, i);
+      size_t idx = static_cast<size_t>(j) * row + i;
+      std::memcpy(&v->c[idx * L], w, sizeof(uint32_t) * L);
+      bool ng = false;
+      v->absv[idx] = abs_limbs(w, L, &ng);
+      v->neg[idx] = ng;
+    }
+  return RSL_OK;
+}
+
+void crt_tables(const std::vector<uint32_t>& primes, int LP, std::vector<uint32_t>* Tg,
+                std::vector<uint32_t>* invM, std::vector<uint32_t>* Plimb) {
+  const int np = static_cast<int>(primes.size());
+  Tg->assign(static_cast<size_t>(np) * np, 0u);
+  invM->assign(np, 0u);
+  Plimb->assign(static_cast<size_t>(np) * LP, 0u);
+  std::vector<uint64_t> run(np, 1);  // prod_{l<j} p_l mod p_i
+  BigU P(1);
+  for (int j = 0; j < np; ++j) {
+    const uint32_t pj = primes[j];
+    for (int i = 0; i < np; ++i) {
+      if (i > j) (*Tg)[static_cast<size_t>(j) * np + i] =
+          static_cast<uint32_t>(((run[i] % primes[i]) << 32) % primes[i]);  // Montgomery form
+    }
+    // invM[j] = (prod_{l<j} p_l)^{-1} mod p_j in Montgomery form
+    uint64_t inv = powmod64(run[j] % pj, pj - 2, pj);
+    (*invM)[j] = static_cast<uint32_t>((inv << 32) % pj);
+    std::vector<uint32_t> lim = P.limbs(LP);
+    std::copy(lim.begin(), lim.end(), Plimb->begin() + static_cast<size_t>(j) * LP);
+    for (int i = 0; i < np; ++i) run[i] = (run[i] * (pj % primes[i])) % primes[i];
+    P = BigU::mul_small(P, pj);
+  }
+}
+
+int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opts, Plan* P,
+              std::string* err) {
+  if (var != RSL_Y && var != RSL_X) {
+    *err = "var must be RSL_Y or RSL_X";
+    return RSL_EINVAL;
+  }
+  rsl_opts o{};
+  if (opts) o = *opts;
+  if (o.points != RSL_POINTS_REPLACE && o.points != RSL_POINTS_FORMAL) {
+    *err = "opts.points must be RSL_POINTS_REPLACE or RSL_POINTS_FORMAL";
+    return RSL_EINVAL;
+  }
+  if (o.prime_start < 0 || o.extra_primes < 0 || o.extra_points < 0 || o.point_origin < 0 ||
+      o.point_origin > (1 << 24) || o.prime_limit < 0) {
+    *err = "invalid options";
+    return RSL_EINVAL;
+  }
+  int rc = make_view(f, var, &P->f, err);
+  if (rc) return rc;
+  rc = make_view(g, var, &P->g, err);
+  if (rc) return rc;
+  P->zero = (P->f.dy < 0 || P->g.dy < 0);
+  P->formal = o.points;
+  P->origin = o.point_origin;
+  if (P->zero) return RSL_OK;
+
+  const View &F = P->f, &G = P->g;
+  const int my = F.dy, ny = G.dy, mx = F.dx, nx = G.dx, m = F.tdeg, n = G.tdeg;
+  P->my = my;
+  P->ny = ny;
+  int64_t d1 = static_cast<int64_t>(ny) * mx + static_cast<int64_t>(my) * nx;
+  int64_t d2 = static_cast<int64_t>(ny) * m + static_cast<int64_t>(my) * n - static_cast<int64_t>(my) * ny;
+  int64_t D = std::min(d1, d2);
+  if (D > (1 << 20)) {
+    *err = "degree bound too large";
+    return RSL_EINVAL;
+  }
+  P->D = static_cast<int>(D);
+  P->s = F.rdeg[my] + G.rdeg[ny];
+  P->E = P->D + P->s + o.extra_points;
+
+  // Hadamard bound: B^2 = (sum_j ||f_j||_1^2)^{n_y} (sum_j ||g_j||_1^2)^{m_y}
+  auto row_sq_sum = [](const View& V) {
+    BigU S;
+    const int row = V.dx + 1;
+    for (int j = 0; j <= V.dy; ++j) {
+      BigU l1;
+      for (int i = 0; i <= V.rdeg[j]; ++i) l1 = BigU::add(l1, V.absv[static_cast<size_t>(j) * row + i]);
+      S = BigU::add(S, BigU::mul(l1, l1));
+    }
+    return S;
+  };
+  BigU B2 = BigU::mul(BigU::pow(row_sq_sum(F), ny), BigU::pow(row_sq_sum(G), my));
+  P->bound_bits = (B2.bitlen() + 1) / 2;
+  BigU fourB2 = BigU::mul_small(B2, 4);
+
+  // primes: largest first, skipping bad primes (p | every coefficient of lc_y f or lc_y g)
+  auto lc_vanishes = [](const View& V, uint32_t p) {
+    const int row = V.dx + 1;
+    for (int i = 0; i <= V.rdeg[V.dy]; ++i) {
+      size_t idx = static_cast<size_t>(V.dy) * row + i;
+      if (V.absv[idx].mod_small(p) != 0) return false;
+    }
+    return true;
+  };
+  const size_t limit = o.prime_limit ? static_cast<size_t>(o.prime_limit) : kMaxPrimes;
+  BigU M(1);
+  P->pidx.clear();
+  P->bad_primes = 0;
+  int extra_left = o.extra_primes;
+  bool enough = false;
+  for (size_t k = static_cast<size_t>(o.prime_start);; ++k) {
+    if (k >= limit) {
+      *err = "prime table exhausted";
+      return RSL_EPRIMES;
+    }
+    const std::vector<uint32_t>& tab = prime_table(k + 1);
+    if (k >= tab.size()) {
+      *err = "prime table exhausted";
+      return RSL_EPRIMES;
+    }
+    uint32_t p = tab[k];
+    if (lc_vanishes(F, p) || lc_vanishes(G, p)) {
+      ++P->bad_primes;
+      continue;
+    }
+    P->pidx.push_back(static_cast<int>(k));
+    M = BigU::mul_small(M, p);
+    if (!enough) enough = BigU::cmp(BigU::mul(M, M), fourB2) > 0;
+    if (enough) {
+      if (extra_left == 0) break;
+      --extra_left;
+    }
+  }
+  P->np = static_cast<int>(P->pidx.size());
+  P->canonical = true;
+  for (int i = 0; i < P->np; ++i)
+    if (P->pidx[i] != i) P->canonical = false;
+
+  P->L_out = std::max(1, (M.bitlen() + 31) / 32);
+  BigU H = M.half();  // (M - 1) / 2, M odd
+  const std::vector<uint32_t>& tab = prime_table(0);
+  std::vector<uint32_t> primes(P->np);
+  for (int i = 0; i < P->np; ++i) primes[i] = tab[P->pidx[i]];
+  P->Hm.resize(P->np);
+  for (int i = 0; i < P->np; ++i) P->Hm[i] = H.mod_small(primes[i]);
+  P->NH = H.neg_limbs(P->L_out);
+  if (!P->canonical) crt_tables(primes, P->L_out, &P->Tg, &P->invM, &P->Plimb);
+  else { P->Tg.clear(); P->invM.clear(); P->Plimb.clear(); }
+
+  // residue tile layout
+  P->rowf = F.dx + 1;
+  P->rowg = G.dx + 1;
+  P->goff = (my + 1) * P->rowf;
+  P->CS = (P->goff + (ny + 1) * P->rowg + 3) & ~3;
+  return RSL_OK;
+}
+
+}  // namespace rsl

@@ -1,0 +1,71 @@
+// Host-side planning of one resultant problem: trimmed view in the
+// eliminated variable, degree bound, Hadamard bound, prime selection with
+// the bad-prime screen, evaluation points, CRT constants and the device
+// footprint.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rsl.h"
+#include "bigint.h"
+#include "modarith.h"
+
+namespace rsl {
+
+// Descending 31-bit primes below 2^31 (index 0 = largest); grows on demand.
+const std::vector<uint32_t>& prime_table(size_t at_least);
+bool is_prime_u32(uint32_t n);
+
+// One input polynomial viewed in the eliminated variable ("y"): rows j are the
+// coefficients of y^j, each a polynomial in the other variable ("x").
+struct View {
+  int dy = -1;              // actual degree in y (-1: zero polynomial)
+  int dx = -1;              // max actual degree in x over all rows
+  int tdeg = -1;            // total degree
+  int L = 1;                // limbs per coefficient
+  std::vector<int> rdeg;    // per-row x-degree, -1 for a zero row
+  std::vector<uint32_t> c;  // rows 0..dy, cols 0..dx, L limbs each (two's complement)
+  std::vector<BigU> absv;   // |coefficient|, same order (planning only)
+  std::vector<uint8_t> neg;
+};
+
+int make_view(const rsl_poly* f, int var, View* v, std::string* err);
+
+struct Plan {
+  View f, g;
+  bool zero = false;        // R = 0 by convention (a zero input)
+  int my = 0, ny = 0;       // formal degrees used on the device
+  int D = 0;                // degree bound
+  int s = 0;                // spare points: deg lc_y f + deg lc_y g
+  int E = 0;                // points 0..E are evaluated (E = D + s + extra)
+  int origin = 0;           // first evaluation point
+  int formal = 0;           // RSL_POINTS_FORMAL
+  int np = 0;               // primes used
+  std::vector<int> pidx;    // indices into prime_table()
+  bool canonical = true;    // pidx == 0..np-1 (global CRT tables apply)
+  int bad_primes = 0;
+  int bound_bits = 0;
+  int L_out = 1;            // CRT output limbs (two's complement)
+  std::vector<uint32_t> Hm; // (M-1)/2 mod p_i
+  std::vector<uint32_t> NH; // 2^(32 L_out) - (M-1)/2, L_out limbs
+  // per-plan CRT tables (only when !canonical)
+  std::vector<uint32_t> Tg, invM, Plimb;
+  // device layout
+  int rowf = 0, rowg = 0;   // row strides (dx + 1) of the residue tiles
+  int CS = 0;               // residue words per prime (f tile + g tile, padded)
+  int goff = 0;             // offset of the g tile inside a prime's residues
+  size_t footprint = 0;
+};
+
+int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opts, Plan* P,
+              std::string* err);
+
+// CRT tables for an ordered prime list (Garner constants and prefix products).
+//   Tg[j*np + i] = (prod_{l<j} p_l mod p_i) R mod p_i          (j < i)
+//   invM[i]      = (prod_{l<i} p_l)^{-1} R mod p_i
+//   Plimb[j*LP + t] = limb t of prod_{l<j} p_l
+void crt_tables(const std::vector<uint32_t>& primes, int LP, std::vector<uint32_t>* Tg,
+                std::vector<uint32_t>* invM, std::vector<uint32_t>* Plimb);
+
+}  // namespace rsl

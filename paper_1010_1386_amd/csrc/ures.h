@@ -1,0 +1,137 @@
+// Per-lane evaluation and univariate resultant over Z_p (host + device).
+//
+// One lane owns one (prime, point) pair.  Its two polynomials A(y) = f(x_i, y)
+// and B(y) = g(x_i, y) live in two columns of a scratch array (LDS on the
+// device, a plain array on the host) with a fixed element stride, so that the
+// same code runs in the kernel and in the host-side self-test.
+//
+// What is computed: the determinant of the Sylvester matrix of A and B with
+// the FORMAL degrees m = m_y, n = n_y, i.e. the image of R^(y)(x_i) mod p
+// (paper Sec. 3.1 and Sec. 4.1: the evaluation homomorphism commutes with the
+// determinant).  Leading coefficients that vanish at x_i are handled by the
+// formal-degree identities
+//   Res_{m,n}(A,B) = (-1)^{n(m-a)} lc(B)^{m-a} Res_{a,n}(A,B)   (deg A = a < m)
+//   Res_{m,n}(A,B) = lc(A)^{n-b} Res_{m,b}(A,B)                 (deg B = b < n)
+// and the value is 0 when both vanish.
+//
+// The Euclidean remainder sequence is computed division-free: each division
+// step replaces A by the pseudo-remainder L^k A mod B (L = lc(B),
+// k = deg A - deg B + 1), formed by k elimination passes
+//   A <- L A - lc(A) y^(deg A - deg B) B .
+// With R = A mod B of degree c, Res(A,B) = (-1)^{ab} L^{a-c} Res(B,R) and
+// Res(B, L^k R) = L^{k b} Res(B, R); the scale factors are kept as a
+// numerator and a denominator so that only one inversion is needed at the end.
+// The denominator prod_t (L_t^{k_t})^{b_t} is accumulated as
+// prod_t U_t^{b_t - b_{t+1}} with U_t = prod_{i<=t} L_i^{k_i}, which costs two
+// multiplies per step in the usual case b_{t+1} = b_t - 1.  In the usual case
+// deg A = deg B + 1 the two passes are fused into one:
+//   R~[j] = L^2 A[j] - L lc(A) B[j-1] - lc(A~) B[j],  lc(A~) = L A[b] - lc(A) B[b-1].
+#pragma once
+#include "modarith.h"
+
+namespace rsl {
+
+template <int STRIDE>
+struct Column {
+  uint32_t* base;
+  RSL_HD uint32_t& operator[](int j) const { return base[j * STRIDE]; }
+};
+
+// Horner evaluation of nrows polynomials in x (Montgomery x~ = x R) whose
+// coefficients are stored as c R^2 mod p ("double" Montgomery form), so that
+// one REDC per step gives acc <- acc x + c in Montgomery form:
+//   REDC(acc~ x~ + c R^2) = (acc x + c) R.
+template <class Col>
+RSL_HD void eval_rows(Col out, const uint32_t* coeff, int nrows, int rowstride,
+                      const int* rdeg, uint32_t xt, uint32_t p, uint32_t pinv) {
+  for (int j = 0; j < nrows; ++j) {
+    const uint32_t* c = coeff + j * rowstride;
+    uint32_t acc = 0;
+    for (int i = rdeg[j]; i >= 0; --i)
+      acc = redc(static_cast<uint64_t>(acc) * xt + c[i], p, pinv);
+    out[j] = acc;
+  }
+}
+
+// Resultant with formal degrees (m, n) of the polynomials in columns A, B
+// (Montgomery form; both columns are overwritten).  Returns the result in
+// Montgomery form.  *bad is set when lc_y f(x_i) or lc_y g(x_i) vanishes.
+template <class Col>
+RSL_HD uint32_t ures_formal(Col A, Col B, int m, int n, const PrimeConst& pc, bool* bad) {
+  const uint32_t p = pc.p, pinv = pc.pinv, one = pc.r1;
+  *bad = (A[m] == 0u) || (B[n] == 0u);
+  if (n == 0) return mpow(B[0], static_cast<uint32_t>(m), one, p, pinv);
+  if (m == 0) return mpow(A[0], static_cast<uint32_t>(n), one, p, pinv);
+  int a = m;
+  while (a >= 0 && A[a] == 0u) --a;
+  int b = n;
+  while (b >= 0 && B[b] == 0u) --b;
+  if (a < 0 || b < 0 || (a < m && b < n)) return 0u;
+  uint32_t num = one, den = one, U = one;
+  uint32_t neg = 0;
+  if (a < m) {
+    num = mpow(B[b], static_cast<uint32_t>(m - a), one, p, pinv);
+    neg ^= static_cast<uint32_t>(n * (m - a)) & 1u;
+  }
+  if (b < n) num = mpow(A[a], static_cast<uint32_t>(n - b), one, p, pinv);
+
+  for (;;) {
+    if (b == 0) {  // B a nonzero constant: Res(A, B) = B^a
+      num = mmul(num, mpow(B[0], static_cast<uint32_t>(a), one, p, pinv), p, pinv);
+      break;
+    }
+    if (a == 0) {  // A a nonzero constant: Res(A, B) = A^b
+      num = mmul(num, mpow(A[0], static_cast<uint32_t>(b), one, p, pinv), p, pinv);
+      break;
+    }
+    if (a < b) {  // Res(A, B) = (-1)^{ab} Res(B, A)
+      Col t = A; A = B; B = t;
+      int ti = a; a = b; b = ti;
+      neg ^= static_cast<uint32_t>(a * b) & 1u;
+      continue;
+    }
+    const uint32_t L = B[b];
+    const int k = a - b + 1;
+    uint32_t y;  // L^k
+    if (k == 2) {
+      const uint32_t lcA = A[a];
+      const uint32_t lcAt = mmulsub(L, A[b], lcA, B[b - 1], p, pinv);
+      const uint32_t alpha = mmul(L, L, p, pinv);
+      const uint32_t beta = mneg(mmul(L, lcA, p, pinv), p);
+      const uint32_t gamma = mneg(lcAt, p);
+      uint32_t prevB = 0u;
+      for (int j = 0; j < b; ++j) {
+        const uint32_t bj = B[j];
+        A[j] = mmad3(alpha, A[j], beta, prevB, gamma, bj, p, pinv);
+        prevB = bj;
+      }
+      y = alpha;
+    } else {
+      for (int d = a; d >= b; --d) {
+        const uint32_t lc = A[d];
+        const int sh = d - b;
+        for (int j = 0; j < d; ++j) {
+          const uint32_t bj = (j >= sh) ? B[j - sh] : 0u;
+          A[j] = mmulsub(L, A[j], lc, bj, p, pinv);
+        }
+      }
+      y = mpow(L, static_cast<uint32_t>(k), one, p, pinv);
+    }
+    int c = b - 1;
+    while (c >= 0 && A[c] == 0u) --c;
+    if (c < 0) return 0u;  // zero remainder with deg B >= 1: common factor at x_i
+    neg ^= static_cast<uint32_t>(a * b) & 1u;
+    const int delta = b - c;
+    const int enum_ = k - 1 + delta;  // exponent of L in the numerator
+    num = mmul(num, (enum_ == k) ? y : mpow(L, static_cast<uint32_t>(enum_), one, p, pinv), p, pinv);
+    U = mmul(U, y, p, pinv);
+    den = mmul(den, (delta == 1) ? U : mpow(U, static_cast<uint32_t>(delta), one, p, pinv), p, pinv);
+    Col t = A; A = B; B = t;  // (A, B) <- (B, R~)
+    a = b;
+    b = c;
+  }
+  uint32_t r = mmul(num, minv(den, one, p, pinv), p, pinv);
+  return neg ? mneg(r, p) : r;
+}
+
+}  // namespace rsl

@@ -1,0 +1,131 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle, bit for bit."""
+
+import json
+import os
+
+import pytest
+
+import oracle
+import workloads
+from workloads import rng_for, small_random, dense_total, sparse_total
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1010_1386_amd as rsl
+    c = rsl.Context(device=0, workspace_bytes=512 << 20)
+    yield c
+    c.close()
+
+
+def _golden(cfg):
+    with open(os.path.join(GOLDEN, f"cfg{cfg}.json")) as fh:
+        return {r["name"]: r for r in json.load(fh)["records"]}
+
+
+def test_config1_res_y_and_res_x_match_golden(ctx):
+    f, g = workloads.config1()
+    gold = _golden(1)
+    for var in "yx":
+        got = ctx.res(f, g, var)
+        want = [int(c) for c in gold[f"cfg1_{var}"]["coeffs"]]
+        assert got == want, var
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_small_random_vs_oracle(ctx, seed):
+    rng = rng_for(700, seed)
+    F = small_random(rng, int(rng.integers(0, 6)), int(rng.integers(0, 6)), int(rng.integers(2, 40)),
+                     density=float(rng.choice([1.0, 0.6])))
+    G = small_random(rng, int(rng.integers(0, 6)), int(rng.integers(0, 6)), int(rng.integers(2, 40)),
+                     density=float(rng.choice([1.0, 0.6])))
+    for var in "yx":
+        assert ctx.res(F, G, var) == oracle.res(F, G, var), (seed, var)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_total_degree_dense_and_sparse(ctx, seed):
+    rng = rng_for(701, seed)
+    d1, d2 = int(rng.integers(3, 9)), int(rng.integers(3, 9))
+    b = int(rng.integers(8, 64))
+    F = dense_total(rng, d1, b, force_top=False) if seed % 2 else sparse_total(rng, d1, b)
+    G = dense_total(rng, d2, b, force_top=False) if seed % 2 else sparse_total(rng, d2, b)
+    for var in "yx":
+        assert ctx.res(F, G, var) == oracle.res(F, G, var), (seed, var)
+
+
+def test_degenerate_inputs(ctx):
+    g = [[1, 2], [3], [0, 5]]
+    assert ctx.res([[0]], g) == []
+    assert ctx.res([[7]], g) == [49]
+    assert ctx.res(g, [[-2]]) == [4]
+    assert ctx.res([[3]], [[5, 1]]) == [1]
+    # common factor (y - x): R = 0
+    f = [[0, -1], [1]]                        # y - x
+    h = [[0, 0, -2], [1, 2], [0, 1]]          # arbitrary
+    fh = oracle.bivar_mul(f, h)
+    gh = oracle.bivar_mul(f, [[1, 1], [1]])
+    assert ctx.res(fh, gh) == []
+    # leading y-coefficient vanishing at integer points: x (x - 3) y^2 + ...
+    F = [[1, 2, 3], [4, 5], [0, -3, 1]]
+    G = [[2, -1], [0, 1, 1], [7, 0, 0, 1]]
+    for var in "yx":
+        assert ctx.res(F, G, var) == oracle.res(F, G, var)
+
+
+def test_planted_bad_point_every_prime(ctx):
+    """lc_y f = (x - a): point a is bad for every prime and must be replaced."""
+    for a in (0, 1, 5):
+        F = [[3, 1, -2], [1, 4], [-a, 1]]
+        G = [[5, -1], [2, 2, 1], [1]]
+        R = oracle.res(F, G)
+        assert ctx.res(F, G) == R
+        assert ctx.res(F, G, points="formal") == R
+        c = ctx.counters()
+        assert c["bad_pairs"] >= 1
+
+
+def test_linear_substitution_closed_form(ctx):
+    rng = rng_for(702, 0)
+    a = [3, -2, 1]
+    f = [[-c for c in a], [1]]
+    G = small_random(rng, 4, 3, 20)
+    assert ctx.res(f, G) == oracle.pcompose_y(G, a)
+
+
+def test_self_consistency_primes_and_points(ctx):
+    """The final R must not depend on which primes or points were used."""
+    rng = rng_for(703, 0)
+    F = dense_total(rng, 7, 30)
+    G = dense_total(rng, 6, 30)
+    base = ctx.res(F, G)
+    assert base == oracle.res(F, G)
+    assert ctx.res(F, G, prime_start=5) == base
+    assert ctx.res(F, G, extra_primes=3) == base
+    assert ctx.res(F, G, point_origin=1000) == base
+    assert ctx.res(F, G, extra_points=17) == base
+    assert ctx.res(F, G, points="formal") == base
+
+
+def test_bad_prime_is_skipped(ctx):
+    """lc_y f = p_0 * c: the largest prime divides the leading coefficient."""
+    import paper_1010_1386_amd as rsl
+    p0 = 2147483647  # largest prime below 2^31, first in the table
+    F = [[1, 2, 3], [5, 0, 1], [p0 * 3, p0 * 2]]
+    G = [[2, 1], [1, 1, 1], [3]]
+    info = rsl.query(F, G, "y")
+    assert info["bad_primes"] >= 1
+    assert ctx.res(F, G) == oracle.res(F, G)
+
+
+def test_prime_table_exhaustion_is_reported(ctx):
+    import paper_1010_1386_amd as rsl
+    F = dense_total(rng_for(704, 0), 5, 20)
+    G = dense_total(rng_for(704, 1), 5, 20)
+    with pytest.raises(rsl.RSLError) as ei:
+        ctx.res(F, G, prime_limit=2)
+    assert ei.value.code == rsl.RSL_EPRIMES

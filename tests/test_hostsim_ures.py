@@ -1,0 +1,137 @@
+"""CPU check of the kernels' per-lane arithmetic (host build) against the oracle.
+
+The device code for evaluation and the univariate resultant over Z_p is plain
+__host__ __device__ C++ (csrc/ures.h, csrc/modarith.h).  tests/hostsim
+compiles it for the host; here it is compared with the oracle's Gaussian
+elimination of the formal-degree Sylvester matrix mod p on random and
+degenerate inputs (vanishing leading coefficients, zero polynomials, common
+factors, degree drops in the remainder sequence).
+"""
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import det_mod, poly_eval_mod
+from workloads import rng_for
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "hostsim", "libhostsim.so")
+SRC = os.path.join(HERE, "hostsim", "hostsim.cpp")
+PRIMES = [2147483647, 2147483629, 2147483587, 1073741827]
+
+
+@pytest.fixture(scope="module")
+def hs():
+    if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
+            os.path.getmtime(SRC),
+            os.path.getmtime(os.path.join(HERE, "..", "paper_1010_1386_amd", "csrc", "ures.h")),
+            os.path.getmtime(os.path.join(HERE, "..", "paper_1010_1386_amd", "csrc", "modarith.h"))):
+        subprocess.check_call(["hipcc", "-O2", "-fPIC", "-shared", "-o", LIB, SRC])
+    lib = ctypes.CDLL(LIB)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    lib.hs_ures.argtypes = [ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p, u32p, u32p,
+                            ctypes.POINTER(ctypes.c_int)]
+    lib.hs_eval.argtypes = [ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p,
+                            ctypes.POINTER(ctypes.c_int), ctypes.c_uint32, u32p]
+    return lib
+
+
+def ures(hs, p, A, B):
+    m, n = len(A) - 1, len(B) - 1
+    a = (ctypes.c_uint32 * len(A))(*A)
+    b = (ctypes.c_uint32 * len(B))(*B)
+    out = ctypes.c_uint32()
+    bad = ctypes.c_int()
+    hs.hs_ures(p, m, n, a, b, ctypes.byref(out), ctypes.byref(bad))
+    return out.value, bool(bad.value)
+
+
+def sylvester_det_mod(A, B, p):
+    """det of the formal Sylvester matrix (A rows first, highest power first) mod p."""
+    m, n = len(A) - 1, len(B) - 1
+    r = m + n
+    if r == 0:
+        return 1 % p
+    S = [[0] * r for _ in range(r)]
+    for i in range(n):
+        for t in range(m + 1):
+            S[i][i + t] = A[m - t]
+    for l in range(m):
+        for t in range(n + 1):
+            S[n + l][l + t] = B[n - t]
+    return det_mod(S, p)
+
+
+def polymul_mod(a, b, p):
+    out = [0] * (len(a) + len(b) - 1)
+    for i, u in enumerate(a):
+        for j, v in enumerate(b):
+            out[i + j] = (out[i + j] + u * v) % p
+    return out
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_random_generic(hs, seed):
+    rng = rng_for(950, seed)
+    p = PRIMES[seed % len(PRIMES)]
+    m, n = int(rng.integers(0, 12)), int(rng.integers(0, 12))
+    A = [int(v) for v in rng.integers(0, p, m + 1)]
+    B = [int(v) for v in rng.integers(0, p, n + 1)]
+    got, _ = ures(hs, p, A, B)
+    assert got == sylvester_det_mod(A, B, p)
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_degenerate(hs, seed):
+    """Small primes-like structure: tiny coefficient alphabet forces zero leading
+    coefficients, degree drops by more than one and common factors."""
+    rng = rng_for(951, seed)
+    p = PRIMES[seed % len(PRIMES)]
+    m, n = int(rng.integers(0, 8)), int(rng.integers(0, 8))
+    alphabet = [0, 0, 1, p - 1, 2]
+    A = [alphabet[int(v)] for v in rng.integers(0, len(alphabet), m + 1)]
+    B = [alphabet[int(v)] for v in rng.integers(0, len(alphabet), n + 1)]
+    if seed % 3 == 0 and m >= 1 and n >= 1:  # plant a common factor (y - 3)
+        c = [p - 3, 1]
+        A = polymul_mod(c, A[:m], p)
+        B = polymul_mod(c, B[:n], p)
+    got, bad = ures(hs, p, A, B)
+    assert got == sylvester_det_mod(A, B, p), (p, A, B)
+    assert bad == (A[-1] == 0 or B[-1] == 0)
+
+
+def test_remainder_degree_drops(hs):
+    """Remainder sequences whose degree falls by more than one at a time."""
+    p = PRIMES[0]
+    cases = [
+        ([1, 0, 0, 0, 1], [1, 0, 1]),          # y^4+1 vs y^2+1: remainder constant
+        ([5, 0, 0, 0, 0, 1], [0, 0, 1]),       # y^5+5 vs y^2: remainder constant
+        ([1, 2, 1], [1, 1]),                   # (y+1)^2 vs y+1: zero remainder
+        ([3, 0, 0, 1], [7, 0, 0, 0, 0, 0, 2]), # deg A < deg B at the start
+        ([0, 0, 0, 0], [1, 2, 3]),             # A = 0 with formal degree 3
+        ([0, 0, 4, 0], [1, 2, 0]),             # both leading coefficients vanish
+        ([2, 3, 0, 0], [1, 1, 1]),             # deg A = 1 < formal 3
+        ([2, 3, 4], [6, 0, 0, 0]),             # deg B = 0 < formal 3
+    ]
+    for A, B in cases:
+        got, _ = ures(hs, p, A, B)
+        assert got == sylvester_det_mod(A, B, p), (A, B)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_eval_rows(hs, seed):
+    rng = rng_for(952, seed)
+    p = PRIMES[seed % len(PRIMES)]
+    nrows, stride = int(rng.integers(1, 6)), int(rng.integers(1, 9))
+    coeff = [int(v) for v in rng.integers(0, p, nrows * stride)]
+    rdeg = [int(rng.integers(-1, stride)) for _ in range(nrows)]
+    x = int(rng.integers(0, 5000))
+    out = (ctypes.c_uint32 * nrows)()
+    hs.hs_eval(p, nrows, stride, (ctypes.c_uint32 * len(coeff))(*coeff), (ctypes.c_int * nrows)(*rdeg), x, out)
+    for j in range(nrows):
+        row = coeff[j * stride: j * stride + rdeg[j] + 1]
+        assert out[j] == poly_eval_mod(row, x, p)
