@@ -19,6 +19,12 @@ import threading
 
 import numpy as np
 
+# torch must be imported before librsl.so is loaded: torch ships its own HIP
+# runtime (SONAME libamdhip64.so.7); loading torch first makes librsl bind to
+# that same runtime, so device pointers and streams are shared.  Loading the
+# system runtime first would put two HIP runtimes into one process.
+import torch  # noqa: F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_HERE, "librsl.so")
 
