@@ -161,6 +161,47 @@ int rsl_batch(rsl_ctx *ctx, int n, const rsl_poly *f, const rsl_poly *g, const i
 /* Counters of the last rsl_res / rsl_batch on this context. */
 int rsl_last_counters(rsl_ctx *ctx, rsl_counters *c);
 
+/* ---------------------------------------------------------- resident jobs */
+/*
+ * A job is a planned batch whose inputs stay resident in device memory, so
+ * that the device pipeline can be run repeatedly without host work (used for
+ * throughput measurement and by the server).  The job owns its device buffers
+ * (allocated with hipMalloc at creation, freed by rsl_job_destroy) and must be
+ * used with the context it was created on.
+ */
+typedef struct rsl_job rsl_job;
+
+typedef struct {
+  int32_t n_problems;     /* problems submitted */
+  int32_t n_live;         /* problems with device work (non-zero inputs) */
+  int64_t pairs;          /* (prime, point) univariate resultants per run */
+  int64_t mulmods;        /* algorithmic multiply-adds of evaluation + remainder sequences per run */
+  size_t device_bytes;    /* device memory held by the job */
+  size_t upload_bytes;    /* host -> device bytes at creation */
+  size_t download_bytes;  /* device -> host bytes per rsl_job_results */
+} rsl_job_info;
+
+/* Plan n problems and upload their inputs (status per problem in `status`, may be NULL). */
+int rsl_job_create(rsl_ctx *ctx, int n, const rsl_poly *f, const rsl_poly *g, const int *var,
+                   const rsl_opts *opts, int *status, rsl_job **out);
+/* Run the device pipeline on the resident inputs; asynchronous on the context stream. */
+int rsl_job_run(rsl_ctx *ctx, rsl_job *job, int mode);
+/* Wait for the last run, copy the results back and decode them. */
+int rsl_job_results(rsl_ctx *ctx, rsl_job *job, rsl_result *out, int *status);
+int rsl_job_info_get(const rsl_job *job, rsl_job_info *info);
+int rsl_job_destroy(rsl_job *job);
+
+/* --------------------------------------------------------------- profiling */
+/* Stages: 0 reduce, 1 eval+ures, 2 interp (convolution), 3 interp (basis
+ * change), 4 interp (gapped points), 5 CRT. */
+#define RSL_NUM_STAGES 6
+/* While enabled, every batched launch records HIP events on the context
+ * stream at each stage boundary. */
+int rsl_profile_enable(rsl_ctx *ctx, int on);
+/* Synchronise, add up the stage durations of all launches recorded since the
+ * last call into stage_ms[RSL_NUM_STAGES], and reset. */
+int rsl_profile_take(rsl_ctx *ctx, double *stage_ms, int *runs);
+
 /* ---------------------------------------------------------------- serving */
 typedef struct rsl_server rsl_server;
 

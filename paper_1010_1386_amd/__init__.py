@@ -77,6 +77,14 @@ class rsl_stats(ctypes.Structure):
                 ("max_batch", ctypes.c_int64)]
 
 
+class rsl_job_info(ctypes.Structure):
+    _fields_ = [("n_problems", ctypes.c_int32), ("n_live", ctypes.c_int32), ("pairs", ctypes.c_int64),
+                ("mulmods", ctypes.c_int64), ("device_bytes", ctypes.c_size_t), ("upload_bytes", ctypes.c_size_t),
+                ("download_bytes", ctypes.c_size_t)]
+
+
+STAGES = ("reduce", "eval_ures", "interp_conv", "interp_stir", "interp_newton", "crt")
+
 _P = ctypes.POINTER
 _vp = ctypes.c_void_p
 _SIGS = {
@@ -96,6 +104,14 @@ _SIGS = {
     "rsl_server_wait": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_int]),
     "rsl_server_stats": (ctypes.c_int, [_vp, _P(rsl_stats)]),
     "rsl_server_destroy": (ctypes.c_int, [_vp]),
+    "rsl_job_create": (ctypes.c_int, [_vp, ctypes.c_int, _P(rsl_poly), _P(rsl_poly), _P(ctypes.c_int),
+                                      _P(rsl_opts), _P(ctypes.c_int), _P(_vp)]),
+    "rsl_job_run": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "rsl_job_results": (ctypes.c_int, [_vp, _vp, _P(rsl_result), _P(ctypes.c_int)]),
+    "rsl_job_info_get": (ctypes.c_int, [_vp, _P(rsl_job_info)]),
+    "rsl_job_destroy": (ctypes.c_int, [_vp]),
+    "rsl_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "rsl_profile_take": (ctypes.c_int, [_vp, _P(ctypes.c_double), _P(ctypes.c_int)]),
     "rsl_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "rsl_last_error": (ctypes.c_char_p, [_vp]),
     "rsl_version": (ctypes.c_char_p, []),
@@ -288,7 +304,7 @@ class Context:
             polys.append((pf, pg))
             outs.append(r)
             fa[k], ga[k], va[k], ra[k] = pf.c, pg.c, v, r.c
-        code = RSL_BATCHED if mode in ("batched", RSL_BATCHED) else RSL_PLAIN
+        code = _modecode(mode)
         with self.lock:
             rc = _lib.rsl_batch(self.h, n, fa, ga, va, ra, st, code)
         self._check(rc, "rsl_batch")
@@ -297,6 +313,87 @@ class Context:
             outs[k].c = ra[k]
             res.append(outs[k].value())
         return res
+
+
+    def profile_enable(self, on=True):
+        self._check(_lib.rsl_profile_enable(self.h, 1 if on else 0), "rsl_profile_enable")
+
+    def profile_take(self):
+        """(per-stage device ms summed over the profiled launches, number of launches)."""
+        ms = (ctypes.c_double * len(STAGES))()
+        runs = ctypes.c_int()
+        self._check(_lib.rsl_profile_take(self.h, ms, ctypes.byref(runs)), "rsl_profile_take")
+        return dict(zip(STAGES, list(ms))), runs.value
+
+    def job(self, problems, **opts):
+        return Job(self, problems, **opts)
+
+
+def _modecode(mode):
+    return RSL_BATCHED if mode in ("batched", RSL_BATCHED) else RSL_PLAIN
+
+
+class Job:
+    """Problems planned once with inputs resident on the device; run() repeats the device pipeline."""
+
+    def __init__(self, ctx, problems, **opts):
+        self.ctx = ctx
+        n = len(problems)
+        self.n = n
+        self._polys = []
+        self._outs = []
+        self.fa = (rsl_poly * max(n, 1))()
+        self.ga = (rsl_poly * max(n, 1))()
+        self.va = (ctypes.c_int * max(n, 1))()
+        self.ra = (rsl_result * max(n, 1))()
+        for k, (f, g, var) in enumerate(problems):
+            pf, pg = _as_poly(f), _as_poly(g)
+            v = _var_code(var)
+            info = rsl_info()
+            ctx._check(_lib.rsl_query(ctypes.byref(pf.c), ctypes.byref(pg.c), v, ctypes.byref(info)), "rsl_query")
+            r = _Result(max(info.D, 0), info.out_limbs)
+            self._polys.append((pf, pg))
+            self._outs.append(r)
+            self.fa[k], self.ga[k], self.va[k], self.ra[k] = pf.c, pg.c, v, r.c
+        o = _opts(**opts)
+        st = (ctypes.c_int * max(n, 1))()
+        h = _vp()
+        with ctx.lock:
+            rc = _lib.rsl_job_create(ctx.h, n, self.fa, self.ga, self.va, ctypes.byref(o), st, ctypes.byref(h))
+        ctx._check(rc, "rsl_job_create")
+        self.h = h
+
+    def run(self, mode="batched"):
+        with self.ctx.lock:
+            rc = _lib.rsl_job_run(self.ctx.h, self.h, _modecode(mode))
+        self.ctx._check(rc, "rsl_job_run")
+
+    def results(self):
+        st = (ctypes.c_int * max(self.n, 1))()
+        with self.ctx.lock:
+            rc = _lib.rsl_job_results(self.ctx.h, self.h, self.ra, st)
+        self.ctx._check(rc, "rsl_job_results")
+        out = []
+        for k in range(self.n):
+            self._outs[k].c = self.ra[k]
+            out.append(self._outs[k].value())
+        return out
+
+    def info(self):
+        i = rsl_job_info()
+        _lib.rsl_job_info_get(self.h, ctypes.byref(i))
+        return {name: getattr(i, name) for name, _ in rsl_job_info._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.rsl_job_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _default = None

@@ -7,6 +7,7 @@
 
 #include "batch.h"
 #include "context.h"
+#include "job.h"
 #include "kernels.h"
 
 namespace rsl {
@@ -118,6 +119,7 @@ int ensure_tables(rsl_ctx* ctx, int np, int kneed, int sneed) {
   ctx->kstride = ks;
   ctx->sstride = sstride;
   ctx->LPg = LPg;
+  ctx->table_gen += 1;
   return RSL_OK;
 }
 
@@ -157,119 +159,6 @@ int ensure_staging(rsl_ctx* ctx, size_t up, size_t down) {
     ctx->h_down_bytes = sz;
   }
   return RSL_OK;
-}
-
-Layout layout_of(const Plan& P) {
-  Layout L;
-  const size_t A = 256;
-  L.L_in = std::max(P.f.L, P.g.L);
-  const int ncoef = P.goff + (P.ny + 1) * P.rowg;
-  size_t o = 0;
-  L.u_coeff = o; o = align_up(o + static_cast<size_t>(ncoef) * L.L_in * 4, A);
-  L.u_rdeg = o;  o = align_up(o + static_cast<size_t>(P.my + P.ny + 2) * 4, A);
-  L.u_pidx = o;  o = align_up(o + static_cast<size_t>(P.np) * 4, A);
-  L.u_Hm = o;    o = align_up(o + static_cast<size_t>(P.np) * 4, A);
-  L.u_NH = o;    o = align_up(o + static_cast<size_t>(P.L_out) * 4, A);
-  if (!P.canonical) {
-    L.u_Tg = o;    o = align_up(o + static_cast<size_t>(P.np) * P.np * 4, A);
-    L.u_invM = o;  o = align_up(o + static_cast<size_t>(P.np) * 4, A);
-    L.u_Plimb = o; o = align_up(o + static_cast<size_t>(P.np) * P.L_out * 4, A);
-  }
-  L.u_status = o; o = align_up(o + static_cast<size_t>(P.np + 2) * 4, A);
-  L.up_off = 0;
-  L.up_bytes = o;
-  const size_t np = P.np;
-  L.resid = o; o = align_up(o + np * P.CS * 4, A);
-  L.zval = o;  o = align_up(o + np * (P.E + 1) * 4, A);
-  L.zbad = o;  o = align_up(o + np * (P.E + 1), A);
-  L.aconv = o; o = align_up(o + np * (P.D + 1) * 4, A);
-  L.cres = o;  o = align_up(o + np * (P.D + 1) * 4, A);
-  L.out = o;
-  L.out_bytes = static_cast<size_t>(P.D + 1) * P.L_out * 4;
-  o = align_up(o + L.out_bytes, A);
-  L.status = L.u_status;
-  L.status_bytes = static_cast<size_t>(P.np + 2) * 4;
-  L.total = o;
-  return L;
-}
-
-void fill_upload(const Plan& P, const Layout& L, uint8_t* blob) {
-  // coefficients: f tile rows 0..my (stride rowf), then g tile rows 0..ny (stride rowg),
-  // sign-extended to L_in limbs
-  uint32_t* c = reinterpret_cast<uint32_t*>(blob + L.u_coeff);
-  const int Li = L.L_in;
-  auto put = [&](const View& V, int rows, int rowstride, size_t base) {
-    for (int j = 0; j < rows; ++j)
-      for (int i = 0; i < rowstride; ++i) {
-        uint32_t* dst = c + (base + static_cast<size_t>(j) * rowstride + i) * Li;
-        if (i <= V.rdeg[j]) {
-          const uint32_t* src = &V.c[(static_cast<size_t>(j) * (V.dx + 1) + i) * V.L];
-          const uint32_t ext = (src[V.L - 1] >> 31) ? 0xFFFFFFFFu : 0u;
-          for (int l = 0; l < Li; ++l) dst[l] = (l < V.L) ? src[l] : ext;
-        } else {
-          for (int l = 0; l < Li; ++l) dst[l] = 0;
-        }
-      }
-  };
-  put(P.f, P.my + 1, P.rowf, 0);
-  put(P.g, P.ny + 1, P.rowg, static_cast<size_t>(P.goff));
-  int* rd = reinterpret_cast<int*>(blob + L.u_rdeg);
-  for (int j = 0; j <= P.my; ++j) rd[j] = P.f.rdeg[j];
-  for (int j = 0; j <= P.ny; ++j) rd[P.my + 1 + j] = P.g.rdeg[j];
-  std::memcpy(blob + L.u_pidx, P.pidx.data(), P.np * 4);
-  std::memcpy(blob + L.u_Hm, P.Hm.data(), P.np * 4);
-  std::memcpy(blob + L.u_NH, P.NH.data(), P.L_out * 4);
-  if (!P.canonical) {
-    std::memcpy(blob + L.u_Tg, P.Tg.data(), P.Tg.size() * 4);
-    std::memcpy(blob + L.u_invM, P.invM.data(), P.invM.size() * 4);
-    std::memcpy(blob + L.u_Plimb, P.Plimb.data(), P.Plimb.size() * 4);
-  }
-  std::memset(blob + L.u_status, 0, static_cast<size_t>(P.np + 2) * 4);
-}
-
-DevProblem dev_problem(const rsl_ctx* ctx, const Plan& P, const Layout& L, uint8_t* base) {
-  DevProblem d{};
-  d.my = P.my;
-  d.ny = P.ny;
-  d.rowf = P.rowf;
-  d.rowg = P.rowg;
-  d.goff = P.goff;
-  d.CS = P.CS;
-  d.ncoef = P.goff + (P.ny + 1) * P.rowg;
-  d.L_in = L.L_in;
-  d.D = P.D;
-  d.E = P.E;
-  d.origin = P.origin;
-  d.formal = P.formal;
-  d.np = P.np;
-  d.L_out = P.L_out;
-  uint8_t* up = base + L.up_off;
-  d.coeff = reinterpret_cast<const uint32_t*>(up + L.u_coeff);
-  d.rdeg = reinterpret_cast<const int*>(up + L.u_rdeg);
-  d.pidx = reinterpret_cast<const int*>(up + L.u_pidx);
-  d.Hm = reinterpret_cast<const uint32_t*>(up + L.u_Hm);
-  d.NH = reinterpret_cast<const uint32_t*>(up + L.u_NH);
-  if (P.canonical) {
-    d.Tg = ctx->d_Tg;
-    d.tgs = ctx->npcap;
-    d.invM = ctx->d_invM;
-    d.Plimb = ctx->d_Plimb;
-    d.LP = ctx->LPg;
-  } else {
-    d.Tg = reinterpret_cast<const uint32_t*>(up + L.u_Tg);
-    d.tgs = P.np;
-    d.invM = reinterpret_cast<const uint32_t*>(up + L.u_invM);
-    d.Plimb = reinterpret_cast<const uint32_t*>(up + L.u_Plimb);
-    d.LP = P.L_out;
-  }
-  d.resid = reinterpret_cast<uint32_t*>(base + L.resid);
-  d.zval = reinterpret_cast<uint32_t*>(base + L.zval);
-  d.zbad = base + L.zbad;
-  d.aconv = reinterpret_cast<uint32_t*>(base + L.aconv);
-  d.cres = reinterpret_cast<uint32_t*>(base + L.cres);
-  d.out = reinterpret_cast<uint32_t*>(base + L.out);
-  d.status = reinterpret_cast<int*>(up + L.u_status);
-  return d;
 }
 
 // Signed limbs needed by a two's complement value.
@@ -312,51 +201,36 @@ int decode_result(const Plan& P, const uint32_t* limbs, rsl_result* out) {
   return RSL_OK;
 }
 
-// One problem on the context stream, synchronously.
-static int run_plain(rsl_ctx* ctx, const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opts,
-                     rsl_result* out, rsl_counters* cnt) {
-  if (!out) return fail(ctx, RSL_EINVAL, "null result");
-  Plan P;
-  int rc = make_plan(f, g, var, opts, &P, &ctx->err);
-  if (rc) return rc;
-  cnt->problems += 1;
-  if (P.zero) return decode_result(P, nullptr, out);
-  if (P.np > 256) return fail(ctx, RSL_EINVAL, "more than 256 primes needed (coefficients too large)");
-  if (P.E > 3800) return fail(ctx, RSL_EINVAL, "more than 3800 evaluation points needed (degree bound too large)");
-  int maxg = 0;
-  for (int g0 : P.pidx) maxg = std::max(maxg, g0 + 1);
-  if ((rc = ensure_tables(ctx, maxg, P.E, P.D))) return rc;
-  Layout L = layout_of(P);
-  if (L.total > ctx->ws_bytes)
-    return fail(ctx, RSL_ENOMEM, "workspace of " + std::to_string(ctx->ws_bytes) + " bytes < footprint " +
-                                     std::to_string(L.total));
-  if ((rc = ensure_staging(ctx, L.up_bytes, L.out_bytes + L.status_bytes))) return rc;
-  fill_upload(P, L, ctx->h_up);
-  DevProblem dp = dev_problem(ctx, P, L, ctx->ws);
-  DevTables T = tables_of(ctx);
-  hipStream_t st = ctx->stream;
-  if ((rc = hip_check(ctx, hipMemcpyAsync(ctx->ws + L.up_off, ctx->h_up, L.up_bytes, hipMemcpyHostToDevice, st),
-                      "upload")) ||
-      (rc = hip_check(ctx, hipEventRecord(ctx->e0, st), "event")) ||
-      (rc = hip_check(ctx, launch_pipeline(dp, T, st), "launch")) ||
-      (rc = hip_check(ctx, hipEventRecord(ctx->e1, st), "event")) ||
-      (rc = hip_check(ctx, hipMemcpyAsync(ctx->h_down, ctx->ws + L.out, L.out_bytes, hipMemcpyDeviceToHost, st),
-                      "download")) ||
-      (rc = hip_check(ctx, hipMemcpyAsync(ctx->h_down + L.out_bytes, ctx->ws + L.status, L.status_bytes,
-                                          hipMemcpyDeviceToHost, st), "download")) ||
-      (rc = hip_check(ctx, hipStreamSynchronize(st), "hipStreamSynchronize")))
-    return rc;
-  float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, ctx->e0, ctx->e1);
-  cnt->ms_device += ms;
-  const int* status = reinterpret_cast<const int*>(ctx->h_down + L.out_bytes);
-  if (status[0] & kErrTooFewGoodPoints) return fail(ctx, RSL_EPRIMES, "fewer than D+1 good points for a prime");
-  cnt->pairs += static_cast<int64_t>(P.np) * (P.E + 1);
-  cnt->bad_pairs += status[P.np + 1];
-  cnt->bad_primes += P.bad_primes;
-  for (int i = 0; i < P.np; ++i) cnt->slow_primes += status[1 + i];
-  rc = decode_result(P, reinterpret_cast<const uint32_t*>(ctx->h_down), out);
-  if (rc == RSL_ERANGE) return fail(ctx, rc, "result buffer too small");
+// Run a job laid out in the context workspace, synchronously.
+static int run_in_workspace(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var,
+                            const rsl_opts* opts, rsl_result* out, int* status, int mode, rsl_counters* cnt) {
+  Job J;
+  std::string err;
+  int rc = job_build(ctx, n, f, g, var, opts, &J, &err);
+  if (rc == RSL_EDEVICE) return rc;
+  if (!J.live.empty()) {
+    if (J.total > ctx->ws_bytes) {
+      const std::string m = "workspace of " + std::to_string(ctx->ws_bytes) + " bytes < footprint " +
+                            std::to_string(J.total);
+      for (int k : J.live) J.pstatus[k] = RSL_ENOMEM;
+      if (status)
+        for (int k = 0; k < n; ++k) status[k] = J.pstatus[k];
+      return fail(ctx, RSL_ENOMEM, m);
+    }
+    job_bind(&J, ctx->ws);
+    hipStream_t st = ctx->stream;
+    if ((rc = job_upload(ctx, &J, st)) || (rc = hip_check(ctx, hipEventRecord(ctx->e0, st), "event")) ||
+        (rc = job_launch(ctx, &J, mode, st, false)) || (rc = hip_check(ctx, hipEventRecord(ctx->e1, st), "event")) ||
+        (rc = job_download(ctx, &J, ctx->h_down, st)) ||
+        (rc = hip_check(ctx, hipStreamSynchronize(st), "hipStreamSynchronize")))
+      return rc;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ctx->e0, ctx->e1);
+    cnt->ms_device += ms;
+  }
+  rc = job_decode(ctx, J, ctx->h_down, out, status, cnt);
+  if (rc && !err.empty() && ctx->err.empty()) ctx->err = err;
+  if (rc && rc != RSL_ERANGE && rc != RSL_EPRIMES && !err.empty()) ctx->err = err;
   return rc;
 }
 
@@ -378,7 +252,9 @@ int rsl_ctx_create(int device, void* d_workspace, size_t ws_bytes, void* stream,
   c->ws = static_cast<uint8_t*>(d_workspace);
   c->ws_bytes = ws_bytes;
   c->stream = static_cast<hipStream_t>(stream);
-  if (hipEventCreate(&c->e0) != hipSuccess || hipEventCreate(&c->e1) != hipSuccess) {
+  bool ok = hipEventCreate(&c->e0) == hipSuccess && hipEventCreate(&c->e1) == hipSuccess;
+  for (int s = 0; s <= kNumStages && ok; ++s) ok = hipEventCreate(&c->ev[s]) == hipSuccess;
+  if (!ok) {
     delete c;
     return RSL_EDEVICE;
   }
@@ -396,6 +272,10 @@ int rsl_ctx_destroy(rsl_ctx* ctx) {
   if (ctx->h_down) (void)hipHostFree(ctx->h_down);
   if (ctx->e0) (void)hipEventDestroy(ctx->e0);
   if (ctx->e1) (void)hipEventDestroy(ctx->e1);
+  for (hipEvent_t e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& set : ctx->evsets)
+    for (hipEvent_t e : set) (void)hipEventDestroy(e);
   delete ctx;
   return RSL_OK;
 }
@@ -422,19 +302,22 @@ int rsl_query(const rsl_poly* f, const rsl_poly* g, int var, rsl_info* info) {
   info->my = P.my;
   info->ny = P.ny;
   info->bad_primes = P.bad_primes;
-  info->footprint_bytes = layout_of(P).total;
+  Job J;
+  std::string e2;
+  if (job_build(nullptr, 1, f, g, &var, nullptr, &J, &e2) == RSL_OK) info->footprint_bytes = J.total;
   return RSL_OK;
 }
 
 int rsl_res(rsl_ctx* ctx, const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opts,
             rsl_result* out) {
-  if (!ctx) return RSL_EINVAL;
+  if (!ctx || !out) return RSL_EINVAL;
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   if (ctx->poisoned) return RSL_EDEVICE;
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, RSL_EDEVICE, "hipSetDevice");
+  ctx->err.clear();
   const double t0 = now_ms();
   rsl_counters cnt{};
-  int rc = run_plain(ctx, f, g, var, opts, out, &cnt);
+  int rc = run_in_workspace(ctx, 1, f, g, &var, opts, out, nullptr, RSL_BATCHED, &cnt);
   cnt.ms_total = now_ms() - t0;
   ctx->last = cnt;
   return rc;
@@ -455,22 +338,13 @@ int rsl_batch(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   if (ctx->poisoned) return RSL_EDEVICE;
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, RSL_EDEVICE, "hipSetDevice");
+  ctx->err.clear();
   const double t0 = now_ms();
   rsl_counters cnt{};
-  int first = RSL_OK;
-  if (mode == RSL_BATCHED) {
-    first = run_batched(ctx, n, f, g, var, out, status, &cnt);
-  } else {
-    for (int k = 0; k < n; ++k) {
-      int rc = run_plain(ctx, &f[k], &g[k], var[k], nullptr, &out[k], &cnt);
-      if (status) status[k] = rc;
-      if (rc && !first) first = rc;
-      if (rc == RSL_EDEVICE) break;
-    }
-  }
+  int rc = run_in_workspace(ctx, n, f, g, var, nullptr, out, status, mode, &cnt);
   cnt.ms_total = now_ms() - t0;
   ctx->last = cnt;
-  return first;
+  return rc;
 }
 
 int rsl_last_counters(rsl_ctx* ctx, rsl_counters* c) {
@@ -496,5 +370,161 @@ const char* rsl_strerror(int code) {
 const char* rsl_last_error(rsl_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 const char* rsl_version(void) { return "rsl 0.1 (gfx950)"; }
+
+// ----------------------------------------------------------- resident jobs
+
+}  // extern "C"
+
+struct rsl_job {
+  rsl::Job J;
+  uint8_t* dmem = nullptr;
+  uint8_t* hdown = nullptr;
+  int gen = -1;
+  rsl_ctx* ctx = nullptr;
+};
+
+namespace rsl {
+
+// Re-point the job's problems at the current constant tables if they moved.
+static int job_refresh(rsl_ctx* ctx, rsl_job* j) {
+  if (j->gen == ctx->table_gen) return RSL_OK;
+  int rc = job_upload(ctx, &j->J, ctx->stream);
+  if (rc) return rc;
+  j->gen = ctx->table_gen;
+  return RSL_OK;
+}
+
+// Per-stage events of one batched launch (profiling).
+static hipEvent_t* next_evset(rsl_ctx* ctx) {
+  if (ctx->evused == static_cast<int>(ctx->evsets.size())) {
+    std::vector<hipEvent_t> set(kNumStages + 1, nullptr);
+    for (auto& e : set)
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->evsets.push_back(set);
+  }
+  return ctx->evsets[ctx->evused++].data();
+}
+
+}  // namespace rsl
+
+extern "C" {
+
+int rsl_job_create(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var,
+                   const rsl_opts* opts, int* status, rsl_job** out) {
+  if (!ctx || !out || n < 0 || (n > 0 && (!f || !g || !var))) return RSL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  if (ctx->poisoned) return RSL_EDEVICE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, RSL_EDEVICE, "hipSetDevice");
+  *out = nullptr;
+  rsl_job* j = new (std::nothrow) rsl_job();
+  if (!j) return RSL_ENOMEM;
+  j->ctx = ctx;
+  std::string err;
+  int rc = job_build(ctx, n, f, g, var, opts, &j->J, &err);
+  if (status)
+    for (int k = 0; k < n; ++k) status[k] = j->J.pstatus[k];
+  if (rc == RSL_EDEVICE) { delete j; return rc; }
+  if (!err.empty()) ctx->err = err;
+  const size_t bytes = std::max<size_t>(j->J.total, 256);
+  if ((rc = hip_check(ctx, hipMalloc(reinterpret_cast<void**>(&j->dmem), bytes), "hipMalloc(job)")) ||
+      (rc = hip_check(ctx, hipHostMalloc(reinterpret_cast<void**>(&j->hdown), std::max<size_t>(j->J.down_bytes, 256),
+                                         hipHostMallocDefault), "hipHostMalloc(job)"))) {
+    if (j->dmem) (void)hipFree(j->dmem);
+    delete j;
+    return rc;
+  }
+  job_bind(&j->J, j->dmem);
+  if ((rc = job_upload(ctx, &j->J, ctx->stream)) ||
+      (rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize"))) {
+    (void)hipFree(j->dmem);
+    (void)hipHostFree(j->hdown);
+    delete j;
+    return rc;
+  }
+  j->gen = ctx->table_gen;
+  *out = j;
+  return RSL_OK;
+}
+
+int rsl_job_run(rsl_ctx* ctx, rsl_job* j, int mode) {
+  if (!ctx || !j || j->ctx != ctx) return RSL_EINVAL;
+  if (mode != RSL_PLAIN && mode != RSL_BATCHED) return fail(ctx, RSL_EINVAL, "mode must be RSL_PLAIN or RSL_BATCHED");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  if (ctx->poisoned) return RSL_EDEVICE;
+  int rc;
+  if ((rc = job_refresh(ctx, j)) || (rc = job_reset(ctx, &j->J, ctx->stream))) return rc;
+  if (ctx->profiling && mode == RSL_BATCHED) {
+    hipEvent_t* ev = next_evset(ctx);
+    if (!ev) return fail(ctx, RSL_EDEVICE, "hipEventCreate");
+    for (int s = 0; s <= kNumStages; ++s) ctx->ev[s] = ev[s];
+    return job_launch(ctx, &j->J, mode, ctx->stream, true);
+  }
+  return job_launch(ctx, &j->J, mode, ctx->stream, false);
+}
+
+int rsl_job_results(rsl_ctx* ctx, rsl_job* j, rsl_result* out, int* status) {
+  if (!ctx || !j || j->ctx != ctx || (j->J.n > 0 && !out)) return RSL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  if (ctx->poisoned) return RSL_EDEVICE;
+  int rc;
+  if ((rc = job_download(ctx, &j->J, j->hdown, ctx->stream)) ||
+      (rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize")))
+    return rc;
+  rsl_counters cnt{};
+  rc = job_decode(ctx, j->J, j->hdown, out, status, &cnt);
+  ctx->last = cnt;
+  return rc;
+}
+
+int rsl_job_info_get(const rsl_job* j, rsl_job_info* info) {
+  if (!j || !info) return RSL_EINVAL;
+  info->n_problems = j->J.n;
+  info->n_live = static_cast<int32_t>(j->J.live.size());
+  info->pairs = j->J.pairs;
+  info->mulmods = j->J.mulmods;
+  info->device_bytes = j->J.total;
+  info->upload_bytes = j->J.up_bytes;
+  info->download_bytes = j->J.down_bytes;
+  return RSL_OK;
+}
+
+int rsl_job_destroy(rsl_job* j) {
+  if (!j) return RSL_EINVAL;
+  if (j->ctx) {
+    std::lock_guard<std::recursive_mutex> lk(j->ctx->mu);
+    (void)hipSetDevice(j->ctx->device);
+    (void)hipStreamSynchronize(j->ctx->stream);
+  }
+  if (j->dmem) (void)hipFree(j->dmem);
+  if (j->hdown) (void)hipHostFree(j->hdown);
+  delete j;
+  return RSL_OK;
+}
+
+int rsl_profile_enable(rsl_ctx* ctx, int on) {
+  if (!ctx) return RSL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->profiling = on != 0;
+  ctx->evused = 0;
+  return RSL_OK;
+}
+
+int rsl_profile_take(rsl_ctx* ctx, double* stage_ms, int* runs) {
+  if (!ctx || !stage_ms) return RSL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  int rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+  if (rc) return rc;
+  for (int s = 0; s < kNumStages; ++s) stage_ms[s] = 0.0;
+  for (int r = 0; r < ctx->evused; ++r) {
+    const std::vector<hipEvent_t>& ev = ctx->evsets[r];
+    for (int s = 0; s < kNumStages; ++s) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[s], ev[s + 1]) == hipSuccess) stage_ms[s] += ms;
+    }
+  }
+  if (runs) *runs = ctx->evused;
+  ctx->evused = 0;
+  return RSL_OK;
+}
 
 }  // extern "C"

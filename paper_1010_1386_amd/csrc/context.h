@@ -11,6 +11,7 @@
 #include "../../include/rsl.h"
 #include "device.h"
 #include "plan.h"
+#include "stages.h"
 
 struct rsl_ctx {
   int device = 0;
@@ -41,6 +42,11 @@ struct rsl_ctx {
   size_t h_down_bytes = 0;
 
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipEvent_t ev[rsl::kNumStages + 1] = {};   // stage boundaries of the last batched launch
+  std::vector<std::vector<hipEvent_t>> evsets; // per-run stage events while profiling
+  int evused = 0;
+  bool profiling = false;
+  int table_gen = 0;                          // bumped whenever the constant tables move
   rsl_counters last{};
   std::recursive_mutex mu;
 };
@@ -60,24 +66,6 @@ DevTables tables_of(const rsl_ctx* ctx);
 // Grow the pinned staging buffers.
 int ensure_staging(rsl_ctx* ctx, size_t up, size_t down);
 
-// Device layout of one planned problem inside a workspace region.
-struct Layout {
-  size_t up_off = 0, up_bytes = 0;     // uploaded inputs (coefficients, tables, zeroed status)
-  size_t resid = 0, zval = 0, zbad = 0, aconv = 0, cres = 0;
-  size_t out = 0, out_bytes = 0;       // output limbs
-  size_t status = 0, status_bytes = 0;
-  size_t total = 0;
-  // offsets inside the upload blob
-  size_t u_coeff = 0, u_rdeg = 0, u_pidx = 0, u_Hm = 0, u_NH = 0, u_Tg = 0, u_invM = 0, u_Plimb = 0;
-  size_t u_status = 0;
-  int L_in = 1;
-};
-
-Layout layout_of(const Plan& P);
-// Fill the upload blob (host) for a plan laid out at device address `base`.
-void fill_upload(const Plan& P, const Layout& L, uint8_t* blob);
-// Device problem descriptor for a plan laid out at device address `base`.
-DevProblem dev_problem(const rsl_ctx* ctx, const Plan& P, const Layout& L, uint8_t* base);
 // Decode the CRT limbs of a problem into the caller's result.
 int decode_result(const Plan& P, const uint32_t* limbs, rsl_result* out);
 

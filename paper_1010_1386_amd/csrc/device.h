@@ -20,21 +20,26 @@ struct DevTables {
   int npcap;                // global prime indices < npcap
 };
 
+// Rows of the transposed residue tiles are padded to a multiple of this
+// (Horner evaluates this many rows at once from one LDS broadcast read).
+constexpr int kRowGroup = 4;
+
 // One resultant problem as laid out in device memory.
 struct DevProblem {
   // shape
   int my, ny;        // formal degrees in the eliminated variable
-  int rowf, rowg;    // row strides of the f and g coefficient tiles
-  int goff, CS;      // offset of the g tile, words per prime tile
-  int ncoef, L_in;   // input coefficients (f tile then g tile), limbs each
+  int rowf, rowg;    // input row strides (x-degree + 1) of f and g
+  int myp, nyp;      // my+1 and ny+1 rounded up to kRowGroup
+  int goff, CS;      // offset of the g tile, words per prime tile (transposed tiles)
+  int ncoef, L_in;   // input coefficients (f rows then g rows), limbs each
   int D, E;          // degree bound; points origin..origin+E are evaluated
   int origin, formal;
   int np, L_out;     // primes, CRT output limbs
   int LP, tgs;       // row stride of Plimb and of Tg
-  int pad0, pad1;
+  int nchunk, kchunk;// Stirling partial sums: k-chunks and rows per chunk
   // inputs (uploaded)
   const uint32_t* coeff;  // ncoef * L_in two's complement limbs
-  const int* rdeg;        // my+1 row degrees of f, then ny+1 of g
+  const int* gdeg;        // max x-degree per group of kRowGroup rows: f groups then g groups
   const int* pidx;        // np global prime indices
   const uint32_t* Hm;     // np: (M-1)/2 mod p_i
   const uint32_t* NH;     // L_out: 2^(32 L_out) - (M-1)/2
@@ -42,18 +47,27 @@ struct DevProblem {
   const uint32_t* invM;   // [i]            (prod_{l<i} p_l)^{-1} R mod p_i
   const uint32_t* Plimb;  // [j * LP + t]   limbs of prod_{l<j} p_l
   // intermediates and output
-  uint32_t* resid;        // np * CS     coefficients as c R^2 mod p
+  uint32_t* resid;        // np * CS     transposed tiles, c R^2 mod p
   uint32_t* zval;         // np * (E+1)  R(x_i) mod p, normal form
   uint8_t* zbad;          // np * (E+1)  leading coefficient vanished at x_i
   uint32_t* aconv;        // np * (D+1)  Newton coefficients (consecutive points)
-  uint32_t* cres;         // np * (D+1)  coefficients of R mod p, normal form
+  uint64_t* cpart;        // nchunk * np * (D+1): partial sums, REDC(sum) = coefficient mod p
   uint32_t* out;          // (D+1) * L_out two's complement limbs of R
-  int* status;            // [0]: error bits, [1 + slot]: 1 if the slot was interpolated on a gapped point set
+  int* status;            // [0] error bits, [1+slot] 1 if gapped interpolation, [1+np] bad pairs
+};
+
+// A unit of work of a stage kernel: one block processes one item.
+struct WorkItem {
+  int prob;  // index into the problem array
+  int slot;  // prime slot (or -1)
+  int blk;   // block index inside the (problem, slot)
+  int sub;   // stage-specific (Stirling k-chunk)
 };
 
 // status[0] error bits
 enum : int {
   kErrTooFewGoodPoints = 1,
+  kErrQueueStall = 2,
 };
 
 }  // namespace rsl

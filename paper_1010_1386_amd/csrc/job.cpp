@@ -1,0 +1,387 @@
+// Job layout, upload, launch and decode (see job.h).
+#include "job.h"
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "context.h"
+#include "kernels.h"
+
+namespace rsl {
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+static int blocks_of(int n, int b) { return (n + b - 1) / b; }
+
+// Algorithmic work of one (prime, point) pair: Horner multiply-adds over all
+// coefficients of f and g, plus m_y n_y multiply-subtracts of the Euclidean
+// remainder sequence (inversions not counted).
+static int64_t pair_mulmods(const Plan& P) {
+  int64_t nf = 0, ng = 0;
+  for (int d : P.f.rdeg) nf += d + 1;
+  for (int d : P.g.rdeg) ng += d + 1;
+  return nf + ng + static_cast<int64_t>(P.my) * P.ny;
+}
+
+int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var, const rsl_opts* opts,
+              Job* J, std::string* err) {
+  J->n = n;
+  J->plans.assign(n, Plan());
+  J->pstatus.assign(n, 0);
+  J->live.clear();
+  for (int s = 0; s < kNumStages; ++s) J->items[s].clear();
+  int maxg = 0, maxE = 0, maxD = 0;
+  for (int k = 0; k < n; ++k) {
+    std::string e;
+    int rc = make_plan(&f[k], &g[k], var[k], opts, &J->plans[k], &e);
+    if (!rc && !J->plans[k].zero) {
+      const Plan& P = J->plans[k];
+      if (P.np > 256) { rc = RSL_EINVAL; e = "more than 256 primes needed (coefficients too large)"; }
+      else if (P.E > 3800) { rc = RSL_EINVAL; e = "more than 3800 evaluation points needed (degree bound too large)"; }
+      else if (std::max(P.my, P.ny) > 255) { rc = RSL_EINVAL; e = "degree in the eliminated variable above 255"; }
+    }
+    J->pstatus[k] = rc;
+    if (rc) {
+      if (err->empty()) *err = "problem " + std::to_string(k) + ": " + e;
+      continue;
+    }
+    const Plan& P = J->plans[k];
+    if (P.zero) continue;
+    J->live.push_back(k);
+    for (int gi : P.pidx) maxg = std::max(maxg, gi + 1);
+    maxE = std::max(maxE, P.E);
+    maxD = std::max(maxD, P.D);
+  }
+  // larger problems first: their work starts early and the tail is short
+  std::vector<int64_t> cost(n, 0);
+  for (int k : J->live) {
+    const Plan& P = J->plans[k];
+    cost[k] = pair_mulmods(P) * P.np * (P.E + 1);
+  }
+  std::stable_sort(J->live.begin(), J->live.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  if (ctx && !J->live.empty()) {
+    int rc = ensure_tables(ctx, maxg, maxE, maxD);
+    if (rc) { *err = ctx->err; return rc; }
+  }
+
+  const int nl = static_cast<int>(J->live.size());
+  J->lay.assign(nl, ProbLayout());
+  J->dev.assign(nl, DevProblem());
+  J->pairs = 0;
+  J->mulmods = 0;
+  // stir chunking: enough blocks in flight to cover HBM latency
+  int64_t stir_base = 0;
+  for (int k : J->live) {
+    const Plan& P = J->plans[k];
+    stir_base += static_cast<int64_t>(P.np) * blocks_of(P.D + 1, 256);
+  }
+  J->crt_ns = 1;
+  for (int li = 0; li < nl; ++li) {
+    const Plan& P = J->plans[J->live[li]];
+    DevProblem& d = J->dev[li];
+    d = DevProblem{};
+    d.my = P.my;
+    d.ny = P.ny;
+    d.rowf = P.rowf;
+    d.rowg = P.rowg;
+    d.myp = (P.my + kRowGroup) / kRowGroup * kRowGroup;
+    d.nyp = (P.ny + kRowGroup) / kRowGroup * kRowGroup;
+    d.goff = P.rowf * d.myp;
+    d.CS = static_cast<int>(align_up(static_cast<size_t>(d.goff) + static_cast<size_t>(P.rowg) * d.nyp, 4));
+    d.ncoef = (P.my + 1) * P.rowf + (P.ny + 1) * P.rowg;
+    d.L_in = std::max(P.f.L, P.g.L);
+    d.D = P.D;
+    d.E = P.E;
+    d.origin = P.origin;
+    d.formal = P.formal;
+    d.np = P.np;
+    d.L_out = P.L_out;
+    int nch = 1;
+    if (stir_base < 4096) nch = static_cast<int>((4096 + stir_base - 1) / std::max<int64_t>(stir_base, 1));
+    nch = std::max(1, std::min(nch, (P.D + 1 + 127) / 128));
+    d.kchunk = (P.D + 1 + nch - 1) / nch;
+    d.nchunk = (P.D + 1 + d.kchunk - 1) / d.kchunk;
+    J->crt_ns = std::max(J->crt_ns, (P.np + 63) / 64);
+    J->pairs += static_cast<int64_t>(P.np) * (P.E + 1);
+    J->mulmods += pair_mulmods(P) * P.np * (P.E + 1);
+  }
+
+  // work items, problem by problem (so that each problem's items are contiguous)
+  for (int li = 0; li < nl; ++li) {
+    const Plan& P = J->plans[J->live[li]];
+    const DevProblem& d = J->dev[li];
+    ProbLayout& L = J->lay[li];
+    for (int s = 0; s < kNumStages; ++s) L.item_begin[s] = static_cast<int>(J->items[s].size());
+    for (int sl = 0; sl < P.np; ++sl)
+      for (int b = 0; b < blocks_of(d.CS, 256); ++b) J->items[kStageReduce].push_back({li, sl, b, 0});
+    for (int sl = 0; sl < P.np; ++sl)
+      for (int b = 0; b < blocks_of(P.E + 1, 64); ++b) J->items[kStageEval].push_back({li, sl, b, 0});
+    for (int sl = 0; sl < P.np; ++sl)
+      for (int b = 0; b < blocks_of(P.D + 1, 256); ++b) J->items[kStageConv].push_back({li, sl, b, 0});
+    for (int sl = 0; sl < P.np; ++sl)
+      for (int b = 0; b < blocks_of(P.D + 1, 256); ++b)
+        for (int ch = 0; ch < d.nchunk; ++ch) {
+          const int ke = std::min(P.D, (ch + 1) * d.kchunk - 1);
+          if (ke >= b * 256) J->items[kStageStir].push_back({li, sl, b, ch});
+        }
+    // gapped interpolation is possible only with a non-constant leading
+    // coefficient (bad points) or a shifted origin
+    if (P.origin != 0 || (!P.formal && P.s > 0))
+      for (int sl = 0; sl < P.np; ++sl) J->items[kStageNewton].push_back({li, sl, 0, 0});
+    for (int b = 0; b < blocks_of(P.D + 1, kCrtWaves); ++b) J->items[kStageCrt].push_back({li, -1, b, 0});
+    for (int s = 0; s < kNumStages; ++s) L.item_end[s] = static_cast<int>(J->items[s].size());
+  }
+
+  // device layout: [problems | items | inputs | statuses][outputs][intermediates]
+  const size_t A = 256;
+  size_t o = 0;
+  J->probs_off = o;
+  o = align_up(o + sizeof(DevProblem) * std::max(nl, 1), A);
+  for (int s = 0; s < kNumStages; ++s) {
+    J->items_off[s] = o;
+    o = align_up(o + sizeof(WorkItem) * J->items[s].size(), A);
+  }
+  for (int li = 0; li < nl; ++li) {
+    const Plan& P = J->plans[J->live[li]];
+    const DevProblem& d = J->dev[li];
+    ProbLayout& L = J->lay[li];
+    L.L_in = d.L_in;
+    L.coeff = o; o = align_up(o + static_cast<size_t>(d.ncoef) * d.L_in * 4, 16);
+    L.gdeg = o;  o = align_up(o + static_cast<size_t>(d.myp + d.nyp) / kRowGroup * 4, 16);
+    L.pidx = o;  o = align_up(o + static_cast<size_t>(P.np) * 4, 16);
+    L.Hm = o;    o = align_up(o + static_cast<size_t>(P.np) * 4, 16);
+    L.NH = o;    o = align_up(o + static_cast<size_t>(P.L_out) * 4, 16);
+    if (!P.canonical) {
+      L.Tg = o;    o = align_up(o + static_cast<size_t>(P.np) * P.np * 4, 16);
+      L.invM = o;  o = align_up(o + static_cast<size_t>(P.np) * 4, 16);
+      L.Plimb = o; o = align_up(o + static_cast<size_t>(P.np) * P.L_out * 4, 16);
+    }
+  }
+  o = align_up(o, A);
+  J->status_off = o;
+  for (int li = 0; li < nl; ++li) {
+    J->lay[li].status = o;
+    o += static_cast<size_t>(J->plans[J->live[li]].np + 2) * 4;
+  }
+  o = align_up(o, A);
+  J->status_bytes = o - J->status_off;
+  J->up_bytes = o;
+  J->down_off = J->status_off;
+  for (int li = 0; li < nl; ++li) {
+    const Plan& P = J->plans[J->live[li]];
+    J->lay[li].out = o;
+    o = align_up(o + static_cast<size_t>(P.D + 1) * P.L_out * 4, 16);
+  }
+  o = align_up(o, A);
+  J->down_bytes = o - J->down_off;
+  for (int li = 0; li < nl; ++li) {
+    const Plan& P = J->plans[J->live[li]];
+    const DevProblem& d = J->dev[li];
+    ProbLayout& L = J->lay[li];
+    const size_t np = P.np;
+    L.resid = o; o = align_up(o + np * d.CS * 4, A);
+    L.zval = o;  o = align_up(o + np * (P.E + 1) * 4, A);
+    L.zbad = o;  o = align_up(o + np * (P.E + 1), A);
+    L.aconv = o; o = align_up(o + np * (P.D + 1) * 4, A);
+    L.cpart = o; o = align_up(o + static_cast<size_t>(d.nchunk) * np * (P.D + 1) * 8, A);
+  }
+  J->queue_off = o;
+  J->queue_bytes = 0;
+  J->total = o;
+
+  // LDS per stage launch (max over problems)
+  for (int s = 0; s < kNumStages; ++s) J->stage_lds[s] = 0;
+  for (int li = 0; li < nl; ++li) {
+    const DevProblem& d = J->dev[li];
+    auto up = [&](int s, size_t words) { J->stage_lds[s] = std::max(J->stage_lds[s], words * 4); };
+    up(kStageEval, eval_lds_words(d));
+    up(kStageConv, static_cast<size_t>(2) * (std::min(d.D + 1, 256 * blocks_of(d.D + 1, 256))));
+    up(kStageStir, d.kchunk);
+    if (J->lay[li].item_end[kStageNewton] > J->lay[li].item_begin[kStageNewton]) up(kStageNewton, newton_lds_words(d, 1024));
+    up(kStageCrt, crt_lds_words(d, J->crt_ns, kCrtWaves));
+  }
+  for (int s = 0; s < kNumStages; ++s)
+    if (J->stage_lds[s] > static_cast<size_t>(kLdsWords) * 4) {
+      *err = "a stage needs more than 64 KB of LDS";
+      return RSL_EINVAL;
+    }
+  return RSL_OK;
+}
+
+void job_bind(Job* J, uint8_t* base) {
+  J->base = base;
+  const int nl = static_cast<int>(J->live.size());
+  J->blob.assign(J->up_bytes, 0);
+  uint8_t* blob = J->blob.data();
+  for (int li = 0; li < nl; ++li) {
+    const Plan& P = J->plans[J->live[li]];
+    const ProbLayout& L = J->lay[li];
+    DevProblem& d = J->dev[li];
+    // inputs: f rows 0..my (stride rowf) then g rows 0..ny (stride rowg),
+    // sign-extended to L_in limbs
+    uint32_t* c = reinterpret_cast<uint32_t*>(blob + L.coeff);
+    const int Li = L.L_in;
+    auto put = [&](const View& V, int rows, int rowstride, size_t first) {
+      for (int j = 0; j < rows; ++j)
+        for (int i = 0; i < rowstride; ++i) {
+          uint32_t* dst = c + (first + static_cast<size_t>(j) * rowstride + i) * Li;
+          if (i <= V.rdeg[j]) {
+            const uint32_t* src = &V.c[(static_cast<size_t>(j) * (V.dx + 1) + i) * V.L];
+            const uint32_t ext = (src[V.L - 1] >> 31) ? 0xFFFFFFFFu : 0u;
+            for (int l = 0; l < Li; ++l) dst[l] = (l < V.L) ? src[l] : ext;
+          } else {
+            for (int l = 0; l < Li; ++l) dst[l] = 0;
+          }
+        }
+    };
+    put(P.f, P.my + 1, P.rowf, 0);
+    put(P.g, P.ny + 1, P.rowg, static_cast<size_t>(P.my + 1) * P.rowf);
+    int* gd = reinterpret_cast<int*>(blob + L.gdeg);
+    const int gf = d.myp / kRowGroup, gg = d.nyp / kRowGroup;
+    for (int q = 0; q < gf; ++q) {
+      int m = -1;
+      for (int j = q * kRowGroup; j < (q + 1) * kRowGroup && j <= P.my; ++j) m = std::max(m, P.f.rdeg[j]);
+      gd[q] = m;
+    }
+    for (int q = 0; q < gg; ++q) {
+      int m = -1;
+      for (int j = q * kRowGroup; j < (q + 1) * kRowGroup && j <= P.ny; ++j) m = std::max(m, P.g.rdeg[j]);
+      gd[gf + q] = m;
+    }
+    std::memcpy(blob + L.pidx, P.pidx.data(), P.np * 4);
+    std::memcpy(blob + L.Hm, P.Hm.data(), P.np * 4);
+    std::memcpy(blob + L.NH, P.NH.data(), P.L_out * 4);
+    if (!P.canonical) {
+      std::memcpy(blob + L.Tg, P.Tg.data(), P.Tg.size() * 4);
+      std::memcpy(blob + L.invM, P.invM.data(), P.invM.size() * 4);
+      std::memcpy(blob + L.Plimb, P.Plimb.data(), P.Plimb.size() * 4);
+    }
+    // device pointers
+    d.coeff = reinterpret_cast<const uint32_t*>(base + L.coeff);
+    d.gdeg = reinterpret_cast<const int*>(base + L.gdeg);
+    d.pidx = reinterpret_cast<const int*>(base + L.pidx);
+    d.Hm = reinterpret_cast<const uint32_t*>(base + L.Hm);
+    d.NH = reinterpret_cast<const uint32_t*>(base + L.NH);
+    d.resid = reinterpret_cast<uint32_t*>(base + L.resid);
+    d.zval = reinterpret_cast<uint32_t*>(base + L.zval);
+    d.zbad = base + L.zbad;
+    d.aconv = reinterpret_cast<uint32_t*>(base + L.aconv);
+    d.cpart = reinterpret_cast<uint64_t*>(base + L.cpart);
+    d.out = reinterpret_cast<uint32_t*>(base + L.out);
+    d.status = reinterpret_cast<int*>(base + L.status);
+  }
+  std::memcpy(blob + J->probs_off, J->dev.data(), sizeof(DevProblem) * nl);
+  for (int s = 0; s < kNumStages; ++s)
+    if (!J->items[s].empty())
+      std::memcpy(blob + J->items_off[s], J->items[s].data(), sizeof(WorkItem) * J->items[s].size());
+}
+
+// CRT tables: canonical prime lists use the context's global tables.
+static void bind_crt_tables(const rsl_ctx* ctx, Job* J) {
+  const int nl = static_cast<int>(J->live.size());
+  for (int li = 0; li < nl; ++li) {
+    const Plan& P = J->plans[J->live[li]];
+    const ProbLayout& L = J->lay[li];
+    DevProblem& d = J->dev[li];
+    if (P.canonical) {
+      d.Tg = ctx->d_Tg;
+      d.tgs = ctx->npcap;
+      d.invM = ctx->d_invM;
+      d.Plimb = ctx->d_Plimb;
+      d.LP = ctx->LPg;
+    } else {
+      d.Tg = reinterpret_cast<const uint32_t*>(J->base + L.Tg);
+      d.tgs = P.np;
+      d.invM = reinterpret_cast<const uint32_t*>(J->base + L.invM);
+      d.Plimb = reinterpret_cast<const uint32_t*>(J->base + L.Plimb);
+      d.LP = P.L_out;
+    }
+  }
+  std::memcpy(J->blob.data() + J->probs_off, J->dev.data(), sizeof(DevProblem) * nl);
+}
+
+int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st) {
+  bind_crt_tables(ctx, J);
+  if (J->up_bytes == 0) return RSL_OK;
+  int rc = ensure_staging(ctx, J->up_bytes, J->down_bytes);
+  if (rc) return rc;
+  std::memcpy(ctx->h_up, J->blob.data(), J->up_bytes);
+  return hip_check(ctx, hipMemcpyAsync(J->base, ctx->h_up, J->up_bytes, hipMemcpyHostToDevice, st), "upload");
+}
+
+int job_reset(rsl_ctx* ctx, Job* J, hipStream_t st) {
+  if (J->status_bytes == 0) return RSL_OK;
+  return hip_check(ctx, hipMemsetAsync(J->base + J->status_off, 0, J->status_bytes, st), "status reset");
+}
+
+int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events) {
+  if (J->live.empty()) return RSL_OK;
+  const DevTables T = tables_of(ctx);
+  const DevProblem* probs = reinterpret_cast<const DevProblem*>(J->base + J->probs_off);
+  auto items = [&](int s) { return reinterpret_cast<const WorkItem*>(J->base + J->items_off[s]); };
+  int rc;
+  if (mode == RSL_PLAIN) {
+    for (size_t li = 0; li < J->live.size(); ++li) {
+      const ProbLayout& L = J->lay[li];
+      const int ns = (J->plans[J->live[li]].np + 63) / 64;
+      for (int s = 0; s < kNumStages; ++s) {
+        const int cnt = L.item_end[s] - L.item_begin[s];
+        if ((rc = hip_check(ctx, launch_stage(s, probs, items(s) + L.item_begin[s], cnt, J->stage_lds[s],
+                                              ns, T, st), "launch")))
+          return rc;
+      }
+    }
+    return RSL_OK;
+  }
+  for (int s = 0; s < kNumStages; ++s) {
+    if (stage_events && (rc = hip_check(ctx, hipEventRecord(ctx->ev[s], st), "event"))) return rc;
+    if ((rc = hip_check(ctx, launch_stage(s, probs, items(s), static_cast<int>(J->items[s].size()),
+                                          J->stage_lds[s], J->crt_ns, T, st), "launch")))
+      return rc;
+  }
+  if (stage_events && (rc = hip_check(ctx, hipEventRecord(ctx->ev[kNumStages], st), "event"))) return rc;
+  return RSL_OK;
+}
+
+int job_download(rsl_ctx* ctx, Job* J, uint8_t* host, hipStream_t st) {
+  if (J->down_bytes == 0) return RSL_OK;
+  return hip_check(ctx, hipMemcpyAsync(host, J->base + J->down_off, J->down_bytes, hipMemcpyDeviceToHost, st),
+                   "download");
+}
+
+int job_decode(rsl_ctx* ctx, const Job& J, const uint8_t* host, rsl_result* out, int* status, rsl_counters* cnt) {
+  std::vector<int> li_of(J.n, -1);
+  for (size_t li = 0; li < J.live.size(); ++li) li_of[J.live[li]] = static_cast<int>(li);
+  int first = RSL_OK;
+  for (int k = 0; k < J.n; ++k) {
+    int rc = J.pstatus[k];
+    const Plan& P = J.plans[k];
+    if (!rc) {
+      cnt->problems += 1;
+      if (P.zero) {
+        rc = decode_result(P, nullptr, &out[k]);
+      } else {
+        const int li = li_of[k];
+        const ProbLayout& L = J.lay[li];
+        const int* st = reinterpret_cast<const int*>(host + (L.status - J.down_off));
+        if (st[0] & kErrTooFewGoodPoints) {
+          rc = RSL_EPRIMES;
+          ctx->err = "fewer than D+1 good points for a prime";
+        } else {
+          rc = decode_result(P, reinterpret_cast<const uint32_t*>(host + (L.out - J.down_off)), &out[k]);
+          if (rc == RSL_ERANGE) ctx->err = "result buffer too small";
+        }
+        cnt->pairs += static_cast<int64_t>(P.np) * (P.E + 1);
+        cnt->bad_pairs += st[P.np + 1];
+        cnt->bad_primes += P.bad_primes;
+        for (int i = 0; i < P.np; ++i) cnt->slow_primes += st[1 + i];
+      }
+    }
+    if (status) status[k] = rc;
+    if (rc && !first) first = rc;
+  }
+  return first;
+}
+
+}  // namespace rsl

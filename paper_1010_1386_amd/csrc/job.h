@@ -1,0 +1,68 @@
+// A job: a planned batch of problems laid out in one device region, runnable
+// as one pipeline per problem (plain) or one launch per stage over all
+// problems (staged), or as a single persistent launch (batched).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rsl.h"
+#include "device.h"
+#include "plan.h"
+#include "stages.h"
+
+struct rsl_ctx;
+
+namespace rsl {
+
+struct ProbLayout {
+  // offsets from the job base
+  size_t coeff, gdeg, pidx, Hm, NH, Tg, invM, Plimb, status;
+  size_t out, resid, zval, zbad, aconv, cpart;
+  int L_in;
+  int item_begin[kNumStages], item_end[kNumStages];
+};
+
+struct Job {
+  int n = 0;                       // problems submitted
+  std::vector<Plan> plans;         // one per problem
+  std::vector<int> pstatus;        // planning status per problem (0 = ok)
+  std::vector<int> live;           // problems with device work, in launch order
+  std::vector<ProbLayout> lay;     // per live problem
+  std::vector<DevProblem> dev;     // per live problem (pointers valid for `base`)
+  std::vector<WorkItem> items[kNumStages];
+  size_t items_off[kNumStages] = {};
+  size_t stage_lds[kNumStages] = {};
+  int crt_ns = 1;
+  size_t probs_off = 0;
+  size_t up_bytes = 0;             // [0, up_bytes) is uploaded
+  size_t down_off = 0, down_bytes = 0;  // statuses + outputs, downloaded
+  size_t status_off = 0, status_bytes = 0;
+  size_t queue_off = 0, queue_bytes = 0;  // persistent-launch task queue
+  int queue_tasks = 0, queue_initial = 0;
+  size_t total = 0;
+  uint8_t* base = nullptr;         // device region the job is laid out in
+  std::vector<uint8_t> blob;       // host image of [0, up_bytes)
+  int64_t pairs = 0;
+  int64_t mulmods = 0;             // algorithmic work of eval + ures (see DESIGN)
+};
+
+// Plan every problem and lay the job out (host only).
+int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var, const rsl_opts* opts,
+              Job* J, std::string* err);
+// Bind the job to a device region (fills device pointers and the upload image).
+void job_bind(Job* J, uint8_t* base);
+// Upload the inputs (asynchronous on the stream, from pinned staging when given).
+int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st);
+// Zero the status words (before a re-run of a resident job).
+int job_reset(rsl_ctx* ctx, Job* J, hipStream_t st);
+// Launch the device pipeline: mode RSL_PLAIN (per problem) or RSL_BATCHED.
+int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events);
+// Download statuses and outputs (asynchronous) into `host` (down_bytes).
+int job_download(rsl_ctx* ctx, Job* J, uint8_t* host, hipStream_t st);
+// Decode the downloaded image into the callers' results.
+int job_decode(rsl_ctx* ctx, const Job& J, const uint8_t* host, rsl_result* out, int* status, rsl_counters* cnt);
+
+}  // namespace rsl

@@ -5,8 +5,11 @@
 
 namespace rsl {
 
-// reduce -> eval+ures -> interpolation (consecutive and gapped) -> CRT, on one stream.
-hipError_t launch_pipeline(const DevProblem& P, const DevTables& T, hipStream_t st);
+// One launch of stage `stage` (see stages.h) over `nitems` work items, one
+// block per item.  lds: dynamic LDS bytes; crt_ns: prime slots per lane of the
+// CRT kernel (ceil(max primes / 64)).
+hipError_t launch_stage(int stage, const DevProblem* probs, const WorkItem* items, int nitems, size_t lds,
+                        int crt_ns, const DevTables& T, hipStream_t st);
 
 // Stirling numbers of the first kind mod p_g for g in [g0, g0+count), rows 0..scap.
 hipError_t launch_stirling_build(uint32_t* stir, int64_t sstride, const PrimeConst* pcs, int g0,

@@ -1,0 +1,504 @@
+// Device code of the pipeline stages.  Each stage_* function processes one
+// work item with one thread block; the stage kernels (kernels.hip) and the
+// persistent batched kernel call the same functions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "device.h"
+#include "ures.h"
+
+namespace rsl {
+
+enum : int {
+  kStageReduce = 0,
+  kStageEval = 1,
+  kStageConv = 2,
+  kStageStir = 3,
+  kStageNewton = 4,
+  kStageCrt = 5,
+  kNumStages = 6,
+};
+
+constexpr int kCrtWaves = 8;          // coefficients per CRT block (one wave each)
+constexpr int kLdsWords = 16384;      // 64 KB of dynamic LDS per block at most
+
+// ------------------------------------------------------------------ helpers
+
+// acc + x y with acc kept below p 2^32 (one conditional subtraction on the high word)
+__device__ __forceinline__ uint64_t mac_fold(uint64_t acc, uint32_t x, uint32_t y, uint32_t p) {
+  acc += static_cast<uint64_t>(x) * y;
+  uint32_t hi = static_cast<uint32_t>(acc >> 32);
+  hi = umin32(hi, hi - p);
+  return (static_cast<uint64_t>(hi) << 32) | static_cast<uint32_t>(acc);
+}
+
+// a + b for a, b < p 2^32, result < p 2^32
+__device__ __forceinline__ uint64_t add_fold(uint64_t a, uint64_t b, uint32_t p) {
+  const uint64_t s = a + b;
+  uint32_t hi = static_cast<uint32_t>(s >> 32);
+  hi = umin32(hi, hi - p);
+  return (static_cast<uint64_t>(hi) << 32) | static_cast<uint32_t>(s);
+}
+
+// ------------------------------------------------------------------ reduce
+
+// Coefficient t of the prime's transposed tile: f part [i][j] (j padded to
+// myp), then g part [i][j] (j padded to nyp).  Stores c R^2 mod p (0 for padding).
+__device__ inline void stage_reduce(const DevProblem& P, const DevTables& T, const WorkItem& w) {
+  const int t = w.blk * blockDim.x + threadIdx.x;
+  if (t >= P.CS) return;
+  const PrimeConst pc = T.pc[P.pidx[w.slot]];
+  int in = -1;
+  if (t < P.goff) {
+    const int i = t / P.myp, j = t - i * P.myp;
+    if (j <= P.my) in = j * P.rowf + i;
+  } else {
+    const int u = t - P.goff;
+    const int i = u / P.nyp, j = u - i * P.nyp;
+    if (i < P.rowg && j <= P.ny) in = (P.my + 1) * P.rowf + j * P.rowg + i;
+  }
+  uint32_t v = 0;
+  if (in >= 0) {
+    const uint32_t* wd = P.coeff + static_cast<size_t>(in) * P.L_in;
+    // two's complement value mod p, top limb signed; -2^31 + 2p > 0 since p > 2^30
+    const int32_t top = static_cast<int32_t>(wd[P.L_in - 1]);
+    uint64_t r = static_cast<uint64_t>(static_cast<int64_t>(top) + 2 * static_cast<int64_t>(pc.p)) % pc.p;
+    for (int l = P.L_in - 2; l >= 0; --l) r = ((r << 32) | wd[l]) % pc.p;
+    v = mmul(static_cast<uint32_t>(r), pc.r3, pc.p, pc.pinv);
+  }
+  P.resid[static_cast<size_t>(w.slot) * P.CS + t] = v;
+}
+
+// -------------------------------------------------------------- eval + ures
+
+// LDS words needed by one eval block (one wave).
+__host__ __device__ inline int eval_lds_words(const DevProblem& P) {
+  const int nm1 = (P.my > P.ny ? P.my : P.ny) + 1;
+  return P.CS + 2 * nm1 * 64;
+}
+
+// One wave: 64 consecutive points of one prime.  The prime's coefficient tile
+// is copied to LDS once; Horner then runs on kRowGroup rows of f and of g at a
+// time (eight independent chains per lane), each step reading kRowGroup
+// coefficients with one broadcast LDS load.  The values f_j(x_i), g_j(x_i) go
+// to two LDS columns per lane and the univariate resultant runs there.
+__device__ inline void stage_eval_ures(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
+  const int lane = threadIdx.x;
+  const PrimeConst pc = T.pc[P.pidx[w.slot]];
+  const uint32_t p = pc.p, pinv = pc.pinv;
+  uint32_t* tile = lds;
+  const uint32_t* src = P.resid + static_cast<size_t>(w.slot) * P.CS;
+  for (int t = lane; t < P.CS; t += 64) tile[t] = src[t];
+  __syncthreads();
+
+  const int nm1 = (P.my > P.ny ? P.my : P.ny) + 1;
+  uint32_t* cols = lds + P.CS;
+  Column<64> A{cols + lane};
+  Column<64> B{cols + nm1 * 64 + lane};
+  const int pt = w.blk * 64 + lane;
+  const uint32_t x = static_cast<uint32_t>(P.origin + (pt < P.E ? pt : P.E));
+  const uint32_t xt = mmul(x, pc.r2, p, pinv);
+
+  const int gf = P.myp / kRowGroup, gg = P.nyp / kRowGroup;
+  const int ng = gf > gg ? gf : gg;
+  const uint32_t* ftile = tile;
+  const uint32_t* gtile = tile + P.goff;
+  for (int q = 0; q < ng; ++q) {
+    const int df = (q < gf) ? P.gdeg[q] : -1;
+    const int dg = (q < gg) ? P.gdeg[gf + q] : -1;
+    const int d = df > dg ? df : dg;
+    uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+    for (int i = d; i >= 0; --i) {
+      if (i <= df) {
+        const uint4 c = *reinterpret_cast<const uint4*>(ftile + i * P.myp + kRowGroup * q);
+        a0 = redc(static_cast<uint64_t>(a0) * xt + c.x, p, pinv);
+        a1 = redc(static_cast<uint64_t>(a1) * xt + c.y, p, pinv);
+        a2 = redc(static_cast<uint64_t>(a2) * xt + c.z, p, pinv);
+        a3 = redc(static_cast<uint64_t>(a3) * xt + c.w, p, pinv);
+      }
+      if (i <= dg) {
+        const uint4 c = *reinterpret_cast<const uint4*>(gtile + i * P.nyp + kRowGroup * q);
+        b0 = redc(static_cast<uint64_t>(b0) * xt + c.x, p, pinv);
+        b1 = redc(static_cast<uint64_t>(b1) * xt + c.y, p, pinv);
+        b2 = redc(static_cast<uint64_t>(b2) * xt + c.z, p, pinv);
+        b3 = redc(static_cast<uint64_t>(b3) * xt + c.w, p, pinv);
+      }
+    }
+    const int j = kRowGroup * q;
+    if (j <= P.my) A[j] = a0;
+    if (j + 1 <= P.my) A[j + 1] = a1;
+    if (j + 2 <= P.my) A[j + 2] = a2;
+    if (j + 3 <= P.my) A[j + 3] = a3;
+    if (j <= P.ny) B[j] = b0;
+    if (j + 1 <= P.ny) B[j + 1] = b1;
+    if (j + 2 <= P.ny) B[j + 2] = b2;
+    if (j + 3 <= P.ny) B[j + 3] = b3;
+  }
+  bool bad = false;
+  const uint32_t r = ures_formal(A, B, P.my, P.ny, pc, &bad);
+  const bool live = pt <= P.E;
+  if (live) {
+    const size_t o = static_cast<size_t>(w.slot) * (P.E + 1) + pt;
+    P.zval[o] = redc(r, p, pinv);
+    P.zbad[o] = bad ? 1 : 0;
+  }
+  const uint64_t nbad = __ballot(live && bad);
+  if (lane == 0 && nbad) atomicAdd(P.status + 1 + P.np, static_cast<int>(__popcll(nbad)));
+}
+
+// ------------------------------------------------------------ interpolation
+
+// The consecutive fast path applies when the D+1 points used are 0..D: always
+// with formal-degree values at origin 0, otherwise when none of the points
+// 0..D was flagged bad.  Block-uniform result (all threads must call it).
+__device__ inline bool fast_prime(const DevProblem& P, int slot) {
+  if (P.origin != 0) return false;
+  if (P.formal) return true;
+  const uint8_t* zb = P.zbad + static_cast<size_t>(slot) * (P.E + 1);
+  int any = 0;
+  for (int i = threadIdx.x; i <= P.D; i += blockDim.x) any |= zb[i];
+  return __syncthreads_or(any) == 0;
+}
+
+// Newton forward differences at 0..D as a convolution:
+//   a_k = Delta^k z_0 / k! = sum_{i<=k} (z_i / i!) ((-1)^(k-i) / (k-i)!)
+__device__ inline void stage_interp_conv(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
+  if (!fast_prime(P, w.slot)) return;
+  const int g = P.pidx[w.slot];
+  const PrimeConst pc = T.pc[g];
+  const uint32_t p = pc.p, pinv = pc.pinv;
+  const uint32_t* ifact = T.ifact + static_cast<size_t>(g) * T.kstride;
+  const int nt = blockDim.x;
+  const int k0 = w.blk * nt;
+  const int kmax = (k0 + nt - 1 < P.D) ? k0 + nt - 1 : P.D;
+  uint32_t* alpha = lds;
+  uint32_t* beta = lds + (kmax + 1);
+  const uint32_t* z = P.zval + static_cast<size_t>(w.slot) * (P.E + 1);
+  for (int i = threadIdx.x; i <= kmax; i += nt) {
+    const uint32_t f = ifact[i];
+    alpha[i] = mmul(z[i], f, p, pinv);    // z_i / i!          (normal form)
+    beta[i] = (i & 1) ? mneg(f, p) : f;   // (-1)^i / i! R     (Montgomery form)
+  }
+  __syncthreads();
+  const int k = k0 + threadIdx.x;
+  if (k > P.D) return;
+  uint64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+  int i = 0;
+  for (; i + 3 <= k; i += 4) {
+    c0 = mac_fold(c0, alpha[i], beta[k - i], p);
+    c1 = mac_fold(c1, alpha[i + 1], beta[k - i - 1], p);
+    c2 = mac_fold(c2, alpha[i + 2], beta[k - i - 2], p);
+    c3 = mac_fold(c3, alpha[i + 3], beta[k - i - 3], p);
+  }
+  for (; i <= k; ++i) c0 = mac_fold(c0, alpha[i], beta[k - i], p);
+  const uint64_t acc = add_fold(add_fold(c0, c1, p), add_fold(c2, c3, p), p);
+  P.aconv[static_cast<size_t>(w.slot) * (P.D + 1) + k] = redc(acc, p, pinv);
+}
+
+// Falling-factorial basis -> monomials, one k-chunk of the sum
+//   c_j = sum_{k >= j} a_k s(k, j)
+// written as a partial sum (REDC of the sum over chunks is c_j).
+__device__ inline void stage_interp_stir(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
+  if (!fast_prime(P, w.slot)) return;
+  const int g = P.pidx[w.slot];
+  const PrimeConst pc = T.pc[g];
+  const uint32_t p = pc.p;
+  const int nt = blockDim.x;
+  const int j0 = w.blk * nt;
+  const int j = j0 + threadIdx.x;
+  const int kb = w.sub * P.kchunk;
+  const int ke = (kb + P.kchunk - 1 < P.D) ? kb + P.kchunk - 1 : P.D;
+  const int ks = kb > j0 ? kb : j0;
+  const uint32_t* a = P.aconv + static_cast<size_t>(w.slot) * (P.D + 1);
+  for (int k = ks + threadIdx.x; k <= ke; k += nt) lds[k - ks] = a[k];
+  __syncthreads();
+  const uint32_t* S = T.stir + static_cast<int64_t>(g) * T.sstride;
+  uint64_t c0 = 0, c1 = 0;
+  int k = ks;
+  for (; k + 3 <= ke; k += 4) {
+    const int64_t o0 = static_cast<int64_t>(k) * (k + 1) / 2;
+    const int64_t o1 = o0 + k + 1, o2 = o1 + k + 2, o3 = o2 + k + 3;
+    const uint32_t s0 = (j <= k) ? S[o0 + j] : 0u;
+    const uint32_t s1 = (j <= k + 1) ? S[o1 + j] : 0u;
+    const uint32_t s2 = (j <= k + 2) ? S[o2 + j] : 0u;
+    const uint32_t s3 = (j <= k + 3) ? S[o3 + j] : 0u;
+    c0 = mac_fold(c0, lds[k - ks], s0, p);
+    c1 = mac_fold(c1, lds[k + 1 - ks], s1, p);
+    c0 = mac_fold(c0, lds[k + 2 - ks], s2, p);
+    c1 = mac_fold(c1, lds[k + 3 - ks], s3, p);
+  }
+  for (; k <= ke; ++k) {
+    const int64_t o = static_cast<int64_t>(k) * (k + 1) / 2;
+    if (j <= k) c0 = mac_fold(c0, lds[k - ks], S[o + j], p);
+  }
+  if (j <= P.D) P.cpart[(static_cast<size_t>(w.sub) * P.np + w.slot) * (P.D + 1) + j] = add_fold(c0, c1, p);
+}
+
+// LDS words of the gapped-interpolation block.
+__host__ __device__ inline int newton_lds_words(const DevProblem& P, int nthreads) {
+  const int e1 = P.E + 1;
+  return 3 * e1 + (e1 > nthreads ? e1 : nthreads);
+}
+
+// Gapped point sets (bad points replaced, or a shifted origin): one block per
+// prime; select the first D+1 usable points, Newton divided differences, then
+// the Newton form expanded in the monomial basis by Horner.
+__device__ inline void stage_interp_newton(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int slot = w.slot;
+  const bool fast = fast_prime(P, slot);
+  if (tid == 0) P.status[1 + slot] = fast ? 0 : 1;
+  if (fast) return;
+  const int g = P.pidx[slot];
+  const PrimeConst pc = T.pc[g];
+  const uint32_t p = pc.p, pinv = pc.pinv;
+  const int E = P.E, D = P.D;
+  const uint32_t* fact = T.fact + static_cast<size_t>(g) * T.kstride;
+  const uint32_t* ifact = T.ifact + static_cast<size_t>(g) * T.kstride;
+  const uint32_t* z = P.zval + static_cast<size_t>(slot) * (E + 1);
+  const uint8_t* zb = P.zbad + static_cast<size_t>(slot) * (E + 1);
+
+  uint32_t* xs = lds;                 // E+1: selected point indices
+  uint32_t* d0 = xs + (E + 1);        // E+1
+  uint32_t* invt = d0 + (E + 1);      // E+1: 1/t R mod p
+  uint32_t* d1 = invt + (E + 1);      // max(E+1, nt); also the scan buffer
+  int* cnt = reinterpret_cast<int*>(d1);
+
+  for (int t = tid + 1; t <= E; t += nt) invt[t] = mmul(ifact[t], fact[t - 1], p, pinv);
+
+  // selection: first D+1 usable points (all points in formal mode)
+  const int chunk = (E + 1 + nt - 1) / nt;
+  const int lo = tid * chunk;
+  const int hi = (lo + chunk < E + 1) ? lo + chunk : E + 1;
+  int c = 0;
+  for (int i = lo; i < hi; ++i) c += (P.formal || !zb[i]) ? 1 : 0;
+  cnt[tid] = c;
+  __syncthreads();
+  for (int off = 1; off < nt; off <<= 1) {  // inclusive Hillis-Steele scan
+    const int v = (tid >= off) ? cnt[tid - off] : 0;
+    __syncthreads();
+    cnt[tid] += v;
+    __syncthreads();
+  }
+  const int total = cnt[nt - 1];
+  int q = cnt[tid] - c;
+  __syncthreads();
+  if (total < D + 1) {
+    if (tid == 0) atomicOr(P.status, kErrTooFewGoodPoints);
+    return;  // block-uniform
+  }
+  for (int i = lo; i < hi && q <= D; ++i)
+    if (P.formal || !zb[i]) {
+      xs[q] = static_cast<uint32_t>(i);
+      d0[q] = z[i];
+      ++q;
+    }
+  __syncthreads();
+
+  // divided differences, level by level (ping-pong buffers)
+  uint32_t* cur = d0;
+  uint32_t* nxt = d1;
+  for (int k = 1; k <= D; ++k) {
+    for (int i = tid; i <= D; i += nt) {
+      if (i >= k) {
+        const uint32_t diff = msubm(cur[i], cur[i - 1], p);
+        nxt[i] = mmul(diff, invt[xs[i] - xs[i - k]], p, pinv);
+      } else {
+        nxt[i] = cur[i];
+      }
+    }
+    __syncthreads();
+    uint32_t* t = cur; cur = nxt; nxt = t;
+  }
+  // Newton form -> monomials: P <- P (x - x_k) + a_k, k = D-1 .. 0
+  uint32_t* coef = invt;  // the inverse table is no longer needed
+  for (int i = tid; i <= D; i += nt) coef[i] = cur[i];
+  __syncthreads();
+  uint32_t* pa = nxt;
+  uint32_t* pb = cur;
+  if (tid == 0) pa[0] = coef[D];
+  __syncthreads();
+  for (int k = D - 1; k >= 0; --k) {
+    const uint32_t xk = static_cast<uint32_t>(P.origin) + xs[k];
+    const uint32_t xkt = mmul(xk, pc.r2, p, pinv);
+    const int deg = D - k;  // degree after this step
+    for (int j = tid; j <= deg; j += nt) {
+      const uint32_t left = (j > 0) ? pa[j - 1] : 0u;
+      const uint32_t mid = (j < deg) ? pa[j] : 0u;
+      uint32_t v = msubm(left, mmul(mid, xkt, p, pinv), p);
+      if (j == 0) v = maddm(v, coef[k], p);
+      pb[j] = v;
+    }
+    __syncthreads();
+    uint32_t* t = pa; pa = pb; pb = t;
+  }
+  // chunk 0 carries c_j 2^32 (REDC gives c_j); the other chunks are zero
+  for (int j = tid; j <= D; j += nt) {
+    P.cpart[static_cast<size_t>(slot) * (D + 1) + j] = static_cast<uint64_t>(pa[j]) << 32;
+    for (int ch = 1; ch < P.nchunk; ++ch)
+      P.cpart[(static_cast<size_t>(ch) * P.np + slot) * (D + 1) + j] = 0;
+  }
+}
+
+// ----------------------------------------------------------------------- CRT
+
+// Whether the Garner table of a problem is staged in LDS by the CRT kernel,
+// and the CRT block's LDS words.
+__host__ __device__ inline bool crt_stage_tg(const DevProblem& P, int ns, int nwaves) {
+  return P.np * P.np + nwaves * (3 * 64 * ns + 4) <= kLdsWords;
+}
+__host__ __device__ inline int crt_lds_words(const DevProblem& P, int ns, int nwaves) {
+  return (crt_stage_tg(P, ns, nwaves) ? P.np * P.np : 0) + nwaves * (3 * 64 * ns + 4);
+}
+
+// One wave per coefficient k.  Garner: lanes own primes (slot i = lane + 64 r);
+// digit v_j is formed in lane j and broadcast, then every lane i > j adds
+// v_j (prod_{l<j} p_l mod p_i).  Radix conversion: lanes own output limbs,
+// S_t = NH_t + sum_j v_j limb_t(prod_{l<j} p_l) in 96 bits, then carries are
+// resolved with wave ballots.  The result is (Y - H) mod 2^(32 L_out) with
+// Y = sum_j v_j prod_{l<j} p_l in [0, M) and H = (M-1)/2: the symmetric residue.
+template <int NS>
+__device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
+  const int nw = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int k_raw = w.blk * nw + wave;
+  const bool valid = k_raw <= P.D;
+  const int k = valid ? k_raw : P.D;
+  const int np = P.np;
+  const bool staged = crt_stage_tg(P, NS, nw);
+  uint32_t* tg = lds;
+  uint32_t* wb = lds + (staged ? np * np : 0) + wave * (3 * 64 * NS + 4);
+  uint32_t* vbuf = wb;
+  uint32_t* sb = wb + 64 * NS;
+  uint32_t* sc = sb + 64 * NS + 2;
+  if (staged) {
+    for (int t = threadIdx.x; t < np * np; t += blockDim.x) {
+      const int j = t / np, i = t - j * np;
+      tg[t] = P.Tg[static_cast<size_t>(j) * P.tgs + i];
+    }
+  }
+  __syncthreads();
+
+  uint32_t u[NS], acc[NS], pp[NS], pinv[NS], invm[NS];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    const int i = lane + 64 * r;
+    acc[r] = 0;
+    if (i < np) {
+      const PrimeConst pc = T.pc[P.pidx[i]];
+      pp[r] = pc.p;
+      pinv[r] = pc.pinv;
+      uint64_t cs = 0;
+      for (int ch = 0; ch < P.nchunk; ++ch)
+        cs = add_fold(cs, P.cpart[(static_cast<size_t>(ch) * np + i) * (P.D + 1) + k], pc.p);
+      u[r] = maddm(redc(cs, pc.p, pc.pinv), P.Hm[i], pc.p);
+      invm[r] = P.invM[i];
+    } else {
+      pp[r] = 3u; pinv[r] = 0u; u[r] = 0u; invm[r] = 0u;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    for (int jj = 0; jj < 64; ++jj) {
+      const int j = r * 64 + jj;
+      if (j >= np) break;
+      const uint32_t vloc = mmul(msubm(u[r], acc[r], pp[r]), invm[r], pp[r], pinv[r]);
+      const uint32_t vj = __builtin_amdgcn_readlane(vloc, jj);
+      if (lane == 0) vbuf[j] = vj;
+#pragma unroll
+      for (int rr = r; rr < NS; ++rr) {
+        const int i = lane + 64 * rr;
+        if (i > j && i < np) {
+          const uint32_t tji = staged ? tg[j * np + i] : P.Tg[static_cast<size_t>(j) * P.tgs + i];
+          acc[rr] = maddm(acc[rr], mmul(vj, tji, pp[rr], pinv[rr]), pp[rr]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // radix conversion: 96-bit column sums per output limb
+  const int L = P.L_out;
+  uint64_t lo[NS];
+  uint32_t hc[NS];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    const int t = lane + 64 * r;
+    lo[r] = (t < L) ? P.NH[t] : 0u;
+    hc[r] = 0u;
+  }
+  int j = 0;
+  for (; j + 1 < np; j += 2) {
+    const uint32_t v0 = vbuf[j], v1 = vbuf[j + 1];
+    const uint32_t* p0 = P.Plimb + static_cast<size_t>(j) * P.LP;
+    const uint32_t* p1 = p0 + P.LP;
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      const int t = lane + 64 * r;
+      if (t < L) {
+        const uint64_t q0 = static_cast<uint64_t>(v0) * p0[t];
+        const uint64_t q1 = static_cast<uint64_t>(v1) * p1[t];
+        lo[r] += q0;
+        hc[r] += (lo[r] < q0) ? 1u : 0u;
+        lo[r] += q1;
+        hc[r] += (lo[r] < q1) ? 1u : 0u;
+      }
+    }
+  }
+  for (; j < np; ++j) {
+    const uint32_t vj = vbuf[j];
+    const uint32_t* pl = P.Plimb + static_cast<size_t>(j) * P.LP;
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      const int t = lane + 64 * r;
+      if (t < L) {
+        const uint64_t prod = static_cast<uint64_t>(vj) * pl[t];
+        lo[r] += prod;
+        hc[r] += (lo[r] < prod) ? 1u : 0u;
+      }
+    }
+  }
+  // limb t receives lo32(S_t) + hi32(S_{t-1}) + top32(S_{t-2})
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    const int t = lane + 64 * r;
+    sb[t + 1] = static_cast<uint32_t>(lo[r] >> 32);
+    sc[t + 2] = hc[r];
+  }
+  if (lane == 0) { sb[0] = 0; sc[0] = 0; sc[1] = 0; }
+  __syncthreads();
+  uint32_t l1[NS], h1[NS];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    const int t = lane + 64 * r;
+    const uint64_t wv = static_cast<uint64_t>(static_cast<uint32_t>(lo[r])) + sb[t] + sc[t];
+    l1[r] = static_cast<uint32_t>(wv);
+    h1[r] = static_cast<uint32_t>(wv >> 32);  // <= 2
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < NS; ++r) sb[lane + 64 * r + 1] = h1[r];
+  __syncthreads();
+  uint64_t cin = 0;
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    const int t = lane + 64 * r;
+    const uint64_t x2 = static_cast<uint64_t>(l1[r]) + sb[t];
+    const uint32_t l2 = static_cast<uint32_t>(x2);
+    const bool gen = (x2 >> 32) != 0 && t < L;
+    const bool prop = (l2 == 0xFFFFFFFFu) && t < L;
+    const uint64_t G = __ballot(gen);
+    const uint64_t Pm = __ballot(prop);
+    const uint64_t X = G | Pm;
+    const unsigned __int128 tot = static_cast<unsigned __int128>(X) + G + cin;
+    const uint64_t S = static_cast<uint64_t>(tot);
+    const uint64_t C = S ^ X ^ G;  // carry into each limb of this group
+    cin = static_cast<uint64_t>(tot >> 64);
+    const uint32_t limb = l2 + static_cast<uint32_t>((C >> lane) & 1u);
+    if (valid && t < L) P.out[static_cast<size_t>(k) * L + t] = limb;
+  }
+}
+
+}  // namespace rsl

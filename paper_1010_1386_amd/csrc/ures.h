@@ -100,7 +100,17 @@ RSL_HD uint32_t ures_formal(Col A, Col B, int m, int n, const PrimeConst& pc, bo
       const uint32_t beta = mneg(mmul(L, lcA, p, pinv), p);
       const uint32_t gamma = mneg(lcAt, p);
       uint32_t prevB = 0u;
-      for (int j = 0; j < b; ++j) {
+      int j = 0;
+      for (; j + 4 <= b; j += 4) {  // four independent updates per trip (ILP)
+        const uint32_t b0 = B[j], b1 = B[j + 1], b2 = B[j + 2], b3 = B[j + 3];
+        const uint32_t a0 = A[j], a1 = A[j + 1], a2 = A[j + 2], a3 = A[j + 3];
+        A[j] = mmad3(alpha, a0, beta, prevB, gamma, b0, p, pinv);
+        A[j + 1] = mmad3(alpha, a1, beta, b0, gamma, b1, p, pinv);
+        A[j + 2] = mmad3(alpha, a2, beta, b1, gamma, b2, p, pinv);
+        A[j + 3] = mmad3(alpha, a3, beta, b2, gamma, b3, p, pinv);
+        prevB = b3;
+      }
+      for (; j < b; ++j) {
         const uint32_t bj = B[j];
         A[j] = mmad3(alpha, A[j], beta, prevB, gamma, bj, p, pinv);
         prevB = bj;

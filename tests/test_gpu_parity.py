@@ -129,3 +129,20 @@ def test_prime_table_exhaustion_is_reported(ctx):
     with pytest.raises(rsl.RSLError) as ei:
         ctx.res(F, G, prime_limit=2)
     assert ei.value.code == rsl.RSL_EPRIMES
+
+
+def _digest(coeffs):
+    import hashlib
+    return hashlib.sha256(",".join(str(c) for c in coeffs).encode()).hexdigest()
+
+
+@pytest.mark.parametrize("var", ["y", "x"])
+def test_config2_matches_golden_digest(ctx, var):
+    """Dense total degree 24, signed 32-bit: res_y and res_x bit-exact (SHA-256 of all coefficients)."""
+    f, g = workloads.config2()
+    rec = _golden(2)[f"cfg2_{var}"]
+    got = ctx.res(f, g, var)
+    assert len(got) - 1 == rec["degree"]
+    for i, v in rec["samples"].items():
+        assert got[int(i)] == int(v)
+    assert _digest(got) == rec["sha256"]
