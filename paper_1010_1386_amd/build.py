@@ -26,7 +26,7 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed fp32 forms are never wanted in this integer code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wall", "-Wno-unused-result"]
+         "-fno-strict-aliasing", "-Wall", "-Wno-unused-result"]
 
 
 def hipcc():

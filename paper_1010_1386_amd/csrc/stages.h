@@ -41,6 +41,47 @@ __device__ __forceinline__ uint64_t add_fold(uint64_t a, uint64_t b, uint32_t p)
   return (static_cast<uint64_t>(hi) << 32) | static_cast<uint32_t>(s);
 }
 
+// Lazy Horner steps acc <- REDC(acc x~ + c) with acc kept in [0, 2p): the
+// input stays below 2p^2 + p < p 2^32, so REDC's bound holds without the final
+// conditional subtraction.  The phases of the independent chains are written
+// interleaved so that each dependent instruction has others to hide behind.
+__device__ __forceinline__ void horner_step4(uint32_t* a, const uint4 c, uint32_t xt, uint32_t p, uint32_t pinv) {
+  const uint64_t t0 = static_cast<uint64_t>(a[0]) * xt + c.x;
+  const uint64_t t1 = static_cast<uint64_t>(a[1]) * xt + c.y;
+  const uint64_t t2 = static_cast<uint64_t>(a[2]) * xt + c.z;
+  const uint64_t t3 = static_cast<uint64_t>(a[3]) * xt + c.w;
+  const uint32_t m0 = static_cast<uint32_t>(t0) * pinv, m1 = static_cast<uint32_t>(t1) * pinv;
+  const uint32_t m2 = static_cast<uint32_t>(t2) * pinv, m3 = static_cast<uint32_t>(t3) * pinv;
+  a[0] = static_cast<uint32_t>((t0 + static_cast<uint64_t>(m0) * p) >> 32);
+  a[1] = static_cast<uint32_t>((t1 + static_cast<uint64_t>(m1) * p) >> 32);
+  a[2] = static_cast<uint32_t>((t2 + static_cast<uint64_t>(m2) * p) >> 32);
+  a[3] = static_cast<uint32_t>((t3 + static_cast<uint64_t>(m3) * p) >> 32);
+}
+
+__device__ __forceinline__ void horner_step8(uint32_t* a, uint32_t* b, const uint4 c, const uint4 d, uint32_t xt,
+                                             uint32_t p, uint32_t pinv) {
+  const uint64_t t0 = static_cast<uint64_t>(a[0]) * xt + c.x;
+  const uint64_t t1 = static_cast<uint64_t>(a[1]) * xt + c.y;
+  const uint64_t t2 = static_cast<uint64_t>(a[2]) * xt + c.z;
+  const uint64_t t3 = static_cast<uint64_t>(a[3]) * xt + c.w;
+  const uint64_t t4 = static_cast<uint64_t>(b[0]) * xt + d.x;
+  const uint64_t t5 = static_cast<uint64_t>(b[1]) * xt + d.y;
+  const uint64_t t6 = static_cast<uint64_t>(b[2]) * xt + d.z;
+  const uint64_t t7 = static_cast<uint64_t>(b[3]) * xt + d.w;
+  const uint32_t m0 = static_cast<uint32_t>(t0) * pinv, m1 = static_cast<uint32_t>(t1) * pinv;
+  const uint32_t m2 = static_cast<uint32_t>(t2) * pinv, m3 = static_cast<uint32_t>(t3) * pinv;
+  const uint32_t m4 = static_cast<uint32_t>(t4) * pinv, m5 = static_cast<uint32_t>(t5) * pinv;
+  const uint32_t m6 = static_cast<uint32_t>(t6) * pinv, m7 = static_cast<uint32_t>(t7) * pinv;
+  a[0] = static_cast<uint32_t>((t0 + static_cast<uint64_t>(m0) * p) >> 32);
+  a[1] = static_cast<uint32_t>((t1 + static_cast<uint64_t>(m1) * p) >> 32);
+  a[2] = static_cast<uint32_t>((t2 + static_cast<uint64_t>(m2) * p) >> 32);
+  a[3] = static_cast<uint32_t>((t3 + static_cast<uint64_t>(m3) * p) >> 32);
+  b[0] = static_cast<uint32_t>((t4 + static_cast<uint64_t>(m4) * p) >> 32);
+  b[1] = static_cast<uint32_t>((t5 + static_cast<uint64_t>(m5) * p) >> 32);
+  b[2] = static_cast<uint32_t>((t6 + static_cast<uint64_t>(m6) * p) >> 32);
+  b[3] = static_cast<uint32_t>((t7 + static_cast<uint64_t>(m7) * p) >> 32);
+}
+
 // ------------------------------------------------------------------ reduce
 
 // Coefficient t of the prime's transposed tile: f part [i][j] (j padded to
@@ -105,35 +146,36 @@ __device__ inline void stage_eval_ures(const DevProblem& P, const DevTables& T, 
   const uint32_t* ftile = tile;
   const uint32_t* gtile = tile + P.goff;
   for (int q = 0; q < ng; ++q) {
-    const int df = (q < gf) ? P.gdeg[q] : -1;
-    const int dg = (q < gg) ? P.gdeg[gf + q] : -1;
-    const int d = df > dg ? df : dg;
-    uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
-    for (int i = d; i >= 0; --i) {
-      if (i <= df) {
-        const uint4 c = *reinterpret_cast<const uint4*>(ftile + i * P.myp + kRowGroup * q);
-        a0 = redc(static_cast<uint64_t>(a0) * xt + c.x, p, pinv);
-        a1 = redc(static_cast<uint64_t>(a1) * xt + c.y, p, pinv);
-        a2 = redc(static_cast<uint64_t>(a2) * xt + c.z, p, pinv);
-        a3 = redc(static_cast<uint64_t>(a3) * xt + c.w, p, pinv);
+    // group degrees are uniform: keep them (and the loop bounds) in SGPRs
+    const int df = __builtin_amdgcn_readfirstlane((q < gf) ? P.gdeg[q] : -1);
+    const int dg = __builtin_amdgcn_readfirstlane((q < gg) ? P.gdeg[gf + q] : -1);
+    const int dboth = df < dg ? df : dg;
+    uint32_t a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0};
+    const uint32_t* fq = ftile + kRowGroup * q;
+    const uint32_t* gq = gtile + kRowGroup * q;
+    int i = df > dg ? df : dg;
+    for (; i > dboth; --i) {  // only the higher-degree tile is active
+      if (i <= df) horner_step4(a, *reinterpret_cast<const uint4*>(fq + i * P.myp), xt, p, pinv);
+      else horner_step4(b, *reinterpret_cast<const uint4*>(gq + i * P.nyp), xt, p, pinv);
+    }
+    if (i >= 0) {  // both tiles: eight independent chains, next rows prefetched
+      uint4 cf = *reinterpret_cast<const uint4*>(fq + i * P.myp);
+      uint4 cg = *reinterpret_cast<const uint4*>(gq + i * P.nyp);
+      for (; i > 0; --i) {
+        const uint4 nf = *reinterpret_cast<const uint4*>(fq + (i - 1) * P.myp);
+        const uint4 ng = *reinterpret_cast<const uint4*>(gq + (i - 1) * P.nyp);
+        horner_step8(a, b, cf, cg, xt, p, pinv);
+        cf = nf;
+        cg = ng;
       }
-      if (i <= dg) {
-        const uint4 c = *reinterpret_cast<const uint4*>(gtile + i * P.nyp + kRowGroup * q);
-        b0 = redc(static_cast<uint64_t>(b0) * xt + c.x, p, pinv);
-        b1 = redc(static_cast<uint64_t>(b1) * xt + c.y, p, pinv);
-        b2 = redc(static_cast<uint64_t>(b2) * xt + c.z, p, pinv);
-        b3 = redc(static_cast<uint64_t>(b3) * xt + c.w, p, pinv);
-      }
+      horner_step8(a, b, cf, cg, xt, p, pinv);
     }
     const int j = kRowGroup * q;
-    if (j <= P.my) A[j] = a0;
-    if (j + 1 <= P.my) A[j + 1] = a1;
-    if (j + 2 <= P.my) A[j + 2] = a2;
-    if (j + 3 <= P.my) A[j + 3] = a3;
-    if (j <= P.ny) B[j] = b0;
-    if (j + 1 <= P.ny) B[j + 1] = b1;
-    if (j + 2 <= P.ny) B[j + 2] = b2;
-    if (j + 3 <= P.ny) B[j + 3] = b3;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (j + r <= P.my) A[j + r] = umin32(a[r], a[r] - p);  // Horner keeps values below 2p
+      if (j + r <= P.ny) B[j + r] = umin32(b[r], b[r] - p);
+    }
   }
   bool bad = false;
   const uint32_t r = ures_formal(A, B, P.my, P.ny, pc, &bad);
@@ -333,23 +375,31 @@ __device__ inline void stage_interp_newton(const DevProblem& P, const DevTables&
     __syncthreads();
     uint32_t* t = pa; pa = pb; pb = t;
   }
-  // chunk 0 carries c_j 2^32 (REDC gives c_j); the other chunks are zero
+  // the first chunk the CRT reads for coefficient j carries c_j 2^32 (REDC gives
+  // c_j); the later chunks are zero
   for (int j = tid; j <= D; j += nt) {
-    P.cpart[static_cast<size_t>(slot) * (D + 1) + j] = static_cast<uint64_t>(pa[j]) << 32;
-    for (int ch = 1; ch < P.nchunk; ++ch)
+    const int ch0 = j / P.kchunk;
+    P.cpart[(static_cast<size_t>(ch0) * P.np + slot) * (D + 1) + j] = static_cast<uint64_t>(pa[j]) << 32;
+    for (int ch = ch0 + 1; ch < P.nchunk; ++ch)
       P.cpart[(static_cast<size_t>(ch) * P.np + slot) * (D + 1) + j] = 0;
   }
 }
 
 // ----------------------------------------------------------------------- CRT
 
-// Whether the Garner table of a problem is staged in LDS by the CRT kernel,
+// Whether the Garner table (np^2 words) and the limb table of the prefix
+// products (np L_out words) of a problem are staged in LDS by the CRT kernel,
 // and the CRT block's LDS words.
+__host__ __device__ inline int crt_wave_words(int ns) { return 3 * 64 * ns + 4; }
 __host__ __device__ inline bool crt_stage_tg(const DevProblem& P, int ns, int nwaves) {
-  return P.np * P.np + nwaves * (3 * 64 * ns + 4) <= kLdsWords;
+  return P.np * P.np + nwaves * crt_wave_words(ns) <= kLdsWords;
+}
+__host__ __device__ inline bool crt_stage_pl(const DevProblem& P, int ns, int nwaves) {
+  return crt_stage_tg(P, ns, nwaves) && P.np * P.np + P.np * P.L_out + nwaves * crt_wave_words(ns) <= kLdsWords;
 }
 __host__ __device__ inline int crt_lds_words(const DevProblem& P, int ns, int nwaves) {
-  return (crt_stage_tg(P, ns, nwaves) ? P.np * P.np : 0) + nwaves * (3 * 64 * ns + 4);
+  return (crt_stage_tg(P, ns, nwaves) ? P.np * P.np : 0) + (crt_stage_pl(P, ns, nwaves) ? P.np * P.L_out : 0) +
+         nwaves * crt_wave_words(ns);
 }
 
 // One wave per coefficient k.  Garner: lanes own primes (slot i = lane + 64 r);
@@ -368,8 +418,11 @@ __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const 
   const int k = valid ? k_raw : P.D;
   const int np = P.np;
   const bool staged = crt_stage_tg(P, NS, nw);
+  const bool staged_pl = crt_stage_pl(P, NS, nw);
+  const int L = P.L_out;
   uint32_t* tg = lds;
-  uint32_t* wb = lds + (staged ? np * np : 0) + wave * (3 * 64 * NS + 4);
+  uint32_t* pls = lds + (staged ? np * np : 0);
+  uint32_t* wb = pls + (staged_pl ? np * L : 0) + wave * crt_wave_words(NS);
   uint32_t* vbuf = wb;
   uint32_t* sb = wb + 64 * NS;
   uint32_t* sc = sb + 64 * NS + 2;
@@ -377,6 +430,12 @@ __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const 
     for (int t = threadIdx.x; t < np * np; t += blockDim.x) {
       const int j = t / np, i = t - j * np;
       tg[t] = P.Tg[static_cast<size_t>(j) * P.tgs + i];
+    }
+  }
+  if (staged_pl) {
+    for (int t = threadIdx.x; t < np * L; t += blockDim.x) {
+      const int j = t / L, l = t - j * L;
+      pls[t] = P.Plimb[static_cast<size_t>(j) * P.LP + l];
     }
   }
   __syncthreads();
@@ -390,9 +449,17 @@ __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const 
       const PrimeConst pc = T.pc[P.pidx[i]];
       pp[r] = pc.p;
       pinv[r] = pc.pinv;
+      // partial sums of the chunks that reach coefficient k (independent loads)
+      const uint64_t* cp = P.cpart + static_cast<size_t>(i) * (P.D + 1) + k;
+      const size_t cstride = static_cast<size_t>(np) * (P.D + 1);
       uint64_t cs = 0;
-      for (int ch = 0; ch < P.nchunk; ++ch)
-        cs = add_fold(cs, P.cpart[(static_cast<size_t>(ch) * np + i) * (P.D + 1) + k], pc.p);
+      int ch = k / P.kchunk;
+      for (; ch + 4 <= P.nchunk; ch += 4) {
+        const uint64_t q0 = cp[ch * cstride], q1 = cp[(ch + 1) * cstride];
+        const uint64_t q2 = cp[(ch + 2) * cstride], q3 = cp[(ch + 3) * cstride];
+        cs = add_fold(cs, add_fold(add_fold(q0, q1, pc.p), add_fold(q2, q3, pc.p), pc.p), pc.p);
+      }
+      for (; ch < P.nchunk; ++ch) cs = add_fold(cs, cp[ch * cstride], pc.p);
       u[r] = maddm(redc(cs, pc.p, pc.pinv), P.Hm[i], pc.p);
       invm[r] = P.invM[i];
     } else {
@@ -420,7 +487,6 @@ __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const 
   __syncthreads();
 
   // radix conversion: 96-bit column sums per output limb
-  const int L = P.L_out;
   uint64_t lo[NS];
   uint32_t hc[NS];
 #pragma unroll
@@ -429,27 +495,33 @@ __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const 
     lo[r] = (t < L) ? P.NH[t] : 0u;
     hc[r] = 0u;
   }
+  const uint32_t* plb = staged_pl ? pls : P.Plimb;
+  const int pls_stride = staged_pl ? L : P.LP;
   int j = 0;
-  for (; j + 1 < np; j += 2) {
-    const uint32_t v0 = vbuf[j], v1 = vbuf[j + 1];
-    const uint32_t* p0 = P.Plimb + static_cast<size_t>(j) * P.LP;
-    const uint32_t* p1 = p0 + P.LP;
+  for (; j + 4 <= np; j += 4) {
+    const uint32_t v0 = vbuf[j], v1 = vbuf[j + 1], v2 = vbuf[j + 2], v3 = vbuf[j + 3];
+    const uint32_t* p0 = plb + static_cast<size_t>(j) * pls_stride;
 #pragma unroll
     for (int r = 0; r < NS; ++r) {
       const int t = lane + 64 * r;
       if (t < L) {
-        const uint64_t q0 = static_cast<uint64_t>(v0) * p0[t];
-        const uint64_t q1 = static_cast<uint64_t>(v1) * p1[t];
+        const uint32_t w0 = p0[t], w1 = p0[pls_stride + t], w2 = p0[2 * pls_stride + t], w3 = p0[3 * pls_stride + t];
+        const uint64_t q0 = static_cast<uint64_t>(v0) * w0, q1 = static_cast<uint64_t>(v1) * w1;
+        const uint64_t q2 = static_cast<uint64_t>(v2) * w2, q3 = static_cast<uint64_t>(v3) * w3;
         lo[r] += q0;
         hc[r] += (lo[r] < q0) ? 1u : 0u;
         lo[r] += q1;
         hc[r] += (lo[r] < q1) ? 1u : 0u;
+        lo[r] += q2;
+        hc[r] += (lo[r] < q2) ? 1u : 0u;
+        lo[r] += q3;
+        hc[r] += (lo[r] < q3) ? 1u : 0u;
       }
     }
   }
   for (; j < np; ++j) {
     const uint32_t vj = vbuf[j];
-    const uint32_t* pl = P.Plimb + static_cast<size_t>(j) * P.LP;
+    const uint32_t* pl = plb + static_cast<size_t>(j) * pls_stride;
 #pragma unroll
     for (int r = 0; r < NS; ++r) {
       const int t = lane + 64 * r;

@@ -53,6 +53,43 @@ RSL_HD void eval_rows(Col out, const uint32_t* coeff, int nrows, int rowstride,
   }
 }
 
+// Four fused updates r_i = (al a_i + be q_i + ga b_i) / R mod p with
+// (q_0..q_3) = (bp, b0, b1, b2), phases interleaved across the four (see mmad3).
+RSL_HD void mmad3x4(uint32_t al, uint32_t be, uint32_t ga, uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3,
+                    uint32_t bp, uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3, uint32_t p, uint32_t pinv,
+                    uint32_t* r0, uint32_t* r1, uint32_t* r2, uint32_t* r3) {
+  uint64_t t0 = static_cast<uint64_t>(al) * a0, t1 = static_cast<uint64_t>(al) * a1;
+  uint64_t t2 = static_cast<uint64_t>(al) * a2, t3 = static_cast<uint64_t>(al) * a3;
+  t0 += static_cast<uint64_t>(be) * bp;
+  t1 += static_cast<uint64_t>(be) * b0;
+  t2 += static_cast<uint64_t>(be) * b1;
+  t3 += static_cast<uint64_t>(be) * b2;
+  t0 += static_cast<uint64_t>(ga) * b0;
+  t1 += static_cast<uint64_t>(ga) * b1;
+  t2 += static_cast<uint64_t>(ga) * b2;
+  t3 += static_cast<uint64_t>(ga) * b3;
+  uint32_t h0 = static_cast<uint32_t>(t0 >> 32), h1 = static_cast<uint32_t>(t1 >> 32);
+  uint32_t h2 = static_cast<uint32_t>(t2 >> 32), h3 = static_cast<uint32_t>(t3 >> 32);
+  h0 = umin32(h0, h0 - p);
+  h1 = umin32(h1, h1 - p);
+  h2 = umin32(h2, h2 - p);
+  h3 = umin32(h3, h3 - p);
+  t0 = (static_cast<uint64_t>(h0) << 32) | static_cast<uint32_t>(t0);
+  t1 = (static_cast<uint64_t>(h1) << 32) | static_cast<uint32_t>(t1);
+  t2 = (static_cast<uint64_t>(h2) << 32) | static_cast<uint32_t>(t2);
+  t3 = (static_cast<uint64_t>(h3) << 32) | static_cast<uint32_t>(t3);
+  const uint32_t m0 = static_cast<uint32_t>(t0) * pinv, m1 = static_cast<uint32_t>(t1) * pinv;
+  const uint32_t m2 = static_cast<uint32_t>(t2) * pinv, m3 = static_cast<uint32_t>(t3) * pinv;
+  const uint32_t u0 = static_cast<uint32_t>((t0 + static_cast<uint64_t>(m0) * p) >> 32);
+  const uint32_t u1 = static_cast<uint32_t>((t1 + static_cast<uint64_t>(m1) * p) >> 32);
+  const uint32_t u2 = static_cast<uint32_t>((t2 + static_cast<uint64_t>(m2) * p) >> 32);
+  const uint32_t u3 = static_cast<uint32_t>((t3 + static_cast<uint64_t>(m3) * p) >> 32);
+  *r0 = umin32(u0, u0 - p);
+  *r1 = umin32(u1, u1 - p);
+  *r2 = umin32(u2, u2 - p);
+  *r3 = umin32(u3, u3 - p);
+}
+
 // Resultant with formal degrees (m, n) of the polynomials in columns A, B
 // (Montgomery form; both columns are overwritten).  Returns the result in
 // Montgomery form.  *bad is set when lc_y f(x_i) or lc_y g(x_i) vanishes.
@@ -101,14 +138,27 @@ RSL_HD uint32_t ures_formal(Col A, Col B, int m, int n, const PrimeConst& pc, bo
       const uint32_t gamma = mneg(lcAt, p);
       uint32_t prevB = 0u;
       int j = 0;
-      for (; j + 4 <= b; j += 4) {  // four independent updates per trip (ILP)
-        const uint32_t b0 = B[j], b1 = B[j + 1], b2 = B[j + 2], b3 = B[j + 3];
-        const uint32_t a0 = A[j], a1 = A[j + 1], a2 = A[j + 2], a3 = A[j + 3];
-        A[j] = mmad3(alpha, a0, beta, prevB, gamma, b0, p, pinv);
-        A[j + 1] = mmad3(alpha, a1, beta, b0, gamma, b1, p, pinv);
-        A[j + 2] = mmad3(alpha, a2, beta, b1, gamma, b2, p, pinv);
-        A[j + 3] = mmad3(alpha, a3, beta, b2, gamma, b3, p, pinv);
-        prevB = b3;
+      if (b >= 4) {
+        // software-pipelined: the next four A/B values are loaded before the
+        // current four are combined, so LDS latency overlaps the arithmetic
+        uint32_t b0 = B[0], b1 = B[1], b2 = B[2], b3 = B[3];
+        uint32_t a0 = A[0], a1 = A[1], a2 = A[2], a3 = A[3];
+        for (; j + 4 <= b; j += 4) {
+          const bool more = j + 8 <= b;
+          const uint32_t nb0 = more ? B[j + 4] : 0u, nb1 = more ? B[j + 5] : 0u;
+          const uint32_t nb2 = more ? B[j + 6] : 0u, nb3 = more ? B[j + 7] : 0u;
+          const uint32_t na0 = more ? A[j + 4] : 0u, na1 = more ? A[j + 5] : 0u;
+          const uint32_t na2 = more ? A[j + 6] : 0u, na3 = more ? A[j + 7] : 0u;
+          uint32_t r0, r1, r2, r3;
+          mmad3x4(alpha, beta, gamma, a0, a1, a2, a3, prevB, b0, b1, b2, b3, p, pinv, &r0, &r1, &r2, &r3);
+          A[j] = r0;
+          A[j + 1] = r1;
+          A[j + 2] = r2;
+          A[j + 3] = r3;
+          prevB = b3;
+          b0 = nb0; b1 = nb1; b2 = nb2; b3 = nb3;
+          a0 = na0; a1 = na1; a2 = na2; a3 = na3;
+        }
       }
       for (; j < b; ++j) {
         const uint32_t bj = B[j];

@@ -1,0 +1,108 @@
+"""GPU parity on the larger workloads, where the full oracle is too slow to run in a test.
+
+* curve analysis (f = F (y^2 - h), g = f_y, D = 2054, 83 primes): the closed
+  factorisation R = (-1)^{d(d-1)/2 + e(e-1)/2} 4 h res_y(F, F_y) res_y(F, Q)^2
+  (pinned against the oracle on small cases in test_abi_host.py), randomised
+  checks modulo 61-bit primes (Schwartz-Zippel), an exact integer point check,
+  and the planted variants (a bad point for every prime; R(a) = 0);
+* batch of 512: batched = plain (bit-identical), oracle on the small problems,
+  modulo-q checks on a sample of the rest.
+"""
+
+import random
+
+import pytest
+
+import oracle
+import workloads
+from oracle import peval, pmul, psub
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1010_1386_amd as rsl
+    c = rsl.Context(device=0, workspace_bytes=1 << 30)
+    yield c
+    c.close()
+
+
+def _res_FQ(F, h):
+    """res_y(F, y^2 - h) = E(x,h)^2 - h O(x,h)^2 with F = E(x, y^2) + y O(x, y^2)."""
+    E, O, hp = [], [], [1]
+    for j, row in enumerate(F):
+        t = pmul(list(row), hp)
+        if j % 2 == 0:
+            E = psub(E, psub([], t))
+        else:
+            O = psub(O, psub([], t))
+            hp = pmul(hp, h)
+    return psub(pmul(E, E), pmul(h, pmul(O, O)))
+
+
+def _modq_checks(f, g, R, var, n, seed):
+    rnd = random.Random(seed)
+    qs = oracle.next_check_primes(4)
+    for k in range(n):
+        q = qs[k % len(qs)]
+        t = rnd.randrange(q)
+        assert peval(R, t) % q == oracle.res_at_point_mod(f, g, t, q, var), (k, t, q)
+
+
+@pytest.mark.parametrize("variant", ["a", "b", "c"])
+def test_curve_workload(ctx, variant):
+    f, g, F, h = workloads.config3(variant)
+    R = ctx.res(f, g, "y")
+    Ft = oracle.bivar_trim(F)
+    Fy = [[j * c for c in Ft[j]] for j in range(1, len(Ft))]
+    S = ctx.res(Ft, Fy, "y")
+    e = len(Ft) - 1
+    d = e + 2
+    sign = -1 if (d * (d - 1) // 2 + e * (e - 1) // 2) % 2 else 1
+    rFQ = _res_FQ(Ft, h)
+    assert R == pmul([4 * sign], pmul(list(h), pmul(S, pmul(rFQ, rFQ))))
+    assert len(R) - 1 <= oracle.degree_bound(f, g)
+    _modq_checks(f, g, R, "y", 12 if variant == "a" else 4, 31 + ord(variant))
+    if variant == "a":
+        assert peval(R, 3) == oracle.res_at_int_point(f, g, 3)
+    if variant == "c":
+        a = next(x for x in range(1, 200) if peval(list(h), x) == 0)
+        assert peval(R, a) == 0
+    if variant == "b":
+        c = ctx.counters()
+        assert c["bad_pairs"] > 0 and c["slow_primes"] > 0
+        assert ctx.res(f, g, "y", points="formal") == R
+
+
+def test_batch_of_512_batched_equals_plain(ctx):
+    pairs = workloads.config4()
+    probs = [(f, g, "y") for f, g in pairs]
+    got_b = ctx.batch(probs, mode="batched")
+    got_p = ctx.batch(probs, mode="plain")
+    assert got_b == got_p
+    # full oracle on the smallest problems
+    small = sorted(range(len(pairs)), key=lambda k: sum(len(r) for r in pairs[k][0]) + sum(len(r) for r in pairs[k][1]))
+    for k in small[:12]:
+        f, g = pairs[k]
+        assert got_b[k] == oracle.res(f, g), k
+    # modulo-q checks on a sample of all sizes
+    for k in range(0, len(pairs), 16):
+        f, g = pairs[k]
+        _modq_checks(f, g, got_b[k], "y", 1, k)
+
+
+def test_resident_job_reruns_are_identical(ctx):
+    pairs = workloads.config4(40)
+    probs = [(f, g, "yx"[k % 2]) for k, (f, g) in enumerate(pairs)]
+    job = ctx.job(probs)
+    job.run("batched")
+    r1 = job.results()
+    for _ in range(3):
+        job.run("batched")
+    r2 = job.results()
+    job.run("plain")
+    r3 = job.results()
+    job.close()
+    assert r1 == r2 == r3
+    assert r1 == ctx.batch(probs, mode="plain")
