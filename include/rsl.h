@@ -49,9 +49,10 @@ extern "C" {
 #define RSL_Y 0 /* res(f, g, y) in Z[x] */
 #define RSL_X 1 /* res(f, g, x) in Z[y] */
 
-/* rsl_batch modes */
-#define RSL_PLAIN 0   /* one pipeline (reduce, eval+ures, interp, crt) per problem */
-#define RSL_BATCHED 1 /* all problems in one persistent launch                     */
+/* execution modes of rsl_batch / rsl_job_run */
+#define RSL_PLAIN 0   /* one pipeline (reduce, eval+ures, interp, crt) per problem          */
+#define RSL_BATCHED 1 /* all problems in one persistent launch (device task queue)          */
+#define RSL_STAGED 2  /* one launch per stage, each over the work items of all problems     */
 
 /* point policy (rsl_opts.points) */
 #define RSL_POINTS_REPLACE 0 /* bad points skipped: first D+1 good points of 0..D+s */
@@ -152,7 +153,8 @@ int rsl_res_x(rsl_ctx *ctx, const rsl_poly *f, const rsl_poly *g, rsl_result *ou
  * A batch of n independent problems (f[k], g[k], var[k]) -> out[k].
  * mode RSL_PLAIN runs one pipeline per problem on the context stream;
  * RSL_BATCHED plans all problems together and runs them in one persistent
- * launch.  Both give bit-identical results.  Per-problem status codes go to
+ * launch; RSL_STAGED runs one launch per stage over all problems.  All modes
+ * give bit-identical results.  Per-problem status codes go to
  * status[k] (may be NULL); the call returns the first nonzero one.
  */
 int rsl_batch(rsl_ctx *ctx, int n, const rsl_poly *f, const rsl_poly *g, const int *var,

@@ -36,7 +36,7 @@ _lib = ctypes.CDLL(_LIBPATH)
 RSL_OK, RSL_EINVAL, RSL_ERANGE, RSL_ENOMEM, RSL_EPRIMES, RSL_EDEVICE, RSL_EAGAIN, RSL_ETIMEDOUT = (
     0, -1, -2, -3, -4, -5, -6, -7)
 RSL_Y, RSL_X = 0, 1
-RSL_PLAIN, RSL_BATCHED = 0, 1
+RSL_PLAIN, RSL_BATCHED, RSL_STAGED = 0, 1, 2
 RSL_POINTS_REPLACE, RSL_POINTS_FORMAL = 0, 1
 
 
@@ -330,7 +330,11 @@ class Context:
 
 
 def _modecode(mode):
-    return RSL_BATCHED if mode in ("batched", RSL_BATCHED) else RSL_PLAIN
+    codes = {"plain": RSL_PLAIN, "batched": RSL_BATCHED, "staged": RSL_STAGED,
+             RSL_PLAIN: RSL_PLAIN, RSL_BATCHED: RSL_BATCHED, RSL_STAGED: RSL_STAGED}
+    if mode not in codes:
+        raise ValueError("mode must be 'plain', 'batched' or 'staged'")
+    return codes[mode]
 
 
 class Job:

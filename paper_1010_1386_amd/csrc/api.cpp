@@ -50,7 +50,8 @@ int ensure_tables(rsl_ctx* ctx, int np, int kneed, int sneed) {
   const int new_np = std::max(ctx->npcap, static_cast<int>(align_up(std::max(np, 1), 64)));
   const int new_k = std::max(ctx->kcap, static_cast<int>(align_up(kneed + 1, 256)) - 1);
   const int new_s = std::max(ctx->scap, static_cast<int>(align_up(sneed + 1, 256)) - 1);
-  int rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+  // the old tables may still be read by work in flight on any stream
+  int rc = hip_check(ctx, hipDeviceSynchronize(), "hipDeviceSynchronize");
   if (rc) return rc;
   free_tables(ctx);
 
@@ -317,7 +318,7 @@ int rsl_res(rsl_ctx* ctx, const rsl_poly* f, const rsl_poly* g, int var, const r
   ctx->err.clear();
   const double t0 = now_ms();
   rsl_counters cnt{};
-  int rc = run_in_workspace(ctx, 1, f, g, &var, opts, out, nullptr, RSL_BATCHED, &cnt);
+  int rc = run_in_workspace(ctx, 1, f, g, &var, opts, out, nullptr, RSL_STAGED, &cnt);
   cnt.ms_total = now_ms() - t0;
   ctx->last = cnt;
   return rc;
@@ -334,7 +335,8 @@ int rsl_res_x(rsl_ctx* ctx, const rsl_poly* f, const rsl_poly* g, rsl_result* ou
 int rsl_batch(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var, rsl_result* out,
               int* status, int mode) {
   if (!ctx || n < 0 || (n > 0 && (!f || !g || !var || !out))) return RSL_EINVAL;
-  if (mode != RSL_PLAIN && mode != RSL_BATCHED) return fail(ctx, RSL_EINVAL, "mode must be RSL_PLAIN or RSL_BATCHED");
+  if (mode != RSL_PLAIN && mode != RSL_BATCHED && mode != RSL_STAGED)
+    return fail(ctx, RSL_EINVAL, "mode must be RSL_PLAIN, RSL_BATCHED or RSL_STAGED");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   if (ctx->poisoned) return RSL_EDEVICE;
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, RSL_EDEVICE, "hipSetDevice");
@@ -448,12 +450,13 @@ int rsl_job_create(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, co
 
 int rsl_job_run(rsl_ctx* ctx, rsl_job* j, int mode) {
   if (!ctx || !j || j->ctx != ctx) return RSL_EINVAL;
-  if (mode != RSL_PLAIN && mode != RSL_BATCHED) return fail(ctx, RSL_EINVAL, "mode must be RSL_PLAIN or RSL_BATCHED");
+  if (mode != RSL_PLAIN && mode != RSL_BATCHED && mode != RSL_STAGED)
+    return fail(ctx, RSL_EINVAL, "mode must be RSL_PLAIN, RSL_BATCHED or RSL_STAGED");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   if (ctx->poisoned) return RSL_EDEVICE;
   int rc;
   if ((rc = job_refresh(ctx, j)) || (rc = job_reset(ctx, &j->J, ctx->stream))) return rc;
-  if (ctx->profiling && mode == RSL_BATCHED) {
+  if (ctx->profiling && mode != RSL_PLAIN) {
     hipEvent_t* ev = next_evset(ctx);
     if (!ev) return fail(ctx, RSL_EDEVICE, "hipEventCreate");
     for (int s = 0; s <= kNumStages; ++s) ctx->ev[s] = ev[s];

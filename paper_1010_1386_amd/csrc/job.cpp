@@ -158,6 +158,37 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       L.Plimb = o; o = align_up(o + static_cast<size_t>(P.np) * P.L_out * 4, 16);
     }
   }
+  // persistent queue: [state | tasks | ready | counters]; an initial image is
+  // uploaded with the inputs and copied to the live queue before each launch
+  {
+    int64_t cap = 0, crt_total = 0, initial = 0;
+    for (int li = 0; li < nl; ++li) {
+      const Plan& P = J->plans[J->live[li]];
+      const DevProblem& d = J->dev[li];
+      const int64_t ne = blocks_of(P.E + 1, 64), nc = blocks_of(P.D + 1, 64);
+      const int64_t ns = nc * d.nchunk;
+      cap += static_cast<int64_t>(P.np) * (1 + ne + std::max<int64_t>(nc + ns, 1));
+      const int64_t ncrt = blocks_of(P.D + 1, kCrtPerTask);
+      cap += ncrt;
+      crt_total += ncrt;
+      initial += P.np;
+    }
+    J->q_capacity = static_cast<int>(std::max<int64_t>(cap, 1));
+    J->q_crt_total = static_cast<int>(crt_total);
+    J->q_initial = static_cast<int>(initial);
+    size_t qo = 0;
+    qo = align_up(qo + sizeof(QueueState), A);
+    J->q_tasks = qo;
+    qo = align_up(qo + sizeof(Task) * J->q_capacity, A);
+    J->q_ready = qo;
+    qo = align_up(qo + sizeof(int) * J->q_capacity, A);
+    J->q_counters = qo;
+    qo = align_up(qo + sizeof(ProbCounters) * std::max(nl, 1), A);
+    J->queue_bytes = qo;
+    o = align_up(o, A);
+    J->qinit_off = o;
+    o += J->queue_bytes;
+  }
   o = align_up(o, A);
   J->status_off = o;
   for (int li = 0; li < nl; ++li) {
@@ -187,7 +218,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     L.cpart = o; o = align_up(o + static_cast<size_t>(d.nchunk) * np * (P.D + 1) * 8, A);
   }
   J->queue_off = o;
-  J->queue_bytes = 0;
+  o = align_up(o + J->queue_bytes, A);
   J->total = o;
 
   // LDS per stage launch (max over problems)
@@ -200,6 +231,17 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     up(kStageStir, d.kchunk);
     if (J->lay[li].item_end[kStageNewton] > J->lay[li].item_begin[kStageNewton]) up(kStageNewton, newton_lds_words(d, 1024));
     up(kStageCrt, crt_lds_words(d, J->crt_ns, kCrtWaves));
+  }
+  J->persist_lds = 0;
+  for (int li = 0; li < nl; ++li) {
+    const DevProblem& d = J->dev[li];
+    size_t w = eval_lds_words(d);
+    w = std::max<size_t>(w, static_cast<size_t>(2) * (d.D + 1));
+    w = std::max<size_t>(w, d.kchunk);
+    if (J->lay[li].item_end[kStageNewton] > J->lay[li].item_begin[kStageNewton])
+      w = std::max<size_t>(w, newton_lds_words(d, 64));
+    w = std::max<size_t>(w, crt_lds_words(d, J->crt_ns, 1));
+    J->persist_lds = std::max(J->persist_lds, w * 4);
   }
   for (int s = 0; s < kNumStages; ++s)
     if (J->stage_lds[s] > static_cast<size_t>(kLdsWords) * 4) {
@@ -271,6 +313,34 @@ void job_bind(Job* J, uint8_t* base) {
     d.out = reinterpret_cast<uint32_t*>(base + L.out);
     d.status = reinterpret_cast<int*>(base + L.status);
   }
+  // initial queue image: one REDUCE task per (problem, prime slot), largest problems first
+  {
+    uint8_t* q = blob + J->qinit_off;
+    QueueState* qs = reinterpret_cast<QueueState*>(q);
+    Task* tasks = reinterpret_cast<Task*>(q + J->q_tasks);
+    int* ready = reinterpret_cast<int*>(q + J->q_ready);
+    ProbCounters* cnt = reinterpret_cast<ProbCounters*>(q + J->q_counters);
+    int t = 0;
+    for (int li = 0; li < nl; ++li) {
+      const Plan& P = J->plans[J->live[li]];
+      const DevProblem& d = J->dev[li];
+      const int ne = blocks_of(P.E + 1, 64), nc = blocks_of(P.D + 1, 64);
+      cnt[li].slots_left = P.np;
+      for (int sl = 0; sl < P.np; ++sl) {
+        cnt[li].eval_left[sl] = ne;
+        cnt[li].conv_left[sl] = nc;
+        cnt[li].stir_left[sl] = nc * d.nchunk;
+        tasks[t] = Task{(kTaskReduce << 24) | li, sl, 0, 0};
+        ready[t] = 1;
+        ++t;
+      }
+    }
+    qs->head = 0;
+    qs->tail = t;
+    qs->done = (J->q_crt_total == 0) ? 1 : 0;
+    qs->crt_done = 0;
+    qs->err = 0;
+  }
   std::memcpy(blob + J->probs_off, J->dev.data(), sizeof(DevProblem) * nl);
   for (int s = 0; s < kNumStages; ++s)
     if (!J->items[s].empty())
@@ -301,13 +371,16 @@ static void bind_crt_tables(const rsl_ctx* ctx, Job* J) {
   std::memcpy(J->blob.data() + J->probs_off, J->dev.data(), sizeof(DevProblem) * nl);
 }
 
-int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st) {
+int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st, uint8_t* pinned) {
   bind_crt_tables(ctx, J);
   if (J->up_bytes == 0) return RSL_OK;
-  int rc = ensure_staging(ctx, J->up_bytes, J->down_bytes);
-  if (rc) return rc;
-  std::memcpy(ctx->h_up, J->blob.data(), J->up_bytes);
-  return hip_check(ctx, hipMemcpyAsync(J->base, ctx->h_up, J->up_bytes, hipMemcpyHostToDevice, st), "upload");
+  if (!pinned) {
+    int rc = ensure_staging(ctx, J->up_bytes, J->down_bytes);
+    if (rc) return rc;
+    pinned = ctx->h_up;
+  }
+  std::memcpy(pinned, J->blob.data(), J->up_bytes);
+  return hip_check(ctx, hipMemcpyAsync(J->base, pinned, J->up_bytes, hipMemcpyHostToDevice, st), "upload");
 }
 
 int job_reset(rsl_ctx* ctx, Job* J, hipStream_t st) {
@@ -332,6 +405,37 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
           return rc;
       }
     }
+    return RSL_OK;
+  }
+  if (mode == RSL_BATCHED) {
+    if (J->persist_lds > static_cast<size_t>(kLdsWords) * 4)
+      return fail(ctx, RSL_EINVAL, "persistent launch needs more than 64 KB of LDS per workgroup");
+    QueueDesc Q{};
+    uint8_t* qb = J->base + J->queue_off;
+    Q.state = reinterpret_cast<QueueState*>(qb);
+    Q.tasks = reinterpret_cast<Task*>(qb + J->q_tasks);
+    Q.ready = reinterpret_cast<int*>(qb + J->q_ready);
+    Q.counters = reinterpret_cast<ProbCounters*>(qb + J->q_counters);
+    Q.capacity = J->q_capacity;
+    Q.crt_total = J->q_crt_total;
+    Q.nprob = static_cast<int>(J->live.size());
+    if (J->persist_grid == 0) {
+      const int per_cu = persistent_blocks_per_cu(J->crt_ns, J->persist_lds);
+      int cus = 256;
+      hipDeviceProp_t prop;
+      if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) cus = prop.multiProcessorCount;
+      J->persist_grid = std::max(1, per_cu * cus);
+    }
+    if ((rc = hip_check(ctx, hipMemcpyAsync(qb, J->base + J->qinit_off, J->queue_bytes, hipMemcpyDeviceToDevice, st),
+                        "queue reset")))
+      return rc;
+    if (stage_events && (rc = hip_check(ctx, hipEventRecord(ctx->ev[0], st), "event"))) return rc;
+    if ((rc = hip_check(ctx, launch_persistent(probs, Q, T, J->crt_ns, J->persist_grid, J->persist_lds, st),
+                        "persistent launch")))
+      return rc;
+    if (stage_events)
+      for (int s = 1; s <= kNumStages; ++s)
+        if ((rc = hip_check(ctx, hipEventRecord(ctx->ev[s], st), "event"))) return rc;
     return RSL_OK;
   }
   for (int s = 0; s < kNumStages; ++s) {
@@ -365,7 +469,10 @@ int job_decode(rsl_ctx* ctx, const Job& J, const uint8_t* host, rsl_result* out,
         const int li = li_of[k];
         const ProbLayout& L = J.lay[li];
         const int* st = reinterpret_cast<const int*>(host + (L.status - J.down_off));
-        if (st[0] & kErrTooFewGoodPoints) {
+        if (st[0] & kErrQueueStall) {
+          rc = RSL_EDEVICE;
+          ctx->err = "persistent launch: a wave gave up waiting on the task queue";
+        } else if (st[0] & kErrTooFewGoodPoints) {
           rc = RSL_EPRIMES;
           ctx->err = "fewer than D+1 good points for a prime";
         } else {

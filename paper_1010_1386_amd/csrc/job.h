@@ -11,6 +11,7 @@
 #include "../../include/rsl.h"
 #include "device.h"
 #include "plan.h"
+#include "persistent.h"
 #include "stages.h"
 
 struct rsl_ctx;
@@ -40,8 +41,12 @@ struct Job {
   size_t up_bytes = 0;             // [0, up_bytes) is uploaded
   size_t down_off = 0, down_bytes = 0;  // statuses + outputs, downloaded
   size_t status_off = 0, status_bytes = 0;
-  size_t queue_off = 0, queue_bytes = 0;  // persistent-launch task queue
-  int queue_tasks = 0, queue_initial = 0;
+  // persistent launch: initial queue image (uploaded) and the live queue
+  size_t qinit_off = 0, queue_off = 0, queue_bytes = 0;
+  size_t q_tasks = 0, q_ready = 0, q_counters = 0;  // offsets inside a queue image
+  int q_capacity = 0, q_initial = 0, q_crt_total = 0;
+  size_t persist_lds = 0;
+  int persist_grid = 0;
   size_t total = 0;
   uint8_t* base = nullptr;         // device region the job is laid out in
   std::vector<uint8_t> blob;       // host image of [0, up_bytes)
@@ -54,11 +59,14 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
               Job* J, std::string* err);
 // Bind the job to a device region (fills device pointers and the upload image).
 void job_bind(Job* J, uint8_t* base);
-// Upload the inputs (asynchronous on the stream, from pinned staging when given).
-int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st);
+// Upload the inputs (asynchronous on the stream) through `pinned` (>= up_bytes of
+// pinned host memory that stays untouched until the copy is done), or through
+// the context's staging buffer when pinned is null.
+int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st, uint8_t* pinned = nullptr);
 // Zero the status words (before a re-run of a resident job).
 int job_reset(rsl_ctx* ctx, Job* J, hipStream_t st);
-// Launch the device pipeline: mode RSL_PLAIN (per problem) or RSL_BATCHED.
+// Launch the device pipeline: RSL_PLAIN (per problem), RSL_STAGED (one launch per
+// stage over all problems) or RSL_BATCHED (one persistent launch).
 int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events);
 // Download statuses and outputs (asynchronous) into `host` (down_bytes).
 int job_download(rsl_ctx* ctx, Job* J, uint8_t* host, hipStream_t st);

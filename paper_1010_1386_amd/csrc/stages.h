@@ -409,13 +409,16 @@ __host__ __device__ inline int crt_lds_words(const DevProblem& P, int ns, int nw
 // resolved with wave ballots.  The result is (Y - H) mod 2^(32 L_out) with
 // Y = sum_j v_j prod_{l<j} p_l in [0, M) and H = (M-1)/2: the symmetric residue.
 template <int NS>
-__device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
+__device__ inline void crt_one(const DevProblem& P, const DevTables& T, int k_raw, const uint32_t* tg, bool staged,
+                               const uint32_t* pls, bool staged_pl, uint32_t* wb);
+
+// One block: the Garner table (and, when it fits, the limb table) staged in
+// LDS once, then `cpw` coefficients per wave, k = (blk * waves + wave) * cpw + c.
+template <int NS>
+__device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds,
+                                 int cpw = 1) {
   const int nw = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int k_raw = w.blk * nw + wave;
-  const bool valid = k_raw <= P.D;
-  const int k = valid ? k_raw : P.D;
   const int np = P.np;
   const bool staged = crt_stage_tg(P, NS, nw);
   const bool staged_pl = crt_stage_pl(P, NS, nw);
@@ -423,9 +426,6 @@ __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const 
   uint32_t* tg = lds;
   uint32_t* pls = lds + (staged ? np * np : 0);
   uint32_t* wb = pls + (staged_pl ? np * L : 0) + wave * crt_wave_words(NS);
-  uint32_t* vbuf = wb;
-  uint32_t* sb = wb + 64 * NS;
-  uint32_t* sc = sb + 64 * NS + 2;
   if (staged) {
     for (int t = threadIdx.x; t < np * np; t += blockDim.x) {
       const int j = t / np, i = t - j * np;
@@ -439,6 +439,20 @@ __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const 
     }
   }
   __syncthreads();
+  for (int c = 0; c < cpw; ++c) crt_one<NS>(P, T, (w.blk * nw + wave) * cpw + c, tg, staged, pls, staged_pl, wb);
+}
+
+template <int NS>
+__device__ inline void crt_one(const DevProblem& P, const DevTables& T, int k_raw, const uint32_t* tg, bool staged,
+                               const uint32_t* pls, bool staged_pl, uint32_t* wb) {
+  const int lane = threadIdx.x & 63;
+  const bool valid = k_raw <= P.D;
+  const int k = valid ? k_raw : P.D;
+  const int np = P.np;
+  const int L = P.L_out;
+  uint32_t* vbuf = wb;
+  uint32_t* sb = wb + 64 * NS;
+  uint32_t* sc = sb + 64 * NS + 2;
 
   uint32_t u[NS], acc[NS], pp[NS], pinv[NS], invm[NS];
 #pragma unroll

@@ -1,6 +1,88 @@
-"""Python wrapper of the request server (rsl_server_*)."""
+"""Python wrapper of the request server (rsl_server_* in include/rsl.h)."""
+
+from __future__ import annotations
+
+import ctypes
+
+from . import (RSLError, RSL_EAGAIN, _Result, _as_poly, _lib, _var_code, _vp, rsl_info, rsl_stats)
+
+RSL_ETIMEDOUT = -7
 
 
 class Server:
-    def __init__(self, *a, **k):
-        raise NotImplementedError("server not built yet")
+    """Continuous-batching request server on a Context.
+
+    submit() copies the inputs and returns a ticket; wait(ticket) returns the
+    resultant (list of ints).  Admission is FIFO by slots and device footprint.
+    """
+
+    def __init__(self, ctx, budget_bytes=64 << 20, max_slots=64, max_queue=4096):
+        self.ctx = ctx
+        h = _vp()
+        rc = _lib.rsl_server_create(ctx.h, budget_bytes, max_slots, max_queue, ctypes.byref(h))
+        if rc:
+            raise RSLError(rc, "rsl_server_create: " + ctx.last_error())
+        self.h = h
+        self._outs = {}
+
+    def submit(self, f, g, var="y"):
+        pf, pg = _as_poly(f), _as_poly(g)
+        v = _var_code(var)
+        info = rsl_info()
+        rc = _lib.rsl_query(ctypes.byref(pf.c), ctypes.byref(pg.c), v, ctypes.byref(info))
+        if rc:
+            raise RSLError(rc, "rsl_query")
+        out = _Result(max(info.D, 0), info.out_limbs)
+        t = ctypes.c_uint64()
+        rc = _lib.rsl_server_submit(self.h, ctypes.byref(pf.c), ctypes.byref(pg.c), v, ctypes.byref(out.c),
+                                    ctypes.byref(t))
+        if rc:
+            raise RSLError(rc, "rsl_server_submit")
+        self._outs[t.value] = out
+        return t.value
+
+    def try_submit(self, f, g, var="y"):
+        """Like submit() but returns None when the server queue is full."""
+        try:
+            return self.submit(f, g, var)
+        except RSLError as e:
+            if e.code == RSL_EAGAIN:
+                return None
+            raise
+
+    def poll(self, ticket):
+        st = ctypes.c_int()
+        rc = _lib.rsl_server_poll(self.h, ticket, ctypes.byref(st))
+        if rc < 0:
+            raise RSLError(rc, "rsl_server_poll")
+        if rc == 0:
+            return None
+        out = self._outs.pop(ticket)
+        if st.value:
+            raise RSLError(st.value, "request failed")
+        return out.value()
+
+    def wait(self, ticket, timeout_ms=-1):
+        rc = _lib.rsl_server_wait(self.h, ticket, timeout_ms)
+        if rc == RSL_ETIMEDOUT:
+            return None
+        out = self._outs.pop(ticket)
+        if rc:
+            raise RSLError(rc, "request failed")
+        return out.value()
+
+    def stats(self):
+        s = rsl_stats()
+        _lib.rsl_server_stats(self.h, ctypes.byref(s))
+        return {name: getattr(s, name) for name, _ in rsl_stats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.rsl_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

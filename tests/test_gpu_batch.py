@@ -1,0 +1,77 @@
+"""GPU: the three execution modes (one pipeline per problem, one launch per stage,
+one persistent launch with a device task queue) give the same bits, equal to the
+oracle, on mixed batches (both variables, bad points, bad primes, zero inputs,
+more than 64 primes)."""
+
+import pytest
+
+import oracle
+from workloads import dense_total, rng_for, small_random, sparse_total
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1010_1386_amd as rsl
+    c = rsl.Context(device=0, workspace_bytes=1 << 30)
+    yield c
+    c.close()
+
+
+def mixed_batch(n, seed):
+    rng = rng_for(710, seed)
+    probs = []
+    for k in range(n):
+        kind = k % 5
+        if kind == 0:
+            F = dense_total(rng, int(rng.integers(2, 8)), int(rng.integers(8, 64)))
+            G = dense_total(rng, int(rng.integers(2, 8)), int(rng.integers(8, 64)))
+        elif kind == 1:
+            F = sparse_total(rng, int(rng.integers(3, 8)), int(rng.integers(8, 40)))
+            G = sparse_total(rng, int(rng.integers(3, 8)), int(rng.integers(8, 40)))
+        elif kind == 2:  # leading y-coefficient x (x - 2): bad points 0 and 2 for every prime
+            F = small_random(rng, 3, 4, 20)
+            F[3] = [0, -2, 1, 0, 0]
+            G = small_random(rng, 2, 3, 20)
+        elif kind == 3:
+            F = small_random(rng, int(rng.integers(0, 4)), int(rng.integers(0, 4)), 12, 0.5)
+            G = small_random(rng, int(rng.integers(0, 4)), int(rng.integers(0, 4)), 12, 0.5)
+        else:
+            F = dense_total(rng, 4, 10)
+            G = [[0]]  # zero polynomial
+        probs.append((F, G, "yx"[k % 2]))
+    return probs
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_modes_agree_with_oracle(ctx, seed):
+    probs = mixed_batch(25, seed)
+    want = [oracle.res(f, g, v) for f, g, v in probs]
+    for mode in ("batched", "staged", "plain"):
+        assert ctx.batch(probs, mode=mode) == want, mode
+
+
+def test_persistent_launch_with_many_primes_and_large_degree(ctx):
+    """More than 64 primes per problem (two prime slots per lane in CRT) and D > 256."""
+    rng = rng_for(711, 0)
+    F = dense_total(rng, 10, 64)
+    G = dense_total(rng, 10, 64)
+    H = dense_total(rng, 6, 120)
+    probs = [(F, G, "y"), (G, F, "x"), (H, F, "y")]
+    got = ctx.batch(probs, mode="batched")
+    assert got == ctx.batch(probs, mode="staged")
+    for (f, g, v), r in zip(probs, got):
+        assert r == oracle.res(f, g, v)
+
+
+def test_resident_job_all_modes(ctx):
+    probs = mixed_batch(30, 7)
+    job = ctx.job(probs)
+    outs = []
+    for mode in ("batched", "staged", "plain", "batched"):
+        job.run(mode)
+        outs.append(job.results())
+    job.close()
+    assert all(o == outs[0] for o in outs)
+    assert outs[0] == [oracle.res(f, g, v) for f, g, v in probs]

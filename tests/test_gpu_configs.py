@@ -23,7 +23,7 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def ctx():
     import paper_1010_1386_amd as rsl
-    c = rsl.Context(device=0, workspace_bytes=1 << 30)
+    c = rsl.Context(device=0, workspace_bytes=4 << 30)
     yield c
     c.close()
 
@@ -79,8 +79,9 @@ def test_batch_of_512_batched_equals_plain(ctx):
     pairs = workloads.config4()
     probs = [(f, g, "y") for f, g in pairs]
     got_b = ctx.batch(probs, mode="batched")
+    got_s = ctx.batch(probs, mode="staged")
     got_p = ctx.batch(probs, mode="plain")
-    assert got_b == got_p
+    assert got_b == got_s == got_p
     # full oracle on the smallest problems
     small = sorted(range(len(pairs)), key=lambda k: sum(len(r) for r in pairs[k][0]) + sum(len(r) for r in pairs[k][1]))
     for k in small[:12]:

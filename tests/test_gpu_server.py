@@ -1,0 +1,101 @@
+"""GPU: the continuous-batching server returns the same bits as the direct call, alone
+and in a mix, admits by footprint, and reports latency statistics."""
+
+import threading
+import time
+
+import pytest
+
+import oracle
+from workloads import dense_total, rng_for
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rsl():
+    import paper_1010_1386_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ref(rsl):
+    c = rsl.Context(device=0, workspace_bytes=512 << 20)
+    yield c
+    c.close()
+
+
+def requests(n, seed, dmax=12):
+    rng = rng_for(720, seed)
+    out = []
+    for k in range(n):
+        d1, d2 = int(rng.integers(3, dmax)), int(rng.integers(3, dmax))
+        b1, b2 = int(rng.integers(8, 48)), int(rng.integers(8, 48))
+        out.append((dense_total(rng, d1, b1), dense_total(rng, d2, b2), "yx"[k % 2]))
+    return out
+
+
+def test_server_results_match_direct_calls(rsl, ref):
+    ctx = rsl.Context(device=0, workspace_bytes=256 << 20)
+    srv = rsl.Server(ctx, budget_bytes=128 << 20, max_slots=16, max_queue=1024)
+    reqs = requests(48, 0)
+    tickets = [srv.submit(f, g, v) for f, g, v in reqs]
+    got = [srv.wait(t) for t in tickets]
+    want = ref.batch(reqs, mode="staged")
+    assert got == want
+    for k in range(0, 48, 12):  # the oracle on a few
+        f, g, v = reqs[k]
+        assert got[k] == oracle.res(f, g, v)
+    st = srv.stats()
+    assert st["completed"] == 48 and st["in_flight"] == 0
+    assert 0 < st["p50_ms"] <= st["p99_ms"]
+    assert st["max_batch"] >= 2  # requests shared device iterations
+    assert st["admitted_bytes_peak"] <= 128 << 20
+    srv.close()
+    ctx.close()
+
+
+def test_alone_and_in_a_mix_are_identical(rsl):
+    ctx = rsl.Context(device=0, workspace_bytes=256 << 20)
+    srv = rsl.Server(ctx, budget_bytes=128 << 20, max_slots=32)
+    reqs = requests(30, 1)
+    probe = reqs[7]
+    alone = srv.wait(srv.submit(*probe))
+    results = {}
+
+    def client(idx):
+        f, g, v = reqs[idx]
+        results[idx] = srv.wait(srv.submit(f, g, v))
+
+    threads = [threading.Thread(target=client, args=(i,)) for i in range(len(reqs))]
+    for t in threads:
+        t.start()
+        time.sleep(0.0005)  # staggered arrivals: later requests join running batches
+    for t in threads:
+        t.join()
+    assert results[7] == alone
+    srv.close()
+    ctx.close()
+
+
+def test_admission_limits(rsl):
+    ctx = rsl.Context(device=0, workspace_bytes=64 << 20)
+    big = dense_total(rng_for(721, 0), 20, 40)
+    small = requests(1, 2)[0]
+    srv = rsl.Server(ctx, budget_bytes=1 << 20, max_slots=4, max_queue=3)
+    with pytest.raises(rsl.RSLError) as ei:
+        srv.submit(big, big, "y")  # footprint above the whole budget
+    assert ei.value.code == rsl.RSL_ENOMEM
+    tickets, refused = [], 0
+    for _ in range(40):
+        t = srv.try_submit(*small)
+        if t is None:
+            refused += 1
+        else:
+            tickets.append(t)
+    outs = [srv.wait(t) for t in tickets]
+    assert refused > 0 and all(o == outs[0] for o in outs)
+    st = srv.stats()
+    assert st["rejected"] >= refused
+    srv.close()
+    ctx.close()
