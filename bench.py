@@ -86,6 +86,67 @@ def cpu_baseline(f, g, pairs_per_resultant, seconds=12.0):
     }
 
 
+def serve_bench(n):
+    """Serving workload: requests with degrees U{8..48}, bits U{8..48}, res_y or res_x.
+
+    Saturated throughput T of the server (all requests submitted at once), then
+    Poisson arrivals at 0.5 T, 0.8 T and 1.0 T with p50/p99 latency, against the
+    serial plain path (one rsl_res call after the other)."""
+    import threading
+    import numpy as np
+    import paper_1010_1386_amd as rsl
+    import workloads
+
+    reqs = workloads.config5(n)
+    polys = [(rsl.Poly(f), rsl.Poly(g), v) for f, g, v in reqs]
+    ctx = rsl.Context(0, workspace_bytes=1 << 30)
+    # serial plain path (also warms the constant tables for the largest shapes)
+    lat_plain = []
+    t0 = time.perf_counter()
+    for f, g, v in polys:
+        t1 = time.perf_counter()
+        ctx.res(f, g, v)
+        lat_plain.append((time.perf_counter() - t1) * 1e3)
+    plain_rate = n / (time.perf_counter() - t0)
+
+    def run(rate, budget=64 << 20):
+        srv = rsl.Server(ctx, budget_bytes=budget, max_slots=256, max_queue=1 << 20)
+        arrivals = None if rate is None else workloads.poisson_arrivals(n, rate)
+        tickets = [None] * n
+        t_start = time.perf_counter()
+
+        def producer():
+            for k, (f, g, v) in enumerate(polys):
+                if arrivals is not None:
+                    dt = arrivals[k] - (time.perf_counter() - t_start)
+                    if dt > 0:
+                        time.sleep(dt)
+                tickets[k] = srv.submit(f, g, v)
+
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        for t in tickets:
+            srv.wait(t)
+        wall = time.perf_counter() - t_start
+        st = srv.stats()
+        srv.close()
+        return {"offered_rps": rate, "completed": st["completed"], "resultants_per_s": n / wall,
+                "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+                "device_iterations": st["launches"], "max_batch": st["max_batch"],
+                "admitted_bytes_peak": st["admitted_bytes_peak"], "budget_bytes": budget}
+
+    sat = run(None)
+    T = sat["resultants_per_s"]
+    loads = [run(f * T) for f in (0.5, 0.8, 1.0)]
+    ctx.close()
+    return {"metric": "serving: resultants/s and latency, continuous batching vs serial plain path",
+            "requests": n, "workload": "degrees U{8..48}, signed U{8..48}-bit, dense, res_y/res_x w.p. 1/2",
+            "saturated": sat, "poisson": loads,
+            "serial_plain": {"resultants_per_s": plain_rate, "p50_ms": float(np.percentile(lat_plain, 50)),
+                             "p99_ms": float(np.percentile(lat_plain, 99))}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +154,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=100)
+    ap.add_argument("--serve", type=int, default=0, metavar="N",
+                    help="serving benchmark instead: N Poisson-arriving requests of the serving workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
     a = ap.parse_args()
@@ -113,6 +176,10 @@ def main():
     import torch
     import paper_1010_1386_amd as rsl
     import workloads
+
+    if a.serve:
+        print(json.dumps(serve_bench(a.serve)))
+        return
 
     f, g = workloads.config2()
     problems = [(f, g, "y"), (f, g, "x")]

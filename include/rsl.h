@@ -51,8 +51,12 @@ extern "C" {
 
 /* execution modes of rsl_batch / rsl_job_run */
 #define RSL_PLAIN 0   /* one pipeline (reduce, eval+ures, interp, crt) per problem          */
-#define RSL_BATCHED 1 /* all problems in one persistent launch (device task queue)          */
+#define RSL_BATCHED 1 /* all problems in one persistent launch (device task queue); a wave
+                         waits at most RSL_QUEUE_WAIT_MS (environment, read by
+                         rsl_ctx_create; default 10000) for its next task, after which
+                         the launch ends and the run returns RSL_EDEVICE             */
 #define RSL_STAGED 2  /* one launch per stage, each over the work items of all problems     */
+#define RSL_AUTO 3    /* the schedule the autotuner chose for this shape (RSL_STAGED if none) */
 
 /* point policy (rsl_opts.points) */
 #define RSL_POINTS_REPLACE 0 /* bad points skipped: first D+1 good points of 0..D+s */
@@ -192,6 +196,31 @@ int rsl_job_run(rsl_ctx *ctx, rsl_job *job, int mode);
 int rsl_job_results(rsl_ctx *ctx, rsl_job *job, rsl_result *out, int *status);
 int rsl_job_info_get(const rsl_job *job, rsl_job_info *info);
 int rsl_job_destroy(rsl_job *job);
+
+/* --------------------------------------------------------------- autotuner */
+/*
+ * The autotuner times candidate schedules of a job -- staged or persistent
+ * launch, interpolation chunking (blocks kept in flight), persistent grid size
+ * -- on the job itself, checks that every candidate produces the same output
+ * bytes as the first (a candidate that differs is an error, RSL_EDEVICE), keeps
+ * the fastest, re-lays the job out with it, and records it in the context's
+ * cache under the job's shape bucket (problems, max degree bound, max primes,
+ * max degree, all rounded to powers of two).  Jobs created later with the
+ * same bucket are laid out with the cached choice; RSL_AUTO runs it.
+ */
+typedef struct {
+  int32_t mode;          /* RSL_STAGED or RSL_BATCHED */
+  int32_t chunk_target;  /* interpolation blocks kept in flight */
+  int32_t grid_mult;     /* persistent workgroups per resident slot */
+  int32_t candidates;    /* candidates timed */
+  double ms;             /* device time of one run of the chosen schedule */
+  double ms_worst;       /* device time of the slowest candidate */
+} rsl_tune_result;
+
+int rsl_job_tune(rsl_ctx *ctx, rsl_job *job, int reps, rsl_tune_result *best);
+/* Save / load the tuning cache as text lines "key mode chunk_target grid_mult ms". */
+int rsl_tune_save(rsl_ctx *ctx, const char *path);
+int rsl_tune_load(rsl_ctx *ctx, const char *path);
 
 /* --------------------------------------------------------------- profiling */
 /* Stages: 0 reduce, 1 eval+ures, 2 interp (convolution), 3 interp (basis

@@ -29,14 +29,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_HERE, "librsl.so")
 
 if not os.path.exists(_LIBPATH):
-    raise ImportError(f"librsl.so not built ({_LIBPATH}); run `python -m paper_1010_1386_amd.build`")
+    raise ImportError(f"librsl.so not built ({_LIBPATH}); run `python paper_1010_1386_amd/build.py`")
 
 _lib = ctypes.CDLL(_LIBPATH)
 
 RSL_OK, RSL_EINVAL, RSL_ERANGE, RSL_ENOMEM, RSL_EPRIMES, RSL_EDEVICE, RSL_EAGAIN, RSL_ETIMEDOUT = (
     0, -1, -2, -3, -4, -5, -6, -7)
 RSL_Y, RSL_X = 0, 1
-RSL_PLAIN, RSL_BATCHED, RSL_STAGED = 0, 1, 2
+RSL_PLAIN, RSL_BATCHED, RSL_STAGED, RSL_AUTO = 0, 1, 2, 3
 RSL_POINTS_REPLACE, RSL_POINTS_FORMAL = 0, 1
 
 
@@ -83,6 +83,11 @@ class rsl_job_info(ctypes.Structure):
                 ("download_bytes", ctypes.c_size_t)]
 
 
+class rsl_tune_result(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("chunk_target", ctypes.c_int32), ("grid_mult", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("ms", ctypes.c_double), ("ms_worst", ctypes.c_double)]
+
+
 STAGES = ("reduce", "eval_ures", "interp_conv", "interp_stir", "interp_newton", "crt")
 
 _P = ctypes.POINTER
@@ -110,6 +115,9 @@ _SIGS = {
     "rsl_job_results": (ctypes.c_int, [_vp, _vp, _P(rsl_result), _P(ctypes.c_int)]),
     "rsl_job_info_get": (ctypes.c_int, [_vp, _P(rsl_job_info)]),
     "rsl_job_destroy": (ctypes.c_int, [_vp]),
+    "rsl_job_tune": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _P(rsl_tune_result)]),
+    "rsl_tune_save": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+    "rsl_tune_load": (ctypes.c_int, [_vp, ctypes.c_char_p]),
     "rsl_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "rsl_profile_take": (ctypes.c_int, [_vp, _P(ctypes.c_double), _P(ctypes.c_int)]),
     "rsl_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -325,15 +333,23 @@ class Context:
         self._check(_lib.rsl_profile_take(self.h, ms, ctypes.byref(runs)), "rsl_profile_take")
         return dict(zip(STAGES, list(ms))), runs.value
 
+    def tune_save(self, path):
+        with self.lock:
+            self._check(_lib.rsl_tune_save(self.h, os.fsencode(path)), "rsl_tune_save")
+
+    def tune_load(self, path):
+        with self.lock:
+            self._check(_lib.rsl_tune_load(self.h, os.fsencode(path)), "rsl_tune_load")
+
     def job(self, problems, **opts):
         return Job(self, problems, **opts)
 
 
 def _modecode(mode):
-    codes = {"plain": RSL_PLAIN, "batched": RSL_BATCHED, "staged": RSL_STAGED,
-             RSL_PLAIN: RSL_PLAIN, RSL_BATCHED: RSL_BATCHED, RSL_STAGED: RSL_STAGED}
+    codes = {"plain": RSL_PLAIN, "batched": RSL_BATCHED, "staged": RSL_STAGED, "auto": RSL_AUTO,
+             RSL_PLAIN: RSL_PLAIN, RSL_BATCHED: RSL_BATCHED, RSL_STAGED: RSL_STAGED, RSL_AUTO: RSL_AUTO}
     if mode not in codes:
-        raise ValueError("mode must be 'plain', 'batched' or 'staged'")
+        raise ValueError("mode must be 'plain', 'batched', 'staged' or 'auto'")
     return codes[mode]
 
 
@@ -382,6 +398,17 @@ class Job:
             self._outs[k].c = self.ra[k]
             out.append(self._outs[k].value())
         return out
+
+    def tune(self, reps=5):
+        """Time the candidate schedules on this job, keep the fastest (the job is laid
+        out again with it) and remember it for jobs of the same shape bucket."""
+        r = rsl_tune_result()
+        with self.ctx.lock:
+            rc = _lib.rsl_job_tune(self.ctx.h, self.h, int(reps), ctypes.byref(r))
+        self.ctx._check(rc, "rsl_job_tune")
+        names = {RSL_STAGED: "staged", RSL_BATCHED: "batched"}
+        return {"mode": names.get(r.mode, r.mode), "chunk_target": r.chunk_target, "grid_mult": r.grid_mult,
+                "candidates": r.candidates, "ms": r.ms, "ms_worst": r.ms_worst}
 
     def info(self):
         i = rsl_job_info()

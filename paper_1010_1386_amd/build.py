@@ -1,6 +1,6 @@
 """Build the native library librsl.so (HIP kernels for gfx950 + C-ABI host code).
 
-Usage: python -m paper_1010_1386_amd.build   (or build() from __graft_entry__)
+Usage: python paper_1010_1386_amd/build.py   (or build() from __graft_entry__)
 
 Every source is compiled with hipcc for --offload-arch=gfx950 into _build/
 and linked into paper_1010_1386_amd/librsl.so (in-tree, so that a snapshot of
@@ -21,7 +21,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librsl.so")
 
-SOURCES = ["kernels.hip", "api.cpp", "plan.cpp", "job.cpp", "batch.cpp", "server.cpp", "persistent.hip"]
+SOURCES = ["kernels.hip", "api.cpp", "plan.cpp", "job.cpp", "tune.cpp", "server.cpp", "persistent.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed fp32 forms are never wanted in this integer code

@@ -2,10 +2,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
-#include "batch.h"
 #include "context.h"
 #include "job.h"
 #include "kernels.h"
@@ -209,6 +209,20 @@ static int run_in_workspace(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_po
   std::string err;
   int rc = job_build(ctx, n, f, g, var, opts, &J, &err);
   if (rc == RSL_EDEVICE) return rc;
+  if (mode == RSL_AUTO) {
+    // the schedule the autotuner chose for this shape, else the staged default
+    mode = RSL_STAGED;
+    auto it = ctx->tune_cache.find(tune_key(J));
+    if (it != ctx->tune_cache.end()) {
+      mode = it->second.cfg.mode;
+      if (it->second.cfg.chunk_target != J.tune.chunk_target) {
+        J = Job();
+        err.clear();
+        rc = job_build(ctx, n, f, g, var, opts, &J, &err, &it->second.cfg);
+        if (rc == RSL_EDEVICE) return rc;
+      }
+    }
+  }
   if (!J.live.empty()) {
     if (J.total > ctx->ws_bytes) {
       const std::string m = "workspace of " + std::to_string(ctx->ws_bytes) + " bytes < footprint " +
@@ -259,6 +273,12 @@ int rsl_ctx_create(int device, void* d_workspace, size_t ws_bytes, void* stream,
     delete c;
     return RSL_EDEVICE;
   }
+  // bound on a persistent-launch wave's wait for its next task
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || khz <= 0) khz = 100000;
+  double wait_ms = 10000.0;
+  if (const char* env = std::getenv("RSL_QUEUE_WAIT_MS")) wait_ms = std::max(0.0, std::atof(env));
+  c->queue_wait_ticks = static_cast<int64_t>(wait_ms * khz);
   *out = c;
   return RSL_OK;
 }
@@ -268,7 +288,6 @@ int rsl_ctx_destroy(rsl_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   free_tables(ctx);
-  batch_release(ctx);
   if (ctx->h_up) (void)hipHostFree(ctx->h_up);
   if (ctx->h_down) (void)hipHostFree(ctx->h_down);
   if (ctx->e0) (void)hipEventDestroy(ctx->e0);
@@ -335,8 +354,8 @@ int rsl_res_x(rsl_ctx* ctx, const rsl_poly* f, const rsl_poly* g, rsl_result* ou
 int rsl_batch(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var, rsl_result* out,
               int* status, int mode) {
   if (!ctx || n < 0 || (n > 0 && (!f || !g || !var || !out))) return RSL_EINVAL;
-  if (mode != RSL_PLAIN && mode != RSL_BATCHED && mode != RSL_STAGED)
-    return fail(ctx, RSL_EINVAL, "mode must be RSL_PLAIN, RSL_BATCHED or RSL_STAGED");
+  if (mode != RSL_PLAIN && mode != RSL_BATCHED && mode != RSL_STAGED && mode != RSL_AUTO)
+    return fail(ctx, RSL_EINVAL, "mode must be RSL_PLAIN, RSL_BATCHED, RSL_STAGED or RSL_AUTO");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   if (ctx->poisoned) return RSL_EDEVICE;
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, RSL_EDEVICE, "hipSetDevice");
@@ -372,137 +391,6 @@ const char* rsl_strerror(int code) {
 const char* rsl_last_error(rsl_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 const char* rsl_version(void) { return "rsl 0.1 (gfx950)"; }
-
-// ----------------------------------------------------------- resident jobs
-
-}  // extern "C"
-
-struct rsl_job {
-  rsl::Job J;
-  uint8_t* dmem = nullptr;
-  uint8_t* hdown = nullptr;
-  int gen = -1;
-  rsl_ctx* ctx = nullptr;
-};
-
-namespace rsl {
-
-// Re-point the job's problems at the current constant tables if they moved.
-static int job_refresh(rsl_ctx* ctx, rsl_job* j) {
-  if (j->gen == ctx->table_gen) return RSL_OK;
-  int rc = job_upload(ctx, &j->J, ctx->stream);
-  if (rc) return rc;
-  j->gen = ctx->table_gen;
-  return RSL_OK;
-}
-
-// Per-stage events of one batched launch (profiling).
-static hipEvent_t* next_evset(rsl_ctx* ctx) {
-  if (ctx->evused == static_cast<int>(ctx->evsets.size())) {
-    std::vector<hipEvent_t> set(kNumStages + 1, nullptr);
-    for (auto& e : set)
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    ctx->evsets.push_back(set);
-  }
-  return ctx->evsets[ctx->evused++].data();
-}
-
-}  // namespace rsl
-
-extern "C" {
-
-int rsl_job_create(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var,
-                   const rsl_opts* opts, int* status, rsl_job** out) {
-  if (!ctx || !out || n < 0 || (n > 0 && (!f || !g || !var))) return RSL_EINVAL;
-  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-  if (ctx->poisoned) return RSL_EDEVICE;
-  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, RSL_EDEVICE, "hipSetDevice");
-  *out = nullptr;
-  rsl_job* j = new (std::nothrow) rsl_job();
-  if (!j) return RSL_ENOMEM;
-  j->ctx = ctx;
-  std::string err;
-  int rc = job_build(ctx, n, f, g, var, opts, &j->J, &err);
-  if (status)
-    for (int k = 0; k < n; ++k) status[k] = j->J.pstatus[k];
-  if (rc == RSL_EDEVICE) { delete j; return rc; }
-  if (!err.empty()) ctx->err = err;
-  const size_t bytes = std::max<size_t>(j->J.total, 256);
-  if ((rc = hip_check(ctx, hipMalloc(reinterpret_cast<void**>(&j->dmem), bytes), "hipMalloc(job)")) ||
-      (rc = hip_check(ctx, hipHostMalloc(reinterpret_cast<void**>(&j->hdown), std::max<size_t>(j->J.down_bytes, 256),
-                                         hipHostMallocDefault), "hipHostMalloc(job)"))) {
-    if (j->dmem) (void)hipFree(j->dmem);
-    delete j;
-    return rc;
-  }
-  job_bind(&j->J, j->dmem);
-  if ((rc = job_upload(ctx, &j->J, ctx->stream)) ||
-      (rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize"))) {
-    (void)hipFree(j->dmem);
-    (void)hipHostFree(j->hdown);
-    delete j;
-    return rc;
-  }
-  j->gen = ctx->table_gen;
-  *out = j;
-  return RSL_OK;
-}
-
-int rsl_job_run(rsl_ctx* ctx, rsl_job* j, int mode) {
-  if (!ctx || !j || j->ctx != ctx) return RSL_EINVAL;
-  if (mode != RSL_PLAIN && mode != RSL_BATCHED && mode != RSL_STAGED)
-    return fail(ctx, RSL_EINVAL, "mode must be RSL_PLAIN, RSL_BATCHED or RSL_STAGED");
-  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-  if (ctx->poisoned) return RSL_EDEVICE;
-  int rc;
-  if ((rc = job_refresh(ctx, j)) || (rc = job_reset(ctx, &j->J, ctx->stream))) return rc;
-  if (ctx->profiling && mode != RSL_PLAIN) {
-    hipEvent_t* ev = next_evset(ctx);
-    if (!ev) return fail(ctx, RSL_EDEVICE, "hipEventCreate");
-    for (int s = 0; s <= kNumStages; ++s) ctx->ev[s] = ev[s];
-    return job_launch(ctx, &j->J, mode, ctx->stream, true);
-  }
-  return job_launch(ctx, &j->J, mode, ctx->stream, false);
-}
-
-int rsl_job_results(rsl_ctx* ctx, rsl_job* j, rsl_result* out, int* status) {
-  if (!ctx || !j || j->ctx != ctx || (j->J.n > 0 && !out)) return RSL_EINVAL;
-  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-  if (ctx->poisoned) return RSL_EDEVICE;
-  int rc;
-  if ((rc = job_download(ctx, &j->J, j->hdown, ctx->stream)) ||
-      (rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize")))
-    return rc;
-  rsl_counters cnt{};
-  rc = job_decode(ctx, j->J, j->hdown, out, status, &cnt);
-  ctx->last = cnt;
-  return rc;
-}
-
-int rsl_job_info_get(const rsl_job* j, rsl_job_info* info) {
-  if (!j || !info) return RSL_EINVAL;
-  info->n_problems = j->J.n;
-  info->n_live = static_cast<int32_t>(j->J.live.size());
-  info->pairs = j->J.pairs;
-  info->mulmods = j->J.mulmods;
-  info->device_bytes = j->J.total;
-  info->upload_bytes = j->J.up_bytes;
-  info->download_bytes = j->J.down_bytes;
-  return RSL_OK;
-}
-
-int rsl_job_destroy(rsl_job* j) {
-  if (!j) return RSL_EINVAL;
-  if (j->ctx) {
-    std::lock_guard<std::recursive_mutex> lk(j->ctx->mu);
-    (void)hipSetDevice(j->ctx->device);
-    (void)hipStreamSynchronize(j->ctx->stream);
-  }
-  if (j->dmem) (void)hipFree(j->dmem);
-  if (j->hdown) (void)hipHostFree(j->hdown);
-  delete j;
-  return RSL_OK;
-}
 
 int rsl_profile_enable(rsl_ctx* ctx, int on) {
   if (!ctx) return RSL_EINVAL;

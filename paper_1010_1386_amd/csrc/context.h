@@ -4,6 +4,7 @@
 
 #include <chrono>
 #include <cstdint>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -12,6 +13,19 @@
 #include "device.h"
 #include "plan.h"
 #include "stages.h"
+
+namespace rsl {
+// Schedule parameters of a job layout (chosen by the autotuner).
+struct TuneConfig {
+  int mode = RSL_STAGED;      // RSL_STAGED or RSL_BATCHED
+  int chunk_target = 4096;    // interpolation blocks to keep in flight (sets the k-/i-chunking)
+  int grid_mult = 1;          // persistent launch: workgroups = grid_mult x resident capacity
+};
+struct TuneEntry {
+  TuneConfig cfg;
+  double ms = 0.0;            // measured time per run of the winning schedule
+};
+}  // namespace rsl
 
 struct rsl_ctx {
   int device = 0;
@@ -47,6 +61,8 @@ struct rsl_ctx {
   int evused = 0;
   bool profiling = false;
   int table_gen = 0;                          // bumped whenever the constant tables move
+  int64_t queue_wait_ticks = 0;               // persistent launch: longest wait for a task (counter ticks)
+  std::map<std::string, rsl::TuneEntry> tune_cache; // shape bucket -> best schedule
   rsl_counters last{};
   std::recursive_mutex mu;
 };

@@ -37,6 +37,7 @@ struct DevProblem {
   int np, L_out;     // primes, CRT output limbs
   int LP, tgs;       // row stride of Plimb and of Tg
   int nchunk, kchunk;// Stirling partial sums: k-chunks and rows per chunk
+  int ncchunk, cchunk;// convolution partial sums: i-chunks and terms per chunk
   // inputs (uploaded)
   const uint32_t* coeff;  // ncoef * L_in two's complement limbs
   const int* gdeg;        // max x-degree per group of kRowGroup rows: f groups then g groups
@@ -50,7 +51,7 @@ struct DevProblem {
   uint32_t* resid;        // np * CS     transposed tiles, c R^2 mod p
   uint32_t* zval;         // np * (E+1)  R(x_i) mod p, normal form
   uint8_t* zbad;          // np * (E+1)  leading coefficient vanished at x_i
-  uint32_t* aconv;        // np * (D+1)  Newton coefficients (consecutive points)
+  uint64_t* aconv;        // ncchunk * np * (D+1): partial sums, REDC(sum) = Newton coefficient a_k
   uint64_t* cpart;        // nchunk * np * (D+1): partial sums, REDC(sum) = coefficient mod p
   uint32_t* out;          // (D+1) * L_out two's complement limbs of R
   int* status;            // [0] error bits, [1+slot] 1 if gapped interpolation, [1+np] bad pairs

@@ -25,7 +25,9 @@ static int64_t pair_mulmods(const Plan& P) {
 }
 
 int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var, const rsl_opts* opts,
-              Job* J, std::string* err) {
+              Job* J, std::string* err, const TuneConfig* tc) {
+  J->tune = tc ? *tc : TuneConfig();
+  const int64_t target = std::max(64, J->tune.chunk_target);
   J->n = n;
   J->plans.assign(n, Plan());
   J->pstatus.assign(n, 0);
@@ -98,10 +100,12 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     d.np = P.np;
     d.L_out = P.L_out;
     int nch = 1;
-    if (stir_base < 4096) nch = static_cast<int>((4096 + stir_base - 1) / std::max<int64_t>(stir_base, 1));
+    if (stir_base < target) nch = static_cast<int>((target + stir_base - 1) / std::max<int64_t>(stir_base, 1));
     nch = std::max(1, std::min(nch, (P.D + 1 + 127) / 128));
     d.kchunk = (P.D + 1 + nch - 1) / nch;
     d.nchunk = (P.D + 1 + d.kchunk - 1) / d.kchunk;
+    d.cchunk = d.kchunk;  // same split for the convolution's input range
+    d.ncchunk = d.nchunk;
     J->crt_ns = std::max(J->crt_ns, (P.np + 63) / 64);
     J->pairs += static_cast<int64_t>(P.np) * (P.E + 1);
     J->mulmods += pair_mulmods(P) * P.np * (P.E + 1);
@@ -118,7 +122,9 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     for (int sl = 0; sl < P.np; ++sl)
       for (int b = 0; b < blocks_of(P.E + 1, 64); ++b) J->items[kStageEval].push_back({li, sl, b, 0});
     for (int sl = 0; sl < P.np; ++sl)
-      for (int b = 0; b < blocks_of(P.D + 1, 256); ++b) J->items[kStageConv].push_back({li, sl, b, 0});
+      for (int b = 0; b < blocks_of(P.D + 1, 256); ++b)
+        for (int ch = 0; ch < d.ncchunk; ++ch)
+          if (ch * d.cchunk <= std::min(P.D, b * 256 + 255)) J->items[kStageConv].push_back({li, sl, b, ch});
     for (int sl = 0; sl < P.np; ++sl)
       for (int b = 0; b < blocks_of(P.D + 1, 256); ++b)
         for (int ch = 0; ch < d.nchunk; ++ch) {
@@ -167,7 +173,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       const DevProblem& d = J->dev[li];
       const int64_t ne = blocks_of(P.E + 1, 64), nc = blocks_of(P.D + 1, 64);
       const int64_t ns = nc * d.nchunk;
-      cap += static_cast<int64_t>(P.np) * (1 + ne + std::max<int64_t>(nc + ns, 1));
+      cap += static_cast<int64_t>(P.np) * (1 + ne + std::max<int64_t>(nc * d.ncchunk + ns, 1));
       const int64_t ncrt = blocks_of(P.D + 1, kCrtPerTask);
       cap += ncrt;
       crt_total += ncrt;
@@ -214,7 +220,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     L.resid = o; o = align_up(o + np * d.CS * 4, A);
     L.zval = o;  o = align_up(o + np * (P.E + 1) * 4, A);
     L.zbad = o;  o = align_up(o + np * (P.E + 1), A);
-    L.aconv = o; o = align_up(o + np * (P.D + 1) * 4, A);
+    L.aconv = o; o = align_up(o + static_cast<size_t>(d.ncchunk) * np * (P.D + 1) * 8, A);
     L.cpart = o; o = align_up(o + static_cast<size_t>(d.nchunk) * np * (P.D + 1) * 8, A);
   }
   J->queue_off = o;
@@ -227,7 +233,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     const DevProblem& d = J->dev[li];
     auto up = [&](int s, size_t words) { J->stage_lds[s] = std::max(J->stage_lds[s], words * 4); };
     up(kStageEval, eval_lds_words(d));
-    up(kStageConv, static_cast<size_t>(2) * (std::min(d.D + 1, 256 * blocks_of(d.D + 1, 256))));
+    up(kStageConv, static_cast<size_t>(std::min(d.cchunk, d.D + 1)) + std::min(d.D + 1, d.cchunk + 256));
     up(kStageStir, d.kchunk);
     if (J->lay[li].item_end[kStageNewton] > J->lay[li].item_begin[kStageNewton]) up(kStageNewton, newton_lds_words(d, 1024));
     up(kStageCrt, crt_lds_words(d, J->crt_ns, kCrtWaves));
@@ -236,7 +242,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   for (int li = 0; li < nl; ++li) {
     const DevProblem& d = J->dev[li];
     size_t w = eval_lds_words(d);
-    w = std::max<size_t>(w, static_cast<size_t>(2) * (d.D + 1));
+    w = std::max<size_t>(w, static_cast<size_t>(std::min(d.cchunk, d.D + 1)) + std::min(d.D + 1, d.cchunk + 64));
     w = std::max<size_t>(w, d.kchunk);
     if (J->lay[li].item_end[kStageNewton] > J->lay[li].item_begin[kStageNewton])
       w = std::max<size_t>(w, newton_lds_words(d, 64));
@@ -308,7 +314,7 @@ void job_bind(Job* J, uint8_t* base) {
     d.resid = reinterpret_cast<uint32_t*>(base + L.resid);
     d.zval = reinterpret_cast<uint32_t*>(base + L.zval);
     d.zbad = base + L.zbad;
-    d.aconv = reinterpret_cast<uint32_t*>(base + L.aconv);
+    d.aconv = reinterpret_cast<uint64_t*>(base + L.aconv);
     d.cpart = reinterpret_cast<uint64_t*>(base + L.cpart);
     d.out = reinterpret_cast<uint32_t*>(base + L.out);
     d.status = reinterpret_cast<int*>(base + L.status);
@@ -328,7 +334,7 @@ void job_bind(Job* J, uint8_t* base) {
       cnt[li].slots_left = P.np;
       for (int sl = 0; sl < P.np; ++sl) {
         cnt[li].eval_left[sl] = ne;
-        cnt[li].conv_left[sl] = nc;
+        cnt[li].conv_left[sl] = nc * d.ncchunk;
         cnt[li].stir_left[sl] = nc * d.nchunk;
         tasks[t] = Task{(kTaskReduce << 24) | li, sl, 0, 0};
         ready[t] = 1;
@@ -419,12 +425,13 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
     Q.capacity = J->q_capacity;
     Q.crt_total = J->q_crt_total;
     Q.nprob = static_cast<int>(J->live.size());
+    Q.wait_ticks = ctx->queue_wait_ticks;
     if (J->persist_grid == 0) {
       const int per_cu = persistent_blocks_per_cu(J->crt_ns, J->persist_lds);
       int cus = 256;
       hipDeviceProp_t prop;
       if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) cus = prop.multiProcessorCount;
-      J->persist_grid = std::max(1, per_cu * cus);
+      J->persist_grid = std::max(1, per_cu * cus * std::max(1, J->tune.grid_mult));
     }
     if ((rc = hip_check(ctx, hipMemcpyAsync(qb, J->base + J->qinit_off, J->queue_bytes, hipMemcpyDeviceToDevice, st),
                         "queue reset")))

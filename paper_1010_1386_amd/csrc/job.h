@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/rsl.h"
+#include "context.h"
 #include "device.h"
 #include "plan.h"
 #include "persistent.h"
@@ -18,6 +19,7 @@ struct rsl_ctx;
 
 namespace rsl {
 
+// Schedule parameters chosen by the autotuner (tune.cpp).
 struct ProbLayout {
   // offsets from the job base
   size_t coeff, gdeg, pidx, Hm, NH, Tg, invM, Plimb, status;
@@ -51,12 +53,16 @@ struct Job {
   uint8_t* base = nullptr;         // device region the job is laid out in
   std::vector<uint8_t> blob;       // host image of [0, up_bytes)
   int64_t pairs = 0;
-  int64_t mulmods = 0;             // algorithmic work of eval + ures (see DESIGN)
+  int64_t mulmods = 0;             // algorithmic work of eval + ures: Montgomery products over all pairs
+  TuneConfig tune;                 // schedule parameters the job was laid out with
 };
+
+// Autotuner cache key of a planned job (its shape bucket).
+std::string tune_key(const Job& J);
 
 // Plan every problem and lay the job out (host only).
 int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var, const rsl_opts* opts,
-              Job* J, std::string* err);
+              Job* J, std::string* err, const TuneConfig* tc = nullptr);
 // Bind the job to a device region (fills device pointers and the upload image).
 void job_bind(Job* J, uint8_t* base);
 // Upload the inputs (asynchronous on the stream) through `pinned` (>= up_bytes of

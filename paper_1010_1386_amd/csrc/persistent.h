@@ -51,6 +51,7 @@ struct QueueDesc {
   int capacity;
   int crt_total;
   int nprob;
+  int64_t wait_ticks;  // longest wait for a queue slot, in wall-clock counter ticks
 };
 
 hipError_t launch_persistent(const DevProblem* probs, const QueueDesc& Q, const DevTables& T, int ns, int grid,

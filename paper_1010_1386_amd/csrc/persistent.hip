@@ -13,8 +13,9 @@
 //
 // Termination: every wave exits once the done flag is set (or on an error),
 // so a wave waiting on an empty queue slot never outlives the batch.  The
-// wait is bounded: after kSpinLimit polls the wave records kErrQueueStall and
-// raises the done flag, which ends the launch.
+// wait is bounded in wall-clock time (QueueDesc::wait_ticks of the constant
+// rate counter): past it the wave records kErrQueueStall and raises the done
+// flag, which ends the launch.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -24,8 +25,6 @@
 #include "stages.h"
 
 namespace rsl {
-
-constexpr int kSpinLimit = 1 << 26;
 
 __device__ __forceinline__ int ld_acquire(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -78,11 +77,11 @@ __global__ __launch_bounds__(64) void k_persistent(const DevProblem* probs, Queu
     if (tid == 0) {
       quit = 0;
       const int s = atomicAdd(&Q.state->head, 1);
-      int polls = 0;
-      for (;;) {
+      const uint64_t t0 = wall_clock64();
+      for (int polls = 1;; ++polls) {
         if (ld_acquire(&Q.state->done)) { quit = 1; break; }
         if (s < Q.capacity && ld_acquire(&Q.ready[s])) { cur = Q.tasks[s]; break; }
-        if (++polls > kSpinLimit) {
+        if ((polls & 63) == 0 && static_cast<int64_t>(wall_clock64() - t0) > Q.wait_ticks) {
           queue_abort(Q, probs);
           quit = 1;
           break;
@@ -124,7 +123,8 @@ __global__ __launch_bounds__(64) void k_persistent(const DevProblem* probs, Queu
         if (tid == 0) {
           if (fast) {
             const int nb = (P.D + 64) / 64;
-            enqueue(Q, probs, nb, [&](int i) { return mk(kTaskConv, prob, t.slot, i, 0); });
+            enqueue(Q, probs, nb * P.ncchunk,
+                    [&](int i) { return mk(kTaskConv, prob, t.slot, i / P.ncchunk, i % P.ncchunk); });
           } else {
             enqueue(Q, probs, 1, [&](int) { return mk(kTaskNewton, prob, t.slot, 0, 0); });
           }

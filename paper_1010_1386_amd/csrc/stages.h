@@ -203,8 +203,10 @@ __device__ inline bool fast_prime(const DevProblem& P, int slot) {
   return __syncthreads_or(any) == 0;
 }
 
-// Newton forward differences at 0..D as a convolution:
+// Newton forward differences at 0..D as a convolution, one i-chunk of it:
 //   a_k = Delta^k z_0 / k! = sum_{i<=k} (z_i / i!) ((-1)^(k-i) / (k-i)!)
+// Each thread owns one k; the chunk's partial sum is stored unreduced
+// (below p 2^32; REDC of the sum over chunks is a_k).
 __device__ inline void stage_interp_conv(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
   if (!fast_prime(P, w.slot)) return;
   const int g = P.pidx[w.slot];
@@ -214,28 +216,34 @@ __device__ inline void stage_interp_conv(const DevProblem& P, const DevTables& T
   const int nt = blockDim.x;
   const int k0 = w.blk * nt;
   const int kmax = (k0 + nt - 1 < P.D) ? k0 + nt - 1 : P.D;
+  const int ib = w.sub * P.cchunk;
+  const int ie = (ib + P.cchunk - 1 < kmax) ? ib + P.cchunk - 1 : kmax;  // last i used by this block
+  // alpha_i = z_i / i! for i in [ib, ie]; beta_t = (-1)^t / t! R for t in [k0 - ie, kmax - ib]
+  const int tb = (k0 - ie > 0) ? k0 - ie : 0;
+  const int te = kmax - ib;
   uint32_t* alpha = lds;
-  uint32_t* beta = lds + (kmax + 1);
+  uint32_t* beta = lds + (ie - ib + 1 > 0 ? ie - ib + 1 : 0);
   const uint32_t* z = P.zval + static_cast<size_t>(w.slot) * (P.E + 1);
-  for (int i = threadIdx.x; i <= kmax; i += nt) {
-    const uint32_t f = ifact[i];
-    alpha[i] = mmul(z[i], f, p, pinv);    // z_i / i!          (normal form)
-    beta[i] = (i & 1) ? mneg(f, p) : f;   // (-1)^i / i! R     (Montgomery form)
+  for (int i = ib + threadIdx.x; i <= ie; i += nt) alpha[i - ib] = mmul(z[i], ifact[i], p, pinv);
+  for (int t = tb + threadIdx.x; t <= te; t += nt) {
+    const uint32_t f = ifact[t];
+    beta[t - tb] = (t & 1) ? mneg(f, p) : f;
   }
   __syncthreads();
   const int k = k0 + threadIdx.x;
   if (k > P.D) return;
+  const int iend = (ie < k) ? ie : k;
   uint64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-  int i = 0;
-  for (; i + 3 <= k; i += 4) {
-    c0 = mac_fold(c0, alpha[i], beta[k - i], p);
-    c1 = mac_fold(c1, alpha[i + 1], beta[k - i - 1], p);
-    c2 = mac_fold(c2, alpha[i + 2], beta[k - i - 2], p);
-    c3 = mac_fold(c3, alpha[i + 3], beta[k - i - 3], p);
+  int i = ib;
+  for (; i + 3 <= iend; i += 4) {
+    c0 = mac_fold(c0, alpha[i - ib], beta[k - i - tb], p);
+    c1 = mac_fold(c1, alpha[i + 1 - ib], beta[k - i - 1 - tb], p);
+    c2 = mac_fold(c2, alpha[i + 2 - ib], beta[k - i - 2 - tb], p);
+    c3 = mac_fold(c3, alpha[i + 3 - ib], beta[k - i - 3 - tb], p);
   }
-  for (; i <= k; ++i) c0 = mac_fold(c0, alpha[i], beta[k - i], p);
+  for (; i <= iend; ++i) c0 = mac_fold(c0, alpha[i - ib], beta[k - i - tb], p);
   const uint64_t acc = add_fold(add_fold(c0, c1, p), add_fold(c2, c3, p), p);
-  P.aconv[static_cast<size_t>(w.slot) * (P.D + 1) + k] = redc(acc, p, pinv);
+  P.aconv[(static_cast<size_t>(w.sub) * P.np + w.slot) * (P.D + 1) + k] = acc;
 }
 
 // Falling-factorial basis -> monomials, one k-chunk of the sum
@@ -252,8 +260,14 @@ __device__ inline void stage_interp_stir(const DevProblem& P, const DevTables& T
   const int kb = w.sub * P.kchunk;
   const int ke = (kb + P.kchunk - 1 < P.D) ? kb + P.kchunk - 1 : P.D;
   const int ks = kb > j0 ? kb : j0;
-  const uint32_t* a = P.aconv + static_cast<size_t>(w.slot) * (P.D + 1);
-  for (int k = ks + threadIdx.x; k <= ke; k += nt) lds[k - ks] = a[k];
+  // a_k = REDC(sum of the convolution chunks that reach k)
+  const uint64_t* ap = P.aconv + static_cast<size_t>(w.slot) * (P.D + 1);
+  const size_t astride = static_cast<size_t>(P.np) * (P.D + 1);
+  for (int k = ks + threadIdx.x; k <= ke; k += nt) {
+    uint64_t s = 0;
+    for (int ch = 0; ch <= k / P.cchunk; ++ch) s = add_fold(s, ap[ch * astride + k], p);
+    lds[k - ks] = redc(s, p, pc.pinv);
+  }
   __syncthreads();
   const uint32_t* S = T.stir + static_cast<int64_t>(g) * T.sstride;
   uint64_t c0 = 0, c1 = 0;

@@ -1,0 +1,308 @@
+// Resident jobs (rsl_job_*) and the schedule autotuner (rsl_job_tune, rsl_tune_*).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+
+#include "context.h"
+#include "job.h"
+#include "kernels.h"
+
+struct rsl_job {
+  rsl::Job J;
+  uint8_t* dmem = nullptr;
+  uint8_t* hdown = nullptr;
+  int gen = -1;
+  rsl_ctx* ctx = nullptr;
+  // inputs, kept so that the autotuner can lay the job out again
+  std::vector<std::vector<uint32_t>> fbuf, gbuf;
+  std::vector<rsl_poly> f, g;
+  std::vector<int> var;
+  rsl_opts opts{};
+  bool has_opts = false;
+};
+
+namespace rsl {
+
+static int ilog2up(int64_t v) {
+  int b = 0;
+  while ((int64_t(1) << b) < v) ++b;
+  return b;
+}
+
+// Shape bucket of a job: problems, max degree bound, max primes, max degree in the
+// eliminated variable -- each rounded up to a power of two.
+std::string tune_key(const Job& J) {
+  int64_t maxD = 0, maxnp = 0, maxdeg = 0;
+  for (int k : J.live) {
+    const Plan& P = J.plans[k];
+    maxD = std::max<int64_t>(maxD, P.D + 1);
+    maxnp = std::max<int64_t>(maxnp, P.np);
+    maxdeg = std::max<int64_t>(maxdeg, std::max(P.my, P.ny) + 1);
+  }
+  std::ostringstream os;
+  os << "n" << ilog2up(std::max<size_t>(J.live.size(), 1)) << ".D" << ilog2up(maxD) << ".p" << ilog2up(maxnp)
+     << ".m" << ilog2up(maxdeg);
+  return os.str();
+}
+
+static void release_mem(rsl_job* j) {
+  if (j->dmem) (void)hipFree(j->dmem);
+  if (j->hdown) (void)hipHostFree(j->hdown);
+  j->dmem = nullptr;
+  j->hdown = nullptr;
+}
+
+// Lay the job out with `tc`, allocate its device buffers and upload the inputs.
+static int materialize(rsl_ctx* ctx, rsl_job* j, const TuneConfig& tc) {
+  release_mem(j);
+  j->J = Job();
+  std::string err;
+  const int n = static_cast<int>(j->f.size());
+  int rc = job_build(ctx, n, j->f.data(), j->g.data(), j->var.data(), j->has_opts ? &j->opts : nullptr, &j->J,
+                     &err, &tc);
+  if (rc == RSL_EDEVICE) return rc;
+  if (!err.empty()) ctx->err = err;
+  const size_t bytes = std::max<size_t>(j->J.total, 256);
+  if ((rc = hip_check(ctx, hipMalloc(reinterpret_cast<void**>(&j->dmem), bytes), "hipMalloc(job)")) ||
+      (rc = hip_check(ctx, hipHostMalloc(reinterpret_cast<void**>(&j->hdown),
+                                         std::max<size_t>(j->J.down_bytes, 256), hipHostMallocDefault),
+                      "hipHostMalloc(job)"))) {
+    release_mem(j);
+    return rc;
+  }
+  job_bind(&j->J, j->dmem);
+  if ((rc = job_upload(ctx, &j->J, ctx->stream)) ||
+      (rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize"))) {
+    release_mem(j);
+    return rc;
+  }
+  j->gen = ctx->table_gen;
+  return RSL_OK;
+}
+
+// Re-point the job's problems at the current constant tables if they moved.
+static int job_refresh(rsl_ctx* ctx, rsl_job* j) {
+  if (j->gen == ctx->table_gen) return RSL_OK;
+  int rc = job_upload(ctx, &j->J, ctx->stream);
+  if (rc) return rc;
+  j->gen = ctx->table_gen;
+  return RSL_OK;
+}
+
+// Per-stage events of one launch (profiling).
+static hipEvent_t* next_evset(rsl_ctx* ctx) {
+  if (ctx->evused == static_cast<int>(ctx->evsets.size())) {
+    std::vector<hipEvent_t> set(kNumStages + 1, nullptr);
+    for (auto& e : set)
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->evsets.push_back(set);
+  }
+  return ctx->evsets[ctx->evused++].data();
+}
+
+static int run_job(rsl_ctx* ctx, rsl_job* j, int mode) {
+  if (mode == RSL_AUTO) mode = j->J.tune.mode;
+  int rc;
+  if ((rc = job_refresh(ctx, j)) || (rc = job_reset(ctx, &j->J, ctx->stream))) return rc;
+  if (ctx->profiling && mode != RSL_PLAIN) {
+    hipEvent_t* ev = next_evset(ctx);
+    if (!ev) return fail(ctx, RSL_EDEVICE, "hipEventCreate");
+    for (int s = 0; s <= kNumStages; ++s) ctx->ev[s] = ev[s];
+    return job_launch(ctx, &j->J, mode, ctx->stream, true);
+  }
+  return job_launch(ctx, &j->J, mode, ctx->stream, false);
+}
+
+}  // namespace rsl
+
+using namespace rsl;
+
+extern "C" {
+
+int rsl_job_create(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var, const rsl_opts* opts,
+                   int* status, rsl_job** out) {
+  if (!ctx || !out || n < 0 || (n > 0 && (!f || !g || !var))) return RSL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  if (ctx->poisoned) return RSL_EDEVICE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, RSL_EDEVICE, "hipSetDevice");
+  *out = nullptr;
+  rsl_job* j = new (std::nothrow) rsl_job();
+  if (!j) return RSL_ENOMEM;
+  j->ctx = ctx;
+  j->fbuf.resize(n);
+  j->gbuf.resize(n);
+  j->f.resize(n);
+  j->g.resize(n);
+  j->var.assign(var, var + n);
+  for (int k = 0; k < n; ++k) {
+    auto copy = [](const rsl_poly& p, std::vector<uint32_t>* buf, rsl_poly* dst) {
+      *dst = p;
+      if (p.coeff && p.dx >= 0 && p.dy >= 0 && p.limbs >= 1) {
+        buf->assign(p.coeff, p.coeff + static_cast<size_t>(p.dx + 1) * (p.dy + 1) * p.limbs);
+        dst->coeff = buf->data();
+      }
+    };
+    copy(f[k], &j->fbuf[k], &j->f[k]);
+    copy(g[k], &j->gbuf[k], &j->g[k]);
+  }
+  if (opts) {
+    j->opts = *opts;
+    j->has_opts = true;
+  }
+  // the shape bucket's cached schedule, if the autotuner has seen this shape
+  TuneConfig tc;
+  if (!ctx->tune_cache.empty()) {
+    Job probe;
+    std::string e;
+    if (job_build(nullptr, n, j->f.data(), j->g.data(), j->var.data(), opts, &probe, &e) == RSL_OK) {
+      auto it = ctx->tune_cache.find(tune_key(probe));
+      if (it != ctx->tune_cache.end()) tc = it->second.cfg;
+    }
+  }
+  int rc = materialize(ctx, j, tc);
+  if (status)
+    for (int k = 0; k < n; ++k) status[k] = k < static_cast<int>(j->J.pstatus.size()) ? j->J.pstatus[k] : rc;
+  if (rc) {
+    release_mem(j);
+    delete j;
+    return rc;
+  }
+  *out = j;
+  return RSL_OK;
+}
+
+int rsl_job_run(rsl_ctx* ctx, rsl_job* j, int mode) {
+  if (!ctx || !j || j->ctx != ctx) return RSL_EINVAL;
+  if (mode != RSL_PLAIN && mode != RSL_BATCHED && mode != RSL_STAGED && mode != RSL_AUTO)
+    return fail(ctx, RSL_EINVAL, "mode must be RSL_PLAIN, RSL_BATCHED, RSL_STAGED or RSL_AUTO");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  if (ctx->poisoned) return RSL_EDEVICE;
+  return run_job(ctx, j, mode);
+}
+
+int rsl_job_results(rsl_ctx* ctx, rsl_job* j, rsl_result* out, int* status) {
+  if (!ctx || !j || j->ctx != ctx || (j->J.n > 0 && !out)) return RSL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  if (ctx->poisoned) return RSL_EDEVICE;
+  int rc;
+  if ((rc = job_download(ctx, &j->J, j->hdown, ctx->stream)) ||
+      (rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize")))
+    return rc;
+  rsl_counters cnt{};
+  rc = job_decode(ctx, j->J, j->hdown, out, status, &cnt);
+  ctx->last = cnt;
+  return rc;
+}
+
+int rsl_job_info_get(const rsl_job* j, rsl_job_info* info) {
+  if (!j || !info) return RSL_EINVAL;
+  info->n_problems = j->J.n;
+  info->n_live = static_cast<int32_t>(j->J.live.size());
+  info->pairs = j->J.pairs;
+  info->mulmods = j->J.mulmods;
+  info->device_bytes = j->J.total;
+  info->upload_bytes = j->J.up_bytes;
+  info->download_bytes = j->J.down_bytes;
+  return RSL_OK;
+}
+
+int rsl_job_destroy(rsl_job* j) {
+  if (!j) return RSL_EINVAL;
+  if (j->ctx) {
+    std::lock_guard<std::recursive_mutex> lk(j->ctx->mu);
+    (void)hipSetDevice(j->ctx->device);
+    (void)hipStreamSynchronize(j->ctx->stream);
+  }
+  release_mem(j);
+  delete j;
+  return RSL_OK;
+}
+
+int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
+  if (!ctx || !j || j->ctx != ctx || reps < 1) return RSL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  if (ctx->poisoned) return RSL_EDEVICE;
+  if (j->J.live.empty()) {
+    if (best) *best = rsl_tune_result{RSL_STAGED, j->J.tune.chunk_target, 1, 0, 0.0, 0.0};
+    return RSL_OK;
+  }
+  std::vector<TuneConfig> cands;
+  for (int target : {1024, 4096, 16384}) {
+    cands.push_back(TuneConfig{RSL_STAGED, target, 1});
+    cands.push_back(TuneConfig{RSL_BATCHED, target, 1});
+  }
+  cands.push_back(TuneConfig{RSL_BATCHED, 4096, 2});
+  std::vector<uint8_t> ref;
+  TuneConfig win = cands[0];
+  double win_ms = 1e300, worst_ms = 0.0;
+  int rc;
+  for (const TuneConfig& tc : cands) {
+    if ((rc = materialize(ctx, j, tc))) return rc;
+    // warm-up run (also the correctness check), then `reps` timed runs
+    if ((rc = run_job(ctx, j, tc.mode)) || (rc = job_download(ctx, &j->J, j->hdown, ctx->stream)) ||
+        (rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize")))
+      return rc;
+    // statuses and outputs do not depend on the schedule: every candidate must
+    // download the same bytes
+    std::vector<uint8_t> img(j->hdown, j->hdown + j->J.down_bytes);
+    if (ref.empty()) {
+      ref = img;
+    } else if (img != ref) {
+      return fail(ctx, RSL_EDEVICE, "autotuner: a candidate schedule produced different output bytes");
+    }
+    if ((rc = hip_check(ctx, hipEventRecord(ctx->e0, ctx->stream), "event"))) return rc;
+    for (int r = 0; r < reps; ++r)
+      if ((rc = run_job(ctx, j, tc.mode))) return rc;
+    if ((rc = hip_check(ctx, hipEventRecord(ctx->e1, ctx->stream), "event")) ||
+        (rc = hip_check(ctx, hipEventSynchronize(ctx->e1), "event")))
+      return rc;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ctx->e0, ctx->e1);
+    const double per = ms / reps;
+    worst_ms = std::max(worst_ms, per);
+    if (per < win_ms) {
+      win_ms = per;
+      win = tc;
+    }
+  }
+  if ((rc = materialize(ctx, j, win))) return rc;
+  ctx->tune_cache[tune_key(j->J)] = TuneEntry{win, win_ms};
+  if (best) *best = rsl_tune_result{win.mode, win.chunk_target, win.grid_mult, static_cast<int32_t>(cands.size()),
+                                    win_ms, worst_ms};
+  return RSL_OK;
+}
+
+int rsl_tune_save(rsl_ctx* ctx, const char* path) {
+  if (!ctx || !path) return RSL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  std::ofstream os(path);
+  if (!os) return fail(ctx, RSL_EINVAL, std::string("cannot write ") + path);
+  for (const auto& kv : ctx->tune_cache)
+    os << kv.first << " " << kv.second.cfg.mode << " " << kv.second.cfg.chunk_target << " "
+       << kv.second.cfg.grid_mult << " " << kv.second.ms << "\n";
+  return RSL_OK;
+}
+
+int rsl_tune_load(rsl_ctx* ctx, const char* path) {
+  if (!ctx || !path) return RSL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  std::ifstream is(path);
+  if (!is) return fail(ctx, RSL_EINVAL, std::string("cannot read ") + path);
+  std::string key;
+  TuneEntry e;
+  while (is >> key >> e.cfg.mode >> e.cfg.chunk_target >> e.cfg.grid_mult >> e.ms) {
+    if ((e.cfg.mode != RSL_STAGED && e.cfg.mode != RSL_BATCHED) || e.cfg.chunk_target < 64 || e.cfg.grid_mult < 1 ||
+        e.cfg.grid_mult > 8)
+      return fail(ctx, RSL_EINVAL, "malformed tuning cache line for " + key);
+    ctx->tune_cache[key] = e;
+  }
+  return RSL_OK;
+}
+
+}  // extern "C"

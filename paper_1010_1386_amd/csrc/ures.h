@@ -112,9 +112,15 @@ RSL_HD uint32_t ures_formal(Col A, Col B, int m, int n, const PrimeConst& pc, bo
   }
   if (b < n) num = mpow(A[a], static_cast<uint32_t>(n - b), one, p, pinv);
 
+  // In the usual case (deg A = deg B + 1 and every remainder one degree lower)
+  // the scalars a division needs -- L = lc(B), lc(A), A[b], B[b-1] -- are
+  // carried in registers from the previous division: new A = old B, new B = R~,
+  // so lc(A') = L, A'[b'] = B[b-1], L' = R~[b-1], B'[b'-1] = R~[b-2].
+  bool carried = false;
+  uint32_t cL = 0, clcA = 0, cAb = 0, cBb1 = 0;
   for (;;) {
     if (b == 0) {  // B a nonzero constant: Res(A, B) = B^a
-      num = mmul(num, mpow(B[0], static_cast<uint32_t>(a), one, p, pinv), p, pinv);
+      num = mmul(num, mpow(carried ? cL : B[0], static_cast<uint32_t>(a), one, p, pinv), p, pinv);
       break;
     }
     if (a == 0) {  // A a nonzero constant: Res(A, B) = A^b
@@ -125,14 +131,20 @@ RSL_HD uint32_t ures_formal(Col A, Col B, int m, int n, const PrimeConst& pc, bo
       Col t = A; A = B; B = t;
       int ti = a; a = b; b = ti;
       neg ^= static_cast<uint32_t>(a * b) & 1u;
+      carried = false;
       continue;
     }
-    const uint32_t L = B[b];
+    const uint32_t L = carried ? cL : B[b];
     const int k = a - b + 1;
     uint32_t y;  // L^k
+    int c;       // degree of the remainder
+    uint32_t last1 = 0, last2 = 0;  // R~[b-1], R~[b-2]
+    uint32_t Bb1 = 0;               // B[b-1]
     if (k == 2) {
-      const uint32_t lcA = A[a];
-      const uint32_t lcAt = mmulsub(L, A[b], lcA, B[b - 1], p, pinv);
+      const uint32_t lcA = carried ? clcA : A[a];
+      const uint32_t Ab = carried ? cAb : A[b];
+      Bb1 = carried ? cBb1 : B[b - 1];
+      const uint32_t lcAt = mmulsub(L, Ab, lcA, Bb1, p, pinv);
       const uint32_t alpha = mmul(L, L, p, pinv);
       const uint32_t beta = mneg(mmul(L, lcA, p, pinv), p);
       const uint32_t gamma = mneg(lcAt, p);
@@ -155,6 +167,8 @@ RSL_HD uint32_t ures_formal(Col A, Col B, int m, int n, const PrimeConst& pc, bo
           A[j + 1] = r1;
           A[j + 2] = r2;
           A[j + 3] = r3;
+          last2 = r2;
+          last1 = r3;
           prevB = b3;
           b0 = nb0; b1 = nb1; b2 = nb2; b3 = nb3;
           a0 = na0; a1 = na1; a2 = na2; a3 = na3;
@@ -162,10 +176,19 @@ RSL_HD uint32_t ures_formal(Col A, Col B, int m, int n, const PrimeConst& pc, bo
       }
       for (; j < b; ++j) {
         const uint32_t bj = B[j];
-        A[j] = mmad3(alpha, A[j], beta, prevB, gamma, bj, p, pinv);
+        const uint32_t r = mmad3(alpha, A[j], beta, prevB, gamma, bj, p, pinv);
+        A[j] = r;
+        last2 = last1;
+        last1 = r;
         prevB = bj;
       }
       y = alpha;
+      if (last1 != 0u) {
+        c = b - 1;
+      } else {
+        c = b - 2;
+        while (c >= 0 && A[c] == 0u) --c;
+      }
     } else {
       for (int d = a; d >= b; --d) {
         const uint32_t lc = A[d];
@@ -176,9 +199,14 @@ RSL_HD uint32_t ures_formal(Col A, Col B, int m, int n, const PrimeConst& pc, bo
         }
       }
       y = mpow(L, static_cast<uint32_t>(k), one, p, pinv);
+      c = b - 1;
+      while (c >= 0 && A[c] == 0u) --c;
+      if (c == b - 1) {  // the next division may still use carried scalars
+        Bb1 = B[b - 1];
+        last1 = A[b - 1];
+        last2 = (b >= 2) ? A[b - 2] : 0u;
+      }
     }
-    int c = b - 1;
-    while (c >= 0 && A[c] == 0u) --c;
     if (c < 0) return 0u;  // zero remainder with deg B >= 1: common factor at x_i
     neg ^= static_cast<uint32_t>(a * b) & 1u;
     const int delta = b - c;
@@ -186,6 +214,13 @@ RSL_HD uint32_t ures_formal(Col A, Col B, int m, int n, const PrimeConst& pc, bo
     num = mmul(num, (enum_ == k) ? y : mpow(L, static_cast<uint32_t>(enum_), one, p, pinv), p, pinv);
     U = mmul(U, y, p, pinv);
     den = mmul(den, (delta == 1) ? U : mpow(U, static_cast<uint32_t>(delta), one, p, pinv), p, pinv);
+    carried = (delta == 1);
+    if (carried) {
+      cL = last1;    // lc of the new B (= R~)
+      clcA = L;      // lc of the new A (= old B)
+      cAb = Bb1;     // new A[new b] = old B[b-1]
+      cBb1 = last2;  // new B[new b - 1] = R~[b-2]
+    }
     Col t = A; A = B; B = t;  // (A, B) <- (B, R~)
     a = b;
     b = c;

@@ -75,3 +75,51 @@ def test_resident_job_all_modes(ctx):
     job.close()
     assert all(o == outs[0] for o in outs)
     assert outs[0] == [oracle.res(f, g, v) for f, g, v in probs]
+
+
+def test_autotuner_keeps_bits_and_caches_choice(ctx, tmp_path):
+    probs = mixed_batch(20, 11)
+    want = [oracle.res(f, g, v) for f, g, v in probs]
+    job = ctx.job(probs)
+    best = job.tune(reps=2)
+    assert best["mode"] in ("staged", "batched") and best["candidates"] >= 2
+    assert 0 < best["ms"] <= best["ms_worst"]
+    job.run("auto")
+    assert job.results() == want
+    job.close()
+    # the choice is cached for the shape bucket: rsl_batch in auto mode uses it
+    assert ctx.batch(probs, mode="auto") == want
+    path = tmp_path / "tune.txt"
+    ctx.tune_save(str(path))
+    lines = path.read_text().split("\n")
+    assert len([l for l in lines if l.strip()]) == 1
+    key, mode, target, gm, ms = lines[0].split()
+    assert int(mode) in (1, 2) and int(target) >= 64 and int(gm) >= 1
+    import paper_1010_1386_amd as rsl
+    c2 = rsl.Context(device=0, workspace_bytes=256 << 20)
+    c2.tune_load(str(path))
+    j2 = c2.job(probs)
+    j2.run("auto")
+    assert j2.results() == want
+    j2.close()
+    bad = tmp_path / "bad.txt"
+    bad.write_text(key + " 7 4096 1 1.0\n")
+    with pytest.raises(rsl.RSLError):
+        c2.tune_load(str(bad))
+    c2.close()
+
+
+def test_queue_wait_bound_ends_the_launch(monkeypatch):
+    """A zero wait bound (set from the host) makes the first idle wave give up: the
+    persistent launch ends, the run reports a device error, and the context stays
+    usable for the other modes."""
+    import paper_1010_1386_amd as rsl
+    monkeypatch.setenv("RSL_QUEUE_WAIT_MS", "0")
+    c = rsl.Context(device=0, workspace_bytes=256 << 20)
+    monkeypatch.delenv("RSL_QUEUE_WAIT_MS")
+    probs = mixed_batch(10, 12)
+    with pytest.raises(rsl.RSLError) as ei:
+        c.batch(probs, mode="batched")
+    assert ei.value.code == rsl.RSL_EDEVICE
+    assert c.batch(probs, mode="staged") == [oracle.res(f, g, v) for f, g, v in probs]
+    c.close()
