@@ -113,7 +113,10 @@ typedef struct {
   int32_t point_origin;/* evaluate at origin, origin+1, ... instead of 0, 1, ... */
   int32_t extra_points;/* evaluate at this many points beyond D + s */
   int32_t prime_limit; /* test hook: treat the prime table as having only this many entries */
-  int32_t reserved[2];
+  int32_t eval_lanes;  /* lanes per (prime, point) pair in evaluation: 1, 2 or 4 (an upper
+                          bound: problems of low degree use fewer); 0 = chosen from the job
+                          size or by the autotuner */
+  int32_t reserved;
 } rsl_opts;
 
 /* Counters of the last call on a context (or of a server). */
@@ -212,13 +215,14 @@ typedef struct {
   int32_t mode;          /* RSL_STAGED or RSL_BATCHED */
   int32_t chunk_target;  /* interpolation blocks kept in flight */
   int32_t grid_mult;     /* persistent workgroups per resident slot */
+  int32_t evk;           /* lanes per (prime, point) pair in evaluation: 1, 2 or 4 */
   int32_t candidates;    /* candidates timed */
   double ms;             /* device time of one run of the chosen schedule */
   double ms_worst;       /* device time of the slowest candidate */
 } rsl_tune_result;
 
 int rsl_job_tune(rsl_ctx *ctx, rsl_job *job, int reps, rsl_tune_result *best);
-/* Save / load the tuning cache as text lines "key mode chunk_target grid_mult ms". */
+/* Save / load the tuning cache as text lines "key mode chunk_target grid_mult evk ms". */
 int rsl_tune_save(rsl_ctx *ctx, const char *path);
 int rsl_tune_load(rsl_ctx *ctx, const char *path);
 

@@ -60,7 +60,7 @@ class rsl_info(ctypes.Structure):
 class rsl_opts(ctypes.Structure):
     _fields_ = [("points", ctypes.c_int32), ("prime_start", ctypes.c_int32), ("extra_primes", ctypes.c_int32),
                 ("point_origin", ctypes.c_int32), ("extra_points", ctypes.c_int32),
-                ("prime_limit", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("prime_limit", ctypes.c_int32), ("eval_lanes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class rsl_counters(ctypes.Structure):
@@ -85,7 +85,8 @@ class rsl_job_info(ctypes.Structure):
 
 class rsl_tune_result(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("chunk_target", ctypes.c_int32), ("grid_mult", ctypes.c_int32),
-                ("candidates", ctypes.c_int32), ("ms", ctypes.c_double), ("ms_worst", ctypes.c_double)]
+                ("evk", ctypes.c_int32), ("candidates", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("ms_worst", ctypes.c_double)]
 
 
 STAGES = ("reduce", "eval_ures", "interp_conv", "interp_stir", "interp_newton", "crt")
@@ -218,8 +219,12 @@ def query(f, g, var="y"):
     return {name: getattr(info, name) for name, _ in rsl_info._fields_}
 
 
-def _opts(points="replace", prime_start=0, extra_primes=0, point_origin=0, extra_points=0, prime_limit=0):
+def _opts(points="replace", prime_start=0, extra_primes=0, point_origin=0, extra_points=0, prime_limit=0,
+          eval_lanes=0):
+    if eval_lanes not in (0, 1, 2, 4):
+        raise ValueError("eval_lanes must be 0, 1, 2 or 4")
     o = rsl_opts()
+    o.eval_lanes = eval_lanes
     o.points = RSL_POINTS_FORMAL if points in ("formal", RSL_POINTS_FORMAL) else RSL_POINTS_REPLACE
     o.prime_start, o.extra_primes = prime_start, extra_primes
     o.point_origin, o.extra_points, o.prime_limit = point_origin, extra_points, prime_limit
@@ -408,7 +413,7 @@ class Job:
         self.ctx._check(rc, "rsl_job_tune")
         names = {RSL_STAGED: "staged", RSL_BATCHED: "batched"}
         return {"mode": names.get(r.mode, r.mode), "chunk_target": r.chunk_target, "grid_mult": r.grid_mult,
-                "candidates": r.candidates, "ms": r.ms, "ms_worst": r.ms_worst}
+                "lanes_per_pair": r.evk, "candidates": r.candidates, "ms": r.ms, "ms_worst": r.ms_worst}
 
     def info(self):
         i = rsl_job_info()

@@ -20,6 +20,7 @@ struct TuneConfig {
   int mode = RSL_STAGED;      // RSL_STAGED or RSL_BATCHED
   int chunk_target = 4096;    // interpolation blocks to keep in flight (sets the k-/i-chunking)
   int grid_mult = 1;          // persistent launch: workgroups = grid_mult x resident capacity
+  int evk = 0;                // lanes per (prime, point) pair in evaluation; 0 = from the job size
 };
 struct TuneEntry {
   TuneConfig cfg;

@@ -78,6 +78,22 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     const Plan& P = J->plans[k];
     stir_base += static_cast<int64_t>(P.np) * blocks_of(P.D + 1, 256);
   }
+  // evaluation: with few (prime, point) pairs one lane per pair leaves most
+  // SIMDs with a single wave; split each pair over K lanes until about four
+  // waves per SIMD are in flight (problems of degree below 4K stay at one lane)
+  int64_t all_pairs = 0;
+  for (int k : J->live) all_pairs += static_cast<int64_t>(J->plans[k].np) * (J->plans[k].E + 1);
+  int evk = J->tune.evk;
+  if (opts && opts->eval_lanes > 0) evk = opts->eval_lanes;
+  if (evk != 0 && evk != 1 && evk != 2 && evk != 4) {
+    *err = "eval_lanes must be 0, 1, 2 or 4";
+    return RSL_EINVAL;
+  }
+  if (evk <= 0) {
+    constexpr int64_t kLanesInFlight = 256LL * 4 * 4 * 64;
+    evk = 1;
+    while (evk < 4 && all_pairs * evk < kLanesInFlight) evk *= 2;
+  }
   J->crt_ns = 1;
   for (int li = 0; li < nl; ++li) {
     const Plan& P = J->plans[J->live[li]];
@@ -104,6 +120,9 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     nch = std::max(1, std::min(nch, (P.D + 1 + 127) / 128));
     d.kchunk = (P.D + 1 + nch - 1) / nch;
     d.nchunk = (P.D + 1 + d.kchunk - 1) / d.kchunk;
+    d.evk = 1;
+    while (d.evk < evk && std::min(P.my, P.ny) >= 4 * d.evk * 2) d.evk *= 2;
+    d.evpb = 64 / d.evk;
     d.cchunk = d.kchunk;  // same split for the convolution's input range
     d.ncchunk = d.nchunk;
     J->crt_ns = std::max(J->crt_ns, (P.np + 63) / 64);
@@ -120,7 +139,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     for (int sl = 0; sl < P.np; ++sl)
       for (int b = 0; b < blocks_of(d.CS, 256); ++b) J->items[kStageReduce].push_back({li, sl, b, 0});
     for (int sl = 0; sl < P.np; ++sl)
-      for (int b = 0; b < blocks_of(P.E + 1, 64); ++b) J->items[kStageEval].push_back({li, sl, b, 0});
+      for (int b = 0; b < blocks_of(P.E + 1, d.evpb); ++b) J->items[kStageEval].push_back({li, sl, b, 0});
     for (int sl = 0; sl < P.np; ++sl)
       for (int b = 0; b < blocks_of(P.D + 1, 256); ++b)
         for (int ch = 0; ch < d.ncchunk; ++ch)
@@ -171,7 +190,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     for (int li = 0; li < nl; ++li) {
       const Plan& P = J->plans[J->live[li]];
       const DevProblem& d = J->dev[li];
-      const int64_t ne = blocks_of(P.E + 1, 64), nc = blocks_of(P.D + 1, 64);
+      const int64_t ne = blocks_of(P.E + 1, d.evpb), nc = blocks_of(P.D + 1, 64);
       const int64_t ns = nc * d.nchunk;
       cap += static_cast<int64_t>(P.np) * (1 + ne + std::max<int64_t>(nc * d.ncchunk + ns, 1));
       const int64_t ncrt = blocks_of(P.D + 1, kCrtPerTask);
@@ -232,7 +251,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   for (int li = 0; li < nl; ++li) {
     const DevProblem& d = J->dev[li];
     auto up = [&](int s, size_t words) { J->stage_lds[s] = std::max(J->stage_lds[s], words * 4); };
-    up(kStageEval, eval_lds_words(d));
+    up(kStageEval, d.evk > 1 ? eval_group_lds_words(d, d.evk) : eval_lds_words(d));
     up(kStageConv, static_cast<size_t>(std::min(d.cchunk, d.D + 1)) + std::min(d.D + 1, d.cchunk + 256));
     up(kStageStir, d.kchunk);
     if (J->lay[li].item_end[kStageNewton] > J->lay[li].item_begin[kStageNewton]) up(kStageNewton, newton_lds_words(d, 1024));
@@ -241,7 +260,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   J->persist_lds = 0;
   for (int li = 0; li < nl; ++li) {
     const DevProblem& d = J->dev[li];
-    size_t w = eval_lds_words(d);
+    size_t w = d.evk > 1 ? eval_group_lds_words(d, d.evk) : eval_lds_words(d);
     w = std::max<size_t>(w, static_cast<size_t>(std::min(d.cchunk, d.D + 1)) + std::min(d.D + 1, d.cchunk + 64));
     w = std::max<size_t>(w, d.kchunk);
     if (J->lay[li].item_end[kStageNewton] > J->lay[li].item_begin[kStageNewton])
@@ -330,7 +349,7 @@ void job_bind(Job* J, uint8_t* base) {
     for (int li = 0; li < nl; ++li) {
       const Plan& P = J->plans[J->live[li]];
       const DevProblem& d = J->dev[li];
-      const int ne = blocks_of(P.E + 1, 64), nc = blocks_of(P.D + 1, 64);
+      const int ne = blocks_of(P.E + 1, d.evpb), nc = blocks_of(P.D + 1, 64);
       cnt[li].slots_left = P.np;
       for (int sl = 0; sl < P.np; ++sl) {
         cnt[li].eval_left[sl] = ne;

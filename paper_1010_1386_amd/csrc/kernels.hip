@@ -32,7 +32,7 @@ __global__ __launch_bounds__(64) void k_eval_ures(const DevProblem* probs, const
   extern __shared__ uint4 lds4[];  // 16-byte aligned: the Horner loop reads uint4 rows
   uint32_t* lds = reinterpret_cast<uint32_t*>(lds4);
   const WorkItem w = items[blockIdx.x];
-  stage_eval_ures(probs[w.prob], T, w, lds);
+  stage_eval(probs[w.prob], T, w, lds);
 }
 
 __global__ __launch_bounds__(256) void k_interp_conv(const DevProblem* probs, const WorkItem* items, DevTables T) {

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(64) void k_persistent(const DevProblem* probs, Queu
       case kTaskReduce:
         for (int b = 0; b * 64 < P.CS; ++b) stage_reduce(P, T, WorkItem{prob, t.slot, b, 0});
         break;
-      case kTaskEval: stage_eval_ures(P, T, w, lds); break;
+      case kTaskEval: stage_eval(P, T, w, lds); break;
       case kTaskConv: stage_interp_conv(P, T, w, lds); break;
       case kTaskStir: stage_interp_stir(P, T, w, lds); break;
       case kTaskNewton: stage_interp_newton(P, T, w, lds); break;
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(64) void k_persistent(const DevProblem* probs, Queu
     } else if (tid == 0) {
       switch (type) {
         case kTaskReduce: {
-          const int nb = (P.E + 64) / 64;
+          const int nb = (P.E + P.evpb) / P.evpb;
           enqueue(Q, probs, nb, [&](int i) { return mk(kTaskEval, prob, t.slot, i, 0); });
           break;
         }

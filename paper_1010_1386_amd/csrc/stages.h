@@ -189,6 +189,146 @@ __device__ inline void stage_eval_ures(const DevProblem& P, const DevTables& T, 
   if (lane == 0 && nbad) atomicAdd(P.status + 1 + P.np, static_cast<int>(__popcll(nbad)));
 }
 
+// LDS words of a grouped eval block (K lanes per pair, 64/K pairs).
+__host__ __device__ inline int eval_group_lds_words(const DevProblem& P, int K) {
+  const int nm1 = (P.my > P.ny ? P.my : P.ny) + 1;
+  return P.CS + 2 * nm1 * (64 / K);
+}
+
+// Lanes of one wave meet here: LDS operations of a wave execute in program
+// order, so the fences only keep the compiler from moving memory operations
+// across this point.
+struct WaveSync {
+  __device__ void operator()() const {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+};
+
+// One wave, K lanes per (prime, point) pair: 64/K consecutive points of one
+// prime.  Lane l of a pair evaluates rows j = 4q + l + K r (r < 4/K) of every
+// row group q, so all lanes walk the same group degrees; the columns hold pair
+// q at LDS word q + j (64/K), which makes the K lanes' accesses to one j-slice
+// conflict-free.  The K lanes then run ures_group on the shared columns.
+template <int K>
+__device__ inline void stage_eval_ures_group(const DevProblem& P, const DevTables& T, const WorkItem& w,
+                                             uint32_t* lds) {
+  constexpr int PB = 64 / K;            // pairs per block
+  constexpr int R = kRowGroup / K;      // rows of a group per lane
+  constexpr int NG = (R == 1) ? 2 : 1;  // groups per Horner pass (four chains per lane)
+  const int lane = threadIdx.x;
+  const int l = lane / PB, q = lane % PB;
+  const PrimeConst pc = T.pc[P.pidx[w.slot]];
+  const uint32_t p = pc.p, pinv = pc.pinv;
+  uint32_t* tile = lds;
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(P.resid + static_cast<size_t>(w.slot) * P.CS);
+    uint4* dst = reinterpret_cast<uint4*>(tile);
+    for (int t = lane; t < P.CS / 4; t += 64) dst[t] = src[t];
+  }
+  __syncthreads();
+
+  const int nm1 = (P.my > P.ny ? P.my : P.ny) + 1;
+  uint32_t* cols = lds + P.CS;
+  Column<PB> A{cols + q};
+  Column<PB> B{cols + nm1 * PB + q};
+  const int pt = w.blk * PB + q;
+  const uint32_t x = static_cast<uint32_t>(P.origin + (pt < P.E ? pt : P.E));
+  const uint32_t xt = mmul(x, pc.r2, p, pinv);
+
+  const int gf = P.myp / kRowGroup, gg = P.nyp / kRowGroup;
+  const int ng = gf > gg ? gf : gg;
+  for (int q0 = 0; q0 < ng; q0 += NG) {
+    // chains: [group][f or g][row]; a missing group reads column l of row 0
+    // (in the tile) and is never stored
+    int deg[NG][2];
+    const uint32_t* base[NG][2];
+    int stride[2] = {P.myp, P.nyp};
+    int top = -1;
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+      const int qq = q0 + gi;
+      deg[gi][0] = __builtin_amdgcn_readfirstlane((qq < gf) ? P.gdeg[qq] : -1);
+      deg[gi][1] = __builtin_amdgcn_readfirstlane((qq < gg) ? P.gdeg[gf + qq] : -1);
+      base[gi][0] = tile + ((qq < gf) ? kRowGroup * qq : 0) + l;
+      base[gi][1] = tile + P.goff + ((qq < gg) ? kRowGroup * qq : 0) + l;
+      top = deg[gi][0] > top ? deg[gi][0] : top;
+      top = deg[gi][1] > top ? deg[gi][1] : top;
+    }
+    uint32_t acc[NG][2][R];
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi)
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[gi][s][r] = 0u;
+    for (int i = top; i >= 0; --i) {
+      uint32_t c[NG][2][R];
+#pragma unroll
+      for (int gi = 0; gi < NG; ++gi)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const bool on = i <= deg[gi][s];  // uniform; rows above a chain's degree add zeros
+          const uint32_t* rowp = base[gi][s] + (on ? i : 0) * stride[s];
+#pragma unroll
+          for (int r = 0; r < R; ++r) c[gi][s][r] = on ? rowp[K * r] : 0u;
+        }
+      uint64_t t[NG][2][R];
+#pragma unroll
+      for (int gi = 0; gi < NG; ++gi)
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int r = 0; r < R; ++r) t[gi][s][r] = static_cast<uint64_t>(acc[gi][s][r]) * xt + c[gi][s][r];
+      uint32_t mm[NG][2][R];
+#pragma unroll
+      for (int gi = 0; gi < NG; ++gi)
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int r = 0; r < R; ++r) mm[gi][s][r] = static_cast<uint32_t>(t[gi][s][r]) * pinv;
+#pragma unroll
+      for (int gi = 0; gi < NG; ++gi)
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            acc[gi][s][r] = static_cast<uint32_t>((t[gi][s][r] + static_cast<uint64_t>(mm[gi][s][r]) * p) >> 32);
+    }
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int j = kRowGroup * (q0 + gi) + l + K * r;
+        const uint32_t va = acc[gi][0][r], vb = acc[gi][1][r];
+        if (q0 + gi < gf && j <= P.my) A[j] = umin32(va, va - p);  // Horner keeps values below 2p
+        if (q0 + gi < gg && j <= P.ny) B[j] = umin32(vb, vb - p);
+      }
+  }
+  WaveSync sync;
+  sync();
+  bool bad = false;
+  const uint32_t r = ures_group<K>(A, B, P.my, P.ny, pc, l, &bad, sync);
+  const bool live = pt <= P.E && l == 0;
+  if (live) {
+    const size_t o = static_cast<size_t>(w.slot) * (P.E + 1) + pt;
+    P.zval[o] = redc(r, p, pinv);
+    P.zbad[o] = bad ? 1 : 0;
+  }
+  const uint64_t nbad = __ballot(live && bad);
+  if (lane == 0 && nbad) atomicAdd(P.status + 1 + P.np, static_cast<int>(__popcll(nbad)));
+}
+
+// Dispatch on the problem's lanes per pair (block-uniform).
+__device__ inline void stage_eval(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
+  switch (P.evk) {
+    case 2: stage_eval_ures_group<2>(P, T, w, lds); break;
+    case 4: stage_eval_ures_group<4>(P, T, w, lds); break;
+    default: stage_eval_ures(P, T, w, lds); break;
+  }
+}
+
 // ------------------------------------------------------------ interpolation
 
 // The consecutive fast path applies when the D+1 points used are 0..D: always

@@ -229,20 +229,25 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   if (ctx->poisoned) return RSL_EDEVICE;
   if (j->J.live.empty()) {
-    if (best) *best = rsl_tune_result{RSL_STAGED, j->J.tune.chunk_target, 1, 0, 0.0, 0.0};
+    if (best) *best = rsl_tune_result{RSL_STAGED, j->J.tune.chunk_target, 1, 1, 0, 0.0, 0.0};
     return RSL_OK;
   }
+  // coordinate search: schedule x lanes per pair at the default chunking, then
+  // the chunking (and the persistent grid) around the best of those
   std::vector<TuneConfig> cands;
-  for (int target : {1024, 4096, 16384}) {
-    cands.push_back(TuneConfig{RSL_STAGED, target, 1});
-    cands.push_back(TuneConfig{RSL_BATCHED, target, 1});
-  }
-  cands.push_back(TuneConfig{RSL_BATCHED, 4096, 2});
+  for (int evk : {1, 2, 4})
+    for (int mode : {RSL_STAGED, RSL_BATCHED}) cands.push_back(TuneConfig{mode, 4096, 1, evk});
+  const size_t phase1 = cands.size();
   std::vector<uint8_t> ref;
   TuneConfig win = cands[0];
   double win_ms = 1e300, worst_ms = 0.0;
   int rc;
-  for (const TuneConfig& tc : cands) {
+  for (size_t ci = 0; ci < cands.size(); ++ci) {
+    if (ci == phase1) {
+      for (int target : {1024, 16384}) cands.push_back(TuneConfig{win.mode, target, 1, win.evk});
+      if (win.mode == RSL_BATCHED) cands.push_back(TuneConfig{RSL_BATCHED, 4096, 2, win.evk});
+    }
+    const TuneConfig tc = cands[ci];
     if ((rc = materialize(ctx, j, tc))) return rc;
     // warm-up run (also the correctness check), then `reps` timed runs
     if ((rc = run_job(ctx, j, tc.mode)) || (rc = job_download(ctx, &j->J, j->hdown, ctx->stream)) ||
@@ -273,8 +278,8 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
   }
   if ((rc = materialize(ctx, j, win))) return rc;
   ctx->tune_cache[tune_key(j->J)] = TuneEntry{win, win_ms};
-  if (best) *best = rsl_tune_result{win.mode, win.chunk_target, win.grid_mult, static_cast<int32_t>(cands.size()),
-                                    win_ms, worst_ms};
+  if (best) *best = rsl_tune_result{win.mode, win.chunk_target, win.grid_mult, win.evk,
+                                    static_cast<int32_t>(cands.size()), win_ms, worst_ms};
   return RSL_OK;
 }
 
@@ -285,7 +290,7 @@ int rsl_tune_save(rsl_ctx* ctx, const char* path) {
   if (!os) return fail(ctx, RSL_EINVAL, std::string("cannot write ") + path);
   for (const auto& kv : ctx->tune_cache)
     os << kv.first << " " << kv.second.cfg.mode << " " << kv.second.cfg.chunk_target << " "
-       << kv.second.cfg.grid_mult << " " << kv.second.ms << "\n";
+       << kv.second.cfg.grid_mult << " " << kv.second.cfg.evk << " " << kv.second.ms << "\n";
   return RSL_OK;
 }
 
@@ -296,9 +301,9 @@ int rsl_tune_load(rsl_ctx* ctx, const char* path) {
   if (!is) return fail(ctx, RSL_EINVAL, std::string("cannot read ") + path);
   std::string key;
   TuneEntry e;
-  while (is >> key >> e.cfg.mode >> e.cfg.chunk_target >> e.cfg.grid_mult >> e.ms) {
+  while (is >> key >> e.cfg.mode >> e.cfg.chunk_target >> e.cfg.grid_mult >> e.cfg.evk >> e.ms) {
     if ((e.cfg.mode != RSL_STAGED && e.cfg.mode != RSL_BATCHED) || e.cfg.chunk_target < 64 || e.cfg.grid_mult < 1 ||
-        e.cfg.grid_mult > 8)
+        e.cfg.grid_mult > 8 || (e.cfg.evk != 1 && e.cfg.evk != 2 && e.cfg.evk != 4))
       return fail(ctx, RSL_EINVAL, "malformed tuning cache line for " + key);
     ctx->tune_cache[key] = e;
   }

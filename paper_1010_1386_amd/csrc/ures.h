@@ -90,6 +90,42 @@ RSL_HD void mmad3x4(uint32_t al, uint32_t be, uint32_t ga, uint32_t a0, uint32_t
   *r3 = umin32(u3, u3 - p);
 }
 
+// Four fused updates r_i = (al a_i + be q_i + ga b_i) / R mod p with independent q_i.
+RSL_HD void mmad3x4s(uint32_t al, uint32_t be, uint32_t ga, uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3,
+                     uint32_t q0, uint32_t q1, uint32_t q2, uint32_t q3, uint32_t b0, uint32_t b1, uint32_t b2,
+                     uint32_t b3, uint32_t p, uint32_t pinv, uint32_t* r0, uint32_t* r1, uint32_t* r2, uint32_t* r3) {
+  uint64_t t0 = static_cast<uint64_t>(al) * a0, t1 = static_cast<uint64_t>(al) * a1;
+  uint64_t t2 = static_cast<uint64_t>(al) * a2, t3 = static_cast<uint64_t>(al) * a3;
+  t0 += static_cast<uint64_t>(be) * q0;
+  t1 += static_cast<uint64_t>(be) * q1;
+  t2 += static_cast<uint64_t>(be) * q2;
+  t3 += static_cast<uint64_t>(be) * q3;
+  t0 += static_cast<uint64_t>(ga) * b0;
+  t1 += static_cast<uint64_t>(ga) * b1;
+  t2 += static_cast<uint64_t>(ga) * b2;
+  t3 += static_cast<uint64_t>(ga) * b3;
+  uint32_t h0 = static_cast<uint32_t>(t0 >> 32), h1 = static_cast<uint32_t>(t1 >> 32);
+  uint32_t h2 = static_cast<uint32_t>(t2 >> 32), h3 = static_cast<uint32_t>(t3 >> 32);
+  h0 = umin32(h0, h0 - p);
+  h1 = umin32(h1, h1 - p);
+  h2 = umin32(h2, h2 - p);
+  h3 = umin32(h3, h3 - p);
+  t0 = (static_cast<uint64_t>(h0) << 32) | static_cast<uint32_t>(t0);
+  t1 = (static_cast<uint64_t>(h1) << 32) | static_cast<uint32_t>(t1);
+  t2 = (static_cast<uint64_t>(h2) << 32) | static_cast<uint32_t>(t2);
+  t3 = (static_cast<uint64_t>(h3) << 32) | static_cast<uint32_t>(t3);
+  const uint32_t m0 = static_cast<uint32_t>(t0) * pinv, m1 = static_cast<uint32_t>(t1) * pinv;
+  const uint32_t m2 = static_cast<uint32_t>(t2) * pinv, m3 = static_cast<uint32_t>(t3) * pinv;
+  const uint32_t u0 = static_cast<uint32_t>((t0 + static_cast<uint64_t>(m0) * p) >> 32);
+  const uint32_t u1 = static_cast<uint32_t>((t1 + static_cast<uint64_t>(m1) * p) >> 32);
+  const uint32_t u2 = static_cast<uint32_t>((t2 + static_cast<uint64_t>(m2) * p) >> 32);
+  const uint32_t u3 = static_cast<uint32_t>((t3 + static_cast<uint64_t>(m3) * p) >> 32);
+  *r0 = umin32(u0, u0 - p);
+  *r1 = umin32(u1, u1 - p);
+  *r2 = umin32(u2, u2 - p);
+  *r3 = umin32(u3, u3 - p);
+}
+
 // Resultant with formal degrees (m, n) of the polynomials in columns A, B
 // (Montgomery form; both columns are overwritten).  Returns the result in
 // Montgomery form.  *bad is set when lc_y f(x_i) or lc_y g(x_i) vanishes.
@@ -222,6 +258,131 @@ RSL_HD uint32_t ures_formal(Col A, Col B, int m, int n, const PrimeConst& pc, bo
       cBb1 = last2;  // new B[new b - 1] = R~[b-2]
     }
     Col t = A; A = B; B = t;  // (A, B) <- (B, R~)
+    a = b;
+    b = c;
+  }
+  uint32_t r = mmul(num, minv(den, one, p, pinv), p, pinv);
+  return neg ? mneg(r, p) : r;
+}
+
+}  // namespace rsl
+
+namespace rsl {
+
+// The same resultant computed by a group of K lanes that share the columns A
+// and B (K > 1).  Every lane keeps the same scalar state; the elimination
+// passes over the coefficient index j are split cyclically (lane l takes
+// j = l, l+K, ...).  Within a pass a lane writes only its own A[j] and reads
+// A[j], B[j], B[j-1] and scalars that the pass does not write, so lanes only
+// need to agree between passes: sync() is called after every pass (a wave's
+// lanes run in lockstep, so on the device sync() only has to stop the compiler
+// from moving memory operations across it).  The caller syncs after writing
+// the columns.
+template <int K, class Col, class Sync>
+RSL_HD uint32_t ures_group(Col A, Col B, int m, int n, const PrimeConst& pc, int l, bool* bad, Sync sync) {
+  const uint32_t p = pc.p, pinv = pc.pinv, one = pc.r1;
+  *bad = (A[m] == 0u) || (B[n] == 0u);
+  if (n == 0) return mpow(B[0], static_cast<uint32_t>(m), one, p, pinv);
+  if (m == 0) return mpow(A[0], static_cast<uint32_t>(n), one, p, pinv);
+  int a = m;
+  while (a >= 0 && A[a] == 0u) --a;
+  int b = n;
+  while (b >= 0 && B[b] == 0u) --b;
+  if (a < 0 || b < 0 || (a < m && b < n)) return 0u;
+  uint32_t num = one, den = one, U = one;
+  uint32_t neg = 0;
+  if (a < m) {
+    num = mpow(B[b], static_cast<uint32_t>(m - a), one, p, pinv);
+    neg ^= static_cast<uint32_t>(n * (m - a)) & 1u;
+  }
+  if (b < n) num = mpow(A[a], static_cast<uint32_t>(n - b), one, p, pinv);
+
+  // usual case: lc(A') = L and A'[b'] = B[b-1] are known from the previous
+  // division (new A = old B); L' and B'[b'-1] are read after the pass
+  bool carried = false;
+  uint32_t clcA = 0, cAb = 0;
+  for (;;) {
+    if (b == 0) {
+      num = mmul(num, mpow(B[0], static_cast<uint32_t>(a), one, p, pinv), p, pinv);
+      break;
+    }
+    if (a == 0) {
+      num = mmul(num, mpow(A[0], static_cast<uint32_t>(b), one, p, pinv), p, pinv);
+      break;
+    }
+    if (a < b) {
+      Col t = A; A = B; B = t;
+      int ti = a; a = b; b = ti;
+      neg ^= static_cast<uint32_t>(a * b) & 1u;
+      carried = false;
+      continue;
+    }
+    const uint32_t L = B[b];
+    const int k = a - b + 1;
+    uint32_t y;
+    int c;
+    uint32_t Bb1 = 0;
+    if (k == 2) {
+      const uint32_t lcA = carried ? clcA : A[a];
+      const uint32_t Ab = carried ? cAb : A[b];
+      Bb1 = B[b - 1];
+      const uint32_t lcAt = mmulsub(L, Ab, lcA, Bb1, p, pinv);
+      const uint32_t alpha = mmul(L, L, p, pinv);
+      const uint32_t beta = mneg(mmul(L, lcA, p, pinv), p);
+      const uint32_t gamma = mneg(lcAt, p);
+      int j = l;
+      for (; j + 3 * K < b; j += 4 * K) {
+        const uint32_t bp = (j > 0) ? B[j - 1] : 0u;
+        uint32_t r0, r1, r2, r3;
+        // q_i = B[j_i - 1], b_i = B[j_i] for j_i = j + iK
+        const uint32_t a0 = A[j], a1 = A[j + K], a2 = A[j + 2 * K], a3 = A[j + 3 * K];
+        const uint32_t b0 = B[j], b1 = B[j + K], b2 = B[j + 2 * K], b3 = B[j + 3 * K];
+        const uint32_t q1 = B[j + K - 1], q2 = B[j + 2 * K - 1], q3 = B[j + 3 * K - 1];
+        mmad3x4s(alpha, beta, gamma, a0, a1, a2, a3, bp, q1, q2, q3, b0, b1, b2, b3, p, pinv, &r0, &r1, &r2, &r3);
+        A[j] = r0;
+        A[j + K] = r1;
+        A[j + 2 * K] = r2;
+        A[j + 3 * K] = r3;
+      }
+      for (; j < b; j += K) {
+        const uint32_t bp = (j > 0) ? B[j - 1] : 0u;
+        A[j] = mmad3(alpha, A[j], beta, bp, gamma, B[j], p, pinv);
+      }
+      sync();
+      y = alpha;
+      const uint32_t last1 = A[b - 1];
+      if (last1 != 0u) {
+        c = b - 1;
+      } else {
+        c = b - 2;
+        while (c >= 0 && A[c] == 0u) --c;
+      }
+    } else {
+      for (int d = a; d >= b; --d) {
+        const uint32_t lc = A[d];
+        const int sh = d - b;
+        for (int j = l; j < d; j += K) {
+          const uint32_t bj = (j >= sh) ? B[j - sh] : 0u;
+          A[j] = mmulsub(L, A[j], lc, bj, p, pinv);
+        }
+        sync();
+      }
+      y = mpow(L, static_cast<uint32_t>(k), one, p, pinv);
+      c = b - 1;
+      while (c >= 0 && A[c] == 0u) --c;
+      Bb1 = B[b - 1];
+    }
+    if (c < 0) return 0u;
+    neg ^= static_cast<uint32_t>(a * b) & 1u;
+    const int delta = b - c;
+    const int enum_ = k - 1 + delta;
+    num = mmul(num, (enum_ == k) ? y : mpow(L, static_cast<uint32_t>(enum_), one, p, pinv), p, pinv);
+    U = mmul(U, y, p, pinv);
+    den = mmul(den, (delta == 1) ? U : mpow(U, static_cast<uint32_t>(delta), one, p, pinv), p, pinv);
+    carried = (delta == 1);
+    clcA = L;
+    cAb = Bb1;
+    Col t = A; A = B; B = t;
     a = b;
     b = c;
   }

@@ -1,13 +1,82 @@
 // Host build of the kernels' per-lane arithmetic, for CPU tests of its logic
 // against the oracle (test infrastructure only; not part of the library).
+#include <condition_variable>
 #include <cstdint>
+#include <mutex>
+#include <thread>
 #include <vector>
 #include "../../paper_1010_1386_amd/csrc/modarith.h"
 #include "../../paper_1010_1386_amd/csrc/ures.h"
 
 using namespace rsl;
 
+namespace {
+
+// Reusable barrier for the K lane threads of the group simulation.
+struct Barrier {
+  std::mutex mu;
+  std::condition_variable cv;
+  int n, waiting = 0, gen = 0;
+  explicit Barrier(int k) : n(k) {}
+  void wait() {
+    std::unique_lock<std::mutex> lk(mu);
+    const int g = gen;
+    if (++waiting == n) {
+      waiting = 0;
+      ++gen;
+      cv.notify_all();
+    } else {
+      cv.wait(lk, [&] { return gen != g; });
+    }
+  }
+};
+
+template <int K>
+uint32_t group_run(const PrimeConst& pc, int m, int n, std::vector<uint32_t>& a, std::vector<uint32_t>& b,
+                   bool* bad, int* agree) {
+  Barrier bar(K);
+  uint32_t r[K];
+  bool bd[K];
+  std::vector<std::thread> th;
+  for (int l = 0; l < K; ++l)
+    th.emplace_back([&, l] {
+      r[l] = ures_group<K>(Column<1>{a.data()}, Column<1>{b.data()}, m, n, pc, l, &bd[l], [&] { bar.wait(); });
+    });
+  for (auto& t : th) t.join();
+  *agree = 1;
+  for (int l = 1; l < K; ++l)
+    if (r[l] != r[0] || bd[l] != bd[0]) *agree = 0;
+  *bad = bd[0];
+  return r[0];
+}
+
+}  // namespace
+
 extern "C" {
+
+// The K-lane group form of the same resultant, run by K host threads that
+// meet at a barrier wherever the kernel's lanes synchronise.  *agree is 0 if
+// the lanes finished with different results.
+int hs_ures_group(int K, uint32_t p, int m, int n, const uint32_t* A, const uint32_t* B, uint32_t* out, int* bad,
+                  int* agree) {
+  PrimeConst pc = make_prime_const(p);
+  int nm = (m > n ? m : n) + 1;
+  std::vector<uint32_t> a(nm, 0), b(nm, 0);
+  for (int j = 0; j <= m; ++j) a[j] = mmul(A[j] % p, pc.r2, p, pc.pinv);
+  for (int j = 0; j <= n; ++j) b[j] = mmul(B[j] % p, pc.r2, p, pc.pinv);
+  bool bd = false;
+  uint32_t r;
+  switch (K) {
+    case 2: r = group_run<2>(pc, m, n, a, b, &bd, agree); break;
+    case 4: r = group_run<4>(pc, m, n, a, b, &bd, agree); break;
+    case 8: r = group_run<8>(pc, m, n, a, b, &bd, agree); break;
+    default: return -1;
+  }
+  *out = redc(r, p, pc.pinv);
+  *bad = bd;
+  return 0;
+}
+
 
 // Resultant over Z_p with formal degrees (m, n) of A (m+1 coefficients) and B
 // (n+1 coefficients), given and returned in normal form.

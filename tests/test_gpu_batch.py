@@ -93,8 +93,8 @@ def test_autotuner_keeps_bits_and_caches_choice(ctx, tmp_path):
     ctx.tune_save(str(path))
     lines = path.read_text().split("\n")
     assert len([l for l in lines if l.strip()]) == 1
-    key, mode, target, gm, ms = lines[0].split()
-    assert int(mode) in (1, 2) and int(target) >= 64 and int(gm) >= 1
+    key, mode, target, gm, evk, ms = lines[0].split()
+    assert int(mode) in (1, 2) and int(target) >= 64 and int(gm) >= 1 and int(evk) in (1, 2, 4)
     import paper_1010_1386_amd as rsl
     c2 = rsl.Context(device=0, workspace_bytes=256 << 20)
     c2.tune_load(str(path))
@@ -103,7 +103,7 @@ def test_autotuner_keeps_bits_and_caches_choice(ctx, tmp_path):
     assert j2.results() == want
     j2.close()
     bad = tmp_path / "bad.txt"
-    bad.write_text(key + " 7 4096 1 1.0\n")
+    bad.write_text(key + " 7 4096 1 1 1.0\n")
     with pytest.raises(rsl.RSLError):
         c2.tune_load(str(bad))
     c2.close()
@@ -123,3 +123,38 @@ def test_queue_wait_bound_ends_the_launch(monkeypatch):
     assert ei.value.code == rsl.RSL_EDEVICE
     assert c.batch(probs, mode="staged") == [oracle.res(f, g, v) for f, g, v in probs]
     c.close()
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+def test_eval_lanes_per_pair(ctx, lanes):
+    """Evaluation with 1, 2 or 4 lanes per (prime, point) pair gives the same bits in
+    every schedule: oracle on the small mixed problems, agreement across lane counts
+    and modulo-q checks on problems of degree 16..30 (where 4 lanes apply)."""
+    small = mixed_batch(15, 20)
+    rng = rng_for(712, 0)
+    big = [(dense_total(rng, d, b), dense_total(rng, d - 1, b), "yx"[i % 2])
+           for i, (d, b) in enumerate([(16, 12), (22, 30), (30, 8)])]
+    # a bad point for every prime at degree 20: leading y-coefficient x (x - 5)
+    F = dense_total(rng, 20, 10)
+    F[20] = [0, -5, 1]
+    big.append((F, dense_total(rng, 18, 10), "y"))
+    probs = small + big
+    job = ctx.job(probs, eval_lanes=lanes)
+    got = {}
+    for mode in ("staged", "batched", "plain"):
+        job.run(mode)
+        got[mode] = job.results()
+    job.close()
+    assert got["staged"] == got["batched"] == got["plain"]
+    res = got["staged"]
+    assert res[:len(small)] == [oracle.res(f, g, v) for f, g, v in small]
+    ref = ctx.job(probs, eval_lanes=1)
+    ref.run("staged")
+    assert ref.results() == res
+    ref.close()
+    rnd = __import__("random").Random(lanes)
+    qs = oracle.next_check_primes(2)
+    for (f, g, v), R in zip(big, res[len(small):]):
+        for q in qs:
+            t = rnd.randrange(q)
+            assert oracle.peval(R, t) % q == oracle.res_at_point_mod(f, g, t, q, v)

@@ -37,17 +37,28 @@ def hs():
                             ctypes.POINTER(ctypes.c_int)]
     lib.hs_eval.argtypes = [ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p,
                             ctypes.POINTER(ctypes.c_int), ctypes.c_uint32, u32p]
+    lib.hs_ures_group.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p, u32p, u32p,
+                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     return lib
 
 
-def ures(hs, p, A, B):
+def ures(hs, p, A, B, K=1):
+    """The lane code: one lane (K = 1) or a group of K lanes on K host threads."""
     m, n = len(A) - 1, len(B) - 1
     a = (ctypes.c_uint32 * len(A))(*A)
     b = (ctypes.c_uint32 * len(B))(*B)
     out = ctypes.c_uint32()
     bad = ctypes.c_int()
-    hs.hs_ures(p, m, n, a, b, ctypes.byref(out), ctypes.byref(bad))
+    if K == 1:
+        hs.hs_ures(p, m, n, a, b, ctypes.byref(out), ctypes.byref(bad))
+    else:
+        agree = ctypes.c_int()
+        assert hs.hs_ures_group(K, p, m, n, a, b, ctypes.byref(out), ctypes.byref(bad), ctypes.byref(agree)) == 0
+        assert agree.value == 1, "lanes of the group disagree"
     return out.value, bool(bad.value)
+
+
+KS = [1, 2, 4, 8]
 
 
 def sylvester_det_mod(A, B, p):
@@ -74,19 +85,34 @@ def polymul_mod(a, b, p):
     return out
 
 
+@pytest.mark.parametrize("K", KS)
 @pytest.mark.parametrize("seed", range(30))
-def test_random_generic(hs, seed):
+def test_random_generic(hs, seed, K):
     rng = rng_for(950, seed)
     p = PRIMES[seed % len(PRIMES)]
     m, n = int(rng.integers(0, 12)), int(rng.integers(0, 12))
     A = [int(v) for v in rng.integers(0, p, m + 1)]
     B = [int(v) for v in rng.integers(0, p, n + 1)]
-    got, _ = ures(hs, p, A, B)
+    got, _ = ures(hs, p, A, B, K)
     assert got == sylvester_det_mod(A, B, p)
 
 
+@pytest.mark.parametrize("K", KS)
+@pytest.mark.parametrize("seed", range(6))
+def test_random_large_degree(hs, seed, K):
+    """Degrees 13..40: every lane of a group runs several four-way fused updates."""
+    rng = rng_for(953, seed)
+    p = PRIMES[seed % len(PRIMES)]
+    m, n = int(rng.integers(13, 41)), int(rng.integers(13, 41))
+    A = [int(v) for v in rng.integers(0, p, m + 1)]
+    B = [int(v) for v in rng.integers(0, p, n + 1)]
+    got, _ = ures(hs, p, A, B, K)
+    assert got == sylvester_det_mod(A, B, p)
+
+
+@pytest.mark.parametrize("K", KS)
 @pytest.mark.parametrize("seed", range(60))
-def test_degenerate(hs, seed):
+def test_degenerate(hs, seed, K):
     """Small primes-like structure: tiny coefficient alphabet forces zero leading
     coefficients, degree drops by more than one and common factors."""
     rng = rng_for(951, seed)
@@ -99,12 +125,13 @@ def test_degenerate(hs, seed):
         c = [p - 3, 1]
         A = polymul_mod(c, A[:m], p)
         B = polymul_mod(c, B[:n], p)
-    got, bad = ures(hs, p, A, B)
+    got, bad = ures(hs, p, A, B, K)
     assert got == sylvester_det_mod(A, B, p), (p, A, B)
     assert bad == (A[-1] == 0 or B[-1] == 0)
 
 
-def test_remainder_degree_drops(hs):
+@pytest.mark.parametrize("K", KS)
+def test_remainder_degree_drops(hs, K):
     """Remainder sequences whose degree falls by more than one at a time."""
     p = PRIMES[0]
     cases = [
@@ -118,7 +145,7 @@ def test_remainder_degree_drops(hs):
         ([2, 3, 4], [6, 0, 0, 0]),             # deg B = 0 < formal 3
     ]
     for A, B in cases:
-        got, _ = ures(hs, p, A, B)
+        got, _ = ures(hs, p, A, B, K)
         assert got == sylvester_det_mod(A, B, p), (A, B)
 
 
