@@ -58,6 +58,12 @@ extern "C" {
 #define RSL_STAGED 2  /* one launch per stage, each over the work items of all problems     */
 #define RSL_AUTO 3    /* the schedule the autotuner chose for this shape (RSL_STAGED if none) */
 
+/* rsl_job_run only: OR into the mode to replay the run (status reset and every
+ * launch of the schedule) as a HIP graph captured on the context stream on first
+ * use and re-captured when the context's constant tables move.  Runs with
+ * profiling enabled are not captured. */
+#define RSL_GRAPH 0x100
+
 /* point policy (rsl_opts.points) */
 #define RSL_POINTS_REPLACE 0 /* bad points skipped: first D+1 good points of 0..D+s */
 #define RSL_POINTS_FORMAL 1  /* all points 0..D used (formal-degree values)          */

@@ -37,6 +37,7 @@ RSL_OK, RSL_EINVAL, RSL_ERANGE, RSL_ENOMEM, RSL_EPRIMES, RSL_EDEVICE, RSL_EAGAIN
     0, -1, -2, -3, -4, -5, -6, -7)
 RSL_Y, RSL_X = 0, 1
 RSL_PLAIN, RSL_BATCHED, RSL_STAGED, RSL_AUTO = 0, 1, 2, 3
+RSL_GRAPH = 0x100
 RSL_POINTS_REPLACE, RSL_POINTS_FORMAL = 0, 1
 
 
@@ -388,9 +389,11 @@ class Job:
         ctx._check(rc, "rsl_job_create")
         self.h = h
 
-    def run(self, mode="batched"):
+    def run(self, mode="batched", graph=False):
+        """One device run of the whole pipeline; graph=True replays it as a captured HIP graph."""
+        code = _modecode(mode) | (RSL_GRAPH if graph else 0)
         with self.ctx.lock:
-            rc = _lib.rsl_job_run(self.ctx.h, self.h, _modecode(mode))
+            rc = _lib.rsl_job_run(self.ctx.h, self.h, code)
         self.ctx._check(rc, "rsl_job_run")
 
     def results(self):

@@ -410,7 +410,8 @@ int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st, uint8_t* pinned) {
 
 int job_reset(rsl_ctx* ctx, Job* J, hipStream_t st) {
   if (J->status_bytes == 0) return RSL_OK;
-  return hip_check(ctx, hipMemsetAsync(J->base + J->status_off, 0, J->status_bytes, st), "status reset");
+  return hip_check(ctx, launch_copy_words(reinterpret_cast<uint32_t*>(J->base + J->status_off), nullptr,
+                                          J->status_bytes / 4, st), "status reset");
 }
 
 int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events) {
@@ -452,7 +453,9 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
       if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) cus = prop.multiProcessorCount;
       J->persist_grid = std::max(1, per_cu * cus * std::max(1, J->tune.grid_mult));
     }
-    if ((rc = hip_check(ctx, hipMemcpyAsync(qb, J->base + J->qinit_off, J->queue_bytes, hipMemcpyDeviceToDevice, st),
+    if ((rc = hip_check(ctx, launch_copy_words(reinterpret_cast<uint32_t*>(qb),
+                                               reinterpret_cast<const uint32_t*>(J->base + J->qinit_off),
+                                               J->queue_bytes / 4, st),
                         "queue reset")))
       return rc;
     if (stage_events && (rc = hip_check(ctx, hipEventRecord(ctx->ev[0], st), "event"))) return rc;

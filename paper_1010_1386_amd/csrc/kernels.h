@@ -15,4 +15,7 @@ hipError_t launch_stage(int stage, const DevProblem* probs, const WorkItem* item
 hipError_t launch_stirling_build(uint32_t* stir, int64_t sstride, const PrimeConst* pcs, int g0,
                                  int count, int scap, hipStream_t st);
 
+// dst[t] = src[t] (or 0 when src is null) for t < n words.
+hipError_t launch_copy_words(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t st);
+
 }  // namespace rsl

@@ -15,6 +15,8 @@
 //   crt         Garner mixed-radix digits + radix conversion to limbs (Sec. 4.1, step 3)
 //   stirling_build  per-prime table of Stirling numbers of the first kind
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <cstdint>
 
 #include "device.h"
@@ -22,6 +24,8 @@
 #include "stages.h"
 
 namespace rsl {
+
+static_assert(kCrtWaves == kCrtBlockCoeffs, "one coefficient per wave of a CRT block");
 
 __global__ __launch_bounds__(256) void k_reduce(const DevProblem* probs, const WorkItem* items, DevTables T) {
   const WorkItem w = items[blockIdx.x];
@@ -109,6 +113,21 @@ hipError_t launch_stage(int stage, const DevProblem* probs, const WorkItem* item
       break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// Device-to-device word copy / fill, launched as kernels so that a resident
+// job's per-run resets are plain kernel nodes when the run is captured in a graph.
+__global__ __launch_bounds__(256) void k_copy_words(uint32_t* dst, const uint32_t* src, size_t n) {
+  for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
+       t += static_cast<size_t>(gridDim.x) * blockDim.x)
+    dst[t] = src ? src[t] : 0u;
+}
+
+hipError_t launch_copy_words(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_copy_words, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, dst, src, n);
   return hipGetLastError();
 }
 

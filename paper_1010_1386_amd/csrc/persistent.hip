@@ -26,6 +26,8 @@
 
 namespace rsl {
 
+static_assert(kCrtPerTask == kCrtBlockCoeffs, "a CRT task is one CRT block's coefficients");
+
 __device__ __forceinline__ int ld_acquire(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }

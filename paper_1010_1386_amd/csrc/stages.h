@@ -20,7 +20,7 @@ enum : int {
   kNumStages = 6,
 };
 
-constexpr int kCrtWaves = 8;          // coefficients per CRT block (one wave each)
+constexpr int kCrtWaves = 8;          // waves of a CRT block (one coefficient each)
 constexpr int kLdsWords = 16384;      // 64 KB of dynamic LDS per block at most
 
 // ------------------------------------------------------------------ helpers
@@ -544,16 +544,22 @@ __device__ inline void stage_interp_newton(const DevProblem& P, const DevTables&
 // Whether the Garner table (np^2 words) and the limb table of the prefix
 // products (np L_out words) of a problem are staged in LDS by the CRT kernel,
 // and the CRT block's LDS words.
+// Residues of the block's coefficients (kCrtBlockCoeffs per block) are
+// staged in LDS first: [coefficient][prime].
+constexpr int kCrtBlockCoeffs = 8;
 __host__ __device__ inline int crt_wave_words(int ns) { return 3 * 64 * ns + 4; }
+__host__ __device__ inline int crt_base_words(const DevProblem& P, int ns, int nwaves) {
+  return nwaves * crt_wave_words(ns) + kCrtBlockCoeffs * P.np;
+}
 __host__ __device__ inline bool crt_stage_tg(const DevProblem& P, int ns, int nwaves) {
-  return P.np * P.np + nwaves * crt_wave_words(ns) <= kLdsWords;
+  return P.np * P.np + crt_base_words(P, ns, nwaves) <= kLdsWords;
 }
 __host__ __device__ inline bool crt_stage_pl(const DevProblem& P, int ns, int nwaves) {
-  return crt_stage_tg(P, ns, nwaves) && P.np * P.np + P.np * P.L_out + nwaves * crt_wave_words(ns) <= kLdsWords;
+  return crt_stage_tg(P, ns, nwaves) && P.np * P.np + P.np * P.L_out + crt_base_words(P, ns, nwaves) <= kLdsWords;
 }
 __host__ __device__ inline int crt_lds_words(const DevProblem& P, int ns, int nwaves) {
   return (crt_stage_tg(P, ns, nwaves) ? P.np * P.np : 0) + (crt_stage_pl(P, ns, nwaves) ? P.np * P.L_out : 0) +
-         nwaves * crt_wave_words(ns);
+         crt_base_words(P, ns, nwaves);
 }
 
 // One wave per coefficient k.  Garner: lanes own primes (slot i = lane + 64 r);
@@ -564,10 +570,14 @@ __host__ __device__ inline int crt_lds_words(const DevProblem& P, int ns, int nw
 // Y = sum_j v_j prod_{l<j} p_l in [0, M) and H = (M-1)/2: the symmetric residue.
 template <int NS>
 __device__ inline void crt_one(const DevProblem& P, const DevTables& T, int k_raw, const uint32_t* tg, bool staged,
-                               const uint32_t* pls, bool staged_pl, uint32_t* wb);
+                               const uint32_t* pls, bool staged_pl, uint32_t* wb, const uint32_t* ures);
 
 // One block: the Garner table (and, when it fits, the limb table) staged in
-// LDS once, then `cpw` coefficients per wave, k = (blk * waves + wave) * cpw + c.
+// LDS once, then `cpw` coefficients per wave, k = (blk * waves + wave) * cpw + c
+// (waves * cpw = kCrtBlockCoeffs).  The residues u_i of the block's
+// coefficients are summed from the basis-change partial sums first, with the
+// block's threads reading kCrtBlockCoeffs consecutive coefficients of one
+// prime together (the partial sums are stored coefficient-major per prime).
 template <int NS>
 __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds,
                                  int cpw = 1) {
@@ -579,7 +589,25 @@ __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const 
   const int L = P.L_out;
   uint32_t* tg = lds;
   uint32_t* pls = lds + (staged ? np * np : 0);
-  uint32_t* wb = pls + (staged_pl ? np * L : 0) + wave * crt_wave_words(NS);
+  uint32_t* wbase = pls + (staged_pl ? np * L : 0);
+  uint32_t* wb = wbase + wave * crt_wave_words(NS);
+  uint32_t* ures = wbase + nw * crt_wave_words(NS);  // [kCrtBlockCoeffs][np]
+  const int kbase = w.blk * kCrtBlockCoeffs;
+  const size_t cstride = static_cast<size_t>(np) * (P.D + 1);
+  for (int t = threadIdx.x; t < np * kCrtBlockCoeffs; t += blockDim.x) {
+    const int i = t / kCrtBlockCoeffs, c = t - i * kCrtBlockCoeffs;
+    const int k = (kbase + c <= P.D) ? kbase + c : P.D;
+    const PrimeConst pc = T.pc[P.pidx[i]];
+    const uint64_t* cp = P.cpart + static_cast<size_t>(i) * (P.D + 1) + k;
+    uint64_t cs = 0;
+    int ch = k / P.kchunk;
+    for (; ch + 2 <= P.nchunk; ch += 2) {
+      const uint64_t q0 = cp[ch * cstride], q1 = cp[(ch + 1) * cstride];
+      cs = add_fold(cs, add_fold(q0, q1, pc.p), pc.p);
+    }
+    if (ch < P.nchunk) cs = add_fold(cs, cp[ch * cstride], pc.p);
+    ures[c * np + i] = maddm(redc(cs, pc.p, pc.pinv), P.Hm[i], pc.p);
+  }
   if (staged) {
     for (int t = threadIdx.x; t < np * np; t += blockDim.x) {
       const int j = t / np, i = t - j * np;
@@ -593,12 +621,15 @@ __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const 
     }
   }
   __syncthreads();
-  for (int c = 0; c < cpw; ++c) crt_one<NS>(P, T, (w.blk * nw + wave) * cpw + c, tg, staged, pls, staged_pl, wb);
+  for (int c = 0; c < cpw; ++c) {
+    const int local = wave * cpw + c;
+    crt_one<NS>(P, T, kbase + local, tg, staged, pls, staged_pl, wb, ures + local * np);
+  }
 }
 
 template <int NS>
 __device__ inline void crt_one(const DevProblem& P, const DevTables& T, int k_raw, const uint32_t* tg, bool staged,
-                               const uint32_t* pls, bool staged_pl, uint32_t* wb) {
+                               const uint32_t* pls, bool staged_pl, uint32_t* wb, const uint32_t* ures) {
   const int lane = threadIdx.x & 63;
   const bool valid = k_raw <= P.D;
   const int k = valid ? k_raw : P.D;
@@ -617,18 +648,7 @@ __device__ inline void crt_one(const DevProblem& P, const DevTables& T, int k_ra
       const PrimeConst pc = T.pc[P.pidx[i]];
       pp[r] = pc.p;
       pinv[r] = pc.pinv;
-      // partial sums of the chunks that reach coefficient k (independent loads)
-      const uint64_t* cp = P.cpart + static_cast<size_t>(i) * (P.D + 1) + k;
-      const size_t cstride = static_cast<size_t>(np) * (P.D + 1);
-      uint64_t cs = 0;
-      int ch = k / P.kchunk;
-      for (; ch + 4 <= P.nchunk; ch += 4) {
-        const uint64_t q0 = cp[ch * cstride], q1 = cp[(ch + 1) * cstride];
-        const uint64_t q2 = cp[(ch + 2) * cstride], q3 = cp[(ch + 3) * cstride];
-        cs = add_fold(cs, add_fold(add_fold(q0, q1, pc.p), add_fold(q2, q3, pc.p), pc.p), pc.p);
-      }
-      for (; ch < P.nchunk; ++ch) cs = add_fold(cs, cp[ch * cstride], pc.p);
-      u[r] = maddm(redc(cs, pc.p, pc.pinv), P.Hm[i], pc.p);
+      u[r] = ures[i];  // (c_k mod p_i) + H mod p_i
       invm[r] = P.invM[i];
     } else {
       pp[r] = 3u; pinv[r] = 0u; u[r] = 0u; invm[r] = 0u;

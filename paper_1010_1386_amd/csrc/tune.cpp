@@ -25,6 +25,9 @@ struct rsl_job {
   std::vector<int> var;
   rsl_opts opts{};
   bool has_opts = false;
+  // captured runs, per schedule (index = mode), valid for table generation graph_gen
+  hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+  int graph_gen[4] = {-1, -1, -1, -1};
 };
 
 namespace rsl {
@@ -51,7 +54,16 @@ std::string tune_key(const Job& J) {
   return os.str();
 }
 
+static void release_graphs(rsl_job* j) {
+  for (int m = 0; m < 4; ++m) {
+    if (j->graph[m]) (void)hipGraphExecDestroy(j->graph[m]);
+    j->graph[m] = nullptr;
+    j->graph_gen[m] = -1;
+  }
+}
+
 static void release_mem(rsl_job* j) {
+  release_graphs(j);
   if (j->dmem) (void)hipFree(j->dmem);
   if (j->hdown) (void)hipHostFree(j->hdown);
   j->dmem = nullptr;
@@ -89,7 +101,9 @@ static int materialize(rsl_ctx* ctx, rsl_job* j, const TuneConfig& tc) {
 // Re-point the job's problems at the current constant tables if they moved.
 static int job_refresh(rsl_ctx* ctx, rsl_job* j) {
   if (j->gen == ctx->table_gen) return RSL_OK;
+  // (synchronous: the upload goes through the context's shared staging buffer)
   int rc = job_upload(ctx, &j->J, ctx->stream);
+  if (!rc) rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
   if (rc) return rc;
   j->gen = ctx->table_gen;
   return RSL_OK;
@@ -106,10 +120,39 @@ static hipEvent_t* next_evset(rsl_ctx* ctx) {
   return ctx->evsets[ctx->evused++].data();
 }
 
+// Capture reset + launches of `mode` into a graph on the context stream.
+static int capture(rsl_ctx* ctx, rsl_job* j, int mode) {
+  if (j->graph[mode]) (void)hipGraphExecDestroy(j->graph[mode]);
+  j->graph[mode] = nullptr;
+  int rc;
+  if ((rc = hip_check(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal), "begin capture")))
+    return rc;
+  int rc_launch = job_reset(ctx, &j->J, ctx->stream);
+  if (!rc_launch) rc_launch = job_launch(ctx, &j->J, mode, ctx->stream, false);
+  hipGraph_t g = nullptr;
+  if ((rc = hip_check(ctx, hipStreamEndCapture(ctx->stream, &g), "end capture"))) return rc;
+  if (rc_launch) {
+    (void)hipGraphDestroy(g);
+    return rc_launch;
+  }
+  rc = hip_check(ctx, hipGraphInstantiate(&j->graph[mode], g, nullptr, nullptr, 0), "graph instantiate");
+  (void)hipGraphDestroy(g);
+  if (rc) return rc;
+  j->graph_gen[mode] = ctx->table_gen;
+  return RSL_OK;
+}
+
 static int run_job(rsl_ctx* ctx, rsl_job* j, int mode) {
+  const bool graph = (mode & RSL_GRAPH) != 0;
+  mode &= ~RSL_GRAPH;
   if (mode == RSL_AUTO) mode = j->J.tune.mode;
   int rc;
-  if ((rc = job_refresh(ctx, j)) || (rc = job_reset(ctx, &j->J, ctx->stream))) return rc;
+  if ((rc = job_refresh(ctx, j))) return rc;
+  if (graph && !ctx->profiling && !j->J.live.empty()) {
+    if (j->graph_gen[mode] != ctx->table_gen && (rc = capture(ctx, j, mode))) return rc;
+    return hip_check(ctx, hipGraphLaunch(j->graph[mode], ctx->stream), "graph launch");
+  }
+  if ((rc = job_reset(ctx, &j->J, ctx->stream))) return rc;
   if (ctx->profiling && mode != RSL_PLAIN) {
     hipEvent_t* ev = next_evset(ctx);
     if (!ev) return fail(ctx, RSL_EDEVICE, "hipEventCreate");
@@ -179,8 +222,9 @@ int rsl_job_create(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, co
 
 int rsl_job_run(rsl_ctx* ctx, rsl_job* j, int mode) {
   if (!ctx || !j || j->ctx != ctx) return RSL_EINVAL;
-  if (mode != RSL_PLAIN && mode != RSL_BATCHED && mode != RSL_STAGED && mode != RSL_AUTO)
-    return fail(ctx, RSL_EINVAL, "mode must be RSL_PLAIN, RSL_BATCHED, RSL_STAGED or RSL_AUTO");
+  const int base = mode & ~RSL_GRAPH;
+  if (base != RSL_PLAIN && base != RSL_BATCHED && base != RSL_STAGED && base != RSL_AUTO)
+    return fail(ctx, RSL_EINVAL, "mode must be RSL_PLAIN, RSL_BATCHED, RSL_STAGED or RSL_AUTO (| RSL_GRAPH)");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   if (ctx->poisoned) return RSL_EDEVICE;
   return run_job(ctx, j, mode);

@@ -158,3 +158,25 @@ def test_eval_lanes_per_pair(ctx, lanes):
         for q in qs:
             t = rnd.randrange(q)
             assert oracle.peval(R, t) % q == oracle.res_at_point_mod(f, g, t, q, v)
+
+
+@pytest.mark.parametrize("mode", ["staged", "batched", "plain"])
+def test_graph_replays_match_eager(ctx, mode):
+    """Captured runs replayed several times, with other eager work and
+    synchronisations in between, give the eager bits every time."""
+    probs = mixed_batch(20, 13)
+    job = ctx.job(probs)
+    job.run(mode)
+    eager = job.results()
+    assert eager == [oracle.res(f, g, v) for f, g, v in probs]
+    other = ctx.job(mixed_batch(6, 14))
+    for rep in range(4):
+        job.run(mode, graph=True)
+        assert job.results() == eager, rep
+        other.run("staged")  # unrelated eager work on the same stream
+        other.results()
+        job.run(mode, graph=True)
+        job.run(mode, graph=True)
+        assert job.results() == eager, rep
+    other.close()
+    job.close()
