@@ -154,6 +154,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=100)
+    ap.add_argument("--schedule", choices=["auto", "staged", "batched"], default="auto",
+                    help="auto: autotune the job first; otherwise that schedule with the default layout")
     ap.add_argument("--serve", type=int, default=0, metavar="N",
                     help="serving benchmark instead: N Poisson-arriving requests of the serving workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -188,7 +190,11 @@ def main():
     info = job.info()
     # schedule: the autotuner times every candidate layout (staged launches /
     # one persistent launch x interpolation chunking) and keeps the fastest
-    tune = job.tune(reps=max(3, a.warmup // 4))
+    if a.schedule == "auto":
+        tune = job.tune(reps=max(3, a.warmup // 4))
+    else:
+        tune = {"mode": a.schedule, "chunk_target": 4096, "grid_mult": 1, "lanes_per_pair": None,
+                "candidates": 0, "ms": None, "ms_worst": None}
     mode = tune["mode"]
 
     # correctness gate: bit-exact against the oracle's stored digests
@@ -204,15 +210,22 @@ def main():
             print("bench: result differs from the oracle digest", file=sys.stderr)
             sys.exit(1)
 
-    def timed(mode, steps, warmup):
+    def timed(mode, steps, warmup, graph=False):
         for _ in range(warmup):
-            job.run(mode)
+            job.run(mode, graph=graph)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            job.run(mode)
+            job.run(mode, graph=graph)
         torch.cuda.synchronize()
         return time.perf_counter() - t0
+
+    # launch path: eager launches or one captured graph per step (checked first)
+    job.run(mode, graph=True)
+    if job.results() != res:
+        print("bench: graph replay differs from the eager run", file=sys.stderr)
+        sys.exit(1)
+    use_graph = timed(mode, a.plain_steps, 5, graph=True) < timed(mode, a.plain_steps, 5)
 
     def stage_profile(m, steps):
         """Per-stage device ms per step from HIP events on the library's stream
@@ -227,7 +240,7 @@ def main():
         ctx.profile_enable(False)
         return {k: v / max(runs, 1) for k, v in stages.items()}
 
-    dt = timed(mode, a.steps, a.warmup)
+    dt = timed(mode, a.steps, a.warmup, graph=use_graph)
     ms_step = dt / a.steps * 1e3
     value = 2 * a.steps / dt
     stages = stage_profile(mode, a.steps)
@@ -288,7 +301,8 @@ def main():
         "config": {"workload": "dense total-degree-24 pair, uniform signed 32-bit coefficients; "
                                "res_y and res_x per step (57 primes x 577 points each)",
                    "problems_per_step": 2, "primes": 57, "points": 577,
-                   "schedule": {"batched": "persistent", "staged": "staged"}[mode],
+                   "schedule": {"batched": "persistent", "staged": "staged"}[mode] + (" (graph)" if use_graph else ""),
+                   "lanes_per_pair": tune["lanes_per_pair"],
                    "chunk_target": tune["chunk_target"], "grid_mult": tune["grid_mult"]},
         "verified_bit_exact": verified,
         "modp_univariate_resultants_per_s": pairs / (ures_ms * 1e-3),

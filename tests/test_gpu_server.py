@@ -38,12 +38,15 @@ def requests(n, seed, dmax=12):
 def test_server_results_match_direct_calls(rsl, ref):
     ctx = rsl.Context(device=0, workspace_bytes=256 << 20)
     srv = rsl.Server(ctx, budget_bytes=128 << 20, max_slots=16, max_queue=1024)
-    reqs = requests(48, 0)
+    # a burst of requests large enough that they queue behind busy lanes
+    reqs = requests(48, 0, dmax=22)
     tickets = [srv.submit(f, g, v) for f, g, v in reqs]
     got = [srv.wait(t) for t in tickets]
     want = ref.batch(reqs, mode="staged")
     assert got == want
-    for k in range(0, 48, 12):  # the oracle on a few
+    small = [k for k, (f, g, v) in enumerate(reqs) if len(f) <= 8 and len(g) <= 8]
+    assert small
+    for k in small[:4]:  # the oracle on a few
         f, g, v = reqs[k]
         assert got[k] == oracle.res(f, g, v)
     st = srv.stats()
