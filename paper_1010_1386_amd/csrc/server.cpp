@@ -176,8 +176,10 @@ void retire(rsl_server* S, Lane& ln) {
   S->cv_done.notify_all();
 }
 
-// Plan the admitted group and launch it on the lane (server lock held).
-// Returns RSL_ENOMEM when the arena has no room yet (the group is requeued).
+// Plan the admitted group and launch it on the lane.  Called WITHOUT the
+// server lock (clients keep submitting meanwhile); touches only the lane and
+// the arena, which belong to the scheduler thread.  Returns RSL_ENOMEM when the
+// arena has no room yet.
 int launch(rsl_server* S, Lane& ln, std::vector<std::shared_ptr<Request>>& grp) {
   rsl_ctx* ctx = S->ctx;
   const int n = static_cast<int>(grp.size());
@@ -222,12 +224,17 @@ int launch(rsl_server* S, Lane& ln, std::vector<std::shared_ptr<Request>>& grp) 
   ln.outs.resize(n);
   for (int k = 0; k < n; ++k) ln.outs[k] = *grp[k]->out;
   ln.busy = true;
-  S->bytes_used += bytes;
+  return RSL_OK;
+}
+
+// Book a launched lane in the server's accounting (server lock held).
+void account(rsl_server* S, const Lane& ln) {
+  const int n = static_cast<int>(ln.reqs.size());
+  S->bytes_used += ln.bytes;
   S->slots_used += n;
   S->admitted_peak = std::max<int64_t>(S->admitted_peak, static_cast<int64_t>(S->bytes_used));
   S->launches += 1;
   S->max_batch = std::max<int64_t>(S->max_batch, n);
-  return RSL_OK;
 }
 
 void scheduler(rsl_server* S) {
@@ -253,21 +260,29 @@ void scheduler(rsl_server* S) {
         S->pending.pop_front();
       }
       if (grp.empty()) break;
+      // plan and launch without the lock: requests arriving meanwhile queue up
+      // and form the next batch
+      std::vector<std::shared_ptr<Request>> back;  // returned to the queue, in order
+      lk.unlock();
       int rc = launch(S, ln, grp);
       while (rc == RSL_ENOMEM && grp.size() > 1) {  // arena fragmented: shrink the group
-        S->pending.push_front(grp.back());
+        back.insert(back.begin(), grp.back());
         grp.pop_back();
         rc = launch(S, ln, grp);
       }
+      lk.lock();
       if (rc == RSL_ENOMEM && any_busy) {  // no room yet: wait for a batch to finish
-        S->pending.push_front(grp.front());
-        break;
+        back.insert(back.begin(), grp.front());
+        grp.clear();
       }
+      for (auto it = back.rbegin(); it != back.rend(); ++it) S->pending.push_front(*it);
+      if (grp.empty()) break;
       if (rc) {
         for (auto& r : grp) finish(S, *r, rc);
         S->cv_done.notify_all();
         continue;
       }
+      account(S, ln);
       any_busy = true;
     }
     if (S->stop && S->pending.empty() && !any_busy) break;
