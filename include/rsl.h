@@ -194,6 +194,10 @@ typedef struct {
   size_t device_bytes;    /* device memory held by the job */
   size_t upload_bytes;    /* host -> device bytes at creation */
   size_t download_bytes;  /* device -> host bytes per rsl_job_results */
+  int32_t layout_mode;    /* schedule the layout was tuned for (RSL_STAGED or RSL_BATCHED) */
+  int32_t chunk_target;   /* interpolation chunking of the layout */
+  int32_t grid_mult;      /* persistent grid multiplier */
+  int32_t eval_lanes;     /* most lanes per (prime, point) pair used by any problem */
 } rsl_job_info;
 
 /* Plan n problems and upload their inputs (status per problem in `status`, may be NULL). */

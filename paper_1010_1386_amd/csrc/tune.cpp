@@ -253,6 +253,12 @@ int rsl_job_info_get(const rsl_job* j, rsl_job_info* info) {
   info->device_bytes = j->J.total;
   info->upload_bytes = j->J.up_bytes;
   info->download_bytes = j->J.down_bytes;
+  info->layout_mode = j->J.tune.mode;
+  info->chunk_target = j->J.tune.chunk_target;
+  info->grid_mult = j->J.tune.grid_mult;
+  int lanes = 1;
+  for (const DevProblem& d : j->J.dev) lanes = std::max(lanes, d.evk);
+  info->eval_lanes = lanes;
   return RSL_OK;
 }
 
@@ -298,12 +304,27 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
         (rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize")))
       return rc;
     // statuses and outputs do not depend on the schedule: every candidate must
-    // download the same bytes
-    std::vector<uint8_t> img(j->hdown, j->hdown + j->J.down_bytes);
+    // download the same words (alignment padding between them is not compared)
+    std::vector<uint8_t> img;
+    for (size_t li = 0; li < j->J.live.size(); ++li) {
+      const Plan& P = j->J.plans[j->J.live[li]];
+      const ProbLayout& L = j->J.lay[li];
+      const uint8_t* st = j->hdown + (L.status - j->J.down_off);
+      const uint8_t* out = j->hdown + (L.out - j->J.down_off);
+      img.insert(img.end(), st, st + static_cast<size_t>(P.np + 2) * 4);
+      img.insert(img.end(), out, out + static_cast<size_t>(P.D + 1) * P.L_out * 4);
+    }
     if (ref.empty()) {
       ref = img;
     } else if (img != ref) {
-      return fail(ctx, RSL_EDEVICE, "autotuner: a candidate schedule produced different output bytes");
+      size_t at = 0;
+      while (at < img.size() && img[at] == ref[at]) ++at;
+      return fail(ctx, RSL_EDEVICE,
+                  "autotuner: candidate (mode " + std::to_string(tc.mode) + ", chunk target " +
+                      std::to_string(tc.chunk_target) + ", grid x" + std::to_string(tc.grid_mult) +
+                      ", lanes per pair " + std::to_string(tc.evk) +
+                      ") differs from the first candidate in its statuses or outputs (byte " + std::to_string(at) +
+                      " of the compared image)");
     }
     if ((rc = hip_check(ctx, hipEventRecord(ctx->e0, ctx->stream), "event"))) return rc;
     for (int r = 0; r < reps; ++r)
