@@ -122,7 +122,8 @@ typedef struct {
   int32_t eval_lanes;  /* lanes per (prime, point) pair in evaluation: 1, 2 or 4 (an upper
                           bound: problems of low degree use fewer); 0 = chosen from the job
                           size or by the autotuner */
-  int32_t reserved;
+  int32_t eval_regs;   /* 0: keep both polynomials of a pair in registers when the shape
+                          allows (degrees <= 32 differing by at most one); -1: never */
 } rsl_opts;
 
 /* Counters of the last call on a context (or of a server). */

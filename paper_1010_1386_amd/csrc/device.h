@@ -39,6 +39,7 @@ struct DevProblem {
   int nchunk, kchunk;// Stirling partial sums: k-chunks and rows per chunk
   int ncchunk, cchunk;// convolution partial sums: i-chunks and terms per chunk
   int evk, evpb;     // evaluation: lanes per (prime, point) pair (1, 2, 4), pairs per block (64 / evk)
+  int regn, pad0;    // evaluation with the polynomials in registers up to this degree (8..32), 0 = no
   // inputs (uploaded)
   const uint32_t* coeff;  // ncoef * L_in two's complement limbs
   const int* gdeg;        // max x-degree per group of kRowGroup rows: f groups then g groups

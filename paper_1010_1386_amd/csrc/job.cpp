@@ -2,6 +2,7 @@
 #include "job.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -89,10 +90,21 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     *err = "eval_lanes must be 0, 1, 2 or 4";
     return RSL_EINVAL;
   }
+  const bool regs_ok = !(opts && opts->eval_regs < 0);
+  auto regn_of = [&](const Plan& P) {
+    if (!regs_ok || P.my < 1 || P.ny < 1 || std::abs(P.my - P.ny) > 1) return 0;
+    for (int nmax : {8, 16, 24, 32})
+      if (std::max(P.my, P.ny) <= nmax) return nmax;
+    return 0;
+  };
   if (evk <= 0) {
+    // the register form needs no cross-lane work: keep one lane per pair for it
+    bool all_regs = true;
+    for (int k : J->live) all_regs = all_regs && regn_of(J->plans[k]) > 0;
     constexpr int64_t kLanesInFlight = 256LL * 4 * 4 * 64;
     evk = 1;
-    while (evk < 4 && all_pairs * evk < kLanesInFlight) evk *= 2;
+    if (!all_regs)
+      while (evk < 4 && all_pairs * evk < kLanesInFlight) evk *= 2;
   }
   J->crt_ns = 1;
   for (int li = 0; li < nl; ++li) {
@@ -123,6 +135,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     d.evk = 1;
     while (d.evk < evk && std::min(P.my, P.ny) >= 4 * d.evk * 2) d.evk *= 2;
     d.evpb = 64 / d.evk;
+    d.regn = (d.evk == 1) ? regn_of(P) : 0;
     d.cchunk = d.kchunk;  // same split for the convolution's input range
     d.ncchunk = d.nchunk;
     J->crt_ns = std::max(J->crt_ns, (P.np + 63) / 64);
@@ -251,7 +264,8 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   for (int li = 0; li < nl; ++li) {
     const DevProblem& d = J->dev[li];
     auto up = [&](int s, size_t words) { J->stage_lds[s] = std::max(J->stage_lds[s], words * 4); };
-    up(kStageEval, d.evk > 1 ? eval_group_lds_words(d, d.evk) : eval_lds_words(d));
+    up(kStageEval, d.evk > 1 ? eval_group_lds_words(d, d.evk)
+                              : (d.regn ? eval_regs_lds_words(d, d.regn) : eval_lds_words(d)));
     up(kStageConv, static_cast<size_t>(std::min(d.cchunk, d.D + 1)) + std::min(d.D + 1, d.cchunk + 256));
     up(kStageStir, d.kchunk);
     if (J->lay[li].item_end[kStageNewton] > J->lay[li].item_begin[kStageNewton]) up(kStageNewton, newton_lds_words(d, 1024));
@@ -260,7 +274,8 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   J->persist_lds = 0;
   for (int li = 0; li < nl; ++li) {
     const DevProblem& d = J->dev[li];
-    size_t w = d.evk > 1 ? eval_group_lds_words(d, d.evk) : eval_lds_words(d);
+    size_t w = d.evk > 1 ? eval_group_lds_words(d, d.evk)
+                         : (d.regn ? eval_regs_lds_words(d, d.regn) : eval_lds_words(d));
     w = std::max<size_t>(w, static_cast<size_t>(std::min(d.cchunk, d.D + 1)) + std::min(d.D + 1, d.cchunk + 64));
     w = std::max<size_t>(w, d.kchunk);
     if (J->lay[li].item_end[kStageNewton] > J->lay[li].item_begin[kStageNewton])
@@ -447,7 +462,8 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
     Q.nprob = static_cast<int>(J->live.size());
     Q.wait_ticks = ctx->queue_wait_ticks;
     if (J->persist_grid == 0) {
-      const int per_cu = persistent_blocks_per_cu(J->crt_ns, J->persist_lds);
+      // at most two waiting waves per SIMD by default: idle waves only poll
+      const int per_cu = std::min(8, persistent_blocks_per_cu(J->crt_ns, J->persist_lds));
       int cus = 256;
       hipDeviceProp_t prop;
       if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) cus = prop.multiProcessorCount;

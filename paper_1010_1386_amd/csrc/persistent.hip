@@ -28,8 +28,11 @@ namespace rsl {
 
 static_assert(kCrtPerTask == kCrtBlockCoeffs, "a CRT task is one CRT block's coefficients");
 
-__device__ __forceinline__ int ld_acquire(const int* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Polling load: coherent at device scope but without the cache invalidation an
+// acquire implies (thousands of waiting waves must not keep invalidating the
+// caches the working waves use); an acquire fence follows a successful poll.
+__device__ __forceinline__ int ld_poll(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_release(int* p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -55,8 +58,10 @@ __device__ inline void enqueue(const QueueDesc& Q, const DevProblem* probs, int 
     }
     Q.tasks[s] = make(i);
   }
-  __threadfence();
-  for (int i = 0; i < n; ++i) st_release(&Q.ready[base + i], 1);
+  // one release for the task records (and everything this wave has seen),
+  // then plain flag stores
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  for (int i = 0; i < n; ++i) __hip_atomic_store(&Q.ready[base + i], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ inline Task mk(int type, int prob, int slot, int blk, int sub) {
@@ -81,8 +86,12 @@ __global__ __launch_bounds__(64) void k_persistent(const DevProblem* probs, Queu
       const int s = atomicAdd(&Q.state->head, 1);
       const uint64_t t0 = wall_clock64();
       for (int polls = 1;; ++polls) {
-        if (ld_acquire(&Q.state->done)) { quit = 1; break; }
-        if (s < Q.capacity && ld_acquire(&Q.ready[s])) { cur = Q.tasks[s]; break; }
+        if (ld_poll(&Q.state->done)) { quit = 1; break; }
+        if (s < Q.capacity && ld_poll(&Q.ready[s])) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          cur = Q.tasks[s];
+          break;
+        }
         if ((polls & 63) == 0 && static_cast<int64_t>(wall_clock64() - t0) > Q.wait_ticks) {
           queue_abort(Q, probs);
           quit = 1;
@@ -104,15 +113,15 @@ __global__ __launch_bounds__(64) void k_persistent(const DevProblem* probs, Queu
       case kTaskReduce:
         for (int b = 0; b * 64 < P.CS; ++b) stage_reduce(P, T, WorkItem{prob, t.slot, b, 0});
         break;
-      case kTaskEval: stage_eval(P, T, w, lds); break;
+      case kTaskEval: stage_eval<false>(P, T, w, lds); break;
       case kTaskConv: stage_interp_conv(P, T, w, lds); break;
       case kTaskStir: stage_interp_stir(P, T, w, lds); break;
       case kTaskNewton: stage_interp_newton(P, T, w, lds); break;
       case kTaskCrt: stage_crt<NS>(P, T, w, lds, kCrtPerTask); break;
       default: break;
     }
-    // successors (decided by thread 0 after the block's writes are visible)
-    __threadfence();
+    // successors (decided by thread 0 after the block's writes are released)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (type == kTaskEval) {
       // last EVAL of the slot: choose the interpolation path (block-uniform)
@@ -120,7 +129,7 @@ __global__ __launch_bounds__(64) void k_persistent(const DevProblem* probs, Queu
       if (tid == 0) last = (atomicSub(&C->eval_left[t.slot], 1) == 1);
       __syncthreads();
       if (last) {
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the other eval blocks' flags
         const bool fast = fast_prime(P, t.slot);
         if (tid == 0) {
           if (fast) {

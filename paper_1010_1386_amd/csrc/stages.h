@@ -7,6 +7,7 @@
 
 #include "device.h"
 #include "ures.h"
+#include "ures_regs.h"
 
 namespace rsl {
 
@@ -320,12 +321,107 @@ __device__ inline void stage_eval_ures_group(const DevProblem& P, const DevTable
   if (lane == 0 && nbad) atomicAdd(P.status + 1 + P.np, static_cast<int>(__popcll(nbad)));
 }
 
-// Dispatch on the problem's lanes per pair (block-uniform).
+// LDS words of a register-form eval block: the tile plus two scratch columns
+// of NMAX + 1 entries per lane for lanes that leave the register path.
+__host__ __device__ inline int eval_regs_lds_words(const DevProblem& P, int nmax) {
+  return P.CS + 2 * (nmax + 1) * 64;
+}
+
+// One wave, one lane per (prime, point) pair, the two polynomials in registers
+// (ures_regs): Horner as in stage_eval_ures, then the unrolled remainder
+// sequence; no LDS traffic after the tile except for lanes that fall back.
+template <int NMAX>
+__device__ inline void stage_eval_ures_regs(const DevProblem& P, const DevTables& T, const WorkItem& w,
+                                            uint32_t* lds) {
+  constexpr int N = RegPoly<NMAX>::kN;
+  const int lane = threadIdx.x;
+  const PrimeConst pc = T.pc[P.pidx[w.slot]];
+  const uint32_t p = pc.p, pinv = pc.pinv;
+  uint32_t* tile = lds;
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(P.resid + static_cast<size_t>(w.slot) * P.CS);
+    uint4* dst = reinterpret_cast<uint4*>(tile);
+    for (int t = lane; t < P.CS / 4; t += 64) dst[t] = src[t];
+  }
+  __syncthreads();
+  uint32_t* cols = lds + P.CS;
+  const int pt = w.blk * 64 + lane;
+  const uint32_t x = static_cast<uint32_t>(P.origin + (pt < P.E ? pt : P.E));
+  const uint32_t xt = mmul(x, pc.r2, p, pinv);
+
+  uint32_t X[N], Y[N];
+  const int gf = P.myp / kRowGroup, gg = P.nyp / kRowGroup;
+  const int ng = gf > gg ? gf : gg;
+  const uint32_t* ftile = tile;
+  const uint32_t* gtile = tile + P.goff;
+#pragma unroll
+  for (int q = 0; q < N / kRowGroup; ++q) {
+    uint32_t a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0};
+    if (q < ng) {
+      const int df = __builtin_amdgcn_readfirstlane((q < gf) ? P.gdeg[q] : -1);
+      const int dg = __builtin_amdgcn_readfirstlane((q < gg) ? P.gdeg[gf + q] : -1);
+      const int dboth = df < dg ? df : dg;
+      const uint32_t* fq = ftile + kRowGroup * q;
+      const uint32_t* gq = gtile + kRowGroup * q;
+      int i = df > dg ? df : dg;
+      for (; i > dboth; --i) {
+        if (i <= df) horner_step4(a, *reinterpret_cast<const uint4*>(fq + i * P.myp), xt, p, pinv);
+        else horner_step4(b, *reinterpret_cast<const uint4*>(gq + i * P.nyp), xt, p, pinv);
+      }
+      if (i >= 0) {
+        uint4 cf = *reinterpret_cast<const uint4*>(fq + i * P.myp);
+        uint4 cg = *reinterpret_cast<const uint4*>(gq + i * P.nyp);
+        for (; i > 0; --i) {
+          const uint4 nf = *reinterpret_cast<const uint4*>(fq + (i - 1) * P.myp);
+          const uint4 ngv = *reinterpret_cast<const uint4*>(gq + (i - 1) * P.nyp);
+          horner_step8(a, b, cf, cg, xt, p, pinv);
+          cf = nf;
+          cg = ngv;
+        }
+        horner_step8(a, b, cf, cg, xt, p, pinv);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = kRowGroup * q + r;
+      X[j] = (j <= P.my) ? umin32(a[r], a[r] - p) : 0u;  // Horner keeps values below 2p
+      Y[j] = (j <= P.ny) ? umin32(b[r], b[r] - p) : 0u;
+    }
+  }
+  bool bad = false;
+  const uint32_t r = ures_regs<NMAX>(X, Y, P.my, P.ny, pc, &bad, Column<64>{cols + lane},
+                                     Column<64>{cols + (NMAX + 1) * 64 + lane});
+  const bool live = pt <= P.E;
+  if (live) {
+    const size_t o = static_cast<size_t>(w.slot) * (P.E + 1) + pt;
+    P.zval[o] = redc(r, p, pinv);
+    P.zbad[o] = bad ? 1 : 0;
+  }
+  const uint64_t nbad = __ballot(live && bad);
+  if (lane == 0 && nbad) atomicAdd(P.status + 1 + P.np, static_cast<int>(__popcll(nbad)));
+}
+
+// Dispatch on the problem's evaluation layout (block-uniform).  With
+// use_regs = false the register form is skipped (the LDS-column code computes
+// the same values), which keeps the register budget of a kernel that also
+// runs the other stages small.
+template <bool use_regs = true>
 __device__ inline void stage_eval(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
   switch (P.evk) {
-    case 2: stage_eval_ures_group<2>(P, T, w, lds); break;
-    case 4: stage_eval_ures_group<4>(P, T, w, lds); break;
-    default: stage_eval_ures(P, T, w, lds); break;
+    case 2: stage_eval_ures_group<2>(P, T, w, lds); return;
+    case 4: stage_eval_ures_group<4>(P, T, w, lds); return;
+    default: break;
+  }
+  if (!use_regs) {
+    stage_eval_ures(P, T, w, lds);
+    return;
+  }
+  switch (P.regn) {
+    case 8: stage_eval_ures_regs<8>(P, T, w, lds); return;
+    case 16: stage_eval_ures_regs<16>(P, T, w, lds); return;
+    case 24: stage_eval_ures_regs<24>(P, T, w, lds); return;
+    case 32: stage_eval_ures_regs<32>(P, T, w, lds); return;
+    default: stage_eval_ures(P, T, w, lds); return;
   }
 }
 

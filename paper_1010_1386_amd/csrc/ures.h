@@ -129,6 +129,17 @@ RSL_HD void mmad3x4s(uint32_t al, uint32_t be, uint32_t ga, uint32_t a0, uint32_
 // Resultant with formal degrees (m, n) of the polynomials in columns A, B
 // (Montgomery form; both columns are overwritten).  Returns the result in
 // Montgomery form.  *bad is set when lc_y f(x_i) or lc_y g(x_i) vanishes.
+// State of the remainder sequence between divisions: actual degrees a, b of
+// the polynomials in A, B, the numerator and denominator of the scale factor,
+// the running product U of the L_t^{k_t}, and the sign.
+struct UresState {
+  int a, b;
+  uint32_t num, den, U, neg;
+};
+
+template <class Col>
+RSL_HD uint32_t ures_run(Col A, Col B, UresState st, const PrimeConst& pc);
+
 template <class Col>
 RSL_HD uint32_t ures_formal(Col A, Col B, int m, int n, const PrimeConst& pc, bool* bad) {
   const uint32_t p = pc.p, pinv = pc.pinv, one = pc.r1;
@@ -140,13 +151,22 @@ RSL_HD uint32_t ures_formal(Col A, Col B, int m, int n, const PrimeConst& pc, bo
   int b = n;
   while (b >= 0 && B[b] == 0u) --b;
   if (a < 0 || b < 0 || (a < m && b < n)) return 0u;
-  uint32_t num = one, den = one, U = one;
+  uint32_t num = one;
   uint32_t neg = 0;
   if (a < m) {
     num = mpow(B[b], static_cast<uint32_t>(m - a), one, p, pinv);
     neg ^= static_cast<uint32_t>(n * (m - a)) & 1u;
   }
   if (b < n) num = mpow(A[a], static_cast<uint32_t>(n - b), one, p, pinv);
+  return ures_run(A, B, UresState{a, b, num, one, one, neg}, pc);
+}
+
+// The division loop from state st (A, B of actual degrees st.a, st.b).
+template <class Col>
+RSL_HD uint32_t ures_run(Col A, Col B, UresState st, const PrimeConst& pc) {
+  const uint32_t p = pc.p, pinv = pc.pinv, one = pc.r1;
+  int a = st.a, b = st.b;
+  uint32_t num = st.num, den = st.den, U = st.U, neg = st.neg;
 
   // In the usual case (deg A = deg B + 1 and every remainder one degree lower)
   // the scalars a division needs -- L = lc(B), lc(A), A[b], B[b-1] -- are

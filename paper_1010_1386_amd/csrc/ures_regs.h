@@ -1,0 +1,193 @@
+// Univariate resultant over Z_p with the two polynomials in registers.
+//
+// The same division-free remainder sequence as ures_formal (ures.h), for the
+// shapes that dominate: formal degrees m, n <= NMAX with |m - n| <= 1 and
+// nonvanishing leading coefficients.  Every index is a compile-time constant:
+// the generic division steps are unrolled for the degrees NMAX-1, ..., 1 of B
+// (a lane enters the sequence at its own degree), the two coefficient arrays
+// swap roles from one step to the next by construction, and no scratch memory
+// is touched.  A lane whose remainder sequence leaves the generic pattern
+// (a remainder of degree below deg B - 1), or whose leading coefficient
+// vanishes at the point, finishes with the general code on two scratch
+// columns, resuming from the state it reached.
+#pragma once
+#include "modarith.h"
+#include "ures.h"
+
+namespace rsl {
+
+// Registers per polynomial: rows 0..NMAX rounded up to whole row groups of 4.
+template <int NMAX>
+struct RegPoly {
+  static constexpr int kN = (NMAX / 4 + 1) * 4;
+};
+
+template <int N>
+RSL_HD uint32_t reg_get(const uint32_t (&v)[N], int i) {
+  uint32_t r = 0u;
+#pragma unroll
+  for (int j = 0; j < N; ++j) r = (j == i) ? v[j] : r;
+  return r;
+}
+
+// One generic division with deg B = BS (compile time), deg A = BS + 1:
+//   R[j] = L^2 A[j] - L lc(A) B[j-1] - lc(A~) B[j]   (j < BS), stored over A.
+// Returns false (and leaves the step's scalars) when deg R < BS - 1.
+template <int BS, int N>
+RSL_HD bool reg_step(uint32_t (&A)[N], const uint32_t (&B)[N], uint32_t p, uint32_t pinv, uint32_t* L_out,
+                     uint32_t* y_out) {
+  const uint32_t L = B[BS], lcA = A[BS + 1], Ab = A[BS], Bb1 = B[BS - 1];
+  const uint32_t lcAt = mmulsub(L, Ab, lcA, Bb1, p, pinv);
+  const uint32_t alpha = mmul(L, L, p, pinv);
+  const uint32_t beta = mneg(mmul(L, lcA, p, pinv), p);
+  const uint32_t gamma = mneg(lcAt, p);
+#pragma unroll
+  for (int j = 0; j < BS; ++j) A[j] = mmad3(alpha, A[j], beta, j > 0 ? B[j - 1] : 0u, gamma, B[j], p, pinv);
+  *L_out = L;
+  *y_out = alpha;
+  return A[BS - 1] != 0u;
+}
+
+// Steps BS = HI, HI-1, ..., 1, entered at BS = b0: A is in X when BS is odd.
+template <int BS, int N>
+struct RegChain {
+  RSL_HD static void run(uint32_t (&X)[N], uint32_t (&Y)[N], int b0, uint32_t p, uint32_t pinv, uint32_t& num,
+                         uint32_t& den, uint32_t& U, bool& slow, int& f_bs, uint32_t& f_L, uint32_t& f_y) {
+    if (BS <= b0 && !slow) {
+      uint32_t L, y;
+      const bool generic = (BS & 1) ? reg_step<BS>(X, Y, p, pinv, &L, &y) : reg_step<BS>(Y, X, p, pinv, &L, &y);
+      if (generic) {  // k = 2, delta = 1: num L^2, U L^2, den U; the sign is unchanged
+        num = mmul(num, y, p, pinv);
+        U = mmul(U, y, p, pinv);
+        den = mmul(den, U, p, pinv);
+      } else {
+        slow = true;
+        f_bs = BS;
+        f_L = L;
+        f_y = y;
+      }
+    }
+    RegChain<BS - 1, N>::run(X, Y, b0, p, pinv, num, den, U, slow, f_bs, f_L, f_y);
+  }
+};
+template <int N>
+struct RegChain<0, N> {
+  RSL_HD static void run(uint32_t (&)[N], uint32_t (&)[N], int, uint32_t, uint32_t, uint32_t&, uint32_t&, uint32_t&,
+                         bool&, int&, uint32_t&, uint32_t&) {}
+};
+
+// Res_{m,n}(A, B) with A's coefficients in X[0..m], B's in Y[0..n] (Montgomery
+// form; zero above the degree).  m, n must be the same in every lane that
+// takes part (they are per problem).  CA, CB: two scratch columns of at least
+// NMAX + 1 entries used only by lanes that leave the register path.
+template <int NMAX, class Col>
+RSL_HD uint32_t ures_regs(uint32_t (&X)[RegPoly<NMAX>::kN], uint32_t (&Y)[RegPoly<NMAX>::kN], int m, int n,
+                          const PrimeConst& pc, bool* bad, Col CA, Col CB) {
+  constexpr int N = RegPoly<NMAX>::kN;
+  const uint32_t p = pc.p, pinv = pc.pinv, one = pc.r1;
+  const uint32_t lcf = reg_get(X, m), lcg = reg_get(Y, n);
+  *bad = (lcf == 0u) || (lcg == 0u);
+  const bool shape_ok = m >= 1 && n >= 1 && m <= NMAX && n <= NMAX && (m - n <= 1) && (n - m <= 1);
+  if (!shape_ok || *bad) {
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (j <= NMAX) {
+        CA[j] = X[j];
+        CB[j] = Y[j];
+      }
+    bool b2 = false;
+    return ures_formal(CA, CB, m, n, pc, &b2);
+  }
+  uint32_t neg = 0u;
+  if (m < n) {  // Res(A, B) = (-1)^{mn} Res(B, A)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const uint32_t t = X[j];
+      X[j] = Y[j];
+      Y[j] = t;
+    }
+    neg = static_cast<uint32_t>(m * n) & 1u;
+    const int t = m;
+    m = n;
+    n = t;
+  }
+  uint32_t num = one, den = one, U = one;
+  bool slow = false;
+  int f_a = 0, f_b = 0, f_k = 0;
+  uint32_t f_L = 0, f_y = 0;
+  bool r_in_x = false;  // where a frozen lane's remainder lies
+  bool a_in_x = true;   // where A lies now
+  int b0;
+  if (m == n) {
+    // first division, k = 1: R = L A - lc(A) B, then (A, B) <- (B, R)
+    const uint32_t L = lcg, lcA = lcf;
+#pragma unroll
+    for (int j = 0; j < N; ++j) X[j] = (j < n) ? mmulsub(L, X[j], lcA, Y[j], p, pinv) : 0u;
+    if (reg_get(X, n - 1) != 0u) {  // delta = 1: num L, U L, den U
+      neg ^= static_cast<uint32_t>(n * n) & 1u;
+      num = mmul(num, L, p, pinv);
+      U = mmul(U, L, p, pinv);
+      den = mmul(den, U, p, pinv);
+    } else {
+      slow = true;
+      f_a = n;
+      f_b = n;
+      f_k = 1;
+      f_L = L;
+      f_y = L;
+      r_in_x = true;
+    }
+    a_in_x = false;
+    b0 = n - 1;
+  } else {
+    b0 = n;
+  }
+  if (!slow && b0 >= 1) {
+    // the chain wants A in X exactly when the step's degree is odd
+    if (a_in_x != ((b0 & 1) != 0)) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const uint32_t t = X[j];
+        X[j] = Y[j];
+        Y[j] = t;
+      }
+    }
+    int f_bs = 0;
+    RegChain<NMAX - 1, N>::run(X, Y, b0, p, pinv, num, den, U, slow, f_bs, f_L, f_y);
+    if (slow) {
+      f_a = f_bs + 1;
+      f_b = f_bs;
+      f_k = 2;
+      r_in_x = (f_bs & 1) != 0;
+    }
+    // generic end: the last remainder (degree 0) is in X (step 1 is odd)
+  } else if (!slow) {
+    // b0 == 0: the remainder of the first division is the constant X[0]
+  }
+  if (!slow) {
+    // B is the nonzero constant X[0] and deg A = 1: num B^1
+    num = mmul(num, X[0], p, pinv);
+    const uint32_t r = mmul(num, minv(den, one, p, pinv), p, pinv);
+    return neg ? mneg(r, p) : r;
+  }
+  // leave the register path: remainder column R (degree < f_b - 1) and B
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+    if (j <= NMAX) {
+      CA[j] = r_in_x ? X[j] : Y[j];  // R
+      CB[j] = r_in_x ? Y[j] : X[j];  // B
+    }
+  int c = f_b - 1;
+  while (c >= 0 && CA[c] == 0u) --c;
+  if (c < 0) return 0u;  // zero remainder with deg B >= 1
+  neg ^= static_cast<uint32_t>(f_a * f_b) & 1u;
+  const int delta = f_b - c;
+  const int enum_ = f_k - 1 + delta;
+  num = mmul(num, mpow(f_L, static_cast<uint32_t>(enum_), one, p, pinv), p, pinv);
+  U = mmul(U, f_y, p, pinv);
+  den = mmul(den, mpow(U, static_cast<uint32_t>(delta), one, p, pinv), p, pinv);
+  // (A, B) <- (B, R)
+  return ures_run(CB, CA, UresState{f_b, c, num, den, U, neg}, pc);
+}
+
+}  // namespace rsl

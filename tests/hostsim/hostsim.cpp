@@ -7,6 +7,7 @@
 #include <vector>
 #include "../../paper_1010_1386_amd/csrc/modarith.h"
 #include "../../paper_1010_1386_amd/csrc/ures.h"
+#include "../../paper_1010_1386_amd/csrc/ures_regs.h"
 
 using namespace rsl;
 
@@ -31,6 +32,21 @@ struct Barrier {
   }
 };
 
+template <int NMAX>
+int regs_run(const PrimeConst& pc, int m, int n, const uint32_t* A, const uint32_t* B, uint32_t* out, int* bad) {
+  constexpr int N = RegPoly<NMAX>::kN;
+  uint32_t X[N] = {}, Y[N] = {};
+  if (m > NMAX + 3 || n > NMAX + 3) return -1;
+  for (int j = 0; j <= m && j < N; ++j) X[j] = mmul(A[j] % pc.p, pc.r2, pc.p, pc.pinv);
+  for (int j = 0; j <= n && j < N; ++j) Y[j] = mmul(B[j] % pc.p, pc.r2, pc.p, pc.pinv);
+  std::vector<uint32_t> ca(N + 64, 0), cb(N + 64, 0);
+  bool bd = false;
+  const uint32_t r = ures_regs<NMAX>(X, Y, m, n, pc, &bd, Column<1>{ca.data()}, Column<1>{cb.data()});
+  *out = redc(r, pc.p, pc.pinv);
+  *bad = bd;
+  return 0;
+}
+
 template <int K>
 uint32_t group_run(const PrimeConst& pc, int m, int n, std::vector<uint32_t>& a, std::vector<uint32_t>& b,
                    bool* bad, int* agree) {
@@ -53,6 +69,20 @@ uint32_t group_run(const PrimeConst& pc, int m, int n, std::vector<uint32_t>& a,
 }  // namespace
 
 extern "C" {
+
+// The register form (ures_regs<NMAX>) of the same resultant; m, n <= NMAX.
+int hs_ures_regs(int nmax, uint32_t p, int m, int n, const uint32_t* A, const uint32_t* B, uint32_t* out,
+                 int* bad) {
+  PrimeConst pc = make_prime_const(p);
+  if (m > nmax || n > nmax) return -1;
+  switch (nmax) {
+    case 8: return regs_run<8>(pc, m, n, A, B, out, bad);
+    case 16: return regs_run<16>(pc, m, n, A, B, out, bad);
+    case 24: return regs_run<24>(pc, m, n, A, B, out, bad);
+    case 32: return regs_run<32>(pc, m, n, A, B, out, bad);
+    default: return -1;
+  }
+}
 
 // The K-lane group form of the same resultant, run by K host threads that
 // meet at a barrier wherever the kernel's lanes synchronise.  *agree is 0 if

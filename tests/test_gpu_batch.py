@@ -180,3 +180,29 @@ def test_graph_replays_match_eager(ctx, mode):
         assert job.results() == eager, rep
     other.close()
     job.close()
+
+
+def test_register_form_matches_lds_columns(ctx):
+    """Pairs kept in registers (degrees <= 32 differing by at most one) give the same
+    bits as the LDS-column code, including planted bad points, equal and adjacent
+    degrees in both orders, and the oracle on the small ones."""
+    rng = rng_for(713, 0)
+    probs = []
+    for k, (d1, d2) in enumerate([(3, 3), (5, 4), (4, 5), (8, 8), (12, 11), (16, 16), (23, 24), (31, 30), (32, 32)]):
+        f = dense_total(rng, d1, 16 if d1 > 8 else 40)
+        g = dense_total(rng, d2, 16 if d2 > 8 else 40)
+        probs.append((f, g, "yx"[k % 2]))
+    F = dense_total(rng, 10, 12)
+    F[10] = [0, -3, 1]  # lc_y = x (x - 3): bad points 0 and 3 for every prime
+    probs.append((F, dense_total(rng, 10, 12), "y"))
+    a = ctx.job(probs)
+    b = ctx.job(probs, eval_regs=False)
+    for mode in ("staged", "plain"):
+        a.run(mode)
+        b.run(mode)
+        ra, rb = a.results(), b.results()
+        assert ra == rb, mode
+    a.close()
+    b.close()
+    for (f, g, v), r in zip(probs[:4], ra[:4]):
+        assert r == oracle.res(f, g, v)

@@ -37,19 +37,25 @@ def hs():
                             ctypes.POINTER(ctypes.c_int)]
     lib.hs_eval.argtypes = [ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p,
                             ctypes.POINTER(ctypes.c_int), ctypes.c_uint32, u32p]
+    lib.hs_ures_regs.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p, u32p, u32p,
+                                 ctypes.POINTER(ctypes.c_int)]
     lib.hs_ures_group.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p, u32p, u32p,
                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     return lib
 
 
 def ures(hs, p, A, B, K=1):
-    """The lane code: one lane (K = 1) or a group of K lanes on K host threads."""
+    """The lane code: one lane (K = 1), a group of K lanes on K host threads, or
+    (K = "regs8", "regs24", ...) the register form for degrees up to that bound."""
     m, n = len(A) - 1, len(B) - 1
     a = (ctypes.c_uint32 * len(A))(*A)
     b = (ctypes.c_uint32 * len(B))(*B)
     out = ctypes.c_uint32()
     bad = ctypes.c_int()
-    if K == 1:
+    if isinstance(K, str):
+        nmax = int(K[4:])
+        assert hs.hs_ures_regs(nmax, p, m, n, a, b, ctypes.byref(out), ctypes.byref(bad)) == 0
+    elif K == 1:
         hs.hs_ures(p, m, n, a, b, ctypes.byref(out), ctypes.byref(bad))
     else:
         agree = ctypes.c_int()
@@ -58,7 +64,7 @@ def ures(hs, p, A, B, K=1):
     return out.value, bool(bad.value)
 
 
-KS = [1, 2, 4, 8]
+KS = [1, 2, 4, 8, "regs16"]
 
 
 def sylvester_det_mod(A, B, p):
@@ -97,13 +103,15 @@ def test_random_generic(hs, seed, K):
     assert got == sylvester_det_mod(A, B, p)
 
 
-@pytest.mark.parametrize("K", KS)
+@pytest.mark.parametrize("K", [1, 2, 4, 8, "regs32"])
 @pytest.mark.parametrize("seed", range(6))
 def test_random_large_degree(hs, seed, K):
     """Degrees 13..40: every lane of a group runs several four-way fused updates."""
     rng = rng_for(953, seed)
     p = PRIMES[seed % len(PRIMES)]
     m, n = int(rng.integers(13, 41)), int(rng.integers(13, 41))
+    if isinstance(K, str):
+        m, n = min(m, 32), min(n, 32)
     A = [int(v) for v in rng.integers(0, p, m + 1)]
     B = [int(v) for v in rng.integers(0, p, n + 1)]
     got, _ = ures(hs, p, A, B, K)
@@ -162,3 +170,33 @@ def test_eval_rows(hs, seed):
     for j in range(nrows):
         row = coeff[j * stride: j * stride + rdeg[j] + 1]
         assert out[j] == poly_eval_mod(row, x, p)
+
+
+@pytest.mark.parametrize("nmax", [8, 16, 24, 32])
+@pytest.mark.parametrize("seed", range(40))
+def test_register_form_shapes(hs, nmax, seed):
+    """The register form on its own shapes (|m - n| <= 1, generic and with planted
+    degree drops, vanishing leading coefficients and common factors) and on
+    shapes it hands to the general code."""
+    rng = rng_for(954, seed)
+    p = PRIMES[seed % len(PRIMES)]
+    n = int(rng.integers(1, nmax + 1))
+    kind = seed % 5
+    m = n + int(rng.integers(-1, 2)) if kind != 4 else int(rng.integers(0, nmax + 1))
+    m = max(0, min(nmax, m))
+    A = [int(v) for v in rng.integers(0, p, m + 1)]
+    B = [int(v) for v in rng.integers(0, p, n + 1)]
+    if kind == 1 and m >= 2 and n >= 2:  # common factor (y - 5): a zero remainder
+        A = polymul_mod([p - 5, 1], A[:m], p)
+        B = polymul_mod([p - 5, 1], B[:n], p)
+    if kind == 2:  # small alphabet: remainders that drop by more than one degree
+        alphabet = [0, 0, 1, p - 1]
+        A = [alphabet[int(v)] for v in rng.integers(0, 4, m + 1)]
+        B = [alphabet[int(v)] for v in rng.integers(0, 4, n + 1)]
+        A[-1] = A[-1] or 1
+        B[-1] = B[-1] or 1
+    if kind == 3:  # a vanishing leading coefficient
+        A[-1] = 0
+    got, bad = ures(hs, p, A, B, "regs%d" % nmax)
+    assert got == sylvester_det_mod(A, B, p), (m, n, kind)
+    assert bad == (A[-1] == 0 or B[-1] == 0)
