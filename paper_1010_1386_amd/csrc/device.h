@@ -56,7 +56,8 @@ struct DevProblem {
   uint64_t* aconv;        // ncchunk * np * (D+1): partial sums, REDC(sum) = Newton coefficient a_k
   uint64_t* cpart;        // nchunk * np * (D+1): partial sums, REDC(sum) = coefficient mod p
   uint32_t* out;          // (D+1) * L_out two's complement limbs of R
-  int* status;            // [0] error bits, [1+slot] 1 if gapped interpolation, [1+np] bad pairs
+  int* status;            // [0] error bits, [1+slot] 1 if gapped interpolation, [1+np] bad pairs,
+                          // [2+np+slot] 1 if a point among 0..D was bad for the prime
 };
 
 // A unit of work of a stage kernel: one block processes one item.

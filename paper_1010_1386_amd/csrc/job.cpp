@@ -231,7 +231,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   J->status_off = o;
   for (int li = 0; li < nl; ++li) {
     J->lay[li].status = o;
-    o += static_cast<size_t>(J->plans[J->live[li]].np + 2) * 4;
+    o += static_cast<size_t>(2 * J->plans[J->live[li]].np + 2) * 4;
   }
   o = align_up(o, A);
   J->status_bytes = o - J->status_off;

@@ -114,6 +114,18 @@ __device__ inline void stage_reduce(const DevProblem& P, const DevTables& T, con
 
 // -------------------------------------------------------------- eval + ures
 
+// Bad-pair bookkeeping of one eval wave: the count, and a per-prime flag set
+// when a bad point lies among 0..D (the interpolation then needs the gapped
+// point set).
+__device__ inline void eval_report_bad(const DevProblem& P, int slot, int pt, bool live, bool bad) {
+  const uint64_t nbad = __ballot(live && bad);
+  const uint64_t early = __ballot(live && bad && pt <= P.D);
+  if ((threadIdx.x & 63) == 0) {
+    if (nbad) atomicAdd(P.status + 1 + P.np, static_cast<int>(__popcll(nbad)));
+    if (early) atomicOr(P.status + 2 + P.np + slot, 1);
+  }
+}
+
 // LDS words needed by one eval block (one wave).
 __host__ __device__ inline int eval_lds_words(const DevProblem& P) {
   const int nm1 = (P.my > P.ny ? P.my : P.ny) + 1;
@@ -186,8 +198,7 @@ __device__ inline void stage_eval_ures(const DevProblem& P, const DevTables& T, 
     P.zval[o] = redc(r, p, pinv);
     P.zbad[o] = bad ? 1 : 0;
   }
-  const uint64_t nbad = __ballot(live && bad);
-  if (lane == 0 && nbad) atomicAdd(P.status + 1 + P.np, static_cast<int>(__popcll(nbad)));
+  eval_report_bad(P, w.slot, pt, live, bad);
 }
 
 // LDS words of a grouped eval block (K lanes per pair, 64/K pairs).
@@ -317,8 +328,7 @@ __device__ inline void stage_eval_ures_group(const DevProblem& P, const DevTable
     P.zval[o] = redc(r, p, pinv);
     P.zbad[o] = bad ? 1 : 0;
   }
-  const uint64_t nbad = __ballot(live && bad);
-  if (lane == 0 && nbad) atomicAdd(P.status + 1 + P.np, static_cast<int>(__popcll(nbad)));
+  eval_report_bad(P, w.slot, pt, live, bad);
 }
 
 // LDS words of a register-form eval block: the tile plus two scratch columns
@@ -397,8 +407,7 @@ __device__ inline void stage_eval_ures_regs(const DevProblem& P, const DevTables
     P.zval[o] = redc(r, p, pinv);
     P.zbad[o] = bad ? 1 : 0;
   }
-  const uint64_t nbad = __ballot(live && bad);
-  if (lane == 0 && nbad) atomicAdd(P.status + 1 + P.np, static_cast<int>(__popcll(nbad)));
+  eval_report_bad(P, w.slot, pt, live, bad);
 }
 
 // Dispatch on the problem's evaluation layout (block-uniform).  With
@@ -429,14 +438,11 @@ __device__ inline void stage_eval(const DevProblem& P, const DevTables& T, const
 
 // The consecutive fast path applies when the D+1 points used are 0..D: always
 // with formal-degree values at origin 0, otherwise when none of the points
-// 0..D was flagged bad.  Block-uniform result (all threads must call it).
+// 0..D was flagged bad (the evaluation stage sets a per-prime flag).
 __device__ inline bool fast_prime(const DevProblem& P, int slot) {
   if (P.origin != 0) return false;
   if (P.formal) return true;
-  const uint8_t* zb = P.zbad + static_cast<size_t>(slot) * (P.E + 1);
-  int any = 0;
-  for (int i = threadIdx.x; i <= P.D; i += blockDim.x) any |= zb[i];
-  return __syncthreads_or(any) == 0;
+  return __builtin_amdgcn_readfirstlane(P.status[2 + P.np + slot]) == 0;
 }
 
 // Newton forward differences at 0..D as a convolution, one i-chunk of it:
@@ -457,13 +463,33 @@ __device__ inline void stage_interp_conv(const DevProblem& P, const DevTables& T
   // alpha_i = z_i / i! for i in [ib, ie]; beta_t = (-1)^t / t! R for t in [k0 - ie, kmax - ib]
   const int tb = (k0 - ie > 0) ? k0 - ie : 0;
   const int te = kmax - ib;
+  const int na = ie - ib + 1 > 0 ? ie - ib + 1 : 0;
+  const int nb = te - tb + 1 > 0 ? te - tb + 1 : 0;
   uint32_t* alpha = lds;
-  uint32_t* beta = lds + (ie - ib + 1 > 0 ? ie - ib + 1 : 0);
+  uint32_t* beta = lds + na;
   const uint32_t* z = P.zval + static_cast<size_t>(w.slot) * (P.E + 1);
-  for (int i = ib + threadIdx.x; i <= ie; i += nt) alpha[i - ib] = mmul(z[i], ifact[i], p, pinv);
-  for (int t = tb + threadIdx.x; t <= te; t += nt) {
-    const uint32_t f = ifact[t];
-    beta[t - tb] = (t & 1) ? mneg(f, p) : f;
+  // alpha then beta as one index range, two entries per thread per pass so
+  // that their loads are in flight together
+  for (int base = threadIdx.x; base < na + nb; base += 2 * nt) {
+    uint32_t zv[2], fv[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = base + u * nt;
+      const int ec = e < na + nb ? e : na + nb - 1;
+      const int idx = ec < na ? ib + ec : tb + (ec - na);
+      fv[u] = ifact[idx];
+      zv[u] = ec < na ? z[idx] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = base + u * nt;
+      if (e < na) {
+        alpha[e] = mmul(zv[u], fv[u], p, pinv);
+      } else if (e < na + nb) {
+        const int t = tb + (e - na);
+        beta[e - na] = (t & 1) ? mneg(fv[u], p) : fv[u];
+      }
+    }
   }
   __syncthreads();
   const int k = k0 + threadIdx.x;
@@ -500,25 +526,37 @@ __device__ inline void stage_interp_stir(const DevProblem& P, const DevTables& T
   const uint64_t* ap = P.aconv + static_cast<size_t>(w.slot) * (P.D + 1);
   const size_t astride = static_cast<size_t>(P.np) * (P.D + 1);
   for (int k = ks + threadIdx.x; k <= ke; k += nt) {
+    const int nch = k / P.cchunk + 1;
+    uint64_t q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) q[u] = ap[(u < nch ? u : nch - 1) * astride + k];
     uint64_t s = 0;
-    for (int ch = 0; ch <= k / P.cchunk; ++ch) s = add_fold(s, ap[ch * astride + k], p);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (u < nch) s = add_fold(s, q[u], p);
+    for (int ch = 8; ch < nch; ++ch) s = add_fold(s, ap[ch * astride + k], p);
     lds[k - ks] = redc(s, p, pc.pinv);
   }
   __syncthreads();
   const uint32_t* S = T.stir + static_cast<int64_t>(g) * T.sstride;
   uint64_t c0 = 0, c1 = 0;
   int k = ks;
-  for (; k + 3 <= ke; k += 4) {
-    const int64_t o0 = static_cast<int64_t>(k) * (k + 1) / 2;
-    const int64_t o1 = o0 + k + 1, o2 = o1 + k + 2, o3 = o2 + k + 3;
-    const uint32_t s0 = (j <= k) ? S[o0 + j] : 0u;
-    const uint32_t s1 = (j <= k + 1) ? S[o1 + j] : 0u;
-    const uint32_t s2 = (j <= k + 2) ? S[o2 + j] : 0u;
-    const uint32_t s3 = (j <= k + 3) ? S[o3 + j] : 0u;
-    c0 = mac_fold(c0, lds[k - ks], s0, p);
-    c1 = mac_fold(c1, lds[k + 1 - ks], s1, p);
-    c0 = mac_fold(c0, lds[k + 2 - ks], s2, p);
-    c1 = mac_fold(c1, lds[k + 3 - ks], s3, p);
+  // eight table rows per pass: their loads are in flight together (the
+  // table streams from memory; j <= k masks the upper triangle)
+  const int jc = j <= P.D ? j : P.D;
+  for (; k + 7 <= ke; k += 8) {
+    uint32_t sv[8];
+    int64_t o = static_cast<int64_t>(k) * (k + 1) / 2;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      sv[u] = (jc <= k + u) ? S[o + jc] : 0u;
+      o += k + u + 1;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u += 2) {
+      c0 = mac_fold(c0, lds[k + u - ks], sv[u], p);
+      c1 = mac_fold(c1, lds[k + u + 1 - ks], sv[u + 1], p);
+    }
   }
   for (; k <= ke; ++k) {
     const int64_t o = static_cast<int64_t>(k) * (k + 1) / 2;
@@ -640,12 +678,33 @@ __device__ inline void stage_interp_newton(const DevProblem& P, const DevTables&
 // Whether the Garner table (np^2 words) and the limb table of the prefix
 // products (np L_out words) of a problem are staged in LDS by the CRT kernel,
 // and the CRT block's LDS words.
+// dst[t] = src(t) for t < n with the block's threads; every thread issues up
+// to eight loads (clamped to valid indices) before storing any, so a small
+// table costs about one memory latency.
+template <class F>
+__device__ inline void block_stage(uint32_t* dst, int n, F src) {
+  const int nt = blockDim.x;
+  for (int base = threadIdx.x; base < n; base += 8 * nt) {
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = base + u * nt;
+      v[u] = src(t < n ? t : n - 1);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = base + u * nt;
+      if (t < n) dst[t] = v[u];
+    }
+  }
+}
+
 // Residues of the block's coefficients (kCrtBlockCoeffs per block) are
 // staged in LDS first: [coefficient][prime].
 constexpr int kCrtBlockCoeffs = 8;
 __host__ __device__ inline int crt_wave_words(int ns) { return 3 * 64 * ns + 4; }
 __host__ __device__ inline int crt_base_words(const DevProblem& P, int ns, int nwaves) {
-  return nwaves * crt_wave_words(ns) + kCrtBlockCoeffs * P.np;
+  return nwaves * crt_wave_words(ns) + kCrtBlockCoeffs * P.np + 3 * P.np;
 }
 __host__ __device__ inline bool crt_stage_tg(const DevProblem& P, int ns, int nwaves) {
   return P.np * P.np + crt_base_words(P, ns, nwaves) <= kLdsWords;
@@ -666,7 +725,8 @@ __host__ __device__ inline int crt_lds_words(const DevProblem& P, int ns, int nw
 // Y = sum_j v_j prod_{l<j} p_l in [0, M) and H = (M-1)/2: the symmetric residue.
 template <int NS>
 __device__ inline void crt_one(const DevProblem& P, const DevTables& T, int k_raw, const uint32_t* tg, bool staged,
-                               const uint32_t* pls, bool staged_pl, uint32_t* wb, const uint32_t* ures);
+                               const uint32_t* pls, bool staged_pl, uint32_t* wb, const uint32_t* ures,
+                               const uint32_t* pconst);
 
 // One block: the Garner table (and, when it fits, the limb table) staged in
 // LDS once, then `cpw` coefficients per wave, k = (blk * waves + wave) * cpw + c
@@ -688,44 +748,57 @@ __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const 
   uint32_t* wbase = pls + (staged_pl ? np * L : 0);
   uint32_t* wb = wbase + wave * crt_wave_words(NS);
   uint32_t* ures = wbase + nw * crt_wave_words(NS);  // [kCrtBlockCoeffs][np]
+  uint32_t* pconst = ures + kCrtBlockCoeffs * np;     // [3][np]: p, -p^{-1} mod 2^32, Garner inverse
   const int kbase = w.blk * kCrtBlockCoeffs;
   const size_t cstride = static_cast<size_t>(np) * (P.D + 1);
+  // tables first (independent loads, several in flight per thread), then the
+  // residue sums, whose loads overlap the tables' latency
+  if (staged)
+    block_stage(tg, np * np, [&](int t) {
+      const int j = t / np, i = t - j * np;
+      return P.Tg[static_cast<size_t>(j) * P.tgs + i];
+    });
+  if (staged_pl)
+    block_stage(pls, np * L, [&](int t) {
+      const int j = t / L, l = t - j * L;
+      return P.Plimb[static_cast<size_t>(j) * P.LP + l];
+    });
   for (int t = threadIdx.x; t < np * kCrtBlockCoeffs; t += blockDim.x) {
     const int i = t / kCrtBlockCoeffs, c = t - i * kCrtBlockCoeffs;
     const int k = (kbase + c <= P.D) ? kbase + c : P.D;
-    const PrimeConst pc = T.pc[P.pidx[i]];
     const uint64_t* cp = P.cpart + static_cast<size_t>(i) * (P.D + 1) + k;
+    const int ch0 = k / P.kchunk;
+    uint64_t q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int ch = ch0 + u < P.nchunk ? ch0 + u : P.nchunk - 1;
+      q[u] = cp[ch * cstride];
+    }
+    const PrimeConst pc = T.pc[P.pidx[i]];
+    const uint32_t hm = P.Hm[i];
     uint64_t cs = 0;
-    int ch = k / P.kchunk;
-    for (; ch + 2 <= P.nchunk; ch += 2) {
-      const uint64_t q0 = cp[ch * cstride], q1 = cp[(ch + 1) * cstride];
-      cs = add_fold(cs, add_fold(q0, q1, pc.p), pc.p);
-    }
-    if (ch < P.nchunk) cs = add_fold(cs, cp[ch * cstride], pc.p);
-    ures[c * np + i] = maddm(redc(cs, pc.p, pc.pinv), P.Hm[i], pc.p);
-  }
-  if (staged) {
-    for (int t = threadIdx.x; t < np * np; t += blockDim.x) {
-      const int j = t / np, i = t - j * np;
-      tg[t] = P.Tg[static_cast<size_t>(j) * P.tgs + i];
-    }
-  }
-  if (staged_pl) {
-    for (int t = threadIdx.x; t < np * L; t += blockDim.x) {
-      const int j = t / L, l = t - j * L;
-      pls[t] = P.Plimb[static_cast<size_t>(j) * P.LP + l];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (ch0 + u < P.nchunk) cs = add_fold(cs, q[u], pc.p);
+    for (int ch = ch0 + 8; ch < P.nchunk; ++ch) cs = add_fold(cs, cp[ch * cstride], pc.p);
+    ures[c * np + i] = maddm(redc(cs, pc.p, pc.pinv), hm, pc.p);
+    if (c == 0) {
+      pconst[i] = pc.p;
+      pconst[np + i] = pc.pinv;
+      pconst[2 * np + i] = P.invM[i];
     }
   }
   __syncthreads();
   for (int c = 0; c < cpw; ++c) {
     const int local = wave * cpw + c;
-    crt_one<NS>(P, T, kbase + local, tg, staged, pls, staged_pl, wb, ures + local * np);
+    crt_one<NS>(P, T, kbase + local, tg, staged, pls, staged_pl, wb, ures + local * np, pconst);
   }
 }
 
 template <int NS>
 __device__ inline void crt_one(const DevProblem& P, const DevTables& T, int k_raw, const uint32_t* tg, bool staged,
-                               const uint32_t* pls, bool staged_pl, uint32_t* wb, const uint32_t* ures) {
+                               const uint32_t* pls, bool staged_pl, uint32_t* wb, const uint32_t* ures,
+                               const uint32_t* pconst) {
   const int lane = threadIdx.x & 63;
   const bool valid = k_raw <= P.D;
   const int k = valid ? k_raw : P.D;
@@ -741,11 +814,10 @@ __device__ inline void crt_one(const DevProblem& P, const DevTables& T, int k_ra
     const int i = lane + 64 * r;
     acc[r] = 0;
     if (i < np) {
-      const PrimeConst pc = T.pc[P.pidx[i]];
-      pp[r] = pc.p;
-      pinv[r] = pc.pinv;
+      pp[r] = pconst[i];
+      pinv[r] = pconst[np + i];
       u[r] = ures[i];  // (c_k mod p_i) + H mod p_i
-      invm[r] = P.invM[i];
+      invm[r] = pconst[2 * np + i];
     } else {
       pp[r] = 3u; pinv[r] = 0u; u[r] = 0u; invm[r] = 0u;
     }

@@ -311,7 +311,7 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
       const ProbLayout& L = j->J.lay[li];
       const uint8_t* st = j->hdown + (L.status - j->J.down_off);
       const uint8_t* out = j->hdown + (L.out - j->J.down_off);
-      img.insert(img.end(), st, st + static_cast<size_t>(P.np + 2) * 4);
+      img.insert(img.end(), st, st + static_cast<size_t>(2 * P.np + 2) * 4);
       img.insert(img.end(), out, out + static_cast<size_t>(P.D + 1) * P.L_out * 4);
     }
     if (ref.empty()) {
