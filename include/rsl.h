@@ -58,6 +58,11 @@ extern "C" {
 #define RSL_STAGED 2  /* one launch per stage, each over the work items of all problems     */
 #define RSL_AUTO 3    /* the schedule the autotuner chose for this shape (RSL_STAGED if none) */
 
+/* Environment read by rsl_ctx_create (test hooks): RSL_CRT_GARNER=1 makes the
+ * CRT stage use Garner's mixed-radix digits for every coefficient instead of
+ * the direct form (whose quotient estimate falls back to Garner only when it
+ * cannot be decided); the results are identical. */
+
 /* rsl_job_run only: OR into the mode to replay the run (status reset and every
  * launch of the schedule) as a HIP graph captured on the context stream on first
  * use and re-captured when the context's constant tables move.  Runs with

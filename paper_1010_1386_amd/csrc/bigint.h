@@ -102,6 +102,20 @@ struct BigU {
     return r;
   }
 
+  // floor(a / m)
+  BigU div_small(uint32_t m) const {
+    BigU r;
+    r.d.assign(d.size(), 0u);
+    uint64_t rem = 0;
+    for (size_t i = d.size(); i-- > 0;) {
+      const uint64_t cur = (rem << 32) | d[i];
+      r.d[i] = static_cast<uint32_t>(cur / m);
+      rem = cur % m;
+    }
+    r.trim();
+    return r;
+  }
+
   uint32_t mod_small(uint32_t m) const {
     uint64_t r = 0;
     for (size_t i = d.size(); i-- > 0;) r = ((r << 32) | d[i]) % m;

@@ -63,6 +63,7 @@ struct rsl_ctx {
   bool profiling = false;
   int table_gen = 0;                          // bumped whenever the constant tables move
   int64_t queue_wait_ticks = 0;               // persistent launch: longest wait for a task (counter ticks)
+  bool crt_garner = false;                    // test hook (RSL_CRT_GARNER): CRT by Garner's digits only
   std::map<std::string, rsl::TuneEntry> tune_cache; // shape bucket -> best schedule
   rsl_counters last{};
   std::recursive_mutex mu;

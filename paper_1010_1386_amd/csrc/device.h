@@ -39,7 +39,8 @@ struct DevProblem {
   int nchunk, kchunk;// Stirling partial sums: k-chunks and rows per chunk
   int ncchunk, cchunk;// convolution partial sums: i-chunks and terms per chunk
   int evk, evpb;     // evaluation: lanes per (prime, point) pair (1, 2, 4), pairs per block (64 / evk)
-  int regn, pad0;    // evaluation with the polynomials in registers up to this degree (8..32), 0 = no
+  int regn;          // evaluation with the polynomials in registers up to this degree (8..32), 0 = no
+  int crt_garner;    // 1: CRT by Garner's digits only (test hook), 0: direct form with Garner fallback
   // inputs (uploaded)
   const uint32_t* coeff;  // ncoef * L_in two's complement limbs
   const int* gdeg;        // max x-degree per group of kRowGroup rows: f groups then g groups
@@ -49,6 +50,10 @@ struct DevProblem {
   const uint32_t* Tg;     // [j * tgs + i]  (prod_{l<j} p_l mod p_i) R
   const uint32_t* invM;   // [i]            (prod_{l<i} p_l)^{-1} R mod p_i
   const uint32_t* Plimb;  // [j * LP + t]   limbs of prod_{l<j} p_l
+  const uint32_t* Mi;     // [j * L_out + t] limbs of M / p_j (direct CRT)
+  const uint32_t* wdir;   // [i]            (M / p_i)^{-1} R mod p_i
+  const uint32_t* rinv;   // [2 i], [2 i + 1] low, high word of floor(2^64 / p_i)
+  const uint32_t* negM;   // L_out: 2^(32 L_out) - M
   // intermediates and output
   uint32_t* resid;        // np * CS     transposed tiles, c R^2 mod p
   uint32_t* zval;         // np * (E+1)  R(x_i) mod p, normal form

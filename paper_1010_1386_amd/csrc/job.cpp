@@ -136,6 +136,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     while (d.evk < evk && std::min(P.my, P.ny) >= 4 * d.evk * 2) d.evk *= 2;
     d.evpb = 64 / d.evk;
     d.regn = (d.evk == 1) ? regn_of(P) : 0;
+    d.crt_garner = (ctx && ctx->crt_garner) ? 1 : 0;
     d.cchunk = d.kchunk;  // same split for the convolution's input range
     d.ncchunk = d.nchunk;
     J->crt_ns = std::max(J->crt_ns, (P.np + 63) / 64);
@@ -190,6 +191,10 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     L.pidx = o;  o = align_up(o + static_cast<size_t>(P.np) * 4, 16);
     L.Hm = o;    o = align_up(o + static_cast<size_t>(P.np) * 4, 16);
     L.NH = o;    o = align_up(o + static_cast<size_t>(P.L_out) * 4, 16);
+    L.Mi = o;    o = align_up(o + static_cast<size_t>(P.np) * P.L_out * 4, 16);
+    L.wdir = o;  o = align_up(o + static_cast<size_t>(P.np) * 4, 16);
+    L.rinv = o;  o = align_up(o + static_cast<size_t>(P.np) * 8, 16);
+    L.negM = o;  o = align_up(o + static_cast<size_t>(P.L_out) * 4, 16);
     if (!P.canonical) {
       L.Tg = o;    o = align_up(o + static_cast<size_t>(P.np) * P.np * 4, 16);
       L.invM = o;  o = align_up(o + static_cast<size_t>(P.np) * 4, 16);
@@ -334,6 +339,10 @@ void job_bind(Job* J, uint8_t* base) {
     std::memcpy(blob + L.pidx, P.pidx.data(), P.np * 4);
     std::memcpy(blob + L.Hm, P.Hm.data(), P.np * 4);
     std::memcpy(blob + L.NH, P.NH.data(), P.L_out * 4);
+    std::memcpy(blob + L.Mi, P.Mi.data(), P.Mi.size() * 4);
+    std::memcpy(blob + L.wdir, P.wdir.data(), P.wdir.size() * 4);
+    std::memcpy(blob + L.rinv, P.rinv.data(), P.rinv.size() * 4);
+    std::memcpy(blob + L.negM, P.negM.data(), P.negM.size() * 4);
     if (!P.canonical) {
       std::memcpy(blob + L.Tg, P.Tg.data(), P.Tg.size() * 4);
       std::memcpy(blob + L.invM, P.invM.data(), P.invM.size() * 4);
@@ -345,6 +354,10 @@ void job_bind(Job* J, uint8_t* base) {
     d.pidx = reinterpret_cast<const int*>(base + L.pidx);
     d.Hm = reinterpret_cast<const uint32_t*>(base + L.Hm);
     d.NH = reinterpret_cast<const uint32_t*>(base + L.NH);
+    d.Mi = reinterpret_cast<const uint32_t*>(base + L.Mi);
+    d.wdir = reinterpret_cast<const uint32_t*>(base + L.wdir);
+    d.rinv = reinterpret_cast<const uint32_t*>(base + L.rinv);
+    d.negM = reinterpret_cast<const uint32_t*>(base + L.negM);
     d.resid = reinterpret_cast<uint32_t*>(base + L.resid);
     d.zval = reinterpret_cast<uint32_t*>(base + L.zval);
     d.zbad = base + L.zbad;

@@ -22,7 +22,7 @@ namespace rsl {
 // Schedule parameters chosen by the autotuner (tune.cpp).
 struct ProbLayout {
   // offsets from the job base
-  size_t coeff, gdeg, pidx, Hm, NH, Tg, invM, Plimb, status;
+  size_t coeff, gdeg, pidx, Hm, NH, Tg, invM, Plimb, Mi, wdir, rinv, negM, status;
   size_t out, resid, zval, zbad, aconv, cpart;
   int L_in;
   int item_begin[kNumStages], item_end[kNumStages];

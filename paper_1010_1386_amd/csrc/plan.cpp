@@ -151,6 +151,26 @@ void crt_tables(const std::vector<uint32_t>& primes, int LP, std::vector<uint32_
   }
 }
 
+void direct_crt_tables(const std::vector<uint32_t>& primes, const BigU& M, int L, std::vector<uint32_t>* Mi,
+                       std::vector<uint32_t>* wdir, std::vector<uint32_t>* rinv, std::vector<uint32_t>* negM) {
+  const int np = static_cast<int>(primes.size());
+  Mi->assign(static_cast<size_t>(np) * L, 0u);
+  wdir->assign(np, 0u);
+  rinv->assign(2 * static_cast<size_t>(np), 0u);
+  for (int i = 0; i < np; ++i) {
+    const uint32_t p = primes[i];
+    const BigU mi = M.div_small(p);
+    const std::vector<uint32_t> lim = mi.limbs(L);
+    std::copy(lim.begin(), lim.end(), Mi->begin() + static_cast<size_t>(i) * L);
+    const uint64_t inv = powmod64(mi.mod_small(p), p - 2, p);
+    (*wdir)[i] = static_cast<uint32_t>((inv << 32) % p);  // Montgomery form
+    const uint64_t r = ~static_cast<uint64_t>(0) / p;      // floor(2^64 / p), p odd
+    (*rinv)[2 * i] = static_cast<uint32_t>(r);
+    (*rinv)[2 * i + 1] = static_cast<uint32_t>(r >> 32);
+  }
+  *negM = M.neg_limbs(L);
+}
+
 int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opts, Plan* P,
               std::string* err) {
   if (var != RSL_Y && var != RSL_X) {
@@ -260,6 +280,7 @@ int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opt
   P->NH = H.neg_limbs(P->L_out);
   if (!P->canonical) crt_tables(primes, P->L_out, &P->Tg, &P->invM, &P->Plimb);
   else { P->Tg.clear(); P->invM.clear(); P->Plimb.clear(); }
+  direct_crt_tables(primes, M, P->L_out, &P->Mi, &P->wdir, &P->rinv, &P->negM);
 
   // residue tile layout
   P->rowf = F.dx + 1;

@@ -51,6 +51,9 @@ struct Plan {
   std::vector<uint32_t> NH; // 2^(32 L_out) - (M-1)/2, L_out limbs
   // per-plan CRT tables (only when !canonical)
   std::vector<uint32_t> Tg, invM, Plimb;
+  // direct CRT tables: limbs of M / p_j ([np][L_out]), (M / p_i)^{-1} R mod p_i,
+  // floor(2^64 / p_i) as (low, high) words, 2^(32 L_out) - M
+  std::vector<uint32_t> Mi, wdir, rinv, negM;
   // device layout
   int rowf = 0, rowg = 0;   // row strides (dx + 1) of the residue tiles
   int CS = 0;               // residue words per prime (f tile + g tile, padded)
@@ -67,5 +70,9 @@ int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opt
 //   Plimb[j*LP + t] = limb t of prod_{l<j} p_l
 void crt_tables(const std::vector<uint32_t>& primes, int LP, std::vector<uint32_t>* Tg,
                 std::vector<uint32_t>* invM, std::vector<uint32_t>* Plimb);
+
+// Direct-CRT tables for an ordered prime list with product M (see Plan).
+void direct_crt_tables(const std::vector<uint32_t>& primes, const BigU& M, int L, std::vector<uint32_t>* Mi,
+                       std::vector<uint32_t>* wdir, std::vector<uint32_t>* rinv, std::vector<uint32_t>* negM);
 
 }  // namespace rsl

@@ -702,166 +702,50 @@ __device__ inline void block_stage(uint32_t* dst, int n, F src) {
 // Residues of the block's coefficients (kCrtBlockCoeffs per block) are
 // staged in LDS first: [coefficient][prime].
 constexpr int kCrtBlockCoeffs = 8;
+constexpr int kCrtConsts = 6;  // per prime: p, -p^{-1}, Garner inverse, w, r_lo, r_hi
 __host__ __device__ inline int crt_wave_words(int ns) { return 3 * 64 * ns + 4; }
 __host__ __device__ inline int crt_base_words(const DevProblem& P, int ns, int nwaves) {
-  return nwaves * crt_wave_words(ns) + kCrtBlockCoeffs * P.np + 3 * P.np;
+  return nwaves * crt_wave_words(ns) + kCrtBlockCoeffs * P.np + kCrtConsts * P.np;
 }
-__host__ __device__ inline bool crt_stage_tg(const DevProblem& P, int ns, int nwaves) {
-  return P.np * P.np + crt_base_words(P, ns, nwaves) <= kLdsWords;
-}
-__host__ __device__ inline bool crt_stage_pl(const DevProblem& P, int ns, int nwaves) {
-  return crt_stage_tg(P, ns, nwaves) && P.np * P.np + P.np * P.L_out + crt_base_words(P, ns, nwaves) <= kLdsWords;
+// The table of the M / p_j limbs is staged in LDS when it fits.
+__host__ __device__ inline bool crt_stage_mi(const DevProblem& P, int ns, int nwaves) {
+  return P.np * P.L_out + crt_base_words(P, ns, nwaves) <= kLdsWords;
 }
 __host__ __device__ inline int crt_lds_words(const DevProblem& P, int ns, int nwaves) {
-  return (crt_stage_tg(P, ns, nwaves) ? P.np * P.np : 0) + (crt_stage_pl(P, ns, nwaves) ? P.np * P.L_out : 0) +
-         crt_base_words(P, ns, nwaves);
+  return (crt_stage_mi(P, ns, nwaves) ? P.np * P.L_out : 0) + crt_base_words(P, ns, nwaves);
 }
 
-// One wave per coefficient k.  Garner: lanes own primes (slot i = lane + 64 r);
-// digit v_j is formed in lane j and broadcast, then every lane i > j adds
-// v_j (prod_{l<j} p_l mod p_i).  Radix conversion: lanes own output limbs,
-// S_t = NH_t + sum_j v_j limb_t(prod_{l<j} p_l) in 96 bits, then carries are
-// resolved with wave ballots.  The result is (Y - H) mod 2^(32 L_out) with
-// Y = sum_j v_j prod_{l<j} p_l in [0, M) and H = (M-1)/2: the symmetric residue.
-template <int NS>
-__device__ inline void crt_one(const DevProblem& P, const DevTables& T, int k_raw, const uint32_t* tg, bool staged,
-                               const uint32_t* pls, bool staged_pl, uint32_t* wb, const uint32_t* ures,
-                               const uint32_t* pconst);
-
-// One block: the Garner table (and, when it fits, the limb table) staged in
-// LDS once, then `cpw` coefficients per wave, k = (blk * waves + wave) * cpw + c
-// (waves * cpw = kCrtBlockCoeffs).  The residues u_i of the block's
-// coefficients are summed from the basis-change partial sums first, with the
-// block's threads reading kCrtBlockCoeffs consecutive coefficients of one
-// prime together (the partial sums are stored coefficient-major per prime).
-template <int NS>
-__device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds,
-                                 int cpw = 1) {
-  const int nw = blockDim.x >> 6;
-  const int wave = threadIdx.x >> 6;
-  const int np = P.np;
-  const bool staged = crt_stage_tg(P, NS, nw);
-  const bool staged_pl = crt_stage_pl(P, NS, nw);
-  const int L = P.L_out;
-  uint32_t* tg = lds;
-  uint32_t* pls = lds + (staged ? np * np : 0);
-  uint32_t* wbase = pls + (staged_pl ? np * L : 0);
-  uint32_t* wb = wbase + wave * crt_wave_words(NS);
-  uint32_t* ures = wbase + nw * crt_wave_words(NS);  // [kCrtBlockCoeffs][np]
-  uint32_t* pconst = ures + kCrtBlockCoeffs * np;     // [3][np]: p, -p^{-1} mod 2^32, Garner inverse
-  const int kbase = w.blk * kCrtBlockCoeffs;
-  const size_t cstride = static_cast<size_t>(np) * (P.D + 1);
-  // tables first (independent loads, several in flight per thread), then the
-  // residue sums, whose loads overlap the tables' latency
-  if (staged)
-    block_stage(tg, np * np, [&](int t) {
-      const int j = t / np, i = t - j * np;
-      return P.Tg[static_cast<size_t>(j) * P.tgs + i];
-    });
-  if (staged_pl)
-    block_stage(pls, np * L, [&](int t) {
-      const int j = t / L, l = t - j * L;
-      return P.Plimb[static_cast<size_t>(j) * P.LP + l];
-    });
-  for (int t = threadIdx.x; t < np * kCrtBlockCoeffs; t += blockDim.x) {
-    const int i = t / kCrtBlockCoeffs, c = t - i * kCrtBlockCoeffs;
-    const int k = (kbase + c <= P.D) ? kbase + c : P.D;
-    const uint64_t* cp = P.cpart + static_cast<size_t>(i) * (P.D + 1) + k;
-    const int ch0 = k / P.kchunk;
-    uint64_t q[8];
+// Sum of a 32-bit value over the 64 lanes of a wave (every lane gets it).
+__device__ inline uint32_t wave_sum32(uint32_t v) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int ch = ch0 + u < P.nchunk ? ch0 + u : P.nchunk - 1;
-      q[u] = cp[ch * cstride];
-    }
-    const PrimeConst pc = T.pc[P.pidx[i]];
-    const uint32_t hm = P.Hm[i];
-    uint64_t cs = 0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (ch0 + u < P.nchunk) cs = add_fold(cs, q[u], pc.p);
-    for (int ch = ch0 + 8; ch < P.nchunk; ++ch) cs = add_fold(cs, cp[ch * cstride], pc.p);
-    ures[c * np + i] = maddm(redc(cs, pc.p, pc.pinv), hm, pc.p);
-    if (c == 0) {
-      pconst[i] = pc.p;
-      pconst[np + i] = pc.pinv;
-      pconst[2 * np + i] = P.invM[i];
-    }
-  }
-  __syncthreads();
-  for (int c = 0; c < cpw; ++c) {
-    const int local = wave * cpw + c;
-    crt_one<NS>(P, T, kbase + local, tg, staged, pls, staged_pl, wb, ures + local * np, pconst);
-  }
+  for (int m = 32; m >= 1; m >>= 1) v += static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), m, 64));
+  return v;
 }
 
+// Radix conversion of one coefficient (lanes own output limbs t = lane + 64 r):
+//   Z_t = init_t + sum_j v_j tab[j][t]   (96-bit column sums),
+// carries resolved with wave ballots; writes Z mod 2^(32 L_out).
 template <int NS>
-__device__ inline void crt_one(const DevProblem& P, const DevTables& T, int k_raw, const uint32_t* tg, bool staged,
-                               const uint32_t* pls, bool staged_pl, uint32_t* wb, const uint32_t* ures,
-                               const uint32_t* pconst) {
+__device__ inline void crt_radix(const DevProblem& P, int k, bool valid, const uint32_t* vbuf, const uint32_t* tab,
+                                 int tstride, const uint64_t* init, uint32_t* sb, uint32_t* sc) {
   const int lane = threadIdx.x & 63;
-  const bool valid = k_raw <= P.D;
-  const int k = valid ? k_raw : P.D;
-  const int np = P.np;
-  const int L = P.L_out;
-  uint32_t* vbuf = wb;
-  uint32_t* sb = wb + 64 * NS;
-  uint32_t* sc = sb + 64 * NS + 2;
-
-  uint32_t u[NS], acc[NS], pp[NS], pinv[NS], invm[NS];
-#pragma unroll
-  for (int r = 0; r < NS; ++r) {
-    const int i = lane + 64 * r;
-    acc[r] = 0;
-    if (i < np) {
-      pp[r] = pconst[i];
-      pinv[r] = pconst[np + i];
-      u[r] = ures[i];  // (c_k mod p_i) + H mod p_i
-      invm[r] = pconst[2 * np + i];
-    } else {
-      pp[r] = 3u; pinv[r] = 0u; u[r] = 0u; invm[r] = 0u;
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < NS; ++r) {
-    for (int jj = 0; jj < 64; ++jj) {
-      const int j = r * 64 + jj;
-      if (j >= np) break;
-      const uint32_t vloc = mmul(msubm(u[r], acc[r], pp[r]), invm[r], pp[r], pinv[r]);
-      const uint32_t vj = __builtin_amdgcn_readlane(vloc, jj);
-      if (lane == 0) vbuf[j] = vj;
-#pragma unroll
-      for (int rr = r; rr < NS; ++rr) {
-        const int i = lane + 64 * rr;
-        if (i > j && i < np) {
-          const uint32_t tji = staged ? tg[j * np + i] : P.Tg[static_cast<size_t>(j) * P.tgs + i];
-          acc[rr] = maddm(acc[rr], mmul(vj, tji, pp[rr], pinv[rr]), pp[rr]);
-        }
-      }
-    }
-  }
-  __syncthreads();
-
-  // radix conversion: 96-bit column sums per output limb
+  const int np = P.np, L = P.L_out;
   uint64_t lo[NS];
   uint32_t hc[NS];
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
-    const int t = lane + 64 * r;
-    lo[r] = (t < L) ? P.NH[t] : 0u;
+    lo[r] = init[r];
     hc[r] = 0u;
   }
-  const uint32_t* plb = staged_pl ? pls : P.Plimb;
-  const int pls_stride = staged_pl ? L : P.LP;
   int j = 0;
   for (; j + 4 <= np; j += 4) {
     const uint32_t v0 = vbuf[j], v1 = vbuf[j + 1], v2 = vbuf[j + 2], v3 = vbuf[j + 3];
-    const uint32_t* p0 = plb + static_cast<size_t>(j) * pls_stride;
+    const uint32_t* p0 = tab + static_cast<size_t>(j) * tstride;
 #pragma unroll
     for (int r = 0; r < NS; ++r) {
       const int t = lane + 64 * r;
       if (t < L) {
-        const uint32_t w0 = p0[t], w1 = p0[pls_stride + t], w2 = p0[2 * pls_stride + t], w3 = p0[3 * pls_stride + t];
+        const uint32_t w0 = p0[t], w1 = p0[tstride + t], w2 = p0[2 * tstride + t], w3 = p0[3 * tstride + t];
         const uint64_t q0 = static_cast<uint64_t>(v0) * w0, q1 = static_cast<uint64_t>(v1) * w1;
         const uint64_t q2 = static_cast<uint64_t>(v2) * w2, q3 = static_cast<uint64_t>(v3) * w3;
         lo[r] += q0;
@@ -877,7 +761,7 @@ __device__ inline void crt_one(const DevProblem& P, const DevTables& T, int k_ra
   }
   for (; j < np; ++j) {
     const uint32_t vj = vbuf[j];
-    const uint32_t* pl = plb + static_cast<size_t>(j) * pls_stride;
+    const uint32_t* pl = tab + static_cast<size_t>(j) * tstride;
 #pragma unroll
     for (int r = 0; r < NS; ++r) {
       const int t = lane + 64 * r;
@@ -889,14 +773,19 @@ __device__ inline void crt_one(const DevProblem& P, const DevTables& T, int k_ra
     }
   }
   // limb t receives lo32(S_t) + hi32(S_{t-1}) + top32(S_{t-2})
+  WaveSync sync;
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
     const int t = lane + 64 * r;
     sb[t + 1] = static_cast<uint32_t>(lo[r] >> 32);
     sc[t + 2] = hc[r];
   }
-  if (lane == 0) { sb[0] = 0; sc[0] = 0; sc[1] = 0; }
-  __syncthreads();
+  if (lane == 0) {
+    sb[0] = 0;
+    sc[0] = 0;
+    sc[1] = 0;
+  }
+  sync();
   uint32_t l1[NS], h1[NS];
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
@@ -905,10 +794,10 @@ __device__ inline void crt_one(const DevProblem& P, const DevTables& T, int k_ra
     l1[r] = static_cast<uint32_t>(wv);
     h1[r] = static_cast<uint32_t>(wv >> 32);  // <= 2
   }
-  __syncthreads();
+  sync();
 #pragma unroll
   for (int r = 0; r < NS; ++r) sb[lane + 64 * r + 1] = h1[r];
-  __syncthreads();
+  sync();
   uint64_t cin = 0;
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
@@ -926,6 +815,163 @@ __device__ inline void crt_one(const DevProblem& P, const DevTables& T, int k_ra
     cin = static_cast<uint64_t>(tot >> 64);
     const uint32_t limb = l2 + static_cast<uint32_t>((C >> lane) & 1u);
     if (valid && t < L) P.out[static_cast<size_t>(k) * L + t] = limb;
+  }
+}
+
+// One wave per coefficient k; lanes own primes (slot i = lane + 64 r) with the
+// shifted residues u_i = c_k + H mod p_i, H = (M-1)/2, so that Y = c_k + H lies
+// in [0, M) and c_k = Y - H is the symmetric residue.
+//
+// Direct form: with M_i = M / p_i and t_i = u_i (M_i^{-1} mod p_i),
+//   Y = sum_i t_i M_i - q M,  q = floor(sum_i t_i / p_i).
+// q is found from 32-bit fixed-point parts f_i = floor(t_i floor(2^64/p_i) / 2^32),
+// which undershoot t_i 2^32 / p_i by less than 2 each: q = floor(sum f_i / 2^32)
+// whenever the fraction of that sum is below 2^32 - 2 np.  Otherwise (rare)
+// the wave computes Y by Garner's mixed-radix digits instead: digit v_j is
+// formed in lane j and broadcast, every lane i > j adds v_j (prod_{l<j} p_l
+// mod p_i), and Y = sum_j v_j prod_{l<j} p_l.
+// The output Z = Y - H mod 2^(32 L_out) is formed by crt_radix with
+// init = 2^(32 L_out) - H (+ q (2^(32 L_out) - M) in the direct form).
+template <int NS>
+__device__ inline void crt_one(const DevProblem& P, int k_raw, const uint32_t* mi, int mstride, uint32_t* wb,
+                               const uint32_t* ures, const uint32_t* pconst) {
+  const int lane = threadIdx.x & 63;
+  const bool valid = k_raw <= P.D;
+  const int k = valid ? k_raw : P.D;
+  const int np = P.np;
+  const int L = P.L_out;
+  uint32_t* vbuf = wb;
+  uint32_t* sb = wb + 64 * NS;
+  uint32_t* sc = sb + 64 * NS + 2;
+  const uint32_t* cp = pconst;               // p
+  const uint32_t* cpinv = pconst + np;       // -p^{-1} mod 2^32
+  const uint32_t* cinvm = pconst + 2 * np;   // Garner inverse (Montgomery)
+  const uint32_t* cw = pconst + 3 * np;      // (M / p_i)^{-1} mod p_i (Montgomery)
+  const uint32_t* crlo = pconst + 4 * np;    // floor(2^64 / p_i), low word
+  const uint32_t* crhi = pconst + 5 * np;    //                    high word
+
+  uint32_t u[NS];
+  uint32_t fa = 0u, fb = 0u;  // f_i = fa + fb 2^24, summed over the lanes below
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    const int i = lane + 64 * r;
+    u[r] = 0u;
+    if (i < np) {
+      u[r] = ures[i];
+      const uint32_t p = cp[i];
+      const uint32_t t = mmul(u[r], cw[i], p, cpinv[i]);
+      vbuf[i] = t;
+      const uint64_t f = static_cast<uint64_t>(t) * crhi[i] + __umulhi(t, crlo[i]);
+      fa += static_cast<uint32_t>(f) & 0xFFFFFFu;
+      fb += static_cast<uint32_t>(f >> 24);
+    }
+  }
+  const uint64_t Sf = static_cast<uint64_t>(wave_sum32(fa)) + (static_cast<uint64_t>(wave_sum32(fb)) << 24);
+  const uint32_t q = static_cast<uint32_t>(Sf >> 32);
+  const bool direct = static_cast<uint32_t>(Sf) < 0xFFFFFFFFu - 2u * static_cast<uint32_t>(np) && !P.crt_garner;
+  uint64_t init[NS];
+  if (__builtin_amdgcn_readfirstlane(direct ? 1 : 0)) {
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      const int t = lane + 64 * r;
+      init[r] = (t < L) ? static_cast<uint64_t>(P.NH[t]) + static_cast<uint64_t>(q) * P.negM[t] : 0u;
+    }
+    WaveSync()();
+    crt_radix<NS>(P, k, valid, vbuf, mi, mstride, init, sb, sc);
+    return;
+  }
+  // Garner fallback (tables read from global memory)
+  uint32_t acc[NS];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) acc[r] = 0u;
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    for (int jj = 0; jj < 64; ++jj) {
+      const int j = r * 64 + jj;
+      if (j >= np) break;
+      const int i0 = lane + 64 * r;
+      const uint32_t pr = i0 < np ? cp[i0] : 3u, pir = i0 < np ? cpinv[i0] : 0u;
+      const uint32_t im = i0 < np ? cinvm[i0] : 0u;
+      const uint32_t vloc = mmul(msubm(u[r], acc[r], pr), im, pr, pir);
+      const uint32_t vj = __builtin_amdgcn_readlane(vloc, jj);
+      if (lane == 0) vbuf[j] = vj;
+#pragma unroll
+      for (int rr = r; rr < NS; ++rr) {
+        const int i = lane + 64 * rr;
+        if (i > j && i < np) {
+          const uint32_t tji = P.Tg[static_cast<size_t>(j) * P.tgs + i];
+          acc[rr] = maddm(acc[rr], mmul(vj, tji, cp[i], cpinv[i]), cp[i]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    const int t = lane + 64 * r;
+    init[r] = (t < L) ? P.NH[t] : 0u;
+  }
+  WaveSync()();
+  crt_radix<NS>(P, k, valid, vbuf, P.Plimb, P.LP, init, sb, sc);
+}
+
+// One block: the per-prime constants and (when it fits) the M / p_j limb
+// table staged in LDS once, then `cpw` coefficients per wave,
+// k = (blk * waves + wave) * cpw + c (waves * cpw = kCrtBlockCoeffs).  The
+// residues u_i of the block's coefficients are summed from the basis-change
+// partial sums first, with the block's threads reading kCrtBlockCoeffs
+// consecutive coefficients of one prime together.
+template <int NS>
+__device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds,
+                                 int cpw = 1) {
+  const int nw = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6;
+  const int np = P.np;
+  const bool staged_mi = crt_stage_mi(P, NS, nw);
+  const int L = P.L_out;
+  uint32_t* mis = lds;
+  uint32_t* wbase = lds + (staged_mi ? np * L : 0);
+  uint32_t* wb = wbase + wave * crt_wave_words(NS);
+  uint32_t* ures = wbase + nw * crt_wave_words(NS);  // [kCrtBlockCoeffs][np]
+  uint32_t* pconst = ures + kCrtBlockCoeffs * np;     // [kCrtConsts][np]
+  const int kbase = w.blk * kCrtBlockCoeffs;
+  const size_t cstride = static_cast<size_t>(np) * (P.D + 1);
+  if (staged_mi)
+    block_stage(mis, np * L, [&](int t) {
+      const int j = t / L, l = t - j * L;
+      return P.Mi[static_cast<size_t>(j) * L + l];
+    });
+  for (int t = threadIdx.x; t < np * kCrtBlockCoeffs; t += blockDim.x) {
+    const int i = t / kCrtBlockCoeffs, c = t - i * kCrtBlockCoeffs;
+    const int k = (kbase + c <= P.D) ? kbase + c : P.D;
+    const uint64_t* cpp = P.cpart + static_cast<size_t>(i) * (P.D + 1) + k;
+    const int ch0 = k / P.kchunk;
+    uint64_t q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int ch = ch0 + u < P.nchunk ? ch0 + u : P.nchunk - 1;
+      q[u] = cpp[ch * cstride];
+    }
+    const PrimeConst pc = T.pc[P.pidx[i]];
+    const uint32_t hm = P.Hm[i];
+    uint64_t cs = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (ch0 + u < P.nchunk) cs = add_fold(cs, q[u], pc.p);
+    for (int ch = ch0 + 8; ch < P.nchunk; ++ch) cs = add_fold(cs, cpp[ch * cstride], pc.p);
+    ures[c * np + i] = maddm(redc(cs, pc.p, pc.pinv), hm, pc.p);
+    if (c == 0) {
+      pconst[i] = pc.p;
+      pconst[np + i] = pc.pinv;
+      pconst[2 * np + i] = P.invM[i];
+      pconst[3 * np + i] = P.wdir[i];
+      pconst[4 * np + i] = P.rinv[2 * i];
+      pconst[5 * np + i] = P.rinv[2 * i + 1];
+    }
+  }
+  __syncthreads();
+  for (int c = 0; c < cpw; ++c) {
+    const int local = wave * cpw + c;
+    crt_one<NS>(P, kbase + local, staged_mi ? mis : P.Mi, L, wb, ures + local * np, pconst);
   }
 }
 

@@ -206,3 +206,17 @@ def test_register_form_matches_lds_columns(ctx):
     b.close()
     for (f, g, v), r in zip(probs[:4], ra[:4]):
         assert r == oracle.res(f, g, v)
+
+
+def test_crt_direct_form_equals_garner(ctx, monkeypatch):
+    """The direct CRT (quotient from fixed-point parts) and Garner's digits give the
+    same bits, on mixed problems including more than 64 primes."""
+    import paper_1010_1386_amd as rsl
+    monkeypatch.setenv("RSL_CRT_GARNER", "1")
+    cg = rsl.Context(device=0, workspace_bytes=256 << 20)
+    monkeypatch.delenv("RSL_CRT_GARNER")
+    rng = rng_for(714, 0)
+    probs = mixed_batch(12, 15) + [(dense_total(rng, 10, 64), dense_total(rng, 10, 64), "y")]
+    for mode in ("staged", "batched"):
+        assert cg.batch(probs, mode=mode) == ctx.batch(probs, mode=mode), mode
+    cg.close()
