@@ -73,6 +73,20 @@ struct WorkItem {
   int sub;   // stage-specific (Stirling k-chunk)
 };
 
+// Problems of a job that use the same prime share the basis-change table
+// reads: a group lists (problem, slot) members of one global prime index.
+struct StirMember {
+  int prob;
+  int slot;
+};
+struct StirGroup {
+  int g;       // global prime index
+  int first;   // first member in the member list
+  int count;   // members (at most kStirGroupMax)
+  int maxD;    // largest degree bound among the members
+};
+constexpr int kStirGroupMax = 8;
+
 // status[0] error bits
 enum : int {
   kErrTooFewGoodPoints = 1,

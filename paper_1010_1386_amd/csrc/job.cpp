@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <numeric>
 
 #include "context.h"
@@ -106,6 +107,16 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     if (!all_regs)
       while (evk < 4 && all_pairs * evk < kLanesInFlight) evk *= 2;
   }
+  // one chunk length K for the basis change of every problem, so that problems
+  // sharing a prime can share the table reads; chunks of at least 128 rows
+  int Kc = 128;
+  {
+    int64_t nch = 1;
+    if (stir_base < target) nch = (target + stir_base - 1) / std::max<int64_t>(stir_base, 1);
+    int dmax = 0;
+    for (int k : J->live) dmax = std::max(dmax, J->plans[k].D + 1);
+    Kc = std::max<int>(128, static_cast<int>((dmax + nch - 1) / nch));
+  }
   J->crt_ns = 1;
   for (int li = 0; li < nl; ++li) {
     const Plan& P = J->plans[J->live[li]];
@@ -127,10 +138,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     d.formal = P.formal;
     d.np = P.np;
     d.L_out = P.L_out;
-    int nch = 1;
-    if (stir_base < target) nch = static_cast<int>((target + stir_base - 1) / std::max<int64_t>(stir_base, 1));
-    nch = std::max(1, std::min(nch, (P.D + 1 + 127) / 128));
-    d.kchunk = (P.D + 1 + nch - 1) / nch;
+    d.kchunk = Kc;
     d.nchunk = (P.D + 1 + d.kchunk - 1) / d.kchunk;
     d.evk = 1;
     while (d.evk < evk && std::min(P.my, P.ny) >= 4 * d.evk * 2) d.evk *= 2;
@@ -172,6 +180,41 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     for (int s = 0; s < kNumStages; ++s) L.item_end[s] = static_cast<int>(J->items[s].size());
   }
 
+  // prime groups for the basis change: the problems whose interpolation can take
+  // the consecutive-point path (origin 0), by global prime index
+  J->sgroups.clear();
+  J->smembers.clear();
+  J->sg_items.clear();
+  J->sg_lds = 0;
+  {
+    std::map<int, std::vector<StirMember>> by_prime;
+    for (int li = 0; li < nl; ++li) {
+      const Plan& P = J->plans[J->live[li]];
+      if (P.origin != 0) continue;
+      for (int sl = 0; sl < P.np; ++sl) by_prime[P.pidx[sl]].push_back(StirMember{li, sl});
+    }
+    const int gmax = std::max(1, std::min(kStirGroupMax, kLdsWords / Kc));
+    for (const auto& kv : by_prime) {
+      const std::vector<StirMember>& mem = kv.second;
+      for (size_t b = 0; b < mem.size(); b += gmax) {
+        StirGroup G{kv.first, static_cast<int>(J->smembers.size()), static_cast<int>(std::min<size_t>(gmax, mem.size() - b)),
+                    0};
+        for (int m = 0; m < G.count; ++m) {
+          J->smembers.push_back(mem[b + m]);
+          G.maxD = std::max(G.maxD, J->dev[mem[b + m].prob].D);
+        }
+        const int gi = static_cast<int>(J->sgroups.size());
+        J->sgroups.push_back(G);
+        J->sg_lds = std::max<size_t>(J->sg_lds, static_cast<size_t>(G.count) * Kc * 4);
+        for (int jb = 0; jb < blocks_of(G.maxD + 1, 256); ++jb)
+          for (int ch = 0; ch * Kc <= G.maxD; ++ch) {
+            const int ke = std::min(G.maxD, (ch + 1) * Kc - 1);
+            if (ke >= jb * 256) J->sg_items.push_back({gi, -1, jb, ch});
+          }
+      }
+    }
+  }
+
   // device layout: [problems | items | inputs | statuses][outputs][intermediates]
   const size_t A = 256;
   size_t o = 0;
@@ -181,6 +224,12 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     J->items_off[s] = o;
     o = align_up(o + sizeof(WorkItem) * J->items[s].size(), A);
   }
+  J->sg_off = o;
+  o = align_up(o + sizeof(StirGroup) * J->sgroups.size(), A);
+  J->sm_off = o;
+  o = align_up(o + sizeof(StirMember) * J->smembers.size(), A);
+  J->sgi_off = o;
+  o = align_up(o + sizeof(WorkItem) * J->sg_items.size(), A);
   for (int li = 0; li < nl; ++li) {
     const Plan& P = J->plans[J->live[li]];
     const DevProblem& d = J->dev[li];
@@ -398,6 +447,11 @@ void job_bind(Job* J, uint8_t* base) {
   for (int s = 0; s < kNumStages; ++s)
     if (!J->items[s].empty())
       std::memcpy(blob + J->items_off[s], J->items[s].data(), sizeof(WorkItem) * J->items[s].size());
+  if (!J->sgroups.empty()) {
+    std::memcpy(blob + J->sg_off, J->sgroups.data(), sizeof(StirGroup) * J->sgroups.size());
+    std::memcpy(blob + J->sm_off, J->smembers.data(), sizeof(StirMember) * J->smembers.size());
+    std::memcpy(blob + J->sgi_off, J->sg_items.data(), sizeof(WorkItem) * J->sg_items.size());
+  }
 }
 
 // CRT tables: canonical prime lists use the context's global tables.
@@ -498,6 +552,15 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
   }
   for (int s = 0; s < kNumStages; ++s) {
     if (stage_events && (rc = hip_check(ctx, hipEventRecord(ctx->ev[s], st), "event"))) return rc;
+    if (s == kStageStir && !J->sg_items.empty()) {
+      if ((rc = hip_check(ctx, launch_stir_group(probs, reinterpret_cast<const StirGroup*>(J->base + J->sg_off),
+                                                 reinterpret_cast<const StirMember*>(J->base + J->sm_off),
+                                                 reinterpret_cast<const WorkItem*>(J->base + J->sgi_off),
+                                                 static_cast<int>(J->sg_items.size()), J->sg_lds, T, st),
+                          "launch")))
+        return rc;
+      continue;
+    }
     if ((rc = hip_check(ctx, launch_stage(s, probs, items(s), static_cast<int>(J->items[s].size()),
                                           J->stage_lds[s], J->crt_ns, T, st), "launch")))
       return rc;

@@ -36,6 +36,11 @@ struct Job {
   std::vector<ProbLayout> lay;     // per live problem
   std::vector<DevProblem> dev;     // per live problem (pointers valid for `base`)
   std::vector<WorkItem> items[kNumStages];
+  // basis change over prime groups (staged schedule)
+  std::vector<StirGroup> sgroups;
+  std::vector<StirMember> smembers;
+  std::vector<WorkItem> sg_items;
+  size_t sg_off = 0, sm_off = 0, sgi_off = 0, sg_lds = 0;
   size_t items_off[kNumStages] = {};
   size_t stage_lds[kNumStages] = {};
   int crt_ns = 1;

@@ -11,6 +11,10 @@ namespace rsl {
 hipError_t launch_stage(int stage, const DevProblem* probs, const WorkItem* items, int nitems, size_t lds,
                         int crt_ns, const DevTables& T, hipStream_t st);
 
+// Basis change over prime groups (problems sharing a prime share the table reads).
+hipError_t launch_stir_group(const DevProblem* probs, const StirGroup* groups, const StirMember* members,
+                             const WorkItem* items, int nitems, size_t lds, const DevTables& T, hipStream_t st);
+
 // Stirling numbers of the first kind mod p_g for g in [g0, g0+count), rows 0..scap.
 hipError_t launch_stirling_build(uint32_t* stir, int64_t sstride, const PrimeConst* pcs, int g0,
                                  int count, int scap, hipStream_t st);

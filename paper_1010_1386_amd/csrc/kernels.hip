@@ -92,6 +92,21 @@ __global__ __launch_bounds__(1024) void k_stirling_build(uint32_t* stir, int64_t
 
 // ------------------------------------------------------------ launchers
 
+__global__ __launch_bounds__(256) void k_interp_stir_group(const DevProblem* probs, const StirGroup* groups,
+                                                           const StirMember* members, const WorkItem* items,
+                                                           DevTables T) {
+  extern __shared__ uint32_t lds[];
+  const WorkItem w = items[blockIdx.x];
+  stage_interp_stir_group(probs, groups, members, T, w, lds);
+}
+
+hipError_t launch_stir_group(const DevProblem* probs, const StirGroup* groups, const StirMember* members,
+                             const WorkItem* items, int nitems, size_t lds, const DevTables& T, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_interp_stir_group, dim3(nitems), dim3(256), lds, st, probs, groups, members, items, T);
+  return hipGetLastError();
+}
+
 hipError_t launch_stage(int stage, const DevProblem* probs, const WorkItem* items, int nitems, size_t lds,
                         int crt_ns, const DevTables& T, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;

@@ -565,6 +565,96 @@ __device__ inline void stage_interp_stir(const DevProblem& P, const DevTables& T
   if (j <= P.D) P.cpart[(static_cast<size_t>(w.sub) * P.np + w.slot) * (P.D + 1) + j] = add_fold(c0, c1, p);
 }
 
+// The same basis change for every member of a prime group (problems that use
+// one prime): each table row is read once and multiplied into every member's
+// partial sums.  Item: (group, -, j-block, k-chunk); all members share the
+// chunk size (kchunk) and their rows k > D_m contribute zeros.
+__device__ inline void stage_interp_stir_group(const DevProblem* probs, const StirGroup* groups,
+                                               const StirMember* members, const DevTables& T, const WorkItem& w,
+                                               uint32_t* lds) {
+  const StirGroup G = groups[w.prob];
+  const int nt = blockDim.x;
+  const int j0 = w.blk * nt;
+  const int j = j0 + threadIdx.x;
+  const PrimeConst pc = T.pc[G.g];
+  const uint32_t p = pc.p;
+  const int K = probs[members[G.first].prob].kchunk;
+  const int kb = w.sub * K;
+  const int ks = kb > j0 ? kb : j0;
+  const int ke = (kb + K - 1 < G.maxD) ? kb + K - 1 : G.maxD;
+  if (ks > ke) return;
+  const int nk = ke - ks + 1;
+  // per member: its a_k for k in [ks, ke] (0 beyond its degree bound), or inactive
+  bool act[kStirGroupMax];
+#pragma unroll
+  for (int m = 0; m < kStirGroupMax; ++m) {
+    act[m] = false;
+    if (m < G.count) {
+      const StirMember M = members[G.first + m];
+      const DevProblem& P = probs[M.prob];
+      act[m] = P.D >= ks && fast_prime(P, M.slot);
+      if (!act[m]) continue;
+      uint32_t* am = lds + m * K;
+      const uint64_t* ap = P.aconv + static_cast<size_t>(M.slot) * (P.D + 1);
+      const size_t astride = static_cast<size_t>(P.np) * (P.D + 1);
+      for (int k = ks + threadIdx.x; k <= ke; k += nt) {
+        uint32_t v = 0u;
+        if (k <= P.D) {
+          const int nch = k / P.cchunk + 1;
+          uint64_t q[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) q[u] = ap[(u < nch ? u : nch - 1) * astride + k];
+          uint64_t sacc = 0;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (u < nch) sacc = add_fold(sacc, q[u], p);
+          for (int ch = 8; ch < nch; ++ch) sacc = add_fold(sacc, ap[ch * astride + k], p);
+          v = redc(sacc, p, pc.pinv);
+        }
+        am[k - ks] = v;
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t* S = T.stir + static_cast<int64_t>(G.g) * T.sstride;
+  uint64_t acc[kStirGroupMax];
+#pragma unroll
+  for (int m = 0; m < kStirGroupMax; ++m) acc[m] = 0u;
+  const int jc = j <= G.maxD ? j : G.maxD;
+  int k = ks;
+  for (; k + 3 <= ke; k += 4) {
+    uint32_t sv[4];
+    int64_t o = static_cast<int64_t>(k) * (k + 1) / 2;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sv[u] = (jc <= k + u) ? S[o + jc] : 0u;
+      o += k + u + 1;
+    }
+#pragma unroll
+    for (int m = 0; m < kStirGroupMax; ++m)
+      if (act[m]) {
+        const uint32_t* am = lds + m * K + (k - ks);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[m] = mac_fold(acc[m], am[u], sv[u], p);
+      }
+  }
+  for (; k <= ke; ++k) {
+    const int64_t o = static_cast<int64_t>(k) * (k + 1) / 2;
+    const uint32_t sv = (jc <= k) ? S[o + jc] : 0u;
+#pragma unroll
+    for (int m = 0; m < kStirGroupMax; ++m)
+      if (act[m]) acc[m] = mac_fold(acc[m], lds[m * K + (k - ks)], sv, p);
+  }
+#pragma unroll
+  for (int m = 0; m < kStirGroupMax; ++m)
+    if (act[m]) {
+      const StirMember M = members[G.first + m];
+      const DevProblem& P = probs[M.prob];
+      if (j <= P.D) P.cpart[(static_cast<size_t>(w.sub) * P.np + M.slot) * (P.D + 1) + j] = acc[m];
+    }
+  (void)nk;
+}
+
 // LDS words of the gapped-interpolation block.
 __host__ __device__ inline int newton_lds_words(const DevProblem& P, int nthreads) {
   const int e1 = P.E + 1;
