@@ -445,6 +445,16 @@ __device__ inline bool fast_prime(const DevProblem& P, int slot) {
   return __builtin_amdgcn_readfirstlane(P.status[2 + P.np + slot]) == 0;
 }
 
+// Column j of Stirling rows k..k+7 (zero above the diagonal j <= k + u).
+__device__ __forceinline__ void stir_rows8(const uint32_t* S, int k, int j, uint32_t* v) {
+  int64_t o = static_cast<int64_t>(k) * (k + 1) / 2;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    v[u] = (j <= k + u) ? S[o + j] : 0u;
+    o += k + u + 1;
+  }
+}
+
 // Newton forward differences at 0..D as a convolution, one i-chunk of it:
 //   a_k = Delta^k z_0 / k! = sum_{i<=k} (z_i / i!) ((-1)^(k-i) / (k-i)!)
 // Each thread owns one k; the chunk's partial sum is stored unreduced
@@ -544,19 +554,18 @@ __device__ inline void stage_interp_stir(const DevProblem& P, const DevTables& T
   // eight table rows per pass: their loads are in flight together (the
   // table streams from memory; j <= k masks the upper triangle)
   const int jc = j <= P.D ? j : P.D;
+  uint32_t sv[8];
+  if (k + 7 <= ke) stir_rows8(S, k, jc, sv);
   for (; k + 7 <= ke; k += 8) {
-    uint32_t sv[8];
-    int64_t o = static_cast<int64_t>(k) * (k + 1) / 2;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      sv[u] = (jc <= k + u) ? S[o + jc] : 0u;
-      o += k + u + 1;
-    }
+    uint32_t nv[8];
+    if (k + 15 <= ke) stir_rows8(S, k + 8, jc, nv);
 #pragma unroll
     for (int u = 0; u < 8; u += 2) {
       c0 = mac_fold(c0, lds[k + u - ks], sv[u], p);
       c1 = mac_fold(c1, lds[k + u + 1 - ks], sv[u + 1], p);
     }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sv[u] = nv[u];
   }
   for (; k <= ke; ++k) {
     const int64_t o = static_cast<int64_t>(k) * (k + 1) / 2;
@@ -622,21 +631,22 @@ __device__ inline void stage_interp_stir_group(const DevProblem* probs, const St
   for (int m = 0; m < kStirGroupMax; ++m) acc[m] = 0u;
   const int jc = j <= G.maxD ? j : G.maxD;
   int k = ks;
-  for (; k + 3 <= ke; k += 4) {
-    uint32_t sv[4];
-    int64_t o = static_cast<int64_t>(k) * (k + 1) / 2;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      sv[u] = (jc <= k + u) ? S[o + jc] : 0u;
-      o += k + u + 1;
-    }
+  // eight rows per pass, the next pass's rows loaded before this pass's
+  // products (two passes of loads in flight)
+  uint32_t sv[8];
+  if (k + 7 <= ke) stir_rows8(S, k, jc, sv);
+  for (; k + 7 <= ke; k += 8) {
+    uint32_t nv[8];
+    if (k + 15 <= ke) stir_rows8(S, k + 8, jc, nv);
 #pragma unroll
     for (int m = 0; m < kStirGroupMax; ++m)
       if (act[m]) {
         const uint32_t* am = lds + m * K + (k - ks);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[m] = mac_fold(acc[m], am[u], sv[u], p);
+        for (int u = 0; u < 8; ++u) acc[m] = mac_fold(acc[m], am[u], sv[u], p);
       }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sv[u] = nv[u];
   }
   for (; k <= ke; ++k) {
     const int64_t o = static_cast<int64_t>(k) * (k + 1) / 2;
