@@ -193,7 +193,8 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       if (P.origin != 0) continue;
       for (int sl = 0; sl < P.np; ++sl) by_prime[P.pidx[sl]].push_back(StirMember{li, sl});
     }
-    const int gmax = std::max(1, std::min(kStirGroupMax, kLdsWords / Kc));
+    int gmax = kStirGroupMax;
+    while (gmax > 1 && stir_group_lds_words(Kc, gmax) > kLdsWords) --gmax;
     for (const auto& kv : by_prime) {
       const std::vector<StirMember>& mem = kv.second;
       for (size_t b = 0; b < mem.size(); b += gmax) {
@@ -205,11 +206,11 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
         }
         const int gi = static_cast<int>(J->sgroups.size());
         J->sgroups.push_back(G);
-        J->sg_lds = std::max<size_t>(J->sg_lds, static_cast<size_t>(G.count) * Kc * 4);
-        for (int jb = 0; jb < blocks_of(G.maxD + 1, 256); ++jb)
+        J->sg_lds = std::max<size_t>(J->sg_lds, static_cast<size_t>(stir_group_lds_words(Kc, G.count)) * 4);
+        for (int jb = 0; jb < blocks_of(G.maxD + 1, kStirGroupCols); ++jb)
           for (int ch = 0; ch * Kc <= G.maxD; ++ch) {
             const int ke = std::min(G.maxD, (ch + 1) * Kc - 1);
-            if (ke >= jb * 256) J->sg_items.push_back({gi, -1, jb, ch});
+            if (ke >= jb * kStirGroupCols) J->sg_items.push_back({gi, -1, jb, ch});
           }
       }
     }

@@ -103,7 +103,8 @@ __global__ __launch_bounds__(256) void k_interp_stir_group(const DevProblem* pro
 hipError_t launch_stir_group(const DevProblem* probs, const StirGroup* groups, const StirMember* members,
                              const WorkItem* items, int nitems, size_t lds, const DevTables& T, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_interp_stir_group, dim3(nitems), dim3(256), lds, st, probs, groups, members, items, T);
+  hipLaunchKernelGGL(k_interp_stir_group, dim3(nitems), dim3(64 * kStirGroupWaves), lds, st, probs, groups, members,
+                     items, T);
   return hipGetLastError();
 }
 

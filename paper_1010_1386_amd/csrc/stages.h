@@ -576,15 +576,23 @@ __device__ inline void stage_interp_stir(const DevProblem& P, const DevTables& T
 
 // The same basis change for every member of a prime group (problems that use
 // one prime): each table row is read once and multiplied into every member's
-// partial sums.  Item: (group, -, j-block, k-chunk); all members share the
-// chunk size (kchunk) and their rows k > D_m contribute zeros.
+// partial sums.  Item: (group, -, 64-column block, k-chunk); all members share
+// the chunk length (kchunk) and their rows k > D_m contribute zeros.  The four
+// waves of a block split the chunk's rows into four runs (short dependent
+// chains of table loads) and their partial sums are added in LDS.
+constexpr int kStirGroupCols = 64;
+constexpr int kStirGroupWaves = 4;
+__host__ __device__ inline int stir_group_lds_words(int K, int count) {
+  return count * K + 1 + kStirGroupWaves * count * kStirGroupCols * 2;
+}
+
 __device__ inline void stage_interp_stir_group(const DevProblem* probs, const StirGroup* groups,
                                                const StirMember* members, const DevTables& T, const WorkItem& w,
                                                uint32_t* lds) {
   const StirGroup G = groups[w.prob];
-  const int nt = blockDim.x;
-  const int j0 = w.blk * nt;
-  const int j = j0 + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j0 = w.blk * kStirGroupCols;
+  const int j = j0 + lane;
   const PrimeConst pc = T.pc[G.g];
   const uint32_t p = pc.p;
   const int K = probs[members[G.first].prob].kchunk;
@@ -592,7 +600,6 @@ __device__ inline void stage_interp_stir_group(const DevProblem* probs, const St
   const int ks = kb > j0 ? kb : j0;
   const int ke = (kb + K - 1 < G.maxD) ? kb + K - 1 : G.maxD;
   if (ks > ke) return;
-  const int nk = ke - ks + 1;
   // per member: its a_k for k in [ks, ke] (0 beyond its degree bound), or inactive
   bool act[kStirGroupMax];
 #pragma unroll
@@ -606,7 +613,7 @@ __device__ inline void stage_interp_stir_group(const DevProblem* probs, const St
       uint32_t* am = lds + m * K;
       const uint64_t* ap = P.aconv + static_cast<size_t>(M.slot) * (P.D + 1);
       const size_t astride = static_cast<size_t>(P.np) * (P.D + 1);
-      for (int k = ks + threadIdx.x; k <= ke; k += nt) {
+      for (int k = ks + static_cast<int>(threadIdx.x); k <= ke; k += blockDim.x) {
         uint32_t v = 0u;
         if (k <= P.D) {
           const int nch = k / P.cchunk + 1;
@@ -625,19 +632,22 @@ __device__ inline void stage_interp_stir_group(const DevProblem* probs, const St
     }
   }
   __syncthreads();
+  // this wave's run of rows
+  const int nk = ke - ks + 1;
+  const int per = (nk + kStirGroupWaves - 1) / kStirGroupWaves;
+  const int rb = ks + wave * per;
+  const int re = (rb + per - 1 < ke) ? rb + per - 1 : ke;
   const uint32_t* S = T.stir + static_cast<int64_t>(G.g) * T.sstride;
   uint64_t acc[kStirGroupMax];
 #pragma unroll
   for (int m = 0; m < kStirGroupMax; ++m) acc[m] = 0u;
   const int jc = j <= G.maxD ? j : G.maxD;
-  int k = ks;
-  // eight rows per pass, the next pass's rows loaded before this pass's
-  // products (two passes of loads in flight)
+  int k = rb;
   uint32_t sv[8];
-  if (k + 7 <= ke) stir_rows8(S, k, jc, sv);
-  for (; k + 7 <= ke; k += 8) {
+  if (k + 7 <= re) stir_rows8(S, k, jc, sv);
+  for (; k + 7 <= re; k += 8) {
     uint32_t nv[8];
-    if (k + 15 <= ke) stir_rows8(S, k + 8, jc, nv);
+    if (k + 15 <= re) stir_rows8(S, k + 8, jc, nv);
 #pragma unroll
     for (int m = 0; m < kStirGroupMax; ++m)
       if (act[m]) {
@@ -648,21 +658,31 @@ __device__ inline void stage_interp_stir_group(const DevProblem* probs, const St
 #pragma unroll
     for (int u = 0; u < 8; ++u) sv[u] = nv[u];
   }
-  for (; k <= ke; ++k) {
+  for (; k <= re; ++k) {
     const int64_t o = static_cast<int64_t>(k) * (k + 1) / 2;
-    const uint32_t sv = (jc <= k) ? S[o + jc] : 0u;
+    const uint32_t s1 = (jc <= k) ? S[o + jc] : 0u;
 #pragma unroll
     for (int m = 0; m < kStirGroupMax; ++m)
-      if (act[m]) acc[m] = mac_fold(acc[m], lds[m * K + (k - ks)], sv, p);
+      if (act[m]) acc[m] = mac_fold(acc[m], lds[m * K + (k - ks)], s1, p);
   }
+  // add the four waves' partial sums
+  uint64_t* red = reinterpret_cast<uint64_t*>(lds + G.count * K + ((G.count * K) & 1));
 #pragma unroll
   for (int m = 0; m < kStirGroupMax; ++m)
-    if (act[m]) {
-      const StirMember M = members[G.first + m];
-      const DevProblem& P = probs[M.prob];
-      if (j <= P.D) P.cpart[(static_cast<size_t>(w.sub) * P.np + M.slot) * (P.D + 1) + j] = acc[m];
-    }
-  (void)nk;
+    if (m < G.count) red[(wave * G.count + m) * kStirGroupCols + lane] = acc[m];
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int m = 0; m < kStirGroupMax; ++m)
+      if (act[m]) {
+        uint64_t t = red[m * kStirGroupCols + lane];
+#pragma unroll
+        for (int ww = 1; ww < kStirGroupWaves; ++ww) t = add_fold(t, red[(ww * G.count + m) * kStirGroupCols + lane], p);
+        const StirMember M = members[G.first + m];
+        const DevProblem& P = probs[M.prob];
+        if (j <= P.D) P.cpart[(static_cast<size_t>(w.sub) * P.np + M.slot) * (P.D + 1) + j] = t;
+      }
+  }
 }
 
 // LDS words of the gapped-interpolation block.
