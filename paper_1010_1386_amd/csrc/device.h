@@ -12,13 +12,21 @@ struct DevTables {
   const PrimeConst* pc;     // [g]
   const uint32_t* fact;     // [g * kstride + t] = t! R mod p_g          (t <= kcap)
   const uint32_t* ifact;    // [g * kstride + t] = (t!)^{-1} R mod p_g
-  const uint32_t* stir;     // [g * sstride + k(k+1)/2 + j] = s(k, j) R mod p_g  (k <= scap)
+  const uint32_t* stir;     // [g * sstride + stir_rowoff(k) + j] = s(k, j) R mod p_g  (k <= scap)
   int64_t sstride;
   int kstride;
   int kcap;                 // factorials available for t <= kcap
   int scap;                 // Stirling rows available for k <= scap
   int npcap;                // global prime indices < npcap
 };
+
+// Row k of the Stirling triangle (k + 1 entries) starts at a multiple of 32
+// words, so that 64-column segments of a row are whole 128-byte lines:
+//   stir_rowoff(k) = 32 sum_{i<k} ceil((i + 1) / 32) = 32 (a + 1)(16 a + b),  k = 32 a + b.
+__host__ __device__ inline int64_t stir_rowoff(int k) {
+  const int64_t a = k >> 5, b = k & 31;
+  return 32 * (a + 1) * (16 * a + b);
+}
 
 // Rows of the transposed residue tiles are padded to a multiple of this
 // (Horner evaluates this many rows at once from one LDS broadcast read).

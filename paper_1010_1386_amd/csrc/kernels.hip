@@ -77,7 +77,7 @@ __global__ __launch_bounds__(1024) void k_stirling_build(uint32_t* stir, int64_t
   __syncthreads();
   for (int k = 0; k < scap; ++k) {
     const uint32_t kt = mmul(static_cast<uint32_t>(k), pc.r2, pc.p, pc.pinv);
-    uint32_t* row = S + static_cast<int64_t>(k + 1) * (k + 2) / 2;
+    uint32_t* row = S + stir_rowoff(k + 1);
     for (int j = threadIdx.x; j <= k + 1; j += 1024) {
       const uint32_t left = (j > 0) ? cur[j - 1] : 0u;
       const uint32_t mid = (j <= k) ? cur[j] : 0u;

@@ -447,12 +447,8 @@ __device__ inline bool fast_prime(const DevProblem& P, int slot) {
 
 // Column j of Stirling rows k..k+7 (zero above the diagonal j <= k + u).
 __device__ __forceinline__ void stir_rows8(const uint32_t* S, int k, int j, uint32_t* v) {
-  int64_t o = static_cast<int64_t>(k) * (k + 1) / 2;
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    v[u] = (j <= k + u) ? S[o + j] : 0u;
-    o += k + u + 1;
-  }
+  for (int u = 0; u < 8; ++u) v[u] = (j <= k + u) ? S[stir_rowoff(k + u) + j] : 0u;
 }
 
 // Newton forward differences at 0..D as a convolution, one i-chunk of it:
@@ -568,7 +564,7 @@ __device__ inline void stage_interp_stir(const DevProblem& P, const DevTables& T
     for (int u = 0; u < 8; ++u) sv[u] = nv[u];
   }
   for (; k <= ke; ++k) {
-    const int64_t o = static_cast<int64_t>(k) * (k + 1) / 2;
+    const int64_t o = stir_rowoff(k);
     if (j <= k) c0 = mac_fold(c0, lds[k - ks], S[o + j], p);
   }
   if (j <= P.D) P.cpart[(static_cast<size_t>(w.sub) * P.np + w.slot) * (P.D + 1) + j] = add_fold(c0, c1, p);
@@ -659,7 +655,7 @@ __device__ inline void stage_interp_stir_group(const DevProblem* probs, const St
     for (int u = 0; u < 8; ++u) sv[u] = nv[u];
   }
   for (; k <= re; ++k) {
-    const int64_t o = static_cast<int64_t>(k) * (k + 1) / 2;
+    const int64_t o = stir_rowoff(k);
     const uint32_t s1 = (jc <= k) ? S[o + jc] : 0u;
 #pragma unroll
     for (int m = 0; m < kStirGroupMax; ++m)
