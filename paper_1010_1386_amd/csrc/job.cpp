@@ -106,6 +106,8 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     evk = 1;
     if (!all_regs)
       while (evk < 4 && all_pairs * evk < kLanesInFlight) evk *= 2;
+    else if (all_pairs < 2LL * 256 * 4 * 64)
+      evk = 2;  // one wave can issue only about half a SIMD's rate: give each SIMD two
   }
   // one chunk length K for the basis change of every problem, so that problems
   // sharing a prime can share the table reads; chunks of at least 128 rows
@@ -143,7 +145,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     d.evk = 1;
     while (d.evk < evk && std::min(P.my, P.ny) >= 4 * d.evk * 2) d.evk *= 2;
     d.evpb = 64 / d.evk;
-    d.regn = (d.evk == 1) ? regn_of(P) : 0;
+    d.regn = (d.evk <= 2) ? regn_of(P) : 0;
     d.crt_garner = (ctx && ctx->crt_garner) ? 1 : 0;
     d.cchunk = d.kchunk;  // same split for the convolution's input range
     d.ncchunk = d.nchunk;
@@ -178,6 +180,26 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       for (int sl = 0; sl < P.np; ++sl) J->items[kStageNewton].push_back({li, sl, 0, 0});
     for (int b = 0; b < blocks_of(P.D + 1, kCrtWaves); ++b) J->items[kStageCrt].push_back({li, -1, b, 0});
     for (int s = 0; s < kNumStages; ++s) L.item_end[s] = static_cast<int>(J->items[s].size());
+  }
+
+  // evaluation items by layout (stable: a problem's items stay together)
+  {
+    std::vector<WorkItem>& ev = J->items[kStageEval];
+    std::stable_sort(ev.begin(), ev.end(), [&](const WorkItem& a, const WorkItem& b) {
+      return eval_variant(J->dev[a.prob]) < eval_variant(J->dev[b.prob]);
+    });
+    for (int li = 0; li < nl; ++li) J->lay[li].item_begin[kStageEval] = J->lay[li].item_end[kStageEval] = -1;
+    J->eval_ranges.clear();
+    for (int t = 0; t < static_cast<int>(ev.size()); ++t) {
+      ProbLayout& L = J->lay[ev[t].prob];
+      if (L.item_begin[kStageEval] < 0) L.item_begin[kStageEval] = t;
+      L.item_end[kStageEval] = t + 1;
+      const int v = eval_variant(J->dev[ev[t].prob]);
+      if (J->eval_ranges.empty() || J->eval_ranges.back().variant != v) J->eval_ranges.push_back({v, t, t + 1});
+      else J->eval_ranges.back().end = t + 1;
+    }
+    for (int li = 0; li < nl; ++li)
+      if (J->lay[li].item_begin[kStageEval] < 0) J->lay[li].item_begin[kStageEval] = J->lay[li].item_end[kStageEval] = 0;
   }
 
   // prime groups for the basis change: the problems whose interpolation can take
@@ -319,8 +341,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   for (int li = 0; li < nl; ++li) {
     const DevProblem& d = J->dev[li];
     auto up = [&](int s, size_t words) { J->stage_lds[s] = std::max(J->stage_lds[s], words * 4); };
-    up(kStageEval, d.evk > 1 ? eval_group_lds_words(d, d.evk)
-                              : (d.regn ? eval_regs_lds_words(d, d.regn) : eval_lds_words(d)));
+    up(kStageEval, eval_stage_lds_words(d));
     up(kStageConv, static_cast<size_t>(std::min(d.cchunk, d.D + 1)) + std::min(d.D + 1, d.cchunk + 256));
     up(kStageStir, d.kchunk);
     if (J->lay[li].item_end[kStageNewton] > J->lay[li].item_begin[kStageNewton]) up(kStageNewton, newton_lds_words(d, 1024));
@@ -329,8 +350,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   J->persist_lds = 0;
   for (int li = 0; li < nl; ++li) {
     const DevProblem& d = J->dev[li];
-    size_t w = d.evk > 1 ? eval_group_lds_words(d, d.evk)
-                         : (d.regn ? eval_regs_lds_words(d, d.regn) : eval_lds_words(d));
+    size_t w = std::max(eval_group_lds_words(d, d.evk), eval_lds_words(d));  // no register form here
     w = std::max<size_t>(w, static_cast<size_t>(std::min(d.cchunk, d.D + 1)) + std::min(d.D + 1, d.cchunk + 64));
     w = std::max<size_t>(w, d.kchunk);
     if (J->lay[li].item_end[kStageNewton] > J->lay[li].item_begin[kStageNewton])
@@ -509,9 +529,10 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
       const int ns = (J->plans[J->live[li]].np + 63) / 64;
       for (int s = 0; s < kNumStages; ++s) {
         const int cnt = L.item_end[s] - L.item_begin[s];
-        if ((rc = hip_check(ctx, launch_stage(s, probs, items(s) + L.item_begin[s], cnt, J->stage_lds[s],
-                                              ns, T, st), "launch")))
-          return rc;
+        const hipError_t e = (s == kStageEval)
+            ? launch_eval(eval_variant(J->dev[li]), probs, items(s) + L.item_begin[s], cnt, J->stage_lds[s], T, st)
+            : launch_stage(s, probs, items(s) + L.item_begin[s], cnt, J->stage_lds[s], ns, T, st);
+        if ((rc = hip_check(ctx, e, "launch"))) return rc;
       }
     }
     return RSL_OK;
@@ -553,6 +574,13 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
   }
   for (int s = 0; s < kNumStages; ++s) {
     if (stage_events && (rc = hip_check(ctx, hipEventRecord(ctx->ev[s], st), "event"))) return rc;
+    if (s == kStageEval) {
+      for (const Job::EvalRange& r : J->eval_ranges)
+        if ((rc = hip_check(ctx, launch_eval(r.variant, probs, items(s) + r.begin, r.end - r.begin, J->stage_lds[s], T,
+                                             st), "launch")))
+          return rc;
+      continue;
+    }
     if (s == kStageStir && !J->sg_items.empty()) {
       if ((rc = hip_check(ctx, launch_stir_group(probs, reinterpret_cast<const StirGroup*>(J->base + J->sg_off),
                                                  reinterpret_cast<const StirMember*>(J->base + J->sm_off),

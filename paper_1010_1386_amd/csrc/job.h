@@ -36,6 +36,11 @@ struct Job {
   std::vector<ProbLayout> lay;     // per live problem
   std::vector<DevProblem> dev;     // per live problem (pointers valid for `base`)
   std::vector<WorkItem> items[kNumStages];
+  // evaluation items are ordered by layout: one launch per (variant, range)
+  struct EvalRange {
+    int variant, begin, end;
+  };
+  std::vector<EvalRange> eval_ranges;
   // basis change over prime groups (staged schedule)
   std::vector<StirGroup> sgroups;
   std::vector<StirMember> smembers;

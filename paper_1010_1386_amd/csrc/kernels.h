@@ -11,6 +11,10 @@ namespace rsl {
 hipError_t launch_stage(int stage, const DevProblem* probs, const WorkItem* items, int nitems, size_t lds,
                         int crt_ns, const DevTables& T, hipStream_t st);
 
+// Evaluation + univariate resultants of items that all have layout `variant`.
+hipError_t launch_eval(int variant, const DevProblem* probs, const WorkItem* items, int nitems, size_t lds,
+                       const DevTables& T, hipStream_t st);
+
 // Basis change over prime groups (problems sharing a prime share the table reads).
 hipError_t launch_stir_group(const DevProblem* probs, const StirGroup* groups, const StirMember* members,
                              const WorkItem* items, int nitems, size_t lds, const DevTables& T, hipStream_t st);

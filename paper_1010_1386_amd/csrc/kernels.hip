@@ -32,11 +32,33 @@ __global__ __launch_bounds__(256) void k_reduce(const DevProblem* probs, const W
   stage_reduce(probs[w.prob], T, w);
 }
 
+template <int V>
 __global__ __launch_bounds__(64) void k_eval_ures(const DevProblem* probs, const WorkItem* items, DevTables T) {
   extern __shared__ uint4 lds4[];  // 16-byte aligned: the Horner loop reads uint4 rows
   uint32_t* lds = reinterpret_cast<uint32_t*>(lds4);
   const WorkItem w = items[blockIdx.x];
-  stage_eval(probs[w.prob], T, w, lds);
+  stage_eval_variant<V>(probs[w.prob], T, w, lds);
+}
+
+hipError_t launch_eval(int variant, const DevProblem* probs, const WorkItem* items, int nitems, size_t lds,
+                       const DevTables& T, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  const dim3 g(nitems), b(64);
+  switch (variant) {
+    case kEvBase: hipLaunchKernelGGL(k_eval_ures<kEvBase>, g, b, lds, st, probs, items, T); break;
+    case kEvG2: hipLaunchKernelGGL(k_eval_ures<kEvG2>, g, b, lds, st, probs, items, T); break;
+    case kEvG4: hipLaunchKernelGGL(k_eval_ures<kEvG4>, g, b, lds, st, probs, items, T); break;
+    case kEvR8: hipLaunchKernelGGL(k_eval_ures<kEvR8>, g, b, lds, st, probs, items, T); break;
+    case kEvR16: hipLaunchKernelGGL(k_eval_ures<kEvR16>, g, b, lds, st, probs, items, T); break;
+    case kEvR24: hipLaunchKernelGGL(k_eval_ures<kEvR24>, g, b, lds, st, probs, items, T); break;
+    case kEvR32: hipLaunchKernelGGL(k_eval_ures<kEvR32>, g, b, lds, st, probs, items, T); break;
+    case kEvP8: hipLaunchKernelGGL(k_eval_ures<kEvP8>, g, b, lds, st, probs, items, T); break;
+    case kEvP16: hipLaunchKernelGGL(k_eval_ures<kEvP16>, g, b, lds, st, probs, items, T); break;
+    case kEvP24: hipLaunchKernelGGL(k_eval_ures<kEvP24>, g, b, lds, st, probs, items, T); break;
+    case kEvP32: hipLaunchKernelGGL(k_eval_ures<kEvP32>, g, b, lds, st, probs, items, T); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_interp_conv(const DevProblem* probs, const WorkItem* items, DevTables T) {
@@ -114,7 +136,7 @@ hipError_t launch_stage(int stage, const DevProblem* probs, const WorkItem* item
   const dim3 g(nitems);
   switch (stage) {
     case kStageReduce: hipLaunchKernelGGL(k_reduce, g, dim3(256), 0, st, probs, items, T); break;
-    case kStageEval: hipLaunchKernelGGL(k_eval_ures, g, dim3(64), lds, st, probs, items, T); break;
+    case kStageEval: return hipErrorInvalidValue;  // launch_eval: one kernel per layout
     case kStageConv: hipLaunchKernelGGL(k_interp_conv, g, dim3(256), lds, st, probs, items, T); break;
     case kStageStir: hipLaunchKernelGGL(k_interp_stir, g, dim3(256), lds, st, probs, items, T); break;
     case kStageNewton: hipLaunchKernelGGL(k_interp_newton, g, dim3(1024), lds, st, probs, items, T); break;

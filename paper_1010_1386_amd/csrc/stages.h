@@ -410,12 +410,168 @@ __device__ inline void stage_eval_ures_regs(const DevProblem& P, const DevTables
   eval_report_bad(P, w.slot, pt, live, bad);
 }
 
+// LDS words of a two-lanes-per-pair register-form block (32 pairs).
+__host__ __device__ inline int eval_regs2_lds_words(const DevProblem& P, int nmax) {
+  return P.CS + 2 * (nmax + 1) * 32;
+}
+
+// Exchange with the partner lane of a lane pair (lanes 2q and 2q + 1).
+struct PairSwap {
+  __device__ uint32_t operator()(uint32_t v) const {
+    return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(v), 0xB1 /* quad_perm 1,0,3,2 */, 0xF,
+                                                          0xF, false));
+  }
+};
+
+// One wave, two lanes per (prime, point) pair (32 pairs): lane l of pair q
+// evaluates rows j = 4 g + 2 r + l of every row group g and keeps row j in
+// element j / 2, then the pair runs ures_regs2.
+template <int NMAX>
+__device__ inline void stage_eval_ures_regs2(const DevProblem& P, const DevTables& T, const WorkItem& w,
+                                             uint32_t* lds) {
+  constexpr int N2 = RegPoly2<NMAX>::kN;
+  const int lane = threadIdx.x;
+  const int l = lane & 1, q = lane >> 1;
+  const PrimeConst pc = T.pc[P.pidx[w.slot]];
+  const uint32_t p = pc.p, pinv = pc.pinv;
+  uint32_t* tile = lds;
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(P.resid + static_cast<size_t>(w.slot) * P.CS);
+    uint4* dst = reinterpret_cast<uint4*>(tile);
+    for (int t = lane; t < P.CS / 4; t += 64) dst[t] = src[t];
+  }
+  __syncthreads();
+  uint32_t* cols = lds + P.CS;
+  const int pt = w.blk * 32 + q;
+  const uint32_t x = static_cast<uint32_t>(P.origin + (pt < P.E ? pt : P.E));
+  const uint32_t xt = mmul(x, pc.r2, p, pinv);
+
+  uint32_t X[N2], Y[N2];
+  const int gf = P.myp / kRowGroup, gg = P.nyp / kRowGroup;
+  const int ng = gf > gg ? gf : gg;
+  const uint32_t* ftile = tile;
+  const uint32_t* gtile = tile + P.goff;
+#pragma unroll
+  for (int g0 = 0; g0 < N2 / 2; g0 += 2) {
+    // two row groups: chains [group][f or g][r] for rows 4 (g0 + gi) + 2 r + l
+    int deg[2][2];
+    const uint32_t* base[2][2];
+    int top = -1;
+#pragma unroll
+    for (int gi = 0; gi < 2; ++gi) {
+      const int gq = g0 + gi;
+      deg[gi][0] = __builtin_amdgcn_readfirstlane((gq < gf) ? P.gdeg[gq] : -1);
+      deg[gi][1] = __builtin_amdgcn_readfirstlane((gq < gg) ? P.gdeg[gf + gq] : -1);
+      base[gi][0] = ftile + ((gq < gf) ? kRowGroup * gq : 0) + l;
+      base[gi][1] = gtile + ((gq < gg) ? kRowGroup * gq : 0) + l;
+      top = deg[gi][0] > top ? deg[gi][0] : top;
+      top = deg[gi][1] > top ? deg[gi][1] : top;
+    }
+    const int stride[2] = {P.myp, P.nyp};
+    uint32_t acc[2][2][2] = {};
+    if (g0 < ng) {
+      for (int i = top; i >= 0; --i) {
+        uint32_t c[2][2][2];
+#pragma unroll
+        for (int gi = 0; gi < 2; ++gi)
+#pragma unroll
+          for (int sfg = 0; sfg < 2; ++sfg) {
+            const bool on = i <= deg[gi][sfg];
+            const uint32_t* rowp = base[gi][sfg] + (on ? i : 0) * stride[sfg];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) c[gi][sfg][r] = on ? rowp[2 * r] : 0u;
+          }
+        uint64_t t[2][2][2];
+#pragma unroll
+        for (int gi = 0; gi < 2; ++gi)
+#pragma unroll
+          for (int sfg = 0; sfg < 2; ++sfg)
+#pragma unroll
+            for (int r = 0; r < 2; ++r) t[gi][sfg][r] = static_cast<uint64_t>(acc[gi][sfg][r]) * xt + c[gi][sfg][r];
+#pragma unroll
+        for (int gi = 0; gi < 2; ++gi)
+#pragma unroll
+          for (int sfg = 0; sfg < 2; ++sfg)
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+              const uint32_t mm = static_cast<uint32_t>(t[gi][sfg][r]) * pinv;
+              acc[gi][sfg][r] = static_cast<uint32_t>((t[gi][sfg][r] + static_cast<uint64_t>(mm) * p) >> 32);
+            }
+      }
+    }
+#pragma unroll
+    for (int gi = 0; gi < 2; ++gi)
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int k = 2 * (g0 + gi) + r;  // element: row 4 (g0 + gi) + 2 r + l
+        if (k < N2) {
+          const int j = 2 * k + l;
+          const uint32_t va = acc[gi][0][r], vb = acc[gi][1][r];
+          X[k] = (g0 + gi < gf && j <= P.my) ? umin32(va, va - p) : 0u;
+          Y[k] = (g0 + gi < gg && j <= P.ny) ? umin32(vb, vb - p) : 0u;
+        }
+      }
+  }
+  bool bad = false;
+  const uint32_t r = ures_regs2<NMAX>(X, Y, P.my, P.ny, l, pc, &bad, Column<32>{cols + q},
+                                      Column<32>{cols + (NMAX + 1) * 32 + q}, PairSwap(), WaveSync());
+  const bool live = pt <= P.E && l == 0;
+  if (live) {
+    const size_t o = static_cast<size_t>(w.slot) * (P.E + 1) + pt;
+    P.zval[o] = redc(r, p, pinv);
+    P.zbad[o] = bad ? 1 : 0;
+  }
+  eval_report_bad(P, w.slot, pt, live, bad);
+}
+
+// LDS words of the evaluation launch for the problem's layout.
+__host__ __device__ inline int eval_stage_lds_words(const DevProblem& P) {
+  if (P.evk == 2 && P.regn) return eval_regs2_lds_words(P, P.regn);
+  if (P.evk > 1) return eval_group_lds_words(P, P.evk);
+  return P.regn ? eval_regs_lds_words(P, P.regn) : eval_lds_words(P);
+}
+
+// Evaluation layouts; each has a kernel of its own (own register budget).
+enum : int {
+  kEvBase = 0,  // one lane per pair, LDS columns
+  kEvG2,        // two lanes per pair, LDS columns
+  kEvG4,        // four lanes per pair, LDS columns
+  kEvR8, kEvR16, kEvR24, kEvR32,  // one lane per pair, registers (degree bound)
+  kEvP8, kEvP16, kEvP24, kEvP32,  // two lanes per pair, registers
+  kEvNum
+};
+__host__ __device__ inline int eval_variant(const DevProblem& P) {
+  const int r = P.regn == 8 ? 0 : P.regn == 16 ? 1 : P.regn == 24 ? 2 : 3;
+  if (P.evk == 2 && P.regn) return kEvP8 + r;
+  if (P.evk == 2) return kEvG2;
+  if (P.evk == 4) return kEvG4;
+  if (P.regn) return kEvR8 + r;
+  return kEvBase;
+}
+template <int V>
+__device__ inline void stage_eval_variant(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
+  if constexpr (V == kEvBase) stage_eval_ures(P, T, w, lds);
+  else if constexpr (V == kEvG2) stage_eval_ures_group<2>(P, T, w, lds);
+  else if constexpr (V == kEvG4) stage_eval_ures_group<4>(P, T, w, lds);
+  else if constexpr (V >= kEvR8 && V <= kEvR32) stage_eval_ures_regs<8 * (V - kEvR8 + 1)>(P, T, w, lds);
+  else stage_eval_ures_regs2<8 * (V - kEvP8 + 1)>(P, T, w, lds);
+}
+
 // Dispatch on the problem's evaluation layout (block-uniform).  With
 // use_regs = false the register form is skipped (the LDS-column code computes
 // the same values), which keeps the register budget of a kernel that also
 // runs the other stages small.
 template <bool use_regs = true>
 __device__ inline void stage_eval(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
+  if (use_regs && P.evk == 2) {
+    switch (P.regn) {
+      case 8: stage_eval_ures_regs2<8>(P, T, w, lds); return;
+      case 16: stage_eval_ures_regs2<16>(P, T, w, lds); return;
+      case 24: stage_eval_ures_regs2<24>(P, T, w, lds); return;
+      case 32: stage_eval_ures_regs2<32>(P, T, w, lds); return;
+      default: break;
+    }
+  }
   switch (P.evk) {
     case 2: stage_eval_ures_group<2>(P, T, w, lds); return;
     case 4: stage_eval_ures_group<4>(P, T, w, lds); return;

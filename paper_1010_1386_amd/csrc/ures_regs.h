@@ -191,3 +191,203 @@ RSL_HD uint32_t ures_regs(uint32_t (&X)[RegPoly<NMAX>::kN], uint32_t (&Y)[RegPol
 }
 
 }  // namespace rsl
+
+namespace rsl {
+
+// The register form with two lanes per pair: lane l (0 or 1) keeps the
+// coefficients j = 2k + l of each polynomial in its element k.  Swap(v)
+// returns the partner lane's v (a lane-pair exchange on the device); every
+// scalar of the remainder sequence is formed identically in both lanes.
+template <int NMAX>
+struct RegPoly2 {
+  static constexpr int kN = RegPoly<NMAX>::kN / 2;  // elements per lane
+};
+
+// Coefficient j (compile time) as seen by both lanes.
+template <int J, int N, class Swap>
+RSL_HD uint32_t reg2_at(const uint32_t (&v)[N], int l, Swap swp) {
+  const uint32_t mine = v[J >> 1];
+  const uint32_t other = swp(mine);
+  return (l == (J & 1)) ? mine : other;
+}
+// Coefficient j (uniform run-time index) as seen by both lanes.
+template <int N, class Swap>
+RSL_HD uint32_t reg2_get(const uint32_t (&v)[N], int j, int l, Swap swp) {
+  const uint32_t mine = reg_get(v, j >> 1);
+  const uint32_t other = swp(mine);
+  return (l == (j & 1)) ? mine : other;
+}
+
+template <int BS, int N, class Swap>
+RSL_HD bool reg2_step(uint32_t (&A)[N], const uint32_t (&B)[N], int l, uint32_t p, uint32_t pinv, Swap swp,
+                      uint32_t* L_out, uint32_t* y_out) {
+  const uint32_t L = reg2_at<BS>(B, l, swp), lcA = reg2_at<BS + 1>(A, l, swp);
+  const uint32_t Ab = reg2_at<BS>(A, l, swp), Bb1 = reg2_at<BS - 1>(B, l, swp);
+  const uint32_t lcAt = mmulsub(L, Ab, lcA, Bb1, p, pinv);
+  const uint32_t alpha = mmul(L, L, p, pinv);
+  const uint32_t beta = mneg(mmul(L, lcA, p, pinv), p);
+  const uint32_t gamma = mneg(lcAt, p);
+  constexpr int KE = (BS - 1) / 2;  // last element updated (lane 1 may write R[BS], never read)
+  uint32_t bsw[KE + 1];
+#pragma unroll
+  for (int k = 0; k <= KE; ++k) bsw[k] = swp(B[k]);
+#pragma unroll
+  for (int k = 0; k <= KE; ++k) {
+    // B[j - 1] for j = 2k + l: lane 1 takes the partner's element k, lane 0 its element k - 1
+    const uint32_t prev = l ? bsw[k] : (k > 0 ? bsw[k - 1] : 0u);
+    A[k] = mmad3(alpha, A[k], beta, prev, gamma, B[k], p, pinv);
+  }
+  *L_out = L;
+  *y_out = alpha;
+  return reg2_at<BS - 1>(A, l, swp) != 0u;
+}
+
+template <int BS, int N>
+struct RegChain2 {
+  template <class Swap>
+  RSL_HD static void run(uint32_t (&X)[N], uint32_t (&Y)[N], int l, int b0, uint32_t p, uint32_t pinv, Swap swp,
+                         uint32_t& num, uint32_t& den, uint32_t& U, bool& slow, int& f_bs, uint32_t& f_L,
+                         uint32_t& f_y) {
+    if (BS <= b0 && !slow) {
+      uint32_t L, y;
+      const bool generic = (BS & 1) ? reg2_step<BS>(X, Y, l, p, pinv, swp, &L, &y)
+                                    : reg2_step<BS>(Y, X, l, p, pinv, swp, &L, &y);
+      if (generic) {
+        num = mmul(num, y, p, pinv);
+        U = mmul(U, y, p, pinv);
+        den = mmul(den, U, p, pinv);
+      } else {
+        slow = true;
+        f_bs = BS;
+        f_L = L;
+        f_y = y;
+      }
+    }
+    RegChain2<BS - 1, N>::run(X, Y, l, b0, p, pinv, swp, num, den, U, slow, f_bs, f_L, f_y);
+  }
+};
+template <int N>
+struct RegChain2<0, N> {
+  template <class Swap>
+  RSL_HD static void run(uint32_t (&)[N], uint32_t (&)[N], int, int, uint32_t, uint32_t, Swap, uint32_t&, uint32_t&,
+                         uint32_t&, bool&, int&, uint32_t&, uint32_t&) {}
+};
+
+// Res_{m,n}(A, B) by a lane pair: lane l holds A's coefficients j = 2k + l in
+// X[k] and B's in Y[k].  Both lanes return the result.  CA, CB: the pair's two
+// shared scratch columns (NMAX + 1 entries); lanes that leave the register
+// path write their halves there and lane 0 finishes with the column code
+// (sync() orders the two lanes' column writes before lane 0 reads them).
+template <int NMAX, class Col, class Swap, class Sync>
+RSL_HD uint32_t ures_regs2(uint32_t (&X)[RegPoly2<NMAX>::kN], uint32_t (&Y)[RegPoly2<NMAX>::kN], int m, int n,
+                           int l, const PrimeConst& pc, bool* bad, Col CA, Col CB, Swap swp, Sync sync) {
+  constexpr int N = RegPoly2<NMAX>::kN;
+  const uint32_t p = pc.p, pinv = pc.pinv, one = pc.r1;
+  const uint32_t lcf = reg2_get(X, m, l, swp), lcg = reg2_get(Y, n, l, swp);
+  *bad = (lcf == 0u) || (lcg == 0u);
+  const bool shape_ok = m >= 1 && n >= 1 && m <= NMAX && n <= NMAX && (m - n <= 1) && (n - m <= 1);
+  uint32_t neg = 0u, num = one, den = one, U = one;
+  bool slow = false;
+  int f_a = 0, f_b = 0, f_k = 0;
+  uint32_t f_L = 0, f_y = 0;
+  bool r_in_x = false;
+  bool fresh = !shape_ok || *bad;  // leave at once: the general code from the start
+  if (!fresh) {
+    if (m < n) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const uint32_t t = X[k];
+        X[k] = Y[k];
+        Y[k] = t;
+      }
+      neg = static_cast<uint32_t>(m * n) & 1u;
+      const int t = m;
+      m = n;
+      n = t;
+    }
+    bool a_in_x = true;
+    int b0;
+    if (m == n) {
+      const uint32_t L = reg2_get(Y, n, l, swp), lcA = reg2_get(X, n, l, swp);
+#pragma unroll
+      for (int k = 0; k < N; ++k) X[k] = (2 * k + l < n) ? mmulsub(L, X[k], lcA, Y[k], p, pinv) : 0u;
+      if (reg2_get(X, n - 1, l, swp) != 0u) {
+        neg ^= static_cast<uint32_t>(n * n) & 1u;
+        num = mmul(num, L, p, pinv);
+        U = mmul(U, L, p, pinv);
+        den = mmul(den, U, p, pinv);
+      } else {
+        slow = true;
+        f_a = n;
+        f_b = n;
+        f_k = 1;
+        f_L = L;
+        f_y = L;
+        r_in_x = true;
+      }
+      a_in_x = false;
+      b0 = n - 1;
+    } else {
+      b0 = n;
+    }
+    if (!slow && b0 >= 1) {
+      if (a_in_x != ((b0 & 1) != 0)) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          const uint32_t t = X[k];
+          X[k] = Y[k];
+          Y[k] = t;
+        }
+      }
+      int f_bs = 0;
+      RegChain2<NMAX - 1, N>::run(X, Y, l, b0, p, pinv, swp, num, den, U, slow, f_bs, f_L, f_y);
+      if (slow) {
+        f_a = f_bs + 1;
+        f_b = f_bs;
+        f_k = 2;
+        r_in_x = (f_bs & 1) != 0;
+      }
+    }
+    if (!slow) {
+      num = mmul(num, reg2_at<0>(X, l, swp), p, pinv);
+      const uint32_t r = mmul(num, minv(den, one, p, pinv), p, pinv);
+      return neg ? mneg(r, p) : r;
+    }
+  }
+  // leave the register path: both lanes write their halves of the two columns
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+    if (2 * k + l <= NMAX) {
+      if (fresh) {
+        CA[2 * k + l] = X[k];
+        CB[2 * k + l] = Y[k];
+      } else {
+        CA[2 * k + l] = r_in_x ? X[k] : Y[k];  // R
+        CB[2 * k + l] = r_in_x ? Y[k] : X[k];  // B
+      }
+    }
+  sync();
+  uint32_t r = 0u;
+  if (l == 0) {
+    if (fresh) {
+      bool b2 = false;
+      r = ures_formal(CA, CB, m, n, pc, &b2);
+    } else {
+      int c = f_b - 1;
+      while (c >= 0 && CA[c] == 0u) --c;
+      if (c >= 0) {
+        neg ^= static_cast<uint32_t>(f_a * f_b) & 1u;
+        const int delta = f_b - c;
+        const int enum_ = f_k - 1 + delta;
+        num = mmul(num, mpow(f_L, static_cast<uint32_t>(enum_), one, p, pinv), p, pinv);
+        U = mmul(U, f_y, p, pinv);
+        den = mmul(den, mpow(U, static_cast<uint32_t>(delta), one, p, pinv), p, pinv);
+        r = ures_run(CB, CA, UresState{f_b, c, num, den, U, neg}, pc);
+      }
+    }
+  }
+  const uint32_t ro = swp(r);
+  return l == 0 ? r : ro;
+}
+
+}  // namespace rsl

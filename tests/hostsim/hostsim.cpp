@@ -47,6 +47,12 @@ int regs_run(const PrimeConst& pc, int m, int n, const uint32_t* A, const uint32
   return 0;
 }
 
+// Two lane threads of the pair form: the swap is an exchange through two
+// slots between barriers, as the lanes of a pair exchange registers.
+template <int NMAX>
+int regs2_run(const PrimeConst& pc, int m, int n, const uint32_t* A, const uint32_t* B, uint32_t* out, int* bad,
+              int* agree);
+
 template <int K>
 uint32_t group_run(const PrimeConst& pc, int m, int n, std::vector<uint32_t>& a, std::vector<uint32_t>& b,
                    bool* bad, int* agree) {
@@ -66,9 +72,58 @@ uint32_t group_run(const PrimeConst& pc, int m, int n, std::vector<uint32_t>& a,
   return r[0];
 }
 
+template <int NMAX>
+int regs2_run(const PrimeConst& pc, int m, int n, const uint32_t* A, const uint32_t* B, uint32_t* out, int* bad,
+              int* agree) {
+  constexpr int N2 = RegPoly2<NMAX>::kN;
+  Barrier bar(2);
+  uint32_t slot[2] = {0, 0};
+  std::vector<uint32_t> ca(2 * N2 + 64, 0), cb(2 * N2 + 64, 0);
+  uint32_t r[2];
+  bool bd[2];
+  std::vector<std::thread> th;
+  for (int l = 0; l < 2; ++l)
+    th.emplace_back([&, l] {
+      uint32_t X[N2] = {}, Y[N2] = {};
+      for (int k = 0; k < N2; ++k) {
+        const int j = 2 * k + l;
+        if (j <= m) X[k] = mmul(A[j] % pc.p, pc.r2, pc.p, pc.pinv);
+        if (j <= n) Y[k] = mmul(B[j] % pc.p, pc.r2, pc.p, pc.pinv);
+      }
+      auto swp = [&](uint32_t v) {
+        slot[l] = v;
+        bar.wait();
+        const uint32_t o = slot[1 - l];
+        bar.wait();
+        return o;
+      };
+      r[l] = ures_regs2<NMAX>(X, Y, m, n, l, pc, &bd[l], Column<1>{ca.data()}, Column<1>{cb.data()}, swp,
+                              [&] { bar.wait(); });
+    });
+  for (auto& t : th) t.join();
+  *agree = (r[0] == r[1] && bd[0] == bd[1]) ? 1 : 0;
+  *out = redc(r[0], pc.p, pc.pinv);
+  *bad = bd[0];
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
+
+// The two-lanes-per-pair register form, run by two host threads.
+int hs_ures_regs2(int nmax, uint32_t p, int m, int n, const uint32_t* A, const uint32_t* B, uint32_t* out, int* bad,
+                  int* agree) {
+  PrimeConst pc = make_prime_const(p);
+  if (m > nmax || n > nmax) return -1;
+  switch (nmax) {
+    case 8: return regs2_run<8>(pc, m, n, A, B, out, bad, agree);
+    case 16: return regs2_run<16>(pc, m, n, A, B, out, bad, agree);
+    case 24: return regs2_run<24>(pc, m, n, A, B, out, bad, agree);
+    case 32: return regs2_run<32>(pc, m, n, A, B, out, bad, agree);
+    default: return -1;
+  }
+}
 
 // The register form (ures_regs<NMAX>) of the same resultant; m, n <= NMAX.
 int hs_ures_regs(int nmax, uint32_t p, int m, int n, const uint32_t* A, const uint32_t* B, uint32_t* out,

@@ -39,6 +39,8 @@ def hs():
                             ctypes.POINTER(ctypes.c_int), ctypes.c_uint32, u32p]
     lib.hs_ures_regs.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p, u32p, u32p,
                                  ctypes.POINTER(ctypes.c_int)]
+    lib.hs_ures_regs2.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p, u32p, u32p,
+                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     lib.hs_ures_group.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p, u32p, u32p,
                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     return lib
@@ -52,7 +54,12 @@ def ures(hs, p, A, B, K=1):
     b = (ctypes.c_uint32 * len(B))(*B)
     out = ctypes.c_uint32()
     bad = ctypes.c_int()
-    if isinstance(K, str):
+    if isinstance(K, str) and K.startswith("pair"):
+        nmax = int(K[4:])
+        agree = ctypes.c_int()
+        assert hs.hs_ures_regs2(nmax, p, m, n, a, b, ctypes.byref(out), ctypes.byref(bad), ctypes.byref(agree)) == 0
+        assert agree.value == 1, "the two lanes of the pair disagree"
+    elif isinstance(K, str):
         nmax = int(K[4:])
         assert hs.hs_ures_regs(nmax, p, m, n, a, b, ctypes.byref(out), ctypes.byref(bad)) == 0
     elif K == 1:
@@ -64,7 +71,7 @@ def ures(hs, p, A, B, K=1):
     return out.value, bool(bad.value)
 
 
-KS = [1, 2, 4, 8, "regs16"]
+KS = [1, 2, 4, 8, "regs16", "pair16"]
 
 
 def sylvester_det_mod(A, B, p):
@@ -103,7 +110,7 @@ def test_random_generic(hs, seed, K):
     assert got == sylvester_det_mod(A, B, p)
 
 
-@pytest.mark.parametrize("K", [1, 2, 4, 8, "regs32"])
+@pytest.mark.parametrize("K", [1, 2, 4, 8, "regs32", "pair32"])
 @pytest.mark.parametrize("seed", range(6))
 def test_random_large_degree(hs, seed, K):
     """Degrees 13..40: every lane of a group runs several four-way fused updates."""
@@ -172,9 +179,10 @@ def test_eval_rows(hs, seed):
         assert out[j] == poly_eval_mod(row, x, p)
 
 
+@pytest.mark.parametrize("form", ["regs", "pair"])
 @pytest.mark.parametrize("nmax", [8, 16, 24, 32])
 @pytest.mark.parametrize("seed", range(40))
-def test_register_form_shapes(hs, nmax, seed):
+def test_register_form_shapes(hs, form, nmax, seed):
     """The register form on its own shapes (|m - n| <= 1, generic and with planted
     degree drops, vanishing leading coefficients and common factors) and on
     shapes it hands to the general code."""
@@ -197,6 +205,6 @@ def test_register_form_shapes(hs, nmax, seed):
         B[-1] = B[-1] or 1
     if kind == 3:  # a vanishing leading coefficient
         A[-1] = 0
-    got, bad = ures(hs, p, A, B, "regs%d" % nmax)
+    got, bad = ures(hs, p, A, B, "%s%d" % (form, nmax))
     assert got == sylvester_det_mod(A, B, p), (m, n, kind)
     assert bad == (A[-1] == 0 or B[-1] == 0)
