@@ -83,6 +83,29 @@ __device__ __forceinline__ void horner_step8(uint32_t* a, uint32_t* b, const uin
   b[3] = static_cast<uint32_t>((t7 + static_cast<uint64_t>(m7) * p) >> 32);
 }
 
+// Two and four chains of the same lazy Horner step (lane-pair layout).
+__device__ __forceinline__ void horner_step2(uint32_t* a, uint32_t c0, uint32_t c1, uint32_t xt, uint32_t p,
+                                             uint32_t pinv) {
+  const uint64_t t0 = static_cast<uint64_t>(a[0]) * xt + c0;
+  const uint64_t t1 = static_cast<uint64_t>(a[1]) * xt + c1;
+  const uint32_t m0 = static_cast<uint32_t>(t0) * pinv, m1 = static_cast<uint32_t>(t1) * pinv;
+  a[0] = static_cast<uint32_t>((t0 + static_cast<uint64_t>(m0) * p) >> 32);
+  a[1] = static_cast<uint32_t>((t1 + static_cast<uint64_t>(m1) * p) >> 32);
+}
+__device__ __forceinline__ void horner_step2x2(uint32_t* a, uint32_t* b, uint32_t c0, uint32_t c1, uint32_t d0,
+                                               uint32_t d1, uint32_t xt, uint32_t p, uint32_t pinv) {
+  const uint64_t t0 = static_cast<uint64_t>(a[0]) * xt + c0;
+  const uint64_t t1 = static_cast<uint64_t>(a[1]) * xt + c1;
+  const uint64_t t2 = static_cast<uint64_t>(b[0]) * xt + d0;
+  const uint64_t t3 = static_cast<uint64_t>(b[1]) * xt + d1;
+  const uint32_t m0 = static_cast<uint32_t>(t0) * pinv, m1 = static_cast<uint32_t>(t1) * pinv;
+  const uint32_t m2 = static_cast<uint32_t>(t2) * pinv, m3 = static_cast<uint32_t>(t3) * pinv;
+  a[0] = static_cast<uint32_t>((t0 + static_cast<uint64_t>(m0) * p) >> 32);
+  a[1] = static_cast<uint32_t>((t1 + static_cast<uint64_t>(m1) * p) >> 32);
+  b[0] = static_cast<uint32_t>((t2 + static_cast<uint64_t>(m2) * p) >> 32);
+  b[1] = static_cast<uint32_t>((t3 + static_cast<uint64_t>(m3) * p) >> 32);
+}
+
 // ------------------------------------------------------------------ reduce
 
 // Coefficient t of the prime's transposed tile: f part [i][j] (j padded to
@@ -103,11 +126,23 @@ __device__ inline void stage_reduce(const DevProblem& P, const DevTables& T, con
   uint32_t v = 0;
   if (in >= 0) {
     const uint32_t* wd = P.coeff + static_cast<size_t>(in) * P.L_in;
-    // two's complement value mod p, top limb signed; -2^31 + 2p > 0 since p > 2^30
+    // two's complement value mod p without divisions: the signed top limb plus
+    // 2p lies in (0, 4p) since 2^30 < p < 2^31; each lower limb w (< 4p) enters
+    // as r <- r 2^32 + w, with r 2^32 mod p = mmul(r, R^2)
     const int32_t top = static_cast<int32_t>(wd[P.L_in - 1]);
-    uint64_t r = static_cast<uint64_t>(static_cast<int64_t>(top) + 2 * static_cast<int64_t>(pc.p)) % pc.p;
-    for (int l = P.L_in - 2; l >= 0; --l) r = ((r << 32) | wd[l]) % pc.p;
-    v = mmul(static_cast<uint32_t>(r), pc.r3, pc.p, pc.pinv);
+    const uint32_t p = pc.p;
+    uint64_t x = static_cast<uint64_t>(static_cast<int64_t>(top) + 2 * static_cast<int64_t>(p));  // < 4p
+    x = (x >= 2ull * p) ? x - 2ull * p : x;
+    x = (x >= p) ? x - p : x;
+    uint32_t r = static_cast<uint32_t>(x);
+    for (int l = P.L_in - 2; l >= 0; --l) {
+      uint32_t wl = wd[l];
+      wl = umin32(wl, wl - p);
+      wl = umin32(wl, wl - p);
+      wl = umin32(wl, wl - p);
+      r = maddm(mmul(r, pc.r2, p, pc.pinv), wl, p);
+    }
+    v = mmul(r, pc.r3, p, pc.pinv);
   }
   P.resid[static_cast<size_t>(w.slot) * P.CS + t] = v;
 }
@@ -451,66 +486,52 @@ __device__ inline void stage_eval_ures_regs2(const DevProblem& P, const DevTable
   const int ng = gf > gg ? gf : gg;
   const uint32_t* ftile = tile;
   const uint32_t* gtile = tile + P.goff;
+  // one row group per pass (rows 4 g + l and 4 g + 2 + l of f and of g: four
+  // chains): first the steps where only the higher-degree polynomial's rows
+  // are nonzero, then all four chains with the next row's values prefetched
 #pragma unroll
-  for (int g0 = 0; g0 < N2 / 2; g0 += 2) {
-    // two row groups: chains [group][f or g][r] for rows 4 (g0 + gi) + 2 r + l
-    int deg[2][2];
-    const uint32_t* base[2][2];
-    int top = -1;
-#pragma unroll
-    for (int gi = 0; gi < 2; ++gi) {
-      const int gq = g0 + gi;
-      deg[gi][0] = __builtin_amdgcn_readfirstlane((gq < gf) ? P.gdeg[gq] : -1);
-      deg[gi][1] = __builtin_amdgcn_readfirstlane((gq < gg) ? P.gdeg[gf + gq] : -1);
-      base[gi][0] = ftile + ((gq < gf) ? kRowGroup * gq : 0) + l;
-      base[gi][1] = gtile + ((gq < gg) ? kRowGroup * gq : 0) + l;
-      top = deg[gi][0] > top ? deg[gi][0] : top;
-      top = deg[gi][1] > top ? deg[gi][1] : top;
-    }
-    const int stride[2] = {P.myp, P.nyp};
-    uint32_t acc[2][2][2] = {};
-    if (g0 < ng) {
-      for (int i = top; i >= 0; --i) {
-        uint32_t c[2][2][2];
-#pragma unroll
-        for (int gi = 0; gi < 2; ++gi)
-#pragma unroll
-          for (int sfg = 0; sfg < 2; ++sfg) {
-            const bool on = i <= deg[gi][sfg];
-            const uint32_t* rowp = base[gi][sfg] + (on ? i : 0) * stride[sfg];
-#pragma unroll
-            for (int r = 0; r < 2; ++r) c[gi][sfg][r] = on ? rowp[2 * r] : 0u;
-          }
-        uint64_t t[2][2][2];
-#pragma unroll
-        for (int gi = 0; gi < 2; ++gi)
-#pragma unroll
-          for (int sfg = 0; sfg < 2; ++sfg)
-#pragma unroll
-            for (int r = 0; r < 2; ++r) t[gi][sfg][r] = static_cast<uint64_t>(acc[gi][sfg][r]) * xt + c[gi][sfg][r];
-#pragma unroll
-        for (int gi = 0; gi < 2; ++gi)
-#pragma unroll
-          for (int sfg = 0; sfg < 2; ++sfg)
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-              const uint32_t mm = static_cast<uint32_t>(t[gi][sfg][r]) * pinv;
-              acc[gi][sfg][r] = static_cast<uint32_t>((t[gi][sfg][r] + static_cast<uint64_t>(mm) * p) >> 32);
-            }
-      }
-    }
-#pragma unroll
-    for (int gi = 0; gi < 2; ++gi)
-#pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        const int k = 2 * (g0 + gi) + r;  // element: row 4 (g0 + gi) + 2 r + l
-        if (k < N2) {
-          const int j = 2 * k + l;
-          const uint32_t va = acc[gi][0][r], vb = acc[gi][1][r];
-          X[k] = (g0 + gi < gf && j <= P.my) ? umin32(va, va - p) : 0u;
-          Y[k] = (g0 + gi < gg && j <= P.ny) ? umin32(vb, vb - p) : 0u;
+  for (int gq = 0; gq < N2 / 2; ++gq) {
+    uint32_t a[2] = {0u, 0u}, b[2] = {0u, 0u};
+    if (gq < ng) {
+      const int df = __builtin_amdgcn_readfirstlane((gq < gf) ? P.gdeg[gq] : -1);
+      const int dg = __builtin_amdgcn_readfirstlane((gq < gg) ? P.gdeg[gf + gq] : -1);
+      const uint32_t* fq = ftile + kRowGroup * (gq < gf ? gq : 0) + l;
+      const uint32_t* gqp = gtile + kRowGroup * (gq < gg ? gq : 0) + l;
+      const int dboth = df < dg ? df : dg;
+      int i = df > dg ? df : dg;
+      for (; i > dboth; --i) {
+        if (i <= df) {
+          const uint32_t* fr = fq + i * P.myp;
+          horner_step2(a, fr[0], fr[2], xt, p, pinv);
+        } else {
+          const uint32_t* gr = gqp + i * P.nyp;
+          horner_step2(b, gr[0], gr[2], xt, p, pinv);
         }
       }
+      if (i >= 0) {
+        const uint32_t* fr = fq + i * P.myp;
+        const uint32_t* gr = gqp + i * P.nyp;
+        uint32_t f0 = fr[0], f1 = fr[2], g0 = gr[0], g1 = gr[2];
+        for (; i > 0; --i) {
+          const uint32_t* fn = fq + (i - 1) * P.myp;
+          const uint32_t* gn = gqp + (i - 1) * P.nyp;
+          const uint32_t nf0 = fn[0], nf1 = fn[2], ng0 = gn[0], ng1 = gn[2];
+          horner_step2x2(a, b, f0, f1, g0, g1, xt, p, pinv);
+          f0 = nf0;
+          f1 = nf1;
+          g0 = ng0;
+          g1 = ng1;
+        }
+        horner_step2x2(a, b, f0, f1, g0, g1, xt, p, pinv);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int k = 2 * gq + r;  // element: row 4 gq + 2 r + l
+      const int j = 2 * k + l;
+      X[k] = (gq < gf && j <= P.my) ? umin32(a[r], a[r] - p) : 0u;
+      Y[k] = (gq < gg && j <= P.ny) ? umin32(b[r], b[r] - p) : 0u;
+    }
   }
   bool bad = false;
   const uint32_t r = ures_regs2<NMAX>(X, Y, P.my, P.ny, l, pc, &bad, Column<32>{cols + q},
@@ -1010,26 +1031,46 @@ __device__ inline void crt_radix(const DevProblem& P, int k, bool valid, const u
     hc[r] = 0u;
   }
   int j = 0;
-  for (; j + 4 <= np; j += 4) {
-    const uint32_t v0 = vbuf[j], v1 = vbuf[j + 1], v2 = vbuf[j + 2], v3 = vbuf[j + 3];
-    const uint32_t* p0 = tab + static_cast<size_t>(j) * tstride;
+  {
+    // four independent 96-bit accumulators per limb (short dependency chains),
+    // added together afterwards
+    uint64_t lo4[NS][3];
+    uint32_t hc4[NS][3];
 #pragma unroll
-    for (int r = 0; r < NS; ++r) {
-      const int t = lane + 64 * r;
-      if (t < L) {
-        const uint32_t w0 = p0[t], w1 = p0[tstride + t], w2 = p0[2 * tstride + t], w3 = p0[3 * tstride + t];
-        const uint64_t q0 = static_cast<uint64_t>(v0) * w0, q1 = static_cast<uint64_t>(v1) * w1;
-        const uint64_t q2 = static_cast<uint64_t>(v2) * w2, q3 = static_cast<uint64_t>(v3) * w3;
-        lo[r] += q0;
-        hc[r] += (lo[r] < q0) ? 1u : 0u;
-        lo[r] += q1;
-        hc[r] += (lo[r] < q1) ? 1u : 0u;
-        lo[r] += q2;
-        hc[r] += (lo[r] < q2) ? 1u : 0u;
-        lo[r] += q3;
-        hc[r] += (lo[r] < q3) ? 1u : 0u;
+    for (int r = 0; r < NS; ++r)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        lo4[r][a] = 0u;
+        hc4[r][a] = 0u;
+      }
+    for (; j + 4 <= np; j += 4) {
+      const uint32_t v0 = vbuf[j], v1 = vbuf[j + 1], v2 = vbuf[j + 2], v3 = vbuf[j + 3];
+      const uint32_t* p0 = tab + static_cast<size_t>(j) * tstride;
+#pragma unroll
+      for (int r = 0; r < NS; ++r) {
+        const int t = lane + 64 * r;
+        if (t < L) {
+          const uint32_t w0 = p0[t], w1 = p0[tstride + t], w2 = p0[2 * tstride + t], w3 = p0[3 * tstride + t];
+          const uint64_t q0 = static_cast<uint64_t>(v0) * w0, q1 = static_cast<uint64_t>(v1) * w1;
+          const uint64_t q2 = static_cast<uint64_t>(v2) * w2, q3 = static_cast<uint64_t>(v3) * w3;
+          lo[r] += q0;
+          hc[r] += (lo[r] < q0) ? 1u : 0u;
+          lo4[r][0] += q1;
+          hc4[r][0] += (lo4[r][0] < q1) ? 1u : 0u;
+          lo4[r][1] += q2;
+          hc4[r][1] += (lo4[r][1] < q2) ? 1u : 0u;
+          lo4[r][2] += q3;
+          hc4[r][2] += (lo4[r][2] < q3) ? 1u : 0u;
+        }
       }
     }
+#pragma unroll
+    for (int r = 0; r < NS; ++r)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        lo[r] += lo4[r][a];
+        hc[r] += hc4[r][a] + ((lo[r] < lo4[r][a]) ? 1u : 0u);
+      }
   }
   for (; j < np; ++j) {
     const uint32_t vj = vbuf[j];
