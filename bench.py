@@ -147,6 +147,49 @@ def serve_bench(n):
                              "p99_ms": float(np.percentile(lat_plain, 99))}}
 
 
+def batch_bench(steps, warmup):
+    """512 independent pairs (total degrees 6..32, 8..64-bit coefficients, half
+    30%-sparse), res_y of all: the autotuned batched schedule against one
+    pipeline per problem, both on resident inputs, results compared bit for bit."""
+    import torch
+    import paper_1010_1386_amd as rsl
+    import workloads
+
+    pairs = workloads.config4()
+    probs = [(f, g, "y") for f, g in pairs]
+    ctx = rsl.Context(0, workspace_bytes=1 << 30)
+    job = ctx.job(probs)
+    tune = job.tune(reps=2)
+    job.run("auto")
+    got = job.results()
+    job.run("plain")
+    if job.results() != got:
+        print("bench: batched and plain results differ", file=sys.stderr)
+        sys.exit(1)
+    steps = max(1, min(steps, 20))
+
+    def timed(mode):
+        for _ in range(max(1, warmup // 10)):
+            job.run(mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            job.run(mode)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    tb = timed("auto")
+    tp = timed("plain")
+    info = job.info()
+    job.close()
+    ctx.close()
+    return {"workload": "batch of 512 pairs, total degrees 6..32, 8..64-bit coefficients, half 30% sparse; res_y",
+            "problems": len(probs), "mod_p_pairs": info["pairs"], "steps": steps,
+            "batched_resultants_per_s": len(probs) / tb, "batched_ms": tb * 1e3,
+            "plain_resultants_per_s": len(probs) / tp, "plain_ms": tp * 1e3, "batched_vs_plain": tp / tb,
+            "modp_univariate_resultants_per_s": info["pairs"] / tb, "tune": tune, "verified_batched_eq_plain": True}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +201,8 @@ def main():
                     help="auto: autotune the job first; otherwise that schedule with the default layout")
     ap.add_argument("--serve", type=int, default=0, metavar="N",
                     help="serving benchmark instead: N Poisson-arriving requests of the serving workload")
+    ap.add_argument("--batch512", action="store_true",
+                    help="batch benchmark instead: 512 pairs (res_y), autotuned schedule vs one pipeline per problem")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
     a = ap.parse_args()
@@ -182,6 +227,9 @@ def main():
     if a.serve:
         print(json.dumps(serve_bench(a.serve)))
         return
+    if a.batch512:
+        print(json.dumps(batch_bench(a.steps, a.warmup)))
+        return
 
     f, g = workloads.config2()
     problems = [(f, g, "y"), (f, g, "x")]
@@ -196,6 +244,8 @@ def main():
         tune = {"mode": a.schedule, "chunk_target": 4096, "grid_mult": 1, "lanes_per_pair": None,
                 "candidates": 0, "ms": None, "ms_worst": None}
     mode = tune["mode"]
+    info = job.info()  # the layout actually used
+    tune["lanes_per_pair"] = info["eval_lanes"]
 
     # correctness gate: bit-exact against the oracle's stored digests
     job.run(mode)
@@ -274,6 +324,16 @@ def main():
         kernel, launch_ms = "eval_ures", stages["eval_ures"]
     ures_ms = staged_split["eval_ures"]
     dominant = max(staged_split, key=staged_split.get)
+    # HBM bytes per launch of the dominant kernel, from the committed counter
+    # summary of the same kernel sources and layout (None when either changed)
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic_eval_ures_cfg2_pair.json")
+    if mode != "batched" and os.path.exists(tpath):
+        from paper_1010_1386_amd.traffic import traffic_bytes
+        with open(tpath) as fh:
+            trec = json.load(fh)
+        if trec.get("lanes_per_pair") == tune.get("lanes_per_pair"):
+            traffic = traffic_bytes(trec)
     roofline = {
         "bound": "alu",
         "kernel": kernel,
@@ -281,7 +341,8 @@ def main():
         "peak": PEAK_TMULMOD,
         "unit": "Tmulmod/s",
         "frac": mulmods / (launch_ms * 1e-3) / 1e12 / PEAK_TMULMOD,
-        "traffic": None,
+        "traffic": traffic,
+        "traffic_unit": "bytes per launch",
         "mulmods_per_launch": mulmods,
         "launch_ms": launch_ms,
     }

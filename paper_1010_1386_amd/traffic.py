@@ -1,0 +1,94 @@
+"""HBM traffic of a kernel from rocprofv3 counter runs.
+
+Two ``rocprofv3 --pmc`` runs of the same command give FETCH_SIZE and
+WRITE_SIZE (KiB per dispatch); two more runs of ``bench.py
+--copy-calibration BYTES`` give the same counters for a plain device copy of
+known size, from which the counters' scale factors follow.  ``summarize``
+turns the four CSV directories into one JSON record (per-dispatch bytes for
+the kernels whose name starts with a prefix, the factors, and a hash of the
+kernel sources the counters belong to); ``traffic_bytes`` gives the scaled
+bytes per launch, or None when the sources have changed since.
+
+Usage:
+    python -m paper_1010_1386_amd.traffic FETCH_DIR WRITE_DIR COPYF_DIR COPYW_DIR \\
+        KERNEL_PREFIX GRID COPY_BYTES OUT.json
+"""
+
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("stages.h", "ures.h", "ures_regs.h", "modarith.h", "device.h", "kernels.hip")
+
+
+def sources_sha256():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(PKG, "csrc", name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def _per_dispatch(directory, prefix, grid=None):
+    paths = glob.glob(os.path.join(directory, "*counter_collection.csv"))
+    if not paths:
+        raise FileNotFoundError(f"no counter_collection.csv under {directory}")
+    vals = []
+    with open(paths[0]) as fh:
+        for row in csv.DictReader(fh):
+            name = row["Kernel_Name"].replace("void ", "")
+            if name.startswith(prefix) and (grid is None or row["Grid_Size"] == str(grid)):
+                vals.append(float(row["Counter_Value"]))
+    if not vals:
+        raise ValueError(f"no dispatch of {prefix!r} (grid {grid}) in {paths[0]}")
+    return sum(vals) / len(vals)
+
+
+def summarize(fetch_dir, write_dir, copyf_dir, copyw_dir, prefix, grid, copy_bytes):
+    fetch_kib = _per_dispatch(fetch_dir, prefix, grid)
+    write_kib = _per_dispatch(write_dir, prefix, grid)
+    copy_fetch_kib = _per_dispatch(copyf_dir, "__amd_rocclr_copyBuffer")
+    copy_write_kib = _per_dispatch(copyw_dir, "__amd_rocclr_copyBuffer")
+    return {
+        "kernel_prefix": prefix,
+        "grid_size": grid,
+        "fetch_kib_per_dispatch": fetch_kib,
+        "write_kib_per_dispatch": write_kib,
+        "copy_bytes": copy_bytes,
+        "copy_fetch_kib": copy_fetch_kib,
+        "copy_write_kib": copy_write_kib,
+        # a plain copy of copy_bytes reads and writes copy_bytes each
+        "fetch_factor": copy_bytes / 1024.0 / copy_fetch_kib,
+        "write_factor": copy_bytes / 1024.0 / copy_write_kib,
+        "sources_sha256": sources_sha256(),
+    }
+
+
+def traffic_bytes(record):
+    """Scaled HBM bytes per launch, or None if the kernel sources changed."""
+    if record.get("sources_sha256") != sources_sha256():
+        return None
+    return 1024.0 * (record["fetch_kib_per_dispatch"] * record["fetch_factor"] +
+                     record["write_kib_per_dispatch"] * record["write_factor"])
+
+
+def main(argv):
+    if len(argv) != 9:
+        print(__doc__, file=sys.stderr)
+        return 2
+    rec = summarize(argv[1], argv[2], argv[3], argv[4], argv[5], argv[6], int(argv[7]))
+    with open(argv[8], "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(rec))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv))
