@@ -182,24 +182,59 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     for (int s = 0; s < kNumStages; ++s) L.item_end[s] = static_cast<int>(J->items[s].size());
   }
 
-  // evaluation items by layout (stable: a problem's items stay together)
+  // evaluation items by layout (stable: a problem's items stay together, as
+  // the one-pipeline-per-problem schedule needs)
   {
     std::vector<WorkItem>& ev = J->items[kStageEval];
     std::stable_sort(ev.begin(), ev.end(), [&](const WorkItem& a, const WorkItem& b) {
       return eval_variant(J->dev[a.prob]) < eval_variant(J->dev[b.prob]);
     });
     for (int li = 0; li < nl; ++li) J->lay[li].item_begin[kStageEval] = J->lay[li].item_end[kStageEval] = -1;
-    J->eval_ranges.clear();
     for (int t = 0; t < static_cast<int>(ev.size()); ++t) {
       ProbLayout& L = J->lay[ev[t].prob];
       if (L.item_begin[kStageEval] < 0) L.item_begin[kStageEval] = t;
       L.item_end[kStageEval] = t + 1;
-      const int v = eval_variant(J->dev[ev[t].prob]);
-      if (J->eval_ranges.empty() || J->eval_ranges.back().variant != v) J->eval_ranges.push_back({v, t, t + 1});
-      else J->eval_ranges.back().end = t + 1;
     }
     for (int li = 0; li < nl; ++li)
       if (J->lay[li].item_begin[kStageEval] < 0) J->lay[li].item_begin[kStageEval] = J->lay[li].item_end[kStageEval] = 0;
+    // the staged launches take the same items dealt so that all blocks of one
+    // (problem, prime) run on the same XCD: workgroup i of a launch goes to
+    // XCD i mod 8, so the prime's coefficient tile is fetched into one L2
+    // instead of eight
+    constexpr int kXcds = 8;
+    J->eval_staged.clear();
+    J->eval_ranges.clear();
+    size_t b0 = 0;
+    while (b0 < ev.size()) {
+      size_t b1 = b0;
+      const int v = eval_variant(J->dev[ev[b0].prob]);
+      while (b1 < ev.size() && eval_variant(J->dev[ev[b1].prob]) == v) ++b1;
+      std::vector<std::vector<WorkItem>> bins(kXcds);
+      int pairs_seen = -1, last_prob = -1, last_slot = -1;
+      for (size_t t = b0; t < b1; ++t) {
+        if (ev[t].prob != last_prob || ev[t].slot != last_slot) {
+          ++pairs_seen;
+          last_prob = ev[t].prob;
+          last_slot = ev[t].slot;
+        }
+        bins[pairs_seen % kXcds].push_back(ev[t]);
+      }
+      std::vector<size_t> pos(kXcds, 0);
+      for (size_t t = b0; t < b1; ++t) {
+        int x = static_cast<int>((t - b0) % kXcds);
+        if (pos[x] >= bins[x].size()) {  // bin x is empty: take from the fullest
+          size_t best = 0;
+          for (int y = 0; y < kXcds; ++y)
+            if (bins[y].size() - pos[y] > best) {
+              best = bins[y].size() - pos[y];
+              x = y;
+            }
+        }
+        J->eval_staged.push_back(bins[x][pos[x]++]);
+      }
+      J->eval_ranges.push_back({v, static_cast<int>(b0), static_cast<int>(b1)});
+      b0 = b1;
+    }
   }
 
   // prime groups for the basis change: the problems whose interpolation can take
@@ -247,6 +282,8 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     J->items_off[s] = o;
     o = align_up(o + sizeof(WorkItem) * J->items[s].size(), A);
   }
+  J->evs_off = o;
+  o = align_up(o + sizeof(WorkItem) * J->eval_staged.size(), A);
   J->sg_off = o;
   o = align_up(o + sizeof(StirGroup) * J->sgroups.size(), A);
   J->sm_off = o;
@@ -468,6 +505,8 @@ void job_bind(Job* J, uint8_t* base) {
   for (int s = 0; s < kNumStages; ++s)
     if (!J->items[s].empty())
       std::memcpy(blob + J->items_off[s], J->items[s].data(), sizeof(WorkItem) * J->items[s].size());
+  if (!J->eval_staged.empty())
+    std::memcpy(blob + J->evs_off, J->eval_staged.data(), sizeof(WorkItem) * J->eval_staged.size());
   if (!J->sgroups.empty()) {
     std::memcpy(blob + J->sg_off, J->sgroups.data(), sizeof(StirGroup) * J->sgroups.size());
     std::memcpy(blob + J->sm_off, J->smembers.data(), sizeof(StirMember) * J->smembers.size());
@@ -575,9 +614,10 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
   for (int s = 0; s < kNumStages; ++s) {
     if (stage_events && (rc = hip_check(ctx, hipEventRecord(ctx->ev[s], st), "event"))) return rc;
     if (s == kStageEval) {
+      const WorkItem* evs = reinterpret_cast<const WorkItem*>(J->base + J->evs_off);
       for (const Job::EvalRange& r : J->eval_ranges)
-        if ((rc = hip_check(ctx, launch_eval(r.variant, probs, items(s) + r.begin, r.end - r.begin, J->stage_lds[s], T,
-                                             st), "launch")))
+        if ((rc = hip_check(ctx, launch_eval(r.variant, probs, evs + r.begin, r.end - r.begin, J->stage_lds[s], T, st),
+                            "launch")))
           return rc;
       continue;
     }

@@ -40,7 +40,9 @@ struct Job {
   struct EvalRange {
     int variant, begin, end;
   };
-  std::vector<EvalRange> eval_ranges;
+  std::vector<EvalRange> eval_ranges;  // ranges of eval_staged
+  std::vector<WorkItem> eval_staged;   // evaluation items dealt across XCDs
+  size_t evs_off = 0;
   // basis change over prime groups (staged schedule)
   std::vector<StirGroup> sgroups;
   std::vector<StirMember> smembers;

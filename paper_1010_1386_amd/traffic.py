@@ -24,7 +24,7 @@ import os
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("stages.h", "ures.h", "ures_regs.h", "modarith.h", "device.h", "kernels.hip")
+KERNEL_SOURCES = ("stages.h", "ures.h", "ures_regs.h", "modarith.h", "device.h", "kernels.hip", "job.cpp")
 
 
 def sources_sha256():
