@@ -232,13 +232,14 @@ typedef struct {
   int32_t chunk_target;  /* interpolation blocks kept in flight */
   int32_t grid_mult;     /* persistent workgroups per resident slot */
   int32_t evk;           /* lanes per (prime, point) pair in evaluation: 1, 2 or 4 */
+  int32_t conv_whole;    /* 1: convolution sums taken whole, 0: split like the basis change */
   int32_t candidates;    /* candidates timed */
   double ms;             /* device time of one run of the chosen schedule */
   double ms_worst;       /* device time of the slowest candidate */
 } rsl_tune_result;
 
 int rsl_job_tune(rsl_ctx *ctx, rsl_job *job, int reps, rsl_tune_result *best);
-/* Save / load the tuning cache as text lines "key mode chunk_target grid_mult evk ms". */
+/* Save / load the tuning cache as text lines "key mode chunk_target grid_mult evk conv_whole ms". */
 int rsl_tune_save(rsl_ctx *ctx, const char *path);
 int rsl_tune_load(rsl_ctx *ctx, const char *path);
 

@@ -87,7 +87,8 @@ class rsl_job_info(ctypes.Structure):
 
 class rsl_tune_result(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("chunk_target", ctypes.c_int32), ("grid_mult", ctypes.c_int32),
-                ("evk", ctypes.c_int32), ("candidates", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("evk", ctypes.c_int32), ("conv_whole", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("ms", ctypes.c_double),
                 ("ms_worst", ctypes.c_double)]
 
 
@@ -418,7 +419,8 @@ class Job:
         self.ctx._check(rc, "rsl_job_tune")
         names = {RSL_STAGED: "staged", RSL_BATCHED: "batched"}
         return {"mode": names.get(r.mode, r.mode), "chunk_target": r.chunk_target, "grid_mult": r.grid_mult,
-                "lanes_per_pair": r.evk, "candidates": r.candidates, "ms": r.ms, "ms_worst": r.ms_worst}
+                "lanes_per_pair": r.evk, "conv_whole": r.conv_whole, "candidates": r.candidates, "ms": r.ms,
+                "ms_worst": r.ms_worst}
 
     def info(self):
         i = rsl_job_info()

@@ -21,6 +21,7 @@ struct TuneConfig {
   int chunk_target = 4096;    // interpolation blocks to keep in flight (sets the k-/i-chunking)
   int grid_mult = 1;          // persistent launch: workgroups = grid_mult x resident capacity
   int evk = 0;                // lanes per (prime, point) pair in evaluation; 0 = from the job size
+  int conv_whole = 0;         // 1: the convolution sums each coefficient whole (no i-chunks)
 };
 struct TuneEntry {
   TuneConfig cfg;

@@ -147,8 +147,9 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     d.evpb = 64 / d.evk;
     d.regn = (d.evk <= 2) ? regn_of(P) : 0;
     d.crt_garner = (ctx && ctx->crt_garner) ? 1 : 0;
-    d.cchunk = d.kchunk;  // same split for the convolution's input range
-    d.ncchunk = d.nchunk;
+    // the convolution's input range: the basis change's chunking, or whole
+    d.cchunk = J->tune.conv_whole ? P.D + 1 : d.kchunk;
+    d.ncchunk = (P.D + 1 + d.cchunk - 1) / d.cchunk;
     J->crt_ns = std::max(J->crt_ns, (P.np + 63) / 64);
     J->pairs += static_cast<int64_t>(P.np) * (P.E + 1);
     J->mulmods += pair_mulmods(P) * P.np * (P.E + 1);

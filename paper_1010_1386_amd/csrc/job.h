@@ -81,7 +81,8 @@ void job_bind(Job* J, uint8_t* base);
 // pinned host memory that stays untouched until the copy is done), or through
 // the context's staging buffer when pinned is null.
 int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st, uint8_t* pinned = nullptr);
-// Zero the status words (before a re-run of a resident job).
+// Zero the status words before a persistent run (the staged and plain launches
+// clear them in their reduce stage).
 int job_reset(rsl_ctx* ctx, Job* J, hipStream_t st);
 // Launch the device pipeline: RSL_PLAIN (per problem), RSL_STAGED (one launch per
 // stage over all problems) or RSL_BATCHED (one persistent launch).

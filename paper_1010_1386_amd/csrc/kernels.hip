@@ -29,7 +29,7 @@ static_assert(kCrtWaves == kCrtBlockCoeffs, "one coefficient per wave of a CRT b
 
 __global__ __launch_bounds__(256) void k_reduce(const DevProblem* probs, const WorkItem* items, DevTables T) {
   const WorkItem w = items[blockIdx.x];
-  stage_reduce(probs[w.prob], T, w);
+  stage_reduce(probs[w.prob], T, w, true);
 }
 
 template <int V>

@@ -110,7 +110,12 @@ __device__ __forceinline__ void horner_step2x2(uint32_t* a, uint32_t* b, uint32_
 
 // Coefficient t of the prime's transposed tile: f part [i][j] (j padded to
 // myp), then g part [i][j] (j padded to nyp).  Stores c R^2 mod p (0 for padding).
-__device__ inline void stage_reduce(const DevProblem& P, const DevTables& T, const WorkItem& w) {
+// With zero_status, the block of (slot 0, block 0) also clears the problem's
+// status words (a launch that runs before every other stage of the problem).
+__device__ inline void stage_reduce(const DevProblem& P, const DevTables& T, const WorkItem& w,
+                                    bool zero_status = false) {
+  if (zero_status && w.slot == 0 && w.blk == 0)
+    for (int i = threadIdx.x; i < 2 * P.np + 2; i += blockDim.x) P.status[i] = 0;
   const int t = w.blk * blockDim.x + threadIdx.x;
   if (t >= P.CS) return;
   const PrimeConst pc = T.pc[P.pidx[w.slot]];

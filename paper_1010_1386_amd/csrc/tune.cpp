@@ -127,7 +127,8 @@ static int capture(rsl_ctx* ctx, rsl_job* j, int mode) {
   int rc;
   if ((rc = hip_check(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal), "begin capture")))
     return rc;
-  int rc_launch = job_reset(ctx, &j->J, ctx->stream);
+  // the staged and plain launches clear the statuses in their reduce stage
+  int rc_launch = (mode == RSL_BATCHED) ? job_reset(ctx, &j->J, ctx->stream) : RSL_OK;
   if (!rc_launch) rc_launch = job_launch(ctx, &j->J, mode, ctx->stream, false);
   hipGraph_t g = nullptr;
   if ((rc = hip_check(ctx, hipStreamEndCapture(ctx->stream, &g), "end capture"))) return rc;
@@ -152,7 +153,7 @@ static int run_job(rsl_ctx* ctx, rsl_job* j, int mode) {
     if (j->graph_gen[mode] != ctx->table_gen && (rc = capture(ctx, j, mode))) return rc;
     return hip_check(ctx, hipGraphLaunch(j->graph[mode], ctx->stream), "graph launch");
   }
-  if ((rc = job_reset(ctx, &j->J, ctx->stream))) return rc;
+  if (mode == RSL_BATCHED && (rc = job_reset(ctx, &j->J, ctx->stream))) return rc;
   if (ctx->profiling && mode != RSL_PLAIN) {
     hipEvent_t* ev = next_evset(ctx);
     if (!ev) return fail(ctx, RSL_EDEVICE, "hipEventCreate");
@@ -279,14 +280,14 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   if (ctx->poisoned) return RSL_EDEVICE;
   if (j->J.live.empty()) {
-    if (best) *best = rsl_tune_result{RSL_STAGED, j->J.tune.chunk_target, 1, 1, 0, 0.0, 0.0};
+    if (best) *best = rsl_tune_result{RSL_STAGED, j->J.tune.chunk_target, 1, 1, 0, 0, 0.0, 0.0};
     return RSL_OK;
   }
   // coordinate search: schedule x lanes per pair at the default chunking, then
   // the chunking (and the persistent grid) around the best of those
   std::vector<TuneConfig> cands;
   for (int evk : {1, 2, 4})
-    for (int mode : {RSL_STAGED, RSL_BATCHED}) cands.push_back(TuneConfig{mode, 4096, 1, evk});
+    for (int mode : {RSL_STAGED, RSL_BATCHED}) cands.push_back(TuneConfig{mode, 4096, 1, evk, 0});
   const size_t phase1 = cands.size();
   std::vector<uint8_t> ref;
   TuneConfig win = cands[0];
@@ -294,8 +295,9 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
   int rc;
   for (size_t ci = 0; ci < cands.size(); ++ci) {
     if (ci == phase1) {
-      for (int target : {1024, 16384}) cands.push_back(TuneConfig{win.mode, target, 1, win.evk});
-      if (win.mode == RSL_BATCHED) cands.push_back(TuneConfig{RSL_BATCHED, 4096, 2, win.evk});
+      for (int target : {1024, 16384}) cands.push_back(TuneConfig{win.mode, target, 1, win.evk, 0});
+      cands.push_back(TuneConfig{win.mode, 4096, 1, win.evk, 1});
+      if (win.mode == RSL_BATCHED) cands.push_back(TuneConfig{RSL_BATCHED, 4096, 2, win.evk, 0});
     }
     const TuneConfig tc = cands[ci];
     if ((rc = materialize(ctx, j, tc))) return rc;
@@ -343,7 +345,7 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
   }
   if ((rc = materialize(ctx, j, win))) return rc;
   ctx->tune_cache[tune_key(j->J)] = TuneEntry{win, win_ms};
-  if (best) *best = rsl_tune_result{win.mode, win.chunk_target, win.grid_mult, win.evk,
+  if (best) *best = rsl_tune_result{win.mode, win.chunk_target, win.grid_mult, win.evk, win.conv_whole,
                                     static_cast<int32_t>(cands.size()), win_ms, worst_ms};
   return RSL_OK;
 }
@@ -355,7 +357,8 @@ int rsl_tune_save(rsl_ctx* ctx, const char* path) {
   if (!os) return fail(ctx, RSL_EINVAL, std::string("cannot write ") + path);
   for (const auto& kv : ctx->tune_cache)
     os << kv.first << " " << kv.second.cfg.mode << " " << kv.second.cfg.chunk_target << " "
-       << kv.second.cfg.grid_mult << " " << kv.second.cfg.evk << " " << kv.second.ms << "\n";
+       << kv.second.cfg.grid_mult << " " << kv.second.cfg.evk << " " << kv.second.cfg.conv_whole << " "
+       << kv.second.ms << "\n";
   return RSL_OK;
 }
 
@@ -366,9 +369,10 @@ int rsl_tune_load(rsl_ctx* ctx, const char* path) {
   if (!is) return fail(ctx, RSL_EINVAL, std::string("cannot read ") + path);
   std::string key;
   TuneEntry e;
-  while (is >> key >> e.cfg.mode >> e.cfg.chunk_target >> e.cfg.grid_mult >> e.cfg.evk >> e.ms) {
+  while (is >> key >> e.cfg.mode >> e.cfg.chunk_target >> e.cfg.grid_mult >> e.cfg.evk >> e.cfg.conv_whole >> e.ms) {
     if ((e.cfg.mode != RSL_STAGED && e.cfg.mode != RSL_BATCHED) || e.cfg.chunk_target < 64 || e.cfg.grid_mult < 1 ||
-        e.cfg.grid_mult > 8 || (e.cfg.evk != 1 && e.cfg.evk != 2 && e.cfg.evk != 4))
+        e.cfg.grid_mult > 8 || (e.cfg.evk != 1 && e.cfg.evk != 2 && e.cfg.evk != 4) ||
+        (e.cfg.conv_whole != 0 && e.cfg.conv_whole != 1))
       return fail(ctx, RSL_EINVAL, "malformed tuning cache line for " + key);
     ctx->tune_cache[key] = e;
   }

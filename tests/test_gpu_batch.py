@@ -93,7 +93,7 @@ def test_autotuner_keeps_bits_and_caches_choice(ctx, tmp_path):
     ctx.tune_save(str(path))
     lines = path.read_text().split("\n")
     assert len([l for l in lines if l.strip()]) == 1
-    key, mode, target, gm, evk, ms = lines[0].split()
+    key, mode, target, gm, evk, cw, ms = lines[0].split()
     assert int(mode) in (1, 2) and int(target) >= 64 and int(gm) >= 1 and int(evk) in (1, 2, 4)
     import paper_1010_1386_amd as rsl
     c2 = rsl.Context(device=0, workspace_bytes=256 << 20)
@@ -103,7 +103,7 @@ def test_autotuner_keeps_bits_and_caches_choice(ctx, tmp_path):
     assert j2.results() == want
     j2.close()
     bad = tmp_path / "bad.txt"
-    bad.write_text(key + " 7 4096 1 1 1.0\n")
+    bad.write_text(key + " 7 4096 1 1 0 1.0\n")
     with pytest.raises(rsl.RSLError):
         c2.tune_load(str(bad))
     c2.close()
