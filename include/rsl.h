@@ -169,6 +169,17 @@ int rsl_res_y(rsl_ctx *ctx, const rsl_poly *f, const rsl_poly *g, rsl_result *ou
 int rsl_res_x(rsl_ctx *ctx, const rsl_poly *f, const rsl_poly *g, rsl_result *out);
 
 /*
+ * Both projections of one system, R^(y) = res(f, g, y) into out_y and
+ * R^(x) = res(f, g, x) into out_x (the solver needs both, paper Sec. 3), as
+ * one job whose stage launches carry both problems (and share the
+ * basis-change table reads where the two use the same primes).  Synchronous
+ * like rsl_res; opts (may be NULL) applies to both; returns the first nonzero
+ * status of the two.
+ */
+int rsl_res_xy(rsl_ctx *ctx, const rsl_poly *f, const rsl_poly *g, const rsl_opts *opts, rsl_result *out_y,
+               rsl_result *out_x);
+
+/*
  * A batch of n independent problems (f[k], g[k], var[k]) -> out[k].
  * mode RSL_PLAIN runs one pipeline per problem on the context stream;
  * RSL_BATCHED plans all problems together and runs them in one persistent

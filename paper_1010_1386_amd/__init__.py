@@ -103,6 +103,7 @@ _SIGS = {
     "rsl_res": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), ctypes.c_int, _P(rsl_opts), _P(rsl_result)]),
     "rsl_res_y": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), _P(rsl_result)]),
     "rsl_res_x": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), _P(rsl_result)]),
+    "rsl_res_xy": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), _P(rsl_opts), _P(rsl_result), _P(rsl_result)]),
     "rsl_batch": (ctypes.c_int, [_vp, ctypes.c_int, _P(rsl_poly), _P(rsl_poly), _P(ctypes.c_int),
                                  _P(rsl_result), _P(ctypes.c_int), ctypes.c_int]),
     "rsl_last_counters": (ctypes.c_int, [_vp, _P(rsl_counters)]),
@@ -302,6 +303,22 @@ class Context:
     def res_x(self, f, g):
         return self.res(f, g, "x")
 
+    def res_xy(self, f, g, **opts):
+        """(res(f, g, y), res(f, g, x)) computed as one job."""
+        pf, pg = _as_poly(f), _as_poly(g)
+        o = _opts(**opts)
+        outs = []
+        for v in (RSL_Y, RSL_X):
+            info = rsl_info()
+            self._check(_lib.rsl_query(ctypes.byref(pf.c), ctypes.byref(pg.c), v, ctypes.byref(info)), "rsl_query")
+            lim = info.out_limbs + (1 if o.extra_primes else 0) + o.extra_primes
+            outs.append(_Result(max(info.D, 0), max(1, lim)))
+        with self.lock:
+            rc = _lib.rsl_res_xy(self.h, ctypes.byref(pf.c), ctypes.byref(pg.c), ctypes.byref(o),
+                                 ctypes.byref(outs[0].c), ctypes.byref(outs[1].c))
+        self._check(rc, "rsl_res_xy")
+        return outs[0].value(), outs[1].value()
+
     def batch(self, problems, mode="batched"):
         """problems: list of (f, g, var); returns a list of results (lists of ints)."""
         n = len(problems)
@@ -461,6 +478,10 @@ def res_y(f, g):
 
 def res_x(f, g):
     return res(f, g, "x")
+
+
+def res_xy(f, g, **opts):
+    return default_context().res_xy(f, g, **opts)
 
 
 def batch(problems, mode="batched"):

@@ -352,6 +352,26 @@ int rsl_res_x(rsl_ctx* ctx, const rsl_poly* f, const rsl_poly* g, rsl_result* ou
   return rsl_res(ctx, f, g, RSL_X, nullptr, out);
 }
 
+int rsl_res_xy(rsl_ctx* ctx, const rsl_poly* f, const rsl_poly* g, const rsl_opts* opts, rsl_result* out_y,
+               rsl_result* out_x) {
+  if (!ctx || !f || !g || !out_y || !out_x) return RSL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  if (ctx->poisoned) return RSL_EDEVICE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, RSL_EDEVICE, "hipSetDevice");
+  ctx->err.clear();
+  const double t0 = now_ms();
+  const rsl_poly fs[2] = {*f, *f}, gs[2] = {*g, *g};
+  const int var[2] = {RSL_Y, RSL_X};
+  rsl_result out[2] = {*out_y, *out_x};
+  rsl_counters cnt{};
+  int rc = run_in_workspace(ctx, 2, fs, gs, var, opts, out, nullptr, RSL_AUTO, &cnt);
+  *out_y = out[0];
+  *out_x = out[1];
+  cnt.ms_total = now_ms() - t0;
+  ctx->last = cnt;
+  return rc;
+}
+
 int rsl_batch(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var, rsl_result* out,
               int* status, int mode) {
   if (!ctx || n < 0 || (n > 0 && (!f || !g || !var || !out))) return RSL_EINVAL;

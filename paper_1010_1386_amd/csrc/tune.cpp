@@ -294,11 +294,6 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
   double win_ms = 1e300, worst_ms = 0.0;
   int rc;
   for (size_t ci = 0; ci < cands.size(); ++ci) {
-    if (ci == phase1) {
-      for (int target : {1024, 16384}) cands.push_back(TuneConfig{win.mode, target, 1, win.evk, 0});
-      cands.push_back(TuneConfig{win.mode, 4096, 1, win.evk, 1});
-      if (win.mode == RSL_BATCHED) cands.push_back(TuneConfig{RSL_BATCHED, 4096, 2, win.evk, 0});
-    }
     const TuneConfig tc = cands[ci];
     if ((rc = materialize(ctx, j, tc))) return rc;
     // warm-up run (also the correctness check), then `reps` timed runs
@@ -341,6 +336,11 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
     if (per < win_ms) {
       win_ms = per;
       win = tc;
+    }
+    if (ci + 1 == phase1) {  // phase two around the winner of phase one
+      for (int target : {1024, 16384}) cands.push_back(TuneConfig{win.mode, target, 1, win.evk, 0});
+      cands.push_back(TuneConfig{win.mode, 4096, 1, win.evk, 1});
+      if (win.mode == RSL_BATCHED) cands.push_back(TuneConfig{RSL_BATCHED, 4096, 2, win.evk, 0});
     }
   }
   if ((rc = materialize(ctx, j, win))) return rc;

@@ -220,3 +220,15 @@ def test_crt_direct_form_equals_garner(ctx, monkeypatch):
     for mode in ("staged", "batched"):
         assert cg.batch(probs, mode=mode) == ctx.batch(probs, mode=mode), mode
     cg.close()
+
+
+def test_both_projections_in_one_call(ctx):
+    """res_xy gives R^(y) and R^(x) of one system, equal to the separate calls
+    and to the oracle."""
+    rng = rng_for(715, 0)
+    for k in range(4):
+        f = dense_total(rng, 3 + k, 20)
+        g = sparse_total(rng, 4 + k, 16) if k % 2 else dense_total(rng, 2 + k, 30)
+        ry, rx = ctx.res_xy(f, g)
+        assert ry == ctx.res(f, g, "y") and rx == ctx.res(f, g, "x")
+        assert ry == oracle.res(f, g, "y") and rx == oracle.res(f, g, "x")
