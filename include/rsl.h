@@ -37,7 +37,11 @@ extern "C" {
 
 /* ----------------------------------------------------------------- codes */
 #define RSL_OK 0
-#define RSL_EINVAL (-1)   /* null pointer, negative dims, limbs < 1, bad var/mode  */
+#define RSL_EINVAL (-1)   /* null pointer, negative dims, limbs < 1, bad var/mode;
+                             a problem beyond the supported sizes: more than 512
+                             primes, more than 3800 points, degree in the
+                             eliminated variable above 255, or more than 256
+                             primes in the persistent schedule             */
 #define RSL_ERANGE (-2)   /* output buffer too small: nothing written              */
 #define RSL_ENOMEM (-3)   /* workspace or budget smaller than the footprint        */
 #define RSL_EPRIMES (-4)  /* prime table exhausted (too many bad primes)           */

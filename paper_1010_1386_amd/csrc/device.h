@@ -94,6 +94,7 @@ struct StirGroup {
   int maxD;    // largest degree bound among the members
 };
 constexpr int kStirGroupMax = 8;
+constexpr int kMaxPrimes = 512;  // primes per problem (CRT: 8 slots per lane)
 
 // status[0] error bits
 enum : int {

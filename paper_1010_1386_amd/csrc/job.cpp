@@ -41,7 +41,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     int rc = make_plan(&f[k], &g[k], var[k], opts, &J->plans[k], &e);
     if (!rc && !J->plans[k].zero) {
       const Plan& P = J->plans[k];
-      if (P.np > 256) { rc = RSL_EINVAL; e = "more than 256 primes needed (coefficients too large)"; }
+      if (P.np > kMaxPrimes) { rc = RSL_EINVAL; e = "more than 512 primes needed (coefficients too large)"; }
       else if (P.E > 3800) { rc = RSL_EINVAL; e = "more than 3800 evaluation points needed (degree bound too large)"; }
       else if (std::max(P.my, P.ny) > 255) { rc = RSL_EINVAL; e = "degree in the eliminated variable above 255"; }
     }
@@ -120,6 +120,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     Kc = std::max<int>(128, static_cast<int>((dmax + nch - 1) / nch));
   }
   J->crt_ns = 1;
+  J->max_np = 0;
   for (int li = 0; li < nl; ++li) {
     const Plan& P = J->plans[J->live[li]];
     DevProblem& d = J->dev[li];
@@ -151,9 +152,12 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     d.cchunk = J->tune.conv_whole ? P.D + 1 : d.kchunk;
     d.ncchunk = (P.D + 1 + d.cchunk - 1) / d.cchunk;
     J->crt_ns = std::max(J->crt_ns, (P.np + 63) / 64);
+    J->max_np = std::max(J->max_np, P.np);
     J->pairs += static_cast<int64_t>(P.np) * (P.E + 1);
     J->mulmods += pair_mulmods(P) * P.np * (P.E + 1);
   }
+
+  if (J->crt_ns == 5 || J->crt_ns == 7) ++J->crt_ns;  // CRT kernels exist for 1-4, 6 and 8 slots per lane
 
   // work items, problem by problem (so that each problem's items are contiguous)
   for (int li = 0; li < nl; ++li) {
@@ -383,7 +387,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     up(kStageConv, static_cast<size_t>(std::min(d.cchunk, d.D + 1)) + std::min(d.D + 1, d.cchunk + 256));
     up(kStageStir, d.kchunk);
     if (J->lay[li].item_end[kStageNewton] > J->lay[li].item_begin[kStageNewton]) up(kStageNewton, newton_lds_words(d, 1024));
-    up(kStageCrt, crt_lds_words(d, J->crt_ns, kCrtWaves));
+    up(kStageCrt, crt_lds_words(d, J->crt_ns, crt_block_waves(J->crt_ns)));
   }
   J->persist_lds = 0;
   for (int li = 0; li < nl; ++li) {
@@ -475,7 +479,8 @@ void job_bind(Job* J, uint8_t* base) {
     d.status = reinterpret_cast<int*>(base + L.status);
   }
   // initial queue image: one REDUCE task per (problem, prime slot), largest problems first
-  {
+  // (none when a problem has more primes than the persistent schedule takes)
+  if (J->max_np <= kMaxSlots) {
     uint8_t* q = blob + J->qinit_off;
     QueueState* qs = reinterpret_cast<QueueState*>(q);
     Task* tasks = reinterpret_cast<Task*>(q + J->q_tasks);
@@ -578,6 +583,8 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
     return RSL_OK;
   }
   if (mode == RSL_BATCHED) {
+    if (J->max_np > kMaxSlots)
+      return fail(ctx, RSL_EINVAL, "the persistent schedule takes at most 256 primes per problem");
     if (J->persist_lds > static_cast<size_t>(kLdsWords) * 4)
       return fail(ctx, RSL_EINVAL, "persistent launch needs more than 64 KB of LDS per workgroup");
     QueueDesc Q{};

@@ -83,7 +83,7 @@ template <int NS>
 __global__ __launch_bounds__(512) void k_crt(const DevProblem* probs, const WorkItem* items, DevTables T) {
   extern __shared__ uint32_t lds[];
   const WorkItem w = items[blockIdx.x];
-  stage_crt<NS>(probs[w.prob], T, w, lds);
+  stage_crt<NS>(probs[w.prob], T, w, lds, kCrtBlockCoeffs / static_cast<int>(blockDim.x >> 6));
 }
 
 // s(k+1, j) = s(k, j-1) - k s(k, j); one block per prime, rows in LDS.
@@ -146,6 +146,8 @@ hipError_t launch_stage(int stage, const DevProblem* probs, const WorkItem* item
         case 2: hipLaunchKernelGGL(k_crt<2>, g, dim3(kCrtWaves * 64), lds, st, probs, items, T); break;
         case 3: hipLaunchKernelGGL(k_crt<3>, g, dim3(kCrtWaves * 64), lds, st, probs, items, T); break;
         case 4: hipLaunchKernelGGL(k_crt<4>, g, dim3(kCrtWaves * 64), lds, st, probs, items, T); break;
+        case 6: hipLaunchKernelGGL(k_crt<6>, g, dim3(crt_block_waves(6) * 64), lds, st, probs, items, T); break;
+        case 8: hipLaunchKernelGGL(k_crt<8>, g, dim3(crt_block_waves(8) * 64), lds, st, probs, items, T); break;
         default: return hipErrorInvalidValue;
       }
       break;

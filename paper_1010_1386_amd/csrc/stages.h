@@ -22,6 +22,9 @@ enum : int {
 };
 
 constexpr int kCrtWaves = 8;          // waves of a CRT block (one coefficient each)
+// waves of a CRT block with ns prime slots per lane (more slots: fewer waves,
+// two coefficients each, to stay within the LDS of a block)
+__host__ __device__ inline int crt_block_waves(int ns) { return ns > 4 ? 4 : kCrtWaves; }
 constexpr int kLdsWords = 16384;      // 64 KB of dynamic LDS per block at most
 
 // ------------------------------------------------------------------ helpers

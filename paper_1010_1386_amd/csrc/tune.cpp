@@ -12,6 +12,7 @@
 #include "context.h"
 #include "job.h"
 #include "kernels.h"
+#include "persistent.h"
 
 struct rsl_job {
   rsl::Job J;
@@ -287,7 +288,8 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
   // the chunking (and the persistent grid) around the best of those
   std::vector<TuneConfig> cands;
   for (int evk : {1, 2, 4})
-    for (int mode : {RSL_STAGED, RSL_BATCHED}) cands.push_back(TuneConfig{mode, 4096, 1, evk, 0});
+    for (int mode : {RSL_STAGED, RSL_BATCHED})
+      if (mode == RSL_STAGED || j->J.max_np <= kMaxSlots) cands.push_back(TuneConfig{mode, 4096, 1, evk, 0});
   const size_t phase1 = cands.size();
   std::vector<uint8_t> ref;
   TuneConfig win = cands[0];

@@ -1,6 +1,6 @@
 """Write the stored expected resultants under tests/golden/ (calls only oracle/ and workloads/).
 
-Usage:  python tests/golden/make_golden.py [--configs 1 2 4] [--jobs N]
+Usage:  python tests/golden/make_golden.py [--configs 1 2 4 6] [--jobs N]
 
 For each workload the oracle's exact resultant is stored as its degree, a
 SHA-256 digest of the canonical decimal coefficient list (lowest power first,
@@ -63,6 +63,13 @@ def jobs_for(cfg):
             Ft, Gt = oracle.bivar_trim(f), oracle.bivar_trim(g)
             if len(Ft) - 1 + len(Gt) - 1 <= 24:
                 out.append((f"cfg4_{k}_y", f, g, "y", False))
+        return out
+    if cfg == 6:  # large-coefficient random curves (paper Table 3), first pair of each set
+        out = []
+        for deg, k, sparse in ((9, 128, False), (9, 512, False), (9, 512, True), (15, 128, False)):
+            f, g = workloads.table3_curves(deg, k, sparse)[0]
+            name = f"t3_{deg}_{k}_{'sparse' if sparse else 'dense'}"
+            out.append((name + "_y", f, g, "y", False))
         return out
     raise ValueError(cfg)
 

@@ -192,6 +192,23 @@ def config5(count=1000):
     return out
 
 
+def table3_curves(degree, shift, sparse=False, count=5, bits=8):
+    """Random-curve instances of the large-coefficient experiment (paper Table 3):
+    ``count`` curves of total degree ``degree`` (dense, or with each coefficient
+    zeroed with probability 0.3), signed ``bits``-bit base coefficients (the
+    paper leaves the base distribution open), each multiplied by 2^shift with
+    the constant coefficient then increased by one.  The instance set is all
+    pairs of the curves."""
+    rng = rng_for(6, 1000 * degree + (1 if sparse else 0), shift)
+    curves = []
+    for _ in range(count):
+        F = sparse_total(rng, degree, bits) if sparse else dense_total(rng, degree, bits)
+        F = [[c << shift for c in row] for row in F]
+        F[0][0] += 1
+        curves.append(F)
+    return [(curves[a], curves[b]) for a in range(count) for b in range(a + 1, count)]
+
+
 def poisson_arrivals(count, rate, seed_part=0):
     """Arrival times (seconds) of a Poisson stream with the given rate (requests/s)."""
     rng = rng_for(5, 1 << 20, seed_part)
