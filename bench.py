@@ -190,6 +190,62 @@ def batch_bench(steps, warmup):
             "modp_univariate_resultants_per_s": info["pairs"] / tb, "tune": tune, "verified_batched_eq_plain": True}
 
 
+def table3_bench(steps, warmup):
+    """The large-coefficient random curves of the paper's Table 3: for each set
+    (total degree 9 or 15, dense or 30% sparse, coefficients times 2^k for
+    k = 128, 512) the 10 pairs' res_y in one job, autotuned schedule against one
+    pipeline per problem, results compared bit for bit; k = 2048 needs more
+    primes than the CRT covers and is reported as refused."""
+    import torch
+    import paper_1010_1386_amd as rsl
+    import workloads
+
+    ctx = rsl.Context(0, workspace_bytes=2 << 30)
+    steps = max(1, min(steps, 20))
+    rows = []
+    for deg in (9, 15):
+        for k in (128, 512, 2048):
+            for sparse in (False, True):
+                probs = [(f, g, "y") for f, g in workloads.table3_curves(deg, k, sparse)]
+                name = f"degree {deg}, 2^{k}, {'sparse' if sparse else 'dense'}"
+                np_max = max(rsl.query(f, g, v)["n_primes"] for f, g, v in probs)
+                try:
+                    job = ctx.job(probs)
+                except rsl.RSLError as e:
+                    rows.append({"set": name, "primes": np_max, "refused": str(e)})
+                    continue
+                tune = job.tune(reps=2)
+                job.run("auto")
+                got = job.results()
+                job.run("plain")
+                if job.results() != got:
+                    print(f"bench: batched and plain results differ on {name}", file=sys.stderr)
+                    sys.exit(1)
+
+                def timed(mode):
+                    for _ in range(max(1, warmup // 10)):
+                        job.run(mode)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(steps):
+                        job.run(mode)
+                    torch.cuda.synchronize()
+                    return (time.perf_counter() - t0) / steps
+
+                tb, tp = timed("auto"), timed("plain")
+                info = job.info()
+                job.close()
+                rows.append({"set": name, "primes": np_max, "degree_bound": max(len(r) - 1 for r in got),
+                             "max_coeff_bits": max(max(abs(c).bit_length() for c in r) for r in got),
+                             "batched_ms": tb * 1e3, "plain_ms": tp * 1e3,
+                             "ms_per_resultant": tb * 1e3 / len(probs), "mod_p_pairs": info["pairs"],
+                             "schedule": tune["mode"]})
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    ctx.close()
+    return {"workload": "large-coefficient random curves (Table 3): 10 pairs of 5 curves per set, res_y",
+            "steps": steps, "sets": rows, "verified_batched_eq_plain": True}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,6 +259,8 @@ def main():
                     help="serving benchmark instead: N Poisson-arriving requests of the serving workload")
     ap.add_argument("--batch512", action="store_true",
                     help="batch benchmark instead: 512 pairs (res_y), autotuned schedule vs one pipeline per problem")
+    ap.add_argument("--table3", action="store_true",
+                    help="large-coefficient benchmark instead: the random-curve sets of Table 3, res_y of all pairs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
     a = ap.parse_args()
@@ -229,6 +287,9 @@ def main():
         return
     if a.batch512:
         print(json.dumps(batch_bench(a.steps, a.warmup)))
+        return
+    if a.table3:
+        print(json.dumps(table3_bench(a.steps, a.warmup)))
         return
 
     f, g = workloads.config2()

@@ -571,7 +571,9 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
   if (mode == RSL_PLAIN) {
     for (size_t li = 0; li < J->live.size(); ++li) {
       const ProbLayout& L = J->lay[li];
-      const int ns = (J->plans[J->live[li]].np + 63) / 64;
+      // the job-wide slot count: CRT kernels exist for 1-4, 6 and 8 slots, and
+      // the CRT's LDS size was taken for that count
+      const int ns = J->crt_ns;
       for (int s = 0; s < kNumStages; ++s) {
         const int cnt = L.item_end[s] - L.item_begin[s];
         const hipError_t e = (s == kStageEval)

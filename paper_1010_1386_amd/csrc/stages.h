@@ -1172,7 +1172,9 @@ __device__ inline void crt_one(const DevProblem& P, int k_raw, const uint32_t* m
   const uint32_t* crhi = pconst + 5 * np;    //                    high word
 
   uint32_t u[NS];
-  uint32_t fa = 0u, fb = 0u;  // f_i = fa + fb 2^24, summed over the lanes below
+  // f_i < 2^32 split as fa + fb 2^16: both halves summed over up to 512 primes
+  // stay below 2^25, so the 32-bit wave sums cannot wrap
+  uint32_t fa = 0u, fb = 0u;
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
     const int i = lane + 64 * r;
@@ -1183,11 +1185,11 @@ __device__ inline void crt_one(const DevProblem& P, int k_raw, const uint32_t* m
       const uint32_t t = mmul(u[r], cw[i], p, cpinv[i]);
       vbuf[i] = t;
       const uint64_t f = static_cast<uint64_t>(t) * crhi[i] + __umulhi(t, crlo[i]);
-      fa += static_cast<uint32_t>(f) & 0xFFFFFFu;
-      fb += static_cast<uint32_t>(f >> 24);
+      fa += static_cast<uint32_t>(f) & 0xFFFFu;
+      fb += static_cast<uint32_t>(f >> 16);
     }
   }
-  const uint64_t Sf = static_cast<uint64_t>(wave_sum32(fa)) + (static_cast<uint64_t>(wave_sum32(fb)) << 24);
+  const uint64_t Sf = static_cast<uint64_t>(wave_sum32(fa)) + (static_cast<uint64_t>(wave_sum32(fb)) << 16);
   const uint32_t q = static_cast<uint32_t>(Sf >> 32);
   const bool direct = static_cast<uint32_t>(Sf) < 0xFFFFFFFFu - 2u * static_cast<uint32_t>(np) && !P.crt_garner;
   uint64_t init[NS];
