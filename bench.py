@@ -214,6 +214,15 @@ def table3_bench(steps, warmup):
                 except rsl.RSLError as e:
                     rows.append({"set": name, "primes": np_max, "refused": str(e)})
                     continue
+                # sizes beyond the library's limits are reported per problem
+                # when the results are read
+                try:
+                    job.run("staged")
+                    job.results()
+                except rsl.RSLError as e:
+                    job.close()
+                    rows.append({"set": name, "primes": np_max, "refused": str(e)})
+                    continue
                 tune = job.tune(reps=2)
                 job.run("auto")
                 got = job.results()

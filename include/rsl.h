@@ -38,7 +38,7 @@ extern "C" {
 /* ----------------------------------------------------------------- codes */
 #define RSL_OK 0
 #define RSL_EINVAL (-1)   /* null pointer, negative dims, limbs < 1, bad var/mode;
-                             a problem beyond the supported sizes: more than 512
+                             a problem beyond the supported sizes: more than 4096
                              primes, more than 3800 points, degree in the
                              eliminated variable above 255, or more than 256
                              primes in the persistent schedule             */

@@ -42,6 +42,7 @@ static void free_tables(rsl_ctx* c) {
   c->d_pc = nullptr;
   c->d_fact = c->d_ifact = c->d_stir = c->d_Tg = c->d_invM = c->d_Plimb = nullptr;
   c->npcap = 0;
+  c->garner_np = 0;
   c->kcap = c->scap = -1;
 }
 
@@ -83,10 +84,12 @@ int ensure_tables(rsl_ctx* ctx, int np, int kneed, int sneed) {
       ifact[static_cast<size_t>(g) * ks + t] = static_cast<uint32_t>((fi[t] << 32) % p);
     }
   }
-  // canonical CRT tables
-  const int LPg = (31 * new_np + 31) / 32 + 1;
+  // canonical CRT tables (Garner's digits serve only the per-lane-slot CRT, so
+  // they cover at most kSlotCrtPrimes primes)
+  const int gnp = std::min(new_np, kSlotCrtPrimes);
+  const int LPg = (31 * gnp + 31) / 32 + 1;
   std::vector<uint32_t> Tg, invM, Plimb;
-  crt_tables(primes, LPg, &Tg, &invM, &Plimb);
+  crt_tables(std::vector<uint32_t>(primes.begin(), primes.begin() + gnp), LPg, &Tg, &invM, &Plimb);
 
   const int64_t sstride = static_cast<int64_t>(align_up(static_cast<size_t>(stir_rowoff(new_s + 1)), 64));
   auto dmalloc = [&](void** p, size_t bytes) { return hip_check(ctx, hipMalloc(p, bytes), "hipMalloc(tables)"); };
@@ -120,6 +123,7 @@ int ensure_tables(rsl_ctx* ctx, int np, int kneed, int sneed) {
   ctx->kstride = ks;
   ctx->sstride = sstride;
   ctx->LPg = LPg;
+  ctx->garner_np = gnp;
   ctx->table_gen += 1;
   return RSL_OK;
 }

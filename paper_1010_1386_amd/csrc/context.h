@@ -45,11 +45,12 @@ struct rsl_ctx {
   uint32_t* d_stir = nullptr;
   int64_t sstride = 0;
   int kstride = 0;
-  // canonical CRT tables for primes 0..npcap-1
+  // canonical Garner tables for primes 0..garner_np-1
   uint32_t* d_Tg = nullptr;
   uint32_t* d_invM = nullptr;
   uint32_t* d_Plimb = nullptr;
   int LPg = 0;
+  int garner_np = 0;
 
   // pinned host staging
   uint8_t* h_up = nullptr;

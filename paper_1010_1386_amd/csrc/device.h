@@ -49,6 +49,8 @@ struct DevProblem {
   int evk, evpb;     // evaluation: lanes per (prime, point) pair (1, 2, 4), pairs per block (64 / evk)
   int regn;          // evaluation with the polynomials in registers up to this degree (8..32), 0 = no
   int crt_garner;    // 1: CRT by Garner's digits only (test hook), 0: direct form with Garner fallback
+  int wide;          // 1: CRT by the wide path (more primes than the per-lane slots cover)
+  int Lw;            // limbs of the rows of Mi and of negM: L_out, or L_out + 1 for the wide path
   // inputs (uploaded)
   const uint32_t* coeff;  // ncoef * L_in two's complement limbs
   const int* gdeg;        // max x-degree per group of kRowGroup rows: f groups then g groups
@@ -58,16 +60,21 @@ struct DevProblem {
   const uint32_t* Tg;     // [j * tgs + i]  (prod_{l<j} p_l mod p_i) R
   const uint32_t* invM;   // [i]            (prod_{l<i} p_l)^{-1} R mod p_i
   const uint32_t* Plimb;  // [j * LP + t]   limbs of prod_{l<j} p_l
-  const uint32_t* Mi;     // [j * L_out + t] limbs of M / p_j (direct CRT)
+  const uint32_t* Mi;     // [j * Lw + t]   limbs of M / p_j (direct CRT)
   const uint32_t* wdir;   // [i]            (M / p_i)^{-1} R mod p_i
   const uint32_t* rinv;   // [2 i], [2 i + 1] low, high word of floor(2^64 / p_i)
-  const uint32_t* negM;   // L_out: 2^(32 L_out) - M
+  const uint32_t* negM;   // Lw: 2^(32 Lw) - M
+  const uint32_t* Mw;     // Lw limbs of M (wide path)
+  const uint32_t* NHM;    // L_out: -(M-1)/2 - M mod 2^(32 L_out) (wide path)
   // intermediates and output
   uint32_t* resid;        // np * CS     transposed tiles, c R^2 mod p
   uint32_t* zval;         // np * (E+1)  R(x_i) mod p, normal form
   uint8_t* zbad;          // np * (E+1)  leading coefficient vanished at x_i
   uint64_t* aconv;        // ncchunk * np * (D+1): partial sums, REDC(sum) = Newton coefficient a_k
   uint64_t* cpart;        // nchunk * np * (D+1): partial sums, REDC(sum) = coefficient mod p
+  uint32_t* wT;           // (D+1) * np  t_{k,i} = u_{k,i} (M / p_i)^{-1} mod p_i (wide path)
+  uint32_t* wq;           // D+1         quotient estimate floor(sum_i f_{k,i} / 2^32) (wide path)
+  uint64_t* wS;           // (D+1) * 2 Lw  column sums over primes per 16-bit half limb (wide path)
   uint32_t* out;          // (D+1) * L_out two's complement limbs of R
   int* status;            // [0] error bits, [1+slot] 1 if gapped interpolation, [1+np] bad pairs,
                           // [2+np+slot] 1 if a point among 0..D was bad for the prime
@@ -94,7 +101,8 @@ struct StirGroup {
   int maxD;    // largest degree bound among the members
 };
 constexpr int kStirGroupMax = 8;
-constexpr int kMaxPrimes = 512;  // primes per problem (CRT: 8 slots per lane)
+constexpr int kSlotCrtPrimes = 512;  // CRT with the primes in per-lane slots (up to 8 per lane)
+constexpr int kMaxPrimes = 4096;     // primes per problem (the wide CRT beyond kSlotCrtPrimes)
 
 // status[0] error bits
 enum : int {

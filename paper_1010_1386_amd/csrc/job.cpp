@@ -41,7 +41,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     int rc = make_plan(&f[k], &g[k], var[k], opts, &J->plans[k], &e);
     if (!rc && !J->plans[k].zero) {
       const Plan& P = J->plans[k];
-      if (P.np > kMaxPrimes) { rc = RSL_EINVAL; e = "more than 512 primes needed (coefficients too large)"; }
+      if (P.np > kMaxPrimes) { rc = RSL_EINVAL; e = "more than 4096 primes needed (coefficients too large)"; }
       else if (P.E > 3800) { rc = RSL_EINVAL; e = "more than 3800 evaluation points needed (degree bound too large)"; }
       else if (std::max(P.my, P.ny) > 255) { rc = RSL_EINVAL; e = "degree in the eliminated variable above 255"; }
     }
@@ -148,10 +148,12 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     d.evpb = 64 / d.evk;
     d.regn = (d.evk <= 2) ? regn_of(P) : 0;
     d.crt_garner = (ctx && ctx->crt_garner) ? 1 : 0;
+    d.wide = P.wide ? 1 : 0;
+    d.Lw = P.Lw;
     // the convolution's input range: the basis change's chunking, or whole
     d.cchunk = J->tune.conv_whole ? P.D + 1 : d.kchunk;
     d.ncchunk = (P.D + 1 + d.cchunk - 1) / d.cchunk;
-    J->crt_ns = std::max(J->crt_ns, (P.np + 63) / 64);
+    if (!P.wide) J->crt_ns = std::max(J->crt_ns, (P.np + 63) / 64);
     J->max_np = std::max(J->max_np, P.np);
     J->pairs += static_cast<int64_t>(P.np) * (P.E + 1);
     J->mulmods += pair_mulmods(P) * P.np * (P.E + 1);
@@ -183,8 +185,44 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     // coefficient (bad points) or a shifted origin
     if (P.origin != 0 || (!P.formal && P.s > 0))
       for (int sl = 0; sl < P.np; ++sl) J->items[kStageNewton].push_back({li, sl, 0, 0});
-    for (int b = 0; b < blocks_of(P.D + 1, kCrtWaves); ++b) J->items[kStageCrt].push_back({li, -1, b, 0});
+    if (!P.wide)
+      for (int b = 0; b < blocks_of(P.D + 1, kCrtWaves); ++b) J->items[kStageCrt].push_back({li, -1, b, 0});
     for (int s = 0; s < kNumStages; ++s) L.item_end[s] = static_cast<int>(J->items[s].size());
+  }
+
+  // wide CRT items, problem by problem
+  for (int pass = 0; pass < 3; ++pass) J->wide_items[pass].clear();
+  for (int li = 0; li < nl; ++li) {
+    const Plan& P = J->plans[J->live[li]];
+    ProbLayout& L = J->lay[li];
+    for (int pass = 0; pass < 3; ++pass) L.wide_begin[pass] = static_cast<int>(J->wide_items[pass].size());
+    if (P.wide) {
+      for (int b = 0; b < blocks_of(P.D + 1, kWideTCoeffs); ++b) J->wide_items[0].push_back({li, -1, b, 0});
+      // column sums: the blocks of one half-limb tile read the same columns of
+      // the M_i table, so they are dealt onto one XCD (workgroup i of a launch
+      // runs on XCD i mod 8; a problem's range starts anywhere, but its items
+      // of one tile keep one residue mod 8)
+      constexpr int kXcds = 8;
+      const int nkt = blocks_of(P.D + 1, kWideKT), nht = blocks_of(2 * P.Lw, kWideHT);
+      std::vector<std::vector<WorkItem>> bins(kXcds);
+      for (int ht = 0; ht < nht; ++ht)
+        for (int kt = 0; kt < nkt; ++kt) bins[ht % kXcds].push_back({li, -1, kt, ht});
+      std::vector<size_t> pos(kXcds, 0);
+      for (int t = 0; t < nkt * nht; ++t) {
+        int x = t % kXcds;
+        if (pos[x] >= bins[x].size()) {  // bin x is empty: take from the fullest
+          size_t best = 0;
+          for (int y = 0; y < kXcds; ++y)
+            if (bins[y].size() - pos[y] > best) {
+              best = bins[y].size() - pos[y];
+              x = y;
+            }
+        }
+        J->wide_items[1].push_back(bins[x][pos[x]++]);
+      }
+      for (int k = 0; k <= P.D; ++k) J->wide_items[2].push_back({li, -1, k, 0});
+    }
+    for (int pass = 0; pass < 3; ++pass) L.wide_end[pass] = static_cast<int>(J->wide_items[pass].size());
   }
 
   // evaluation items by layout (stable: a problem's items stay together, as
@@ -295,6 +333,10 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   o = align_up(o + sizeof(StirMember) * J->smembers.size(), A);
   J->sgi_off = o;
   o = align_up(o + sizeof(WorkItem) * J->sg_items.size(), A);
+  for (int pass = 0; pass < 3; ++pass) {
+    J->wide_off[pass] = o;
+    o = align_up(o + sizeof(WorkItem) * J->wide_items[pass].size(), A);
+  }
   for (int li = 0; li < nl; ++li) {
     const Plan& P = J->plans[J->live[li]];
     const DevProblem& d = J->dev[li];
@@ -305,10 +347,15 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     L.pidx = o;  o = align_up(o + static_cast<size_t>(P.np) * 4, 16);
     L.Hm = o;    o = align_up(o + static_cast<size_t>(P.np) * 4, 16);
     L.NH = o;    o = align_up(o + static_cast<size_t>(P.L_out) * 4, 16);
-    L.Mi = o;    o = align_up(o + static_cast<size_t>(P.np) * P.L_out * 4, 16);
+    L.Mi = o;    o = align_up(o + static_cast<size_t>(P.np) * P.Lw * 4, 16);
     L.wdir = o;  o = align_up(o + static_cast<size_t>(P.np) * 4, 16);
     L.rinv = o;  o = align_up(o + static_cast<size_t>(P.np) * 8, 16);
-    L.negM = o;  o = align_up(o + static_cast<size_t>(P.L_out) * 4, 16);
+    L.negM = o;  o = align_up(o + static_cast<size_t>(P.Lw) * 4, 16);
+    L.Mw = L.NHM = 0;
+    if (P.wide) {
+      L.Mw = o;  o = align_up(o + static_cast<size_t>(P.Lw) * 4, 16);
+      L.NHM = o; o = align_up(o + static_cast<size_t>(P.L_out) * 4, 16);
+    }
     if (!P.canonical) {
       L.Tg = o;    o = align_up(o + static_cast<size_t>(P.np) * P.np * 4, 16);
       L.invM = o;  o = align_up(o + static_cast<size_t>(P.np) * 4, 16);
@@ -373,6 +420,12 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     L.zbad = o;  o = align_up(o + np * (P.E + 1), A);
     L.aconv = o; o = align_up(o + static_cast<size_t>(d.ncchunk) * np * (P.D + 1) * 8, A);
     L.cpart = o; o = align_up(o + static_cast<size_t>(d.nchunk) * np * (P.D + 1) * 8, A);
+    L.wT = L.wq = L.wS = 0;
+    if (P.wide) {
+      L.wT = o; o = align_up(o + np * (P.D + 1) * 4, A);
+      L.wq = o; o = align_up(o + static_cast<size_t>(P.D + 1) * 4, A);
+      L.wS = o; o = align_up(o + static_cast<size_t>(P.D + 1) * 2 * P.Lw * 8, A);
+    }
   }
   J->queue_off = o;
   o = align_up(o + J->queue_bytes, A);
@@ -387,7 +440,15 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     up(kStageConv, static_cast<size_t>(std::min(d.cchunk, d.D + 1)) + std::min(d.D + 1, d.cchunk + 256));
     up(kStageStir, d.kchunk);
     if (J->lay[li].item_end[kStageNewton] > J->lay[li].item_begin[kStageNewton]) up(kStageNewton, newton_lds_words(d, 1024));
-    up(kStageCrt, crt_lds_words(d, J->crt_ns, crt_block_waves(J->crt_ns)));
+    if (!d.wide) up(kStageCrt, crt_lds_words(d, J->crt_ns, crt_block_waves(J->crt_ns)));
+  }
+  for (int pass = 0; pass < 3; ++pass) J->wide_lds[pass] = 0;
+  for (int li = 0; li < nl; ++li) {
+    const DevProblem& d = J->dev[li];
+    if (!d.wide) continue;
+    J->wide_lds[0] = static_cast<size_t>(wide_t_lds_words()) * 4;
+    J->wide_lds[1] = static_cast<size_t>(wide_sum_lds_words()) * 4;
+    J->wide_lds[2] = std::max(J->wide_lds[2], static_cast<size_t>(wide_fin_lds_words(d)) * 4);
   }
   J->persist_lds = 0;
   for (int li = 0; li < nl; ++li) {
@@ -397,11 +458,12 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     w = std::max<size_t>(w, d.kchunk);
     if (J->lay[li].item_end[kStageNewton] > J->lay[li].item_begin[kStageNewton])
       w = std::max<size_t>(w, newton_lds_words(d, 64));
-    w = std::max<size_t>(w, crt_lds_words(d, J->crt_ns, 1));
+    if (!d.wide) w = std::max<size_t>(w, crt_lds_words(d, J->crt_ns, 1));
     J->persist_lds = std::max(J->persist_lds, w * 4);
   }
   for (int s = 0; s < kNumStages; ++s)
-    if (J->stage_lds[s] > static_cast<size_t>(kLdsWords) * 4) {
+    if (J->stage_lds[s] > static_cast<size_t>(kLdsWords) * 4 ||
+        (s < 3 && J->wide_lds[s] > static_cast<size_t>(kLdsWords) * 4)) {
       *err = "a stage needs more than 64 KB of LDS";
       return RSL_EINVAL;
     }
@@ -455,6 +517,10 @@ void job_bind(Job* J, uint8_t* base) {
     std::memcpy(blob + L.wdir, P.wdir.data(), P.wdir.size() * 4);
     std::memcpy(blob + L.rinv, P.rinv.data(), P.rinv.size() * 4);
     std::memcpy(blob + L.negM, P.negM.data(), P.negM.size() * 4);
+    if (P.wide) {
+      std::memcpy(blob + L.Mw, P.Mw.data(), P.Mw.size() * 4);
+      std::memcpy(blob + L.NHM, P.NHM.data(), P.NHM.size() * 4);
+    }
     if (!P.canonical) {
       std::memcpy(blob + L.Tg, P.Tg.data(), P.Tg.size() * 4);
       std::memcpy(blob + L.invM, P.invM.data(), P.invM.size() * 4);
@@ -470,6 +536,11 @@ void job_bind(Job* J, uint8_t* base) {
     d.wdir = reinterpret_cast<const uint32_t*>(base + L.wdir);
     d.rinv = reinterpret_cast<const uint32_t*>(base + L.rinv);
     d.negM = reinterpret_cast<const uint32_t*>(base + L.negM);
+    d.Mw = P.wide ? reinterpret_cast<const uint32_t*>(base + L.Mw) : nullptr;
+    d.NHM = P.wide ? reinterpret_cast<const uint32_t*>(base + L.NHM) : nullptr;
+    d.wT = P.wide ? reinterpret_cast<uint32_t*>(base + L.wT) : nullptr;
+    d.wq = P.wide ? reinterpret_cast<uint32_t*>(base + L.wq) : nullptr;
+    d.wS = P.wide ? reinterpret_cast<uint64_t*>(base + L.wS) : nullptr;
     d.resid = reinterpret_cast<uint32_t*>(base + L.resid);
     d.zval = reinterpret_cast<uint32_t*>(base + L.zval);
     d.zbad = base + L.zbad;
@@ -513,6 +584,9 @@ void job_bind(Job* J, uint8_t* base) {
       std::memcpy(blob + J->items_off[s], J->items[s].data(), sizeof(WorkItem) * J->items[s].size());
   if (!J->eval_staged.empty())
     std::memcpy(blob + J->evs_off, J->eval_staged.data(), sizeof(WorkItem) * J->eval_staged.size());
+  for (int pass = 0; pass < 3; ++pass)
+    if (!J->wide_items[pass].empty())
+      std::memcpy(blob + J->wide_off[pass], J->wide_items[pass].data(), sizeof(WorkItem) * J->wide_items[pass].size());
   if (!J->sgroups.empty()) {
     std::memcpy(blob + J->sg_off, J->sgroups.data(), sizeof(StirGroup) * J->sgroups.size());
     std::memcpy(blob + J->sm_off, J->smembers.data(), sizeof(StirMember) * J->smembers.size());
@@ -529,7 +603,7 @@ static void bind_crt_tables(const rsl_ctx* ctx, Job* J) {
     DevProblem& d = J->dev[li];
     if (P.canonical) {
       d.Tg = ctx->d_Tg;
-      d.tgs = ctx->npcap;
+      d.tgs = ctx->garner_np;
       d.invM = ctx->d_invM;
       d.Plimb = ctx->d_Plimb;
       d.LP = ctx->LPg;
@@ -567,6 +641,7 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
   const DevTables T = tables_of(ctx);
   const DevProblem* probs = reinterpret_cast<const DevProblem*>(J->base + J->probs_off);
   auto items = [&](int s) { return reinterpret_cast<const WorkItem*>(J->base + J->items_off[s]); };
+  auto wide = [&](int pass) { return reinterpret_cast<const WorkItem*>(J->base + J->wide_off[pass]); };
   int rc;
   if (mode == RSL_PLAIN) {
     for (size_t li = 0; li < J->live.size(); ++li) {
@@ -580,6 +655,12 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
             ? launch_eval(eval_variant(J->dev[li]), probs, items(s) + L.item_begin[s], cnt, J->stage_lds[s], T, st)
             : launch_stage(s, probs, items(s) + L.item_begin[s], cnt, J->stage_lds[s], ns, T, st);
         if ((rc = hip_check(ctx, e, "launch"))) return rc;
+      }
+      for (int pass = 0; pass < 3; ++pass) {
+        const int cnt = L.wide_end[pass] - L.wide_begin[pass];
+        if ((rc = hip_check(ctx, launch_crt_wide(pass, probs, wide(pass) + L.wide_begin[pass], cnt, J->wide_lds[pass], T, st),
+                            "launch")))
+          return rc;
       }
     }
     return RSL_OK;
@@ -643,6 +724,11 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
     if ((rc = hip_check(ctx, launch_stage(s, probs, items(s), static_cast<int>(J->items[s].size()),
                                           J->stage_lds[s], J->crt_ns, T, st), "launch")))
       return rc;
+    if (s == kStageCrt)
+      for (int pass = 0; pass < 3; ++pass)
+        if ((rc = hip_check(ctx, launch_crt_wide(pass, probs, wide(pass), static_cast<int>(J->wide_items[pass].size()),
+                                                 J->wide_lds[pass], T, st), "launch")))
+          return rc;
   }
   if (stage_events && (rc = hip_check(ctx, hipEventRecord(ctx->ev[kNumStages], st), "event"))) return rc;
   return RSL_OK;

@@ -22,10 +22,11 @@ namespace rsl {
 // Schedule parameters chosen by the autotuner (tune.cpp).
 struct ProbLayout {
   // offsets from the job base
-  size_t coeff, gdeg, pidx, Hm, NH, Tg, invM, Plimb, Mi, wdir, rinv, negM, status;
-  size_t out, resid, zval, zbad, aconv, cpart;
+  size_t coeff, gdeg, pidx, Hm, NH, Tg, invM, Plimb, Mi, wdir, rinv, negM, Mw, NHM, status;
+  size_t out, resid, zval, zbad, aconv, cpart, wT, wq, wS;
   int L_in;
   int item_begin[kNumStages], item_end[kNumStages];
+  int wide_begin[3], wide_end[3];  // ranges of Job::wide_items[pass] (wide CRT)
 };
 
 struct Job {
@@ -48,6 +49,11 @@ struct Job {
   std::vector<StirMember> smembers;
   std::vector<WorkItem> sg_items;
   size_t sg_off = 0, sm_off = 0, sgi_off = 0, sg_lds = 0;
+  // wide CRT (problems with more primes than the per-lane slots cover): items of
+  // its three passes
+  std::vector<WorkItem> wide_items[3];
+  size_t wide_off[3] = {};
+  size_t wide_lds[3] = {};
   size_t items_off[kNumStages] = {};
   size_t stage_lds[kNumStages] = {};
   int crt_ns = 1;

@@ -15,6 +15,11 @@ hipError_t launch_stage(int stage, const DevProblem* probs, const WorkItem* item
 hipError_t launch_eval(int variant, const DevProblem* probs, const WorkItem* items, int nitems, size_t lds,
                        const DevTables& T, hipStream_t st);
 
+// Pass 0, 1 or 2 of the wide CRT (t values and quotients, column sums, carries
+// and output) over `nitems` items.
+hipError_t launch_crt_wide(int pass, const DevProblem* probs, const WorkItem* items, int nitems, size_t lds,
+                           const DevTables& T, hipStream_t st);
+
 // Basis change over prime groups (problems sharing a prime share the table reads).
 hipError_t launch_stir_group(const DevProblem* probs, const StirGroup* groups, const StirMember* members,
                              const WorkItem* items, int nitems, size_t lds, const DevTables& T, hipStream_t st);

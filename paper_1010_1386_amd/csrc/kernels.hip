@@ -12,7 +12,8 @@
 //   interp_stir falling-factorial -> monomial basis (partial sums per k-chunk)
 //   interp_newton divided differences on a gapped point set (bad points replaced)
 //                                                         (Sec. 4.1, step 3)
-//   crt         Garner mixed-radix digits + radix conversion to limbs (Sec. 4.1, step 3)
+//   crt         direct form with Garner fallback + radix conversion to limbs (Sec. 4.1, step 3)
+//   crt_wide_*  the direct form in three passes for problems with many primes
 //   stirling_build  per-prime table of Stirling numbers of the first kind
 #include <hip/hip_runtime.h>
 
@@ -84,6 +85,37 @@ __global__ __launch_bounds__(512) void k_crt(const DevProblem* probs, const Work
   extern __shared__ uint32_t lds[];
   const WorkItem w = items[blockIdx.x];
   stage_crt<NS>(probs[w.prob], T, w, lds, kCrtBlockCoeffs / static_cast<int>(blockDim.x >> 6));
+}
+
+__global__ __launch_bounds__(256) void k_crt_wide_t(const DevProblem* probs, const WorkItem* items, DevTables T) {
+  extern __shared__ uint32_t lds[];
+  const WorkItem w = items[blockIdx.x];
+  stage_crt_wide_t(probs[w.prob], T, w, lds);
+}
+
+__global__ __launch_bounds__(kWideHT) void k_crt_wide_sum(const DevProblem* probs, const WorkItem* items) {
+  extern __shared__ uint4 lds4[];  // 16-byte aligned: rows of t values are read as uint4
+  const WorkItem w = items[blockIdx.x];
+  stage_crt_wide_sum(probs[w.prob], w, reinterpret_cast<uint32_t*>(lds4));
+}
+
+__global__ __launch_bounds__(64) void k_crt_wide_fin(const DevProblem* probs, const WorkItem* items) {
+  extern __shared__ uint32_t lds[];
+  const WorkItem w = items[blockIdx.x];
+  stage_crt_wide_fin(probs[w.prob], w, lds);
+}
+
+hipError_t launch_crt_wide(int pass, const DevProblem* probs, const WorkItem* items, int nitems, size_t lds,
+                           const DevTables& T, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  const dim3 g(nitems);
+  switch (pass) {
+    case 0: hipLaunchKernelGGL(k_crt_wide_t, g, dim3(256), lds, st, probs, items, T); break;
+    case 1: hipLaunchKernelGGL(k_crt_wide_sum, g, dim3(kWideHT), lds, st, probs, items); break;
+    case 2: hipLaunchKernelGGL(k_crt_wide_fin, g, dim3(64), lds, st, probs, items); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // s(k+1, j) = s(k, j-1) - k s(k, j); one block per prime, rows in LDS.

@@ -27,7 +27,7 @@ std::mutex g_prime_mu;
 std::vector<uint32_t> g_primes;
 uint32_t g_next_candidate = 0x7FFFFFFFu;  // 2^31 - 1
 
-constexpr size_t kMaxPrimes = 1u << 16;
+constexpr size_t kPrimeTableMax = 1u << 16;
 
 }  // namespace
 
@@ -54,7 +54,7 @@ bool is_prime_u32(uint32_t n) {
 
 const std::vector<uint32_t>& prime_table(size_t at_least) {
   std::lock_guard<std::mutex> lk(g_prime_mu);
-  at_least = std::min(at_least, kMaxPrimes);
+  at_least = std::min(at_least, kPrimeTableMax);
   while (g_primes.size() < at_least) {
     uint32_t c = g_next_candidate;
     g_next_candidate -= 2;
@@ -236,7 +236,7 @@ int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opt
     }
     return true;
   };
-  const size_t limit = o.prime_limit ? static_cast<size_t>(o.prime_limit) : kMaxPrimes;
+  const size_t limit = o.prime_limit ? static_cast<size_t>(o.prime_limit) : kPrimeTableMax;
   BigU M(1);
   P->pidx.clear();
   P->bad_primes = 0;
@@ -259,7 +259,13 @@ int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opt
     }
     P->pidx.push_back(static_cast<int>(k));
     M = BigU::mul_small(M, p);
-    if (!enough) enough = BigU::cmp(BigU::mul(M, M), fourB2) > 0;
+    if (!enough) {
+      // M^2 has 2 b - 1 or 2 b bits (b = bits of M): the exact product is
+      // needed only when that range meets the bit length of 4 B^2
+      const int bm = M.bitlen(), bb = fourB2.bitlen();
+      if (2 * bm - 1 > bb) enough = true;
+      else if (2 * bm >= bb) enough = BigU::cmp(BigU::mul(M, M), fourB2) > 0;
+    }
     if (enough) {
       if (extra_left == 0) break;
       --extra_left;
@@ -278,9 +284,20 @@ int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opt
   P->Hm.resize(P->np);
   for (int i = 0; i < P->np; ++i) P->Hm[i] = H.mod_small(primes[i]);
   P->NH = H.neg_limbs(P->L_out);
-  if (!P->canonical) crt_tables(primes, P->L_out, &P->Tg, &P->invM, &P->Plimb);
+  // beyond the per-lane slots the CRT takes the wide path: Y0 = sum_i t_i M_i - q M
+  // with q possibly one short, so Y0 < 2M needs one limb more than M
+  P->wide = P->np > kSlotCrtPrimes;
+  P->Lw = P->wide ? P->L_out + 1 : P->L_out;
+  if (!P->canonical && !P->wide) crt_tables(primes, P->L_out, &P->Tg, &P->invM, &P->Plimb);
   else { P->Tg.clear(); P->invM.clear(); P->Plimb.clear(); }
-  direct_crt_tables(primes, M, P->L_out, &P->Mi, &P->wdir, &P->rinv, &P->negM);
+  direct_crt_tables(primes, M, P->Lw, &P->Mi, &P->wdir, &P->rinv, &P->negM);
+  if (P->wide) {
+    P->Mw = M.limbs(P->Lw);
+    P->NHM = BigU::add(H, M).neg_limbs(P->L_out);
+  } else {
+    P->Mw.clear();
+    P->NHM.clear();
+  }
 
   // residue tile layout
   P->rowf = F.dx + 1;

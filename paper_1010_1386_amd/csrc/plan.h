@@ -9,6 +9,7 @@
 
 #include "../../include/rsl.h"
 #include "bigint.h"
+#include "device.h"
 #include "modarith.h"
 
 namespace rsl {
@@ -47,13 +48,17 @@ struct Plan {
   int bad_primes = 0;
   int bound_bits = 0;
   int L_out = 1;            // CRT output limbs (two's complement)
+  bool wide = false;        // CRT by the wide path (more than kSlotCrtPrimes primes)
+  int Lw = 1;               // limbs of the Mi rows and of negM: L_out, or L_out + 1 when wide
   std::vector<uint32_t> Hm; // (M-1)/2 mod p_i
   std::vector<uint32_t> NH; // 2^(32 L_out) - (M-1)/2, L_out limbs
   // per-plan CRT tables (only when !canonical)
   std::vector<uint32_t> Tg, invM, Plimb;
-  // direct CRT tables: limbs of M / p_j ([np][L_out]), (M / p_i)^{-1} R mod p_i,
-  // floor(2^64 / p_i) as (low, high) words, 2^(32 L_out) - M
+  // direct CRT tables: limbs of M / p_j ([np][Lw]), (M / p_i)^{-1} R mod p_i,
+  // floor(2^64 / p_i) as (low, high) words, 2^(32 Lw) - M
   std::vector<uint32_t> Mi, wdir, rinv, negM;
+  // wide path: M in Lw limbs, -(M-1)/2 - M mod 2^(32 L_out)
+  std::vector<uint32_t> Mw, NHM;
   // device layout
   int rowf = 0, rowg = 0;   // row strides (dx + 1) of the residue tiles
   int CS = 0;               // residue words per prime (f tile + g tile, padded)

@@ -1298,4 +1298,203 @@ __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const 
   }
 }
 
+// ------------------------------------------------------------------ wide CRT
+// Problems with more primes than the per-lane slots cover.  The same direct
+// form Y = sum_i t_i M_i - q M (M_i = M / p_i, t_i = u_i M_i^{-1} mod p_i) in
+// three passes over device memory:
+//   1. per coefficient k: t_{k,i} for every prime, and the quotient estimate
+//      q_k = floor(sum_i f_{k,i} / 2^32) from the fixed-point parts, which is
+//      the true quotient or one short of it (each f undershoots by < 2);
+//   2. the integer contraction S[k][h] = sum_i t_{k,i} m_{i,h} over 16-bit
+//      halves m_{i,h} of the M_i limbs (each term < 2^47, so 4096 primes sum
+//      below 2^59 without carries), tiled 16 coefficients x 256 half limbs;
+//   3. one wave per coefficient: Y0 = sum_h S[k][h] 2^(16 h) + q_k (2^(32 Lw) - M)
+//      mod 2^(32 Lw), which lies in [0, 2M) (Lw = L_out + 1 limbs hold it),
+//      compared with M; the output is Y0 - H (- M when Y0 >= M) mod 2^(32 L_out).
+constexpr int kWideTCoeffs = 8;    // coefficients per block of pass 1 (256 threads)
+constexpr int kWideKT = 16;        // coefficients per block of pass 2
+constexpr int kWideHT = 256;       // half limbs per block of pass 2 (one per thread)
+constexpr int kWideChunk = 64;     // primes per LDS chunk of pass 2
+
+__host__ __device__ inline int wide_t_lds_words() { return 4 * 2 * kWideTCoeffs; }
+__host__ __device__ inline int wide_sum_lds_words() { return kWideChunk * kWideKT; }
+__host__ __device__ inline int wide_fin_lds_words(const DevProblem& P) { return P.Lw; }
+
+// Carry into this lane when every lane adds its `gen` (carry out of its own
+// limb) and passes an incoming carry on when `prop` (limb all ones); `cin` is
+// the carry into lane 0 and becomes the carry out of lane 63.
+__device__ inline uint32_t wave_carry_in(bool gen, bool prop, uint64_t* cin) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t G = __ballot(gen);
+  const uint64_t X = G | __ballot(prop);
+  const unsigned __int128 tot = static_cast<unsigned __int128>(X) + G + *cin;
+  const uint64_t C = static_cast<uint64_t>(tot) ^ X ^ G;
+  *cin = static_cast<uint64_t>(tot >> 64);
+  return static_cast<uint32_t>((C >> lane) & 1u);
+}
+
+// Pass 1: block item blk covers coefficients blk*8 .. blk*8+7; thread owns
+// coefficient c = tid mod 8 and primes tid/8 + 32 r.
+__device__ inline void stage_crt_wide_t(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
+  const int c = threadIdx.x & (kWideTCoeffs - 1);
+  const int k_raw = w.blk * kWideTCoeffs + c;
+  const bool valid = k_raw <= P.D;
+  const int k = valid ? k_raw : P.D;
+  const int np = P.np;
+  const size_t cstride = static_cast<size_t>(np) * (P.D + 1);
+  uint32_t fa = 0u, fb = 0u;  // 16-bit halves of the f parts, summed
+  for (int i = threadIdx.x / kWideTCoeffs; i < np; i += blockDim.x / kWideTCoeffs) {
+    const uint64_t* cpp = P.cpart + static_cast<size_t>(i) * (P.D + 1) + k;
+    const PrimeConst pc = T.pc[P.pidx[i]];
+    uint64_t cs = 0;
+    for (int ch = 0; ch < P.nchunk; ++ch) cs = add_fold(cs, cpp[ch * cstride], pc.p);
+    const uint32_t u = maddm(redc(cs, pc.p, pc.pinv), P.Hm[i], pc.p);  // c_k + H mod p
+    const uint32_t t = mmul(u, P.wdir[i], pc.p, pc.pinv);
+    if (valid) P.wT[static_cast<size_t>(k) * np + i] = t;
+    const uint64_t f = static_cast<uint64_t>(t) * P.rinv[2 * i + 1] + __umulhi(t, P.rinv[2 * i]);
+    fa += static_cast<uint32_t>(f) & 0xFFFFu;
+    fb += static_cast<uint32_t>(f >> 16);
+  }
+  // lanes of one coefficient differ in lane bits 3..5
+#pragma unroll
+  for (int m = kWideTCoeffs; m < 64; m <<= 1) {
+    fa += static_cast<uint32_t>(__shfl_xor(static_cast<int>(fa), m, 64));
+    fb += static_cast<uint32_t>(__shfl_xor(static_cast<int>(fb), m, 64));
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  if (lane < kWideTCoeffs) {
+    lds[wave * 2 * kWideTCoeffs + lane] = fa;
+    lds[wave * 2 * kWideTCoeffs + kWideTCoeffs + lane] = fb;
+  }
+  __syncthreads();
+  if (threadIdx.x < kWideTCoeffs && valid) {
+    uint64_t sa = 0, sb = 0;
+    for (int v = 0; v < nw; ++v) {
+      sa += lds[v * 2 * kWideTCoeffs + c];
+      sb += lds[v * 2 * kWideTCoeffs + kWideTCoeffs + c];
+    }
+    P.wq[k] = static_cast<uint32_t>((sa + (sb << 16)) >> 32);
+  }
+}
+
+// Pass 2: item (blk = coefficient tile, sub = half-limb tile); the block's
+// t values for 64 primes at a time are staged in LDS as [prime][coefficient]
+// (read back as broadcasts), each thread streams its half-limb column of the
+// M_i table.
+__device__ inline void stage_crt_wide_sum(const DevProblem& P, const WorkItem& w, uint32_t* lds) {
+  const int np = P.np, nh = 2 * P.Lw;
+  const int k0 = w.blk * kWideKT;
+  const int h = w.sub * kWideHT + static_cast<int>(threadIdx.x);
+  const bool hv = h < nh;
+  const uint16_t* M16 = reinterpret_cast<const uint16_t*>(P.Mi);
+  uint64_t acc[kWideKT];
+#pragma unroll
+  for (int c = 0; c < kWideKT; ++c) acc[c] = 0u;
+  for (int i0 = 0; i0 < np; i0 += kWideChunk) {
+    __syncthreads();  // the previous chunk is consumed
+    for (int e = threadIdx.x; e < kWideChunk * kWideKT; e += blockDim.x) {
+      const int c = e / kWideChunk, ii = e - c * kWideChunk;  // coalesced along the primes of one row
+      const int i = i0 + ii, k = k0 + c;
+      lds[ii * kWideKT + c] = (i < np && k <= P.D) ? P.wT[static_cast<size_t>(k) * np + i] : 0u;
+    }
+    __syncthreads();
+    const int n = min(kWideChunk, np - i0);
+    for (int ii = 0; ii < n; ii += 8) {
+      uint32_t m[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        m[u] = (hv && ii + u < n) ? static_cast<uint32_t>(M16[static_cast<size_t>(i0 + ii + u) * nh + h]) : 0u;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint4* tv = reinterpret_cast<const uint4*>(lds + (ii + u) * kWideKT);
+#pragma unroll
+        for (int q4 = 0; q4 < kWideKT / 4; ++q4) {
+          const uint4 t4 = tv[q4];
+          acc[4 * q4 + 0] += static_cast<uint64_t>(t4.x) * m[u];
+          acc[4 * q4 + 1] += static_cast<uint64_t>(t4.y) * m[u];
+          acc[4 * q4 + 2] += static_cast<uint64_t>(t4.z) * m[u];
+          acc[4 * q4 + 3] += static_cast<uint64_t>(t4.w) * m[u];
+        }
+      }
+    }
+  }
+  if (hv)
+#pragma unroll
+    for (int c = 0; c < kWideKT; ++c)
+      if (k0 + c <= P.D) P.wS[static_cast<size_t>(k0 + c) * nh + h] = acc[c];
+}
+
+// Pass 3: one wave (the whole block) per coefficient k = blk.
+__device__ inline void stage_crt_wide_fin(const DevProblem& P, const WorkItem& w, uint32_t* lds) {
+  const int lane = threadIdx.x & 63;
+  const int k = w.blk;
+  const int Lw = P.Lw, L = P.L_out;
+  const uint64_t* S = P.wS + static_cast<size_t>(k) * 2 * Lw;
+  const uint32_t q = P.wq[k];
+  uint32_t* y = lds;
+  // Y0 limbs, 64 at a time; V_t = S_{2t} + S_{2t+1} 2^16 + q negM_t < 2^77 is
+  // (lo: 64 bits, hi: 32 bits), and limb t is lo32(V_t) + mid32(V_{t-1}) +
+  // hi(V_{t-2}) plus carries; the values of lanes 62 and 63 carry over
+  uint32_t pm = 0u, ph1 = 0u, ph2 = 0u, pc1 = 0u;
+  uint64_t cin = 0u;
+  for (int t0 = 0; t0 < Lw; t0 += 64) {
+    const int t = t0 + lane;
+    uint64_t lo = 0u;
+    uint32_t hi = 0u;
+    if (t < Lw) {
+      const uint64_t s0 = S[2 * t], s1 = S[2 * t + 1];
+      const uint64_t a = s1 << 16;
+      lo = s0 + a;
+      hi = static_cast<uint32_t>(s1 >> 48) + (lo < a ? 1u : 0u);
+      const uint64_t b = static_cast<uint64_t>(q) * P.negM[t];
+      lo += b;
+      hi += (lo < b) ? 1u : 0u;
+    }
+    const uint32_t mid = static_cast<uint32_t>(lo >> 32);
+    uint32_t mprev = static_cast<uint32_t>(__shfl_up(static_cast<int>(mid), 1, 64));
+    uint32_t hprev2 = static_cast<uint32_t>(__shfl_up(static_cast<int>(hi), 2, 64));
+    if (lane == 0) {
+      mprev = pm;
+      hprev2 = ph2;
+    }
+    if (lane == 1) hprev2 = ph1;
+    const uint64_t s = static_cast<uint64_t>(static_cast<uint32_t>(lo)) + mprev + hprev2;
+    const uint32_t l1 = static_cast<uint32_t>(s), h1 = static_cast<uint32_t>(s >> 32);  // h1 <= 2
+    uint32_t h1prev = static_cast<uint32_t>(__shfl_up(static_cast<int>(h1), 1, 64));
+    if (lane == 0) h1prev = pc1;
+    const uint64_t x2 = static_cast<uint64_t>(l1) + h1prev;
+    const uint32_t l2 = static_cast<uint32_t>(x2);
+    const uint32_t cy = wave_carry_in((x2 >> 32) != 0, l2 == 0xFFFFFFFFu, &cin);
+    if (t < Lw) y[t] = l2 + cy;
+    pm = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(mid), 63));
+    ph1 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(hi), 63));
+    ph2 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(hi), 62));
+    pc1 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(h1), 63));
+  }
+  WaveSync()();
+  // Y0 >= M ?  (top limbs first; equal counts as >=)
+  int ge = 1;
+  for (int t0 = ((Lw - 1) / 64) * 64; t0 >= 0; t0 -= 64) {
+    const int t = t0 + lane;
+    const uint32_t yv = (t < Lw) ? y[t] : 0u, mv = (t < Lw) ? P.Mw[t] : 0u;
+    const uint64_t gt = __ballot(yv > mv), lt = __ballot(yv < mv);
+    const uint64_t d = gt | lt;
+    if (d) {
+      const int top = 63 - __clzll(static_cast<long long>(d));
+      ge = static_cast<int>((gt >> top) & 1u);
+      break;
+    }
+  }
+  // output: Y0 - H (- M) mod 2^(32 L_out)
+  const uint32_t* A = ge ? P.NHM : P.NH;
+  cin = 0u;
+  for (int t0 = 0; t0 < L; t0 += 64) {
+    const int t = t0 + lane;
+    const uint64_t x = (t < L) ? static_cast<uint64_t>(y[t]) + A[t] : 0u;
+    const uint32_t l = static_cast<uint32_t>(x);
+    const uint32_t cy = wave_carry_in((x >> 32) != 0, l == 0xFFFFFFFFu && t < L, &cin);
+    if (t < L) P.out[static_cast<size_t>(k) * L + t] = l + cy;
+  }
+}
+
 }  // namespace rsl

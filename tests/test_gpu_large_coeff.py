@@ -1,7 +1,8 @@
 """GPU: the large-coefficient random curves of the paper's Table 3 (curves of
 degree 9 and 15, multiplied by 2^k with the constant coefficient increased by
-one): hundreds of primes per problem (CRT with up to eight prime slots per
-lane), multi-limb inputs, stored oracle digests and modulo-q checks."""
+one): hundreds to thousands of primes per problem (CRT with up to eight prime
+slots per lane, the wide CRT beyond 512 primes), multi-limb inputs, stored
+oracle digests and modulo-q checks."""
 
 import hashlib
 import json
@@ -12,6 +13,7 @@ import pytest
 
 import oracle
 import workloads
+from workloads import dense_total, rng_for, small_random, sparse_total
 
 pytestmark = pytest.mark.gpu
 
@@ -78,8 +80,56 @@ def test_persistent_schedule_refuses_many_primes(rsl, ctx):
     assert ctx.batch([(f, g, "y")], mode="auto") == ctx.batch([(f, g, "y")], mode="staged")
 
 
-def test_beyond_512_primes_is_refused(rsl, ctx):
-    f, g = workloads.table3_curves(9, 2048)[0]
+@pytest.mark.parametrize("extra", [520, 1100])
+def test_wide_crt_small_problems_match_oracle(rsl, ctx, extra):
+    """Primes beyond the bound (more than 512 in all) send small problems through
+    the wide CRT: exact oracle results in both schedules, bad points included."""
+    rng = rng_for(716, extra)
+    probs = []
+    for k in range(8):
+        F = dense_total(rng, int(rng.integers(2, 7)), int(rng.integers(8, 64)))
+        G = sparse_total(rng, int(rng.integers(3, 7)), int(rng.integers(8, 40)))
+        probs.append((F, G, "yx"[k % 2]))
+    F = small_random(rng, 3, 4, 20)
+    F[3] = [0, -2, 1, 0, 0]  # lc_y = x (x - 2): points 0 and 2 are bad for every prime
+    probs.append((F, small_random(rng, 2, 3, 20), "y"))
+    want = [oracle.res(f, g, v) for f, g, v in probs]
+    job = ctx.job(probs, extra_primes=extra)
+    for mode in ("staged", "plain"):
+        job.run(mode)
+        assert job.results() == want, mode
+    with pytest.raises(rsl.RSLError) as ei:
+        job.run("batched")
+    assert ei.value.code == rsl.RSL_EINVAL
+    job.close()
+
+
+def test_wide_crt_equals_slot_crt(rsl, ctx, gold):
+    """The (9, 2^512) pair with 304 primes (slot CRT) and with 564 (wide CRT):
+    the same bits, equal to the stored oracle digest."""
+    f, g = workloads.table3_curves(9, 512)[0]
+    rec = gold["t3_9_512_dense_y"]
+    for extra in (0, 260):
+        R = ctx.res(f, g, "y", extra_primes=extra)
+        assert len(R) - 1 == rec["degree"] and digest(R) == rec["sha256"], extra
+
+
+@pytest.mark.parametrize("deg", [9, 15])
+def test_2048_bit_scale_all_pairs(rsl, ctx, deg):
+    """Coefficients times 2^2048 (1196 and 1993 primes): all ten pairs staged =
+    plain, both variables, modulo-q checks."""
+    pairs = workloads.table3_curves(deg, 2048)
+    probs = [(f, g, "yx"[i % 2]) for i, (f, g) in enumerate(pairs)]
+    assert min(rsl.query(f, g, v)["n_primes"] for f, g, v in probs) > 512
+    got = ctx.batch(probs, mode="staged")
+    assert got == ctx.batch(probs, mode="plain")
+    for i in (0, 5, 9):
+        f, g, v = probs[i]
+        modq(f, g, got[i], v, 2, 100 + i)
+
+
+def test_beyond_4096_primes_is_refused(rsl, ctx):
+    f, g = workloads.table3_curves(9, 8192)[0]
     with pytest.raises(rsl.RSLError) as ei:
         ctx.res(f, g, "y")
     assert ei.value.code == rsl.RSL_EINVAL
