@@ -190,7 +190,7 @@ def batch_bench(steps, warmup):
             "modp_univariate_resultants_per_s": info["pairs"] / tb, "tune": tune, "verified_batched_eq_plain": True}
 
 
-def table3_bench(steps, warmup):
+def table3_bench(steps, warmup, only=None):
     """The large-coefficient random curves of the paper's Table 3: for each set
     (total degree 9 or 15, dense or 30% sparse, coefficients times 2^k for
     k = 128, 512) the 10 pairs' res_y in one job, autotuned schedule against one
@@ -206,6 +206,8 @@ def table3_bench(steps, warmup):
     for deg in (9, 15):
         for k in (128, 512, 2048):
             for sparse in (False, True):
+                if only and f"{deg}:{k}" not in only:
+                    continue
                 probs = [(f, g, "y") for f, g in workloads.table3_curves(deg, k, sparse)]
                 name = f"degree {deg}, 2^{k}, {'sparse' if sparse else 'dense'}"
                 np_max = max(rsl.query(f, g, v)["n_primes"] for f, g, v in probs)
@@ -270,6 +272,8 @@ def main():
                     help="batch benchmark instead: 512 pairs (res_y), autotuned schedule vs one pipeline per problem")
     ap.add_argument("--table3", action="store_true",
                     help="large-coefficient benchmark instead: the random-curve sets of Table 3, res_y of all pairs")
+    ap.add_argument("--table3-only", default="", metavar="DEG:K[,DEG:K]",
+                    help="with --table3: only these sets (e.g. 15:2048)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
     a = ap.parse_args()
@@ -298,7 +302,8 @@ def main():
         print(json.dumps(batch_bench(a.steps, a.warmup)))
         return
     if a.table3:
-        print(json.dumps(table3_bench(a.steps, a.warmup)))
+        only = [x for x in a.table3_only.split(",") if x]
+        print(json.dumps(table3_bench(a.steps, a.warmup, only)))
         return
 
     f, g = workloads.config2()

@@ -167,8 +167,13 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     const DevProblem& d = J->dev[li];
     ProbLayout& L = J->lay[li];
     for (int s = 0; s < kNumStages; ++s) L.item_begin[s] = static_cast<int>(J->items[s].size());
-    for (int sl = 0; sl < P.np; ++sl)
-      for (int b = 0; b < blocks_of(d.CS, 256); ++b) J->items[kStageReduce].push_back({li, sl, b, 0});
+    if (d.L_in > 2) {  // long limb chains: staged limbs, eight primes per thread
+      for (int sl = 0; sl < P.np; sl += kReduceMlSlots)
+        for (int b = 0; b < blocks_of(d.CS, kReduceMlCoeffs); ++b) J->items[kStageReduce].push_back({li, sl, b, 1});
+    } else {
+      for (int sl = 0; sl < P.np; ++sl)
+        for (int b = 0; b < blocks_of(d.CS, 256); ++b) J->items[kStageReduce].push_back({li, sl, b, 0});
+    }
     for (int sl = 0; sl < P.np; ++sl)
       for (int b = 0; b < blocks_of(P.E + 1, d.evpb); ++b) J->items[kStageEval].push_back({li, sl, b, 0});
     for (int sl = 0; sl < P.np; ++sl)
@@ -198,12 +203,12 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     for (int pass = 0; pass < 3; ++pass) L.wide_begin[pass] = static_cast<int>(J->wide_items[pass].size());
     if (P.wide) {
       for (int b = 0; b < blocks_of(P.D + 1, kWideTCoeffs); ++b) J->wide_items[0].push_back({li, -1, b, 0});
-      // column sums: the blocks of one half-limb tile read the same columns of
+      // column sums: the blocks of one limb tile read the same columns of
       // the M_i table, so they are dealt onto one XCD (workgroup i of a launch
       // runs on XCD i mod 8; a problem's range starts anywhere, but its items
       // of one tile keep one residue mod 8)
       constexpr int kXcds = 8;
-      const int nkt = blocks_of(P.D + 1, kWideKT), nht = blocks_of(2 * P.Lw, kWideHT);
+      const int nkt = blocks_of(P.D + 1, kWideKT), nht = blocks_of(P.Lw, kWideHT);
       std::vector<std::vector<WorkItem>> bins(kXcds);
       for (int ht = 0; ht < nht; ++ht)
         for (int kt = 0; kt < nkt; ++kt) bins[ht % kXcds].push_back({li, -1, kt, ht});
@@ -441,6 +446,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     up(kStageStir, d.kchunk);
     if (J->lay[li].item_end[kStageNewton] > J->lay[li].item_begin[kStageNewton]) up(kStageNewton, newton_lds_words(d, 1024));
     if (!d.wide) up(kStageCrt, crt_lds_words(d, J->crt_ns, crt_block_waves(J->crt_ns)));
+    if (d.L_in > 2) up(kStageReduce, reduce_ml_lds_words());
   }
   for (int pass = 0; pass < 3; ++pass) J->wide_lds[pass] = 0;
   for (int li = 0; li < nl; ++li) {

@@ -29,8 +29,12 @@ namespace rsl {
 static_assert(kCrtWaves == kCrtBlockCoeffs, "one coefficient per wave of a CRT block");
 
 __global__ __launch_bounds__(256) void k_reduce(const DevProblem* probs, const WorkItem* items, DevTables T) {
+  extern __shared__ uint32_t lds[];
   const WorkItem w = items[blockIdx.x];
-  stage_reduce(probs[w.prob], T, w, true);
+  if (w.sub)
+    stage_reduce_ml(probs[w.prob], T, w, lds);
+  else
+    stage_reduce(probs[w.prob], T, w, true);
 }
 
 template <int V>
@@ -167,7 +171,7 @@ hipError_t launch_stage(int stage, const DevProblem* probs, const WorkItem* item
   if (nitems <= 0) return hipSuccess;
   const dim3 g(nitems);
   switch (stage) {
-    case kStageReduce: hipLaunchKernelGGL(k_reduce, g, dim3(256), 0, st, probs, items, T); break;
+    case kStageReduce: hipLaunchKernelGGL(k_reduce, g, dim3(256), lds, st, probs, items, T); break;
     case kStageEval: return hipErrorInvalidValue;  // launch_eval: one kernel per layout
     case kStageConv: hipLaunchKernelGGL(k_interp_conv, g, dim3(256), lds, st, probs, items, T); break;
     case kStageStir: hipLaunchKernelGGL(k_interp_stir, g, dim3(256), lds, st, probs, items, T); break;

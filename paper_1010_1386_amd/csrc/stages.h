@@ -155,6 +155,86 @@ __device__ inline void stage_reduce(const DevProblem& P, const DevTables& T, con
   P.resid[static_cast<size_t>(w.slot) * P.CS + t] = v;
 }
 
+// Multi-limb inputs: a block takes 64 transposed positions and 32 prime slots
+// (item: slot = first slot, blk = position block, sub = 1).  The 64
+// coefficients' limbs are staged in LDS 64 limbs at a time (coalesced reads of
+// each coefficient's limb run, stored [limb][coefficient] with a padded row);
+// thread (c, q) runs the Horner steps of the limbs, top limb first, for slots
+// slot + q + 4 r, r < 8: eight independent chains.
+constexpr int kReduceMlCoeffs = 64;
+constexpr int kReduceMlSlots = 32;
+constexpr int kReduceMlLimbs = 64;
+__host__ __device__ inline int reduce_ml_lds_words() { return kReduceMlLimbs * (kReduceMlCoeffs + 1); }
+
+__device__ inline void stage_reduce_ml(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
+  if (w.slot == 0 && w.blk == 0)
+    for (int i = threadIdx.x; i < 2 * P.np + 2; i += blockDim.x) P.status[i] = 0;
+  constexpr int kPer = kReduceMlSlots / 4;
+  const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int t = w.blk * kReduceMlCoeffs + c;
+  auto input_of = [&](int tt) {
+    if (tt >= P.CS) return -1;
+    if (tt < P.goff) {
+      const int i = tt / P.myp, j = tt - i * P.myp;
+      return (j <= P.my) ? j * P.rowf + i : -1;
+    }
+    const int u = tt - P.goff;
+    const int i = u / P.nyp, j = u - i * P.nyp;
+    return (i < P.rowg && j <= P.ny) ? (P.my + 1) * P.rowf + j * P.rowg + i : -1;
+  };
+  const int in = input_of(t);
+  uint32_t p[kPer], pinv[kPer], r2[kPer], r3[kPer], acc[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int sl = w.slot + q + 4 * r;
+    const PrimeConst pc = T.pc[P.pidx[sl < P.np ? sl : 0]];
+    p[r] = pc.p;
+    pinv[r] = pc.pinv;
+    r2[r] = pc.r2;
+    r3[r] = pc.r3;
+    acc[r] = 0u;
+  }
+  const int L = P.L_in;
+  for (int l1 = L; l1 > 0; l1 -= kReduceMlLimbs) {  // limbs [l0, l1), top chunk first
+    const int l0 = l1 > kReduceMlLimbs ? l1 - kReduceMlLimbs : 0, nl = l1 - l0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kReduceMlCoeffs * nl; e += blockDim.x) {
+      const int cc = e / nl, l = e - cc * nl;
+      const int ci = input_of(w.blk * kReduceMlCoeffs + cc);
+      lds[l * (kReduceMlCoeffs + 1) + cc] = (ci >= 0) ? P.coeff[static_cast<size_t>(ci) * L + l0 + l] : 0u;
+    }
+    __syncthreads();
+    for (int l = nl - 1; l >= 0; --l) {
+      const uint32_t wd = lds[l * (kReduceMlCoeffs + 1) + c];
+      if (l0 + l == L - 1) {
+        // the signed top limb plus 2p lies in (0, 4p) since 2^30 < p < 2^31
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+          uint64_t x = static_cast<uint64_t>(static_cast<int64_t>(static_cast<int32_t>(wd)) + 2 * static_cast<int64_t>(p[r]));
+          x = (x >= 2ull * p[r]) ? x - 2ull * p[r] : x;
+          x = (x >= p[r]) ? x - p[r] : x;
+          acc[r] = static_cast<uint32_t>(x);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+          uint32_t wl = umin32(wd, wd - p[r]);
+          wl = umin32(wl, wl - p[r]);
+          wl = umin32(wl, wl - p[r]);
+          acc[r] = maddm(mmul(acc[r], r2[r], p[r], pinv[r]), wl, p[r]);
+        }
+      }
+    }
+  }
+  if (t >= P.CS) return;
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int sl = w.slot + q + 4 * r;
+    if (sl < P.np)
+      P.resid[static_cast<size_t>(sl) * P.CS + t] = (in >= 0) ? mmul(acc[r], r3[r], p[r], pinv[r]) : 0u;
+  }
+}
+
 // -------------------------------------------------------------- eval + ures
 
 // Bad-pair bookkeeping of one eval wave: the count, and a per-prime flag set
@@ -1307,13 +1387,13 @@ __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const 
 //      the true quotient or one short of it (each f undershoots by < 2);
 //   2. the integer contraction S[k][h] = sum_i t_{k,i} m_{i,h} over 16-bit
 //      halves m_{i,h} of the M_i limbs (each term < 2^47, so 4096 primes sum
-//      below 2^59 without carries), tiled 16 coefficients x 256 half limbs;
+//      below 2^59 without carries), tiled 16 coefficients x 256 limbs;
 //   3. one wave per coefficient: Y0 = sum_h S[k][h] 2^(16 h) + q_k (2^(32 Lw) - M)
 //      mod 2^(32 Lw), which lies in [0, 2M) (Lw = L_out + 1 limbs hold it),
 //      compared with M; the output is Y0 - H (- M when Y0 >= M) mod 2^(32 L_out).
 constexpr int kWideTCoeffs = 8;    // coefficients per block of pass 1 (256 threads)
 constexpr int kWideKT = 16;        // coefficients per block of pass 2
-constexpr int kWideHT = 256;       // half limbs per block of pass 2 (one per thread)
+constexpr int kWideHT = 256;       // limbs per block of pass 2 (one per thread)
 constexpr int kWideChunk = 64;     // primes per LDS chunk of pass 2
 
 __host__ __device__ inline int wide_t_lds_words() { return 4 * 2 * kWideTCoeffs; }
@@ -1377,19 +1457,30 @@ __device__ inline void stage_crt_wide_t(const DevProblem& P, const DevTables& T,
   }
 }
 
-// Pass 2: item (blk = coefficient tile, sub = half-limb tile); the block's
-// t values for 64 primes at a time are staged in LDS as [prime][coefficient]
-// (read back as broadcasts), each thread streams its half-limb column of the
-// M_i table.
+// Pass 2: item (blk = coefficient tile, sub = limb tile); the block's t values
+// for 64 primes at a time are staged in LDS as [prime][coefficient] (read
+// back as broadcasts); each thread streams one limb column of the M_i table
+// and splits it into its two 16-bit halves, so every t value feeds two
+// multiply-adds.  Loads go out a group of 8 primes ahead of their use, from
+// clamped (always valid) addresses.
 __device__ inline void stage_crt_wide_sum(const DevProblem& P, const WorkItem& w, uint32_t* lds) {
-  const int np = P.np, nh = 2 * P.Lw;
+  constexpr int G = 8;
+  const int np = P.np, Lw = P.Lw, nh = 2 * Lw;
   const int k0 = w.blk * kWideKT;
-  const int h = w.sub * kWideHT + static_cast<int>(threadIdx.x);
-  const bool hv = h < nh;
-  const uint16_t* M16 = reinterpret_cast<const uint16_t*>(P.Mi);
-  uint64_t acc[kWideKT];
+  const int t = w.sub * kWideHT + static_cast<int>(threadIdx.x);
+  const bool tv_ok = t < Lw;
+  const uint32_t* Mcol = P.Mi + (tv_ok ? t : Lw - 1);
+  uint64_t alo[kWideKT], ahi[kWideKT];
 #pragma unroll
-  for (int c = 0; c < kWideKT; ++c) acc[c] = 0u;
+  for (int c = 0; c < kWideKT; ++c) alo[c] = ahi[c] = 0u;
+  // no masks needed: the staged t values are zero beyond the last prime, and
+  // lanes beyond the last limb store nothing
+  auto load_group = [&](int ibase, uint32_t* m) {
+#pragma unroll
+    for (int u = 0; u < G; ++u) m[u] = Mcol[static_cast<size_t>(min(ibase + u, np - 1)) * Lw];
+  };
+  uint32_t mcur[G], mnext[G];
+  load_group(0, mcur);
   for (int i0 = 0; i0 < np; i0 += kWideChunk) {
     __syncthreads();  // the previous chunk is consumed
     for (int e = threadIdx.x; e < kWideChunk * kWideKT; e += blockDim.x) {
@@ -1399,29 +1490,38 @@ __device__ inline void stage_crt_wide_sum(const DevProblem& P, const WorkItem& w
     }
     __syncthreads();
     const int n = min(kWideChunk, np - i0);
-    for (int ii = 0; ii < n; ii += 8) {
-      uint32_t m[8];
+    for (int ii = 0; ii < n; ii += G) {
+      load_group(i0 + ii + G, mnext);  // beyond np: clamped (their t values are zero)
+      __builtin_amdgcn_sched_barrier(0);  // issue them before this group's arithmetic
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        m[u] = (hv && ii + u < n) ? static_cast<uint32_t>(M16[static_cast<size_t>(i0 + ii + u) * nh + h]) : 0u;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < G; ++u) {
+        const uint32_t lo = mcur[u] & 0xFFFFu, hi = mcur[u] >> 16;
         const uint4* tv = reinterpret_cast<const uint4*>(lds + (ii + u) * kWideKT);
 #pragma unroll
         for (int q4 = 0; q4 < kWideKT / 4; ++q4) {
           const uint4 t4 = tv[q4];
-          acc[4 * q4 + 0] += static_cast<uint64_t>(t4.x) * m[u];
-          acc[4 * q4 + 1] += static_cast<uint64_t>(t4.y) * m[u];
-          acc[4 * q4 + 2] += static_cast<uint64_t>(t4.z) * m[u];
-          acc[4 * q4 + 3] += static_cast<uint64_t>(t4.w) * m[u];
+          alo[4 * q4 + 0] += static_cast<uint64_t>(t4.x) * lo;
+          ahi[4 * q4 + 0] += static_cast<uint64_t>(t4.x) * hi;
+          alo[4 * q4 + 1] += static_cast<uint64_t>(t4.y) * lo;
+          ahi[4 * q4 + 1] += static_cast<uint64_t>(t4.y) * hi;
+          alo[4 * q4 + 2] += static_cast<uint64_t>(t4.z) * lo;
+          ahi[4 * q4 + 2] += static_cast<uint64_t>(t4.z) * hi;
+          alo[4 * q4 + 3] += static_cast<uint64_t>(t4.w) * lo;
+          ahi[4 * q4 + 3] += static_cast<uint64_t>(t4.w) * hi;
         }
       }
+#pragma unroll
+      for (int u = 0; u < G; ++u) mcur[u] = mnext[u];
     }
   }
-  if (hv)
+  if (tv_ok)
 #pragma unroll
     for (int c = 0; c < kWideKT; ++c)
-      if (k0 + c <= P.D) P.wS[static_cast<size_t>(k0 + c) * nh + h] = acc[c];
+      if (k0 + c <= P.D) {
+        uint64_t* dst = P.wS + static_cast<size_t>(k0 + c) * nh + 2 * t;
+        dst[0] = alo[c];
+        dst[1] = ahi[c];
+      }
 }
 
 // Pass 3: one wave (the whole block) per coefficient k = blk.

@@ -72,6 +72,31 @@ def test_all_pairs_batched_equals_plain_and_modq(rsl, ctx, deg, k):
         modq(f, g, got[i], v, 2, i)
 
 
+def test_multi_limb_reduction_paths_agree(rsl, ctx):
+    """Inputs of 5 limbs: the staged and plain schedules reduce them with staged
+    limbs and eight primes per thread, the persistent schedule one chain per
+    thread; all ten pairs give the same bits."""
+    pairs = workloads.table3_curves(9, 128)
+    probs = [(f, g, "yx"[i % 2]) for i, (f, g) in enumerate(pairs)]
+    got = ctx.batch(probs, mode="staged")
+    assert got == ctx.batch(probs, mode="batched") == ctx.batch(probs, mode="plain")
+
+
+def test_long_limb_chains_match_oracle(rsl, ctx):
+    """Small problems with coefficients of about 2200 bits (70 limbs: two limb
+    chunks in the reduction) and of 100 bits, mixed: exact oracle results."""
+    rng = rng_for(717, 0)
+    probs = []
+    for k in range(6):
+        bits = 2200 if k % 2 == 0 else 100
+        F = small_random(rng, int(rng.integers(1, 4)), int(rng.integers(0, 3)), bits)
+        G = small_random(rng, int(rng.integers(1, 3)), int(rng.integers(0, 3)), bits)
+        probs.append((F, G, "yx"[k % 2]))
+    want = [oracle.res(f, g, v) for f, g, v in probs]
+    for mode in ("staged", "plain"):
+        assert ctx.batch(probs, mode=mode) == want, mode
+
+
 def test_persistent_schedule_refuses_many_primes(rsl, ctx):
     f, g = workloads.table3_curves(9, 512)[0]
     with pytest.raises(rsl.RSLError) as ei:
