@@ -272,6 +272,8 @@ def main():
                     help="batch benchmark instead: 512 pairs (res_y), autotuned schedule vs one pipeline per problem")
     ap.add_argument("--table3", action="store_true",
                     help="large-coefficient benchmark instead: the random-curve sets of Table 3, res_y of all pairs")
+    ap.add_argument("--eval-schur", action="store_true",
+                    help="univariate resultants by the Schur algorithm (comparison runs; use with --schedule staged)")
     ap.add_argument("--table3-only", default="", metavar="DEG:K[,DEG:K]",
                     help="with --table3: only these sets (e.g. 15:2048)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -309,7 +311,7 @@ def main():
     f, g = workloads.config2()
     problems = [(f, g, "y"), (f, g, "x")]
     ctx = rsl.Context(0, workspace_bytes=256 << 20)
-    job = ctx.job(problems)
+    job = ctx.job(problems, eval_schur=a.eval_schur)
     info = job.info()
     # schedule: the autotuner times every candidate layout (staged launches /
     # one persistent launch x interpolation chunking) and keeps the fastest
@@ -370,10 +372,14 @@ def main():
     value = 2 * a.steps / dt
     stages = stage_profile(mode, a.steps)
     other = "staged" if mode == "batched" else "batched"
-    dto = timed(other, a.plain_steps, max(1, a.warmup // 4))
+    try:
+        dto = timed(other, a.plain_steps, max(1, a.warmup // 4))
+    except rsl.RSLError:  # a layout the persistent schedule does not run (Schur evaluation)
+        dto = None
     dtp = timed("plain", a.plain_steps, max(1, a.warmup // 4))
     plain_value = 2 * a.plain_steps / dtp
-    schedules = {mode: ms_step, other: dto / a.plain_steps * 1e3, "plain": dtp / a.plain_steps * 1e3}
+    schedules = {mode: ms_step, other: None if dto is None else dto / a.plain_steps * 1e3,
+                 "plain": dtp / a.plain_steps * 1e3}
     if mode == "batched":
         # the staged launches give the per-stage split of the same work
         staged_split = stage_profile("staged", a.plain_steps)
@@ -439,6 +445,7 @@ def main():
                    "problems_per_step": 2, "primes": 57, "points": 577,
                    "schedule": {"batched": "persistent", "staged": "staged"}[mode] + (" (graph)" if use_graph else ""),
                    "lanes_per_pair": tune["lanes_per_pair"],
+                   "ures": "schur" if (a.eval_schur or tune.get("schur")) else "remainder sequence",
                    "chunk_target": tune["chunk_target"], "grid_mult": tune["grid_mult"]},
         "verified_bit_exact": verified,
         "modp_univariate_resultants_per_s": pairs / (ures_ms * 1e-3),

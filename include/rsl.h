@@ -133,6 +133,12 @@ typedef struct {
                           size or by the autotuner */
   int32_t eval_regs;   /* 0: keep both polynomials of a pair in registers when the shape
                           allows (degrees <= 32 differing by at most one); -1: never */
+  int32_t eval_schur;  /* 1: univariate resultants by the generalised Schur algorithm on
+                          the displacement generators of the Sylvester matrix (paper
+                          Sec. 4.1), one wave per (prime, point), for problems with
+                          m_y, n_y >= 1 and m_y + n_y <= 64 (others keep the remainder
+                          sequence); staged and plain schedules only; 0 = remainder
+                          sequence unless the autotuner chose Schur */
 } rsl_opts;
 
 /* Counters of the last call on a context (or of a server). */
@@ -248,13 +254,15 @@ typedef struct {
   int32_t grid_mult;     /* persistent workgroups per resident slot */
   int32_t evk;           /* lanes per (prime, point) pair in evaluation: 1, 2 or 4 */
   int32_t conv_whole;    /* 1: convolution sums taken whole, 0: split like the basis change */
+  int32_t schur;         /* 1: evaluation by the Schur algorithm (see rsl_opts.eval_schur) */
   int32_t candidates;    /* candidates timed */
   double ms;             /* device time of one run of the chosen schedule */
   double ms_worst;       /* device time of the slowest candidate */
 } rsl_tune_result;
 
 int rsl_job_tune(rsl_ctx *ctx, rsl_job *job, int reps, rsl_tune_result *best);
-/* Save / load the tuning cache as text lines "key mode chunk_target grid_mult evk conv_whole ms". */
+/* Save / load the tuning cache as text lines
+ * "key mode chunk_target grid_mult evk conv_whole schur ms". */
 int rsl_tune_save(rsl_ctx *ctx, const char *path);
 int rsl_tune_load(rsl_ctx *ctx, const char *path);
 

@@ -22,6 +22,7 @@ struct TuneConfig {
   int grid_mult = 1;          // persistent launch: workgroups = grid_mult x resident capacity
   int evk = 0;                // lanes per (prime, point) pair in evaluation; 0 = from the job size
   int conv_whole = 0;         // 1: the convolution sums each coefficient whole (no i-chunks)
+  int schur = 0;              // 1: evaluation by the Schur algorithm where the shape allows
 };
 struct TuneEntry {
   TuneConfig cfg;

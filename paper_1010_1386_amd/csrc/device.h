@@ -49,6 +49,7 @@ struct DevProblem {
   int evk, evpb;     // evaluation: lanes per (prime, point) pair (1, 2, 4), pairs per block (64 / evk)
   int regn;          // evaluation with the polynomials in registers up to this degree (8..32), 0 = no
   int crt_garner;    // 1: CRT by Garner's digits only (test hook), 0: direct form with Garner fallback
+  int schur;         // 1: univariate resultants by the Schur algorithm (one wave per pair)
   int wide;          // 1: CRT by the wide path (more primes than the per-lane slots cover)
   int Lw;            // limbs of the rows of Mi and of negM: L_out, or L_out + 1 for the wide path
   // inputs (uploaded)

@@ -121,6 +121,8 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   }
   J->crt_ns = 1;
   J->max_np = 0;
+  J->any_schur = false;
+  const bool schur_req = (opts && opts->eval_schur > 0) || J->tune.schur != 0;
   for (int li = 0; li < nl; ++li) {
     const Plan& P = J->plans[J->live[li]];
     DevProblem& d = J->dev[li];
@@ -147,6 +149,13 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     while (d.evk < evk && std::min(P.my, P.ny) >= 4 * d.evk * 2) d.evk *= 2;
     d.evpb = 64 / d.evk;
     d.regn = (d.evk <= 2) ? regn_of(P) : 0;
+    d.schur = (schur_req && P.my >= 1 && P.ny >= 1 && P.my + P.ny <= kSchurMaxR) ? 1 : 0;
+    if (d.schur) {  // one wave per pair, kSchurPts points per block
+      d.evk = 1;
+      d.evpb = kSchurPts;
+      d.regn = 0;
+      J->any_schur = true;
+    }
     d.crt_garner = (ctx && ctx->crt_garner) ? 1 : 0;
     d.wide = P.wide ? 1 : 0;
     d.Lw = P.Lw;
@@ -674,6 +683,8 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
   if (mode == RSL_BATCHED) {
     if (J->max_np > kMaxSlots)
       return fail(ctx, RSL_EINVAL, "the persistent schedule takes at most 256 primes per problem");
+    if (J->any_schur)
+      return fail(ctx, RSL_EINVAL, "the persistent schedule does not run the Schur evaluation");
     if (J->persist_lds > static_cast<size_t>(kLdsWords) * 4)
       return fail(ctx, RSL_EINVAL, "persistent launch needs more than 64 KB of LDS per workgroup");
     QueueDesc Q{};

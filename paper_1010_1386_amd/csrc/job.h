@@ -58,6 +58,7 @@ struct Job {
   size_t stage_lds[kNumStages] = {};
   int crt_ns = 1;
   int max_np = 0;                  // most primes of any live problem
+  bool any_schur = false;          // some problem evaluates by the Schur algorithm
   size_t probs_off = 0;
   size_t up_bytes = 0;             // [0, up_bytes) is uploaded
   size_t down_off = 0, down_bytes = 0;  // statuses + outputs, downloaded

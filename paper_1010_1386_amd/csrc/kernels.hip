@@ -61,6 +61,7 @@ hipError_t launch_eval(int variant, const DevProblem* probs, const WorkItem* ite
     case kEvP16: hipLaunchKernelGGL(k_eval_ures<kEvP16>, g, b, lds, st, probs, items, T); break;
     case kEvP24: hipLaunchKernelGGL(k_eval_ures<kEvP24>, g, b, lds, st, probs, items, T); break;
     case kEvP32: hipLaunchKernelGGL(k_eval_ures<kEvP32>, g, b, lds, st, probs, items, T); break;
+    case kEvSchur: hipLaunchKernelGGL(k_eval_ures<kEvSchur>, g, b, lds, st, probs, items, T); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -633,8 +633,127 @@ __device__ inline void stage_eval_ures_regs2(const DevProblem& P, const DevTable
   eval_report_bad(P, w.slot, pt, live, bad);
 }
 
+// ------------------------------------------------ eval + Schur (Sec. 4.1)
+// The univariate resultant as the determinant of the Sylvester matrix S
+// (n_y rows of f's coefficients, then m_y rows of g's), triangularised by the
+// generalised Schur algorithm on its displacement generators.  With K the
+// down-shift inside each of the two row blocks and Z the column shift,
+//   S - K S Z^T = G B^T,  G = [e_0, e_n],  B = [row 0 of S, row n of S],
+// a rank-2 displacement (a single generator when one block is empty).  Step
+// k reads the pivot row (g0, b0) of the current generators, d = g0 . b0, and
+// forms the generators of the Schur complement without divisions:
+//   G' = [ g0_1 G_0 - g0_0 G_1 ,  (f d e_0 + K' G b0) ],
+//   B' = [ b0_1 B_0 - b0_0 B_1 ,  d e_0 + Z' (B g0) ],
+// which represent d times the complement of the represented matrix; so the
+// pivots of S are d_k / sigma_k with sigma_{k+1} = d_k sigma_k, and
+// det S = prod d_k / prod sigma_k (one inversion at the end).  (f = 1 when
+// rows k and k+1 lie in the same block; K' shifts inside blocks.)  A zero
+// pivot before the last step (a vanishing leading minor) ends the recursion:
+// the point then goes through the remainder sequence, as do bad points and
+// problems with an empty block.
+//
+// One wave per (prime, point); lane l holds row l of both generators (degree
+// sum m_y + n_y <= 64); the points of a block (kSchurPts) run one after the
+// other over the prime's tile, staged once.  Lane j evaluates the
+// coefficients a_{m-j} = f_{m-j}(x_i) and b_{n-j} = g_{n-j}(x_i).
+constexpr int kSchurPts = 16;
+constexpr int kSchurMaxR = 64;
+__host__ __device__ inline int eval_schur_lds_words(const DevProblem& P) {
+  const int nm1 = (P.my > P.ny ? P.my : P.ny) + 1;
+  return P.CS + 2 * nm1;
+}
+
+__device__ inline void stage_eval_schur(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
+  const int lane = threadIdx.x;
+  const PrimeConst pc = T.pc[P.pidx[w.slot]];
+  const uint32_t p = pc.p, pinv = pc.pinv, one = pc.r1;
+  uint32_t* tile = lds;
+  const uint32_t* src = P.resid + static_cast<size_t>(w.slot) * P.CS;
+  for (int t = lane; t < P.CS; t += 64) tile[t] = src[t];
+  const int nm1 = (P.my > P.ny ? P.my : P.ny) + 1;
+  uint32_t* colA = lds + P.CS;  // columns of the one-lane fallback
+  uint32_t* colB = colA + nm1;
+  __syncthreads();
+  const int m = P.my, n = P.ny, r = m + n;
+  const bool two = n > 0 && m > 0;
+  const int nxa = P.rowf, nxb = P.rowg;
+  const int nx = nxa > nxb ? nxa : nxb;
+  const int ra = m - lane, rb = n - lane;  // this lane's rows of f and g
+  for (int s = 0; s < kSchurPts; ++s) {
+    const int pt = w.blk * kSchurPts + s;
+    if (pt > P.E) break;
+    const uint32_t x = static_cast<uint32_t>(P.origin + pt);
+    const uint32_t xt = mmul(x, pc.r2, p, pinv);
+    // Horner in x over every power (zero coefficients beyond a row's degree);
+    // values stay below 2p as in horner_step4
+    auto hstep = [&](uint32_t acc, uint32_t c) {
+      const uint64_t t = static_cast<uint64_t>(acc) * xt + c;
+      const uint32_t mq = static_cast<uint32_t>(t) * pinv;
+      return static_cast<uint32_t>((t + static_cast<uint64_t>(mq) * p) >> 32);
+    };
+    uint32_t av = 0u, bv = 0u;
+    for (int i = nx - 1; i >= 0; --i) {
+      av = hstep(av, (ra >= 0 && i < nxa) ? tile[i * P.myp + ra] : 0u);
+      bv = hstep(bv, (rb >= 0 && i < nxb) ? tile[P.goff + i * P.nyp + rb] : 0u);
+    }
+    av = umin32(av, av - p);
+    bv = umin32(bv, bv - p);
+    const uint32_t lcf = __builtin_amdgcn_readlane(av, 0), lcg = __builtin_amdgcn_readlane(bv, 0);
+    bool bad = (lcf == 0u) || (lcg == 0u);
+    uint32_t res = 0u;
+    bool done = false;
+    if (!bad && two && r <= kSchurMaxR) {
+      uint32_t G0 = (lane == 0) ? one : 0u, G1 = (lane == n) ? one : 0u;
+      uint32_t B0 = av, B1 = bv;  // S[0][l] = a_{m-l}, S[n][l] = b_{n-l}
+      uint32_t num = one, den = one, sigma = one;
+      done = true;
+      for (int k = 0; k < r; ++k) {
+        const uint32_t ga = __builtin_amdgcn_readlane(G0, k), gb = __builtin_amdgcn_readlane(G1, k);
+        const uint32_t ba = __builtin_amdgcn_readlane(B0, k), bb = __builtin_amdgcn_readlane(B1, k);
+        const uint32_t d = mmulsub(ga, ba, mneg(gb, p), bb, p, pinv);  // ga ba + gb bb
+        num = mmul(num, d, p, pinv);
+        den = mmul(den, sigma, p, pinv);
+        if (k == r - 1) break;
+        if (d == 0u) {  // a vanishing leading minor
+          done = false;
+          break;
+        }
+        const uint32_t xg = mmulsub(gb, G0, ga, G1, p, pinv);
+        const uint32_t yb = mmulsub(bb, B0, ba, B1, p, pinv);
+        const uint32_t c = mmulsub(G0, ba, mneg(G1, p), bb, p, pinv);  // G b0
+        const uint32_t u = mmulsub(ga, B0, mneg(gb, p), B1, p, pinv);  // B g0
+        const uint32_t cprev = static_cast<uint32_t>(__shfl_up(static_cast<int>(c), 1, 64));
+        const uint32_t uprev = static_cast<uint32_t>(__shfl_up(static_cast<int>(u), 1, 64));
+        if (lane > k) {
+          G0 = xg;
+          G1 = (lane == n) ? 0u : ((lane == k + 1) ? d : cprev);
+          B0 = yb;
+          B1 = (lane == k + 1) ? d : uprev;
+        }
+        sigma = mmul(sigma, d, p, pinv);
+      }
+      if (done) res = (num == 0u) ? 0u : mmul(num, minv(den, one, p, pinv), p, pinv);
+    }
+    if (!done) {
+      // remainder sequence in lane 0 on the evaluated coefficients
+      if (ra >= 0) colA[ra] = av;
+      if (rb >= 0) colB[rb] = bv;
+      WaveSync()();
+      if (lane == 0) res = ures_formal(Column<1>{colA}, Column<1>{colB}, m, n, pc, &bad);
+      WaveSync()();
+    }
+    if (lane == 0) {
+      const size_t o = static_cast<size_t>(w.slot) * (P.E + 1) + pt;
+      P.zval[o] = redc(res, p, pinv);
+      P.zbad[o] = bad ? 1 : 0;
+    }
+    eval_report_bad(P, w.slot, pt, lane == 0, bad);
+  }
+}
+
 // LDS words of the evaluation launch for the problem's layout.
 __host__ __device__ inline int eval_stage_lds_words(const DevProblem& P) {
+  if (P.schur) return eval_schur_lds_words(P);
   if (P.evk == 2 && P.regn) return eval_regs2_lds_words(P, P.regn);
   if (P.evk > 1) return eval_group_lds_words(P, P.evk);
   return P.regn ? eval_regs_lds_words(P, P.regn) : eval_lds_words(P);
@@ -647,9 +766,11 @@ enum : int {
   kEvG4,        // four lanes per pair, LDS columns
   kEvR8, kEvR16, kEvR24, kEvR32,  // one lane per pair, registers (degree bound)
   kEvP8, kEvP16, kEvP24, kEvP32,  // two lanes per pair, registers
+  kEvSchur,     // one wave per pair, Schur algorithm on the Sylvester generators
   kEvNum
 };
 __host__ __device__ inline int eval_variant(const DevProblem& P) {
+  if (P.schur) return kEvSchur;
   const int r = P.regn == 8 ? 0 : P.regn == 16 ? 1 : P.regn == 24 ? 2 : 3;
   if (P.evk == 2 && P.regn) return kEvP8 + r;
   if (P.evk == 2) return kEvG2;
@@ -663,6 +784,7 @@ __device__ inline void stage_eval_variant(const DevProblem& P, const DevTables& 
   else if constexpr (V == kEvG2) stage_eval_ures_group<2>(P, T, w, lds);
   else if constexpr (V == kEvG4) stage_eval_ures_group<4>(P, T, w, lds);
   else if constexpr (V >= kEvR8 && V <= kEvR32) stage_eval_ures_regs<8 * (V - kEvR8 + 1)>(P, T, w, lds);
+  else if constexpr (V == kEvSchur) stage_eval_schur(P, T, w, lds);
   else stage_eval_ures_regs2<8 * (V - kEvP8 + 1)>(P, T, w, lds);
 }
 

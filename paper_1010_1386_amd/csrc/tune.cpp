@@ -281,7 +281,7 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   if (ctx->poisoned) return RSL_EDEVICE;
   if (j->J.live.empty()) {
-    if (best) *best = rsl_tune_result{RSL_STAGED, j->J.tune.chunk_target, 1, 1, 0, 0, 0.0, 0.0};
+    if (best) *best = rsl_tune_result{RSL_STAGED, j->J.tune.chunk_target, 1, 1, 0, 0, 0, 0.0, 0.0};
     return RSL_OK;
   }
   // coordinate search: schedule x lanes per pair at the default chunking, then
@@ -289,7 +289,14 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
   std::vector<TuneConfig> cands;
   for (int evk : {1, 2, 4})
     for (int mode : {RSL_STAGED, RSL_BATCHED})
-      if (mode == RSL_STAGED || j->J.max_np <= kMaxSlots) cands.push_back(TuneConfig{mode, 4096, 1, evk, 0});
+      if (mode == RSL_STAGED || j->J.max_np <= kMaxSlots) cands.push_back(TuneConfig{mode, 4096, 1, evk, 0, 0});
+  // the Schur evaluation (one wave per pair) when every problem's shape allows it
+  bool schur_ok = true;
+  for (int k : j->J.live) {
+    const Plan& P = j->J.plans[k];
+    schur_ok = schur_ok && P.my >= 1 && P.ny >= 1 && P.my + P.ny <= kSchurMaxR;
+  }
+  if (schur_ok) cands.push_back(TuneConfig{RSL_STAGED, 4096, 1, 1, 0, 1});
   const size_t phase1 = cands.size();
   std::vector<uint8_t> ref;
   TuneConfig win = cands[0];
@@ -321,7 +328,7 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
       return fail(ctx, RSL_EDEVICE,
                   "autotuner: candidate (mode " + std::to_string(tc.mode) + ", chunk target " +
                       std::to_string(tc.chunk_target) + ", grid x" + std::to_string(tc.grid_mult) +
-                      ", lanes per pair " + std::to_string(tc.evk) +
+                      ", lanes per pair " + std::to_string(tc.evk) + ", Schur " + std::to_string(tc.schur) +
                       ") differs from the first candidate in its statuses or outputs (byte " + std::to_string(at) +
                       " of the compared image)");
     }
@@ -340,14 +347,14 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
       win = tc;
     }
     if (ci + 1 == phase1) {  // phase two around the winner of phase one
-      for (int target : {1024, 16384}) cands.push_back(TuneConfig{win.mode, target, 1, win.evk, 0});
-      cands.push_back(TuneConfig{win.mode, 4096, 1, win.evk, 1});
-      if (win.mode == RSL_BATCHED) cands.push_back(TuneConfig{RSL_BATCHED, 4096, 2, win.evk, 0});
+      for (int target : {1024, 16384}) cands.push_back(TuneConfig{win.mode, target, 1, win.evk, 0, win.schur});
+      cands.push_back(TuneConfig{win.mode, 4096, 1, win.evk, 1, win.schur});
+      if (win.mode == RSL_BATCHED) cands.push_back(TuneConfig{RSL_BATCHED, 4096, 2, win.evk, 0, 0});
     }
   }
   if ((rc = materialize(ctx, j, win))) return rc;
   ctx->tune_cache[tune_key(j->J)] = TuneEntry{win, win_ms};
-  if (best) *best = rsl_tune_result{win.mode, win.chunk_target, win.grid_mult, win.evk, win.conv_whole,
+  if (best) *best = rsl_tune_result{win.mode, win.chunk_target, win.grid_mult, win.evk, win.conv_whole, win.schur,
                                     static_cast<int32_t>(cands.size()), win_ms, worst_ms};
   return RSL_OK;
 }
@@ -360,7 +367,7 @@ int rsl_tune_save(rsl_ctx* ctx, const char* path) {
   for (const auto& kv : ctx->tune_cache)
     os << kv.first << " " << kv.second.cfg.mode << " " << kv.second.cfg.chunk_target << " "
        << kv.second.cfg.grid_mult << " " << kv.second.cfg.evk << " " << kv.second.cfg.conv_whole << " "
-       << kv.second.ms << "\n";
+       << kv.second.cfg.schur << " " << kv.second.ms << "\n";
   return RSL_OK;
 }
 
@@ -371,10 +378,12 @@ int rsl_tune_load(rsl_ctx* ctx, const char* path) {
   if (!is) return fail(ctx, RSL_EINVAL, std::string("cannot read ") + path);
   std::string key;
   TuneEntry e;
-  while (is >> key >> e.cfg.mode >> e.cfg.chunk_target >> e.cfg.grid_mult >> e.cfg.evk >> e.cfg.conv_whole >> e.ms) {
+  while (is >> key >> e.cfg.mode >> e.cfg.chunk_target >> e.cfg.grid_mult >> e.cfg.evk >> e.cfg.conv_whole >>
+         e.cfg.schur >> e.ms) {
     if ((e.cfg.mode != RSL_STAGED && e.cfg.mode != RSL_BATCHED) || e.cfg.chunk_target < 64 || e.cfg.grid_mult < 1 ||
         e.cfg.grid_mult > 8 || (e.cfg.evk != 1 && e.cfg.evk != 2 && e.cfg.evk != 4) ||
-        (e.cfg.conv_whole != 0 && e.cfg.conv_whole != 1))
+        (e.cfg.conv_whole != 0 && e.cfg.conv_whole != 1) || (e.cfg.schur != 0 && e.cfg.schur != 1) ||
+        (e.cfg.schur && e.cfg.mode != RSL_STAGED))
       return fail(ctx, RSL_EINVAL, "malformed tuning cache line for " + key);
     ctx->tune_cache[key] = e;
   }

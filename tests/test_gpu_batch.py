@@ -93,8 +93,9 @@ def test_autotuner_keeps_bits_and_caches_choice(ctx, tmp_path):
     ctx.tune_save(str(path))
     lines = path.read_text().split("\n")
     assert len([l for l in lines if l.strip()]) == 1
-    key, mode, target, gm, evk, cw, ms = lines[0].split()
+    key, mode, target, gm, evk, cw, sch, ms = lines[0].split()
     assert int(mode) in (1, 2) and int(target) >= 64 and int(gm) >= 1 and int(evk) in (1, 2, 4)
+    assert int(sch) in (0, 1)
     import paper_1010_1386_amd as rsl
     c2 = rsl.Context(device=0, workspace_bytes=256 << 20)
     c2.tune_load(str(path))
@@ -103,7 +104,7 @@ def test_autotuner_keeps_bits_and_caches_choice(ctx, tmp_path):
     assert j2.results() == want
     j2.close()
     bad = tmp_path / "bad.txt"
-    bad.write_text(key + " 7 4096 1 1 0 1.0\n")
+    bad.write_text(key + " 7 4096 1 1 0 0 1.0\n")
     with pytest.raises(rsl.RSLError):
         c2.tune_load(str(bad))
     c2.close()
@@ -232,3 +233,39 @@ def test_both_projections_in_one_call(ctx):
         ry, rx = ctx.res_xy(f, g)
         assert ry == ctx.res(f, g, "y") and rx == ctx.res(f, g, "x")
         assert ry == oracle.res(f, g, "y") and rx == oracle.res(f, g, "x")
+
+
+def test_schur_evaluation_matches_remainder_sequence(ctx):
+    """The Schur evaluation (generators of the Sylvester matrix, one wave per pair)
+    gives the bits of the remainder sequence: mixed problems (zero inputs, bad
+    points, constant degrees), degrees up to 24 + 24, a pair whose leading minor
+    vanishes at every point (every point takes the fallback), formal points,
+    extra points and a shifted origin; the oracle on the small problems."""
+    import paper_1010_1386_amd as rsl
+    rng = rng_for(719, 0)
+    small = mixed_batch(15, 21)
+    a = dense_total(rng, 3, 8)[0]
+    h, c, k = dense_total(rng, 2, 8)[0], dense_total(rng, 2, 8)[0], dense_total(rng, 1, 8)[0]
+    a = a or [1]
+    # f = a y^3 + 2a y^2 + h y + c, g = k (3 y + 6): a 6k - 2a 3k = 0 at every x
+    F = [c, h, [2 * v for v in a], a]
+    G = [[6 * v for v in k], [3 * v for v in k]]
+    small.append((F, G, "y"))
+    big = [(dense_total(rng, 24, 32), dense_total(rng, 24, 32), "y"),
+           (dense_total(rng, 12, 16), sparse_total(rng, 10, 16), "x")]
+    probs = small + big
+    want = [oracle.res(f, g, v) for f, g, v in small]
+    for opts in ({}, {"points": "formal"}, {"extra_points": 3}, {"point_origin": 1000}):
+        js = ctx.job(probs, eval_schur=True, **opts)
+        jr = ctx.job(probs, **opts)
+        for mode in ("staged", "plain"):
+            js.run(mode)
+            jr.run(mode)
+            got = js.results()
+            assert got == jr.results(), (opts, mode)
+            assert got[:len(small)] == want, (opts, mode)
+        with pytest.raises(rsl.RSLError) as ei:
+            js.run("batched")
+        assert ei.value.code == rsl.RSL_EINVAL
+        js.close()
+        jr.close()
