@@ -51,6 +51,10 @@ struct DevProblem {
   int crt_garner;    // 1: CRT by Garner's digits only (test hook), 0: direct form with Garner fallback
   int schur;         // 1: univariate resultants by the Schur algorithm (one wave per pair)
   int wide;          // 1: CRT by the wide path (more primes than the per-lane slots cover)
+  // the same system eliminated in x (the next problem): the reduction of prime
+  // slots < pshared also writes its residue tiles (transposed positions)
+  int pshared, pmyp, pnyp, pgoff, pCS;
+  uint32_t* presid;
   int Lw;            // limbs of the rows of Mi and of negM: L_out, or L_out + 1 for the wide path
   // inputs (uploaded)
   const uint32_t* coeff;  // ncoef * L_in two's complement limbs

@@ -63,7 +63,26 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     const Plan& P = J->plans[k];
     cost[k] = pair_mulmods(P) * P.np * (P.E + 1);
   }
-  std::stable_sort(J->live.begin(), J->live.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  // a system eliminated in y directly followed by the same system eliminated in
+  // x shares the reduction of their common primes: the y problem writes both
+  // residue tiles (pair_of[k] = the y problem of x problem k)
+  std::vector<int> pair_of(n, -1);
+  auto same_poly = [](const rsl_poly& a, const rsl_poly& b) {
+    if (a.dx != b.dx || a.dy != b.dy || a.limbs != b.limbs) return false;
+    if (a.coeff == b.coeff) return true;
+    const size_t words = static_cast<size_t>(a.dx + 1) * (a.dy + 1) * a.limbs;
+    return std::memcmp(a.coeff, b.coeff, words * 4) == 0;
+  };
+  for (int k = 1; k < n; ++k)
+    if (var[k] == RSL_X && var[k - 1] == RSL_Y && !J->pstatus[k] && !J->pstatus[k - 1] &&
+        !J->plans[k].zero && !J->plans[k - 1].zero && same_poly(f[k], f[k - 1]) && same_poly(g[k], g[k - 1]))
+      pair_of[k] = k - 1;
+  std::stable_sort(J->live.begin(), J->live.end(), [&](int a, int b) {
+    // a pair ranks by its y problem, the x problem right after it
+    const int ra = pair_of[a] >= 0 ? pair_of[a] : a, rb = pair_of[b] >= 0 ? pair_of[b] : b;
+    if (ra == rb) return pair_of[b] >= 0 && pair_of[a] < 0;
+    return cost[ra] > cost[rb] || (cost[ra] == cost[rb] && ra < rb);
+  });
   if (ctx && !J->live.empty()) {
     int rc = ensure_tables(ctx, maxg, maxE, maxD);
     if (rc) { *err = ctx->err; return rc; }
@@ -72,6 +91,24 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   const int nl = static_cast<int>(J->live.size());
   J->lay.assign(nl, ProbLayout());
   J->dev.assign(nl, DevProblem());
+  J->partner.assign(nl, -1);
+  J->pshared.assign(nl, 0);
+  J->skip_reduce.assign(nl, 0);
+  {
+    std::vector<int> li_of(n, -1);
+    for (int li = 0; li < nl; ++li) li_of[J->live[li]] = li;
+    for (int k = 0; k < n; ++k) {
+      if (pair_of[k] < 0) continue;
+      const int la = li_of[pair_of[k]], lb = li_of[k];
+      const Plan &A = J->plans[pair_of[k]], &B = J->plans[k];
+      int ns = 0;
+      while (ns < A.np && ns < B.np && A.pidx[ns] == B.pidx[ns]) ++ns;
+      if (ns == 0) continue;
+      J->partner[la] = lb;
+      J->pshared[la] = ns;
+      J->skip_reduce[lb] = ns;
+    }
+  }
   J->pairs = 0;
   J->mulmods = 0;
   // stir chunking: enough blocks in flight to cover HBM latency
@@ -169,6 +206,16 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   }
 
   if (J->crt_ns == 5 || J->crt_ns == 7) ++J->crt_ns;  // CRT kernels exist for 1-4, 6 and 8 slots per lane
+  for (int li = 0; li < nl; ++li)
+    if (J->partner[li] >= 0) {
+      const DevProblem& b = J->dev[J->partner[li]];
+      DevProblem& a = J->dev[li];
+      a.pshared = J->pshared[li];
+      a.pmyp = b.myp;
+      a.pnyp = b.nyp;
+      a.pgoff = b.goff;
+      a.pCS = b.CS;
+    }
 
   // work items, problem by problem (so that each problem's items are contiguous)
   for (int li = 0; li < nl; ++li) {
@@ -176,12 +223,19 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     const DevProblem& d = J->dev[li];
     ProbLayout& L = J->lay[li];
     for (int s = 0; s < kNumStages; ++s) L.item_begin[s] = static_cast<int>(J->items[s].size());
+    // slots below skip_reduce are reduced by the partner (the same system in y);
+    // item slot 0 of block 0 also clears the statuses, so a problem whose
+    // slots are all shared keeps one such item
+    const int s0 = J->skip_reduce[li];
     if (d.L_in > 2) {  // long limb chains: staged limbs, eight primes per thread
-      for (int sl = 0; sl < P.np; sl += kReduceMlSlots)
+      const int first = (s0 / kReduceMlSlots) * kReduceMlSlots;
+      for (int sl = first; sl < P.np; sl += kReduceMlSlots)
         for (int b = 0; b < blocks_of(d.CS, kReduceMlCoeffs); ++b) J->items[kStageReduce].push_back({li, sl, b, 1});
+      if (first >= P.np) J->items[kStageReduce].push_back({li, 0, 0, 1});
     } else {
-      for (int sl = 0; sl < P.np; ++sl)
+      for (int sl = s0; sl < P.np; ++sl)
         for (int b = 0; b < blocks_of(d.CS, 256); ++b) J->items[kStageReduce].push_back({li, sl, b, 0});
+      if (s0 > 0) J->items[kStageReduce].push_back({li, 0, 0, 0});
     }
     for (int sl = 0; sl < P.np; ++sl)
       for (int b = 0; b < blocks_of(P.E + 1, d.evpb); ++b) J->items[kStageEval].push_back({li, sl, b, 0});
@@ -564,6 +618,8 @@ void job_bind(Job* J, uint8_t* base) {
     d.out = reinterpret_cast<uint32_t*>(base + L.out);
     d.status = reinterpret_cast<int*>(base + L.status);
   }
+  for (int li = 0; li < nl; ++li)
+    J->dev[li].presid = (J->partner[li] >= 0) ? reinterpret_cast<uint32_t*>(base + J->lay[J->partner[li]].resid) : nullptr;
   // initial queue image: one REDUCE task per (problem, prime slot), largest problems first
   // (none when a problem has more primes than the persistent schedule takes)
   if (J->max_np <= kMaxSlots) {
@@ -642,7 +698,15 @@ int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st, uint8_t* pinned) {
     pinned = ctx->h_up;
   }
   std::memcpy(pinned, J->blob.data(), J->up_bytes);
-  return hip_check(ctx, hipMemcpyAsync(J->base, pinned, J->up_bytes, hipMemcpyHostToDevice, st), "upload");
+  int rc = hip_check(ctx, hipMemcpyAsync(J->base, pinned, J->up_bytes, hipMemcpyHostToDevice, st), "upload");
+  // the residue tiles a partner fills get their padding cleared once (the
+  // partner writes only the coefficient positions)
+  for (size_t li = 0; !rc && li < J->live.size(); ++li)
+    if (J->skip_reduce[li] > 0)
+      rc = hip_check(ctx, launch_copy_words(J->dev[li].resid, nullptr,
+                                            static_cast<size_t>(J->skip_reduce[li]) * J->dev[li].CS, st),
+                     "clear shared tiles");
+  return rc;
 }
 
 int job_reset(rsl_ctx* ctx, Job* J, hipStream_t st) {

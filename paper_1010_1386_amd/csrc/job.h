@@ -59,6 +59,10 @@ struct Job {
   int crt_ns = 1;
   int max_np = 0;                  // most primes of any live problem
   bool any_schur = false;          // some problem evaluates by the Schur algorithm
+  // live index of the partner (the same system eliminated in x) that a
+  // problem's reduction also fills, -1 if none; prime slots shared
+  std::vector<int> partner, pshared;
+  std::vector<int> skip_reduce;     // leading prime slots a problem's partner reduces for it
   size_t probs_off = 0;
   size_t up_bytes = 0;             // [0, up_bytes) is uploaded
   size_t down_off = 0, down_bytes = 0;  // statuses + outputs, downloaded

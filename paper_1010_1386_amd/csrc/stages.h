@@ -115,6 +115,19 @@ __device__ __forceinline__ void horner_step2x2(uint32_t* a, uint32_t* b, uint32_
 // myp), then g part [i][j] (j padded to nyp).  Stores c R^2 mod p (0 for padding).
 // With zero_status, the block of (slot 0, block 0) also clears the problem's
 // status words (a launch that runs before every other stage of the problem).
+// Position in the partner's tiles (the system eliminated in x) of the
+// coefficient at tile position t (inside the f or g rectangle): x^i y^j there
+// is y'^i x'^j, so [x-power i][row j] becomes [x'-power j][row i].
+__device__ inline int partner_pos(const DevProblem& P, int t) {
+  if (t < P.goff) {
+    const int i = t / P.myp, j = t - i * P.myp;
+    return j * P.pmyp + i;
+  }
+  const int u = t - P.goff;
+  const int i = u / P.nyp, j = u - i * P.nyp;
+  return P.pgoff + j * P.pnyp + i;
+}
+
 __device__ inline void stage_reduce(const DevProblem& P, const DevTables& T, const WorkItem& w,
                                     bool zero_status = false) {
   if (zero_status && w.slot == 0 && w.blk == 0)
@@ -151,6 +164,7 @@ __device__ inline void stage_reduce(const DevProblem& P, const DevTables& T, con
       r = maddm(mmul(r, pc.r2, p, pc.pinv), wl, p);
     }
     v = mmul(r, pc.r3, p, pc.pinv);
+    if (w.slot < P.pshared) P.presid[static_cast<size_t>(w.slot) * P.pCS + partner_pos(P, t)] = v;
   }
   P.resid[static_cast<size_t>(w.slot) * P.CS + t] = v;
 }
@@ -227,11 +241,15 @@ __device__ inline void stage_reduce_ml(const DevProblem& P, const DevTables& T, 
     }
   }
   if (t >= P.CS) return;
+  const int tp = (in >= 0 && w.slot < P.pshared) ? partner_pos(P, t) : 0;
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
     const int sl = w.slot + q + 4 * r;
-    if (sl < P.np)
-      P.resid[static_cast<size_t>(sl) * P.CS + t] = (in >= 0) ? mmul(acc[r], r3[r], p[r], pinv[r]) : 0u;
+    if (sl < P.np) {
+      const uint32_t v = (in >= 0) ? mmul(acc[r], r3[r], p[r], pinv[r]) : 0u;
+      P.resid[static_cast<size_t>(sl) * P.CS + t] = v;
+      if (in >= 0 && sl < P.pshared) P.presid[static_cast<size_t>(sl) * P.pCS + tp] = v;
+    }
   }
 }
 

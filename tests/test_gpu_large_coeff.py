@@ -158,3 +158,21 @@ def test_beyond_4096_primes_is_refused(rsl, ctx):
     with pytest.raises(rsl.RSLError) as ei:
         ctx.res(f, g, "y")
     assert ei.value.code == rsl.RSL_EINVAL
+
+
+def test_joint_projections_share_the_reduction(rsl, ctx):
+    """res_y and res_x of one system in one job: the y problem's reduction also
+    fills the x problem's residue tiles for their common primes.  Equal to the
+    separate calls in every schedule, with 5-limb (dense and sparse) and
+    one-limb inputs, and with the x problem needing more or fewer primes."""
+    rng = rng_for(720, 0)
+    systems = [workloads.table3_curves(9, 128)[0], workloads.table3_curves(9, 128, sparse=True)[1],
+               (dense_total(rng, 6, 20), dense_total(rng, 4, 30)),
+               (small_random(rng, 2, 7, 40), small_random(rng, 5, 1, 12))]
+    for F, G in systems:
+        sep = [ctx.res(F, G, "y"), ctx.res(F, G, "x")]
+        assert list(ctx.res_xy(F, G)) == sep
+        for mode in ("staged", "plain", "batched"):
+            assert ctx.batch([(F, G, "y"), (F, G, "x")], mode=mode) == sep, mode
+    F, G = systems[3]
+    assert rsl.query(F, G, "y")["n_primes"] != rsl.query(F, G, "x")["n_primes"]
