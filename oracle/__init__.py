@@ -21,6 +21,9 @@ What it computes, and where the paper defines it:
 * ``res_at_int_point`` -- exact integer Bareiss determinant of the Sylvester
   matrix specialised at an integer x0 (formal degrees), used for exact point
   checks where the full oracle is too slow.
+* ``zx_gcd`` / ``sqfree_part`` / ``yun`` -- gcd, square-free part and the
+  square-free factorisation (Yun's algorithm) over Z[x] for the Project step
+  (Sec. 3.2), by the primitive Euclidean algorithm with exact integers.
 
 Parity status of each function is documented in its docstring; all of them
 are pinned by tests in ``tests/test_oracle_*.py``.
@@ -32,6 +35,7 @@ from .resultant import (sylvester, bareiss_det, res, res_y, res_x, leibniz_det,
                         degree_bound, hadamard_bound_sq)
 from .modular import (det_mod, res_at_point_mod, res_at_int_point, poly_eval_mod,
                       is_probable_prime, next_check_primes)
+from .sqfree import (zx_gcd, zx_pp, zx_content, zx_deriv, zx_divexact, sqfree_part, yun)
 
 __all__ = [
     "padd", "psub", "pmul", "pdivexact", "ptrim", "peval", "pcompose_y",
@@ -40,4 +44,5 @@ __all__ = [
     "degree_bound", "hadamard_bound_sq",
     "det_mod", "res_at_point_mod", "res_at_int_point", "poly_eval_mod",
     "is_probable_prime", "next_check_primes",
+    "zx_gcd", "zx_pp", "zx_content", "zx_deriv", "zx_divexact", "sqfree_part", "yun",
 ]
