@@ -188,6 +188,50 @@ int rsl_res_x(rsl_ctx *ctx, const rsl_poly *f, const rsl_poly *g, rsl_result *ou
  */
 int rsl_res_xy(rsl_ctx *ctx, const rsl_poly *f, const rsl_poly *g, const rsl_opts *opts, rsl_result *out_y,
                rsl_result *out_x);
+/* The x problem of such a pair also takes its residues of the common primes
+ * from the y problem's reduction (the tiles are each other's transposes). */
+
+/* ------------------------------------------- gcd and square-free part in Z[x]
+ * The step after the resultant: the solver's Project step (paper Sec. 3.2)
+ * takes a square-free factorisation of R by Yun's algorithm, i.e. gcds of R
+ * and its derivatives, and the paper's outlook (Sec. 6) proposes the modular
+ * route for it.
+ *
+ * A univariate input: deg + 1 coefficients, lowest power first, each `limbs`
+ * little-endian 32-bit limbs in two's complement (deg -1 or all-zero: the zero
+ * polynomial; leading zero coefficients are trimmed).  Host memory, caller
+ * owned, read during the call only.
+ */
+typedef struct {
+  int32_t deg;
+  int32_t limbs;
+  const uint32_t *coeff;
+} rsl_upoly;
+
+/*
+ * G = gcd(pp(u), pp(v)) in Z[x] (primitive, positive leading coefficient; the
+ * zero polynomial when u = v = 0) and the exact cofactors u / G and v / G, by
+ * the modular route: per prime (not dividing a leading coefficient) Euclid's
+ * algorithm over Z_p on the device, the gcd made monic and scaled by
+ * gcd(lc u, lc v); the primes of least gcd degree kept; Chinese remaindering,
+ * the content of the scaled gcd removed modulo each prime, the cofactors by
+ * exact long division modulo each prime.  The kept primes' product exceeds
+ * twice (deg u + deg v + 2) times Mignotte's bounds on G and on the cofactors,
+ * and every reconstructed coefficient is checked against its bound, so the
+ * identities G (u/G) = u and G (v/G) = v hold over Z (the result is certified,
+ * not probabilistic).  Synchronous; uses the context workspace (RSL_ENOMEM
+ * when it is too small).  Any of g, ug, vg may be NULL.  Output buffers as in
+ * rsl_res (RSL_ERANGE with deg and needed_limbs set when too small).
+ */
+int rsl_gcd(rsl_ctx *ctx, const rsl_upoly *u, const rsl_upoly *v, rsl_result *g, rsl_result *ug,
+            rsl_result *vg);
+
+/*
+ * Square-free part: g = gcd(pp(r), pp(r)') and q = r / g (the content and sign
+ * of r stay in q; pp(q) is the square-free part of r).  Computed as
+ * rsl_gcd(r, r').  Either output may be NULL.
+ */
+int rsl_sqfree_part(rsl_ctx *ctx, const rsl_upoly *r, rsl_result *q, rsl_result *g);
 
 /*
  * A batch of n independent problems (f[k], g[k], var[k]) -> out[k].

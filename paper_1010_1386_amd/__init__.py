@@ -86,6 +86,10 @@ class rsl_job_info(ctypes.Structure):
                 ("chunk_target", ctypes.c_int32), ("grid_mult", ctypes.c_int32), ("eval_lanes", ctypes.c_int32)]
 
 
+class rsl_upoly(ctypes.Structure):
+    _fields_ = [("deg", ctypes.c_int32), ("limbs", ctypes.c_int32), ("coeff", ctypes.POINTER(ctypes.c_uint32))]
+
+
 class rsl_tune_result(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("chunk_target", ctypes.c_int32), ("grid_mult", ctypes.c_int32),
                 ("evk", ctypes.c_int32), ("conv_whole", ctypes.c_int32), ("schur", ctypes.c_int32),
@@ -106,6 +110,8 @@ _SIGS = {
     "rsl_res_y": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), _P(rsl_result)]),
     "rsl_res_x": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), _P(rsl_result)]),
     "rsl_res_xy": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), _P(rsl_opts), _P(rsl_result), _P(rsl_result)]),
+    "rsl_gcd": (ctypes.c_int, [_vp, _P(rsl_upoly), _P(rsl_upoly), _P(rsl_result), _P(rsl_result), _P(rsl_result)]),
+    "rsl_sqfree_part": (ctypes.c_int, [_vp, _P(rsl_upoly), _P(rsl_result), _P(rsl_result)]),
     "rsl_batch": (ctypes.c_int, [_vp, ctypes.c_int, _P(rsl_poly), _P(rsl_poly), _P(ctypes.c_int),
                                  _P(rsl_result), _P(ctypes.c_int), ctypes.c_int]),
     "rsl_last_counters": (ctypes.c_int, [_vp, _P(rsl_counters)]),
@@ -184,6 +190,23 @@ class Poly:
                 self.buf = np.frombuffer(raw, dtype=np.uint32).copy()
         self.c = rsl_poly(self.dx, self.dy, self.limbs,
                           self.buf.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+
+
+class UPoly:
+    """A univariate integer polynomial (list, lowest power first) packed as C-ABI limbs."""
+
+    def __init__(self, a):
+        vals = [int(v) for v in a]
+        bits = max((v.bit_length() + 1 for v in vals), default=1)
+        self.limbs = max(1, (bits + 31) // 32)
+        nb = 4 * self.limbs
+        raw = b"".join(v.to_bytes(nb, "little", signed=True) for v in vals) or bytes(nb)
+        self.buf = np.frombuffer(raw, dtype=np.uint32).copy()
+        self.deg = len(vals) - 1
+        self.c = rsl_upoly(self.deg, self.limbs, self.buf.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+        # size of any factor's coefficients (Mignotte): deg + log2 ||a||_2 bits
+        norm2 = sum(v * v for v in vals)
+        self.factor_bits = max(self.deg, 0) + (norm2.bit_length() + 2) // 2 + 2
 
 
 def _as_poly(F):
@@ -321,6 +344,29 @@ class Context:
                                  ctypes.byref(outs[0].c), ctypes.byref(outs[1].c))
         self._check(rc, "rsl_res_xy")
         return outs[0].value(), outs[1].value()
+
+    def gcd(self, u, v):
+        """(G, u / G, v / G): G = gcd(pp(u), pp(v)) in Z[x], primitive with positive
+        leading coefficient; polynomials as lists of ints, lowest power first."""
+        pu, pv = UPoly(u), UPoly(v)
+        bits = max(pu.factor_bits, pv.factor_bits)
+        limbs = bits // 32 + 2
+        outs = [_Result(max(pu.deg, pv.deg, 0), limbs) for _ in range(3)]
+        with self.lock:
+            rc = _lib.rsl_gcd(self.h, ctypes.byref(pu.c), ctypes.byref(pv.c), ctypes.byref(outs[0].c),
+                              ctypes.byref(outs[1].c), ctypes.byref(outs[2].c))
+        self._check(rc, "rsl_gcd")
+        return tuple(o.value() for o in outs)
+
+    def sqfree_part(self, r):
+        """(q, g): g = gcd(pp(r), pp(r)'), q = r / g (pp(q) is the square-free part)."""
+        pr = UPoly(r)
+        limbs = pr.factor_bits // 32 + 2
+        outs = [_Result(max(pr.deg, 0), limbs) for _ in range(2)]
+        with self.lock:
+            rc = _lib.rsl_sqfree_part(self.h, ctypes.byref(pr.c), ctypes.byref(outs[0].c), ctypes.byref(outs[1].c))
+        self._check(rc, "rsl_sqfree_part")
+        return tuple(o.value() for o in outs)
 
     def batch(self, problems, mode="batched"):
         """problems: list of (f, g, var); returns a list of results (lists of ints)."""

@@ -147,6 +147,53 @@ struct BigU {
     return out;
   }
 
+  // a >> k bits
+  BigU shr(int k) const {
+    BigU r;
+    const int w = k / 32, b = k % 32;
+    if (static_cast<size_t>(w) >= d.size()) return r;
+    r.d.resize(d.size() - w);
+    for (size_t i = 0; i < r.d.size(); ++i) {
+      const uint64_t lo = d[i + w], hi = (i + w + 1 < d.size()) ? d[i + w + 1] : 0u;
+      r.d[i] = static_cast<uint32_t>(((hi << 32) | lo) >> b);
+    }
+    while (!r.d.empty() && r.d.back() == 0u) r.d.pop_back();
+    return r;
+  }
+  int ctz() const {  // trailing zero bits (0 for zero)
+    for (size_t i = 0; i < d.size(); ++i)
+      if (d[i]) return static_cast<int>(32 * i) + __builtin_ctz(d[i]);
+    return 0;
+  }
+  // a << k bits
+  BigU shl(int k) const {
+    if (d.empty()) return BigU();
+    BigU r;
+    const int w = k / 32, b = k % 32;
+    r.d.assign(d.size() + w + 1, 0u);
+    for (size_t i = 0; i < d.size(); ++i) {
+      const uint64_t v = static_cast<uint64_t>(d[i]) << b;
+      r.d[i + w] |= static_cast<uint32_t>(v);
+      r.d[i + w + 1] |= static_cast<uint32_t>(v >> 32);
+    }
+    while (!r.d.empty() && r.d.back() == 0u) r.d.pop_back();
+    return r;
+  }
+  // greatest common divisor (binary algorithm; gcd(0, b) = b)
+  static BigU gcd(BigU a, BigU b) {
+    if (a.is_zero()) return b;
+    if (b.is_zero()) return a;
+    const int za = a.ctz(), zb = b.ctz(), z = za < zb ? za : zb;
+    a = a.shr(za);
+    b = b.shr(zb);
+    while (!b.is_zero()) {  // both odd here
+      if (cmp(a, b) > 0) { BigU t = a; a = b; b = t; }
+      b = sub(b, a);
+      if (!b.is_zero()) b = b.shr(b.ctz());
+    }
+    return a.shl(z);
+  }
+
   std::vector<uint32_t> limbs(int L) const {
     std::vector<uint32_t> out(L, 0);
     for (int i = 0; i < L && static_cast<size_t>(i) < d.size(); ++i) out[i] = d[i];

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include "device.h"
+#include "zgcd.h"
 
 namespace rsl {
 
@@ -19,6 +20,11 @@ hipError_t launch_eval(int variant, const DevProblem* probs, const WorkItem* ite
 // and output) over `nitems` items.
 hipError_t launch_crt_wide(int pass, const DevProblem* probs, const WorkItem* items, int nitems, size_t lds,
                            const DevTables& T, hipStream_t st);
+
+// Pass 0 (reduce u, v over `nitems` items), 1 (Euclid per prime slot), 2 (pack
+// the kept scaled gcds) or 3 (G and the cofactors per kept slot) of the modular gcd.
+hipError_t launch_zgcd_pass(int pass, const ZgcdDesc& Z, const WorkItem* items, int nitems, const DevTables& T,
+                            hipStream_t st);
 
 // Basis change over prime groups (problems sharing a prime share the table reads).
 hipError_t launch_stir_group(const DevProblem* probs, const StirGroup* groups, const StirMember* members,

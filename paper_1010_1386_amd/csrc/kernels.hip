@@ -23,6 +23,7 @@
 #include "device.h"
 #include "kernels.h"
 #include "stages.h"
+#include "zgcd.h"
 
 namespace rsl {
 
@@ -118,6 +119,44 @@ hipError_t launch_crt_wide(int pass, const DevProblem* probs, const WorkItem* it
     case 0: hipLaunchKernelGGL(k_crt_wide_t, g, dim3(256), lds, st, probs, items, T); break;
     case 1: hipLaunchKernelGGL(k_crt_wide_sum, g, dim3(kWideHT), lds, st, probs, items); break;
     case 2: hipLaunchKernelGGL(k_crt_wide_fin, g, dim3(64), lds, st, probs, items); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kZThreads) void k_zreduce(ZgcdDesc Z, const WorkItem* items, DevTables T) {
+  stage_zreduce(Z, T, items[blockIdx.x]);
+}
+__global__ __launch_bounds__(kZThreads) void k_zgcd(ZgcdDesc Z, DevTables T) {
+  extern __shared__ uint32_t lds[];
+  stage_zgcd(Z, T, blockIdx.x, lds);
+}
+__global__ __launch_bounds__(kZThreads) void k_zpack(ZgcdDesc Z, DevTables T) { stage_zpack(Z, T, blockIdx.x); }
+__global__ __launch_bounds__(kZThreads) void k_zcof(ZgcdDesc Z, DevTables T) {
+  extern __shared__ uint32_t lds[];
+  stage_zcof(Z, T, blockIdx.x, lds);
+}
+
+hipError_t launch_zgcd_pass(int pass, const ZgcdDesc& Z, const WorkItem* items, int nitems, const DevTables& T,
+                            hipStream_t st) {
+  const dim3 b(kZThreads);
+  switch (pass) {
+    case 0:
+      if (nitems <= 0) return hipSuccess;
+      hipLaunchKernelGGL(k_zreduce, dim3(nitems), b, 0, st, Z, items, T);
+      break;
+    case 1:
+      if (Z.np <= 0) return hipSuccess;
+      hipLaunchKernelGGL(k_zgcd, dim3(Z.np), b, static_cast<size_t>(zgcd_lds_words(Z)) * 4, st, Z, T);
+      break;
+    case 2:
+      if (Z.nk <= 0) return hipSuccess;
+      hipLaunchKernelGGL(k_zpack, dim3(Z.nk), b, 0, st, Z, T);
+      break;
+    case 3:
+      if (Z.nk <= 0) return hipSuccess;
+      hipLaunchKernelGGL(k_zcof, dim3(Z.nk), b, static_cast<size_t>(zcof_lds_words(Z)) * 4, st, Z, T);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -171,6 +171,39 @@ void direct_crt_tables(const std::vector<uint32_t>& primes, const BigU& M, int L
   *negM = M.neg_limbs(L);
 }
 
+void plan_crt(Plan* P) {
+  const std::vector<uint32_t>& tab = prime_table(0);
+  P->np = static_cast<int>(P->pidx.size());
+  P->canonical = true;
+  for (int i = 0; i < P->np; ++i)
+    if (P->pidx[i] != i) P->canonical = false;
+  std::vector<uint32_t> primes(P->np);
+  BigU M(1);
+  for (int i = 0; i < P->np; ++i) {
+    primes[i] = tab[P->pidx[i]];
+    M = BigU::mul_small(M, primes[i]);
+  }
+  P->L_out = std::max(1, (M.bitlen() + 31) / 32);
+  BigU H = M.half();  // (M - 1) / 2, M odd
+  P->Hm.resize(P->np);
+  for (int i = 0; i < P->np; ++i) P->Hm[i] = H.mod_small(primes[i]);
+  P->NH = H.neg_limbs(P->L_out);
+  // beyond the per-lane slots the CRT takes the wide path: Y0 = sum_i t_i M_i - q M
+  // with q possibly one short, so Y0 < 2M needs one limb more than M
+  P->wide = P->np > kSlotCrtPrimes;
+  P->Lw = P->wide ? P->L_out + 1 : P->L_out;
+  if (!P->canonical && !P->wide) crt_tables(primes, P->L_out, &P->Tg, &P->invM, &P->Plimb);
+  else { P->Tg.clear(); P->invM.clear(); P->Plimb.clear(); }
+  direct_crt_tables(primes, M, P->Lw, &P->Mi, &P->wdir, &P->rinv, &P->negM);
+  if (P->wide) {
+    P->Mw = M.limbs(P->Lw);
+    P->NHM = BigU::add(H, M).neg_limbs(P->L_out);
+  } else {
+    P->Mw.clear();
+    P->NHM.clear();
+  }
+}
+
 int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opts, Plan* P,
               std::string* err) {
   if (var != RSL_Y && var != RSL_X) {
@@ -271,33 +304,7 @@ int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opt
       --extra_left;
     }
   }
-  P->np = static_cast<int>(P->pidx.size());
-  P->canonical = true;
-  for (int i = 0; i < P->np; ++i)
-    if (P->pidx[i] != i) P->canonical = false;
-
-  P->L_out = std::max(1, (M.bitlen() + 31) / 32);
-  BigU H = M.half();  // (M - 1) / 2, M odd
-  const std::vector<uint32_t>& tab = prime_table(0);
-  std::vector<uint32_t> primes(P->np);
-  for (int i = 0; i < P->np; ++i) primes[i] = tab[P->pidx[i]];
-  P->Hm.resize(P->np);
-  for (int i = 0; i < P->np; ++i) P->Hm[i] = H.mod_small(primes[i]);
-  P->NH = H.neg_limbs(P->L_out);
-  // beyond the per-lane slots the CRT takes the wide path: Y0 = sum_i t_i M_i - q M
-  // with q possibly one short, so Y0 < 2M needs one limb more than M
-  P->wide = P->np > kSlotCrtPrimes;
-  P->Lw = P->wide ? P->L_out + 1 : P->L_out;
-  if (!P->canonical && !P->wide) crt_tables(primes, P->L_out, &P->Tg, &P->invM, &P->Plimb);
-  else { P->Tg.clear(); P->invM.clear(); P->Plimb.clear(); }
-  direct_crt_tables(primes, M, P->Lw, &P->Mi, &P->wdir, &P->rinv, &P->negM);
-  if (P->wide) {
-    P->Mw = M.limbs(P->Lw);
-    P->NHM = BigU::add(H, M).neg_limbs(P->L_out);
-  } else {
-    P->Mw.clear();
-    P->NHM.clear();
-  }
+  plan_crt(P);
 
   // residue tile layout
   P->rowf = F.dx + 1;

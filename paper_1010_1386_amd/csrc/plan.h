@@ -69,6 +69,11 @@ struct Plan {
 int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opts, Plan* P,
               std::string* err);
 
+// CRT constants of P->pidx (prime product M): np, canonical, L_out, H mod p_i,
+// 2^(32 L_out) - H, the wide-path choice, Garner tables (non-canonical slot
+// path only) and the direct-CRT tables.
+void plan_crt(Plan* P);
+
 // CRT tables for an ordered prime list (Garner constants and prefix products).
 //   Tg[j*np + i] = (prod_{l<j} p_l mod p_i) R mod p_i          (j < i)
 //   invM[i]      = (prod_{l<i} p_l)^{-1} R mod p_i

@@ -115,6 +115,26 @@ __device__ __forceinline__ void horner_step2x2(uint32_t* a, uint32_t* b, uint32_
 // myp), then g part [i][j] (j padded to nyp).  Stores c R^2 mod p (0 for padding).
 // With zero_status, the block of (slot 0, block 0) also clears the problem's
 // status words (a launch that runs before every other stage of the problem).
+// A two's complement value of L limbs mod p, without divisions: the signed top
+// limb plus 2p lies in (0, 4p) since 2^30 < p < 2^31; each lower limb w (< 4p)
+// enters as r <- r 2^32 + w, with r 2^32 mod p = mmul(r, R^2).
+__device__ inline uint32_t limbs_mod_p(const uint32_t* wd, int L, const PrimeConst& pc) {
+  const uint32_t p = pc.p;
+  const int32_t top = static_cast<int32_t>(wd[L - 1]);
+  uint64_t x = static_cast<uint64_t>(static_cast<int64_t>(top) + 2 * static_cast<int64_t>(p));  // < 4p
+  x = (x >= 2ull * p) ? x - 2ull * p : x;
+  x = (x >= p) ? x - p : x;
+  uint32_t r = static_cast<uint32_t>(x);
+  for (int l = L - 2; l >= 0; --l) {
+    uint32_t wl = wd[l];
+    wl = umin32(wl, wl - p);
+    wl = umin32(wl, wl - p);
+    wl = umin32(wl, wl - p);
+    r = maddm(mmul(r, pc.r2, p, pc.pinv), wl, p);
+  }
+  return r;
+}
+
 // Position in the partner's tiles (the system eliminated in x) of the
 // coefficient at tile position t (inside the f or g rectangle): x^i y^j there
 // is y'^i x'^j, so [x-power i][row j] becomes [x'-power j][row i].
@@ -146,23 +166,8 @@ __device__ inline void stage_reduce(const DevProblem& P, const DevTables& T, con
   }
   uint32_t v = 0;
   if (in >= 0) {
-    const uint32_t* wd = P.coeff + static_cast<size_t>(in) * P.L_in;
-    // two's complement value mod p without divisions: the signed top limb plus
-    // 2p lies in (0, 4p) since 2^30 < p < 2^31; each lower limb w (< 4p) enters
-    // as r <- r 2^32 + w, with r 2^32 mod p = mmul(r, R^2)
-    const int32_t top = static_cast<int32_t>(wd[P.L_in - 1]);
     const uint32_t p = pc.p;
-    uint64_t x = static_cast<uint64_t>(static_cast<int64_t>(top) + 2 * static_cast<int64_t>(p));  // < 4p
-    x = (x >= 2ull * p) ? x - 2ull * p : x;
-    x = (x >= p) ? x - p : x;
-    uint32_t r = static_cast<uint32_t>(x);
-    for (int l = P.L_in - 2; l >= 0; --l) {
-      uint32_t wl = wd[l];
-      wl = umin32(wl, wl - p);
-      wl = umin32(wl, wl - p);
-      wl = umin32(wl, wl - p);
-      r = maddm(mmul(r, pc.r2, p, pc.pinv), wl, p);
-    }
+    const uint32_t r = limbs_mod_p(P.coeff + static_cast<size_t>(in) * P.L_in, P.L_in, pc);
     v = mmul(r, pc.r3, p, pc.pinv);
     if (w.slot < P.pshared) P.presid[static_cast<size_t>(w.slot) * P.pCS + partner_pos(P, t)] = v;
   }
