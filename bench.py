@@ -257,6 +257,54 @@ def table3_bench(steps, warmup, only=None):
             "steps": steps, "sets": rows, "verified_batched_eq_plain": True}
 
 
+def sqfree_bench(steps, with_cpu_baseline=True):
+    """The square-free part of resultants by the modular gcd: R = res_y of the
+    dense degree-24 pair (square-free: Euclid runs to a constant gcd), and
+    R = res_y(f, f_y) with f = F (y^2 - h), which has a repeated factor.
+    Each call is host to host (planning, prime selection, two device passes,
+    Chinese remaindering, certificate checks)."""
+    import paper_1010_1386_amd as rsl
+    import workloads
+
+    ctx = rsl.Context(0, workspace_bytes=1 << 30)
+    f, g = workloads.config2()
+    cases = [("R = res_y of the dense degree-24 pair", ctx.res(f, g, "y"))]
+    rng = workloads.rng_for(722, 0)
+    for d in (6, 8):
+        F = workloads.dense_total(rng, d, 8)
+        h = [int(v) for v in rng.integers(-9, 10, size=3)]
+        h[-1] = h[-1] or 1
+        fb = [[0] * len(F[0]) for _ in range(len(F) + 2)]
+        for j, row in enumerate(F):  # F (y^2 - h): rows are y-powers
+            for i, c in enumerate(row):
+                fb[j + 2][i] += c
+                for t, hc in enumerate(h):
+                    if i + t >= len(fb[j]):
+                        fb[j].extend([0] * (i + t + 1 - len(fb[j])))
+                    fb[j][i + t] -= c * hc
+        fy = [[(j + 1) * c for c in fb[j + 1]] for j in range(len(fb) - 1)]
+        cases.append((f"R = res_y(f, f_y), f = F (y^2 - h), F dense of total degree {d}", ctx.res(fb, fy, "y")))
+    rows = []
+    steps = max(1, min(steps, 20))
+    for name, R in cases:
+        q, gg = ctx.sqfree_part(R)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.sqfree_part(R)
+        dt = (time.perf_counter() - t0) / steps
+        row = {"case": name, "deg_R": len(R) - 1, "max_coeff_bits": max(abs(c).bit_length() for c in R),
+               "deg_gcd": len(gg) - 1, "deg_sqfree_part": len(q) - 1, "ms_per_call": dt * 1e3}
+        if with_cpu_baseline and len(R) <= 100:
+            import oracle
+            t0 = time.perf_counter()
+            want = oracle.sqfree_part(R)
+            row["cpu_baseline"] = {"kind": "oracle", "ms": (time.perf_counter() - t0) * 1e3, "cores": 1,
+                                   "matches": oracle.zx_pp(q) == want}
+        rows.append(row)
+    ctx.close()
+    return {"workload": "square-free part of resultants (modular gcd of R and R')", "steps": steps, "cases": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,6 +322,8 @@ def main():
                     help="large-coefficient benchmark instead: the random-curve sets of Table 3, res_y of all pairs")
     ap.add_argument("--eval-schur", action="store_true",
                     help="univariate resultants by the Schur algorithm (comparison runs; use with --schedule staged)")
+    ap.add_argument("--sqfree", action="store_true",
+                    help="square-free part of resultants by the modular gcd instead")
     ap.add_argument("--table3-only", default="", metavar="DEG:K[,DEG:K]",
                     help="with --table3: only these sets (e.g. 15:2048)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -302,6 +352,9 @@ def main():
         return
     if a.batch512:
         print(json.dumps(batch_bench(a.steps, a.warmup)))
+        return
+    if a.sqfree:
+        print(json.dumps(sqfree_bench(a.steps, not a.no_cpu_baseline)))
         return
     if a.table3:
         only = [x for x in a.table3_only.split(",") if x]

@@ -114,10 +114,15 @@ int bitlen_i(int64_t v) {
   return b;
 }
 
-struct Dev {  // bump allocator over the context workspace; null (and bad) past its end
+// Bump allocator over the context workspace (null, and bad, past its end).
+// Uploads of a phase are gathered on the host and sent by flush() as one copy
+// from pinned memory.
+struct Dev {
   uint8_t* base;
   size_t cap, used = 0;
   bool bad = false;
+  std::vector<uint8_t> host;  // staged bytes of [lo, hi)
+  size_t lo = 0, hi = 0;
   template <class T>
   T* take(size_t count) {
     const size_t at = align_up(used, 256), bytes = sizeof(T) * std::max<size_t>(count, 1);
@@ -128,7 +133,36 @@ struct Dev {  // bump allocator over the context workspace; null (and bad) past 
     used = at + bytes;
     return reinterpret_cast<T*>(base + at);
   }
+  void put(void* dst, const void* src, size_t bytes) {
+    if (!bytes || !dst) return;
+    const size_t off = static_cast<uint8_t*>(dst) - base;
+    if (hi == lo) lo = hi = off;
+    if (off < lo) {  // allocations only grow: not expected, but keep it correct
+      host.insert(host.begin(), lo - off, 0u);
+      lo = off;
+    }
+    if (off + bytes > hi) {
+      host.resize(off + bytes - lo, 0u);
+      hi = off + bytes;
+    }
+    std::memcpy(host.data() + (off - lo), src, bytes);
+  }
 };
+
+int flush(rsl_ctx* ctx, Dev* D) {
+  if (D->bad) return fail(ctx, RSL_ENOMEM, "workspace smaller than the gcd footprint");
+  if (D->hi == D->lo) return RSL_OK;
+  const size_t n = D->hi - D->lo;
+  // the pinned buffer may still feed an earlier copy of this call
+  int rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+  if (!rc) rc = ensure_staging(ctx, n, 0);
+  if (rc) return rc;
+  std::memcpy(ctx->h_up, D->host.data(), n);
+  rc = hip_check(ctx, hipMemcpyAsync(D->base + D->lo, ctx->h_up, n, hipMemcpyHostToDevice, ctx->stream), "upload");
+  D->host.clear();
+  D->lo = D->hi = 0;
+  return rc;
+}
 
 // Device copies of a prime list's CRT tables.
 struct CrtDev {
@@ -138,15 +172,12 @@ struct CrtDev {
   uint32_t *Mw = nullptr, *NHM = nullptr, *Tg = nullptr, *invM = nullptr, *Plimb = nullptr;
 };
 
-int upload(rsl_ctx* ctx, void* dst, const void* src, size_t bytes) {
-  if (!bytes) return RSL_OK;
-  if (!dst) return fail(ctx, RSL_ENOMEM, "workspace smaller than the gcd footprint");
-  return hip_check(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream), "upload");
-}
 template <class T>
 int upload_vec(rsl_ctx* ctx, Dev* D, const std::vector<T>& v, T** out) {
   *out = D->take<T>(v.size());
-  return upload(ctx, *out, v.data(), v.size() * sizeof(T));
+  if (!*out) return fail(ctx, RSL_ENOMEM, "workspace smaller than the gcd footprint");
+  D->put(*out, v.data(), v.size() * sizeof(T));
+  return RSL_OK;
 }
 
 int crt_setup(rsl_ctx* ctx, Dev* D, const std::vector<int>& pidx, CrtDev* C) {
@@ -217,10 +248,9 @@ int run_crt(rsl_ctx* ctx, Dev* D, const std::vector<DevProblem>& probs) {
   if (probs.empty()) return RSL_OK;
   const bool wide = probs[0].wide != 0;
   const int np = probs[0].np;
-  DevProblem* dprobs = D->take<DevProblem>(probs.size());
-  int rc = upload(ctx, dprobs, probs.data(), sizeof(DevProblem) * probs.size());
+  DevProblem* dprobs = nullptr;
+  int rc = upload_vec(ctx, D, probs, &dprobs);
   if (rc) return rc;
-  if (D->bad) return fail(ctx, RSL_ENOMEM, "workspace smaller than the gcd footprint");
   const DevTables T = tables_of(ctx);
   if (!wide) {
     int ns = (np + 63) / 64;
@@ -232,7 +262,7 @@ int run_crt(rsl_ctx* ctx, Dev* D, const std::vector<DevProblem>& probs) {
       lds = std::max(lds, static_cast<size_t>(crt_lds_words(probs[q], ns, crt_block_waves(ns))) * 4);
     }
     WorkItem* ditems = nullptr;
-    if ((rc = upload_vec(ctx, D, items, &ditems))) return rc;
+    if ((rc = upload_vec(ctx, D, items, &ditems)) || (rc = flush(ctx, D))) return rc;
     return hip_check(ctx, launch_stage(kStageCrt, dprobs, ditems, static_cast<int>(items.size()), lds, ns, T, ctx->stream),
                      "gcd CRT");
   }
@@ -247,14 +277,15 @@ int run_crt(rsl_ctx* ctx, Dev* D, const std::vector<DevProblem>& probs) {
     for (int k = 0; k <= d.D; ++k) items[2].push_back({qi, -1, k, 0});
     lds[2] = std::max(lds[2], static_cast<size_t>(wide_fin_lds_words(d)) * 4);
   }
-  for (int pass = 0; pass < 3; ++pass) {
-    WorkItem* ditems = nullptr;
-    if ((rc = upload_vec(ctx, D, items[pass], &ditems)) ||
-        (rc = hip_check(ctx, launch_crt_wide(pass, dprobs, ditems, static_cast<int>(items[pass].size()), lds[pass], T,
-                                             ctx->stream),
+  WorkItem* ditems[3];
+  for (int pass = 0; pass < 3; ++pass)
+    if ((rc = upload_vec(ctx, D, items[pass], &ditems[pass]))) return rc;
+  if ((rc = flush(ctx, D))) return rc;
+  for (int pass = 0; pass < 3; ++pass)
+    if ((rc = hip_check(ctx, launch_crt_wide(pass, dprobs, ditems[pass], static_cast<int>(items[pass].size()), lds[pass],
+                                             T, ctx->stream),
                         "gcd CRT")))
       return rc;
-  }
   return RSL_OK;
 }
 
@@ -335,27 +366,30 @@ int gcd_core(rsl_ctx* ctx, const UPoly& u, const UPoly& v, rsl_result* gout, rsl
     Z.Lv = v.L;
     Z.np = np;
     Z.gs = (nv >= 0 ? std::min(nu, nv) : nu) + 1;
-    uint32_t *du = D.take<uint32_t>(u.c.size()), *dv = D.take<uint32_t>(v.c.size());
-    int* dp = D.take<int>(np);
-    uint32_t* dell = D.take<uint32_t>(np);
-    Z.up = D.take<uint32_t>(static_cast<size_t>(np) * (nu + 1));
-    Z.vp = D.take<uint32_t>(static_cast<size_t>(np) * (nv + 1));
-    Z.gt = D.take<uint32_t>(static_cast<size_t>(np) * Z.gs);
-    Z.gdeg = D.take<int>(np);
     std::vector<WorkItem> items;
     for (int s = 0; s < np; ++s) {
       for (int b = 0; b < blocks_of(nu + 1, kZThreads); ++b) items.push_back({0, s, b, 0});
       for (int b = 0; b < blocks_of(nv + 1, kZThreads); ++b) items.push_back({0, s, b, 1});
     }
+    uint32_t *du = D.take<uint32_t>(u.c.size()), *dv = D.take<uint32_t>(v.c.size());
+    int* dp = D.take<int>(np);
+    uint32_t* dell = D.take<uint32_t>(np);
     WorkItem* ditems = D.take<WorkItem>(items.size());
+    Z.up = D.take<uint32_t>(static_cast<size_t>(np) * (nu + 1));
+    Z.vp = D.take<uint32_t>(static_cast<size_t>(np) * (nv + 1));
+    Z.gt = D.take<uint32_t>(static_cast<size_t>(np) * Z.gs);
+    Z.gdeg = D.take<int>(np);
     if (D.bad) return fail(ctx, RSL_ENOMEM, "workspace smaller than the gcd footprint");
     Z.u = du;
     Z.v = dv;
     Z.pidx = dp;
     Z.ell = dell;
-    if ((rc = upload(ctx, du, u.c.data(), u.c.size() * 4)) || (rc = upload(ctx, dv, v.c.data(), v.c.size() * 4)) ||
-        (rc = upload(ctx, dp, pidx.data(), np * 4)) || (rc = upload(ctx, dell, ellp.data(), np * 4)) ||
-        (rc = upload(ctx, ditems, items.data(), items.size() * sizeof(WorkItem))) ||
+    D.put(du, u.c.data(), u.c.size() * 4);
+    D.put(dv, v.c.data(), v.c.size() * 4);
+    D.put(dp, pidx.data(), np * 4);
+    D.put(dell, ellp.data(), np * 4);
+    D.put(ditems, items.data(), items.size() * sizeof(WorkItem));
+    if ((rc = flush(ctx, &D)) ||
         (rc = hip_check(ctx, launch_zgcd_pass(0, Z, ditems, static_cast<int>(items.size()), T, ctx->stream), "zreduce")) ||
         (rc = hip_check(ctx, launch_zgcd_pass(1, Z, nullptr, 0, T, ctx->stream), "zgcd")))
       return rc;
@@ -387,8 +421,7 @@ int gcd_core(rsl_ctx* ctx, const UPoly& u, const UPoly& v, rsl_result* gout, rsl
     uint32_t* out0 = D.take<uint32_t>(static_cast<size_t>(dg + 1) * L);
     std::vector<DevProblem> p0{crt_problem(ctx, &D, C, dg, Z.c0, out0)};
     if (D.bad) return fail(ctx, RSL_ENOMEM, "workspace smaller than the gcd footprint");
-    if (D.bad) return fail(ctx, RSL_ENOMEM, "workspace smaller than the gcd footprint");
-    if ((rc = hip_check(ctx, launch_zgcd_pass(2, Z, nullptr, 0, T, ctx->stream), "zpack")) ||
+    if ((rc = flush(ctx, &D)) || (rc = hip_check(ctx, launch_zgcd_pass(2, Z, nullptr, 0, T, ctx->stream), "zpack")) ||
         (rc = run_crt(ctx, &D, p0)))
       return rc;
     std::vector<uint32_t> gt(static_cast<size_t>(dg + 1) * L);
@@ -426,9 +459,8 @@ int gcd_core(rsl_ctx* ctx, const UPoly& u, const UPoly& v, rsl_result* gout, rsl
     if (nv >= 0) p1.push_back(crt_problem(ctx, &D, C, nb, Z.cb, outb));
     if (D.bad) return fail(ctx, RSL_ENOMEM, "workspace smaller than the gcd footprint");
     const int zero = 0;
-    if (D.bad) return fail(ctx, RSL_ENOMEM, "workspace smaller than the gcd footprint");
-    if ((rc = upload(ctx, Z.rem, &zero, 4)) ||
-        (rc = hip_check(ctx, launch_zgcd_pass(3, Z, nullptr, 0, T, ctx->stream), "zcof")) ||
+    D.put(Z.rem, &zero, 4);
+    if ((rc = flush(ctx, &D)) || (rc = hip_check(ctx, launch_zgcd_pass(3, Z, nullptr, 0, T, ctx->stream), "zcof")) ||
         (rc = run_crt(ctx, &D, p1)))
       return rc;
     std::vector<uint32_t> g(static_cast<size_t>(dg + 1) * L), a(static_cast<size_t>(na + 1) * L), b;

@@ -127,12 +127,12 @@ hipError_t launch_crt_wide(int pass, const DevProblem* probs, const WorkItem* it
 __global__ __launch_bounds__(kZThreads) void k_zreduce(ZgcdDesc Z, const WorkItem* items, DevTables T) {
   stage_zreduce(Z, T, items[blockIdx.x]);
 }
-__global__ __launch_bounds__(kZThreads) void k_zgcd(ZgcdDesc Z, DevTables T) {
+__global__ __launch_bounds__(64) void k_zgcd(ZgcdDesc Z, DevTables T) {
   extern __shared__ uint32_t lds[];
   stage_zgcd(Z, T, blockIdx.x, lds);
 }
 __global__ __launch_bounds__(kZThreads) void k_zpack(ZgcdDesc Z, DevTables T) { stage_zpack(Z, T, blockIdx.x); }
-__global__ __launch_bounds__(kZThreads) void k_zcof(ZgcdDesc Z, DevTables T) {
+__global__ __launch_bounds__(64) void k_zcof(ZgcdDesc Z, DevTables T) {
   extern __shared__ uint32_t lds[];
   stage_zcof(Z, T, blockIdx.x, lds);
 }
@@ -147,7 +147,7 @@ hipError_t launch_zgcd_pass(int pass, const ZgcdDesc& Z, const WorkItem* items, 
       break;
     case 1:
       if (Z.np <= 0) return hipSuccess;
-      hipLaunchKernelGGL(k_zgcd, dim3(Z.np), b, static_cast<size_t>(zgcd_lds_words(Z)) * 4, st, Z, T);
+      hipLaunchKernelGGL(k_zgcd, dim3(Z.np), dim3(64), static_cast<size_t>(zgcd_lds_words(Z)) * 4, st, Z, T);
       break;
     case 2:
       if (Z.nk <= 0) return hipSuccess;
@@ -155,7 +155,7 @@ hipError_t launch_zgcd_pass(int pass, const ZgcdDesc& Z, const WorkItem* items, 
       break;
     case 3:
       if (Z.nk <= 0) return hipSuccess;
-      hipLaunchKernelGGL(k_zcof, dim3(Z.nk), b, static_cast<size_t>(zcof_lds_words(Z)) * 4, st, Z, T);
+      hipLaunchKernelGGL(k_zcof, dim3(Z.nk), dim3(64), static_cast<size_t>(zcof_lds_words(Z)) * 4, st, Z, T);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -3,8 +3,9 @@
 // R by Yun's algorithm, i.e. gcds of R and its derivatives; the outlook of
 // Sec. 6 proposes the modular route for it).  Device stages, per prime slot:
 //   zreduce  u, v mod p (two's complement limbs, division-free)
-//   zgcd     Euclid's algorithm over Z_p in LDS; the gcd made monic and
-//            scaled by ell = gcd(lc u, lc v) mod p
+//   zgcd     Euclid's algorithm over Z_p in LDS, one wave per prime,
+//            division-free steps; the gcd made monic and scaled by
+//            ell = gcd(lc u, lc v) mod p
 //   zpack    the kept slots' scaled gcds in the CRT input layout
 //   zcof     G mod p = scaled gcd / (signed content), then the exact quotients
 //            u / G and v / G by long division over Z_p (a nonzero remainder
@@ -44,7 +45,7 @@ struct ZgcdDesc {
   int* rem;             // [0] set when a division leaves a remainder
 };
 
-constexpr int kZThreads = 256;
+constexpr int kZThreads = 256;  // reduce and pack; Euclid and the divisions run one wave per slot
 
 // residues of u (sub 0) or v (sub 1): item slot, block of 256 coefficients
 __device__ inline void stage_zreduce(const ZgcdDesc& Z, const DevTables& T, const WorkItem& w) {
@@ -57,68 +58,56 @@ __device__ inline void stage_zreduce(const ZgcdDesc& Z, const DevTables& T, cons
   dst[static_cast<size_t>(w.slot) * (n + 1) + t] = limbs_mod_p(src, L, pc);
 }
 
-__host__ __device__ inline int zgcd_lds_words(const ZgcdDesc& Z) { return (Z.nu + 1) + (Z.nv + 2) + 8; }
+__host__ __device__ inline int zgcd_lds_words(const ZgcdDesc& Z) { return (Z.nu + 1) + (Z.nv + 2); }
 
-// Degree of a[0..d] after its top entry was cleared: the next nonzero from d - 1 down.
-__device__ inline int zscan_down(const uint32_t* a, int d) {
-  --d;
-  while (d >= 0 && a[d] == 0u) --d;
-  return d;
+// Degree of a[0..d-1] (its entries below d): the highest nonzero, found 64
+// entries at a time by a wave ballot (-1 when all are zero).  Wave-uniform.
+__device__ inline int zdeg_below(const uint32_t* a, int d) {
+  const int lane = threadIdx.x & 63;
+  for (int top = d; top > 0; top -= 64) {
+    const int j = top - 64 + lane;
+    const uint64_t nz = __ballot(j >= 0 && a[j] != 0u);
+    if (nz) return top - 64 + (63 - __clzll(static_cast<long long>(nz)));
+  }
+  return -1;
 }
 
-// One block per prime slot.
+// One wave per prime slot.  Pseudo-remainder steps without divisions,
+//   A <- lc(B) A - lc(A) x^(deg A - deg B) B,
+// keep A a nonzero multiple of the remainder sequence's members, so the last
+// nonzero one is a multiple of the gcd; one inversion at the end makes it monic.
 __device__ inline void stage_zgcd(const ZgcdDesc& Z, const DevTables& T, int slot, uint32_t* lds) {
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x;
   const PrimeConst pc = T.pc[Z.pidx[slot]];
   const uint32_t p = pc.p, pinv = pc.pinv, one = pc.r1;
   uint32_t* X = lds;                 // nu + 1 words
-  uint32_t* Y = lds + (Z.nu + 1);    // nv + 1 words (at least one)
-  int* sh = reinterpret_cast<int*>(Y + (Z.nv + 1) + 1);
-  for (int k = tid; k <= Z.nu; k += blockDim.x)
-    X[k] = mmul(Z.up[static_cast<size_t>(slot) * (Z.nu + 1) + k], pc.r2, p, pinv);
-  for (int k = tid; k <= Z.nv; k += blockDim.x)
-    Y[k] = mmul(Z.vp[static_cast<size_t>(slot) * (Z.nv + 1) + k], pc.r2, p, pinv);
-  __syncthreads();
-  if (tid == 0) {
-    sh[0] = zscan_down(X, Z.nu + 1);
-    sh[1] = (Z.nv >= 0) ? zscan_down(Y, Z.nv + 1) : -1;
-  }
-  __syncthreads();
+  uint32_t* Y = lds + (Z.nu + 1);    // nv + 1 words
+  for (int k = lane; k <= Z.nu; k += 64) X[k] = mmul(Z.up[static_cast<size_t>(slot) * (Z.nu + 1) + k], pc.r2, p, pinv);
+  for (int k = lane; k <= Z.nv; k += 64) Y[k] = mmul(Z.vp[static_cast<size_t>(slot) * (Z.nv + 1) + k], pc.r2, p, pinv);
+  WaveSync()();
   uint32_t* A = X;
   uint32_t* B = Y;
-  int da = sh[0], db = sh[1];
+  int da = zdeg_below(X, Z.nu + 1), db = (Z.nv >= 0) ? zdeg_below(Y, Z.nv + 1) : -1;
   if (da < db) {
-    uint32_t* s = A; A = B; B = s;
+    uint32_t* t = A; A = B; B = t;
     const int d = da; da = db; db = d;
   }
-  while (db >= 0) {  // A <- A mod B, then swap
-    __syncthreads();
-    if (tid == 0) sh[2] = static_cast<int>(minv(B[db], one, p, pinv));
-    __syncthreads();
-    const uint32_t inv = static_cast<uint32_t>(sh[2]);
+  while (db >= 0) {
     while (da >= db) {
-      const uint32_t q = mmul(A[da], inv, p, pinv);
+      const uint32_t la = A[da], lb = B[db];
       const int s = da - db;
-      for (int j = tid; j < db; j += blockDim.x) A[j + s] = msubm(A[j + s], mmul(q, B[j], p, pinv), p);
-      __syncthreads();
-      if (tid == 0) {
-        A[da] = 0u;
-        sh[3] = zscan_down(A, da);
-      }
-      __syncthreads();
-      da = sh[3];
+      for (int j = lane; j < da; j += 64)
+        A[j] = (j >= s) ? mmulsub(lb, A[j], la, B[j - s], p, pinv) : mmul(lb, A[j], p, pinv);
+      WaveSync()();
+      da = zdeg_below(A, da);
     }
-    uint32_t* s = A; A = B; B = s;
+    uint32_t* t = A; A = B; B = t;
     const int d = da; da = db; db = d;
   }
-  // A (degree da) is the gcd: monic, times ell
-  __syncthreads();
-  if (tid == 0) sh[2] = (da >= 0) ? static_cast<int>(minv(A[da], one, p, pinv)) : 0;
-  __syncthreads();
-  const uint32_t inv = static_cast<uint32_t>(sh[2]);
-  for (int k = tid; k <= da; k += blockDim.x)
+  const uint32_t inv = (da >= 0) ? minv(A[da], one, p, pinv) : 0u;
+  for (int k = lane; k <= da; k += 64)
     Z.gt[static_cast<size_t>(slot) * Z.gs + k] = mmul(mmul(A[k], inv, p, pinv), Z.ell[slot], p, pinv);
-  if (tid == 0) Z.gdeg[slot] = da;
+  if (lane == 0) Z.gdeg[slot] = da;
 }
 
 // kept slot i: the scaled gcd in the CRT input layout (Montgomery form: the
@@ -133,7 +122,7 @@ __device__ inline void stage_zpack(const ZgcdDesc& Z, const DevTables& T, int i)
 
 __host__ __device__ inline int zcof_lds_words(const ZgcdDesc& Z) {
   const int n = Z.nu > Z.nv ? Z.nu : Z.nv;
-  return (n + 1) + (Z.dg + 1) + 8;
+  return (n + 1) + (Z.dg + 1);
 }
 
 // Long division of W (degree n, Montgomery) by G (degree dg, Montgomery,
@@ -142,15 +131,14 @@ __host__ __device__ inline int zcof_lds_words(const ZgcdDesc& Z) {
 __device__ inline void zdivide(uint32_t* W, int n, const uint32_t* G, int dg, uint32_t ginv, uint64_t* q,
                                int* rem, const PrimeConst& pc) {
   const uint32_t p = pc.p, pinv = pc.pinv;
+  const int lane = threadIdx.x;
   for (int k = n - dg; k >= 0; --k) {
     const uint32_t qk = mmul(W[k + dg], ginv, p, pinv);
-    if (threadIdx.x == 0) q[k] = qk;
-    for (int j = threadIdx.x; j < dg; j += blockDim.x) W[k + j] = msubm(W[k + j], mmul(qk, G[j], p, pinv), p);
-    __syncthreads();
+    if (lane == 0) q[k] = qk;
+    for (int j = lane; j < dg; j += 64) W[k + j] = msubm(W[k + j], mmul(qk, G[j], p, pinv), p);
+    WaveSync()();
   }
-  bool nz = false;
-  for (int j = threadIdx.x; j < dg; j += blockDim.x) nz = nz || (W[j] != 0u);
-  if (nz) rem[0] = 1;
+  if (zdeg_below(W, dg) >= 0 && lane == 0) rem[0] = 1;
 }
 
 // kept slot i: G mod p, then u / G and v / G
@@ -162,25 +150,19 @@ __device__ inline void stage_zcof(const ZgcdDesc& Z, const DevTables& T, int i, 
   const int n = Z.nu > Z.nv ? Z.nu : Z.nv;
   uint32_t* W = lds;              // n + 1 words
   uint32_t* G = lds + (n + 1);    // dg + 1 words
-  uint32_t* sh = G + (Z.dg + 1);
   const uint32_t sM = mmul(Z.sinv[i], pc.r2, p, pinv);
-  for (int k = tid; k <= Z.dg; k += blockDim.x) {
+  for (int k = tid; k <= Z.dg; k += 64) {
     const uint32_t g = mmul(mmul(Z.gt[static_cast<size_t>(slot) * Z.gs + k], pc.r2, p, pinv), sM, p, pinv);
     G[k] = g;
     Z.cg[static_cast<size_t>(i) * (Z.dg + 1) + k] = g;
   }
-  for (int k = tid; k <= Z.nu; k += blockDim.x)
-    W[k] = mmul(Z.up[static_cast<size_t>(slot) * (Z.nu + 1) + k], pc.r2, p, pinv);
-  __syncthreads();
-  if (tid == 0) sh[0] = minv(G[Z.dg], one, p, pinv);
-  __syncthreads();
-  const uint32_t ginv = sh[0];
+  for (int k = tid; k <= Z.nu; k += 64) W[k] = mmul(Z.up[static_cast<size_t>(slot) * (Z.nu + 1) + k], pc.r2, p, pinv);
+  WaveSync()();
+  const uint32_t ginv = minv(G[Z.dg], one, p, pinv);
   zdivide(W, Z.nu, G, Z.dg, ginv, Z.ca + static_cast<size_t>(i) * (Z.nu - Z.dg + 1), Z.rem, pc);
   if (Z.nv < Z.dg) return;  // v = 0 (no cofactor)
-  __syncthreads();
-  for (int k = tid; k <= Z.nv; k += blockDim.x)
-    W[k] = mmul(Z.vp[static_cast<size_t>(slot) * (Z.nv + 1) + k], pc.r2, p, pinv);
-  __syncthreads();
+  for (int k = tid; k <= Z.nv; k += 64) W[k] = mmul(Z.vp[static_cast<size_t>(slot) * (Z.nv + 1) + k], pc.r2, p, pinv);
+  WaveSync()();
   zdivide(W, Z.nv, G, Z.dg, ginv, Z.cb + static_cast<size_t>(i) * (Z.nv - Z.dg + 1), Z.rem, pc);
 }
 
