@@ -292,14 +292,24 @@ def sqfree_bench(steps, with_cpu_baseline=True):
         for _ in range(steps):
             ctx.sqfree_part(R)
         dt = (time.perf_counter() - t0) / steps
+        fac = ctx.sqfree_factor(R)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.sqfree_factor(R)
+        dty = (time.perf_counter() - t0) / steps
         row = {"case": name, "deg_R": len(R) - 1, "max_coeff_bits": max(abs(c).bit_length() for c in R),
-               "deg_gcd": len(gg) - 1, "deg_sqfree_part": len(q) - 1, "ms_per_call": dt * 1e3}
+               "deg_gcd": len(gg) - 1, "deg_sqfree_part": len(q) - 1, "ms_per_call": dt * 1e3,
+               "yun_factor_degrees": [len(r) - 1 for r in fac], "yun_ms_per_call": dty * 1e3}
         if with_cpu_baseline and len(R) <= 100:
             import oracle
             t0 = time.perf_counter()
             want = oracle.sqfree_part(R)
             row["cpu_baseline"] = {"kind": "oracle", "ms": (time.perf_counter() - t0) * 1e3, "cores": 1,
                                    "matches": oracle.zx_pp(q) == want}
+            t0 = time.perf_counter()
+            wfac = oracle.yun(R)
+            row["cpu_baseline_yun"] = {"kind": "oracle", "ms": (time.perf_counter() - t0) * 1e3, "cores": 1,
+                                       "matches": wfac == fac}
         rows.append(row)
     ctx.close()
     return {"workload": "square-free part of resultants (modular gcd of R and R')", "steps": steps, "cases": rows}

@@ -234,6 +234,18 @@ int rsl_gcd(rsl_ctx *ctx, const rsl_upoly *u, const rsl_upoly *v, rsl_result *g,
 int rsl_sqfree_part(rsl_ctx *ctx, const rsl_upoly *r, rsl_result *q, rsl_result *g);
 
 /*
+ * Square-free factorisation pp(r) = prod_{i>=1} r_i^i (Yun's algorithm, the
+ * one the paper's Project step names): r_i primitive, positive leading
+ * coefficient, square-free and pairwise coprime; each gcd with its cofactors
+ * by rsl_gcd's certified modular route on the device, the differences
+ * c - b' on the host.  factors[i] receives r_{i+1} for i < *nfactors
+ * (trailing factors equal to 1 are dropped; zero or constant r gives none).
+ * RSL_ERANGE when *nfactors > max_factors (nothing written) or a buffer is too
+ * small.
+ */
+int rsl_sqfree_factor(rsl_ctx *ctx, const rsl_upoly *r, int max_factors, rsl_result *factors, int *nfactors);
+
+/*
  * A batch of n independent problems (f[k], g[k], var[k]) -> out[k].
  * mode RSL_PLAIN runs one pipeline per problem on the context stream;
  * RSL_BATCHED plans all problems together and runs them in one persistent

@@ -112,6 +112,7 @@ _SIGS = {
     "rsl_res_xy": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), _P(rsl_opts), _P(rsl_result), _P(rsl_result)]),
     "rsl_gcd": (ctypes.c_int, [_vp, _P(rsl_upoly), _P(rsl_upoly), _P(rsl_result), _P(rsl_result), _P(rsl_result)]),
     "rsl_sqfree_part": (ctypes.c_int, [_vp, _P(rsl_upoly), _P(rsl_result), _P(rsl_result)]),
+    "rsl_sqfree_factor": (ctypes.c_int, [_vp, _P(rsl_upoly), ctypes.c_int, _P(rsl_result), _P(ctypes.c_int)]),
     "rsl_batch": (ctypes.c_int, [_vp, ctypes.c_int, _P(rsl_poly), _P(rsl_poly), _P(ctypes.c_int),
                                  _P(rsl_result), _P(ctypes.c_int), ctypes.c_int]),
     "rsl_last_counters": (ctypes.c_int, [_vp, _P(rsl_counters)]),
@@ -367,6 +368,23 @@ class Context:
             rc = _lib.rsl_sqfree_part(self.h, ctypes.byref(pr.c), ctypes.byref(outs[0].c), ctypes.byref(outs[1].c))
         self._check(rc, "rsl_sqfree_part")
         return tuple(o.value() for o in outs)
+
+    def sqfree_factor(self, r):
+        """[r_1, r_2, ...] with pp(r) = prod r_i^i (Yun's algorithm on the device gcd)."""
+        pr = UPoly(r)
+        n = max(pr.deg, 1)
+        limbs = pr.factor_bits // 32 + 2
+        outs = [_Result(max(pr.deg, 0), limbs) for _ in range(n)]
+        arr = (rsl_result * n)(*[o.c for o in outs])
+        cnt = ctypes.c_int(0)
+        with self.lock:
+            rc = _lib.rsl_sqfree_factor(self.h, ctypes.byref(pr.c), n, arr, ctypes.byref(cnt))
+        self._check(rc, "rsl_sqfree_factor")
+        res = []
+        for i in range(cnt.value):
+            outs[i].c = arr[i]
+            res.append(outs[i].value())
+        return res
 
     def batch(self, problems, mode="batched"):
         """problems: list of (f, g, var); returns a list of results (lists of ints)."""

@@ -312,16 +312,61 @@ void put_zero(rsl_result* r) {
   }
 }
 
-int put(const Plan& shape, const std::vector<uint32_t>& limbs, rsl_result* r) {
-  if (!r) return RSL_OK;
-  return decode_result(shape, limbs.data(), r);
+// CRT output limbs ((D + 1) x L) as a trimmed polynomial
+UPoly as_upoly(const std::vector<uint32_t>& limbs, int D, int L) {
+  UPoly r;
+  r.L = L;
+  r.deg = D;
+  auto nonzero = [&](int k) {
+    for (int l = 0; l < L; ++l)
+      if (limbs[static_cast<size_t>(k) * L + l]) return true;
+    return false;
+  };
+  while (r.deg >= 0 && !nonzero(r.deg)) --r.deg;
+  r.c.assign(limbs.begin(), limbs.begin() + static_cast<size_t>(r.deg + 1) * L);
+  return r;
 }
 
-int gcd_core(rsl_ctx* ctx, const UPoly& u, const UPoly& v, rsl_result* gout, rsl_result* uout, rsl_result* vout) {
+int write_result(const UPoly& u, rsl_result* r) {
+  if (!r) return RSL_OK;
+  if (u.deg < 0) {
+    put_zero(r);
+    return RSL_OK;
+  }
+  Plan shape;
+  shape.L_out = u.L;
+  shape.D = u.deg;
+  return decode_result(shape, u.c.data(), r);
+}
+
+// x - y, one limb wider than the wider operand
+UPoly sub_upoly(const UPoly& x, const UPoly& y) {
+  UPoly r;
+  r.L = std::max(x.L, y.L) + 1;
+  const int n = std::max(x.deg, y.deg);
+  r.c.assign(static_cast<size_t>(n + 1) * r.L, 0u);
+  auto limb = [](const UPoly& u, int k, int l) -> uint32_t {
+    if (k > u.deg) return 0u;
+    const uint32_t* c = u.at(k);
+    return (l < u.L) ? c[l] : ((c[u.L - 1] >> 31) ? 0xFFFFFFFFu : 0u);
+  };
+  for (int k = 0; k <= n; ++k) {
+    int64_t borrow = 0;
+    for (int l = 0; l < r.L; ++l) {
+      const int64_t v = static_cast<int64_t>(limb(x, k, l)) - limb(y, k, l) - borrow;
+      borrow = v < 0 ? 1 : 0;
+      r.c[static_cast<size_t>(k) * r.L + l] = static_cast<uint32_t>(v + (borrow << 32));
+    }
+  }
+  r.deg = n;
+  std::vector<uint32_t> tmp = r.c;
+  return as_upoly(tmp, n, r.L);
+}
+
+// G = gcd(pp(u), pp(v)), A = u / G, B = v / G (see the file comment)
+int gcd_core(rsl_ctx* ctx, const UPoly& u, const UPoly& v, UPoly* gout, UPoly* uout, UPoly* vout) {
   if (u.deg < 0 && v.deg < 0) {
-    put_zero(gout);
-    put_zero(uout);
-    put_zero(vout);
+    *gout = *uout = *vout = UPoly();
     return RSL_OK;
   }
   if (u.deg < 0) return gcd_core(ctx, v, u, gout, vout, uout);
@@ -475,18 +520,9 @@ int gcd_core(rsl_ctx* ctx, const UPoly& u, const UPoly& v, rsl_result* gout, rsl
     // certificate
     if (remv || max_bits(g, dg, L) > bG || max_bits(a, na, L) > bA || (nv >= 0 && max_bits(b, nb, L) > bB))
       continue;  // all kept primes unlucky (vanishingly rare): more primes
-    Plan shape;
-    shape.L_out = L;
-    shape.D = dg;
-    if ((rc = put(shape, g, gout))) return rc;
-    shape.D = na;
-    if ((rc = put(shape, a, uout))) return rc;
-    if (nv >= 0) {
-      shape.D = nb;
-      if ((rc = put(shape, b, vout))) return rc;
-    } else {
-      put_zero(vout);
-    }
+    *gout = as_upoly(g, dg, L);
+    *uout = as_upoly(a, na, L);
+    *vout = (nv >= 0) ? as_upoly(b, nb, L) : UPoly();
     return RSL_OK;
   }
   return fail(ctx, RSL_EPRIMES, "modular gcd: no consistent set of primes found");
@@ -510,7 +546,10 @@ int rsl_gcd(rsl_ctx* ctx, const rsl_upoly* u, const rsl_upoly* v, rsl_result* g,
   int rc = read_upoly(u, &U, &err);
   if (!rc) rc = read_upoly(v, &V, &err);
   if (rc) return fail(ctx, rc, err);
-  return gcd_core(ctx, U, V, g, ug, vg);
+  UPoly G, A, B;
+  if ((rc = gcd_core(ctx, U, V, &G, &A, &B))) return rc;
+  int r1 = write_result(G, g), r2 = write_result(A, ug), r3 = write_result(B, vg);
+  return r1 ? r1 : (r2 ? r2 : r3);
 }
 
 int rsl_sqfree_part(rsl_ctx* ctx, const rsl_upoly* r, rsl_result* q, rsl_result* g) {
@@ -528,7 +567,52 @@ int rsl_sqfree_part(rsl_ctx* ctx, const rsl_upoly* r, rsl_result* q, rsl_result*
     put_zero(g);
     return RSL_OK;
   }
-  return gcd_core(ctx, R, derivative(R), g, q, nullptr);
+  UPoly G, Q, C;
+  if ((rc = gcd_core(ctx, R, derivative(R), &G, &Q, &C))) return rc;
+  const int r1 = write_result(Q, q), r2 = write_result(G, g);
+  return r1 ? r1 : r2;
+}
+
+int rsl_sqfree_factor(rsl_ctx* ctx, const rsl_upoly* r, int max_factors, rsl_result* factors, int* nfactors) {
+  if (!ctx || !r || !nfactors || max_factors < 0 || (max_factors > 0 && !factors)) return RSL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  if (ctx->poisoned) return RSL_EDEVICE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, RSL_EDEVICE, "hipSetDevice");
+  ctx->err.clear();
+  UPoly R;
+  std::string err;
+  int rc = read_upoly(r, &R, &err);
+  if (rc) return fail(ctx, rc, err);
+  // Yun: a = gcd(f, f'), b = f / a, c = f' / a, d = c - b'; then
+  // r_i = gcd(b, d), b <- b / r_i, c <- d / r_i, d <- c - b' while deg b > 0
+  std::vector<UPoly> out;
+  if (R.deg > 0) {
+    UPoly G, B, C;
+    if ((rc = gcd_core(ctx, R, derivative(R), &G, &B, &C))) return rc;
+    UPoly D = sub_upoly(C, derivative(B));
+    while (B.deg > 0) {
+      UPoly Ri, B2, C2;
+      if ((rc = gcd_core(ctx, B, D, &Ri, &B2, &C2))) return rc;
+      out.push_back(Ri);
+      B = B2;
+      D = sub_upoly(C2, derivative(B));
+    }
+    auto is_one = [](const UPoly& u) {
+      if (u.deg != 0) return false;
+      for (int l = 0; l < u.L; ++l)
+        if (u.c[l] != (l == 0 ? 1u : 0u)) return false;
+      return true;
+    };
+    while (!out.empty() && is_one(out.back())) out.pop_back();
+  }
+  *nfactors = static_cast<int>(out.size());
+  if (static_cast<int>(out.size()) > max_factors) return fail(ctx, RSL_ERANGE, "more square-free factors than buffers");
+  int first = RSL_OK;
+  for (size_t i = 0; i < out.size(); ++i) {
+    const int ri = write_result(out[i], &factors[i]);
+    if (ri && !first) first = ri;
+  }
+  return first;
 }
 
 }  // extern "C"

@@ -122,3 +122,27 @@ def test_square_free_part_of_resultants(ctx):
         q, g = ctx.sqfree_part(R)
         assert zx_pp(q) == sqfree_part(R)
         assert len(g) > 1  # a repeated factor exists
+
+
+def test_yun_factorisation_matches_oracle(ctx):
+    """Yun's loop on the device gcd: closed form, products with planted
+    multiplicities, a resultant with a repeated factor, degenerate inputs."""
+    from oracle.sqfree import yun
+    f1, f2, f3, f4 = [-1, 1], [2, 1], [1, 0, 1], [-3, 2]
+    r = [6 * c for c in prod([zx_pow(f1, 3), zx_pow(f2, 2), f3, f4])]
+    assert ctx.sqfree_factor(r) == yun(r) == [zx_pp(pmul(f3, f4)), f2, f1]
+    rnd = random.Random(31)
+    for _ in range(4):
+        parts = [(ptrim([rnd.randint(-20, 20), rnd.randint(-20, 20), rnd.choice([1, 2, 5])]), e)
+                 for e in (1, 2, 2, 4) if rnd.random() < 0.8]
+        r = prod([zx_pow(p, e) for p, e in parts] + [[rnd.choice([-3, 1, 12])]])
+        assert ctx.sqfree_factor(r) == yun(r)
+    assert ctx.sqfree_factor([]) == [] and ctx.sqfree_factor([7]) == []
+    assert ctx.sqfree_factor([0, 0, 0, 5]) == yun([0, 0, 0, 5]) == [[1], [1], [0, 1]]
+    rng = rng_for(723, 0)
+    F = dense_total(rng, 4, 6)
+    f = oracle.bivar_mul(F, [[-2, 1, 3], [0], [1]])
+    fy = [[(j + 1) * c for c in f[j + 1]] for j in range(len(f) - 1)]
+    R = ctx.res(f, fy, "y")
+    fac = ctx.sqfree_factor(R)
+    assert fac == yun(R) and len(fac) >= 2
