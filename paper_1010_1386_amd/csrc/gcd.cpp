@@ -474,9 +474,16 @@ int gcd_core(rsl_ctx* ctx, const UPoly& u, const UPoly& v, UPoly* gout, UPoly* u
 
     // content s of G~ and the sign of its leading coefficient: G = G~ / (sign s)
     BigU s;
-    for (int k = 0; k <= dg; ++k) {
+    for (int k = dg; k >= 0; --k) {  // leading coefficient first (nonzero)
       bool n;
-      s = BigU::gcd(s, abs_limbs(gt.data() + static_cast<size_t>(k) * L, L, &n));
+      const BigU c = abs_limbs(gt.data() + static_cast<size_t>(k) * L, L, &n);
+      if (s.d.size() == 1 && !c.is_zero()) {  // a one-limb content: reduce c first
+        const uint32_t r = c.mod_small(s.d[0]);
+        s = BigU::gcd(s, BigU(r));
+      } else {
+        s = BigU::gcd(s, c);
+      }
+      if (s.d.size() == 1 && s.d[0] == 1u) break;  // content 1
     }
     bool lneg;
     (void)abs_limbs(gt.data() + static_cast<size_t>(dg) * L, L, &lneg);

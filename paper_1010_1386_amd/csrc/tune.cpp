@@ -290,8 +290,10 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
   for (int evk : {1, 2, 4})
     for (int mode : {RSL_STAGED, RSL_BATCHED})
       if (mode == RSL_STAGED || j->J.max_np <= kMaxSlots) cands.push_back(TuneConfig{mode, 4096, 1, evk, 0, 0});
-  // the Schur evaluation (one wave per pair) when every problem's shape allows it
-  bool schur_ok = true;
+  // the Schur evaluation (one wave per pair) when every problem's shape allows
+  // it and the job is small: its O(r) depth can only pay when the remainder
+  // sequence's one or two lanes per pair leave most of the chip idle
+  bool schur_ok = j->J.pairs <= 16384;
   for (int k : j->J.live) {
     const Plan& P = j->J.plans[k];
     schur_ok = schur_ok && P.my >= 1 && P.ny >= 1 && P.my + P.ny <= kSchurMaxR;
