@@ -284,6 +284,7 @@ int rsl_ctx_create(int device, void* d_workspace, size_t ws_bytes, void* stream,
   if (const char* env = std::getenv("RSL_QUEUE_WAIT_MS")) wait_ms = std::max(0.0, std::atof(env));
   c->queue_wait_ticks = static_cast<int64_t>(wait_ms * khz);
   if (const char* env = std::getenv("RSL_CRT_GARNER")) c->crt_garner = std::atoi(env) != 0;
+  if (const char* env = std::getenv("RSL_WIDE_VALU")) c->wide_valu = std::atoi(env) != 0;
   *out = c;
   return RSL_OK;
 }

@@ -77,9 +77,12 @@ struct DevProblem {
   uint8_t* zbad;          // np * (E+1)  leading coefficient vanished at x_i
   uint64_t* aconv;        // ncchunk * np * (D+1): partial sums, REDC(sum) = Newton coefficient a_k
   uint64_t* cpart;        // nchunk * np * (D+1): partial sums, REDC(sum) = coefficient mod p
-  uint32_t* wT;           // (D+1) * np  t_{k,i} = u_{k,i} (M / p_i)^{-1} mod p_i (wide path)
+  uint32_t* wT;           // wdpad * wnpad  t_{k,i} = u_{k,i} (M / p_i)^{-1} mod p_i, zero padded (wide path)
   uint32_t* wq;           // D+1         quotient estimate floor(sum_i f_{k,i} / 2^32) (wide path)
-  uint64_t* wS;           // (D+1) * 2 Lw  column sums over primes per 16-bit half limb (wide path)
+  uint64_t* wS;           // (D+1) * Lw * 2  column sum of each limb as (low, high) 64-bit words (wide path)
+  const int8_t* wMd;      // 5 * wlpad * wnpad  7-bit digit planes of the M_i limbs, [digit][limb][prime]
+  int wdpad, wlpad, wnpad;// D+1, Lw and np rounded up (64, 32, 64); wT rows have wnpad entries
+  int wide_mfma;          // 1: contraction on the matrix cores
   uint32_t* out;          // (D+1) * L_out two's complement limbs of R
   int* status;            // [0] error bits, [1+slot] 1 if gapped interpolation, [1+np] bad pairs,
                           // [2+np+slot] 1 if a point among 0..D was bad for the prime

@@ -235,8 +235,10 @@ DevProblem crt_problem(const rsl_ctx* ctx, Dev* D, const CrtDev& C, int Dg, uint
     d.Plimb = C.Plimb;
     d.LP = P.L_out;
   }
-  if (P.wide) {
-    d.wT = D->take<uint32_t>(static_cast<size_t>(Dg + 1) * P.np);
+  if (P.wide) {  // the vector-ALU contraction (rows of wT padded to a multiple of 64 primes)
+    d.wnpad = (P.np + 63) / 64 * 64;
+    d.wdpad = (Dg + 1 + 63) / 64 * 64;
+    d.wT = D->take<uint32_t>(static_cast<size_t>(d.wdpad) * d.wnpad);
     d.wq = D->take<uint32_t>(Dg + 1);
     d.wS = D->take<uint64_t>(static_cast<size_t>(Dg + 1) * 2 * P.Lw);
   }

@@ -196,6 +196,10 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     d.crt_garner = (ctx && ctx->crt_garner) ? 1 : 0;
     d.wide = P.wide ? 1 : 0;
     d.Lw = P.Lw;
+    d.wide_mfma = (P.wide && !(ctx && ctx->wide_valu)) ? 1 : 0;
+    d.wdpad = static_cast<int>(align_up(static_cast<size_t>(P.D + 1), kWideMfmaKT));
+    d.wlpad = static_cast<int>(align_up(static_cast<size_t>(P.Lw), kWideMfmaTT));
+    d.wnpad = static_cast<int>(align_up(static_cast<size_t>(P.np), kWideMfmaK));
     // the convolution's input range: the basis change's chunking, or whole
     d.cchunk = J->tune.conv_whole ? P.D + 1 : d.kchunk;
     d.ncchunk = (P.D + 1 + d.cchunk - 1) / d.cchunk;
@@ -260,8 +264,10 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
 
   // wide CRT items, problem by problem
   for (int pass = 0; pass < 3; ++pass) J->wide_items[pass].clear();
+  J->wide_mfma = false;
   for (int li = 0; li < nl; ++li) {
     const Plan& P = J->plans[J->live[li]];
+    const DevProblem& d = J->dev[li];
     ProbLayout& L = J->lay[li];
     for (int pass = 0; pass < 3; ++pass) L.wide_begin[pass] = static_cast<int>(J->wide_items[pass].size());
     if (P.wide) {
@@ -271,7 +277,10 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       // runs on XCD i mod 8; a problem's range starts anywhere, but its items
       // of one tile keep one residue mod 8)
       constexpr int kXcds = 8;
-      const int nkt = blocks_of(P.D + 1, kWideKT), nht = blocks_of(P.Lw, kWideHT);
+      const bool mfma = d.wide_mfma != 0;
+      J->wide_mfma = mfma;
+      const int nkt = mfma ? d.wdpad / kWideMfmaKT : blocks_of(P.D + 1, kWideKT);
+      const int nht = mfma ? d.wlpad / kWideMfmaTT : blocks_of(P.Lw, kWideHT);
       std::vector<std::vector<WorkItem>> bins(kXcds);
       for (int ht = 0; ht < nht; ++ht)
         for (int kt = 0; kt < nkt; ++kt) bins[ht % kXcds].push_back({li, -1, kt, ht});
@@ -422,6 +431,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     L.Mw = L.NHM = 0;
     if (P.wide) {
       L.Mw = o;  o = align_up(o + static_cast<size_t>(P.Lw) * 4, 16);
+      L.wMd = o; o = align_up(o + static_cast<size_t>(kWideDigits) * d.wlpad * d.wnpad, 16);
       L.NHM = o; o = align_up(o + static_cast<size_t>(P.L_out) * 4, 16);
     }
     if (!P.canonical) {
@@ -490,7 +500,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     L.cpart = o; o = align_up(o + static_cast<size_t>(d.nchunk) * np * (P.D + 1) * 8, A);
     L.wT = L.wq = L.wS = 0;
     if (P.wide) {
-      L.wT = o; o = align_up(o + np * (P.D + 1) * 4, A);
+      L.wT = o; o = align_up(o + static_cast<size_t>(d.wdpad) * d.wnpad * 4, A);
       L.wq = o; o = align_up(o + static_cast<size_t>(P.D + 1) * 4, A);
       L.wS = o; o = align_up(o + static_cast<size_t>(P.D + 1) * 2 * P.Lw * 8, A);
     }
@@ -516,7 +526,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     const DevProblem& d = J->dev[li];
     if (!d.wide) continue;
     J->wide_lds[0] = static_cast<size_t>(wide_t_lds_words()) * 4;
-    J->wide_lds[1] = static_cast<size_t>(wide_sum_lds_words()) * 4;
+    J->wide_lds[1] = static_cast<size_t>(J->wide_mfma ? wide_mfma_lds_words() : wide_sum_lds_words()) * 4;
     J->wide_lds[2] = std::max(J->wide_lds[2], static_cast<size_t>(wide_fin_lds_words(d)) * 4);
   }
   J->persist_lds = 0;
@@ -589,6 +599,15 @@ void job_bind(Job* J, uint8_t* base) {
     if (P.wide) {
       std::memcpy(blob + L.Mw, P.Mw.data(), P.Mw.size() * 4);
       std::memcpy(blob + L.NHM, P.NHM.data(), P.NHM.size() * 4);
+      // 7-bit digit planes of the M_i limbs, [digit][limb][prime], zero padded
+      int8_t* md = reinterpret_cast<int8_t*>(blob + L.wMd);
+      const size_t plane = static_cast<size_t>(d.wlpad) * d.wnpad;
+      for (int i = 0; i < P.np; ++i)
+        for (int t = 0; t < P.Lw; ++t) {
+          const uint32_t m = P.Mi[static_cast<size_t>(i) * P.Lw + t];
+          for (int dd = 0; dd < kWideDigits; ++dd)
+            md[dd * plane + static_cast<size_t>(t) * d.wnpad + i] = static_cast<int8_t>((m >> (7 * dd)) & 127u);
+        }
     }
     if (!P.canonical) {
       std::memcpy(blob + L.Tg, P.Tg.data(), P.Tg.size() * 4);
@@ -610,6 +629,7 @@ void job_bind(Job* J, uint8_t* base) {
     d.wT = P.wide ? reinterpret_cast<uint32_t*>(base + L.wT) : nullptr;
     d.wq = P.wide ? reinterpret_cast<uint32_t*>(base + L.wq) : nullptr;
     d.wS = P.wide ? reinterpret_cast<uint64_t*>(base + L.wS) : nullptr;
+    d.wMd = (P.wide && d.wide_mfma) ? reinterpret_cast<const int8_t*>(base + L.wMd) : nullptr;
     d.resid = reinterpret_cast<uint32_t*>(base + L.resid);
     d.zval = reinterpret_cast<uint32_t*>(base + L.zval);
     d.zbad = base + L.zbad;
@@ -702,6 +722,11 @@ int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st, uint8_t* pinned) {
   // the residue tiles a partner fills get their padding cleared once (the
   // partner writes only the coefficient positions)
   for (size_t li = 0; !rc && li < J->live.size(); ++li)
+    if (J->dev[li].wide)  // padding of the t rows stays zero (pass 1 writes the rest)
+      rc = hip_check(ctx, launch_copy_words(J->dev[li].wT, nullptr,
+                                            static_cast<size_t>(J->dev[li].wdpad) * J->dev[li].wnpad, st),
+                     "clear t rows");
+  for (size_t li = 0; !rc && li < J->live.size(); ++li)
     if (J->skip_reduce[li] > 0)
       rc = hip_check(ctx, launch_copy_words(J->dev[li].resid, nullptr,
                                             static_cast<size_t>(J->skip_reduce[li]) * J->dev[li].CS, st),
@@ -737,7 +762,8 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
       }
       for (int pass = 0; pass < 3; ++pass) {
         const int cnt = L.wide_end[pass] - L.wide_begin[pass];
-        if ((rc = hip_check(ctx, launch_crt_wide(pass, probs, wide(pass) + L.wide_begin[pass], cnt, J->wide_lds[pass], T, st),
+        const int kp = (pass == 1 && J->wide_mfma) ? 3 : pass;
+        if ((rc = hip_check(ctx, launch_crt_wide(kp, probs, wide(pass) + L.wide_begin[pass], cnt, J->wide_lds[pass], T, st),
                             "launch")))
           return rc;
       }
@@ -807,7 +833,8 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
       return rc;
     if (s == kStageCrt)
       for (int pass = 0; pass < 3; ++pass)
-        if ((rc = hip_check(ctx, launch_crt_wide(pass, probs, wide(pass), static_cast<int>(J->wide_items[pass].size()),
+        if ((rc = hip_check(ctx, launch_crt_wide((pass == 1 && J->wide_mfma) ? 3 : pass, probs, wide(pass),
+                                                 static_cast<int>(J->wide_items[pass].size()),
                                                  J->wide_lds[pass], T, st), "launch")))
           return rc;
   }

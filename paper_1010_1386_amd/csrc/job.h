@@ -22,7 +22,7 @@ namespace rsl {
 // Schedule parameters chosen by the autotuner (tune.cpp).
 struct ProbLayout {
   // offsets from the job base
-  size_t coeff, gdeg, pidx, Hm, NH, Tg, invM, Plimb, Mi, wdir, rinv, negM, Mw, NHM, status;
+  size_t coeff, gdeg, pidx, Hm, NH, Tg, invM, Plimb, Mi, wdir, rinv, negM, Mw, NHM, wMd, status;
   size_t out, resid, zval, zbad, aconv, cpart, wT, wq, wS;
   int L_in;
   int item_begin[kNumStages], item_end[kNumStages];
@@ -52,6 +52,7 @@ struct Job {
   // wide CRT (problems with more primes than the per-lane slots cover): items of
   // its three passes
   std::vector<WorkItem> wide_items[3];
+  bool wide_mfma = false;          // the contraction (pass 1) runs on the matrix cores
   size_t wide_off[3] = {};
   size_t wide_lds[3] = {};
   size_t items_off[kNumStages] = {};

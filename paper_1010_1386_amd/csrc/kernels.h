@@ -17,7 +17,7 @@ hipError_t launch_eval(int variant, const DevProblem* probs, const WorkItem* ite
                        const DevTables& T, hipStream_t st);
 
 // Pass 0, 1 or 2 of the wide CRT (t values and quotients, column sums, carries
-// and output) over `nitems` items.
+// and output) over `nitems` items; pass 3 is pass 1 on the matrix cores.
 hipError_t launch_crt_wide(int pass, const DevProblem* probs, const WorkItem* items, int nitems, size_t lds,
                            const DevTables& T, hipStream_t st);
 

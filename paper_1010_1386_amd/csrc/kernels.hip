@@ -111,6 +111,12 @@ __global__ __launch_bounds__(64) void k_crt_wide_fin(const DevProblem* probs, co
   stage_crt_wide_fin(probs[w.prob], w, lds);
 }
 
+__global__ __launch_bounds__(256) void k_crt_wide_sum_mfma(const DevProblem* probs, const WorkItem* items) {
+  extern __shared__ uint4 lds4[];
+  const WorkItem w = items[blockIdx.x];
+  stage_crt_wide_sum_mfma(probs[w.prob], w, reinterpret_cast<uint32_t*>(lds4));
+}
+
 hipError_t launch_crt_wide(int pass, const DevProblem* probs, const WorkItem* items, int nitems, size_t lds,
                            const DevTables& T, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
@@ -119,6 +125,7 @@ hipError_t launch_crt_wide(int pass, const DevProblem* probs, const WorkItem* it
     case 0: hipLaunchKernelGGL(k_crt_wide_t, g, dim3(256), lds, st, probs, items, T); break;
     case 1: hipLaunchKernelGGL(k_crt_wide_sum, g, dim3(kWideHT), lds, st, probs, items); break;
     case 2: hipLaunchKernelGGL(k_crt_wide_fin, g, dim3(64), lds, st, probs, items); break;
+    case 3: hipLaunchKernelGGL(k_crt_wide_sum_mfma, g, dim3(256), lds, st, probs, items); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

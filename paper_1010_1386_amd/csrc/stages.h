@@ -1540,6 +1540,7 @@ constexpr int kWideTCoeffs = 8;    // coefficients per block of pass 1 (256 thre
 constexpr int kWideKT = 16;        // coefficients per block of pass 2
 constexpr int kWideHT = 256;       // limbs per block of pass 2 (one per thread)
 constexpr int kWideChunk = 64;     // primes per LDS chunk of pass 2
+constexpr int kWideDigits = 5;     // 7-bit digits of t and of the M_i limbs (matrix-core pass 2)
 
 __host__ __device__ inline int wide_t_lds_words() { return 4 * 2 * kWideTCoeffs; }
 __host__ __device__ inline int wide_sum_lds_words() { return kWideChunk * kWideKT; }
@@ -1575,7 +1576,7 @@ __device__ inline void stage_crt_wide_t(const DevProblem& P, const DevTables& T,
     for (int ch = 0; ch < P.nchunk; ++ch) cs = add_fold(cs, cpp[ch * cstride], pc.p);
     const uint32_t u = maddm(redc(cs, pc.p, pc.pinv), P.Hm[i], pc.p);  // c_k + H mod p
     const uint32_t t = mmul(u, P.wdir[i], pc.p, pc.pinv);
-    if (valid) P.wT[static_cast<size_t>(k) * np + i] = t;
+    if (valid) P.wT[static_cast<size_t>(k) * P.wnpad + i] = t;
     const uint64_t f = static_cast<uint64_t>(t) * P.rinv[2 * i + 1] + __umulhi(t, P.rinv[2 * i]);
     fa += static_cast<uint32_t>(f) & 0xFFFFu;
     fb += static_cast<uint32_t>(f >> 16);
@@ -1631,7 +1632,7 @@ __device__ inline void stage_crt_wide_sum(const DevProblem& P, const WorkItem& w
     for (int e = threadIdx.x; e < kWideChunk * kWideKT; e += blockDim.x) {
       const int c = e / kWideChunk, ii = e - c * kWideChunk;  // coalesced along the primes of one row
       const int i = i0 + ii, k = k0 + c;
-      lds[ii * kWideKT + c] = (i < np && k <= P.D) ? P.wT[static_cast<size_t>(k) * np + i] : 0u;
+      lds[ii * kWideKT + c] = (i < np && k <= P.D) ? P.wT[static_cast<size_t>(k) * P.wnpad + i] : 0u;
     }
     __syncthreads();
     const int n = min(kWideChunk, np - i0);
@@ -1662,11 +1663,104 @@ __device__ inline void stage_crt_wide_sum(const DevProblem& P, const WorkItem& w
   if (tv_ok)
 #pragma unroll
     for (int c = 0; c < kWideKT; ++c)
-      if (k0 + c <= P.D) {
+      if (k0 + c <= P.D) {  // column sum of limb t: alo + ahi 2^16 (< 2^76) as (low, high) words
+        const unsigned __int128 v = static_cast<unsigned __int128>(alo[c]) + (static_cast<unsigned __int128>(ahi[c]) << 16);
         uint64_t* dst = P.wS + static_cast<size_t>(k0 + c) * nh + 2 * t;
-        dst[0] = alo[c];
-        dst[1] = ahi[c];
+        dst[0] = static_cast<uint64_t>(v);
+        dst[1] = static_cast<uint64_t>(v >> 64);
       }
+}
+
+// Pass 2 on the matrix cores.  t and the M_i limbs are split into five 7-bit
+// digits each (t = sum_a t_a 2^(7a), m = sum_b m_b 2^(7b), 35 bits >= 32), so
+// every digit is a non-negative int8; the int8 MFMA (16 x 16 outputs, 64
+// primes per step) accumulates sum_i t_a m_b in int32 per anti-diagonal
+// s = a + b: at most 5 * 127^2 * 4096 < 2^29 for 4096 primes, exact.  The
+// column sum is then sum_s D_s 2^(7s) < 2^85.  The limb digits are planes
+// Md[b][t][i] built with the job (a limb's primes contiguous); the block
+// stages its 32 limbs x 64 primes x 5 digits in LDS once per step for its
+// four waves.  The t values come from wT (rows padded with zeros to wnpad)
+// and are split into digits in registers.  Wave w takes coefficients
+// k0 + 16 w ... (one 16-row tile) and the block's 32 limbs (two 16-column
+// tiles); a lane holds row r of A and column r of B for the 16 primes of its
+// quarter kg (any fixed assignment of primes to the K slots serves, as long
+// as A and B use the same one).
+constexpr int kWideMfmaK = 64;   // primes per MFMA step (planes padded to a multiple)
+constexpr int kWideMfmaKT = 64;  // coefficients per block (four waves)
+constexpr int kWideMfmaTT = 32;  // limbs per block
+__host__ __device__ inline int wide_mfma_lds_words() { return kWideDigits * kWideMfmaTT * kWideMfmaK / 4; }
+typedef int wide_v4i __attribute__((ext_vector_type(4)));
+
+__device__ inline void stage_crt_wide_sum_mfma(const DevProblem& P, const WorkItem& w, uint32_t* lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int Lw = P.Lw, nh = 2 * Lw;
+  const int k0 = w.blk * kWideMfmaKT + 16 * wave;  // this wave's coefficient tile
+  const int t0 = w.sub * kWideMfmaTT;
+  const int r = lane & 15, kg = lane >> 4;
+  const size_t mplane = static_cast<size_t>(P.wlpad) * P.wnpad;
+  const uint32_t* trow = P.wT + static_cast<size_t>(k0 + r) * P.wnpad + 16 * kg;
+  uint4* bl = reinterpret_cast<uint4*>(lds);  // [digit][limb][prime quarter]
+  wide_v4i acc[2][2 * kWideDigits - 1];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int d = 0; d < 2 * kWideDigits - 1; ++d) acc[u][d] = wide_v4i{0, 0, 0, 0};
+  for (int i0 = 0; i0 < P.wnpad; i0 += kWideMfmaK) {
+    __syncthreads();  // the previous step's tile is consumed
+    for (int e = threadIdx.x; e < kWideDigits * kWideMfmaTT * 4; e += blockDim.x) {
+      const int d = e / (kWideMfmaTT * 4), rem = e - d * (kWideMfmaTT * 4), tl = rem >> 2, q = rem & 3;
+      bl[e] = *reinterpret_cast<const uint4*>(P.wMd + d * mplane + static_cast<size_t>(t0 + tl) * P.wnpad + i0 + 16 * q);
+    }
+    // the wave's A: 16 t values, split into digit bytes
+    uint32_t tv[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint4 v = *reinterpret_cast<const uint4*>(trow + i0 + 4 * q);
+      tv[4 * q] = v.x;
+      tv[4 * q + 1] = v.y;
+      tv[4 * q + 2] = v.z;
+      tv[4 * q + 3] = v.w;
+    }
+    wide_v4i a[kWideDigits];
+#pragma unroll
+    for (int d = 0; d < kWideDigits; ++d)
+#pragma unroll
+      for (int wd = 0; wd < 4; ++wd) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int by = 0; by < 4; ++by) word |= ((tv[4 * wd + by] >> (7 * d)) & 127u) << (8 * by);
+        a[d][wd] = static_cast<int>(word);
+      }
+    __syncthreads();
+#pragma unroll
+    for (int db = 0; db < kWideDigits; ++db) {
+      const wide_v4i b0 = *reinterpret_cast<const wide_v4i*>(&bl[(db * kWideMfmaTT + r) * 4 + kg]);
+      const wide_v4i b1 = *reinterpret_cast<const wide_v4i*>(&bl[(db * kWideMfmaTT + 16 + r) * 4 + kg]);
+#pragma unroll
+      for (int da = 0; da < kWideDigits; ++da) {
+        acc[0][da + db] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[da], b0, acc[0][da + db], 0, 0, 0);
+        acc[1][da + db] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[da], b1, acc[1][da + db], 0, 0, 0);
+      }
+    }
+  }
+  // lane holds rows 4 kg + e (coefficients) of column r (limb) of each tile
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int t = t0 + 16 * u + r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = k0 + 4 * kg + e;
+      unsigned __int128 v = 0;
+#pragma unroll
+      for (int d = 0; d < 2 * kWideDigits - 1; ++d)
+        v += static_cast<unsigned __int128>(static_cast<uint32_t>(acc[u][d][e])) << (7 * d);
+      if (k <= P.D && t < Lw) {
+        uint64_t* dst = P.wS + static_cast<size_t>(k) * nh + 2 * t;
+        dst[0] = static_cast<uint64_t>(v);
+        dst[1] = static_cast<uint64_t>(v >> 64);
+      }
+    }
+  }
 }
 
 // Pass 3: one wave (the whole block) per coefficient k = blk.
@@ -1677,7 +1771,7 @@ __device__ inline void stage_crt_wide_fin(const DevProblem& P, const WorkItem& w
   const uint64_t* S = P.wS + static_cast<size_t>(k) * 2 * Lw;
   const uint32_t q = P.wq[k];
   uint32_t* y = lds;
-  // Y0 limbs, 64 at a time; V_t = S_{2t} + S_{2t+1} 2^16 + q negM_t < 2^77 is
+  // Y0 limbs, 64 at a time; V_t = (column sum of limb t) + q negM_t < 2^86 is
   // (lo: 64 bits, hi: 32 bits), and limb t is lo32(V_t) + mid32(V_{t-1}) +
   // hi(V_{t-2}) plus carries; the values of lanes 62 and 63 carry over
   uint32_t pm = 0u, ph1 = 0u, ph2 = 0u, pc1 = 0u;
@@ -1687,10 +1781,8 @@ __device__ inline void stage_crt_wide_fin(const DevProblem& P, const WorkItem& w
     uint64_t lo = 0u;
     uint32_t hi = 0u;
     if (t < Lw) {
-      const uint64_t s0 = S[2 * t], s1 = S[2 * t + 1];
-      const uint64_t a = s1 << 16;
-      lo = s0 + a;
-      hi = static_cast<uint32_t>(s1 >> 48) + (lo < a ? 1u : 0u);
+      lo = S[2 * t];
+      hi = static_cast<uint32_t>(S[2 * t + 1]);
       const uint64_t b = static_cast<uint64_t>(q) * P.negM[t];
       lo += b;
       hi += (lo < b) ? 1u : 0u;

@@ -176,3 +176,26 @@ def test_joint_projections_share_the_reduction(rsl, ctx):
             assert ctx.batch([(F, G, "y"), (F, G, "x")], mode=mode) == sep, mode
     F, G = systems[3]
     assert rsl.query(F, G, "y")["n_primes"] != rsl.query(F, G, "x")["n_primes"]
+
+
+def test_wide_contraction_matrix_cores_equal_valu(rsl, ctx, monkeypatch):
+    """The wide CRT's contraction on the matrix cores (7-bit digit planes, int8
+    MFMA, anti-diagonal int32 sums) and on the vector ALUs (16-bit half limbs)
+    give the same bits, on the 2^2048 sets and on small problems pushed past
+    512 primes."""
+    monkeypatch.setenv("RSL_WIDE_VALU", "1")
+    cv = rsl.Context(device=0, workspace_bytes=2 << 30)
+    monkeypatch.delenv("RSL_WIDE_VALU")
+    for deg in (9, 15):
+        probs = [(f, g, "y") for f, g in workloads.table3_curves(deg, 2048)[:4]]
+        assert ctx.batch(probs, mode="staged") == cv.batch(probs, mode="staged"), deg
+    rng = rng_for(724, 0)
+    small = [(dense_total(rng, 4, 30), dense_total(rng, 3, 30), "yx"[k % 2]) for k in range(4)]
+    ja, jb = ctx.job(small, extra_primes=700), cv.job(small, extra_primes=700)
+    for mode in ("staged", "plain"):
+        ja.run(mode)
+        jb.run(mode)
+        assert ja.results() == jb.results() == [oracle.res(f, g, v) for f, g, v in small], mode
+    ja.close()
+    jb.close()
+    cv.close()
