@@ -394,6 +394,7 @@ def main():
     # correctness gate: bit-exact against the oracle's stored digests
     job.run(mode)
     res = job.results()
+    counts = ctx.counters()  # of that results call: pairs, bad pairs, bad primes
     gold_path = os.path.join(ROOT, "tests", "golden", "cfg2.json")
     verified = None
     if os.path.exists(gold_path):
@@ -563,6 +564,8 @@ def main():
                    "chunk_target": tune["chunk_target"], "grid_mult": tune["grid_mult"]},
         "verified_bit_exact": verified,
         "modp_univariate_resultants_per_s": pairs / (ures_ms * 1e-3),
+        "modp_pairs": counts.get("pairs"), "bad_pairs": counts.get("bad_pairs"),
+        "bad_primes": counts.get("bad_primes"),
         "serial_value": serial_value,
         "serial_ms_per_step": dt1 / a.steps * 1e3,
         "plain_value": plain_value,
