@@ -281,6 +281,8 @@ typedef struct {
   int32_t chunk_target;   /* interpolation chunking of the layout */
   int32_t grid_mult;      /* persistent grid multiplier */
   int32_t eval_lanes;     /* most lanes per (prime, point) pair used by any problem */
+  int32_t eval_mfma;      /* problems whose evaluation sums run on the matrix cores (register form,
+                             two lanes per pair, x-degrees below 32) */
 } rsl_job_info;
 
 /* Plan n problems and upload their inputs (status per problem in `status`, may be NULL). */

@@ -83,7 +83,8 @@ class rsl_job_info(ctypes.Structure):
     _fields_ = [("n_problems", ctypes.c_int32), ("n_live", ctypes.c_int32), ("pairs", ctypes.c_int64),
                 ("mulmods", ctypes.c_int64), ("device_bytes", ctypes.c_size_t), ("upload_bytes", ctypes.c_size_t),
                 ("download_bytes", ctypes.c_size_t), ("layout_mode", ctypes.c_int32),
-                ("chunk_target", ctypes.c_int32), ("grid_mult", ctypes.c_int32), ("eval_lanes", ctypes.c_int32)]
+                ("chunk_target", ctypes.c_int32), ("grid_mult", ctypes.c_int32), ("eval_lanes", ctypes.c_int32),
+                ("eval_mfma", ctypes.c_int32)]
 
 
 class rsl_upoly(ctypes.Structure):

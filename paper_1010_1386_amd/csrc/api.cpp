@@ -285,6 +285,7 @@ int rsl_ctx_create(int device, void* d_workspace, size_t ws_bytes, void* stream,
   c->queue_wait_ticks = static_cast<int64_t>(wait_ms * khz);
   if (const char* env = std::getenv("RSL_CRT_GARNER")) c->crt_garner = std::atoi(env) != 0;
   if (const char* env = std::getenv("RSL_WIDE_VALU")) c->wide_valu = std::atoi(env) != 0;
+  if (const char* env = std::getenv("RSL_EVAL_HORNER")) c->eval_horner = std::atoi(env) != 0;
   *out = c;
   return RSL_OK;
 }

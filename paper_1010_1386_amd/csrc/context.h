@@ -67,6 +67,7 @@ struct rsl_ctx {
   int table_gen = 0;                          // bumped whenever the constant tables move
   int64_t queue_wait_ticks = 0;               // persistent launch: longest wait for a task (counter ticks)
   bool crt_garner = false;                    // test hook (RSL_CRT_GARNER): CRT by Garner's digits only
+  bool eval_horner = false;                   // test hook (RSL_EVAL_HORNER): register-form evaluation by Horner's rule only
   bool wide_valu = false;                     // test hook (RSL_WIDE_VALU): wide CRT contraction without matrix cores
   std::map<std::string, rsl::TuneEntry> tune_cache; // shape bucket -> best schedule
   rsl_counters last{};

@@ -51,10 +51,15 @@ struct DevProblem {
   int crt_garner;    // 1: CRT by Garner's digits only (test hook), 0: direct form with Garner fallback
   int schur;         // 1: univariate resultants by the Schur algorithm (one wave per pair)
   int wide;          // 1: CRT by the wide path (more primes than the per-lane slots cover)
+  int evmf;          // 1: the register form's Horner sums on the matrix cores (from the digit tiles)
+  int dRTf, dRTg;    // digit tiles: 16-row tiles of f and of g
+  int dfr;           // digit tiles: operand fragments per prime slot, 5 (dRTf + dRTg)
   // the same system eliminated in x (the next problem): the reduction of prime
   // slots < pshared also writes its residue tiles (transposed positions)
   int pshared, pmyp, pnyp, pgoff, pCS;
   uint32_t* presid;
+  int pdRTf, pdRTg, pdfr;  // the partner's digit tile shape (0 when it has none)
+  uint64_t* pdig;
   int Lw;            // limbs of the rows of Mi and of negM: L_out, or L_out + 1 for the wide path
   // inputs (uploaded)
   const uint32_t* coeff;  // ncoef * L_in two's complement limbs
@@ -73,6 +78,7 @@ struct DevProblem {
   const uint32_t* NHM;    // L_out: -(M-1)/2 - M mod 2^(32 L_out) (wide path)
   // intermediates and output
   uint32_t* resid;        // np * CS     transposed tiles, c R^2 mod p
+  uint64_t* dig;          // np * dfr * 64  7-bit digits of c mod p in matrix-core operand order (evmf)
   uint32_t* zval;         // np * (E+1)  R(x_i) mod p, normal form
   uint8_t* zbad;          // np * (E+1)  leading coefficient vanished at x_i
   uint64_t* aconv;        // ncchunk * np * (D+1): partial sums, REDC(sum) = Newton coefficient a_k

@@ -193,6 +193,13 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       d.regn = 0;
       J->any_schur = true;
     }
+    // the Horner sums on the matrix cores: the register form with two lanes
+    // per pair, at most 32 x-powers (one K slice of the products)
+    d.evmf = (d.evk == 2 && d.regn > 0 && !d.schur && P.rowf <= 32 && P.rowg <= 32 && !(ctx && ctx->eval_horner))
+                 ? 1 : 0;
+    d.dRTf = d.evmf ? dig_rt(P.my + 1) : 0;
+    d.dRTg = d.evmf ? dig_rt(P.ny + 1) : 0;
+    d.dfr = kDigits * (d.dRTf + d.dRTg);
     d.crt_garner = (ctx && ctx->crt_garner) ? 1 : 0;
     d.wide = P.wide ? 1 : 0;
     d.Lw = P.Lw;
@@ -219,6 +226,9 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       a.pnyp = b.nyp;
       a.pgoff = b.goff;
       a.pCS = b.CS;
+      a.pdRTf = b.dRTf;
+      a.pdRTg = b.dRTg;
+      a.pdfr = b.dfr;
     }
 
   // work items, problem by problem (so that each problem's items are contiguous)
@@ -494,6 +504,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     ProbLayout& L = J->lay[li];
     const size_t np = P.np;
     L.resid = o; o = align_up(o + np * d.CS * 4, A);
+    L.dig = o;   o = align_up(o + np * d.dfr * 512, A);
     L.zval = o;  o = align_up(o + np * (P.E + 1) * 4, A);
     L.zbad = o;  o = align_up(o + np * (P.E + 1), A);
     L.aconv = o; o = align_up(o + static_cast<size_t>(d.ncchunk) * np * (P.D + 1) * 8, A);
@@ -631,6 +642,7 @@ void job_bind(Job* J, uint8_t* base) {
     d.wS = P.wide ? reinterpret_cast<uint64_t*>(base + L.wS) : nullptr;
     d.wMd = (P.wide && d.wide_mfma) ? reinterpret_cast<const int8_t*>(base + L.wMd) : nullptr;
     d.resid = reinterpret_cast<uint32_t*>(base + L.resid);
+    d.dig = d.evmf ? reinterpret_cast<uint64_t*>(base + L.dig) : nullptr;
     d.zval = reinterpret_cast<uint32_t*>(base + L.zval);
     d.zbad = base + L.zbad;
     d.aconv = reinterpret_cast<uint64_t*>(base + L.aconv);
@@ -638,8 +650,11 @@ void job_bind(Job* J, uint8_t* base) {
     d.out = reinterpret_cast<uint32_t*>(base + L.out);
     d.status = reinterpret_cast<int*>(base + L.status);
   }
-  for (int li = 0; li < nl; ++li)
-    J->dev[li].presid = (J->partner[li] >= 0) ? reinterpret_cast<uint32_t*>(base + J->lay[J->partner[li]].resid) : nullptr;
+  for (int li = 0; li < nl; ++li) {
+    const int pa = J->partner[li];
+    J->dev[li].presid = (pa >= 0) ? reinterpret_cast<uint32_t*>(base + J->lay[pa].resid) : nullptr;
+    J->dev[li].pdig = (pa >= 0 && J->dev[pa].evmf) ? reinterpret_cast<uint64_t*>(base + J->lay[pa].dig) : nullptr;
+  }
   // initial queue image: one REDUCE task per (problem, prime slot), largest problems first
   // (none when a problem has more primes than the persistent schedule takes)
   if (J->max_np <= kMaxSlots) {
@@ -726,6 +741,11 @@ int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st, uint8_t* pinned) {
       rc = hip_check(ctx, launch_copy_words(J->dev[li].wT, nullptr,
                                             static_cast<size_t>(J->dev[li].wdpad) * J->dev[li].wnpad, st),
                      "clear t rows");
+  for (size_t li = 0; !rc && li < J->live.size(); ++li)
+    if (J->dev[li].evmf)  // digit tiles: only the coefficient positions are written
+      rc = hip_check(ctx, launch_copy_words(reinterpret_cast<uint32_t*>(J->dev[li].dig), nullptr,
+                                            static_cast<size_t>(J->dev[li].np) * J->dev[li].dfr * 128, st),
+                     "clear digit tiles");
   for (size_t li = 0; !rc && li < J->live.size(); ++li)
     if (J->skip_reduce[li] > 0)
       rc = hip_check(ctx, launch_copy_words(J->dev[li].resid, nullptr,

@@ -23,7 +23,7 @@ namespace rsl {
 struct ProbLayout {
   // offsets from the job base
   size_t coeff, gdeg, pidx, Hm, NH, Tg, invM, Plimb, Mi, wdir, rinv, negM, Mw, NHM, wMd, status;
-  size_t out, resid, zval, zbad, aconv, cpart, wT, wq, wS;
+  size_t out, resid, dig, zval, zbad, aconv, cpart, wT, wq, wS;
   int L_in;
   int item_begin[kNumStages], item_end[kNumStages];
   int wide_begin[3], wide_end[3];  // ranges of Job::wide_items[pass] (wide CRT)

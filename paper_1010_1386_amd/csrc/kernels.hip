@@ -63,6 +63,10 @@ hipError_t launch_eval(int variant, const DevProblem* probs, const WorkItem* ite
     case kEvP24: hipLaunchKernelGGL(k_eval_ures<kEvP24>, g, b, lds, st, probs, items, T); break;
     case kEvP32: hipLaunchKernelGGL(k_eval_ures<kEvP32>, g, b, lds, st, probs, items, T); break;
     case kEvSchur: hipLaunchKernelGGL(k_eval_ures<kEvSchur>, g, b, lds, st, probs, items, T); break;
+    case kEvM8: hipLaunchKernelGGL(k_eval_ures<kEvM8>, g, b, lds, st, probs, items, T); break;
+    case kEvM16: hipLaunchKernelGGL(k_eval_ures<kEvM16>, g, b, lds, st, probs, items, T); break;
+    case kEvM24: hipLaunchKernelGGL(k_eval_ures<kEvM24>, g, b, lds, st, probs, items, T); break;
+    case kEvM32: hipLaunchKernelGGL(k_eval_ures<kEvM32>, g, b, lds, st, probs, items, T); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

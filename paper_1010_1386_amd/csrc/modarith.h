@@ -44,8 +44,9 @@ RSL_HD uint32_t mmulsub(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t
   return redc(t, p, pinv);
 }
 
-// (a b + c d + e f) / R mod p for all operands < p: the sum is < 3 p^2 < 2^64;
-// one conditional subtraction of p R on the high word brings it below p R.
+// (a b + c d + e f) / R mod p for all operands <= p: the sum is < 3 p^2 + 3p < 2^64
+// and its high word is below 1.5 p, so one conditional subtraction of p R on
+// the high word brings it below p R.
 RSL_HD uint32_t mmad3(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t e, uint32_t f,
                       uint32_t p, uint32_t pinv) {
   uint64_t t = static_cast<uint64_t>(a) * b + static_cast<uint64_t>(c) * d +

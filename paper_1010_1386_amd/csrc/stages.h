@@ -148,6 +148,42 @@ __device__ inline int partner_pos(const DevProblem& P, int t) {
   return P.pgoff + j * P.pnyp + i;
 }
 
+// Tile position t -> polynomial gp (0: f, 1: g), x-power i and row j; returns
+// the input coefficient's index, -1 for a padding position.
+__device__ inline int tile_coord(const DevProblem& P, int t, int* gp, int* i, int* j) {
+  if (t < P.goff) {
+    *gp = 0;
+    *i = t / P.myp;
+    *j = t - *i * P.myp;
+    return (*j <= P.my) ? *j * P.rowf + *i : -1;
+  }
+  const int u = t - P.goff;
+  *gp = 1;
+  *i = u / P.nyp;
+  *j = u - *i * P.nyp;
+  return (*i < P.rowg && *j <= P.ny) ? (P.my + 1) * P.rowf + *j * P.rowg + *i : -1;
+}
+
+// Digit tiles (evaluation on the matrix cores).  The residue c mod p of the
+// coefficient at x-power i (< 32) and row j of f (gp = 0) or g (gp = 1) is
+// kept as five 7-bit digits: digit b lies in operand fragment b RT + j / 16 of
+// its polynomial (RT = its 16-row tiles; g's fragments follow f's), lane
+// (j mod 16) + 16 (i / 8), byte i mod 8 -- the B operand order of
+// v_mfma_i32_16x16x32_i8 (lane l: column l mod 16, K slice l / 16), so that a
+// wave reads one fragment as one coalesced 8-byte load per lane.  Padding
+// positions are never written (the tiles are cleared at upload).
+__host__ __device__ inline int dig_rt(int rows) { return (rows + 15) / 16; }
+constexpr int kDigits = 5;
+__device__ inline void write_digits(uint64_t* dig, int fr, int rtf, int rtg, int slot, int gp, int i, int j,
+                                    uint32_t r) {
+  const int rt = gp ? rtg : rtf;
+  uint8_t* base = reinterpret_cast<uint8_t*>(dig + (static_cast<size_t>(slot) * fr + (gp ? kDigits * rtf : 0)) * 64);
+  const size_t at = (static_cast<size_t>(j >> 4) * 64 + (j & 15) + 16 * (i >> 3)) * 8 + (i & 7);
+#pragma unroll
+  for (int b = 0; b < kDigits; ++b)
+    base[static_cast<size_t>(b) * rt * 512 + at] = static_cast<uint8_t>((r >> (7 * b)) & 127u);
+}
+
 __device__ inline void stage_reduce(const DevProblem& P, const DevTables& T, const WorkItem& w,
                                     bool zero_status = false) {
   if (zero_status && w.slot == 0 && w.blk == 0)
@@ -155,21 +191,16 @@ __device__ inline void stage_reduce(const DevProblem& P, const DevTables& T, con
   const int t = w.blk * blockDim.x + threadIdx.x;
   if (t >= P.CS) return;
   const PrimeConst pc = T.pc[P.pidx[w.slot]];
-  int in = -1;
-  if (t < P.goff) {
-    const int i = t / P.myp, j = t - i * P.myp;
-    if (j <= P.my) in = j * P.rowf + i;
-  } else {
-    const int u = t - P.goff;
-    const int i = u / P.nyp, j = u - i * P.nyp;
-    if (i < P.rowg && j <= P.ny) in = (P.my + 1) * P.rowf + j * P.rowg + i;
-  }
+  int gp, ci, cj;
+  const int in = tile_coord(P, t, &gp, &ci, &cj);
   uint32_t v = 0;
   if (in >= 0) {
     const uint32_t p = pc.p;
     const uint32_t r = limbs_mod_p(P.coeff + static_cast<size_t>(in) * P.L_in, P.L_in, pc);
     v = mmul(r, pc.r3, p, pc.pinv);
     if (w.slot < P.pshared) P.presid[static_cast<size_t>(w.slot) * P.pCS + partner_pos(P, t)] = v;
+    if (P.dig) write_digits(P.dig, P.dfr, P.dRTf, P.dRTg, w.slot, gp, ci, cj, r);
+    if (P.pdig && w.slot < P.pshared) write_digits(P.pdig, P.pdfr, P.pdRTf, P.pdRTg, w.slot, gp, cj, ci, r);
   }
   P.resid[static_cast<size_t>(w.slot) * P.CS + t] = v;
 }
@@ -247,6 +278,8 @@ __device__ inline void stage_reduce_ml(const DevProblem& P, const DevTables& T, 
   }
   if (t >= P.CS) return;
   const int tp = (in >= 0 && w.slot < P.pshared) ? partner_pos(P, t) : 0;
+  int gp, ci, cj;
+  tile_coord(P, t, &gp, &ci, &cj);
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
     const int sl = w.slot + q + 4 * r;
@@ -254,6 +287,9 @@ __device__ inline void stage_reduce_ml(const DevProblem& P, const DevTables& T, 
       const uint32_t v = (in >= 0) ? mmul(acc[r], r3[r], p[r], pinv[r]) : 0u;
       P.resid[static_cast<size_t>(sl) * P.CS + t] = v;
       if (in >= 0 && sl < P.pshared) P.presid[static_cast<size_t>(sl) * P.pCS + tp] = v;
+      if (in >= 0 && P.dig) write_digits(P.dig, P.dfr, P.dRTf, P.dRTg, sl, gp, ci, cj, acc[r]);
+      if (in >= 0 && P.pdig && sl < P.pshared)
+        write_digits(P.pdig, P.pdfr, P.pdRTf, P.pdRTg, sl, gp, cj, ci, acc[r]);
     }
   }
 }
@@ -656,6 +692,144 @@ __device__ inline void stage_eval_ures_regs2(const DevProblem& P, const DevTable
   eval_report_bad(P, w.slot, pt, live, bad);
 }
 
+// ------------------------------------- eval on the matrix cores + ures_regs2
+// The values f_j(x_k) = sum_i c_ij x_k^i mod p of 32 points and every row j
+// form the product of the power matrix V[k][i] = x_k^i mod p with the residue
+// matrix C[i][j] (i < 32: the K dimension).  Both split into five 7-bit digits
+// (non-negative int8 operands); the digit products V_a C_b accumulate on the
+// matrix cores into the nine anti-diagonal sums S_s = sum_{a+b=s} V_a C_b,
+// each below 5 * 32 * 127^2 < 2^22, and
+//   f_j(x_k) R mod p = REDC(sum_s S_s (2^{7s} R^2 mod p))
+// (a sum below 9 * 2^22 * 2^31 < p 2^32).  Tiles of 16 points x 16 rows;
+// lane l of a 16x16x32 product holds A row l mod 16 (a point) and B column
+// l mod 16 (a row) for the K slice 8 (l / 16) .. 8 (l / 16) + 7, and gets the
+// outputs [4 (l / 16) + r][l mod 16], r < 4.  The values go through LDS into
+// the lane-pair layout of ures_regs2 (the same as stage_eval_ures_regs2).
+typedef int ev_v4i __attribute__((ext_vector_type(4)));
+__host__ __device__ inline int eval_mfma_row_stride(const DevProblem& P) {
+  return 16 * (P.dRTf > P.dRTg ? P.dRTf : P.dRTg) + 1;
+}
+__host__ __device__ inline int eval_mfma_lds_words(const DevProblem& P, int nmax) {
+  return 2 * 32 * eval_mfma_row_stride(P) + 2 * (nmax + 1) * 32;
+}
+
+template <int NMAX>
+__device__ inline void stage_eval_ures_mfma(const DevProblem& P, const DevTables& T, const WorkItem& w,
+                                            uint32_t* lds) {
+  constexpr int N2 = RegPoly2<NMAX>::kN;
+  const int lane = threadIdx.x;
+  const PrimeConst pc = T.pc[P.pidx[w.slot]];
+  const uint32_t p = pc.p, pinv = pc.pinv;
+  const int SR = eval_mfma_row_stride(P);
+  uint32_t* Fv[2] = {lds, lds + 32 * SR};
+  uint32_t* cols = lds + 64 * SR;
+
+  // B operands (digit fragments of the residues), one group per 16-row tile
+  // of f, then of g; the next group's loads are issued a group ahead
+  typedef const __attribute__((address_space(1))) uint64_t* gptr;  // global loads (not flat)
+  const gptr dg = (gptr)(P.dig + static_cast<size_t>(w.slot) * P.dfr * 64);
+  const int ng = P.dRTf + P.dRTg;
+  auto frag = [&](int gi, int b) {
+    const int f = gi < P.dRTf ? b * P.dRTf + gi : kDigits * P.dRTf + b * P.dRTg + (gi - P.dRTf);
+    return dg[static_cast<size_t>(f) * 64 + lane];
+  };
+  uint64_t Bn[kDigits];
+#pragma unroll
+  for (int b = 0; b < kDigits; ++b) Bn[b] = frag(0, b);
+  __builtin_amdgcn_sched_barrier(0);  // issue the loads here, not next to their use
+
+  // A operands: digit a of x_k^(8 g + e), e < 8, for the point k = lane mod 16
+  // of each 16-point tile h and the K slice g = lane / 16
+  uint64_t A[2][kDigits];
+  const int g = lane >> 4;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int pt = w.blk * 32 + 16 * h + (lane & 15);
+    const uint32_t x = static_cast<uint32_t>(P.origin + (pt < P.E ? pt : P.E));
+    const uint32_t xt = mmul(x, pc.r2, p, pinv);
+    const uint32_t x2 = mmul(xt, xt, p, pinv), x4 = mmul(x2, x2, p, pinv), x8 = mmul(x4, x4, p, pinv);
+    const uint32_t x16 = mmul(x8, x8, p, pinv), x24 = mmul(x16, x8, p, pinv);
+    uint32_t pw = g == 0 ? pc.r1 : g == 1 ? x8 : g == 2 ? x16 : x24;
+    uint32_t v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      v[e] = redc(pw, p, pinv);  // x^(8 g + e) mod p
+      if (e < 7) pw = mmul(pw, xt, p, pinv);
+    }
+#pragma unroll
+    for (int a = 0; a < kDigits; ++a) {
+      uint32_t lo = 0u, hi = 0u;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        lo |= ((v[e] >> (7 * a)) & 127u) << (8 * e);
+        hi |= ((v[e + 4] >> (7 * a)) & 127u) << (8 * e);
+      }
+      A[h][a] = (static_cast<uint64_t>(hi) << 32) | lo;
+    }
+  }
+  // recombination weights 2^(7 s) R^2 mod p
+  uint32_t wsum[2 * kDigits - 1];
+  wsum[0] = pc.r2;
+  const uint32_t t128 = mmul(128u, pc.r2, p, pinv);
+#pragma unroll
+  for (int s = 1; s < 2 * kDigits - 1; ++s) wsum[s] = mmul(wsum[s - 1], t128, p, pinv);
+
+  for (int gi = 0; gi < ng; ++gi) {
+    uint64_t B[kDigits];
+#pragma unroll
+    for (int b = 0; b < kDigits; ++b) B[b] = Bn[b];
+    if (gi + 1 < ng) {
+#pragma unroll
+      for (int b = 0; b < kDigits; ++b) Bn[b] = frag(gi + 1, b);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const int gp = gi >= P.dRTf ? 1 : 0, rt = gp ? gi - P.dRTf : gi;
+    uint32_t* F = Fv[gp];
+    {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        ev_v4i S[2 * kDigits - 1];
+#pragma unroll
+        for (int s = 0; s < 2 * kDigits - 1; ++s) S[s] = ev_v4i{0, 0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < kDigits; ++a)
+#pragma unroll
+          for (int b = 0; b < kDigits; ++b)
+            S[a + b] = __builtin_amdgcn_mfma_i32_16x16x32_i8(static_cast<long>(A[h][a]), static_cast<long>(B[b]),
+                                                             S[a + b], 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          uint64_t t = 0;
+#pragma unroll
+          for (int s = 0; s < 2 * kDigits - 1; ++s) t += static_cast<uint64_t>(static_cast<uint32_t>(S[s][r])) * wsum[s];
+          F[(16 * h + 4 * g + r) * SR + 16 * rt + (lane & 15)] = redc(t, p, pinv);
+        }
+      }
+    }
+  }
+  WaveSync()();
+
+  const int l = lane & 1, q = lane >> 1;
+  const int pt = w.blk * 32 + q;
+  uint32_t X[N2], Y[N2];
+#pragma unroll
+  for (int k = 0; k < N2; ++k) {
+    const int j = 2 * k + l;
+    X[k] = (j <= P.my) ? Fv[0][q * SR + j] : 0u;
+    Y[k] = (j <= P.ny) ? Fv[1][q * SR + j] : 0u;
+  }
+  bool bad = false;
+  const uint32_t r = ures_regs2<NMAX>(X, Y, P.my, P.ny, l, pc, &bad, Column<32>{cols + q},
+                                      Column<32>{cols + (NMAX + 1) * 32 + q}, PairSwap(), WaveSync());
+  const bool live = pt <= P.E && l == 0;
+  if (live) {
+    const size_t o = static_cast<size_t>(w.slot) * (P.E + 1) + pt;
+    P.zval[o] = redc(r, p, pinv);
+    P.zbad[o] = bad ? 1 : 0;
+  }
+  eval_report_bad(P, w.slot, pt, live, bad);
+}
+
 // ------------------------------------------------ eval + Schur (Sec. 4.1)
 // The univariate resultant as the determinant of the Sylvester matrix S
 // (n_y rows of f's coefficients, then m_y rows of g's), triangularised by the
@@ -777,7 +951,7 @@ __device__ inline void stage_eval_schur(const DevProblem& P, const DevTables& T,
 // LDS words of the evaluation launch for the problem's layout.
 __host__ __device__ inline int eval_stage_lds_words(const DevProblem& P) {
   if (P.schur) return eval_schur_lds_words(P);
-  if (P.evk == 2 && P.regn) return eval_regs2_lds_words(P, P.regn);
+  if (P.evk == 2 && P.regn) return P.evmf ? eval_mfma_lds_words(P, P.regn) : eval_regs2_lds_words(P, P.regn);
   if (P.evk > 1) return eval_group_lds_words(P, P.evk);
   return P.regn ? eval_regs_lds_words(P, P.regn) : eval_lds_words(P);
 }
@@ -790,12 +964,13 @@ enum : int {
   kEvR8, kEvR16, kEvR24, kEvR32,  // one lane per pair, registers (degree bound)
   kEvP8, kEvP16, kEvP24, kEvP32,  // two lanes per pair, registers
   kEvSchur,     // one wave per pair, Schur algorithm on the Sylvester generators
+  kEvM8, kEvM16, kEvM24, kEvM32,  // two lanes per pair, registers, Horner sums on the matrix cores
   kEvNum
 };
 __host__ __device__ inline int eval_variant(const DevProblem& P) {
   if (P.schur) return kEvSchur;
   const int r = P.regn == 8 ? 0 : P.regn == 16 ? 1 : P.regn == 24 ? 2 : 3;
-  if (P.evk == 2 && P.regn) return kEvP8 + r;
+  if (P.evk == 2 && P.regn) return (P.evmf ? kEvM8 : kEvP8) + r;
   if (P.evk == 2) return kEvG2;
   if (P.evk == 4) return kEvG4;
   if (P.regn) return kEvR8 + r;
@@ -808,6 +983,7 @@ __device__ inline void stage_eval_variant(const DevProblem& P, const DevTables& 
   else if constexpr (V == kEvG4) stage_eval_ures_group<4>(P, T, w, lds);
   else if constexpr (V >= kEvR8 && V <= kEvR32) stage_eval_ures_regs<8 * (V - kEvR8 + 1)>(P, T, w, lds);
   else if constexpr (V == kEvSchur) stage_eval_schur(P, T, w, lds);
+  else if constexpr (V >= kEvM8) stage_eval_ures_mfma<8 * (V - kEvM8 + 1)>(P, T, w, lds);
   else stage_eval_ures_regs2<8 * (V - kEvP8 + 1)>(P, T, w, lds);
 }
 

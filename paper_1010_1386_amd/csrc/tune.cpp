@@ -261,6 +261,9 @@ int rsl_job_info_get(const rsl_job* j, rsl_job_info* info) {
   int lanes = 1;
   for (const DevProblem& d : j->J.dev) lanes = std::max(lanes, d.evk);
   info->eval_lanes = lanes;
+  int mf = 0;
+  for (const DevProblem& d : j->J.dev) mf += d.evmf;
+  info->eval_mfma = mf;
   return RSL_OK;
 }
 

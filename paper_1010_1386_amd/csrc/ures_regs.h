@@ -39,8 +39,8 @@ RSL_HD bool reg_step(uint32_t (&A)[N], const uint32_t (&B)[N], uint32_t p, uint3
   const uint32_t L = B[BS], lcA = A[BS + 1], Ab = A[BS], Bb1 = B[BS - 1];
   const uint32_t lcAt = mmulsub(L, Ab, lcA, Bb1, p, pinv);
   const uint32_t alpha = mmul(L, L, p, pinv);
-  const uint32_t beta = mneg(mmul(L, lcA, p, pinv), p);
-  const uint32_t gamma = mneg(lcAt, p);
+  const uint32_t beta = p - mmul(L, lcA, p, pinv);  // in [1, p]: mmad3 takes operands up to p
+  const uint32_t gamma = p - lcAt;
 #pragma unroll
   for (int j = 0; j < BS; ++j) A[j] = mmad3(alpha, A[j], beta, j > 0 ? B[j - 1] : 0u, gamma, B[j], p, pinv);
   *L_out = L;
@@ -225,8 +225,8 @@ RSL_HD bool reg2_step(uint32_t (&A)[N], const uint32_t (&B)[N], int l, uint32_t 
   const uint32_t Ab = reg2_at<BS>(A, l, swp), Bb1 = reg2_at<BS - 1>(B, l, swp);
   const uint32_t lcAt = mmulsub(L, Ab, lcA, Bb1, p, pinv);
   const uint32_t alpha = mmul(L, L, p, pinv);
-  const uint32_t beta = mneg(mmul(L, lcA, p, pinv), p);
-  const uint32_t gamma = mneg(lcAt, p);
+  const uint32_t beta = p - mmul(L, lcA, p, pinv);  // in [1, p]: mmad3 takes operands up to p
+  const uint32_t gamma = p - lcAt;
   constexpr int KE = (BS - 1) / 2;  // last element updated (lane 1 may write R[BS], never read)
   uint32_t bsw[KE + 1];
 #pragma unroll
