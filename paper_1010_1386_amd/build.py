@@ -26,6 +26,9 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed fp32 forms are never wanted in this integer code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # matrix-core accumulators in ordinary VGPRs: no AGPR copies before the
+         # VALU reads them, and a smaller register footprint per wave
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1",
          "-fno-strict-aliasing", "-Wall", "-Wno-unused-result"]
 
 

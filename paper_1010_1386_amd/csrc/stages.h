@@ -706,11 +706,15 @@ __device__ inline void stage_eval_ures_regs2(const DevProblem& P, const DevTable
 // outputs [4 (l / 16) + r][l mod 16], r < 4.  The values go through LDS into
 // the lane-pair layout of ures_regs2 (the same as stage_eval_ures_regs2).
 typedef int ev_v4i __attribute__((ext_vector_type(4)));
+// LDS: the values [poly][point][row] (odd row stride), and in the same words
+// the two scratch columns per pair of the restart path (read only after the
+// values of the restarting pairs are back in registers).
 __host__ __device__ inline int eval_mfma_row_stride(const DevProblem& P) {
-  return 16 * (P.dRTf > P.dRTg ? P.dRTf : P.dRTg) + 1;
+  return ((P.my > P.ny ? P.my : P.ny) + 1) | 1;
 }
 __host__ __device__ inline int eval_mfma_lds_words(const DevProblem& P, int nmax) {
-  return 2 * 32 * eval_mfma_row_stride(P) + 2 * (nmax + 1) * 32;
+  const int vals = 2 * 32 * eval_mfma_row_stride(P), cols = 2 * (nmax + 1) * 32;
+  return vals > cols ? vals : cols;
 }
 
 template <int NMAX>
@@ -722,7 +726,7 @@ __device__ inline void stage_eval_ures_mfma(const DevProblem& P, const DevTables
   const uint32_t p = pc.p, pinv = pc.pinv;
   const int SR = eval_mfma_row_stride(P);
   uint32_t* Fv[2] = {lds, lds + 32 * SR};
-  uint32_t* cols = lds + 64 * SR;
+  uint32_t* cols = lds;  // restart path only
 
   // B operands (digit fragments of the residues), one group per 16-row tile
   // of f, then of g; the next group's loads are issued a group ahead
@@ -785,6 +789,8 @@ __device__ inline void stage_eval_ures_mfma(const DevProblem& P, const DevTables
     __builtin_amdgcn_sched_barrier(0);
     const int gp = gi >= P.dRTf ? 1 : 0, rt = gp ? gi - P.dRTf : gi;
     uint32_t* F = Fv[gp];
+    const int row = 16 * rt + (lane & 15);
+    const bool keep = row <= (gp ? P.ny : P.my);
     {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -802,7 +808,7 @@ __device__ inline void stage_eval_ures_mfma(const DevProblem& P, const DevTables
           uint64_t t = 0;
 #pragma unroll
           for (int s = 0; s < 2 * kDigits - 1; ++s) t += static_cast<uint64_t>(static_cast<uint32_t>(S[s][r])) * wsum[s];
-          F[(16 * h + 4 * g + r) * SR + 16 * rt + (lane & 15)] = redc(t, p, pinv);
+          if (keep) F[(16 * h + 4 * g + r) * SR + row] = redc(t, p, pinv);
         }
       }
     }
@@ -818,9 +824,22 @@ __device__ inline void stage_eval_ures_mfma(const DevProblem& P, const DevTables
     X[k] = (j <= P.my) ? Fv[0][q * SR + j] : 0u;
     Y[k] = (j <= P.ny) ? Fv[1][q * SR + j] : 0u;
   }
-  bool bad = false;
-  const uint32_t r = ures_regs2<NMAX>(X, Y, P.my, P.ny, l, pc, &bad, Column<32>{cols + q},
-                                      Column<32>{cols + (NMAX + 1) * 32 + q}, PairSwap(), WaveSync());
+  // the generic remainder sequence without per-step branches; a pair that
+  // leaves it (a vanishing leading coefficient, a degree drop) starts over
+  // from its values in LDS with the general column code
+  bool ok, bad;
+  uint32_t r = ures_regs2_generic<NMAX>(X, Y, P.my, P.ny, l, pc, &ok, &bad, PairSwap());
+  if (!ok) {
+#pragma unroll
+    for (int k = 0; k < N2; ++k) {
+      const int j = 2 * k + l;
+      X[k] = (j <= P.my) ? Fv[0][q * SR + j] : 0u;
+      Y[k] = (j <= P.ny) ? Fv[1][q * SR + j] : 0u;
+    }
+    WaveSync()();  // every restarting pair has its values before the columns overwrite them
+    r = ures2_columns<NMAX>(X, Y, P.my, P.ny, l, pc, Column<32>{cols + q}, Column<32>{cols + (NMAX + 1) * 32 + q},
+                            PairSwap(), WaveSync());
+  }
   const bool live = pt <= P.E && l == 0;
   if (live) {
     const size_t o = static_cast<size_t>(w.slot) * (P.E + 1) + pt;

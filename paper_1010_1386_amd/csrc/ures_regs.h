@@ -273,6 +273,119 @@ struct RegChain2<0, N> {
                          uint32_t&, bool&, int&, uint32_t&, uint32_t&) {}
 };
 
+// The generic chain without per-step branches: every step runs whatever its
+// divisor's leading coefficient, and ok collects whether each new remainder
+// kept degree deg B - 1 (if not, the value returned is meaningless and the
+// caller restarts from the original coefficients with ures2_columns).  All
+// branches depend only on the (per-problem) degrees, so the chain runs
+// without divergence; num equals U throughout the generic pattern.
+template <int BS, int N>
+struct RegChain2Gen {
+  template <class Swap>
+  RSL_HD static void run(uint32_t (&X)[N], uint32_t (&Y)[N], int l, int b0, uint32_t p, uint32_t pinv, Swap swp,
+                         uint32_t& den, uint32_t& U, bool& ok) {
+    if (BS <= b0) {
+      uint32_t L, y;
+      const bool generic = (BS & 1) ? reg2_step<BS>(X, Y, l, p, pinv, swp, &L, &y)
+                                    : reg2_step<BS>(Y, X, l, p, pinv, swp, &L, &y);
+      ok = ok && generic;
+      U = mmul(U, y, p, pinv);
+      den = mmul(den, U, p, pinv);
+    }
+    RegChain2Gen<BS - 1, N>::run(X, Y, l, b0, p, pinv, swp, den, U, ok);
+  }
+};
+template <int N>
+struct RegChain2Gen<0, N> {
+  template <class Swap>
+  RSL_HD static void run(uint32_t (&)[N], uint32_t (&)[N], int, int, uint32_t, uint32_t, Swap, uint32_t&, uint32_t&,
+                         bool&) {}
+};
+
+// Res_{m,n}(A, B) by a lane pair along the generic pattern only (layout as in
+// ures_regs2).  *ok is false when the shape is not the register form's, a
+// leading coefficient vanishes (*bad), or a remainder drops more than one
+// degree; both lanes get the same ok and result.
+template <int NMAX, class Swap>
+RSL_HD uint32_t ures_regs2_generic(uint32_t (&X)[RegPoly2<NMAX>::kN], uint32_t (&Y)[RegPoly2<NMAX>::kN], int m,
+                                   int n, int l, const PrimeConst& pc, bool* ok, bool* bad, Swap swp) {
+  constexpr int N = RegPoly2<NMAX>::kN;
+  const uint32_t p = pc.p, pinv = pc.pinv, one = pc.r1;
+  const uint32_t lcf = reg2_get(X, m, l, swp), lcg = reg2_get(Y, n, l, swp);
+  *bad = (lcf == 0u) || (lcg == 0u);
+  const bool shape_ok = m >= 1 && n >= 1 && m <= NMAX && n <= NMAX && (m - n <= 1) && (n - m <= 1);
+  bool good = shape_ok && !*bad;
+  uint32_t neg = 0u, den = one, U = one;
+  if (!shape_ok) {
+    *ok = false;
+    return 0u;
+  }
+  if (m < n) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const uint32_t t = X[k];
+      X[k] = Y[k];
+      Y[k] = t;
+    }
+    neg = static_cast<uint32_t>(m * n) & 1u;
+    const int t = m;
+    m = n;
+    n = t;
+  }
+  bool a_in_x = true;
+  int b0 = n;
+  if (m == n) {  // first division, k = 1: R = L A - lc(A) B
+    const uint32_t L = reg2_get(Y, n, l, swp), lcA = reg2_get(X, n, l, swp);
+#pragma unroll
+    for (int k = 0; k < N; ++k) X[k] = (2 * k + l < n) ? mmulsub(L, X[k], lcA, Y[k], p, pinv) : 0u;
+    good = good && reg2_get(X, n - 1, l, swp) != 0u;
+    neg ^= static_cast<uint32_t>(n * n) & 1u;
+    U = L;
+    den = L;
+    a_in_x = false;
+    b0 = n - 1;
+  }
+  if (b0 >= 1) {
+    if (a_in_x != ((b0 & 1) != 0)) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const uint32_t t = X[k];
+        X[k] = Y[k];
+        Y[k] = t;
+      }
+    }
+    RegChain2Gen<NMAX - 1, N>::run(X, Y, l, b0, p, pinv, swp, den, U, good);
+  }
+  *ok = good;
+  // the last remainder (degree 0) is in X; num = U
+  const uint32_t num = mmul(U, reg2_at<0>(X, l, swp), p, pinv);
+  const uint32_t r = mmul(num, minv(den, one, p, pinv), p, pinv);
+  return neg ? mneg(r, p) : r;
+}
+
+// Res_{m,n}(A, B) from the start by the general column code: the lane pair
+// writes its halves of A and B to its two columns, lane 0 runs ures_formal,
+// and both lanes return its result.
+template <int NMAX, class Col, class Swap, class Sync>
+RSL_HD uint32_t ures2_columns(const uint32_t (&X)[RegPoly2<NMAX>::kN], const uint32_t (&Y)[RegPoly2<NMAX>::kN],
+                              int m, int n, int l, const PrimeConst& pc, Col CA, Col CB, Swap swp, Sync sync) {
+  constexpr int N = RegPoly2<NMAX>::kN;
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+    if (2 * k + l <= NMAX) {
+      CA[2 * k + l] = X[k];
+      CB[2 * k + l] = Y[k];
+    }
+  sync();
+  uint32_t r = 0u;
+  if (l == 0) {
+    bool b2 = false;
+    r = ures_formal(CA, CB, m, n, pc, &b2);
+  }
+  const uint32_t ro = swp(r);
+  return l == 0 ? r : ro;
+}
+
 // Res_{m,n}(A, B) by a lane pair: lane l holds A's coefficients j = 2k + l in
 // X[k] and B's in Y[k].  Both lanes return the result.  CA, CB: the pair's two
 // shared scratch columns (NMAX + 1 entries); lanes that leave the register

@@ -107,9 +107,68 @@ int regs2_run(const PrimeConst& pc, int m, int n, const uint32_t* A, const uint3
   return 0;
 }
 
+// The matrix-core stage's lane-pair path: the branch-free generic chain, and
+// on its failure the column code from the original values.
+template <int NMAX>
+int regs2_gen_run(const PrimeConst& pc, int m, int n, const uint32_t* A, const uint32_t* B, uint32_t* out, int* bad,
+                  int* agree, int* generic) {
+  constexpr int N2 = RegPoly2<NMAX>::kN;
+  Barrier bar(2);
+  uint32_t slot[2] = {0, 0};
+  std::vector<uint32_t> ca(2 * N2 + 64, 0), cb(2 * N2 + 64, 0);
+  uint32_t r[2];
+  bool bd[2], okv[2];
+  std::vector<std::thread> th;
+  for (int l = 0; l < 2; ++l)
+    th.emplace_back([&, l] {
+      uint32_t X[N2] = {}, Y[N2] = {};
+      auto load = [&] {
+        for (int k = 0; k < N2; ++k) {
+          const int j = 2 * k + l;
+          X[k] = (j <= m) ? mmul(A[j] % pc.p, pc.r2, pc.p, pc.pinv) : 0u;
+          Y[k] = (j <= n) ? mmul(B[j] % pc.p, pc.r2, pc.p, pc.pinv) : 0u;
+        }
+      };
+      auto swp = [&](uint32_t v) {
+        slot[l] = v;
+        bar.wait();
+        const uint32_t o = slot[1 - l];
+        bar.wait();
+        return o;
+      };
+      load();
+      r[l] = ures_regs2_generic<NMAX>(X, Y, m, n, l, pc, &okv[l], &bd[l], swp);
+      if (!okv[l]) {
+        load();
+        r[l] = ures2_columns<NMAX>(X, Y, m, n, l, pc, Column<1>{ca.data()}, Column<1>{cb.data()}, swp,
+                                   [&] { bar.wait(); });
+      }
+    });
+  for (auto& t : th) t.join();
+  *agree = (r[0] == r[1] && bd[0] == bd[1] && okv[0] == okv[1]) ? 1 : 0;
+  *out = redc(r[0], pc.p, pc.pinv);
+  *bad = bd[0];
+  *generic = okv[0];
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
+
+// The branch-free generic chain of a lane pair with its column restart.
+int hs_ures_regs2_gen(int nmax, uint32_t p, int m, int n, const uint32_t* A, const uint32_t* B, uint32_t* out,
+                      int* bad, int* agree, int* generic) {
+  PrimeConst pc = make_prime_const(p);
+  if (m > nmax || n > nmax) return -1;
+  switch (nmax) {
+    case 8: return regs2_gen_run<8>(pc, m, n, A, B, out, bad, agree, generic);
+    case 16: return regs2_gen_run<16>(pc, m, n, A, B, out, bad, agree, generic);
+    case 24: return regs2_gen_run<24>(pc, m, n, A, B, out, bad, agree, generic);
+    case 32: return regs2_gen_run<32>(pc, m, n, A, B, out, bad, agree, generic);
+    default: return -1;
+  }
+}
 
 // The two-lanes-per-pair register form, run by two host threads.
 int hs_ures_regs2(int nmax, uint32_t p, int m, int n, const uint32_t* A, const uint32_t* B, uint32_t* out, int* bad,

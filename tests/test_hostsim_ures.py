@@ -29,6 +29,7 @@ def hs():
     if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
             os.path.getmtime(SRC),
             os.path.getmtime(os.path.join(HERE, "..", "paper_1010_1386_amd", "csrc", "ures.h")),
+            os.path.getmtime(os.path.join(HERE, "..", "paper_1010_1386_amd", "csrc", "ures_regs.h")),
             os.path.getmtime(os.path.join(HERE, "..", "paper_1010_1386_amd", "csrc", "modarith.h"))):
         subprocess.check_call(["hipcc", "-O2", "-fPIC", "-shared", "-o", LIB, SRC])
     lib = ctypes.CDLL(LIB)
@@ -41,6 +42,9 @@ def hs():
                                  ctypes.POINTER(ctypes.c_int)]
     lib.hs_ures_regs2.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p, u32p, u32p,
                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.hs_ures_regs2_gen.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p, u32p, u32p,
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_int)]
     lib.hs_ures_group.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p, u32p, u32p,
                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     return lib
@@ -54,7 +58,13 @@ def ures(hs, p, A, B, K=1):
     b = (ctypes.c_uint32 * len(B))(*B)
     out = ctypes.c_uint32()
     bad = ctypes.c_int()
-    if isinstance(K, str) and K.startswith("pair"):
+    if isinstance(K, str) and K.startswith("gen"):
+        nmax = int(K[3:])
+        agree, gen = ctypes.c_int(), ctypes.c_int()
+        assert hs.hs_ures_regs2_gen(nmax, p, m, n, a, b, ctypes.byref(out), ctypes.byref(bad), ctypes.byref(agree),
+                                    ctypes.byref(gen)) == 0
+        assert agree.value == 1, "the two lanes of the pair disagree"
+    elif isinstance(K, str) and K.startswith("pair"):
         nmax = int(K[4:])
         agree = ctypes.c_int()
         assert hs.hs_ures_regs2(nmax, p, m, n, a, b, ctypes.byref(out), ctypes.byref(bad), ctypes.byref(agree)) == 0
@@ -71,7 +81,7 @@ def ures(hs, p, A, B, K=1):
     return out.value, bool(bad.value)
 
 
-KS = [1, 2, 4, 8, "regs16", "pair16"]
+KS = [1, 2, 4, 8, "regs16", "pair16", "gen16"]
 
 
 def sylvester_det_mod(A, B, p):
@@ -110,7 +120,7 @@ def test_random_generic(hs, seed, K):
     assert got == sylvester_det_mod(A, B, p)
 
 
-@pytest.mark.parametrize("K", [1, 2, 4, 8, "regs32", "pair32"])
+@pytest.mark.parametrize("K", [1, 2, 4, 8, "regs32", "pair32", "gen32"])
 @pytest.mark.parametrize("seed", range(6))
 def test_random_large_degree(hs, seed, K):
     """Degrees 13..40: every lane of a group runs several four-way fused updates."""
@@ -179,7 +189,7 @@ def test_eval_rows(hs, seed):
         assert out[j] == poly_eval_mod(row, x, p)
 
 
-@pytest.mark.parametrize("form", ["regs", "pair"])
+@pytest.mark.parametrize("form", ["regs", "pair", "gen"])
 @pytest.mark.parametrize("nmax", [8, 16, 24, 32])
 @pytest.mark.parametrize("seed", range(40))
 def test_register_form_shapes(hs, form, nmax, seed):
@@ -208,3 +218,31 @@ def test_register_form_shapes(hs, form, nmax, seed):
     got, bad = ures(hs, p, A, B, "%s%d" % (form, nmax))
     assert got == sylvester_det_mod(A, B, p), (m, n, kind)
     assert bad == (A[-1] == 0 or B[-1] == 0)
+
+
+@pytest.mark.parametrize("nmax", [8, 24, 32])
+def test_branch_free_chain_takes_generic_inputs(hs, nmax):
+    """Random coefficients of the register form's shapes stay on the branch-free
+    chain (no restart), and its value is the Sylvester determinant; planted
+    degree drops and vanishing leading coefficients restart."""
+    rng = rng_for(955, nmax)
+    p = PRIMES[0]
+    for trial in range(12):
+        n = int(rng.integers(1, nmax + 1))
+        m = max(1, min(nmax, n + int(rng.integers(-1, 2))))
+        A = [int(v) for v in rng.integers(1, p, m + 1)]
+        B = [int(v) for v in rng.integers(1, p, n + 1)]
+        kind = trial % 3
+        if kind == 1:
+            A[-1] = 0
+        if kind == 2 and m >= 2 and n >= 2:  # common factor (y - 5): the remainders end in zero
+            A = polymul_mod([p - 5, 1], A[:m], p)
+            B = polymul_mod([p - 5, 1], B[:n], p)
+        a = (ctypes.c_uint32 * len(A))(*A)
+        b = (ctypes.c_uint32 * len(B))(*B)
+        out, bad, agree, gen = ctypes.c_uint32(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        assert hs.hs_ures_regs2_gen(nmax, p, m, n, a, b, ctypes.byref(out), ctypes.byref(bad), ctypes.byref(agree),
+                                    ctypes.byref(gen)) == 0
+        assert agree.value == 1
+        assert out.value == sylvester_det_mod(A, B, p), (m, n, kind)
+        assert gen.value == (1 if kind == 0 else 0) or (kind == 2 and min(m, n) < 2), (m, n, kind)
