@@ -193,9 +193,9 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       d.regn = 0;
       J->any_schur = true;
     }
-    // the Horner sums on the matrix cores: the register form with two lanes
-    // per pair, at most 32 x-powers (one K slice of the products)
-    d.evmf = (d.evk == 2 && d.regn > 0 && !d.schur && P.rowf <= 32 && P.rowg <= 32 && !(ctx && ctx->eval_horner))
+    // the Horner sums on the matrix cores: the register form (one lane or a
+    // lane pair per (prime, point)), at most 32 x-powers (one K slice of the products)
+    d.evmf = (d.evk <= 2 && d.regn > 0 && !d.schur && P.rowf <= 32 && P.rowg <= 32 && !(ctx && ctx->eval_horner))
                  ? 1 : 0;
     d.dRTf = d.evmf ? dig_rt(P.my + 1) : 0;
     d.dRTg = d.evmf ? dig_rt(P.ny + 1) : 0;

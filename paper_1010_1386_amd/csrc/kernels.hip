@@ -67,6 +67,10 @@ hipError_t launch_eval(int variant, const DevProblem* probs, const WorkItem* ite
     case kEvM16: hipLaunchKernelGGL(k_eval_ures<kEvM16>, g, b, lds, st, probs, items, T); break;
     case kEvM24: hipLaunchKernelGGL(k_eval_ures<kEvM24>, g, b, lds, st, probs, items, T); break;
     case kEvM32: hipLaunchKernelGGL(k_eval_ures<kEvM32>, g, b, lds, st, probs, items, T); break;
+    case kEvQ8: hipLaunchKernelGGL(k_eval_ures<kEvQ8>, g, b, lds, st, probs, items, T); break;
+    case kEvQ16: hipLaunchKernelGGL(k_eval_ures<kEvQ16>, g, b, lds, st, probs, items, T); break;
+    case kEvQ24: hipLaunchKernelGGL(k_eval_ures<kEvQ24>, g, b, lds, st, probs, items, T); break;
+    case kEvQ32: hipLaunchKernelGGL(k_eval_ures<kEvQ32>, g, b, lds, st, probs, items, T); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

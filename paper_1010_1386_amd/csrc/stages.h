@@ -712,20 +712,26 @@ typedef int ev_v4i __attribute__((ext_vector_type(4)));
 __host__ __device__ inline int eval_mfma_row_stride(const DevProblem& P) {
   return ((P.my > P.ny ? P.my : P.ny) + 1) | 1;
 }
-__host__ __device__ inline int eval_mfma_lds_words(const DevProblem& P, int nmax) {
-  const int vals = 2 * 32 * eval_mfma_row_stride(P), cols = 2 * (nmax + 1) * 32;
+__host__ __device__ inline int eval_mfma_lds_words(const DevProblem& P, int nmax, int kl) {
+  const int pts = 64 / kl;
+  const int vals = 2 * pts * eval_mfma_row_stride(P), cols = 2 * (nmax + 1) * pts;
   return vals > cols ? vals : cols;
 }
 
-template <int NMAX>
+// KL lanes per (prime, point) pair: 64 / KL points per wave (4 / KL tiles of
+// 16), then the register form's remainder sequence -- one lane per pair
+// (ures_regs_generic) or a lane pair (ures_regs2_generic) -- without per-step
+// branches; a pair that leaves the generic pattern starts over from its values
+// in LDS with the general column code.
+template <int NMAX, int KL>
 __device__ inline void stage_eval_ures_mfma(const DevProblem& P, const DevTables& T, const WorkItem& w,
                                             uint32_t* lds) {
-  constexpr int N2 = RegPoly2<NMAX>::kN;
+  constexpr int PTS = 64 / KL, H = PTS / 16;
   const int lane = threadIdx.x;
   const PrimeConst pc = T.pc[P.pidx[w.slot]];
   const uint32_t p = pc.p, pinv = pc.pinv;
   const int SR = eval_mfma_row_stride(P);
-  uint32_t* Fv[2] = {lds, lds + 32 * SR};
+  uint32_t* Fv[2] = {lds, lds + PTS * SR};
   uint32_t* cols = lds;  // restart path only
 
   // B operands (digit fragments of the residues), one group per 16-row tile
@@ -744,11 +750,11 @@ __device__ inline void stage_eval_ures_mfma(const DevProblem& P, const DevTables
 
   // A operands: digit a of x_k^(8 g + e), e < 8, for the point k = lane mod 16
   // of each 16-point tile h and the K slice g = lane / 16
-  uint64_t A[2][kDigits];
+  uint64_t A[H][kDigits];
   const int g = lane >> 4;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int pt = w.blk * 32 + 16 * h + (lane & 15);
+  for (int h = 0; h < H; ++h) {
+    const int pt = w.blk * PTS + 16 * h + (lane & 15);
     const uint32_t x = static_cast<uint32_t>(P.origin + (pt < P.E ? pt : P.E));
     const uint32_t xt = mmul(x, pc.r2, p, pinv);
     const uint32_t x2 = mmul(xt, xt, p, pinv), x4 = mmul(x2, x2, p, pinv), x8 = mmul(x4, x4, p, pinv);
@@ -791,56 +797,86 @@ __device__ inline void stage_eval_ures_mfma(const DevProblem& P, const DevTables
     uint32_t* F = Fv[gp];
     const int row = 16 * rt + (lane & 15);
     const bool keep = row <= (gp ? P.ny : P.my);
-    {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        ev_v4i S[2 * kDigits - 1];
+    for (int h = 0; h < H; ++h) {
+      ev_v4i S[2 * kDigits - 1];
 #pragma unroll
-        for (int s = 0; s < 2 * kDigits - 1; ++s) S[s] = ev_v4i{0, 0, 0, 0};
+      for (int s = 0; s < 2 * kDigits - 1; ++s) S[s] = ev_v4i{0, 0, 0, 0};
 #pragma unroll
-        for (int a = 0; a < kDigits; ++a)
+      for (int a = 0; a < kDigits; ++a)
 #pragma unroll
-          for (int b = 0; b < kDigits; ++b)
-            S[a + b] = __builtin_amdgcn_mfma_i32_16x16x32_i8(static_cast<long>(A[h][a]), static_cast<long>(B[b]),
-                                                             S[a + b], 0, 0, 0);
+        for (int b = 0; b < kDigits; ++b)
+          S[a + b] = __builtin_amdgcn_mfma_i32_16x16x32_i8(static_cast<long>(A[h][a]), static_cast<long>(B[b]),
+                                                           S[a + b], 0, 0, 0);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          uint64_t t = 0;
+      for (int r = 0; r < 4; ++r) {
+        uint64_t t = 0;
 #pragma unroll
-          for (int s = 0; s < 2 * kDigits - 1; ++s) t += static_cast<uint64_t>(static_cast<uint32_t>(S[s][r])) * wsum[s];
-          if (keep) F[(16 * h + 4 * g + r) * SR + row] = redc(t, p, pinv);
-        }
+        for (int s = 0; s < 2 * kDigits - 1; ++s) t += static_cast<uint64_t>(static_cast<uint32_t>(S[s][r])) * wsum[s];
+        if (keep) F[(16 * h + 4 * g + r) * SR + row] = redc(t, p, pinv);
       }
     }
   }
   WaveSync()();
 
-  const int l = lane & 1, q = lane >> 1;
-  const int pt = w.blk * 32 + q;
-  uint32_t X[N2], Y[N2];
-#pragma unroll
-  for (int k = 0; k < N2; ++k) {
-    const int j = 2 * k + l;
-    X[k] = (j <= P.my) ? Fv[0][q * SR + j] : 0u;
-    Y[k] = (j <= P.ny) ? Fv[1][q * SR + j] : 0u;
-  }
-  // the generic remainder sequence without per-step branches; a pair that
-  // leaves it (a vanishing leading coefficient, a degree drop) starts over
-  // from its values in LDS with the general column code
   bool ok, bad;
-  uint32_t r = ures_regs2_generic<NMAX>(X, Y, P.my, P.ny, l, pc, &ok, &bad, PairSwap());
-  if (!ok) {
+  uint32_t r;
+  int pt;
+  bool live;
+  if constexpr (KL == 2) {
+    constexpr int N2 = RegPoly2<NMAX>::kN;
+    const int l = lane & 1, q = lane >> 1;
+    pt = w.blk * PTS + q;
+    live = pt <= P.E && l == 0;
+    uint32_t X[N2], Y[N2];
 #pragma unroll
     for (int k = 0; k < N2; ++k) {
       const int j = 2 * k + l;
       X[k] = (j <= P.my) ? Fv[0][q * SR + j] : 0u;
       Y[k] = (j <= P.ny) ? Fv[1][q * SR + j] : 0u;
     }
-    WaveSync()();  // every restarting pair has its values before the columns overwrite them
-    r = ures2_columns<NMAX>(X, Y, P.my, P.ny, l, pc, Column<32>{cols + q}, Column<32>{cols + (NMAX + 1) * 32 + q},
-                            PairSwap(), WaveSync());
+    r = ures_regs2_generic<NMAX>(X, Y, P.my, P.ny, l, pc, &ok, &bad, PairSwap());
+    if (!ok) {
+#pragma unroll
+      for (int k = 0; k < N2; ++k) {
+        const int j = 2 * k + l;
+        X[k] = (j <= P.my) ? Fv[0][q * SR + j] : 0u;
+        Y[k] = (j <= P.ny) ? Fv[1][q * SR + j] : 0u;
+      }
+      WaveSync()();  // every restarting pair has its values before the columns overwrite them
+      r = ures2_columns<NMAX>(X, Y, P.my, P.ny, l, pc, Column<32>{cols + q},
+                              Column<32>{cols + (NMAX + 1) * 32 + q}, PairSwap(), WaveSync());
+    }
+  } else {
+    constexpr int N = RegPoly<NMAX>::kN;
+    pt = w.blk * PTS + lane;
+    live = pt <= P.E;
+    uint32_t X[N], Y[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      X[j] = (j <= P.my) ? Fv[0][lane * SR + j] : 0u;
+      Y[j] = (j <= P.ny) ? Fv[1][lane * SR + j] : 0u;
+    }
+    r = ures_regs_generic<NMAX>(X, Y, P.my, P.ny, pc, &ok, &bad);
+    if (!ok) {
+      // the restarting lanes read their values before any column is written
+      uint32_t va[NMAX + 1], vb[NMAX + 1];
+#pragma unroll
+      for (int j = 0; j <= NMAX; ++j) {
+        va[j] = (j <= P.my) ? Fv[0][lane * SR + j] : 0u;
+        vb[j] = (j <= P.ny) ? Fv[1][lane * SR + j] : 0u;
+      }
+      WaveSync()();
+      Column<64> CA{cols + lane}, CB{cols + (NMAX + 1) * 64 + lane};
+#pragma unroll
+      for (int j = 0; j <= NMAX; ++j) {
+        CA[j] = va[j];
+        CB[j] = vb[j];
+      }
+      bool b2 = false;
+      r = ures_formal(CA, CB, P.my, P.ny, pc, &b2);
+    }
   }
-  const bool live = pt <= P.E && l == 0;
   if (live) {
     const size_t o = static_cast<size_t>(w.slot) * (P.E + 1) + pt;
     P.zval[o] = redc(r, p, pinv);
@@ -970,7 +1006,8 @@ __device__ inline void stage_eval_schur(const DevProblem& P, const DevTables& T,
 // LDS words of the evaluation launch for the problem's layout.
 __host__ __device__ inline int eval_stage_lds_words(const DevProblem& P) {
   if (P.schur) return eval_schur_lds_words(P);
-  if (P.evk == 2 && P.regn) return P.evmf ? eval_mfma_lds_words(P, P.regn) : eval_regs2_lds_words(P, P.regn);
+  if (P.evmf) return eval_mfma_lds_words(P, P.regn, P.evk);
+  if (P.evk == 2 && P.regn) return eval_regs2_lds_words(P, P.regn);
   if (P.evk > 1) return eval_group_lds_words(P, P.evk);
   return P.regn ? eval_regs_lds_words(P, P.regn) : eval_lds_words(P);
 }
@@ -984,12 +1021,14 @@ enum : int {
   kEvP8, kEvP16, kEvP24, kEvP32,  // two lanes per pair, registers
   kEvSchur,     // one wave per pair, Schur algorithm on the Sylvester generators
   kEvM8, kEvM16, kEvM24, kEvM32,  // two lanes per pair, registers, Horner sums on the matrix cores
+  kEvQ8, kEvQ16, kEvQ24, kEvQ32,  // one lane per pair, registers, Horner sums on the matrix cores
   kEvNum
 };
 __host__ __device__ inline int eval_variant(const DevProblem& P) {
   if (P.schur) return kEvSchur;
   const int r = P.regn == 8 ? 0 : P.regn == 16 ? 1 : P.regn == 24 ? 2 : 3;
-  if (P.evk == 2 && P.regn) return (P.evmf ? kEvM8 : kEvP8) + r;
+  if (P.evmf) return (P.evk == 2 ? kEvM8 : kEvQ8) + r;
+  if (P.evk == 2 && P.regn) return kEvP8 + r;
   if (P.evk == 2) return kEvG2;
   if (P.evk == 4) return kEvG4;
   if (P.regn) return kEvR8 + r;
@@ -1002,7 +1041,8 @@ __device__ inline void stage_eval_variant(const DevProblem& P, const DevTables& 
   else if constexpr (V == kEvG4) stage_eval_ures_group<4>(P, T, w, lds);
   else if constexpr (V >= kEvR8 && V <= kEvR32) stage_eval_ures_regs<8 * (V - kEvR8 + 1)>(P, T, w, lds);
   else if constexpr (V == kEvSchur) stage_eval_schur(P, T, w, lds);
-  else if constexpr (V >= kEvM8) stage_eval_ures_mfma<8 * (V - kEvM8 + 1)>(P, T, w, lds);
+  else if constexpr (V >= kEvQ8) stage_eval_ures_mfma<8 * (V - kEvQ8 + 1), 1>(P, T, w, lds);
+  else if constexpr (V >= kEvM8) stage_eval_ures_mfma<8 * (V - kEvM8 + 1), 2>(P, T, w, lds);
   else stage_eval_ures_regs2<8 * (V - kEvP8 + 1)>(P, T, w, lds);
 }
 

@@ -190,6 +190,85 @@ RSL_HD uint32_t ures_regs(uint32_t (&X)[RegPoly<NMAX>::kN], uint32_t (&Y)[RegPol
   return ures_run(CB, CA, UresState{f_b, c, num, den, U, neg}, pc);
 }
 
+// The one-lane generic chain without per-step branches (as RegChain2Gen).
+template <int BS, int N>
+struct RegChainGen {
+  RSL_HD static void run(uint32_t (&X)[N], uint32_t (&Y)[N], int b0, uint32_t p, uint32_t pinv, uint32_t& den,
+                         uint32_t& U, bool& ok) {
+    if (BS <= b0) {
+      uint32_t L, y;
+      const bool generic = (BS & 1) ? reg_step<BS>(X, Y, p, pinv, &L, &y) : reg_step<BS>(Y, X, p, pinv, &L, &y);
+      ok = ok && generic;
+      U = mmul(U, y, p, pinv);
+      den = mmul(den, U, p, pinv);
+    }
+    RegChainGen<BS - 1, N>::run(X, Y, b0, p, pinv, den, U, ok);
+  }
+};
+template <int N>
+struct RegChainGen<0, N> {
+  RSL_HD static void run(uint32_t (&)[N], uint32_t (&)[N], int, uint32_t, uint32_t, uint32_t&, uint32_t&, bool&) {}
+};
+
+// Res_{m,n}(A, B) with A in X, B in Y (one lane) along the generic pattern
+// only; *ok as in ures_regs2_generic (on false the caller restarts from the
+// original coefficients with ures_formal on columns).
+template <int NMAX>
+RSL_HD uint32_t ures_regs_generic(uint32_t (&X)[RegPoly<NMAX>::kN], uint32_t (&Y)[RegPoly<NMAX>::kN], int m, int n,
+                                  const PrimeConst& pc, bool* ok, bool* bad) {
+  constexpr int N = RegPoly<NMAX>::kN;
+  const uint32_t p = pc.p, pinv = pc.pinv, one = pc.r1;
+  const uint32_t lcf = reg_get(X, m), lcg = reg_get(Y, n);
+  *bad = (lcf == 0u) || (lcg == 0u);
+  const bool shape_ok = m >= 1 && n >= 1 && m <= NMAX && n <= NMAX && (m - n <= 1) && (n - m <= 1);
+  if (!shape_ok) {
+    *ok = false;
+    return 0u;
+  }
+  bool good = !*bad;
+  uint32_t neg = 0u, den = one, U = one;
+  if (m < n) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const uint32_t t = X[j];
+      X[j] = Y[j];
+      Y[j] = t;
+    }
+    neg = static_cast<uint32_t>(m * n) & 1u;
+    const int t = m;
+    m = n;
+    n = t;
+  }
+  bool a_in_x = true;
+  int b0 = n;
+  if (m == n) {  // first division, k = 1: R = L A - lc(A) B
+    const uint32_t L = reg_get(Y, n), lcA = reg_get(X, n);
+#pragma unroll
+    for (int j = 0; j < N; ++j) X[j] = (j < n) ? mmulsub(L, X[j], lcA, Y[j], p, pinv) : 0u;
+    good = good && reg_get(X, n - 1) != 0u;
+    neg ^= static_cast<uint32_t>(n * n) & 1u;
+    U = L;
+    den = L;
+    a_in_x = false;
+    b0 = n - 1;
+  }
+  if (b0 >= 1) {
+    if (a_in_x != ((b0 & 1) != 0)) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const uint32_t t = X[j];
+        X[j] = Y[j];
+        Y[j] = t;
+      }
+    }
+    RegChainGen<NMAX - 1, N>::run(X, Y, b0, p, pinv, den, U, good);
+  }
+  *ok = good;
+  const uint32_t num = mmul(U, X[0], p, pinv);  // the last remainder (degree 0) is in X
+  const uint32_t r = mmul(num, minv(den, one, p, pinv), p, pinv);
+  return neg ? mneg(r, p) : r;
+}
+
 }  // namespace rsl
 
 namespace rsl {

@@ -1,4 +1,5 @@
-"""GPU: the register-form evaluation with its Horner sums on the matrix cores
+"""GPU: the register-form evaluation (one lane or a lane pair per (prime,
+point)) with its Horner sums on the matrix cores
 (7-bit digit tiles written by the reduction, int8 products of the point
 powers with the residues, nine anti-diagonal sums recombined modulo p) gives
 the same bits as Horner's rule on the vector ALUs and as the oracle: shapes
@@ -53,9 +54,9 @@ def digest(coeffs):
     return hashlib.sha256(",".join(str(c) for c in coeffs).encode()).hexdigest()
 
 
-def run(c, probs, modes=("staged", "plain")):
+def run(c, probs, modes=("staged", "plain"), lanes=2):
     """Results of one job in each mode (all equal), and its info."""
-    job = c.job(probs, eval_lanes=2)
+    job = c.job(probs, eval_lanes=lanes)
     info = job.info()
     out = {}
     for mode in modes:
@@ -76,18 +77,21 @@ def modq(probs, res, seed, n=2):
             assert oracle.peval(R, t) % q == oracle.res_at_point_mod(f, g, t, q, v), (q, t)
 
 
-def test_degree24_pair_matches_oracle_digests(ctx):
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_degree24_pair_matches_oracle_digests(ctx, lanes):
     f, g = workloads.config2()
-    res, info = run(ctx, [(f, g, "y"), (f, g, "x")])
-    assert info["eval_mfma"] == 2 and info["eval_lanes"] == 2
+    res, info = run(ctx, [(f, g, "y"), (f, g, "x")], lanes=lanes)
+    assert info["eval_mfma"] == 2 and info["eval_lanes"] == lanes
     with open(os.path.join(HERE, "golden", "cfg2.json")) as fh:
         gold = {r["name"]: r["sha256"] for r in json.load(fh)["records"]}
     assert digest(res[0]) == gold["cfg2_y"] and digest(res[1]) == gold["cfg2_x"]
 
 
-def test_small_shapes_match_oracle(ctx):
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_small_shapes_match_oracle(ctx, lanes):
     """Degrees 8..10 (the smallest with two lanes per pair), both projections
-    of each system (shared reduction), a vanishing leading coefficient."""
+    of each system (shared reduction), a vanishing leading coefficient; one
+    lane per pair also at degrees 1..3."""
     rng = rng_for(730, 0)
     probs = []
     for d, bits in [(8, 12), (9, 20), (10, 8)]:
@@ -96,12 +100,17 @@ def test_small_shapes_match_oracle(ctx):
     F = dense_total(rng, 10, 10)
     F[10] = [0, -5, 1]  # lc_y = x (x - 5): points 0 and 5 are bad for every prime
     probs.append((F, dense_total(rng, 9, 10), "y"))
-    res, info = run(ctx, probs, modes=("staged", "plain", "batched"))
+    if lanes == 1:
+        for d in (1, 2, 3):
+            f, g = dense_total(rng, d, 16), dense_total(rng, d, 16)
+            probs += [(f, g, "y"), (f, g, "x")]
+    res, info = run(ctx, probs, modes=("staged", "plain", "batched"), lanes=lanes)
     assert info["eval_mfma"] == len(probs)
     assert res == [oracle.res(f, g, v) for f, g, v in probs]
 
 
-def test_register_bounds_equal_horner(ctx, horner):
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_register_bounds_equal_horner(ctx, horner, lanes):
     """Degrees up to the 32 bound and x-degrees up to the 32-power limit give
     the same bits as Horner's rule; an x-degree past the limit keeps Horner."""
     rng = rng_for(731, 0)
@@ -111,28 +120,29 @@ def test_register_bounds_equal_horner(ctx, horner):
         probs.append((small_random(rng, dy, dx, 16), small_random(rng, dyg, max(dx - 3, 1), 16), "y"))
     past = (small_random(rng, 9, 32, 16), small_random(rng, 9, 5, 16), "y")  # 33 x-powers: Horner
     probs.append(past)
-    got, info = run(ctx, probs)
+    got, info = run(ctx, probs, lanes=lanes)
     assert info["eval_mfma"] == len(probs) - 1
-    ref, rinfo = run(horner, probs)
+    ref, rinfo = run(horner, probs, lanes=3 - lanes)
     assert rinfo["eval_mfma"] == 0
     assert got == ref
     modq(probs, got, 731)
 
 
-def test_multi_limb_joint_projections(ctx, horner):
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_multi_limb_joint_projections(ctx, horner, lanes):
     """160-bit coefficients (the limb-staged reduction writes the digit tiles
     of both projections)."""
     rng = rng_for(732, 0)
     f, g = dense_total(rng, 9, 160), dense_total(rng, 9, 160)
     probs = [(f, g, "y"), (f, g, "x")]
-    got, info = run(ctx, probs)
+    got, info = run(ctx, probs, lanes=lanes)
     assert info["eval_mfma"] == 2
     assert got == [oracle.res(f, g, v) for f, g, v in probs]
     big = [(dense_total(rng, 20, 100), dense_total(rng, 19, 100), v) for v in "y"]
     big.append((big[0][0], big[0][1], "x"))
-    got, info = run(ctx, big)
+    got, info = run(ctx, big, lanes=lanes)
     assert info["eval_mfma"] == 2
-    assert got == run(horner, big)[0]
+    assert got == run(horner, big, lanes=3 - lanes)[0]
     modq(big, got, 732)
 
 
