@@ -602,6 +602,9 @@ def main():
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(f, g, pairs // 2)
+    for _, jobs in inflight_sets[1:]:
+        for j in jobs:
+            j.close()
     for c, j in extra:
         j.close()
         c.close()

@@ -16,6 +16,7 @@ from __future__ import annotations
 import ctypes
 import os
 import threading
+import weakref
 
 import numpy as np
 
@@ -285,9 +286,12 @@ class Context:
             raise RSLError(rc, "rsl_ctx_create")
         self.h = h
         self.lock = threading.RLock()
+        self._owned = weakref.WeakSet()  # jobs and servers made on this context: closed before it
 
     def close(self):
         if getattr(self, "h", None):
+            for o in list(getattr(self, "_owned", ())):
+                o.close()  # their destruction synchronizes on the context's stream
             _lib.rsl_ctx_destroy(self.h)
             self.h = None
 
@@ -452,6 +456,7 @@ class Job:
 
     def __init__(self, ctx, problems, **opts):
         self.ctx = ctx
+        ctx._owned.add(self)
         n = len(problems)
         self.n = n
         self._polys = []

@@ -18,6 +18,7 @@ class Server:
 
     def __init__(self, ctx, budget_bytes=64 << 20, max_slots=64, max_queue=4096):
         self.ctx = ctx
+        ctx._owned.add(self)
         h = _vp()
         rc = _lib.rsl_server_create(ctx.h, budget_bytes, max_slots, max_queue, ctypes.byref(h))
         if rc:

@@ -269,3 +269,22 @@ def test_schur_evaluation_matches_remainder_sequence(ctx):
         assert ei.value.code == rsl.RSL_EINVAL
         js.close()
         jr.close()
+
+
+def test_context_close_closes_its_jobs_first():
+    """A context closed while jobs on it are still open closes them first (their
+    destruction waits on the context's stream), so nothing later touches the
+    destroyed context; closing them again is a no-op."""
+    import paper_1010_1386_amd as rsl
+    c = rsl.Context(device=0, workspace_bytes=64 << 20)
+    probs = mixed_batch(4, 3)
+    jobs = [c.job(probs), c.job(probs, eval_lanes=1)]
+    for j in jobs:
+        j.run("staged")
+    want = [oracle.res(f, g, v) for f, g, v in probs]
+    assert jobs[0].results() == jobs[1].results() == want
+    c.close()
+    assert all(j.h is None for j in jobs)
+    for j in jobs:
+        j.close()
+    del jobs
