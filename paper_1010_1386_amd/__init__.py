@@ -379,7 +379,8 @@ class Context:
         pr = UPoly(r)
         n = max(pr.deg, 1)
         limbs = pr.factor_bits // 32 + 2
-        outs = [_Result(max(pr.deg, 0), limbs) for _ in range(n)]
+        # r_i^i divides pp(r): the i-th factor has degree at most deg r / i
+        outs = [_Result(max(pr.deg, 0) // (i + 1), limbs) for i in range(n)]
         arr = (rsl_result * n)(*[o.c for o in outs])
         cnt = ctypes.c_int(0)
         with self.lock:

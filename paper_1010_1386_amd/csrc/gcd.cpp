@@ -373,6 +373,54 @@ int gcd_core(rsl_ctx* ctx, const UPoly& u, const UPoly& v, UPoly* gout, UPoly* u
   }
   if (u.deg < 0) return gcd_core(ctx, v, u, gout, vout, uout);
   const int nu = u.deg, nv = v.deg;  // nv = -1: v is zero
+  if (nv < 0) {
+    // gcd(u, 0) = pp(u), u / G = sign(lc u) content(u): a one-limb content (the
+    // usual case) is found and divided out on the host, with no modular work;
+    // a larger one takes the modular route below
+    BigU s;
+    for (int k = nu; k >= 0; --k) {
+      bool n;
+      const BigU c = abs_coeff(u, k, &n);
+      if (c.is_zero()) continue;
+      s = (s.d.size() == 1) ? BigU::gcd(s, BigU(c.mod_small(s.d[0]))) : BigU::gcd(s, c);
+      if (s.d.size() == 1 && s.d[0] == 1u) break;
+    }
+    if (s.d.size() == 1) {
+      const uint32_t sv = s.d[0];
+      auto put_signed = [](const BigU& mag, bool negative, uint32_t* out, int L) {
+        for (int l = 0; l < L; ++l) out[l] = l < static_cast<int>(mag.d.size()) ? mag.d[l] : 0u;
+        if (negative) {
+          uint64_t carry = 1;
+          for (int l = 0; l < L; ++l) {
+            const uint64_t t = static_cast<uint64_t>(~out[l]) + carry;
+            out[l] = static_cast<uint32_t>(t);
+            carry = t >> 32;
+          }
+        }
+      };
+      bool lneg;
+      (void)abs_coeff(u, nu, &lneg);
+      UPoly G;
+      G.deg = nu;
+      G.L = u.L + 1;  // |u_k| / s with the sign of u_k / lc(u) always fits
+      G.c.assign(static_cast<size_t>(nu + 1) * G.L, 0u);
+      for (int k = 0; k <= nu; ++k) {
+        bool n;
+        BigU c = abs_coeff(u, k, &n);
+        if (sv != 1u) c = c.div_small(sv);
+        put_signed(c, n != lneg, G.c.data() + static_cast<size_t>(k) * G.L, G.L);
+      }
+      UPoly A;
+      A.deg = 0;
+      A.L = 2;
+      A.c.assign(2, 0u);
+      put_signed(BigU(sv), lneg, A.c.data(), 2);
+      *gout = G;
+      *uout = A;
+      *vout = UPoly();
+      return RSL_OK;
+    }
+  }
   bool neg;
   const BigU lcu = abs_coeff(u, nu, &neg);
   const BigU lcv = (nv >= 0) ? abs_coeff(v, nv, &neg) : BigU();
