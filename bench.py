@@ -550,6 +550,20 @@ def main():
             trec = json.load(fh)
         if trec.get("lanes_per_pair") == tune.get("lanes_per_pair"):
             traffic = traffic_bytes(trec)
+    # VALU instructions per launch of the same kernel (committed SQ counter
+    # summary, same validity rule): lane operations issued per second against
+    # the chip's VALU issue peak
+    valu = None
+    ipath = os.path.join(ROOT, "profiles", "insts_eval_ures_cfg2_pair.json")
+    if mode != "batched" and os.path.exists(ipath):
+        from paper_1010_1386_amd.traffic import valu_issue
+        with open(ipath) as fh:
+            irec = json.load(fh)
+        if irec.get("lanes_per_pair") == tune.get("lanes_per_pair"):
+            vi = valu_issue(irec, launch_ms * 1e-3)
+            if vi is not None:
+                valu = {"lane_ops_per_launch": vi[0], "frac_of_issue_peak": vi[1],
+                        "mfma_insts_per_launch": irec["mfma_insts"]}
     roofline = {
         "bound": "alu",
         "kernel": kernel,
@@ -561,6 +575,7 @@ def main():
         "traffic_unit": "bytes per launch",
         "mulmods_per_launch": mulmods,
         "launch_ms": launch_ms,
+        "valu_issue": valu,
     }
     out = {
         "metric": METRIC,

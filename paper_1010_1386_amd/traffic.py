@@ -9,9 +9,17 @@ the kernels whose name starts with a prefix, the factors, and a hash of the
 kernel sources the counters belong to); ``traffic_bytes`` gives the scaled
 bytes per launch, or None when the sources have changed since.
 
+The same module summarizes instruction counters of a kernel (SQ_WAVES,
+SQ_INSTS_VALU, SQ_INSTS_SALU, SQ_INSTS_LDS in one run, SQ_INSTS_MFMA in
+another) into a record from which ``valu_issue`` gives the VALU lane
+operations per launch and their rate as a fraction of the chip's VALU issue
+peak (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz; a wave64 VALU instruction
+takes four cycles of one SIMD).
+
 Usage:
     python -m paper_1010_1386_amd.traffic FETCH_DIR WRITE_DIR COPYF_DIR COPYW_DIR \\
         KERNEL_PREFIX GRID COPY_BYTES OUT.json
+    python -m paper_1010_1386_amd.traffic --insts SQ_DIR MFMA_DIR KERNEL_PREFIX GRID OUT.json
 """
 
 from __future__ import annotations
@@ -35,7 +43,10 @@ def sources_sha256():
     return h.hexdigest()
 
 
-def _per_dispatch(directory, prefix, grid=None):
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9  # lane operations per second
+
+
+def _per_dispatch(directory, prefix, grid=None, counter=None):
     paths = glob.glob(os.path.join(directory, "*counter_collection.csv"))
     if not paths:
         raise FileNotFoundError(f"no counter_collection.csv under {directory}")
@@ -43,6 +54,8 @@ def _per_dispatch(directory, prefix, grid=None):
     with open(paths[0]) as fh:
         for row in csv.DictReader(fh):
             name = row["Kernel_Name"].replace("void ", "")
+            if counter is not None and row["Counter_Name"] != counter:
+                continue
             if name.startswith(prefix) and (grid is None or row["Grid_Size"] == str(grid)):
                 vals.append(float(row["Counter_Value"]))
     if not vals:
@@ -78,7 +91,33 @@ def traffic_bytes(record):
                      record["write_kib_per_dispatch"] * record["write_factor"])
 
 
+def summarize_insts(sq_dir, mfma_dir, prefix, grid):
+    rec = {"kernel_prefix": prefix, "grid_size": grid}
+    for key, counter in (("waves", "SQ_WAVES"), ("valu_insts", "SQ_INSTS_VALU"), ("salu_insts", "SQ_INSTS_SALU"),
+                         ("lds_insts", "SQ_INSTS_LDS")):
+        rec[key] = _per_dispatch(sq_dir, prefix, grid, counter)
+    rec["mfma_insts"] = _per_dispatch(mfma_dir, prefix, grid, "SQ_INSTS_MFMA")
+    rec["sources_sha256"] = sources_sha256()
+    return rec
+
+
+def valu_issue(record, launch_s):
+    """(VALU lane operations per launch, their rate / the VALU issue peak), or
+    None when the kernel sources have changed since the counters were taken."""
+    if record.get("sources_sha256") != sources_sha256():
+        return None
+    ops = 64.0 * record["valu_insts"]
+    return ops, ops / launch_s / VALU_LANE_OPS_PEAK
+
+
 def main(argv):
+    if len(argv) == 7 and argv[1] == "--insts":
+        rec = summarize_insts(argv[2], argv[3], argv[4], argv[5])
+        with open(argv[6], "w") as fh:
+            json.dump(rec, fh, indent=1)
+            fh.write("\n")
+        print(json.dumps(rec))
+        return 0
     if len(argv) != 9:
         print(__doc__, file=sys.stderr)
         return 2
