@@ -573,6 +573,9 @@ def main():
         "frac": mulmods / (launch_ms * 1e-3) / 1e12 / PEAK_TMULMOD,
         "traffic": traffic,
         "traffic_unit": "bytes per launch",
+        # the same bytes as a rate, against the 8 TB/s HBM peak
+        "traffic_gbs": None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9,
+        "traffic_frac_of_hbm_peak": None if traffic is None else traffic / (launch_ms * 1e-3) / 8e12,
         "mulmods_per_launch": mulmods,
         "launch_ms": launch_ms,
         "valu_issue": valu,
