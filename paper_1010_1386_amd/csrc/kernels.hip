@@ -33,9 +33,9 @@ __global__ __launch_bounds__(256) void k_reduce(const DevProblem* probs, const W
   extern __shared__ uint32_t lds[];
   const WorkItem w = items[blockIdx.x];
   if (w.sub)
-    stage_reduce_ml(probs[w.prob], T, w, lds);
+    stage_reduce_ml(probs[w.prob], T, w, lds, true);
   else
-    stage_reduce(probs[w.prob], T, w, true);
+    stage_reduce(probs[w.prob], T, w, true, true);
 }
 
 template <int V>

@@ -184,8 +184,11 @@ __device__ inline void write_digits(uint64_t* dig, int fr, int rtf, int rtg, int
     base[static_cast<size_t>(b) * rt * 512 + at] = static_cast<uint8_t>((r >> (7 * b)) & 127u);
 }
 
+// staged = true (the reduction launched as its own kernel): the residue tiles
+// are written only for problems whose staged evaluation reads them (Horner
+// forms); the persistent schedule evaluates by Horner and writes them all.
 __device__ inline void stage_reduce(const DevProblem& P, const DevTables& T, const WorkItem& w,
-                                    bool zero_status = false) {
+                                    bool zero_status = false, bool staged = false) {
   if (zero_status && w.slot == 0 && w.blk == 0)
     for (int i = threadIdx.x; i < 2 * P.np + 2; i += blockDim.x) P.status[i] = 0;
   const int t = w.blk * blockDim.x + threadIdx.x;
@@ -193,16 +196,17 @@ __device__ inline void stage_reduce(const DevProblem& P, const DevTables& T, con
   const PrimeConst pc = T.pc[P.pidx[w.slot]];
   int gp, ci, cj;
   const int in = tile_coord(P, t, &gp, &ci, &cj);
+  const bool own_tile = !(staged && P.evmf), partner_tile = !(staged && P.pdig);
   uint32_t v = 0;
   if (in >= 0) {
     const uint32_t p = pc.p;
     const uint32_t r = limbs_mod_p(P.coeff + static_cast<size_t>(in) * P.L_in, P.L_in, pc);
     v = mmul(r, pc.r3, p, pc.pinv);
-    if (w.slot < P.pshared) P.presid[static_cast<size_t>(w.slot) * P.pCS + partner_pos(P, t)] = v;
+    if (w.slot < P.pshared && partner_tile) P.presid[static_cast<size_t>(w.slot) * P.pCS + partner_pos(P, t)] = v;
     if (P.dig) write_digits(P.dig, P.dfr, P.dRTf, P.dRTg, w.slot, gp, ci, cj, r);
     if (P.pdig && w.slot < P.pshared) write_digits(P.pdig, P.pdfr, P.pdRTf, P.pdRTg, w.slot, gp, cj, ci, r);
   }
-  P.resid[static_cast<size_t>(w.slot) * P.CS + t] = v;
+  if (own_tile) P.resid[static_cast<size_t>(w.slot) * P.CS + t] = v;
 }
 
 // Multi-limb inputs: a block takes 64 transposed positions and 32 prime slots
@@ -216,7 +220,8 @@ constexpr int kReduceMlSlots = 32;
 constexpr int kReduceMlLimbs = 64;
 __host__ __device__ inline int reduce_ml_lds_words() { return kReduceMlLimbs * (kReduceMlCoeffs + 1); }
 
-__device__ inline void stage_reduce_ml(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
+__device__ inline void stage_reduce_ml(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds,
+                                       bool staged = false) {
   if (w.slot == 0 && w.blk == 0)
     for (int i = threadIdx.x; i < 2 * P.np + 2; i += blockDim.x) P.status[i] = 0;
   constexpr int kPer = kReduceMlSlots / 4;
@@ -280,13 +285,14 @@ __device__ inline void stage_reduce_ml(const DevProblem& P, const DevTables& T, 
   const int tp = (in >= 0 && w.slot < P.pshared) ? partner_pos(P, t) : 0;
   int gp, ci, cj;
   tile_coord(P, t, &gp, &ci, &cj);
+  const bool own_tile = !(staged && P.evmf), partner_tile = !(staged && P.pdig);
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
     const int sl = w.slot + q + 4 * r;
     if (sl < P.np) {
       const uint32_t v = (in >= 0) ? mmul(acc[r], r3[r], p[r], pinv[r]) : 0u;
-      P.resid[static_cast<size_t>(sl) * P.CS + t] = v;
-      if (in >= 0 && sl < P.pshared) P.presid[static_cast<size_t>(sl) * P.pCS + tp] = v;
+      if (own_tile) P.resid[static_cast<size_t>(sl) * P.CS + t] = v;
+      if (in >= 0 && sl < P.pshared && partner_tile) P.presid[static_cast<size_t>(sl) * P.pCS + tp] = v;
       if (in >= 0 && P.dig) write_digits(P.dig, P.dfr, P.dRTf, P.dRTg, sl, gp, ci, cj, acc[r]);
       if (in >= 0 && P.pdig && sl < P.pshared)
         write_digits(P.pdig, P.pdfr, P.pdRTf, P.pdRTg, sl, gp, cj, ci, acc[r]);
