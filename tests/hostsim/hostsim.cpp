@@ -152,9 +152,55 @@ int regs2_gen_run(const PrimeConst& pc, int m, int n, const uint32_t* A, const u
   return 0;
 }
 
+// The one-lane branch-free chain, and on its failure ures_formal on columns
+// from the original values (the matrix-core stage's one-lane path).
+template <int NMAX>
+int regs_gen_run(const PrimeConst& pc, int m, int n, const uint32_t* A, const uint32_t* B, uint32_t* out, int* bad,
+                 int* generic) {
+  constexpr int N = RegPoly<NMAX>::kN;
+  uint32_t X[N] = {}, Y[N] = {};
+  auto load = [&] {
+    for (int j = 0; j < N; ++j) {
+      X[j] = (j <= m) ? mmul(A[j] % pc.p, pc.r2, pc.p, pc.pinv) : 0u;
+      Y[j] = (j <= n) ? mmul(B[j] % pc.p, pc.r2, pc.p, pc.pinv) : 0u;
+    }
+  };
+  load();
+  bool ok = false, bd = false;
+  uint32_t r = ures_regs_generic<NMAX>(X, Y, m, n, pc, &ok, &bd);
+  if (!ok) {
+    load();
+    std::vector<uint32_t> ca(NMAX + 1, 0), cb(NMAX + 1, 0);
+    for (int j = 0; j <= NMAX; ++j) {
+      ca[j] = j < N ? X[j] : 0u;
+      cb[j] = j < N ? Y[j] : 0u;
+    }
+    bool b2 = false;
+    r = ures_formal(Column<1>{ca.data()}, Column<1>{cb.data()}, m, n, pc, &b2);
+  }
+  *out = redc(r, pc.p, pc.pinv);
+  *bad = bd;
+  *generic = ok;
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
+
+// The one-lane branch-free chain with its column restart.
+int hs_ures_regs_gen(int nmax, uint32_t p, int m, int n, const uint32_t* A, const uint32_t* B, uint32_t* out,
+                     int* bad, int* generic) {
+  PrimeConst pc = make_prime_const(p);
+  if (m > nmax || n > nmax) return -1;
+  switch (nmax) {
+    case 8: return regs_gen_run<8>(pc, m, n, A, B, out, bad, generic);
+    case 16: return regs_gen_run<16>(pc, m, n, A, B, out, bad, generic);
+    case 24: return regs_gen_run<24>(pc, m, n, A, B, out, bad, generic);
+    case 32: return regs_gen_run<32>(pc, m, n, A, B, out, bad, generic);
+    default: return -1;
+  }
+}
 
 // The branch-free generic chain of a lane pair with its column restart.
 int hs_ures_regs2_gen(int nmax, uint32_t p, int m, int n, const uint32_t* A, const uint32_t* B, uint32_t* out,

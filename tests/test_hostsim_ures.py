@@ -42,6 +42,8 @@ def hs():
                                  ctypes.POINTER(ctypes.c_int)]
     lib.hs_ures_regs2.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p, u32p, u32p,
                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.hs_ures_regs_gen.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p, u32p, u32p,
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     lib.hs_ures_regs2_gen.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p, u32p, u32p,
                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int)]
@@ -58,7 +60,11 @@ def ures(hs, p, A, B, K=1):
     b = (ctypes.c_uint32 * len(B))(*B)
     out = ctypes.c_uint32()
     bad = ctypes.c_int()
-    if isinstance(K, str) and K.startswith("gen"):
+    if isinstance(K, str) and K.startswith("lgen"):
+        nmax = int(K[4:])
+        gen = ctypes.c_int()
+        assert hs.hs_ures_regs_gen(nmax, p, m, n, a, b, ctypes.byref(out), ctypes.byref(bad), ctypes.byref(gen)) == 0
+    elif isinstance(K, str) and K.startswith("gen"):
         nmax = int(K[3:])
         agree, gen = ctypes.c_int(), ctypes.c_int()
         assert hs.hs_ures_regs2_gen(nmax, p, m, n, a, b, ctypes.byref(out), ctypes.byref(bad), ctypes.byref(agree),
@@ -81,7 +87,7 @@ def ures(hs, p, A, B, K=1):
     return out.value, bool(bad.value)
 
 
-KS = [1, 2, 4, 8, "regs16", "pair16", "gen16"]
+KS = [1, 2, 4, 8, "regs16", "pair16", "gen16", "lgen16"]
 
 
 def sylvester_det_mod(A, B, p):
@@ -120,7 +126,7 @@ def test_random_generic(hs, seed, K):
     assert got == sylvester_det_mod(A, B, p)
 
 
-@pytest.mark.parametrize("K", [1, 2, 4, 8, "regs32", "pair32", "gen32"])
+@pytest.mark.parametrize("K", [1, 2, 4, 8, "regs32", "pair32", "gen32", "lgen32"])
 @pytest.mark.parametrize("seed", range(6))
 def test_random_large_degree(hs, seed, K):
     """Degrees 13..40: every lane of a group runs several four-way fused updates."""
@@ -189,7 +195,7 @@ def test_eval_rows(hs, seed):
         assert out[j] == poly_eval_mod(row, x, p)
 
 
-@pytest.mark.parametrize("form", ["regs", "pair", "gen"])
+@pytest.mark.parametrize("form", ["regs", "pair", "gen", "lgen"])
 @pytest.mark.parametrize("nmax", [8, 16, 24, 32])
 @pytest.mark.parametrize("seed", range(40))
 def test_register_form_shapes(hs, form, nmax, seed):
