@@ -65,7 +65,10 @@ extern "C" {
 /* Environment read by rsl_ctx_create (test hooks): RSL_CRT_GARNER=1 makes the
  * CRT stage use Garner's mixed-radix digits for every coefficient instead of
  * the direct form (whose quotient estimate falls back to Garner only when it
- * cannot be decided); the results are identical. */
+ * cannot be decided); RSL_WIDE_VALU=1 runs the wide CRT's contraction on the
+ * vector ALUs instead of the int8 matrix cores; RSL_EVAL_HORNER=1 keeps the
+ * register-form evaluation on Horner's rule (vector ALUs) instead of the
+ * int8 matrix-core sums.  In every case the results are identical. */
 
 /* rsl_job_run only: OR into the mode to replay the run (status reset and every
  * launch of the schedule) as a HIP graph captured on the context stream on first
