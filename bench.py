@@ -332,6 +332,8 @@ def main():
                     help="large-coefficient benchmark instead: the random-curve sets of Table 3, res_y of all pairs")
     ap.add_argument("--inflight", type=int, default=4,
                     help="steps in flight: resident jobs of the pair on their own streams, run in turn")
+    ap.add_argument("--eval-lanes", type=int, default=0, choices=[0, 1, 2, 4],
+                    help="lanes per (prime, point) pair of the evaluation (0: the layout heuristics / autotuner)")
     ap.add_argument("--eval-schur", action="store_true",
                     help="univariate resultants by the Schur algorithm (comparison runs; use with --schedule staged)")
     ap.add_argument("--sqfree", action="store_true",
@@ -378,7 +380,7 @@ def main():
     ctx = rsl.Context(0, workspace_bytes=256 << 20)
     # contexts (stream + workspace) of the further steps in flight, made up front
     extra_ctx = [rsl.Context(0, workspace_bytes=256 << 20) for _ in range(max(a.inflight, 1) - 1)]
-    job = ctx.job(problems, eval_schur=a.eval_schur)
+    job = ctx.job(problems, eval_schur=a.eval_schur, eval_lanes=a.eval_lanes)
     info = job.info()
     # schedule: the autotuner times every candidate layout (staged launches /
     # one persistent launch x interpolation chunking) and keeps the fastest
@@ -417,7 +419,7 @@ def main():
             ctx.tune_save(tpath)
             for c in extra_ctx:
                 c.tune_load(tpath)
-                j = c.job(problems, eval_schur=a.eval_schur)
+                j = c.job(problems, eval_schur=a.eval_schur, eval_lanes=a.eval_lanes)
                 j.run(mode)
                 if j.results() != res:
                     print("bench: a further resident job differs from the first", file=sys.stderr)
@@ -429,7 +431,7 @@ def main():
     # counts when steps overlap), a lane pair gives the shorter single launch
     # (which the autotuner times); both sets are timed and the faster kept
     inflight_sets = [(info["eval_lanes"], all_jobs)]
-    if extra and mode == "staged" and info.get("eval_mfma", 0) > 0 and not a.eval_schur:
+    if extra and mode == "staged" and info.get("eval_mfma", 0) > 0 and not a.eval_schur and not a.eval_lanes:
         alt = 1 if info["eval_lanes"] == 2 else 2
         alt_jobs = []
         for c in [ctx] + extra_ctx:
