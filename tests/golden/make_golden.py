@@ -1,12 +1,20 @@
 """Write the stored expected resultants under tests/golden/ (calls only oracle/ and workloads/).
 
-Usage:  python tests/golden/make_golden.py [--configs 1 2 4 6] [--jobs N]
+Usage:  python tests/golden/make_golden.py [--configs 1 2 4 5 6 40 50] [--jobs N]
 
 For each workload the oracle's exact resultant is stored as its degree, a
 SHA-256 digest of the canonical decimal coefficient list (lowest power first,
 comma separated) and, for small results, the coefficients themselves.  The
 GPU parity tests recompute the digest from the library's output, so a match
 is bit-exact equality of every coefficient.
+
+Configs 4 and 5 (the batch of 512 and the serving stream) store the full
+oracle on every problem whose Sylvester matrix has order r = m_y + n_y <= 32.
+Configs 40 and 50 store modular checks of every problem of those workloads:
+for two 61-bit check primes q and seeded points t, the oracle's determinant
+of the Sylvester matrix specialised at t over Z_q, which must equal R(t) mod q
+(evaluation commutes with the determinant, Sec. 4.1; a wrong R passes one
+check with probability at most deg R / q).
 """
 
 from __future__ import annotations
@@ -50,6 +58,36 @@ def _job(args):
     return rec
 
 
+R_FULL = 32  # order of the Sylvester matrix up to which the full oracle runs
+
+
+def _order(f, g, var):
+    if var == "x":
+        f, g = oracle.bivar_transpose(f), oracle.bivar_transpose(g)
+    return len(oracle.bivar_trim(f)) - 1 + len(oracle.bivar_trim(g)) - 1
+
+
+def _modq_job(args):
+    name, f, g, var, seed = args
+    import random
+    rnd = random.Random(seed)
+    qs = oracle.next_check_primes(8)
+    checks = []
+    for j in range(2):
+        q = qs[(seed + j) % len(qs)]
+        t = rnd.randrange(q)
+        checks.append({"q": str(q), "t": str(t), "value": str(oracle.res_at_point_mod(f, g, t, q, var))})
+    return {"name": name, "var": var, "checks": checks}
+
+
+def modq_jobs_for(cfg):
+    if cfg == 40:
+        return [(f"cfg4_{k}_y", f, g, "y", k) for k, (f, g) in enumerate(workloads.config4())]
+    if cfg == 50:
+        return [(f"cfg5_{k}_{v}", f, g, v, k) for k, (f, g, v) in enumerate(workloads.config5())]
+    raise ValueError(cfg)
+
+
 def jobs_for(cfg):
     if cfg == 1:
         f, g = workloads.config1()
@@ -58,12 +96,14 @@ def jobs_for(cfg):
         f, g = workloads.config2()
         return [("cfg2_y", f, g, "y", False), ("cfg2_x", f, g, "x", False)]
     if cfg == 4:
-        out = []
-        for k, (f, g) in enumerate(workloads.config4()):
-            Ft, Gt = oracle.bivar_trim(f), oracle.bivar_trim(g)
-            if len(Ft) - 1 + len(Gt) - 1 <= 24:
-                out.append((f"cfg4_{k}_y", f, g, "y", False))
-        return out
+        out = [(f"cfg4_{k}_y", f, g, "y", False) for k, (f, g) in enumerate(workloads.config4())
+               if _order(f, g, "y") <= R_FULL]
+        # largest first, so that the pool's last jobs are short
+        return sorted(out, key=lambda j: -_order(j[1], j[2], j[3]))
+    if cfg == 5:
+        out = [(f"cfg5_{k}_{v}", f, g, v, False) for k, (f, g, v) in enumerate(workloads.config5())
+               if _order(f, g, v) <= R_FULL]
+        return sorted(out, key=lambda j: -_order(j[1], j[2], j[3]))
     if cfg == 6:  # large-coefficient random curves (paper Table 3), first pair of each set
         out = []
         for deg, k, sparse in ((9, 128, False), (9, 512, False), (9, 512, True), (15, 128, False)):
@@ -80,12 +120,15 @@ def main():
     ap.add_argument("--jobs", type=int, default=os.cpu_count())
     a = ap.parse_args()
     for cfg in a.configs:
-        jobs = jobs_for(cfg)
+        modq = cfg in (40, 50)
+        jobs = modq_jobs_for(cfg) if modq else jobs_for(cfg)
         with ProcessPoolExecutor(max_workers=min(a.jobs, len(jobs))) as ex:
-            recs = list(ex.map(_job, jobs))
+            recs = list(ex.map(_modq_job if modq else _job, jobs))
+        recs.sort(key=lambda r: [int(x) if x.isdigit() else x for x in r["name"].split("_")])
         path = os.path.join(HERE, f"cfg{cfg}.json")
         with open(path, "w") as fh:
-            json.dump({"config": cfg, "generator": "tests/golden/make_golden.py (oracle.res)",
+            json.dump({"config": cfg, "generator": "tests/golden/make_golden.py (oracle.res_at_point_mod)"
+                       if modq else "tests/golden/make_golden.py (oracle.res)",
                        "records": recs}, fh, indent=1)
         print(path, len(recs), "records", flush=True)
 

@@ -5,14 +5,17 @@
   (pinned against the oracle on small cases in test_abi_host.py), randomised
   checks modulo 61-bit primes (Schwartz-Zippel), an exact integer point check,
   and the planted variants (a bad point for every prime; R(a) = 0);
-* batch of 512: batched = plain (bit-identical), oracle on the small problems,
-  modulo-q checks on a sample of the rest.
+* batch of 512: persistent = staged = plain (bit-identical); the oracle's digest on
+  every problem whose Sylvester matrix has order at most 32 (192 of 512), and two
+  modulo-q checks of every one of the 512 against the oracle's specialised determinant
+  (stored by tests/golden/make_golden.py).
 """
 
 import random
 
 import pytest
 
+import _golden
 import oracle
 import workloads
 from oracle import peval, pmul, psub
@@ -82,15 +85,15 @@ def test_batch_of_512_batched_equals_plain(ctx):
     got_s = ctx.batch(probs, mode="staged")
     got_p = ctx.batch(probs, mode="plain")
     assert got_b == got_s == got_p
-    # full oracle on the smallest problems
-    small = sorted(range(len(pairs)), key=lambda k: sum(len(r) for r in pairs[k][0]) + sum(len(r) for r in pairs[k][1]))
-    for k in small[:12]:
-        f, g = pairs[k]
-        assert got_b[k] == oracle.res(f, g), k
-    # modulo-q checks on a sample of all sizes
-    for k in range(0, len(pairs), 16):
-        f, g = pairs[k]
-        _modq_checks(f, g, got_b[k], "y", 1, k)
+    full = _golden.load(4)
+    modq = _golden.load(40)
+    assert len(full) >= 160 and len(modq) == len(pairs)
+    for k in range(len(pairs)):
+        name = f"cfg4_{k}_y"
+        _golden.check_modq(got_b[k], modq[name])
+        if name in full:
+            _golden.check_full(got_b[k], full[name])
+        assert len(got_b[k]) - 1 <= oracle.degree_bound(*pairs[k])
 
 
 def test_resident_job_reruns_are_identical(ctx):

@@ -62,8 +62,9 @@ def test_alone_and_in_a_mix_are_identical(rsl):
     ctx = rsl.Context(device=0, workspace_bytes=256 << 20)
     srv = rsl.Server(ctx, budget_bytes=128 << 20, max_slots=32)
     reqs = requests(30, 1)
-    probe = reqs[7]
-    alone = srv.wait(srv.submit(*probe))
+    # every request alone first: each waits for its result before the next is submitted
+    alone = [srv.wait(srv.submit(*r)) for r in reqs]
+    assert srv.stats()["max_batch"] == 1
     results = {}
 
     def client(idx):
@@ -76,7 +77,7 @@ def test_alone_and_in_a_mix_are_identical(rsl):
         time.sleep(0.0005)  # staggered arrivals: later requests join running batches
     for t in threads:
         t.join()
-    assert results[7] == alone
+    assert [results[k] for k in range(len(reqs))] == alone
     srv.close()
     ctx.close()
 
