@@ -1,12 +1,18 @@
 """Throughput of the modular resultant path on one MI355X; prints one JSON line.
 
-A step computes res_y(f, g) and res_x(f, g) of the dense total-degree-24 pair
-with uniform signed 32-bit coefficients (the synthetic stand-in for the
-paper's curve pairs at that scale): reduction mod 57 primes, evaluation at
-577 points, 65.8K univariate resultants over Z_p, interpolation and CRT, for
-both variables.  Inputs are resident in device memory when the timed region
-starts (a resident job); results are decoded and checked bit-exactly against
-the stored oracle digests before timing.
+A step is one batch of 512 independent resultant problems (the batched
+workload: pairs f, g with total degrees uniform in 6..32, signed 8..64-bit
+coefficients, half dense and half with 30% of the coefficients zeroed;
+res_y of each), computed by one ``rsl_batch`` call from host limbs to host
+limbs: planning (degree and Hadamard bounds, primes, points), upload, the
+device pipeline (reduction mod p, evaluation and univariate resultants over
+Z_p, interpolation, CRT), download and decoding all sit inside the timed
+region.  ``value`` is bivariate resultants per second of the autotuned batched
+schedule; the plain path (one pipeline per problem) is timed the same way.
+The results of the timed calls are checked against the oracle's stored values
+(digests of every problem with Sylvester order <= 32, two checks modulo 61-bit
+primes of every problem).  Device-only rates of a resident job, the per-stage
+split and the dense degree-24 pair with steps in flight are reported beside.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -47,42 +53,53 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def _oracle_pairs(args):
-    """Oracle work unit: mod-p univariate resultants of f(x_i, y), g(x_i, y) (or in x)."""
+def host_cores():
+    """Cores this process may run on (the box's share), at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def _oracle_res(args):
+    """Oracle work unit: the exact resultant by Bareiss elimination over Z[x]."""
     import oracle
-    f, g, var, jobs = args
-    out = []
-    for q, x in jobs:
-        out.append(oracle.res_at_point_mod(f, g, x, q, var))
-    return len(out)
+    f, g, var = args
+    t0 = time.perf_counter()
+    R = oracle.res(f, g, var)
+    return len(R), time.perf_counter() - t0
 
 
-def cpu_baseline(f, g, pairs_per_resultant, seconds=12.0):
-    """Time the oracle's Gaussian elimination over Z_p on a bounded sample of the
-    step's (prime, point) pairs, over all host cores; scale to resultants/s."""
+def cpu_baseline(problems, r_max=24):
+    """The oracle (Bareiss over Z[x], oracle.res) on a bounded sample of the batch: every
+    problem whose Sylvester matrix has order at most r_max, over the host's cores."""
     from concurrent.futures import ProcessPoolExecutor
-    import oracle
-    cores = min(os.cpu_count() or 1, 16)
-    primes = oracle.next_check_primes(57, below=1 << 31)
-    chunk = [(primes[i % len(primes)], i % 577) for i in range(24)]
-    done = 0
+    sample = []
+    for f, g, var in problems:
+        ff = f if var == "y" else [list(c) for c in zip(*f)]
+        gg = g if var == "y" else [list(c) for c in zip(*g)]
+        r = (max((j for j, row in enumerate(ff) if any(row)), default=0)
+             + max((j for j, row in enumerate(gg) if any(row)), default=0))
+        if r <= r_max:
+            sample.append((f, g, var))
+    cores = host_cores()
     t0 = time.perf_counter()
     with ProcessPoolExecutor(max_workers=cores) as ex:
-        while time.perf_counter() - t0 < seconds:
-            futs = [ex.submit(_oracle_pairs, (f, g, "yx"[(done // 24 + c) % 2], chunk)) for c in range(cores)]
-            done += sum(fu.result() for fu in futs)
+        done = list(ex.map(_oracle_res, sample))
     dt = time.perf_counter() - t0
-    pairs_s = done / dt
+    cpu_s = sum(t for _, t in done)
     return {
-        "value": pairs_s / pairs_per_resultant,
+        "value": len(done) / dt,
         "unit": "bivariate resultants/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": (f"{done} mod-p univariate resultants (oracle Gaussian elimination over Z_p of the "
-                   f"48x48 Sylvester matrix at one point) of the same pair, res_y and res_x, in "
-                   f"{dt:.1f} s on {cores} cores of '{cpu_model()}'; scaled by the "
-                   f"{pairs_per_resultant} (prime, point) pairs one resultant needs"),
-        "pairs_per_s": pairs_s,
+        "sample": (f"the {len(done)} problems of the batch whose Sylvester matrix has order <= {r_max} "
+                   f"(of {len(problems)}), each by oracle.res (Bareiss over Z[x]), {dt:.1f} s wall on {cores} "
+                   f"processes of '{cpu_model()}' ({cpu_s:.1f} s of CPU, {cpu_s / max(len(done), 1):.2f} s "
+                   f"per problem); the larger problems of the batch (order up to 64) cost far more each, so "
+                   f"this rate bounds the oracle's rate on the whole batch from above"),
+        "cpu_seconds": cpu_s,
     }
 
 
@@ -315,65 +332,13 @@ def sqfree_bench(steps, with_cpu_baseline=True):
     return {"workload": "square-free part of resultants (modular gcd of R and R')", "steps": steps, "cases": rows}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=40)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--plain-steps", type=int, default=100)
-    ap.add_argument("--schedule", choices=["auto", "staged", "batched"], default="auto",
-                    help="auto: autotune the job first; otherwise that schedule with the default layout")
-    ap.add_argument("--serve", type=int, default=0, metavar="N",
-                    help="serving benchmark instead: N Poisson-arriving requests of the serving workload")
-    ap.add_argument("--batch512", action="store_true",
-                    help="batch benchmark instead: 512 pairs (res_y), autotuned schedule vs one pipeline per problem")
-    ap.add_argument("--table3", action="store_true",
-                    help="large-coefficient benchmark instead: the random-curve sets of Table 3, res_y of all pairs")
-    ap.add_argument("--inflight", type=int, default=4,
-                    help="steps in flight: resident jobs of the pair on their own streams, run in turn")
-    ap.add_argument("--eval-lanes", type=int, default=0, choices=[0, 1, 2, 4],
-                    help="lanes per (prime, point) pair of the evaluation (0: the layout heuristics / autotuner)")
-    ap.add_argument("--eval-schur", action="store_true",
-                    help="univariate resultants by the Schur algorithm (comparison runs; use with --schedule staged)")
-    ap.add_argument("--sqfree", action="store_true",
-                    help="square-free part of resultants by the modular gcd instead")
-    ap.add_argument("--table3-only", default="", metavar="DEG:K[,DEG:K]",
-                    help="with --table3: only these sets (e.g. 15:2048)")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
-                    help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
-    a = ap.parse_args()
-    if a.copy_calibration:
-        import torch
-        src = torch.empty(a.copy_calibration, dtype=torch.uint8, device="cuda:0").fill_(1)
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes": a.copy_calibration, "copies": 5}))
-        return
-    if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no multi-GPU path",
-              file=sys.stderr)
-        sys.exit(2)
-
+def pair_bench(a):
+    """The dense total-degree-24 pair with uniform signed 32-bit coefficients: a step is
+    res_y and res_x of the pair (57 primes x 577 points each) as one resident job, inputs
+    on the device; several steps in flight on their own contexts.  Device-only rates."""
     import torch
     import paper_1010_1386_amd as rsl
     import workloads
-
-    if a.serve:
-        print(json.dumps(serve_bench(a.serve)))
-        return
-    if a.batch512:
-        print(json.dumps(batch_bench(a.steps, a.warmup)))
-        return
-    if a.sqfree:
-        print(json.dumps(sqfree_bench(a.steps, not a.no_cpu_baseline)))
-        return
-    if a.table3:
-        only = [x for x in a.table3_only.split(",") if x]
-        print(json.dumps(table3_bench(a.steps, a.warmup, only)))
-        return
 
     f, g = workloads.config2()
     problems = [(f, g, "y"), (f, g, "x")]
@@ -385,7 +350,7 @@ def main():
     # schedule: the autotuner times every candidate layout (staged launches /
     # one persistent launch x interpolation chunking) and keeps the fastest
     if a.schedule == "auto":
-        tune = job.tune(reps=max(3, a.warmup // 4))
+        tune = job.tune(reps=max(3, a.pair_warmup // 4))
     else:
         tune = {"mode": a.schedule, "chunk_target": 4096, "grid_mult": 1, "lanes_per_pair": None,
                 "candidates": 0, "ms": None, "ms_worst": None}
@@ -473,8 +438,8 @@ def main():
         ctx.profile_enable(False)
         return {k: v / max(runs, 1) for k, v in stages.items()}
 
-    dt1 = timed(mode, a.steps, a.warmup, graph=use_graph)
-    serial_value = 2 * a.steps / dt1
+    dt1 = timed(mode, a.pair_steps, a.pair_warmup, graph=use_graph)
+    serial_value = 2 * a.pair_steps / dt1
 
 
     def timed_inflight(jobs, steps, warmup, graph):
@@ -497,23 +462,23 @@ def main():
                     print("bench: graph replay differs from the eager run", file=sys.stderr)
                     sys.exit(1)
             for graph in (True, False):
-                t = timed_inflight(jobs, a.steps, a.warmup, graph)
+                t = timed_inflight(jobs, a.pair_steps, a.pair_warmup, graph)
                 if best is None or t < best[0]:
                     best = (t, graph, lanes)
         dt, use_graph, inflight_lanes = best
     else:
         dt = dt1
-    ms_step = dt / a.steps * 1e3
-    value = 2 * a.steps / dt
-    stages = stage_profile(mode, a.steps)
+    ms_step = dt / a.pair_steps * 1e3
+    value = 2 * a.pair_steps / dt
+    stages = stage_profile(mode, a.pair_steps)
     other = "staged" if mode == "batched" else "batched"
     try:
-        dto = timed(other, a.plain_steps, max(1, a.warmup // 4))
+        dto = timed(other, a.plain_steps, max(1, a.pair_warmup // 4))
     except rsl.RSLError:  # a layout the persistent schedule does not run (Schur evaluation)
         dto = None
-    dtp = timed("plain", a.plain_steps, max(1, a.warmup // 4))
+    dtp = timed("plain", a.plain_steps, max(1, a.pair_warmup // 4))
     plain_value = 2 * a.plain_steps / dtp
-    schedules = {mode: dt1 / a.steps * 1e3, other: None if dto is None else dto / a.plain_steps * 1e3,
+    schedules = {mode: dt1 / a.pair_steps * 1e3, other: None if dto is None else dto / a.plain_steps * 1e3,
                  "plain": dtp / a.plain_steps * 1e3}
     if extra:
         schedules[f"{mode}, {len(all_jobs)} steps in flight"] = ms_step
@@ -587,8 +552,8 @@ def main():
         "value": value,
         "unit": "bivariate resultants/s",
         "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
+        "steps": a.pair_steps,
+        "warmup": a.pair_warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -609,7 +574,7 @@ def main():
         "modp_pairs": counts.get("pairs"), "bad_pairs": counts.get("bad_pairs"),
         "bad_primes": counts.get("bad_primes"),
         "serial_value": serial_value,
-        "serial_ms_per_step": dt1 / a.steps * 1e3,
+        "serial_ms_per_step": dt1 / a.pair_steps * 1e3,
         "plain_value": plain_value,
         "batched_vs_plain": value / plain_value,
         "serial_batched_vs_plain": serial_value / plain_value,
@@ -620,8 +585,6 @@ def main():
         "dominant_stage": dominant,
         "roofline": roofline,
     }
-    if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(f, g, pairs // 2)
     for _, jobs in inflight_sets[1:]:
         for j in jobs:
             j.close()
@@ -630,6 +593,282 @@ def main():
         c.close()
     job.close()
     ctx.close()
+    return out
+
+
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+MFMA_INT8_PEAK_TOPS = 5000.0  # dense int8 matrix-core multiply-adds x 2, TOP/s (MI355X)
+
+
+def _load_golden(cfg):
+    path = os.path.join(GOLDEN, f"cfg{cfg}.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        return {r["name"]: r for r in json.load(fh)["records"]}
+
+
+def _eval_mod(R, t, q):
+    """R(t) mod q by Horner's rule (checks a result against a stored modular value)."""
+    acc = 0
+    for c in reversed(R):
+        acc = (acc * t + c) % q
+    return acc
+
+
+def verify_batch(results, prefix="cfg4", full_cfg=4, modq_cfg=40, var="y"):
+    """Compare results with the oracle's stored values: the digest of every problem the
+    full oracle covers, and R(t) mod q for the two stored checks of every problem."""
+    full, modq = _load_golden(full_cfg), _load_golden(modq_cfg)
+    if not modq:
+        return None
+    n_full = n_modq = 0
+    for k, R in enumerate(results):
+        name = f"{prefix}_{k}_{var}"
+        rec = modq.get(name)
+        if rec is None:
+            return False
+        for c in rec["checks"]:
+            if _eval_mod(R, int(c["t"]), int(c["q"])) != int(c["value"]):
+                return False
+            n_modq += 1
+        if name in full:
+            if digest(R) != full[name]["sha256"]:
+                return False
+            n_full += 1
+    return {"full_oracle_digests": n_full, "modq_checks": n_modq}
+
+
+def batch_headline(a):
+    import numpy as np
+    import torch
+    import paper_1010_1386_amd as rsl
+    import workloads
+
+    pairs = workloads.config4()
+    probs = [(f, g, "y") for f, g in pairs]
+    pb = rsl.PreparedBatch(probs)  # the caller's data: limbs in, sized result buffers out
+    ctx = rsl.Context(0, workspace_bytes=1 << 30)
+
+    # autotune on a resident job of the batch: the winner is cached for its shape
+    # bucket and used by every RSL_AUTO call of this context
+    job = ctx.job(probs)
+    tune = job.tune(reps=2)
+    info = job.info()
+
+    def counters_sum(acc, c):
+        for k in ("ms_total", "ms_build", "ms_bind", "ms_transfer", "ms_device", "ms_decode"):
+            acc[k] = acc.get(k, 0.0) + c[k]
+
+    def timed_batch(mode, steps, warmup):
+        for _ in range(warmup):
+            pb.run(ctx, mode)
+        torch.cuda.synchronize()
+        acc = {}
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            pb.run(ctx, mode)
+            counters_sum(acc, ctx.counters())
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return dt, {k: v / steps for k, v in acc.items()}
+
+    steps = max(1, a.steps)
+    dt, split = timed_batch("auto", steps, a.warmup)
+    counts = ctx.counters()
+    res = pb.results()  # the last timed call's output
+    verified = verify_batch(res)
+    if verified is False:
+        print("bench: a batch result differs from the oracle's stored values", file=sys.stderr)
+        sys.exit(1)
+    value = len(probs) * steps / dt
+
+    plain_steps = max(1, min(steps, 5))
+    dtp, split_p = timed_batch("plain", plain_steps, 1)
+    if pb.results() != res:
+        print("bench: plain and batched results differ", file=sys.stderr)
+        sys.exit(1)
+    plain_value = len(probs) * plain_steps / dtp
+
+    # device-only: the same batch resident in device memory
+    def timed_job(mode, n):
+        job.run(mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            job.run(mode)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    job.run("auto")
+    if job.results() != res:
+        print("bench: resident job results differ from the batch call", file=sys.stderr)
+        sys.exit(1)
+    dev_ms = timed_job("auto", steps) * 1e3
+    dev_plain_ms = timed_job("plain", plain_steps) * 1e3
+    try:
+        dev_persist_ms = timed_job("batched", 2) * 1e3
+    except rsl.RSLError:
+        dev_persist_ms = None
+
+    # per-stage device time from HIP events on the context's stream (each stage
+    # is one launch, the evaluation one launch per layout variant)
+    ctx.profile_enable(True)
+    for _ in range(2):  # the first pass makes the event sets, the second is measured
+        ctx.profile_take()
+        for _ in range(steps):
+            job.run(tune["mode"])
+    stages, runs = ctx.profile_take()
+    ctx.profile_enable(False)
+    stages = {k: v / max(runs, 1) for k, v in stages.items()}
+    eval_ms = stages["eval_ures"]
+    job.close()
+    ctx.close()
+
+    nps = np.array([i.n_primes for i in pb.infos])
+    Ds = np.array([i.D for i in pb.infos])
+
+    def hist(v):
+        return {"min": int(v.min()), "p50": int(np.percentile(v, 50)), "p90": int(np.percentile(v, 90)),
+                "max": int(v.max()), "sum": int(v.sum())}
+
+    valu_mm, mfma_mm, macs = info["mulmods_valu"], info["mulmods_sums_mfma"], info["mfma_int8_macs"]
+    t_eval = eval_ms * 1e-3
+    roofline = {
+        "bound": "alu",
+        "kernel": "eval_ures (the evaluation stage: one launch per layout variant)",
+        "achieved": valu_mm / t_eval / 1e12,
+        "peak": PEAK_TMULMOD,
+        "unit": "Tmulmod/s",
+        "frac": valu_mm / t_eval / 1e12 / PEAK_TMULMOD,
+        "traffic": None,
+        "per_launch": {"valu_mulmods": valu_mm, "launch_ms": eval_ms,
+                       "note": "VALU part: remainder-sequence products m_y n_y per (prime, point) pair plus the "
+                               "Horner sums of problems whose sums are not on the matrix cores"},
+        "mfma": {"achieved": 2.0 * macs / t_eval / 1e12, "peak": MFMA_INT8_PEAK_TOPS, "unit": "TOP/s int8",
+                 "frac": 2.0 * macs / t_eval / 1e12 / MFMA_INT8_PEAK_TOPS, "int8_macs_per_launch": macs,
+                 "sums_mulmods": mfma_mm,
+                 "note": "evaluation sums on the matrix cores: 25 int8 digit products per residue product, "
+                         "padded 16x16x32 tiles"},
+        "all_products_frac": info["mulmods"] / t_eval / 1e12 / PEAK_TMULMOD,
+    }
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "bivariate resultants/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "batch of 512 independent pairs: total degrees U{6..32}, signed U{8..64}-bit "
+                               "coefficients, pairs 0-255 dense, 256-511 with 30% of the coefficients zeroed; "
+                               "res_y of each, one rsl_batch call per step, host limbs to host limbs",
+                   "problems_per_step": len(probs), "schedule": tune["mode"], "tune": tune,
+                   "n_primes": hist(nps), "degree_bound_D": hist(Ds)},
+        "verified": verified,
+        "host_to_host": True,
+        "step_split_ms": split,
+        "plain_value": plain_value,
+        "plain_ms_per_step": dtp / plain_steps * 1e3,
+        "plain_step_split_ms": split_p,
+        "batched_vs_plain": value / plain_value,
+        "device_only": {"resultants_per_s": len(probs) / (dev_ms * 1e-3), "ms_per_batch": dev_ms,
+                        "plain_ms_per_batch": dev_plain_ms, "persistent_ms_per_batch": dev_persist_ms,
+                        "batched_vs_plain": dev_plain_ms / dev_ms},
+        "modp_univariate_resultants_per_s": info["pairs"] / t_eval,
+        "modp_pairs": counts["pairs"], "bad_pairs": counts["bad_pairs"], "bad_primes": counts["bad_primes"],
+        "stage_ms_per_step": stages,
+        "dominant_stage": max(stages, key=stages.get),
+        "roofline": roofline,
+    }
+    if not a.no_pair:
+        pa = argparse.Namespace(**vars(a))
+        pa.no_cpu_baseline = True
+        pr = pair_bench(pa)
+        out["pair"] = {k: pr[k] for k in ("value", "ms_per_step", "serial_value", "plain_value", "config",
+                                          "verified_bit_exact", "roofline")}
+        out["pair"]["unit"] = "bivariate resultants/s, device only (inputs resident), steps in flight"
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(probs)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed batches (each is one rsl_batch of 512 problems)")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--pair", action="store_true",
+                    help="only the dense degree-24 pair benchmark (device-only, steps in flight)")
+    ap.add_argument("--no-pair", action="store_true", help="leave the pair figures out of the default line")
+    ap.add_argument("--pair-steps", type=int, default=400)
+    ap.add_argument("--pair-warmup", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=100, help="pair benchmark: steps of the comparison schedules")
+    ap.add_argument("--schedule", choices=["auto", "staged", "batched"], default="auto",
+                    help="auto: autotune the job first; otherwise that schedule with the default layout")
+    ap.add_argument("--serve", type=int, default=0, metavar="N",
+                    help="serving benchmark instead: N Poisson-arriving requests of the serving workload")
+    ap.add_argument("--batch512", action="store_true",
+                    help="batch benchmark instead: 512 pairs (res_y), autotuned schedule vs one pipeline per problem")
+    ap.add_argument("--table3", action="store_true",
+                    help="large-coefficient benchmark instead: the random-curve sets of Table 3, res_y of all pairs")
+    ap.add_argument("--inflight", type=int, default=4,
+                    help="steps in flight: resident jobs of the pair on their own streams, run in turn")
+    ap.add_argument("--eval-lanes", type=int, default=0, choices=[0, 1, 2, 4],
+                    help="lanes per (prime, point) pair of the evaluation (0: the layout heuristics / autotuner)")
+    ap.add_argument("--eval-schur", action="store_true",
+                    help="univariate resultants by the Schur algorithm (comparison runs; use with --schedule staged)")
+    ap.add_argument("--sqfree", action="store_true",
+                    help="square-free part of resultants by the modular gcd instead")
+    ap.add_argument("--table3-only", default="", metavar="DEG:K[,DEG:K]",
+                    help="with --table3: only these sets (e.g. 15:2048)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
+    a = ap.parse_args()
+    if a.copy_calibration:
+        import torch
+        src = torch.empty(a.copy_calibration, dtype=torch.uint8, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": a.copy_calibration, "copies": 5}))
+        return
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1010_1386_amd as rsl
+    import workloads
+
+    if a.serve:
+        print(json.dumps(serve_bench(a.serve)))
+        return
+    if a.batch512:
+        print(json.dumps(batch_bench(a.steps, a.warmup)))
+        return
+    if a.sqfree:
+        print(json.dumps(sqfree_bench(a.steps, not a.no_cpu_baseline)))
+        return
+    if a.table3:
+        only = [x for x in a.table3_only.split(",") if x]
+        print(json.dumps(table3_bench(a.steps, a.warmup, only)))
+        return
+
+    if a.pair:
+        print(json.dumps(pair_bench(a)))
+        return
+    out = batch_headline(a)
     print(json.dumps(out))
 
 

@@ -153,6 +153,10 @@ typedef struct {
   int64_t slow_primes;  /* primes interpolated on a non-consecutive point set */
   double ms_device;     /* device time of the last call (HIP events) */
   double ms_total;      /* host wall time of the last call */
+  double ms_build;      /* of ms_total: planning and job layout (host) */
+  double ms_bind;       /* of ms_total: writing the upload image (host) */
+  double ms_transfer;   /* of ms_total: copies and launch overhead outside the device time */
+  double ms_decode;     /* of ms_total: results into the callers' buffers (host) */
 } rsl_counters;
 
 typedef struct rsl_ctx rsl_ctx;
@@ -286,6 +290,11 @@ typedef struct {
   int32_t eval_lanes;     /* most lanes per (prime, point) pair used by any problem */
   int32_t eval_mfma;      /* problems whose evaluation sums run on the matrix cores (register form,
                              two lanes per pair, x-degrees below 32) */
+  int64_t mulmods_sums_mfma;  /* of mulmods: evaluation sums taken on the matrix cores */
+  int64_t mulmods_valu;       /* of mulmods: the rest (remainder sequences, Horner sums) on the vector ALUs */
+  int64_t mfma_int8_macs;     /* int8 multiply-adds the matrix cores issue per run for those sums
+                                 (padded tiles, 25 digit products per residue product) */
+  int64_t interp_mulmods;     /* interpolation products per run: N_p (D+1)(D+2) over problems */
 } rsl_job_info;
 
 /* Plan n problems and upload their inputs (status per problem in `status`, may be NULL). */

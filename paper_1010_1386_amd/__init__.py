@@ -69,7 +69,8 @@ class rsl_opts(ctypes.Structure):
 class rsl_counters(ctypes.Structure):
     _fields_ = [("problems", ctypes.c_int64), ("pairs", ctypes.c_int64), ("bad_pairs", ctypes.c_int64),
                 ("bad_primes", ctypes.c_int64), ("slow_primes", ctypes.c_int64),
-                ("ms_device", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("ms_device", ctypes.c_double), ("ms_total", ctypes.c_double), ("ms_build", ctypes.c_double),
+                ("ms_bind", ctypes.c_double), ("ms_transfer", ctypes.c_double), ("ms_decode", ctypes.c_double)]
 
 
 class rsl_stats(ctypes.Structure):
@@ -85,7 +86,8 @@ class rsl_job_info(ctypes.Structure):
                 ("mulmods", ctypes.c_int64), ("device_bytes", ctypes.c_size_t), ("upload_bytes", ctypes.c_size_t),
                 ("download_bytes", ctypes.c_size_t), ("layout_mode", ctypes.c_int32),
                 ("chunk_target", ctypes.c_int32), ("grid_mult", ctypes.c_int32), ("eval_lanes", ctypes.c_int32),
-                ("eval_mfma", ctypes.c_int32)]
+                ("eval_mfma", ctypes.c_int32), ("mulmods_sums_mfma", ctypes.c_int64), ("mulmods_valu", ctypes.c_int64),
+                ("mfma_int8_macs", ctypes.c_int64), ("interp_mulmods", ctypes.c_int64)]
 
 
 class rsl_upoly(ctypes.Structure):
@@ -394,33 +396,9 @@ class Context:
 
     def batch(self, problems, mode="batched"):
         """problems: list of (f, g, var); returns a list of results (lists of ints)."""
-        n = len(problems)
-        polys, outs = [], []
-        fa = (rsl_poly * max(n, 1))()
-        ga = (rsl_poly * max(n, 1))()
-        va = (ctypes.c_int * max(n, 1))()
-        ra = (rsl_result * max(n, 1))()
-        st = (ctypes.c_int * max(n, 1))()
-        for k, (f, g, var) in enumerate(problems):
-            pf, pg = _as_poly(f), _as_poly(g)
-            v = _var_code(var)
-            info = rsl_info()
-            self._check(_lib.rsl_query(ctypes.byref(pf.c), ctypes.byref(pg.c), v, ctypes.byref(info)),
-                        "rsl_query")
-            r = _Result(max(info.D, 0), info.out_limbs)
-            polys.append((pf, pg))
-            outs.append(r)
-            fa[k], ga[k], va[k], ra[k] = pf.c, pg.c, v, r.c
-        code = _modecode(mode)
-        with self.lock:
-            rc = _lib.rsl_batch(self.h, n, fa, ga, va, ra, st, code)
-        self._check(rc, "rsl_batch")
-        res = []
-        for k in range(n):
-            outs[k].c = ra[k]
-            res.append(outs[k].value())
-        return res
-
+        pb = PreparedBatch(problems)
+        pb.run(self, mode)
+        return pb.results()
 
     def profile_enable(self, on=True):
         self._check(_lib.rsl_profile_enable(self.h, 1 if on else 0), "rsl_profile_enable")
@@ -442,6 +420,52 @@ class Context:
 
     def job(self, problems, **opts):
         return Job(self, problems, **opts)
+
+
+class PreparedBatch:
+    """The C-ABI arguments of one batch, packed once: input limbs, variables and result
+    buffers sized by rsl_query.  run() is then a single rsl_batch call (host limbs in,
+    host limbs out: planning, upload, device pipeline, download and decoding into the
+    result buffers all happen inside it); results() converts the limbs to Python ints."""
+
+    def __init__(self, problems):
+        n = len(problems)
+        self.n = n
+        self._polys, self._outs = [], []
+        self.fa = (rsl_poly * max(n, 1))()
+        self.ga = (rsl_poly * max(n, 1))()
+        self.va = (ctypes.c_int * max(n, 1))()
+        self.ra = (rsl_result * max(n, 1))()
+        self.st = (ctypes.c_int * max(n, 1))()
+        self.infos = []
+        for k, (f, g, var) in enumerate(problems):
+            pf, pg = _as_poly(f), _as_poly(g)
+            v = _var_code(var)
+            info = rsl_info()
+            rc = _lib.rsl_query(ctypes.byref(pf.c), ctypes.byref(pg.c), v, ctypes.byref(info))
+            if rc:
+                raise RSLError(rc, f"rsl_query (problem {k})")
+            r = _Result(max(info.D, 0), info.out_limbs)
+            self._polys.append((pf, pg))
+            self._outs.append(r)
+            self.infos.append(info)
+            self.fa[k], self.ga[k], self.va[k], self.ra[k] = pf.c, pg.c, v, r.c
+
+    def run(self, ctx, mode="auto"):
+        code = _modecode(mode)
+        with ctx.lock:
+            rc = _lib.rsl_batch(ctx.h, self.n, self.fa, self.ga, self.va, self.ra, self.st, code)
+        ctx._check(rc, "rsl_batch")
+
+    def statuses(self):
+        return [self.st[k] for k in range(self.n)]
+
+    def results(self):
+        res = []
+        for k in range(self.n):
+            self._outs[k].c = self.ra[k]
+            res.append(self._outs[k].value())
+        return res
 
 
 def _modecode(mode):

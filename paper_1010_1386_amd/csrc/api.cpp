@@ -209,24 +209,25 @@ int decode_result(const Plan& P, const uint32_t* limbs, rsl_result* out) {
 // Run a job laid out in the context workspace, synchronously.
 static int run_in_workspace(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var,
                             const rsl_opts* opts, rsl_result* out, int* status, int mode, rsl_counters* cnt) {
+  const double t0 = now_ms();
   Job J;
   std::string err;
-  int rc = job_build(ctx, n, f, g, var, opts, &J, &err);
-  if (rc == RSL_EDEVICE) return rc;
+  job_plan(n, f, g, var, opts, &J, &err);
+  // RSL_AUTO: the schedule the autotuner chose for this shape bucket, else the
+  // staged default; the job is laid out once, with the chosen parameters
+  const TuneConfig* tc = nullptr;
   if (mode == RSL_AUTO) {
-    // the schedule the autotuner chose for this shape, else the staged default
     mode = RSL_STAGED;
     auto it = ctx->tune_cache.find(tune_key(J));
     if (it != ctx->tune_cache.end()) {
       mode = it->second.cfg.mode;
-      if (it->second.cfg.chunk_target != J.tune.chunk_target) {
-        J = Job();
-        err.clear();
-        rc = job_build(ctx, n, f, g, var, opts, &J, &err, &it->second.cfg);
-        if (rc == RSL_EDEVICE) return rc;
-      }
+      tc = &it->second.cfg;
     }
   }
+  int rc = job_build(ctx, n, f, g, var, opts, &J, &err, tc, true);
+  if (rc == RSL_EDEVICE) return rc;
+  const double t1 = now_ms();
+  cnt->ms_build += t1 - t0;
   if (!J.live.empty()) {
     if (J.total > ctx->ws_bytes) {
       const std::string m = "workspace of " + std::to_string(ctx->ws_bytes) + " bytes < footprint " +
@@ -236,7 +237,12 @@ static int run_in_workspace(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_po
         for (int k = 0; k < n; ++k) status[k] = J.pstatus[k];
       return fail(ctx, RSL_ENOMEM, m);
     }
-    job_bind(&J, ctx->ws);
+    if ((rc = ensure_staging(ctx, J.up_bytes, J.down_bytes))) return rc;
+    // the upload image is written straight into pinned staging; only the
+    // persistent launch needs its queue image
+    job_bind(&J, ctx->ws, ctx->h_up, mode == RSL_BATCHED);
+    const double t2 = now_ms();
+    cnt->ms_bind += t2 - t1;
     hipStream_t st = ctx->stream;
     if ((rc = job_upload(ctx, &J, st)) || (rc = hip_check(ctx, hipEventRecord(ctx->e0, st), "event")) ||
         (rc = job_launch(ctx, &J, mode, st, false)) || (rc = hip_check(ctx, hipEventRecord(ctx->e1, st), "event")) ||
@@ -246,8 +252,11 @@ static int run_in_workspace(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_po
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ctx->e0, ctx->e1);
     cnt->ms_device += ms;
+    cnt->ms_transfer += now_ms() - t2 - ms;
   }
+  const double t3 = now_ms();
   rc = job_decode(ctx, J, ctx->h_down, out, status, cnt);
+  cnt->ms_decode += now_ms() - t3;
   if (rc && !err.empty() && ctx->err.empty()) ctx->err = err;
   if (rc && rc != RSL_ERANGE && rc != RSL_EPRIMES && !err.empty()) ctx->err = err;
   return rc;

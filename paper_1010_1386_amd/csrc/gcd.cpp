@@ -186,15 +186,15 @@ int crt_setup(rsl_ctx* ctx, Dev* D, const std::vector<int>& pidx, CrtDev* C) {
   plan_crt(&C->P);
   const Plan& P = C->P;
   int rc;
-  if ((rc = upload_vec(ctx, D, P.pidx, &C->pidx)) || (rc = upload_vec(ctx, D, P.Hm, &C->Hm)) ||
-      (rc = upload_vec(ctx, D, P.NH, &C->NH)) || (rc = upload_vec(ctx, D, P.Mi, &C->Mi)) ||
-      (rc = upload_vec(ctx, D, P.wdir, &C->wdir)) || (rc = upload_vec(ctx, D, P.rinv, &C->rinv)) ||
-      (rc = upload_vec(ctx, D, P.negM, &C->negM)))
+  if ((rc = upload_vec(ctx, D, P.pidx, &C->pidx)) || (rc = upload_vec(ctx, D, P.crt->Hm, &C->Hm)) ||
+      (rc = upload_vec(ctx, D, P.crt->NH, &C->NH)) || (rc = upload_vec(ctx, D, P.crt->Mi, &C->Mi)) ||
+      (rc = upload_vec(ctx, D, P.crt->wdir, &C->wdir)) || (rc = upload_vec(ctx, D, P.crt->rinv, &C->rinv)) ||
+      (rc = upload_vec(ctx, D, P.crt->negM, &C->negM)))
     return rc;
-  if (P.wide && ((rc = upload_vec(ctx, D, P.Mw, &C->Mw)) || (rc = upload_vec(ctx, D, P.NHM, &C->NHM)))) return rc;
+  if (P.wide && ((rc = upload_vec(ctx, D, P.crt->Mw, &C->Mw)) || (rc = upload_vec(ctx, D, P.crt->NHM, &C->NHM)))) return rc;
   if (!P.canonical && !P.wide &&
-      ((rc = upload_vec(ctx, D, P.Tg, &C->Tg)) || (rc = upload_vec(ctx, D, P.invM, &C->invM)) ||
-       (rc = upload_vec(ctx, D, P.Plimb, &C->Plimb))))
+      ((rc = upload_vec(ctx, D, P.crt->Tg, &C->Tg)) || (rc = upload_vec(ctx, D, P.crt->invM, &C->invM)) ||
+       (rc = upload_vec(ctx, D, P.crt->Plimb, &C->Plimb))))
     return rc;
   return RSL_OK;
 }

@@ -26,18 +26,16 @@ static int64_t pair_mulmods(const Plan& P) {
   return nf + ng + static_cast<int64_t>(P.my) * P.ny;
 }
 
-int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var, const rsl_opts* opts,
-              Job* J, std::string* err, const TuneConfig* tc) {
-  J->tune = tc ? *tc : TuneConfig();
-  const int64_t target = std::max(64, J->tune.chunk_target);
+int job_plan(int n, const rsl_poly* f, const rsl_poly* g, const int* var, const rsl_opts* opts, Job* J,
+             std::string* err) {
   J->n = n;
   J->plans.assign(n, Plan());
   J->pstatus.assign(n, 0);
   J->live.clear();
-  for (int s = 0; s < kNumStages; ++s) J->items[s].clear();
-  int maxg = 0, maxE = 0, maxD = 0;
-  for (int k = 0; k < n; ++k) {
-    std::string e;
+  // planning is independent per problem: spread it over host threads
+  std::vector<std::string> perr(n);
+  parallel_for(n, 4, [&](int k) {
+    std::string& e = perr[k];
     int rc = make_plan(&f[k], &g[k], var[k], opts, &J->plans[k], &e);
     if (!rc && !J->plans[k].zero) {
       const Plan& P = J->plans[k];
@@ -46,13 +44,36 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       else if (std::max(P.my, P.ny) > 255) { rc = RSL_EINVAL; e = "degree in the eliminated variable above 255"; }
     }
     J->pstatus[k] = rc;
-    if (rc) {
-      if (err->empty()) *err = "problem " + std::to_string(k) + ": " + e;
+  });
+  J->plan_err.clear();
+  for (int k = 0; k < n; ++k) {
+    if (J->pstatus[k]) {
+      if (J->plan_err.empty()) J->plan_err = "problem " + std::to_string(k) + ": " + perr[k];
       continue;
     }
+    if (!J->plans[k].zero) J->live.push_back(k);
+  }
+  if (err && err->empty()) *err = J->plan_err;
+  return RSL_OK;
+}
+
+int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var, const rsl_opts* opts,
+              Job* J, std::string* err, const TuneConfig* tc, bool planned) {
+  if (!planned || J->n != n) job_plan(n, f, g, var, opts, J, err);
+  else if (err->empty()) *err = J->plan_err;
+  J->tune = tc ? *tc : TuneConfig();
+  const int64_t target = std::max(64, J->tune.chunk_target);
+  for (int s = 0; s < kNumStages; ++s) J->items[s].clear();
+  int maxg = 0, maxE = 0, maxD = 0;
+  {
+    // live problems in submission order (the order below is by cost)
+    std::vector<int> live;
+    for (int k = 0; k < n; ++k)
+      if (!J->pstatus[k] && !J->plans[k].zero) live.push_back(k);
+    J->live.swap(live);
+  }
+  for (int k : J->live) {
     const Plan& P = J->plans[k];
-    if (P.zero) continue;
-    J->live.push_back(k);
     for (int gi : P.pidx) maxg = std::max(maxg, gi + 1);
     maxE = std::max(maxE, P.E);
     maxD = std::max(maxD, P.D);
@@ -111,6 +132,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   }
   J->pairs = 0;
   J->mulmods = 0;
+  J->mm_sums_mfma = J->mm_valu = J->mfma_macs = J->interp_mm = 0;
   // stir chunking: enough blocks in flight to cover HBM latency
   int64_t stir_base = 0;
   for (int k : J->live) {
@@ -214,6 +236,20 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     J->max_np = std::max(J->max_np, P.np);
     J->pairs += static_cast<int64_t>(P.np) * (P.E + 1);
     J->mulmods += pair_mulmods(P) * P.np * (P.E + 1);
+    {
+      const int64_t pts = static_cast<int64_t>(P.np) * (P.E + 1);
+      const int64_t sums = pair_mulmods(P) - static_cast<int64_t>(P.my) * P.ny;  // N_f + N_g
+      if (d.evmf) {
+        J->mm_sums_mfma += sums * pts;
+        J->mm_valu += static_cast<int64_t>(P.my) * P.ny * pts;
+        // 25 int8 16x16x32 products per 16-point tile and 16-row tile
+        const int64_t tiles = static_cast<int64_t>(P.np) * blocks_of(P.E + 1, d.evpb) * (d.evpb / 16);
+        J->mfma_macs += tiles * (d.dRTf + d.dRTg) * kDigits * kDigits * 16 * 16 * 32;
+      } else {
+        J->mm_valu += pair_mulmods(P) * pts;
+      }
+      J->interp_mm += static_cast<int64_t>(P.np) * (P.D + 1) * (P.D + 2);
+    }
   }
 
   if (J->crt_ns == 5 || J->crt_ns == 7) ++J->crt_ns;  // CRT kernels exist for 1-4, 6 and 8 slots per lane
@@ -245,7 +281,9 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       const int first = (s0 / kReduceMlSlots) * kReduceMlSlots;
       for (int sl = first; sl < P.np; sl += kReduceMlSlots)
         for (int b = 0; b < blocks_of(d.CS, kReduceMlCoeffs); ++b) J->items[kStageReduce].push_back({li, sl, b, 1});
-      if (first >= P.np) J->items[kStageReduce].push_back({li, 0, 0, 1});
+      // the item of (slot 0, block 0) clears the statuses: keep one whenever the
+      // partner reduces the leading slots (it recomputes the same values)
+      if (first > 0) J->items[kStageReduce].push_back({li, 0, 0, 1});
     } else {
       for (int sl = s0; sl < P.np; ++sl)
         for (int b = 0; b < blocks_of(d.CS, 256); ++b) J->items[kStageReduce].push_back({li, sl, b, 0});
@@ -316,9 +354,20 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   // the one-pipeline-per-problem schedule needs)
   {
     std::vector<WorkItem>& ev = J->items[kStageEval];
-    std::stable_sort(ev.begin(), ev.end(), [&](const WorkItem& a, const WorkItem& b) {
-      return eval_variant(J->dev[a.prob]) < eval_variant(J->dev[b.prob]);
-    });
+    {  // stable counting sort by layout variant
+      std::vector<int> var_of(nl);
+      int nv = 1;
+      for (int li = 0; li < nl; ++li) {
+        var_of[li] = eval_variant(J->dev[li]);
+        nv = std::max(nv, var_of[li] + 1);
+      }
+      std::vector<size_t> start(nv + 1, 0);
+      for (const WorkItem& w : ev) ++start[var_of[w.prob] + 1];
+      for (int v = 0; v < nv; ++v) start[v + 1] += start[v];
+      std::vector<WorkItem> sorted(ev.size());
+      for (const WorkItem& w : ev) sorted[start[var_of[w.prob]]++] = w;
+      ev.swap(sorted);
+    }
     for (int li = 0; li < nl; ++li) J->lay[li].item_begin[kStageEval] = J->lay[li].item_end[kStageEval] = -1;
     for (int t = 0; t < static_cast<int>(ev.size()); ++t) {
       ProbLayout& L = J->lay[ev[t].prob];
@@ -424,6 +473,9 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     J->wide_off[pass] = o;
     o = align_up(o + sizeof(WorkItem) * J->wide_items[pass].size(), A);
   }
+  // CRT constants are laid out once per prime list (problems with the same
+  // canonical list share them)
+  std::map<const CrtConst*, int> crt_owner;
   for (int li = 0; li < nl; ++li) {
     const Plan& P = J->plans[J->live[li]];
     const DevProblem& d = J->dev[li];
@@ -432,6 +484,16 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     L.coeff = o; o = align_up(o + static_cast<size_t>(d.ncoef) * d.L_in * 4, 16);
     L.gdeg = o;  o = align_up(o + static_cast<size_t>(d.myp + d.nyp) / kRowGroup * 4, 16);
     L.pidx = o;  o = align_up(o + static_cast<size_t>(P.np) * 4, 16);
+    auto own = crt_owner.find(P.crt.get());
+    if (own != crt_owner.end()) {
+      const ProbLayout& S = J->lay[own->second];
+      L.Hm = S.Hm; L.NH = S.NH; L.Mi = S.Mi; L.wdir = S.wdir; L.rinv = S.rinv; L.negM = S.negM;
+      L.Mw = S.Mw; L.wMd = S.wMd; L.NHM = S.NHM; L.Tg = S.Tg; L.invM = S.invM; L.Plimb = S.Plimb;
+      L.crt_own = false;
+      continue;
+    }
+    crt_owner[P.crt.get()] = li;
+    L.crt_own = true;
     L.Hm = o;    o = align_up(o + static_cast<size_t>(P.np) * 4, 16);
     L.NH = o;    o = align_up(o + static_cast<size_t>(P.L_out) * 4, 16);
     L.Mi = o;    o = align_up(o + static_cast<size_t>(P.np) * P.Lw * 4, 16);
@@ -560,12 +622,23 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   return RSL_OK;
 }
 
-void job_bind(Job* J, uint8_t* base) {
+void job_bind(Job* J, uint8_t* base, uint8_t* image, bool with_queue) {
   J->base = base;
+  J->with_queue = with_queue;
   const int nl = static_cast<int>(J->live.size());
-  J->blob.assign(J->up_bytes, 0);
-  uint8_t* blob = J->blob.data();
-  for (int li = 0; li < nl; ++li) {
+  if (!image) {
+    J->blob.assign(J->up_bytes, 0);
+    image = J->blob.data();
+  } else {
+    J->blob.clear();
+    // an external image is not zeroed: the queue's ready flags and the
+    // statuses must start at zero (every other region is written whole)
+    if (with_queue) std::memset(image + J->qinit_off, 0, J->up_bytes - J->qinit_off);
+  }
+  J->image = image;
+  uint8_t* blob = image;
+  // each problem writes its own regions (a shared CRT block only by its owner)
+  parallel_for(nl, 8, [&](int li) {
     const Plan& P = J->plans[J->live[li]];
     const ProbLayout& L = J->lay[li];
     DevProblem& d = J->dev[li];
@@ -601,30 +674,32 @@ void job_bind(Job* J, uint8_t* base) {
       gd[gf + q] = m;
     }
     std::memcpy(blob + L.pidx, P.pidx.data(), P.np * 4);
-    std::memcpy(blob + L.Hm, P.Hm.data(), P.np * 4);
-    std::memcpy(blob + L.NH, P.NH.data(), P.L_out * 4);
-    std::memcpy(blob + L.Mi, P.Mi.data(), P.Mi.size() * 4);
-    std::memcpy(blob + L.wdir, P.wdir.data(), P.wdir.size() * 4);
-    std::memcpy(blob + L.rinv, P.rinv.data(), P.rinv.size() * 4);
-    std::memcpy(blob + L.negM, P.negM.data(), P.negM.size() * 4);
+    if (L.crt_own) {
+    std::memcpy(blob + L.Hm, P.crt->Hm.data(), P.np * 4);
+    std::memcpy(blob + L.NH, P.crt->NH.data(), P.L_out * 4);
+    std::memcpy(blob + L.Mi, P.crt->Mi.data(), P.crt->Mi.size() * 4);
+    std::memcpy(blob + L.wdir, P.crt->wdir.data(), P.crt->wdir.size() * 4);
+    std::memcpy(blob + L.rinv, P.crt->rinv.data(), P.crt->rinv.size() * 4);
+    std::memcpy(blob + L.negM, P.crt->negM.data(), P.crt->negM.size() * 4);
     if (P.wide) {
-      std::memcpy(blob + L.Mw, P.Mw.data(), P.Mw.size() * 4);
-      std::memcpy(blob + L.NHM, P.NHM.data(), P.NHM.size() * 4);
+      std::memcpy(blob + L.Mw, P.crt->Mw.data(), P.crt->Mw.size() * 4);
+      std::memcpy(blob + L.NHM, P.crt->NHM.data(), P.crt->NHM.size() * 4);
       // 7-bit digit planes of the M_i limbs, [digit][limb][prime], zero padded
       int8_t* md = reinterpret_cast<int8_t*>(blob + L.wMd);
       const size_t plane = static_cast<size_t>(d.wlpad) * d.wnpad;
       for (int i = 0; i < P.np; ++i)
         for (int t = 0; t < P.Lw; ++t) {
-          const uint32_t m = P.Mi[static_cast<size_t>(i) * P.Lw + t];
+          const uint32_t m = P.crt->Mi[static_cast<size_t>(i) * P.Lw + t];
           for (int dd = 0; dd < kWideDigits; ++dd)
             md[dd * plane + static_cast<size_t>(t) * d.wnpad + i] = static_cast<int8_t>((m >> (7 * dd)) & 127u);
         }
     }
     if (!P.canonical) {
-      std::memcpy(blob + L.Tg, P.Tg.data(), P.Tg.size() * 4);
-      std::memcpy(blob + L.invM, P.invM.data(), P.invM.size() * 4);
-      std::memcpy(blob + L.Plimb, P.Plimb.data(), P.Plimb.size() * 4);
+      std::memcpy(blob + L.Tg, P.crt->Tg.data(), P.crt->Tg.size() * 4);
+      std::memcpy(blob + L.invM, P.crt->invM.data(), P.crt->invM.size() * 4);
+      std::memcpy(blob + L.Plimb, P.crt->Plimb.data(), P.crt->Plimb.size() * 4);
     }
+    }  // crt_own
     // device pointers
     d.coeff = reinterpret_cast<const uint32_t*>(base + L.coeff);
     d.gdeg = reinterpret_cast<const int*>(base + L.gdeg);
@@ -649,7 +724,7 @@ void job_bind(Job* J, uint8_t* base) {
     d.cpart = reinterpret_cast<uint64_t*>(base + L.cpart);
     d.out = reinterpret_cast<uint32_t*>(base + L.out);
     d.status = reinterpret_cast<int*>(base + L.status);
-  }
+  });
   for (int li = 0; li < nl; ++li) {
     const int pa = J->partner[li];
     J->dev[li].presid = (pa >= 0) ? reinterpret_cast<uint32_t*>(base + J->lay[pa].resid) : nullptr;
@@ -657,7 +732,7 @@ void job_bind(Job* J, uint8_t* base) {
   }
   // initial queue image: one REDUCE task per (problem, prime slot), largest problems first
   // (none when a problem has more primes than the persistent schedule takes)
-  if (J->max_np <= kMaxSlots) {
+  if (with_queue && J->max_np <= kMaxSlots) {
     uint8_t* q = blob + J->qinit_off;
     QueueState* qs = reinterpret_cast<QueueState*>(q);
     Task* tasks = reinterpret_cast<Task*>(q + J->q_tasks);
@@ -721,19 +796,24 @@ static void bind_crt_tables(const rsl_ctx* ctx, Job* J) {
       d.LP = P.L_out;
     }
   }
-  std::memcpy(J->blob.data() + J->probs_off, J->dev.data(), sizeof(DevProblem) * nl);
+  std::memcpy(J->image + J->probs_off, J->dev.data(), sizeof(DevProblem) * nl);
 }
 
 int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st, uint8_t* pinned) {
   bind_crt_tables(ctx, J);
-  if (J->up_bytes == 0) return RSL_OK;
-  if (!pinned) {
-    int rc = ensure_staging(ctx, J->up_bytes, J->down_bytes);
-    if (rc) return rc;
-    pinned = ctx->h_up;
+  const size_t up = upload_bytes(*J);
+  if (up == 0) return RSL_OK;
+  if (J->blob.empty() && J->image) {
+    pinned = J->image;  // bound straight into pinned staging
+  } else {
+    if (!pinned) {
+      int rc = ensure_staging(ctx, J->up_bytes, J->down_bytes);
+      if (rc) return rc;
+      pinned = ctx->h_up;
+    }
+    std::memcpy(pinned, J->image, up);
   }
-  std::memcpy(pinned, J->blob.data(), J->up_bytes);
-  int rc = hip_check(ctx, hipMemcpyAsync(J->base, pinned, J->up_bytes, hipMemcpyHostToDevice, st), "upload");
+  int rc = hip_check(ctx, hipMemcpyAsync(J->base, pinned, up, hipMemcpyHostToDevice, st), "upload");
   // the residue tiles a partner fills get their padding cleared once (the
   // partner writes only the coefficient positions)
   for (size_t li = 0; !rc && li < J->live.size(); ++li)
@@ -871,28 +951,37 @@ int job_download(rsl_ctx* ctx, Job* J, uint8_t* host, hipStream_t st) {
 int job_decode(rsl_ctx* ctx, const Job& J, const uint8_t* host, rsl_result* out, int* status, rsl_counters* cnt) {
   std::vector<int> li_of(J.n, -1);
   for (size_t li = 0; li < J.live.size(); ++li) li_of[J.live[li]] = static_cast<int>(li);
-  int first = RSL_OK;
-  for (int k = 0; k < J.n; ++k) {
+  // results are independent per problem: decode them on host threads, then
+  // gather counters and the first error in problem order
+  std::vector<int> rcs(J.n, RSL_OK);
+  parallel_for(J.n, 16, [&](int k) {
     int rc = J.pstatus[k];
     const Plan& P = J.plans[k];
     if (!rc) {
-      cnt->problems += 1;
       if (P.zero) {
         rc = decode_result(P, nullptr, &out[k]);
       } else {
-        const int li = li_of[k];
-        const ProbLayout& L = J.lay[li];
+        const ProbLayout& L = J.lay[li_of[k]];
         const int* st = reinterpret_cast<const int*>(host + (L.status - J.down_off));
-        if (st[0] & kErrQueueStall) {
-          rc = RSL_EDEVICE;
-          ctx->err = "persistent launch: a wave gave up waiting on the task queue";
-        } else if (st[0] & kErrTooFewGoodPoints) {
-          rc = RSL_EPRIMES;
-          ctx->err = "fewer than D+1 good points for a prime";
-        } else {
-          rc = decode_result(P, reinterpret_cast<const uint32_t*>(host + (L.out - J.down_off)), &out[k]);
-          if (rc == RSL_ERANGE) ctx->err = "result buffer too small";
-        }
+        if (st[0] & kErrQueueStall) rc = RSL_EDEVICE;
+        else if (st[0] & kErrTooFewGoodPoints) rc = RSL_EPRIMES;
+        else rc = decode_result(P, reinterpret_cast<const uint32_t*>(host + (L.out - J.down_off)), &out[k]);
+      }
+    }
+    rcs[k] = rc;
+  });
+  int first = RSL_OK;
+  for (int k = 0; k < J.n; ++k) {
+    const int rc = rcs[k];
+    const Plan& P = J.plans[k];
+    if (!J.pstatus[k]) {
+      cnt->problems += 1;
+      if (!P.zero) {
+        const ProbLayout& L = J.lay[li_of[k]];
+        const int* st = reinterpret_cast<const int*>(host + (L.status - J.down_off));
+        if (rc == RSL_EDEVICE) ctx->err = "persistent launch: a wave gave up waiting on the task queue";
+        else if (rc == RSL_EPRIMES) ctx->err = "fewer than D+1 good points for a prime";
+        else if (rc == RSL_ERANGE) ctx->err = "result buffer too small";
         cnt->pairs += static_cast<int64_t>(P.np) * (P.E + 1);
         cnt->bad_pairs += st[P.np + 1];
         cnt->bad_primes += P.bad_primes;

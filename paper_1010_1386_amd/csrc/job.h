@@ -25,6 +25,7 @@ struct ProbLayout {
   size_t coeff, gdeg, pidx, Hm, NH, Tg, invM, Plimb, Mi, wdir, rinv, negM, Mw, NHM, wMd, status;
   size_t out, resid, dig, zval, zbad, aconv, cpart, wT, wq, wS;
   int L_in;
+  bool crt_own;  // this problem's layout holds the CRT constant block it shares
   int item_begin[kNumStages], item_end[kNumStages];
   int wide_begin[3], wide_end[3];  // ranges of Job::wide_items[pass] (wide CRT)
 };
@@ -33,6 +34,7 @@ struct Job {
   int n = 0;                       // problems submitted
   std::vector<Plan> plans;         // one per problem
   std::vector<int> pstatus;        // planning status per problem (0 = ok)
+  std::string plan_err;            // message of the first planning failure
   std::vector<int> live;           // problems with device work, in launch order
   std::vector<ProbLayout> lay;     // per live problem
   std::vector<DevProblem> dev;     // per live problem (pointers valid for `base`)
@@ -76,23 +78,40 @@ struct Job {
   int persist_grid = 0;
   size_t total = 0;
   uint8_t* base = nullptr;         // device region the job is laid out in
-  std::vector<uint8_t> blob;       // host image of [0, up_bytes)
+  std::vector<uint8_t> blob;       // host image of [0, up_bytes) when bound without an external image
+  uint8_t* image = nullptr;        // the host image job_bind wrote (blob or the caller's pinned buffer)
+  bool with_queue = true;          // the image holds the persistent queue (and is uploaded whole)
   int64_t pairs = 0;
   int64_t mulmods = 0;             // algorithmic work of eval + ures: Montgomery products over all pairs
+  int64_t mm_sums_mfma = 0;        // of which evaluation sums on the matrix cores
+  int64_t mm_valu = 0;             // of which on the vector ALUs
+  int64_t mfma_macs = 0;           // int8 multiply-adds issued on the matrix cores for those sums
+  int64_t interp_mm = 0;           // interpolation products: N_p (D+1)(D+2) over problems
   TuneConfig tune;                 // schedule parameters the job was laid out with
 };
 
 // Autotuner cache key of a planned job (its shape bucket).
 std::string tune_key(const Job& J);
 
-// Plan every problem and lay the job out (host only).
+// Plan every problem (host threads): plans, statuses, live problems.
+int job_plan(int n, const rsl_poly* f, const rsl_poly* g, const int* var, const rsl_opts* opts, Job* J,
+             std::string* err);
+// Plan every problem (unless `planned`: J holds job_plan's result for these
+// inputs) and lay the job out (host only).
 int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var, const rsl_opts* opts,
-              Job* J, std::string* err, const TuneConfig* tc = nullptr);
+              Job* J, std::string* err, const TuneConfig* tc = nullptr, bool planned = false);
 // Bind the job to a device region (fills device pointers and the upload image).
-void job_bind(Job* J, uint8_t* base);
-// Upload the inputs (asynchronous on the stream) through `pinned` (>= up_bytes of
-// pinned host memory that stays untouched until the copy is done), or through
-// the context's staging buffer when pinned is null.
+// image: host memory of at least up_bytes to write the upload image into (e.g.
+// pinned staging; null = the job's own blob).  with_queue = false leaves out the
+// persistent queue and the statuses (staged and plain runs clear the statuses
+// themselves): only [0, upload_bytes()) is written and uploaded.
+void job_bind(Job* J, uint8_t* base, uint8_t* image = nullptr, bool with_queue = true);
+// Bytes of the image that job_upload sends.
+inline size_t upload_bytes(const Job& J) { return J.with_queue ? J.up_bytes : J.qinit_off; }
+// Upload the inputs (asynchronous on the stream).  The image is copied to
+// `pinned` (>= up_bytes of pinned host memory that stays untouched until the
+// copy is done) or to the context's staging buffer when pinned is null, unless
+// it already is pinned memory bound with job_bind (then it is sent directly).
 int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st, uint8_t* pinned = nullptr);
 // Zero the status words before a persistent run (the staged and plain launches
 // clear them in their reduce stage).

@@ -2,8 +2,11 @@
 #include "plan.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <thread>
 
 namespace rsl {
 
@@ -113,17 +116,46 @@ int make_view(const rsl_poly* f, int var, View* v, std::string* err) {
   v->rdeg = rdeg;
   const int row = v->dx + 1;
   v->c.assign(static_cast<size_t>(v->dy + 1) * row * L, 0u);
-  v->absv.assign(static_cast<size_t>(v->dy + 1) * row, BigU());
-  v->neg.assign(static_cast<size_t>(v->dy + 1) * row, 0);
-  for (int j = 0; j <= v->dy; ++j)
-    for (int i = 0; i <= v->rdeg[j]; ++i) {
-      const uint32_t* w = at(j, i);
-      size_t idx = static_cast<size_t>(j) * row + i;
-      std::memcpy(&v->c[idx * L], w, sizeof(uint32_t) * L);
-      bool ng = false;
-      v->absv[idx] = abs_limbs(w, L, &ng);
-      v->neg[idx] = ng;
+  v->row_l1.assign(v->dy + 1, BigU());
+  for (int j = 0; j <= v->dy; ++j) {
+    if (v->rdeg[j] < 0) continue;
+    if (var == RSL_Y) {
+      // rows of the original layout are contiguous: one copy per row
+      std::memcpy(&v->c[static_cast<size_t>(j) * row * L], at(j, 0), sizeof(uint32_t) * (v->rdeg[j] + 1) * L);
+    } else {
+      for (int i = 0; i <= v->rdeg[j]; ++i)
+        std::memcpy(&v->c[(static_cast<size_t>(j) * row + i) * L], at(j, i), sizeof(uint32_t) * L);
     }
+    // ||f_j||_1: at most 2^26 coefficients of at most 64 bits fit 128 bits
+    if (L <= 2) {
+      unsigned __int128 acc = 0;
+      const uint32_t* r = &v->c[static_cast<size_t>(j) * row * L];
+      for (int i = 0; i <= v->rdeg[j]; ++i) {
+        const uint32_t* w = r + static_cast<size_t>(i) * L;
+        if (L == 1) {
+          const int64_t x = static_cast<int32_t>(w[0]);
+          acc += static_cast<uint64_t>(x < 0 ? -x : x);
+        } else {
+          const uint64_t u = static_cast<uint64_t>(w[0]) | (static_cast<uint64_t>(w[1]) << 32);
+          acc += (u >> 63) ? (~u + 1) : u;  // |INT64_MIN| = 2^63 as unsigned
+        }
+      }
+      BigU t;
+      for (int q = 0; q < 4 && acc; ++q) {
+        t.d.push_back(static_cast<uint32_t>(acc));
+        acc >>= 32;
+      }
+      v->row_l1[j] = t;
+    } else {
+      BigU t;
+      for (int i = 0; i <= v->rdeg[j]; ++i)
+        t = BigU::add(t, abs_limbs(&v->c[(static_cast<size_t>(j) * row + i) * L], L, nullptr));
+      v->row_l1[j] = t;
+    }
+  }
+  v->lc_abs.assign(v->rdeg[v->dy] + 1, BigU());
+  for (int i = 0; i <= v->rdeg[v->dy]; ++i)
+    v->lc_abs[i] = abs_limbs(&v->c[(static_cast<size_t>(v->dy) * row + i) * L], L, nullptr);
   return RSL_OK;
 }
 
@@ -171,37 +203,101 @@ void direct_crt_tables(const std::vector<uint32_t>& primes, const BigU& M, int L
   *negM = M.neg_limbs(L);
 }
 
+namespace {
+
+std::shared_ptr<const CrtConst> build_crt_const(const std::vector<uint32_t>& primes, bool canonical) {
+  auto C = std::make_shared<CrtConst>();
+  C->np = static_cast<int>(primes.size());
+  BigU M(1);
+  for (uint32_t p : primes) M = BigU::mul_small(M, p);
+  C->L_out = std::max(1, (M.bitlen() + 31) / 32);
+  BigU H = M.half();  // (M - 1) / 2, M odd
+  C->Hm.resize(C->np);
+  for (int i = 0; i < C->np; ++i) C->Hm[i] = H.mod_small(primes[i]);
+  C->NH = H.neg_limbs(C->L_out);
+  // beyond the per-lane slots the CRT takes the wide path: Y0 = sum_i t_i M_i - q M
+  // with q possibly one short, so Y0 < 2M needs one limb more than M
+  C->wide = C->np > kSlotCrtPrimes;
+  C->Lw = C->wide ? C->L_out + 1 : C->L_out;
+  if (!canonical && !C->wide) crt_tables(primes, C->L_out, &C->Tg, &C->invM, &C->Plimb);
+  direct_crt_tables(primes, M, C->Lw, &C->Mi, &C->wdir, &C->rinv, &C->negM);
+  if (C->wide) {
+    C->Mw = M.limbs(C->Lw);
+    C->NHM = BigU::add(H, M).neg_limbs(C->L_out);
+  }
+  return C;
+}
+
+// canonical lists by prime count; dropped whole when it holds more than kCrtCacheBytes
+std::mutex g_crt_mu;
+std::map<int, std::shared_ptr<const CrtConst>> g_crt;
+size_t g_crt_bytes = 0;
+constexpr size_t kCrtCacheBytes = size_t(512) << 20;
+
+size_t crt_bytes(const CrtConst& C) {
+  return 4 * (C.Hm.size() + C.NH.size() + C.Tg.size() + C.invM.size() + C.Plimb.size() + C.Mi.size() +
+              C.wdir.size() + C.rinv.size() + C.negM.size() + C.Mw.size() + C.NHM.size());
+}
+
+}  // namespace
+
 void plan_crt(Plan* P) {
   const std::vector<uint32_t>& tab = prime_table(0);
   P->np = static_cast<int>(P->pidx.size());
   P->canonical = true;
   for (int i = 0; i < P->np; ++i)
     if (P->pidx[i] != i) P->canonical = false;
-  std::vector<uint32_t> primes(P->np);
-  BigU M(1);
-  for (int i = 0; i < P->np; ++i) {
-    primes[i] = tab[P->pidx[i]];
-    M = BigU::mul_small(M, primes[i]);
+  std::shared_ptr<const CrtConst> C;
+  if (P->canonical) {
+    std::lock_guard<std::mutex> lk(g_crt_mu);
+    auto it = g_crt.find(P->np);
+    if (it != g_crt.end()) C = it->second;
   }
-  P->L_out = std::max(1, (M.bitlen() + 31) / 32);
-  BigU H = M.half();  // (M - 1) / 2, M odd
-  P->Hm.resize(P->np);
-  for (int i = 0; i < P->np; ++i) P->Hm[i] = H.mod_small(primes[i]);
-  P->NH = H.neg_limbs(P->L_out);
-  // beyond the per-lane slots the CRT takes the wide path: Y0 = sum_i t_i M_i - q M
-  // with q possibly one short, so Y0 < 2M needs one limb more than M
-  P->wide = P->np > kSlotCrtPrimes;
-  P->Lw = P->wide ? P->L_out + 1 : P->L_out;
-  if (!P->canonical && !P->wide) crt_tables(primes, P->L_out, &P->Tg, &P->invM, &P->Plimb);
-  else { P->Tg.clear(); P->invM.clear(); P->Plimb.clear(); }
-  direct_crt_tables(primes, M, P->Lw, &P->Mi, &P->wdir, &P->rinv, &P->negM);
-  if (P->wide) {
-    P->Mw = M.limbs(P->Lw);
-    P->NHM = BigU::add(H, M).neg_limbs(P->L_out);
-  } else {
-    P->Mw.clear();
-    P->NHM.clear();
+  if (!C) {
+    std::vector<uint32_t> primes(P->np);
+    for (int i = 0; i < P->np; ++i) primes[i] = tab[P->pidx[i]];
+    C = build_crt_const(primes, P->canonical);
+    if (P->canonical) {
+      std::lock_guard<std::mutex> lk(g_crt_mu);
+      const size_t b = crt_bytes(*C);
+      if (g_crt_bytes + b > kCrtCacheBytes) {
+        g_crt.clear();
+        g_crt_bytes = 0;
+      }
+      if (g_crt.emplace(P->np, C).second) g_crt_bytes += b;
+    }
   }
+  P->crt = C;
+  P->L_out = C->L_out;
+  P->wide = C->wide;
+  P->Lw = C->Lw;
+}
+
+void parallel_for(int n, int grain, const std::function<void(int)>& fn, int threads) {
+  if (n <= 0) return;
+  grain = std::max(1, grain);
+  int hw = static_cast<int>(std::thread::hardware_concurrency());
+  if (hw <= 0) hw = 1;
+  int T = threads > 0 ? threads : std::min(hw, 16);
+  T = std::min(T, (n + grain - 1) / grain);
+  if (T <= 1) {
+    for (int i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::atomic<int> next{0};
+  auto body = [&]() {
+    for (;;) {
+      const int b = next.fetch_add(grain);
+      if (b >= n) break;
+      const int e = std::min(n, b + grain);
+      for (int i = b; i < e; ++i) fn(i);
+    }
+  };
+  std::vector<std::thread> th;
+  th.reserve(T - 1);
+  for (int t = 1; t < T; ++t) th.emplace_back(body);
+  body();
+  for (std::thread& t : th) t.join();
 }
 
 int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opts, Plan* P,
@@ -248,12 +344,7 @@ int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opt
   // Hadamard bound: B^2 = (sum_j ||f_j||_1^2)^{n_y} (sum_j ||g_j||_1^2)^{m_y}
   auto row_sq_sum = [](const View& V) {
     BigU S;
-    const int row = V.dx + 1;
-    for (int j = 0; j <= V.dy; ++j) {
-      BigU l1;
-      for (int i = 0; i <= V.rdeg[j]; ++i) l1 = BigU::add(l1, V.absv[static_cast<size_t>(j) * row + i]);
-      S = BigU::add(S, BigU::mul(l1, l1));
-    }
+    for (int j = 0; j <= V.dy; ++j) S = BigU::add(S, BigU::mul(V.row_l1[j], V.row_l1[j]));
     return S;
   };
   BigU B2 = BigU::mul(BigU::pow(row_sq_sum(F), ny), BigU::pow(row_sq_sum(G), my));
@@ -262,11 +353,8 @@ int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opt
 
   // primes: largest first, skipping bad primes (p | every coefficient of lc_y f or lc_y g)
   auto lc_vanishes = [](const View& V, uint32_t p) {
-    const int row = V.dx + 1;
-    for (int i = 0; i <= V.rdeg[V.dy]; ++i) {
-      size_t idx = static_cast<size_t>(V.dy) * row + i;
-      if (V.absv[idx].mod_small(p) != 0) return false;
-    }
+    for (const BigU& a : V.lc_abs)
+      if (a.mod_small(p) != 0) return false;
     return true;
   };
   const size_t limit = o.prime_limit ? static_cast<size_t>(o.prime_limit) : kPrimeTableMax;

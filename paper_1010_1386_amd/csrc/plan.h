@@ -4,6 +4,8 @@
 // footprint.
 #pragma once
 #include <cstdint>
+#include <functional>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -27,8 +29,28 @@ struct View {
   int L = 1;                // limbs per coefficient
   std::vector<int> rdeg;    // per-row x-degree, -1 for a zero row
   std::vector<uint32_t> c;  // rows 0..dy, cols 0..dx, L limbs each (two's complement)
-  std::vector<BigU> absv;   // |coefficient|, same order (planning only)
-  std::vector<uint8_t> neg;
+  std::vector<BigU> row_l1; // per row j: ||f_j||_1, the sum of |coefficient| (planning only)
+  std::vector<BigU> lc_abs; // |coefficient| of the leading row (bad-prime screen)
+};
+
+// CRT constants of one ordered prime list with product M (Sec. 4.1: the
+// integer result is lifted from its images modulo the primes).  Shared by
+// every plan with that list: canonical lists (primes 0..np-1 of the table)
+// come from a process-wide cache.
+struct CrtConst {
+  int np = 0;
+  int L_out = 1;            // CRT output limbs (two's complement)
+  bool wide = false;        // CRT by the wide path (more than kSlotCrtPrimes primes)
+  int Lw = 1;               // limbs of the Mi rows and of negM: L_out, or L_out + 1 when wide
+  std::vector<uint32_t> Hm; // (M-1)/2 mod p_i
+  std::vector<uint32_t> NH; // 2^(32 L_out) - (M-1)/2, L_out limbs
+  // Garner tables (only for a non-canonical list on the slot path)
+  std::vector<uint32_t> Tg, invM, Plimb;
+  // direct CRT tables: limbs of M / p_j ([np][Lw]), (M / p_i)^{-1} R mod p_i,
+  // floor(2^64 / p_i) as (low, high) words, 2^(32 Lw) - M
+  std::vector<uint32_t> Mi, wdir, rinv, negM;
+  // wide path: M in Lw limbs, -(M-1)/2 - M mod 2^(32 L_out)
+  std::vector<uint32_t> Mw, NHM;
 };
 
 int make_view(const rsl_poly* f, int var, View* v, std::string* err);
@@ -47,18 +69,10 @@ struct Plan {
   bool canonical = true;    // pidx == 0..np-1 (global CRT tables apply)
   int bad_primes = 0;
   int bound_bits = 0;
-  int L_out = 1;            // CRT output limbs (two's complement)
-  bool wide = false;        // CRT by the wide path (more than kSlotCrtPrimes primes)
-  int Lw = 1;               // limbs of the Mi rows and of negM: L_out, or L_out + 1 when wide
-  std::vector<uint32_t> Hm; // (M-1)/2 mod p_i
-  std::vector<uint32_t> NH; // 2^(32 L_out) - (M-1)/2, L_out limbs
-  // per-plan CRT tables (only when !canonical)
-  std::vector<uint32_t> Tg, invM, Plimb;
-  // direct CRT tables: limbs of M / p_j ([np][Lw]), (M / p_i)^{-1} R mod p_i,
-  // floor(2^64 / p_i) as (low, high) words, 2^(32 Lw) - M
-  std::vector<uint32_t> Mi, wdir, rinv, negM;
-  // wide path: M in Lw limbs, -(M-1)/2 - M mod 2^(32 L_out)
-  std::vector<uint32_t> Mw, NHM;
+  int L_out = 1;            // CRT output limbs (copied from crt)
+  bool wide = false;        // CRT by the wide path (copied from crt)
+  int Lw = 1;               // copied from crt
+  std::shared_ptr<const CrtConst> crt;
   // device layout
   int rowf = 0, rowg = 0;   // row strides (dx + 1) of the residue tiles
   int CS = 0;               // residue words per prime (f tile + g tile, padded)
@@ -71,8 +85,13 @@ int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opt
 
 // CRT constants of P->pidx (prime product M): np, canonical, L_out, H mod p_i,
 // 2^(32 L_out) - H, the wide-path choice, Garner tables (non-canonical slot
-// path only) and the direct-CRT tables.
+// path only) and the direct-CRT tables.  Canonical lists are computed once
+// per process and shared.
 void plan_crt(Plan* P);
+
+// Run fn(i) for i in [0, n) on up to `threads` host threads (0: the default,
+// at most 16); blocks of `grain` consecutive indices per task.
+void parallel_for(int n, int grain, const std::function<void(int)>& fn, int threads = 0);
 
 // CRT tables for an ordered prime list (Garner constants and prefix products).
 //   Tg[j*np + i] = (prod_{l<j} p_l mod p_i) R mod p_i          (j < i)

@@ -252,6 +252,10 @@ int rsl_job_info_get(const rsl_job* j, rsl_job_info* info) {
   info->n_live = static_cast<int32_t>(j->J.live.size());
   info->pairs = j->J.pairs;
   info->mulmods = j->J.mulmods;
+  info->mulmods_sums_mfma = j->J.mm_sums_mfma;
+  info->mulmods_valu = j->J.mm_valu;
+  info->mfma_int8_macs = j->J.mfma_macs;
+  info->interp_mulmods = j->J.interp_mm;
   info->device_bytes = j->J.total;
   info->upload_bytes = j->J.up_bytes;
   info->download_bytes = j->J.down_bytes;
