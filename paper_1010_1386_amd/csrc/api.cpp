@@ -2,9 +2,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <condition_variable>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <thread>
 
 #include "context.h"
 #include "job.h"
@@ -206,24 +210,237 @@ int decode_result(const Plan& P, const uint32_t* limbs, rsl_result* out) {
   return RSL_OK;
 }
 
+static int grow_pinned(rsl_ctx* ctx, uint8_t** buf, size_t* have, size_t need) {
+  if (need <= *have) return RSL_OK;
+  if (*buf) (void)hipHostFree(*buf);
+  *buf = nullptr;
+  *have = 0;
+  const size_t sz = align_up(std::max(need, static_cast<size_t>(1) << 20), 1 << 20);
+  int rc = hip_check(ctx, hipHostMalloc(reinterpret_cast<void**>(buf), sz, hipHostMallocDefault), "hipHostMalloc");
+  if (!rc) *have = sz;
+  return rc;
+}
+
+// Contiguous ranges by estimated device work: the first range takes half a
+// share (the device starts sooner), the others a full share each; a y problem
+// directly followed by an x problem (a joint pair sharing its reduction) is
+// never split.
+static std::vector<std::pair<int, int>> chunk_ranges(const std::vector<ShapeEst>& est, const int* var, int S) {
+  const int n = static_cast<int>(est.size());
+  double total = 0.0;
+  for (const ShapeEst& e : est) total += e.zero ? 0.0 : e.cost;
+  std::vector<std::pair<int, int>> out;
+  int lo = 0;
+  double acc = 0.0;
+  for (int k = 0; k < n; ++k) {
+    acc += est[k].zero ? 0.0 : est[k].cost;
+    const bool pair_next = k + 1 < n && var[k] == RSL_Y && var[k + 1] == RSL_X;
+    const int c = static_cast<int>(out.size());
+    if (c < S - 1 && !pair_next && acc >= total * (2.0 * c + 1.0) / (2.0 * S - 1.0)) {
+      out.push_back({lo, k + 1});
+      lo = k + 1;
+    }
+  }
+  if (lo < n) out.push_back({lo, n});
+  return out;
+}
+
+// A batch as S chunks in a pipeline: a host thread plans and lays out chunk
+// c + 1 while the device runs chunk c, and chunk c is decoded while later
+// chunks run.  Every chunk is a staged (or plain) job of its own, in its own
+// region of the workspace (the workspace is reused after a synchronization
+// when the regions do not all fit) with its own pinned staging.
+static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var,
+                       const rsl_opts* opts, rsl_result* out, int* status, int mode, const TuneConfig* tc,
+                       const std::vector<std::pair<int, int>>& ranges, const std::vector<ShapeEst>& est,
+                       std::string* err, rsl_counters* cnt) {
+  const int S = static_cast<int>(ranges.size());
+  if (static_cast<int>(ctx->chunk_stage.size()) < S) ctx->chunk_stage.resize(S);
+  for (int c = 0; c < S; ++c) {
+    rsl_ctx::ChunkStage& cs = ctx->chunk_stage[c];
+    if (!cs.e0 && hipEventCreate(&cs.e0) != hipSuccess) return fail(ctx, RSL_EDEVICE, "hipEventCreate");
+    if (!cs.e1 && hipEventCreate(&cs.e1) != hipSuccess) return fail(ctx, RSL_EDEVICE, "hipEventCreate");
+    if (!cs.e2 && hipEventCreate(&cs.e2) != hipSuccess) return fail(ctx, RSL_EDEVICE, "hipEventCreate");
+    if (!cs.e3 && hipEventCreateWithFlags(&cs.e3, hipEventDisableTiming) != hipSuccess)
+      return fail(ctx, RSL_EDEVICE, "hipEventCreate");
+  }
+  if (!ctx->s_up && hipStreamCreateWithFlags(&ctx->s_up, hipStreamNonBlocking) != hipSuccess)
+    return fail(ctx, RSL_EDEVICE, "hipStreamCreate");
+  if (!ctx->s_down && hipStreamCreateWithFlags(&ctx->s_down, hipStreamNonBlocking) != hipSuccess)
+    return fail(ctx, RSL_EDEVICE, "hipStreamCreate");
+  auto sync_all = [&]() {
+    int e = hip_check(ctx, hipStreamSynchronize(ctx->s_up), "hipStreamSynchronize");
+    if (!e) e = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    if (!e) e = hip_check(ctx, hipStreamSynchronize(ctx->s_down), "hipStreamSynchronize");
+    return e;
+  };
+  std::vector<Job> jobs(S);
+  std::vector<std::string> errs(S);
+  std::vector<int> brc(S, RSL_OK);
+  std::vector<char> ready(S, 0);
+  std::mutex mu;
+  std::condition_variable cv;
+  double build_ms = 0.0;
+  // the constant tables for the estimated shapes, before any launch (growing
+  // them later would synchronize the device; a chunk that needs more still
+  // grows them, correctly)
+  {
+    int ng = 0, nE = 0, nD = 0;
+    for (const ShapeEst& e : est)
+      if (!e.zero && !e.bad) {
+        ng = std::max(ng, e.np_est + 2);
+        nE = std::max(nE, e.E);
+        nD = std::max(nD, e.D);
+      }
+    int rc0 = ng ? ensure_tables(ctx, std::min(ng, kMaxPrimes), nE, nD) : RSL_OK;
+    if (rc0) return rc0;
+  }
+  // producer: plans and lays out one chunk after the other (host only; the
+  // tables are grown below, on this thread)
+  const bool trace = std::getenv("RSL_TRACE_CHUNKS") != nullptr;
+  const double tz = now_ms();
+  std::vector<double> t_ready(S), t_enq(S), t_done(S), t_dec(S);
+  std::thread producer([&]() {
+    const double tb = now_ms();
+    for (int c = 0; c < S; ++c) {
+      const int lo = ranges[c].first, hi = ranges[c].second;
+      Job& J = jobs[c];
+      job_plan(hi - lo, f + lo, g + lo, var + lo, opts, &J, &errs[c]);
+      brc[c] = job_build(ctx, J.n, f + lo, g + lo, var + lo, opts, &J, &errs[c], tc, true, true);
+      std::lock_guard<std::mutex> lk(mu);
+      t_ready[c] = now_ms() - tz;
+      ready[c] = 1;
+      cv.notify_all();
+    }
+    build_ms = now_ms() - tb;
+  });
+  hipStream_t st = ctx->stream;
+  int rc = RSL_OK;
+  size_t off = 0;
+  int launched = 0;
+  double bind_ms = 0.0;
+  for (int c = 0; c < S && !rc; ++c) {
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv.wait(lk, [&] { return ready[c] != 0; });
+    }
+    Job& J = jobs[c];
+    if (brc[c]) { rc = brc[c]; break; }
+    if (J.live.empty()) { ++launched; continue; }
+    if (J.total > ctx->ws_bytes) {
+      rc = fail(ctx, RSL_ENOMEM, "workspace of " + std::to_string(ctx->ws_bytes) + " bytes < footprint " +
+                                     std::to_string(J.total) + " of a chunk");
+      for (int k : J.live) J.pstatus[k] = RSL_ENOMEM;
+      break;
+    }
+    if (off + J.total > ctx->ws_bytes) {  // reuse the workspace once the earlier chunks are done
+      if ((rc = sync_all())) break;
+      off = 0;
+    }
+    if ((rc = ensure_tables(ctx, J.need_g, J.need_E, J.need_D))) break;  // a no-op once grown
+    rsl_ctx::ChunkStage& cs = ctx->chunk_stage[c];
+    if ((rc = grow_pinned(ctx, &cs.up, &cs.up_bytes, J.up_bytes)) ||
+        (rc = grow_pinned(ctx, &cs.down, &cs.down_bytes, J.down_bytes)))
+      break;
+    const double t1 = now_ms();
+    job_bind(&J, ctx->ws + off, cs.up, mode == RSL_BATCHED);
+    bind_ms += now_ms() - t1;
+    off = align_up(off + J.total, 256);
+    // upload on the copy stream; the kernels wait for it on the context's
+    // stream; the download waits for the kernels on the other copy stream
+    if ((rc = job_upload_copy(ctx, &J, ctx->s_up)) ||
+        (rc = hip_check(ctx, hipEventRecord(cs.e3, ctx->s_up), "event")) ||
+        (rc = hip_check(ctx, hipStreamWaitEvent(st, cs.e3, 0), "hipStreamWaitEvent")) ||
+        (rc = job_upload_clear(ctx, &J, st)) || (rc = hip_check(ctx, hipEventRecord(cs.e0, st), "event")) ||
+        (rc = job_launch(ctx, &J, mode, st, false)) || (rc = hip_check(ctx, hipEventRecord(cs.e1, st), "event")) ||
+        (rc = hip_check(ctx, hipStreamWaitEvent(ctx->s_down, cs.e1, 0), "hipStreamWaitEvent")) ||
+        (rc = job_download(ctx, &J, cs.down, ctx->s_down)) ||
+        (rc = hip_check(ctx, hipEventRecord(cs.e2, ctx->s_down), "event")))
+      break;
+    t_enq[c] = now_ms() - tz;
+    ++launched;
+  }
+  // decode each launched chunk as soon as its copies are done
+  double dec_ms = 0.0;
+  for (int c = 0; c < launched; ++c) {
+    Job& J = jobs[c];
+    const int lo = ranges[c].first;
+    if (!J.live.empty()) {
+      const int e = hip_check(ctx, hipEventSynchronize(ctx->chunk_stage[c].e2), "hipEventSynchronize");
+      if (e) { rc = rc ? rc : e; break; }
+      t_done[c] = now_ms() - tz;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ctx->chunk_stage[c].e0, ctx->chunk_stage[c].e1);
+      cnt->ms_device += ms;
+    }
+    const double t3 = now_ms();
+    std::vector<int> stc(J.n);
+    const int r = job_decode(ctx, J, J.live.empty() ? nullptr : ctx->chunk_stage[c].down, out + lo, stc.data(), cnt);
+    dec_ms += now_ms() - t3;
+    t_dec[c] = now_ms() - tz;
+    if (status)
+      for (int k = 0; k < J.n; ++k) status[lo + k] = stc[k];
+    if (r && !rc) rc = r;
+  }
+  producer.join();
+  (void)sync_all();
+  if (trace) {
+    for (int c = 0; c < S; ++c) {
+      float dev = 0.f;
+      (void)hipEventElapsedTime(&dev, ctx->chunk_stage[c].e0, ctx->chunk_stage[c].e1);
+      fprintf(stderr, "chunk %d [%d,%d): ready %.2f enq %.2f done %.2f dec %.2f dev %.2f\n", c, ranges[c].first,
+              ranges[c].second, t_ready[c], t_enq[c], t_done[c], t_dec[c], dev);
+    }
+  }
+  cnt->ms_build += build_ms;
+  cnt->ms_bind += bind_ms;
+  cnt->ms_decode += dec_ms;
+  for (int c = 0; c < S; ++c)
+    if (!errs[c].empty() && err->empty()) *err = errs[c];
+  if (status && rc && launched < S)
+    for (int c = launched; c < S; ++c)
+      for (int k = ranges[c].first; k < ranges[c].second; ++k) status[k] = rc;
+  return rc;
+}
+
 // Run a job laid out in the context workspace, synchronously.
 static int run_in_workspace(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var,
                             const rsl_opts* opts, rsl_result* out, int* status, int mode, rsl_counters* cnt) {
   const double t0 = now_ms();
-  Job J;
   std::string err;
-  job_plan(n, f, g, var, opts, &J, &err);
+  // shapes from the inputs alone: the schedule lookup and the chunking need no plans
+  std::vector<ShapeEst> est(n);
+  parallel_for(n, 32, [&](int k) { est[k] = estimate_shape(&f[k], &g[k], var[k]); });
   // RSL_AUTO: the schedule the autotuner chose for this shape bucket, else the
   // staged default; the job is laid out once, with the chosen parameters
   const TuneConfig* tc = nullptr;
   if (mode == RSL_AUTO) {
     mode = RSL_STAGED;
-    auto it = ctx->tune_cache.find(tune_key(J));
+    auto it = ctx->tune_cache.find(tune_key_of(est));
     if (it != ctx->tune_cache.end()) {
       mode = it->second.cfg.mode;
       tc = &it->second.cfg;
     }
   }
+  // large batches on the staged or plain schedule: a pipeline of chunks, so
+  // that host work overlaps the device
+  if (mode != RSL_BATCHED) {
+    int live = 0;
+    for (const ShapeEst& e : est) live += (!e.zero && !e.bad) ? 1 : 0;
+    int S = live >= 384 ? 6 : live >= 192 ? 4 : live >= 96 ? 2 : 1;
+    if (const char* env = std::getenv("RSL_BATCH_CHUNKS")) S = std::max(1, std::min(16, std::atoi(env)));
+    if (S > 1) {
+      std::vector<std::pair<int, int>> ranges = chunk_ranges(est, var, S);
+      if (ranges.size() > 1) {
+        cnt->ms_build += now_ms() - t0;
+        int rc = run_chunked(ctx, n, f, g, var, opts, out, status, mode, tc, ranges, est, &err, cnt);
+        if (rc && !err.empty() && ctx->err.empty()) ctx->err = err;
+        return rc;
+      }
+    }
+  }
+  Job J;
+  job_plan(n, f, g, var, opts, &J, &err);
   int rc = job_build(ctx, n, f, g, var, opts, &J, &err, tc, true);
   if (rc == RSL_EDEVICE) return rc;
   const double t1 = now_ms();
@@ -306,6 +523,16 @@ int rsl_ctx_destroy(rsl_ctx* ctx) {
   free_tables(ctx);
   if (ctx->h_up) (void)hipHostFree(ctx->h_up);
   if (ctx->h_down) (void)hipHostFree(ctx->h_down);
+  for (rsl_ctx::ChunkStage& cs : ctx->chunk_stage) {
+    if (cs.up) (void)hipHostFree(cs.up);
+    if (cs.down) (void)hipHostFree(cs.down);
+    if (cs.e0) (void)hipEventDestroy(cs.e0);
+    if (cs.e1) (void)hipEventDestroy(cs.e1);
+    if (cs.e2) (void)hipEventDestroy(cs.e2);
+    if (cs.e3) (void)hipEventDestroy(cs.e3);
+  }
+  if (ctx->s_up) (void)hipStreamDestroy(ctx->s_up);
+  if (ctx->s_down) (void)hipStreamDestroy(ctx->s_down);
   if (ctx->e0) (void)hipEventDestroy(ctx->e0);
   if (ctx->e1) (void)hipEventDestroy(ctx->e1);
   for (hipEvent_t e : ctx->ev)

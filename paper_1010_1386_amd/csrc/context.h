@@ -59,6 +59,21 @@ struct rsl_ctx {
   uint8_t* h_down = nullptr;
   size_t h_down_bytes = 0;
 
+  // pinned staging and completion events of the pipelined chunks of a batch call
+  struct ChunkStage {
+    uint8_t* up = nullptr;
+    size_t up_bytes = 0;
+    uint8_t* down = nullptr;
+    size_t down_bytes = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;  // around the device pipeline
+    hipEvent_t e2 = nullptr;                // after the download
+    hipEvent_t e3 = nullptr;                // after the upload
+  };
+  std::vector<ChunkStage> chunk_stage;
+  // copy streams of the pipelined batch call (created on first use, default
+  // priority): uploads and downloads of one chunk overlap the kernels of another
+  hipStream_t s_up = nullptr, s_down = nullptr;
+
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipEvent_t ev[rsl::kNumStages + 1] = {};   // stage boundaries of the last batched launch
   std::vector<std::vector<hipEvent_t>> evsets; // per-run stage events while profiling

@@ -57,8 +57,12 @@ int job_plan(int n, const rsl_poly* f, const rsl_poly* g, const int* var, const 
   return RSL_OK;
 }
 
+int64_t problem_cost(const Plan& P) {
+  return pair_mulmods(P) * P.np * (P.E + 1) + static_cast<int64_t>(P.np) * (P.D + 1) * (P.D + 1);
+}
+
 int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var, const rsl_opts* opts,
-              Job* J, std::string* err, const TuneConfig* tc, bool planned) {
+              Job* J, std::string* err, const TuneConfig* tc, bool planned, bool defer_tables) {
   if (!planned || J->n != n) job_plan(n, f, g, var, opts, J, err);
   else if (err->empty()) *err = J->plan_err;
   J->tune = tc ? *tc : TuneConfig();
@@ -104,7 +108,10 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     if (ra == rb) return pair_of[b] >= 0 && pair_of[a] < 0;
     return cost[ra] > cost[rb] || (cost[ra] == cost[rb] && ra < rb);
   });
-  if (ctx && !J->live.empty()) {
+  J->need_g = maxg;
+  J->need_E = maxE;
+  J->need_D = maxD;
+  if (ctx && !defer_tables && !J->live.empty()) {
     int rc = ensure_tables(ctx, maxg, maxE, maxD);
     if (rc) { *err = ctx->err; return rc; }
   }
@@ -799,7 +806,7 @@ static void bind_crt_tables(const rsl_ctx* ctx, Job* J) {
   std::memcpy(J->image + J->probs_off, J->dev.data(), sizeof(DevProblem) * nl);
 }
 
-int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st, uint8_t* pinned) {
+int job_upload_copy(rsl_ctx* ctx, Job* J, hipStream_t st, uint8_t* pinned) {
   bind_crt_tables(ctx, J);
   const size_t up = upload_bytes(*J);
   if (up == 0) return RSL_OK;
@@ -813,7 +820,17 @@ int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st, uint8_t* pinned) {
     }
     std::memcpy(pinned, J->image, up);
   }
-  int rc = hip_check(ctx, hipMemcpyAsync(J->base, pinned, up, hipMemcpyHostToDevice, st), "upload");
+  return hip_check(ctx, hipMemcpyAsync(J->base, pinned, up, hipMemcpyHostToDevice, st), "upload");
+}
+
+int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st, uint8_t* pinned) {
+  int rc = job_upload_copy(ctx, J, st, pinned);
+  if (!rc) rc = job_upload_clear(ctx, J, st);
+  return rc;
+}
+
+int job_upload_clear(rsl_ctx* ctx, Job* J, hipStream_t st) {
+  int rc = RSL_OK;
   // the residue tiles a partner fills get their padding cleared once (the
   // partner writes only the coefficient positions)
   for (size_t li = 0; !rc && li < J->live.size(); ++li)

@@ -61,6 +61,7 @@ struct Job {
   size_t stage_lds[kNumStages] = {};
   int crt_ns = 1;
   int max_np = 0;                  // most primes of any live problem
+  int need_g = 0, need_E = 0, need_D = 0;  // constant tables the job reads (primes, points, degree)
   bool any_schur = false;          // some problem evaluates by the Schur algorithm
   // live index of the partner (the same system eliminated in x) that a
   // problem's reduction also fills, -1 if none; prime slots shared
@@ -90,16 +91,23 @@ struct Job {
   TuneConfig tune;                 // schedule parameters the job was laid out with
 };
 
-// Autotuner cache key of a planned job (its shape bucket).
-std::string tune_key(const Job& J);
+// Autotuner cache key of a batch (its shape bucket), from the inputs alone.
+std::string tune_key(int n, const rsl_poly* f, const rsl_poly* g, const int* var);
+std::string tune_key_of(const std::vector<ShapeEst>& est);
 
 // Plan every problem (host threads): plans, statuses, live problems.
 int job_plan(int n, const rsl_poly* f, const rsl_poly* g, const int* var, const rsl_opts* opts, Job* J,
              std::string* err);
 // Plan every problem (unless `planned`: J holds job_plan's result for these
 // inputs) and lay the job out (host only).
+// defer_tables: leave the context's constant tables alone (the caller grows them
+// to need_g / need_E / need_D before binding; host work only, any thread).
 int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var, const rsl_opts* opts,
-              Job* J, std::string* err, const TuneConfig* tc = nullptr, bool planned = false);
+              Job* J, std::string* err, const TuneConfig* tc = nullptr, bool planned = false,
+              bool defer_tables = false);
+// Device work of a planned problem (evaluation, resultants and interpolation
+// products), for balancing.
+int64_t problem_cost(const Plan& P);
 // Bind the job to a device region (fills device pointers and the upload image).
 // image: host memory of at least up_bytes to write the upload image into (e.g.
 // pinned staging; null = the job's own blob).  with_queue = false leaves out the
@@ -113,6 +121,11 @@ inline size_t upload_bytes(const Job& J) { return J.with_queue ? J.up_bytes : J.
 // copy is done) or to the context's staging buffer when pinned is null, unless
 // it already is pinned memory bound with job_bind (then it is sent directly).
 int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st, uint8_t* pinned = nullptr);
+// The two halves of job_upload: the copy of the image, and the clearing
+// launches of the intermediate buffers the kernels expect zeroed (ordered
+// after the copy; they may run on another stream that waits for it).
+int job_upload_copy(rsl_ctx* ctx, Job* J, hipStream_t st, uint8_t* pinned = nullptr);
+int job_upload_clear(rsl_ctx* ctx, Job* J, hipStream_t st);
 // Zero the status words before a persistent run (the staged and plain launches
 // clear them in their reduce stage).
 int job_reset(rsl_ctx* ctx, Job* J, hipStream_t st);

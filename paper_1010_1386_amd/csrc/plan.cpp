@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -273,12 +275,92 @@ void plan_crt(Plan* P) {
   P->Lw = C->Lw;
 }
 
+namespace {
+
+// Degrees and per-row L1 norms (double) of one input in the eliminated variable's view.
+struct RowScan {
+  int dy = -1, dx = -1, tdeg = -1, lcdeg = -1, L = 1;
+  int64_t nterms = 0;
+  double sq = 0.0;  // sum_j ||f_j||_1^2
+  bool ok = false;
+};
+
+RowScan scan_rows(const rsl_poly* f, int var) {
+  RowScan r;
+  if (!f || f->dx < 0 || f->dy < 0 || f->limbs < 1 || !f->coeff) return r;
+  r.ok = true;
+  const int L = f->limbs;
+  r.L = L;
+  const int Ydim = (var == RSL_Y) ? f->dy : f->dx;
+  const int Xdim = (var == RSL_Y) ? f->dx : f->dy;
+  for (int j = 0; j <= Ydim; ++j) {
+    double l1 = 0.0;
+    int rd = -1;
+    for (int i = 0; i <= Xdim; ++i) {
+      const int yi = (var == RSL_Y) ? j : i, xi = (var == RSL_Y) ? i : j;
+      const uint32_t* w = f->coeff + (static_cast<int64_t>(yi) * (f->dx + 1) + xi) * L;
+      bool nz = false;
+      for (int l = 0; l < L; ++l) nz |= w[l] != 0u;
+      if (!nz) continue;
+      rd = i;
+      // |value| from its top two limbs (two's complement)
+      const bool neg = (w[L - 1] >> 31) != 0;
+      double v = 0.0;
+      for (int l = L - 1; l >= 0 && l >= L - 3; --l) {
+        const uint32_t x = neg ? ~w[l] : w[l];
+        v += std::ldexp(static_cast<double>(x), 32 * l);
+      }
+      l1 += v + 1.0;
+    }
+    if (rd >= 0) {
+      r.dy = j;
+      r.dx = std::max(r.dx, rd);
+      r.tdeg = std::max(r.tdeg, rd + j);
+      r.lcdeg = rd;
+      r.nterms += rd + 1;
+      r.sq += l1 * l1;
+    }
+  }
+  return r;
+}
+
+}  // namespace
+
+ShapeEst estimate_shape(const rsl_poly* f, const rsl_poly* g, int var) {
+  ShapeEst e;
+  const RowScan a = scan_rows(f, var), b = scan_rows(g, var);
+  if (!a.ok || !b.ok || (var != RSL_Y && var != RSL_X)) {
+    e.bad = true;
+    return e;
+  }
+  e.L = std::max(a.L, b.L);
+  if (a.dy < 0 || b.dy < 0) return e;
+  e.zero = false;
+  e.my = a.dy;
+  e.ny = b.dy;
+  const int64_t d1 = static_cast<int64_t>(b.dy) * a.dx + static_cast<int64_t>(a.dy) * b.dx;
+  const int64_t d2 = static_cast<int64_t>(b.dy) * a.tdeg + static_cast<int64_t>(a.dy) * b.tdeg -
+                     static_cast<int64_t>(a.dy) * b.dy;
+  e.D = static_cast<int>(std::min<int64_t>(std::min(d1, d2), 1 << 20));
+  e.E = e.D + a.lcdeg + b.lcdeg;
+  const double lb2 = b.dy * std::log2(std::max(a.sq, 1.0)) + a.dy * std::log2(std::max(b.sq, 1.0));
+  e.np_est = static_cast<int>(std::ceil((lb2 / 2.0 + 1.0) / 30.99)) + 1;
+  e.cost = (static_cast<double>(a.nterms + b.nterms) + static_cast<double>(a.dy) * b.dy) * e.np_est * (e.E + 1) +
+           static_cast<double>(e.np_est) * (e.D + 1) * (e.D + 1);
+  return e;
+}
+
 void parallel_for(int n, int grain, const std::function<void(int)>& fn, int threads) {
   if (n <= 0) return;
   grain = std::max(1, grain);
-  int hw = static_cast<int>(std::thread::hardware_concurrency());
-  if (hw <= 0) hw = 1;
-  int T = threads > 0 ? threads : std::min(hw, 16);
+  static const int default_threads = [] {
+    int hw = static_cast<int>(std::thread::hardware_concurrency());
+    if (hw <= 0) hw = 1;
+    int t = std::min(hw, 16);
+    if (const char* env = std::getenv("RSL_HOST_THREADS")) t = std::max(1, std::min(64, std::atoi(env)));
+    return t;
+  }();
+  int T = threads > 0 ? threads : default_threads;
   T = std::min(T, (n + grain - 1) / grain);
   if (T <= 1) {
     for (int i = 0; i < n; ++i) fn(i);
@@ -341,15 +423,38 @@ int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opt
   P->s = F.rdeg[my] + G.rdeg[ny];
   P->E = P->D + P->s + o.extra_points;
 
-  // Hadamard bound: B^2 = (sum_j ||f_j||_1^2)^{n_y} (sum_j ||g_j||_1^2)^{m_y}
+  // Hadamard bound: B^2 = (sum_j ||f_j||_1^2)^{n_y} (sum_j ||g_j||_1^2)^{m_y}.
+  // Primes are taken until M^2 > 4 B^2 (M their product).  The comparison runs
+  // on log2 values in double precision (relative error far below 1e-12) and
+  // falls back to exact big integers only when the two sides are within a
+  // safety margin of each other, so the prime count is the exact minimum.
   auto row_sq_sum = [](const View& V) {
     BigU S;
     for (int j = 0; j <= V.dy; ++j) S = BigU::add(S, BigU::mul(V.row_l1[j], V.row_l1[j]));
     return S;
   };
-  BigU B2 = BigU::mul(BigU::pow(row_sq_sum(F), ny), BigU::pow(row_sq_sum(G), my));
-  P->bound_bits = (B2.bitlen() + 1) / 2;
-  BigU fourB2 = BigU::mul_small(B2, 4);
+  const BigU Sf = row_sq_sum(F), Sg = row_sq_sum(G);
+  auto log2_of = [](const BigU& a) {
+    if (a.is_zero()) return 0.0;
+    const int nb = a.bitlen();
+    const int sh = std::max(0, nb - 64);
+    const BigU t = a.shr(sh);
+    uint64_t v = 0;
+    for (size_t i = 0; i < t.d.size() && i < 2; ++i) v |= static_cast<uint64_t>(t.d[i]) << (32 * i);
+    return std::log2(static_cast<double>(v)) + sh;
+  };
+  const double lb2 = ny * log2_of(Sf) + my * log2_of(Sg);  // log2(B^2)
+  const double slack = 1e-3 + 1e-9 * lb2;
+  BigU fourB2;  // exact 4 B^2, made on first need
+  bool have_exact = false;
+  auto exact_4b2 = [&]() -> const BigU& {
+    if (!have_exact) {
+      fourB2 = BigU::mul_small(BigU::mul(BigU::pow(Sf, ny), BigU::pow(Sg, my)), 4);
+      have_exact = true;
+    }
+    return fourB2;
+  };
+  P->bound_bits = static_cast<int>((std::floor(lb2) + 2.0) / 2.0);
 
   // primes: largest first, skipping bad primes (p | every coefficient of lc_y f or lc_y g)
   auto lc_vanishes = [](const View& V, uint32_t p) {
@@ -358,7 +463,7 @@ int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opt
     return true;
   };
   const size_t limit = o.prime_limit ? static_cast<size_t>(o.prime_limit) : kPrimeTableMax;
-  BigU M(1);
+  double lm = 0.0;  // log2(M)
   P->pidx.clear();
   P->bad_primes = 0;
   int extra_left = o.extra_primes;
@@ -379,13 +484,16 @@ int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opt
       continue;
     }
     P->pidx.push_back(static_cast<int>(k));
-    M = BigU::mul_small(M, p);
+    lm += std::log2(static_cast<double>(p));
     if (!enough) {
-      // M^2 has 2 b - 1 or 2 b bits (b = bits of M): the exact product is
-      // needed only when that range meets the bit length of 4 B^2
-      const int bm = M.bitlen(), bb = fourB2.bitlen();
-      if (2 * bm - 1 > bb) enough = true;
-      else if (2 * bm >= bb) enough = BigU::cmp(BigU::mul(M, M), fourB2) > 0;
+      const double d = 2.0 * lm - (lb2 + 2.0);  // log2(M^2) - log2(4 B^2)
+      if (d > slack) {
+        enough = true;
+      } else if (d >= -slack) {
+        BigU M(1);
+        for (int i : P->pidx) M = BigU::mul_small(M, tab[i]);
+        enough = BigU::cmp(BigU::mul(M, M), exact_4b2()) > 0;
+      }
     }
     if (enough) {
       if (extra_left == 0) break;

@@ -89,6 +89,19 @@ int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opt
 // per process and shared.
 void plan_crt(Plan* P);
 
+// Shape of a problem from its inputs alone (one pass over the coefficients, no
+// big integers): the degrees the plan will have, and estimates of the prime
+// count (from the Hadamard bound in double precision) and of the device work.
+struct ShapeEst {
+  bool zero = true;         // an input is the zero polynomial (no device work)
+  bool bad = false;         // invalid descriptor
+  int my = 0, ny = 0, D = 0, E = 0;
+  int L = 1;                // most limbs of the inputs
+  int np_est = 0;           // primes for the bound (bad primes not counted)
+  double cost = 0.0;        // evaluation, resultant and interpolation products
+};
+ShapeEst estimate_shape(const rsl_poly* f, const rsl_poly* g, int var);
+
 // Run fn(i) for i in [0, n) on up to `threads` host threads (0: the default,
 // at most 16); blocks of `grain` consecutive indices per task.
 void parallel_for(int n, int grain, const std::function<void(int)>& fn, int threads = 0);

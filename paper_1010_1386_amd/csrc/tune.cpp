@@ -39,19 +39,28 @@ static int ilog2up(int64_t v) {
   return b;
 }
 
-// Shape bucket of a job: problems, max degree bound, max primes, max degree in the
-// eliminated variable -- each rounded up to a power of two.
-std::string tune_key(const Job& J) {
-  int64_t maxD = 0, maxnp = 0, maxdeg = 0;
-  for (int k : J.live) {
-    const Plan& P = J.plans[k];
-    maxD = std::max<int64_t>(maxD, P.D + 1);
-    maxnp = std::max<int64_t>(maxnp, P.np);
-    maxdeg = std::max<int64_t>(maxdeg, std::max(P.my, P.ny) + 1);
+// Shape bucket of a batch: live problems, max degree bound, max degree in the
+// eliminated variable, max input limbs -- each rounded up to a power of two.
+// Computed from the inputs alone (no planning), so that a batch call can look
+// up its schedule before any problem is planned.
+std::string tune_key(int n, const rsl_poly* f, const rsl_poly* g, const int* var) {
+  std::vector<ShapeEst> est(n);
+  parallel_for(n, 32, [&](int k) { est[k] = estimate_shape(&f[k], &g[k], var[k]); });
+  return tune_key_of(est);
+}
+
+std::string tune_key_of(const std::vector<ShapeEst>& est) {
+  int64_t live = 0, maxD = 0, maxdeg = 0, maxL = 0;
+  for (const ShapeEst& e : est) {
+    if (e.zero || e.bad) continue;
+    ++live;
+    maxD = std::max<int64_t>(maxD, e.D + 1);
+    maxdeg = std::max<int64_t>(maxdeg, std::max(e.my, e.ny) + 1);
+    maxL = std::max<int64_t>(maxL, e.L);
   }
   std::ostringstream os;
-  os << "n" << ilog2up(std::max<size_t>(J.live.size(), 1)) << ".D" << ilog2up(maxD) << ".p" << ilog2up(maxnp)
-     << ".m" << ilog2up(maxdeg);
+  os << "n" << ilog2up(std::max<int64_t>(live, 1)) << ".D" << ilog2up(maxD) << ".m" << ilog2up(maxdeg) << ".L"
+     << ilog2up(maxL);
   return os.str();
 }
 
@@ -203,12 +212,8 @@ int rsl_job_create(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, co
   // the shape bucket's cached schedule, if the autotuner has seen this shape
   TuneConfig tc;
   if (!ctx->tune_cache.empty()) {
-    Job probe;
-    std::string e;
-    if (job_build(nullptr, n, j->f.data(), j->g.data(), j->var.data(), opts, &probe, &e) == RSL_OK) {
-      auto it = ctx->tune_cache.find(tune_key(probe));
-      if (it != ctx->tune_cache.end()) tc = it->second.cfg;
-    }
+    auto it = ctx->tune_cache.find(tune_key(n, j->f.data(), j->g.data(), j->var.data()));
+    if (it != ctx->tune_cache.end()) tc = it->second.cfg;
   }
   int rc = materialize(ctx, j, tc);
   if (status)
@@ -362,7 +367,7 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
     }
   }
   if ((rc = materialize(ctx, j, win))) return rc;
-  ctx->tune_cache[tune_key(j->J)] = TuneEntry{win, win_ms};
+  ctx->tune_cache[tune_key(j->J.n, j->f.data(), j->g.data(), j->var.data())] = TuneEntry{win, win_ms};
   if (best) *best = rsl_tune_result{win.mode, win.chunk_target, win.grid_mult, win.evk, win.conv_whole, win.schur,
                                     static_cast<int32_t>(cands.size()), win_ms, worst_ms};
   return RSL_OK;
