@@ -253,7 +253,7 @@ static std::vector<std::pair<int, int>> chunk_ranges(const std::vector<ShapeEst>
 static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var,
                        const rsl_opts* opts, rsl_result* out, int* status, int mode, const TuneConfig* tc,
                        const std::vector<std::pair<int, int>>& ranges, const std::vector<ShapeEst>& est,
-                       std::string* err, rsl_counters* cnt) {
+                       std::string* err, rsl_counters* cnt, double t_entry) {
   const int S = static_cast<int>(ranges.size());
   if (static_cast<int>(ctx->chunk_stage.size()) < S) ctx->chunk_stage.resize(S);
   for (int c = 0; c < S; ++c) {
@@ -268,9 +268,12 @@ static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g
     return fail(ctx, RSL_EDEVICE, "hipStreamCreate");
   if (!ctx->s_down && hipStreamCreateWithFlags(&ctx->s_down, hipStreamNonBlocking) != hipSuccess)
     return fail(ctx, RSL_EDEVICE, "hipStreamCreate");
+  if (!ctx->s_comp2 && hipStreamCreateWithFlags(&ctx->s_comp2, hipStreamNonBlocking) != hipSuccess)
+    return fail(ctx, RSL_EDEVICE, "hipStreamCreate");
   auto sync_all = [&]() {
     int e = hip_check(ctx, hipStreamSynchronize(ctx->s_up), "hipStreamSynchronize");
     if (!e) e = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    if (!e) e = hip_check(ctx, hipStreamSynchronize(ctx->s_comp2), "hipStreamSynchronize");
     if (!e) e = hip_check(ctx, hipStreamSynchronize(ctx->s_down), "hipStreamSynchronize");
     return e;
   };
@@ -299,14 +302,18 @@ static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g
   // tables are grown below, on this thread)
   const bool trace = std::getenv("RSL_TRACE_CHUNKS") != nullptr;
   const double tz = now_ms();
-  std::vector<double> t_ready(S), t_enq(S), t_done(S), t_dec(S);
+  if (trace) fprintf(stderr, "before the pipeline %.2f ms\n", tz - t_entry);
+  std::vector<double> t_ready(S), t_enq(S), t_done(S), t_dec(S), t_plan(S), t_lay(S), t_bind(S), t_dcd(S);
   std::thread producer([&]() {
     const double tb = now_ms();
     for (int c = 0; c < S; ++c) {
       const int lo = ranges[c].first, hi = ranges[c].second;
       Job& J = jobs[c];
+      const double tp0 = now_ms();
       job_plan(hi - lo, f + lo, g + lo, var + lo, opts, &J, &errs[c]);
+      t_plan[c] = now_ms() - tp0;
       brc[c] = job_build(ctx, J.n, f + lo, g + lo, var + lo, opts, &J, &errs[c], tc, true, true);
+      t_lay[c] = now_ms() - tp0 - t_plan[c];
       std::lock_guard<std::mutex> lk(mu);
       t_ready[c] = now_ms() - tz;
       ready[c] = 1;
@@ -344,15 +351,18 @@ static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g
       break;
     const double t1 = now_ms();
     job_bind(&J, ctx->ws + off, cs.up, mode == RSL_BATCHED);
+    t_bind[c] = now_ms() - t1;
     bind_ms += now_ms() - t1;
     off = align_up(off + J.total, 256);
-    // upload on the copy stream; the kernels wait for it on the context's
-    // stream; the download waits for the kernels on the other copy stream
+    // upload on the copy stream; the kernels wait for it on a compute stream
+    // (the context's stream and the second one in turn); the download waits
+    // for the kernels on the other copy stream
+    hipStream_t sc = (c & 1) ? ctx->s_comp2 : st;
     if ((rc = job_upload_copy(ctx, &J, ctx->s_up)) ||
         (rc = hip_check(ctx, hipEventRecord(cs.e3, ctx->s_up), "event")) ||
-        (rc = hip_check(ctx, hipStreamWaitEvent(st, cs.e3, 0), "hipStreamWaitEvent")) ||
-        (rc = job_upload_clear(ctx, &J, st)) || (rc = hip_check(ctx, hipEventRecord(cs.e0, st), "event")) ||
-        (rc = job_launch(ctx, &J, mode, st, false)) || (rc = hip_check(ctx, hipEventRecord(cs.e1, st), "event")) ||
+        (rc = hip_check(ctx, hipStreamWaitEvent(sc, cs.e3, 0), "hipStreamWaitEvent")) ||
+        (rc = job_upload_clear(ctx, &J, sc)) || (rc = hip_check(ctx, hipEventRecord(cs.e0, sc), "event")) ||
+        (rc = job_launch(ctx, &J, mode, sc, false)) || (rc = hip_check(ctx, hipEventRecord(cs.e1, sc), "event")) ||
         (rc = hip_check(ctx, hipStreamWaitEvent(ctx->s_down, cs.e1, 0), "hipStreamWaitEvent")) ||
         (rc = job_download(ctx, &J, cs.down, ctx->s_down)) ||
         (rc = hip_check(ctx, hipEventRecord(cs.e2, ctx->s_down), "event")))
@@ -377,19 +387,25 @@ static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g
     std::vector<int> stc(J.n);
     const int r = job_decode(ctx, J, J.live.empty() ? nullptr : ctx->chunk_stage[c].down, out + lo, stc.data(), cnt);
     dec_ms += now_ms() - t3;
+    t_dcd[c] = now_ms() - t3;
     t_dec[c] = now_ms() - tz;
     if (status)
       for (int k = 0; k < J.n; ++k) status[lo + k] = stc[k];
     if (r && !rc) rc = r;
+    J = Job();  // free the chunk's host state while later chunks still run
   }
+  const double tj0 = now_ms();
   producer.join();
   (void)sync_all();
+  const double tj1 = now_ms();
+  std::vector<Job>().swap(jobs);
+  if (trace) fprintf(stderr, "join+sync %.2f free %.2f\n", tj1 - tj0, now_ms() - tj1);
   if (trace) {
     for (int c = 0; c < S; ++c) {
       float dev = 0.f;
       (void)hipEventElapsedTime(&dev, ctx->chunk_stage[c].e0, ctx->chunk_stage[c].e1);
-      fprintf(stderr, "chunk %d [%d,%d): ready %.2f enq %.2f done %.2f dec %.2f dev %.2f\n", c, ranges[c].first,
-              ranges[c].second, t_ready[c], t_enq[c], t_done[c], t_dec[c], dev);
+      fprintf(stderr, "chunk %d [%d,%d): plan %.2f layout %.2f ready %.2f bind %.2f enq %.2f done %.2f decode %.2f dec %.2f dev %.2f\n", c, ranges[c].first,
+              ranges[c].second, t_plan[c], t_lay[c], t_ready[c], t_bind[c], t_enq[c], t_done[c], t_dcd[c], t_dec[c], dev);
     }
   }
   cnt->ms_build += build_ms;
@@ -433,7 +449,7 @@ static int run_in_workspace(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_po
       std::vector<std::pair<int, int>> ranges = chunk_ranges(est, var, S);
       if (ranges.size() > 1) {
         cnt->ms_build += now_ms() - t0;
-        int rc = run_chunked(ctx, n, f, g, var, opts, out, status, mode, tc, ranges, est, &err, cnt);
+        int rc = run_chunked(ctx, n, f, g, var, opts, out, status, mode, tc, ranges, est, &err, cnt, t0);
         if (rc && !err.empty() && ctx->err.empty()) ctx->err = err;
         return rc;
       }
@@ -533,6 +549,7 @@ int rsl_ctx_destroy(rsl_ctx* ctx) {
   }
   if (ctx->s_up) (void)hipStreamDestroy(ctx->s_up);
   if (ctx->s_down) (void)hipStreamDestroy(ctx->s_down);
+  if (ctx->s_comp2) (void)hipStreamDestroy(ctx->s_comp2);
   if (ctx->e0) (void)hipEventDestroy(ctx->e0);
   if (ctx->e1) (void)hipEventDestroy(ctx->e1);
   for (hipEvent_t e : ctx->ev)

@@ -73,6 +73,9 @@ struct rsl_ctx {
   // copy streams of the pipelined batch call (created on first use, default
   // priority): uploads and downloads of one chunk overlap the kernels of another
   hipStream_t s_up = nullptr, s_down = nullptr;
+  // second compute stream: consecutive chunks alternate between it and the
+  // context's stream, so one chunk's kernels fill the tail of the previous one's
+  hipStream_t s_comp2 = nullptr;
 
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipEvent_t ev[rsl::kNumStages + 1] = {};   // stage boundaries of the last batched launch

@@ -158,8 +158,10 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     return RSL_EINVAL;
   }
   const bool regs_ok = !(opts && opts->eval_regs < 0);
-  auto regn_of = [&](const Plan& P) {
-    if (!regs_ok || P.my < 1 || P.ny < 1 || std::abs(P.my - P.ny) > 1) return 0;
+  // long_ok: shapes with |m_y - n_y| > 1 have a register form only in the
+  // one-lane evaluation on the matrix cores (ures_regs_long)
+  auto regn_of = [&](const Plan& P, bool long_ok = false) {
+    if (!regs_ok || P.my < 1 || P.ny < 1 || (std::abs(P.my - P.ny) > 1 && !long_ok)) return 0;
     for (int nmax : {8, 16, 24, 32})
       if (std::max(P.my, P.ny) <= nmax) return nmax;
     return 0;
@@ -214,7 +216,8 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     d.evk = 1;
     while (d.evk < evk && std::min(P.my, P.ny) >= 4 * d.evk * 2) d.evk *= 2;
     d.evpb = 64 / d.evk;
-    d.regn = (d.evk <= 2) ? regn_of(P) : 0;
+    const bool long_ok = d.evk == 1 && P.rowf <= 32 && P.rowg <= 32 && !(ctx && ctx->eval_horner);
+    d.regn = (d.evk <= 2) ? regn_of(P, long_ok) : 0;
     d.schur = (schur_req && P.my >= 1 && P.ny >= 1 && P.my + P.ny <= kSchurMaxR) ? 1 : 0;
     if (d.schur) {  // one wave per pair, kSchurPts points per block
       d.evk = 1;

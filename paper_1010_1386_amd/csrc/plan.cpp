@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <condition_variable>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -350,36 +352,103 @@ ShapeEst estimate_shape(const rsl_poly* f, const rsl_poly* g, int var) {
   return e;
 }
 
+namespace {
+
+// A fixed set of worker threads, shared by every parallel_for of the process
+// (the batch pipeline runs several at once: planning on its producer thread,
+// binding and decoding on the caller's).  The calling thread works on its own
+// task too, so a task finishes even when every worker is busy elsewhere.
+class HostPool {
+ public:
+  struct Task {
+    const std::function<void(int)>* fn = nullptr;
+    int n = 0, grain = 1;
+    std::atomic<int> next{0};
+    std::atomic<int> left{0};
+    std::mutex m;
+    std::condition_variable done;
+  };
+
+  explicit HostPool(int workers) {
+    for (int t = 0; t < workers; ++t) th_.emplace_back([this] { loop(); });
+  }
+
+  void run(const std::function<void(int)>& fn, int n, int grain) {
+    auto t = std::make_shared<Task>();
+    t->fn = &fn;
+    t->n = n;
+    t->grain = grain;
+    t->left.store(n);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      q_.push_back(t);
+    }
+    cv_.notify_all();
+    work(*t);
+    std::unique_lock<std::mutex> lk(t->m);
+    t->done.wait(lk, [&] { return t->left.load() == 0; });
+  }
+
+ private:
+  void work(Task& t) {
+    for (;;) {
+      const int b = t.next.fetch_add(t.grain);
+      if (b >= t.n) break;
+      const int e = std::min(t.n, b + t.grain);
+      for (int i = b; i < e; ++i) (*t.fn)(i);
+      if (t.left.fetch_sub(e - b) == e - b) {
+        std::lock_guard<std::mutex> lk(t.m);
+        t.done.notify_all();
+      }
+    }
+  }
+  void loop() {
+    for (;;) {
+      std::shared_ptr<Task> t;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return !q_.empty(); });
+        t = q_.front();
+        if (t->next.load() >= t->n) {  // exhausted: take it off the queue
+          q_.pop_front();
+          continue;
+        }
+      }
+      work(*t);
+    }
+  }
+
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::deque<std::shared_ptr<Task>> q_;
+  std::vector<std::thread> th_;
+};
+
+int host_threads() {
+  static const int t = [] {
+    int hw = static_cast<int>(std::thread::hardware_concurrency());
+    if (hw <= 0) hw = 1;
+    int v = std::min(hw, 16);
+    if (const char* env = std::getenv("RSL_HOST_THREADS")) v = std::max(1, std::min(64, std::atoi(env)));
+    return v;
+  }();
+  return t;
+}
+
+}  // namespace
+
 void parallel_for(int n, int grain, const std::function<void(int)>& fn, int threads) {
   if (n <= 0) return;
   grain = std::max(1, grain);
-  static const int default_threads = [] {
-    int hw = static_cast<int>(std::thread::hardware_concurrency());
-    if (hw <= 0) hw = 1;
-    int t = std::min(hw, 16);
-    if (const char* env = std::getenv("RSL_HOST_THREADS")) t = std::max(1, std::min(64, std::atoi(env)));
-    return t;
-  }();
-  int T = threads > 0 ? threads : default_threads;
-  T = std::min(T, (n + grain - 1) / grain);
-  if (T <= 1) {
+  const int T = threads > 0 ? threads : host_threads();
+  if (T <= 1 || n <= grain) {
     for (int i = 0; i < n; ++i) fn(i);
     return;
   }
-  std::atomic<int> next{0};
-  auto body = [&]() {
-    for (;;) {
-      const int b = next.fetch_add(grain);
-      if (b >= n) break;
-      const int e = std::min(n, b + grain);
-      for (int i = b; i < e; ++i) fn(i);
-    }
-  };
-  std::vector<std::thread> th;
-  th.reserve(T - 1);
-  for (int t = 1; t < T; ++t) th.emplace_back(body);
-  body();
-  for (std::thread& t : th) t.join();
+  // the workers live for the rest of the process (never destroyed: no
+  // ordering problem with other static objects at exit)
+  static HostPool* pool = new HostPool(host_threads() - 1);
+  pool->run(fn, n, grain);
 }
 
 int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opts, Plan* P,

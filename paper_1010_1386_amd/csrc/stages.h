@@ -853,6 +853,12 @@ __device__ inline void stage_eval_ures_mfma(const DevProblem& P, const DevTables
       r = ures2_columns<NMAX>(X, Y, P.my, P.ny, l, pc, Column<32>{cols + q},
                               Column<32>{cols + (NMAX + 1) * 32 + q}, PairSwap(), WaveSync());
     }
+  } else if (P.my - P.ny > 1 || P.ny - P.my > 1) {
+    // the long shapes: first division on the lane's own value rows, then the
+    // branch-free chain in registers (ures_regs_long); no other lane's rows are touched
+    pt = w.blk * PTS + lane;
+    live = pt <= P.E;
+    r = ures_regs_long<NMAX>(Column<1>{Fv[0] + lane * SR}, Column<1>{Fv[1] + lane * SR}, P.my, P.ny, pc, &bad);
   } else {
     constexpr int N = RegPoly<NMAX>::kN;
     pt = w.blk * PTS + lane;

@@ -269,6 +269,89 @@ RSL_HD uint32_t ures_regs_generic(uint32_t (&X)[RegPoly<NMAX>::kN], uint32_t (&Y
   return neg ? mneg(r, p) : r;
 }
 
+// Res_{m,n}(A, B) for the shapes with |m - n| >= 2 (one lane).  A and B are
+// rows of scratch memory holding the coefficients (Montgomery form, formal
+// degrees m, n); both are overwritten.  The first division -- k = |m - n| + 1
+// elimination passes of the longer polynomial by the shorter -- runs on the
+// rows, each pass touching only the n positions that meet the shifted divisor
+// (a coefficient that joins that window late takes the powers of L it
+// missed in one product).  If the remainder has the generic degree n - 1, the
+// rest of the sequence runs in registers without branches (RegChainGen) from
+// (B, R~); a lane that leaves the generic pattern there continues with the
+// general code on the rows from the state after the first division (the rows
+// are untouched by the register chain).  Vanishing leading coefficients and
+// non-generic first remainders take the general code too.
+template <int NMAX, class Col>
+RSL_HD uint32_t ures_regs_long(Col A, Col B, int m, int n, const PrimeConst& pc, bool* bad) {
+  constexpr int N = RegPoly<NMAX>::kN;
+  const uint32_t p = pc.p, pinv = pc.pinv, one = pc.r1;
+  *bad = (A[m] == 0u) || (B[n] == 0u);
+  if (*bad || m < 1 || n < 1) {
+    bool b2 = false;
+    return ures_formal(A, B, m, n, pc, &b2);
+  }
+  uint32_t neg = 0u;
+  if (m < n) {  // Res(A, B) = (-1)^{mn} Res(B, A)
+    Col t = A;
+    A = B;
+    B = t;
+    neg = static_cast<uint32_t>(m * n) & 1u;
+    const int ti = m;
+    m = n;
+    n = ti;
+  }
+  const int a = m, b = n, k = a - b + 1;
+  const uint32_t L = B[b];
+  // pass t (degree d = a - t, shift sh = d - b): A[j] <- L A[j] - lc B[j - sh]
+  // for sh <= j < d; position sh joins now and takes L^(t+1)
+  uint32_t Lt = L;
+  for (int t = 0; t < k; ++t) {
+    const int d = a - t, sh = d - b;
+    const uint32_t lc = A[d];
+    A[sh] = mmulsub(Lt, A[sh], lc, B[0], p, pinv);
+    for (int j = sh + 1; j < d; ++j) A[j] = mmulsub(L, A[j], lc, B[j - sh], p, pinv);
+    if (t + 1 < k) Lt = mmul(Lt, L, p, pinv);
+  }
+  const uint32_t y = Lt;  // L^k
+  neg ^= static_cast<uint32_t>(a * b) & 1u;
+  int c = b - 1;
+  while (c >= 0 && A[c] == 0u) --c;
+  if (c < 0) return 0u;  // zero remainder with deg B >= 1
+  const int delta = b - c;
+  if (delta != 1) {
+    const uint32_t num = mpow(L, static_cast<uint32_t>(k - 1 + delta), one, p, pinv);
+    const uint32_t den = mpow(y, static_cast<uint32_t>(delta), one, p, pinv);
+    return ures_run(B, A, UresState{b, c, num, den, y, neg}, pc);
+  }
+  // (A, B) <- (B, R~) with scale num = U = den = L^k
+  if (b == 1) {  // R~ is a nonzero constant: Res(B, R~) = R~^1
+    const uint32_t r = mmul(mmul(y, A[0], p, pinv), minv(y, one, p, pinv), p, pinv);
+    return neg ? mneg(r, p) : r;
+  }
+  uint32_t X[N], Y[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    X[j] = (j <= b) ? B[j] : 0u;
+    Y[j] = (j < b) ? A[j] : 0u;
+  }
+  const int b0 = b - 1;
+  if ((b0 & 1) == 0) {  // the chain wants its dividend in X exactly when the step's degree is odd
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const uint32_t t = X[j];
+      X[j] = Y[j];
+      Y[j] = t;
+    }
+  }
+  uint32_t den = y, U = y;
+  bool ok = true;
+  RegChainGen<NMAX - 1, N>::run(X, Y, b0, p, pinv, den, U, ok);
+  if (!ok) return ures_run(B, A, UresState{b, b0, y, y, y, neg}, pc);
+  const uint32_t num = mmul(U, X[0], p, pinv);  // the last remainder (degree 0) is in X
+  const uint32_t r = mmul(num, minv(den, one, p, pinv), p, pinv);
+  return neg ? mneg(r, p) : r;
+}
+
 }  // namespace rsl
 
 namespace rsl {

@@ -184,9 +184,37 @@ int regs_gen_run(const PrimeConst& pc, int m, int n, const uint32_t* A, const ui
   return 0;
 }
 
+// The general-shape one-lane path: the first division on rows, then the
+// branch-free chain in registers (or the general code from the state reached).
+template <int NMAX>
+int regs_long_run(const PrimeConst& pc, int m, int n, const uint32_t* A, const uint32_t* B, uint32_t* out, int* bad) {
+  std::vector<uint32_t> ra(NMAX + 2, 0), rb(NMAX + 2, 0);
+  for (int j = 0; j <= m; ++j) ra[j] = mmul(A[j] % pc.p, pc.r2, pc.p, pc.pinv);
+  for (int j = 0; j <= n; ++j) rb[j] = mmul(B[j] % pc.p, pc.r2, pc.p, pc.pinv);
+  bool bd = false;
+  const uint32_t r = ures_regs_long<NMAX>(Column<1>{ra.data()}, Column<1>{rb.data()}, m, n, pc, &bd);
+  *out = redc(r, pc.p, pc.pinv);
+  *bad = bd;
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
+
+// The general-shape one-lane register form (any m, n <= nmax).
+int hs_ures_regs_long(int nmax, uint32_t p, int m, int n, const uint32_t* A, const uint32_t* B, uint32_t* out,
+                      int* bad) {
+  PrimeConst pc = make_prime_const(p);
+  if (m > nmax || n > nmax || m < 0 || n < 0) return -1;
+  switch (nmax) {
+    case 8: return regs_long_run<8>(pc, m, n, A, B, out, bad);
+    case 16: return regs_long_run<16>(pc, m, n, A, B, out, bad);
+    case 24: return regs_long_run<24>(pc, m, n, A, B, out, bad);
+    case 32: return regs_long_run<32>(pc, m, n, A, B, out, bad);
+    default: return -1;
+  }
+}
 
 // The one-lane branch-free chain with its column restart.
 int hs_ures_regs_gen(int nmax, uint32_t p, int m, int n, const uint32_t* A, const uint32_t* B, uint32_t* out,

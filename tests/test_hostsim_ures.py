@@ -47,6 +47,8 @@ def hs():
     lib.hs_ures_regs2_gen.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p, u32p, u32p,
                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int)]
+    lib.hs_ures_regs_long.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p, u32p, u32p,
+                                      ctypes.POINTER(ctypes.c_int)]
     lib.hs_ures_group.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, u32p, u32p, u32p,
                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     return lib
@@ -60,7 +62,10 @@ def ures(hs, p, A, B, K=1):
     b = (ctypes.c_uint32 * len(B))(*B)
     out = ctypes.c_uint32()
     bad = ctypes.c_int()
-    if isinstance(K, str) and K.startswith("lgen"):
+    if isinstance(K, str) and K.startswith("long"):
+        nmax = int(K[4:])
+        assert hs.hs_ures_regs_long(nmax, p, m, n, a, b, ctypes.byref(out), ctypes.byref(bad)) == 0
+    elif isinstance(K, str) and K.startswith("lgen"):
         nmax = int(K[4:])
         gen = ctypes.c_int()
         assert hs.hs_ures_regs_gen(nmax, p, m, n, a, b, ctypes.byref(out), ctypes.byref(bad), ctypes.byref(gen)) == 0
@@ -252,3 +257,39 @@ def test_branch_free_chain_takes_generic_inputs(hs, nmax):
         assert agree.value == 1
         assert out.value == sylvester_det_mod(A, B, p), (m, n, kind)
         assert gen.value == (1 if kind == 0 else 0) or (kind == 2 and min(m, n) < 2), (m, n, kind)
+
+
+@pytest.mark.parametrize("nmax", [8, 16, 24, 32])
+@pytest.mark.parametrize("seed", range(60))
+def test_general_shapes_register_form(hs, nmax, seed):
+    """The one-lane register form for any shape (first division on rows, then the
+    branch-free chain): long and short A, generic coefficients, planted common
+    factors, remainders that drop by more than one degree, vanishing leading
+    coefficients of either input, and constants."""
+    rng = rng_for(956, 100 * nmax + seed)
+    p = PRIMES[seed % len(PRIMES)]
+    kind = seed % 6
+    m = int(rng.integers(0, nmax + 1))
+    n = int(rng.integers(0, nmax + 1))
+    if kind in (0, 1, 2) and abs(m - n) < 2 and nmax >= 8:  # mostly the long shapes
+        m = min(nmax, n + 2 + int(rng.integers(0, nmax // 2)))
+        if seed % 2:
+            m, n = n, m
+    A = [int(v) for v in rng.integers(1, p, m + 1)]
+    B = [int(v) for v in rng.integers(1, p, n + 1)]
+    if kind == 1 and m >= 2 and n >= 2:  # common factor (y - 7): a zero remainder somewhere
+        A = polymul_mod([p - 7, 1], A[:m], p)
+        B = polymul_mod([p - 7, 1], B[:n], p)
+    if kind == 2:  # small alphabet: remainders that drop by more than one degree
+        alphabet = [0, 0, 1, p - 1]
+        A = [alphabet[int(v)] for v in rng.integers(0, 4, m + 1)]
+        B = [alphabet[int(v)] for v in rng.integers(0, 4, n + 1)]
+        A[-1] = A[-1] or 1
+        B[-1] = B[-1] or 1
+    if kind == 3:
+        A[-1] = 0
+    if kind == 4:
+        B[-1] = 0
+    got, bad = ures(hs, p, A, B, "long%d" % nmax)
+    assert got == sylvester_det_mod(A, B, p), (m, n, kind)
+    assert bad == (A[-1] == 0 or B[-1] == 0)
