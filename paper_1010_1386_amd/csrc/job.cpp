@@ -158,8 +158,8 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     return RSL_EINVAL;
   }
   const bool regs_ok = !(opts && opts->eval_regs < 0);
-  // long_ok: shapes with |m_y - n_y| > 1 have a register form only in the
-  // one-lane evaluation on the matrix cores (ures_regs_long)
+  // long_ok: shapes with |m_y - n_y| > 1 have a register form only with one
+  // lane per pair (ures_regs_long, after Horner or the matrix-core sums)
   auto regn_of = [&](const Plan& P, bool long_ok = false) {
     if (!regs_ok || P.my < 1 || P.ny < 1 || (std::abs(P.my - P.ny) > 1 && !long_ok)) return 0;
     for (int nmax : {8, 16, 24, 32})
@@ -216,7 +216,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     d.evk = 1;
     while (d.evk < evk && std::min(P.my, P.ny) >= 4 * d.evk * 2) d.evk *= 2;
     d.evpb = 64 / d.evk;
-    const bool long_ok = d.evk == 1 && P.rowf <= 32 && P.rowg <= 32 && !(ctx && ctx->eval_horner);
+    const bool long_ok = d.evk == 1;
     d.regn = (d.evk <= 2) ? regn_of(P, long_ok) : 0;
     d.schur = (schur_req && P.my >= 1 && P.ny >= 1 && P.my + P.ny <= kSchurMaxR) ? 1 : 0;
     if (d.schur) {  // one wave per pair, kSchurPts points per block
@@ -813,8 +813,8 @@ int job_upload_copy(rsl_ctx* ctx, Job* J, hipStream_t st, uint8_t* pinned) {
   bind_crt_tables(ctx, J);
   const size_t up = upload_bytes(*J);
   if (up == 0) return RSL_OK;
-  if (J->blob.empty() && J->image) {
-    pinned = J->image;  // bound straight into pinned staging
+  if ((J->blob.empty() && J->image) || J->direct_image) {
+    pinned = J->image;  // bound straight into pinned staging, or sent from pageable memory
   } else {
     if (!pinned) {
       int rc = ensure_staging(ctx, J->up_bytes, J->down_bytes);

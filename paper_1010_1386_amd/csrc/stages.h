@@ -587,8 +587,22 @@ __device__ inline void stage_eval_ures_regs(const DevProblem& P, const DevTables
     }
   }
   bool bad = false;
-  const uint32_t r = ures_regs<NMAX>(X, Y, P.my, P.ny, pc, &bad, Column<64>{cols + lane},
-                                     Column<64>{cols + (NMAX + 1) * 64 + lane});
+  uint32_t r;
+  if (P.my - P.ny > 1 || P.ny - P.my > 1) {
+    // the long shapes: the values go to the lane's own two columns for the
+    // first division (ures_regs_long), the chain then runs in registers
+    Column<64> CA{cols + lane}, CB{cols + (NMAX + 1) * 64 + lane};
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (j <= NMAX) {
+        if (j <= P.my) CA[j] = X[j];
+        if (j <= P.ny) CB[j] = Y[j];
+      }
+    r = ures_regs_long<NMAX>(CA, CB, P.my, P.ny, pc, &bad);
+  } else {
+    r = ures_regs<NMAX>(X, Y, P.my, P.ny, pc, &bad, Column<64>{cols + lane},
+                        Column<64>{cols + (NMAX + 1) * 64 + lane});
+  }
   const bool live = pt <= P.E;
   if (live) {
     const size_t o = static_cast<size_t>(w.slot) * (P.E + 1) + pt;
