@@ -182,6 +182,25 @@ int rsl_query(const rsl_poly *f, const rsl_poly *g, int var, rsl_info *info);
  */
 int rsl_res(rsl_ctx *ctx, const rsl_poly *f, const rsl_poly *g, int var, const rsl_opts *opts,
             rsl_result *out);
+
+/*
+ * rsl_res_static: the same resultant as rsl_res, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It calls no hipMalloc, hipHostMalloc,
+ * hipFree or other allocating device routine: the job is laid out in a fixed
+ * device array of this library (64 MiB, held on every device the library runs
+ * on until the process ends; the context's workspace is not used), and the
+ * inputs and outputs travel through ordinary host memory.  Limits: a problem
+ * whose footprint (rsl_query's footprint_bytes) exceeds 64 MiB gives
+ * RSL_ENOMEM, and so does one that the context's constant tables do not cover
+ * yet (an earlier rsl_res or rsl_batch on the context of a problem with at
+ * least as many primes and points grows them).  Every call on a device shares
+ * that device's array: calls that overlap on one GPU (from any context or
+ * thread) race and must be serialised by the caller.  Arguments, results and
+ * the other errors are those of rsl_res.
+ */
+int rsl_res_static(rsl_ctx *ctx, const rsl_poly *f, const rsl_poly *g, int var, const rsl_opts *opts,
+                   rsl_result *out);
 int rsl_res_y(rsl_ctx *ctx, const rsl_poly *f, const rsl_poly *g, rsl_result *out);
 int rsl_res_x(rsl_ctx *ctx, const rsl_poly *f, const rsl_poly *g, rsl_result *out);
 

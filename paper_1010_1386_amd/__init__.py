@@ -111,6 +111,7 @@ _SIGS = {
     "rsl_ctx_destroy": (ctypes.c_int, [_vp]),
     "rsl_query": (ctypes.c_int, [_P(rsl_poly), _P(rsl_poly), ctypes.c_int, _P(rsl_info)]),
     "rsl_res": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), ctypes.c_int, _P(rsl_opts), _P(rsl_result)]),
+    "rsl_res_static": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), ctypes.c_int, _P(rsl_opts), _P(rsl_result)]),
     "rsl_res_y": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), _P(rsl_result)]),
     "rsl_res_x": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), _P(rsl_result)]),
     "rsl_res_xy": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), _P(rsl_opts), _P(rsl_result), _P(rsl_result)]),
@@ -329,6 +330,22 @@ class Context:
             rc = _lib.rsl_res(self.h, ctypes.byref(pf.c), ctypes.byref(pg.c), v, ctypes.byref(o),
                               ctypes.byref(out.c))
         self._check(rc, "rsl_res")
+        return out.value()
+
+    def res_static(self, f, g, var="y", **opts):
+        """res(f, g, var) through rsl_res_static: no device memory is allocated (the job
+        lives in the library's fixed device array; the context's tables must cover it)."""
+        pf, pg = _as_poly(f), _as_poly(g)
+        v = _var_code(var)
+        info = rsl_info()
+        self._check(_lib.rsl_query(ctypes.byref(pf.c), ctypes.byref(pg.c), v, ctypes.byref(info)), "rsl_query")
+        o = _opts(**opts)
+        lim = info.out_limbs + (1 if o.extra_primes else 0) + o.extra_primes
+        out = _Result(max(info.D, 0), max(1, lim))
+        with self.lock:
+            rc = _lib.rsl_res_static(self.h, ctypes.byref(pf.c), ctypes.byref(pg.c), v, ctypes.byref(o),
+                                     ctypes.byref(out.c))
+        self._check(rc, "rsl_res_static")
         return out.value()
 
     def res_y(self, f, g):

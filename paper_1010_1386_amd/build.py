@@ -21,7 +21,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librsl.so")
 
-SOURCES = ["kernels.hip", "api.cpp", "plan.cpp", "job.cpp", "tune.cpp", "server.cpp", "persistent.hip", "gcd.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "plan.cpp", "job.cpp", "tune.cpp", "server.cpp", "persistent.hip", "gcd.cpp",
+           "noalloc.cpp"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed fp32 forms are never wanted in this integer code

@@ -82,6 +82,7 @@ struct Job {
   std::vector<uint8_t> blob;       // host image of [0, up_bytes) when bound without an external image
   uint8_t* image = nullptr;        // the host image job_bind wrote (blob or the caller's pinned buffer)
   bool with_queue = true;          // the image holds the persistent queue (and is uploaded whole)
+  bool direct_image = false;       // job_upload sends the image itself (pageable host memory), no staging
   int64_t pairs = 0;
   int64_t mulmods = 0;             // algorithmic work of eval + ures: Montgomery products over all pairs
   int64_t mm_sums_mfma = 0;        // of which evaluation sums on the matrix cores
@@ -94,6 +95,9 @@ struct Job {
 // Autotuner cache key of a batch (its shape bucket), from the inputs alone.
 std::string tune_key(int n, const rsl_poly* f, const rsl_poly* g, const int* var);
 std::string tune_key_of(const std::vector<ShapeEst>& est);
+
+// Size of the fixed device array rsl_res_static lays its job out in.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
 
 // Plan every problem (host threads): plans, statuses, live problems.
 int job_plan(int n, const rsl_poly* f, const rsl_poly* g, const int* var, const rsl_opts* opts, Job* J,
