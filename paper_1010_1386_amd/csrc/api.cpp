@@ -95,7 +95,7 @@ int ensure_tables(rsl_ctx* ctx, int np, int kneed, int sneed) {
   std::vector<uint32_t> Tg, invM, Plimb;
   crt_tables(std::vector<uint32_t>(primes.begin(), primes.begin() + gnp), LPg, &Tg, &invM, &Plimb);
 
-  const int64_t sstride = static_cast<int64_t>(align_up(static_cast<size_t>(stir_rowoff(new_s + 1)), 64));
+  const int64_t sstride = static_cast<int64_t>(align_up(static_cast<size_t>(ckpt_rowoff(new_s / kCkpt + 1)), 64));
   auto dmalloc = [&](void** p, size_t bytes) { return hip_check(ctx, hipMalloc(p, bytes), "hipMalloc(tables)"); };
   if ((rc = dmalloc(reinterpret_cast<void**>(&ctx->d_pc), sizeof(PrimeConst) * new_np)) ||
       (rc = dmalloc(reinterpret_cast<void**>(&ctx->d_fact), fact.size() * 4)) ||

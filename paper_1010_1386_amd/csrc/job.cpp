@@ -178,14 +178,16 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       evk = 2;  // one wave can issue only about half a SIMD's rate: give each SIMD two
   }
   // one chunk length K for the basis change of every problem, so that problems
-  // sharing a prime can share the table reads; chunks of at least 128 rows
-  int Kc = 128;
+  // sharing a prime can share the checkpoint rows; a multiple of the checkpoint
+  // spacing, enough chunks for the target number of blocks in flight
+  int Kc = kCkpt;
   {
     int64_t nch = 1;
     if (stir_base < target) nch = (target + stir_base - 1) / std::max<int64_t>(stir_base, 1);
     int dmax = 0;
     for (int k : J->live) dmax = std::max(dmax, J->plans[k].D + 1);
-    Kc = std::max<int>(128, static_cast<int>((dmax + nch - 1) / nch));
+    Kc = std::max<int>(kCkpt, static_cast<int>((dmax + nch - 1) / nch));
+    Kc = (Kc + kCkpt - 1) / kCkpt * kCkpt;  // chunks start at checkpoint rows
   }
   J->crt_ns = 1;
   J->max_np = 0;
@@ -278,6 +280,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     }
 
   // work items, problem by problem (so that each problem's items are contiguous)
+  J->hseg_items.clear();
   for (int li = 0; li < nl; ++li) {
     const Plan& P = J->plans[J->live[li]];
     const DevProblem& d = J->dev[li];
@@ -305,12 +308,17 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       for (int b = 0; b < blocks_of(P.D + 1, 256); ++b)
         for (int ch = 0; ch < d.ncchunk; ++ch)
           if (ch * d.cchunk <= std::min(P.D, b * 256 + 255)) J->items[kStageConv].push_back({li, sl, b, ch});
+    // basis change: blocks of 256 columns
     for (int sl = 0; sl < P.np; ++sl)
       for (int b = 0; b < blocks_of(P.D + 1, 256); ++b)
         for (int ch = 0; ch < d.nchunk; ++ch) {
           const int ke = std::min(P.D, (ch + 1) * d.kchunk - 1);
           if (ke >= b * 256) J->items[kStageStir].push_back({li, sl, b, ch});
         }
+    L.hseg_begin = static_cast<int>(J->hseg_items.size());
+    for (int sl = 0; sl < P.np; ++sl)
+      for (int b = 0; b < blocks_of(P.D + 1, kHsegRows); ++b) J->hseg_items.push_back({li, sl, b, 0});
+    L.hseg_end = static_cast<int>(J->hseg_items.size());
     // gapped interpolation is possible only with a non-constant leading
     // coefficient (bad points) or a shifted origin
     if (P.origin != 0 || (!P.formal && P.s > 0))
@@ -440,7 +448,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       for (int sl = 0; sl < P.np; ++sl) by_prime[P.pidx[sl]].push_back(StirMember{li, sl});
     }
     int gmax = kStirGroupMax;
-    while (gmax > 1 && stir_group_lds_words(Kc, gmax) > kLdsWords) --gmax;
+    while (gmax > 1 && stir_group_lds_words(gmax, 256) > kLdsWords) --gmax;
     for (const auto& kv : by_prime) {
       const std::vector<StirMember>& mem = kv.second;
       for (size_t b = 0; b < mem.size(); b += gmax) {
@@ -452,11 +460,11 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
         }
         const int gi = static_cast<int>(J->sgroups.size());
         J->sgroups.push_back(G);
-        J->sg_lds = std::max<size_t>(J->sg_lds, static_cast<size_t>(stir_group_lds_words(Kc, G.count)) * 4);
-        for (int jb = 0; jb < blocks_of(G.maxD + 1, kStirGroupCols); ++jb)
+        J->sg_lds = std::max<size_t>(J->sg_lds, static_cast<size_t>(stir_group_lds_words(kStirGroupMax, 256)) * 4);
+        for (int jb = 0; jb < blocks_of(G.maxD + 1, 256); ++jb)
           for (int ch = 0; ch * Kc <= G.maxD; ++ch) {
             const int ke = std::min(G.maxD, (ch + 1) * Kc - 1);
-            if (ke >= jb * kStirGroupCols) J->sg_items.push_back({gi, -1, jb, ch});
+            if (ke >= jb * 256) J->sg_items.push_back({gi, -1, jb, ch});
           }
       }
     }
@@ -479,6 +487,8 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   o = align_up(o + sizeof(StirMember) * J->smembers.size(), A);
   J->sgi_off = o;
   o = align_up(o + sizeof(WorkItem) * J->sg_items.size(), A);
+  J->hseg_off = o;
+  o = align_up(o + sizeof(WorkItem) * J->hseg_items.size(), A);
   for (int pass = 0; pass < 3; ++pass) {
     J->wide_off[pass] = o;
     o = align_up(o + sizeof(WorkItem) * J->wide_items[pass].size(), A);
@@ -530,7 +540,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       const Plan& P = J->plans[J->live[li]];
       const DevProblem& d = J->dev[li];
       const int64_t ne = blocks_of(P.E + 1, d.evpb), nc = blocks_of(P.D + 1, 64);
-      const int64_t ns = nc * d.nchunk;
+      const int64_t ns = blocks_of(P.D + 1, 64) * d.nchunk;
       cap += static_cast<int64_t>(P.np) * (1 + ne + std::max<int64_t>(nc * d.ncchunk + ns, 1));
       const int64_t ncrt = blocks_of(P.D + 1, kCrtPerTask);
       cap += ncrt;
@@ -581,6 +591,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     L.zbad = o;  o = align_up(o + np * (P.E + 1), A);
     L.aconv = o; o = align_up(o + static_cast<size_t>(d.ncchunk) * np * (P.D + 1) * 8, A);
     L.cpart = o; o = align_up(o + static_cast<size_t>(d.nchunk) * np * (P.D + 1) * 8, A);
+    L.hseg = o;  o = align_up(o + np * align_up(static_cast<size_t>(P.D + 1), kCkpt) * 4, A);
     L.wT = L.wq = L.wS = 0;
     if (P.wide) {
       L.wT = o; o = align_up(o + static_cast<size_t>(d.wdpad) * d.wnpad * 4, A);
@@ -599,7 +610,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     auto up = [&](int s, size_t words) { J->stage_lds[s] = std::max(J->stage_lds[s], words * 4); };
     up(kStageEval, eval_stage_lds_words(d));
     up(kStageConv, static_cast<size_t>(std::min(d.cchunk, d.D + 1)) + std::min(d.D + 1, d.cchunk + 256));
-    up(kStageStir, d.kchunk);
+    up(kStageStir, std::max(basis_lds_words(1, 256, 0), kHsegRows));
     if (J->lay[li].item_end[kStageNewton] > J->lay[li].item_begin[kStageNewton]) up(kStageNewton, newton_lds_words(d, 1024));
     if (!d.wide) up(kStageCrt, crt_lds_words(d, J->crt_ns, crt_block_waves(J->crt_ns)));
     if (d.L_in > 2) up(kStageReduce, reduce_ml_lds_words());
@@ -617,7 +628,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     const DevProblem& d = J->dev[li];
     size_t w = std::max(eval_group_lds_words(d, d.evk), eval_lds_words(d));  // no register form here
     w = std::max<size_t>(w, static_cast<size_t>(std::min(d.cchunk, d.D + 1)) + std::min(d.D + 1, d.cchunk + 64));
-    w = std::max<size_t>(w, d.kchunk);
+    w = std::max<size_t>(w, basis_lds_words(1, 64, d.kchunk));
     if (J->lay[li].item_end[kStageNewton] > J->lay[li].item_begin[kStageNewton])
       w = std::max<size_t>(w, newton_lds_words(d, 64));
     if (!d.wide) w = std::max<size_t>(w, crt_lds_words(d, J->crt_ns, 1));
@@ -732,6 +743,8 @@ void job_bind(Job* J, uint8_t* base, uint8_t* image, bool with_queue) {
     d.zbad = base + L.zbad;
     d.aconv = reinterpret_cast<uint64_t*>(base + L.aconv);
     d.cpart = reinterpret_cast<uint64_t*>(base + L.cpart);
+    d.hseg = reinterpret_cast<uint32_t*>(base + L.hseg);
+    d.hstride = static_cast<int>(align_up(static_cast<size_t>(P.D + 1), kCkpt));
     d.out = reinterpret_cast<uint32_t*>(base + L.out);
     d.status = reinterpret_cast<int*>(base + L.status);
   });
@@ -778,6 +791,8 @@ void job_bind(Job* J, uint8_t* base, uint8_t* image, bool with_queue) {
   for (int pass = 0; pass < 3; ++pass)
     if (!J->wide_items[pass].empty())
       std::memcpy(blob + J->wide_off[pass], J->wide_items[pass].data(), sizeof(WorkItem) * J->wide_items[pass].size());
+  if (!J->hseg_items.empty())
+    std::memcpy(blob + J->hseg_off, J->hseg_items.data(), sizeof(WorkItem) * J->hseg_items.size());
   if (!J->sgroups.empty()) {
     std::memcpy(blob + J->sg_off, J->sgroups.data(), sizeof(StirGroup) * J->sgroups.size());
     std::memcpy(blob + J->sm_off, J->smembers.data(), sizeof(StirMember) * J->smembers.size());
@@ -866,6 +881,7 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
   const DevProblem* probs = reinterpret_cast<const DevProblem*>(J->base + J->probs_off);
   auto items = [&](int s) { return reinterpret_cast<const WorkItem*>(J->base + J->items_off[s]); };
   auto wide = [&](int pass) { return reinterpret_cast<const WorkItem*>(J->base + J->wide_off[pass]); };
+  const WorkItem* hseg_items = reinterpret_cast<const WorkItem*>(J->base + J->hseg_off);
   int rc;
   if (mode == RSL_PLAIN) {
     for (size_t li = 0; li < J->live.size(); ++li) {
@@ -875,6 +891,10 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
       const int ns = J->crt_ns;
       for (int s = 0; s < kNumStages; ++s) {
         const int cnt = L.item_end[s] - L.item_begin[s];
+        if (s == kStageStir &&
+            (rc = hip_check(ctx, launch_hseg(probs, hseg_items + L.hseg_begin, L.hseg_end - L.hseg_begin, T, st),
+                            "launch")))
+          return rc;
         const hipError_t e = (s == kStageEval)
             ? launch_eval(eval_variant(J->dev[li]), probs, items(s) + L.item_begin[s], cnt, J->stage_lds[s], T, st)
             : launch_stage(s, probs, items(s) + L.item_begin[s], cnt, J->stage_lds[s], ns, T, st);
@@ -939,6 +959,9 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
           return rc;
       continue;
     }
+    if (s == kStageStir &&
+        (rc = hip_check(ctx, launch_hseg(probs, hseg_items, static_cast<int>(J->hseg_items.size()), T, st), "launch")))
+      return rc;
     if (s == kStageStir && !J->sg_items.empty()) {
       if ((rc = hip_check(ctx, launch_stir_group(probs, reinterpret_cast<const StirGroup*>(J->base + J->sg_off),
                                                  reinterpret_cast<const StirMember*>(J->base + J->sm_off),

@@ -23,7 +23,8 @@ namespace rsl {
 struct ProbLayout {
   // offsets from the job base
   size_t coeff, gdeg, pidx, Hm, NH, Tg, invM, Plimb, Mi, wdir, rinv, negM, Mw, NHM, wMd, status;
-  size_t out, resid, dig, zval, zbad, aconv, cpart, wT, wq, wS;
+  size_t out, resid, dig, zval, zbad, aconv, cpart, hseg, wT, wq, wS;
+  int hseg_begin, hseg_end;        // range of Job::hseg_items
   int L_in;
   bool crt_own;  // this problem's layout holds the CRT constant block it shares
   int item_begin[kNumStages], item_end[kNumStages];
@@ -51,6 +52,9 @@ struct Job {
   std::vector<StirMember> smembers;
   std::vector<WorkItem> sg_items;
   size_t sg_off = 0, sm_off = 0, sgi_off = 0, sg_lds = 0;
+  // segment polynomials of the basis change (before the stir stage)
+  std::vector<WorkItem> hseg_items;
+  size_t hseg_off = 0;
   // wide CRT (problems with more primes than the per-lane slots cover): items of
   // its three passes
   std::vector<WorkItem> wide_items[3];

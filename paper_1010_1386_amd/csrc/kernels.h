@@ -31,6 +31,8 @@ hipError_t launch_stir_group(const DevProblem* probs, const StirGroup* groups, c
                              const WorkItem* items, int nitems, size_t lds, const DevTables& T, hipStream_t st);
 
 // Stirling numbers of the first kind mod p_g for g in [g0, g0+count), rows 0..scap.
+// Segment polynomials of the basis change (stage_interp_hseg), before the stir stage.
+hipError_t launch_hseg(const DevProblem* probs, const WorkItem* items, int nitems, const DevTables& T, hipStream_t st);
 hipError_t launch_stirling_build(uint32_t* stir, int64_t sstride, const PrimeConst* pcs, int g0,
                                  int count, int scap, hipStream_t st);
 

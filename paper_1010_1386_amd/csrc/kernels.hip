@@ -85,7 +85,19 @@ __global__ __launch_bounds__(256) void k_interp_conv(const DevProblem* probs, co
 __global__ __launch_bounds__(256) void k_interp_stir(const DevProblem* probs, const WorkItem* items, DevTables T) {
   extern __shared__ uint32_t lds[];
   const WorkItem w = items[blockIdx.x];
-  stage_interp_stir(probs[w.prob], T, w, lds);
+  stage_interp_stir<true>(probs[w.prob], T, w, lds);
+}
+
+__global__ __launch_bounds__(kHsegRows) void k_interp_hseg(const DevProblem* probs, const WorkItem* items, DevTables T) {
+  __shared__ uint32_t lds[kHsegRows];
+  const WorkItem w = items[blockIdx.x];
+  stage_interp_hseg(probs[w.prob], T, w, lds);
+}
+
+hipError_t launch_hseg(const DevProblem* probs, const WorkItem* items, int nitems, const DevTables& T, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_interp_hseg, dim3(nitems), dim3(kHsegRows), 0, st, probs, items, T);
+  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(1024) void k_interp_newton(const DevProblem* probs, const WorkItem* items, DevTables T) {
@@ -190,13 +202,14 @@ __global__ __launch_bounds__(1024) void k_stirling_build(uint32_t* stir, int64_t
   __syncthreads();
   for (int k = 0; k < scap; ++k) {
     const uint32_t kt = mmul(static_cast<uint32_t>(k), pc.r2, pc.p, pc.pinv);
-    uint32_t* row = S + stir_rowoff(k + 1);
+    const bool keep = ((k + 1) % kCkpt) == 0;  // a checkpoint row
+    uint32_t* row = S + ckpt_rowoff((k + 1) / kCkpt);
     for (int j = threadIdx.x; j <= k + 1; j += 1024) {
       const uint32_t left = (j > 0) ? cur[j - 1] : 0u;
       const uint32_t mid = (j <= k) ? cur[j] : 0u;
       const uint32_t v = msubm(left, mmul(mid, kt, pc.p, pc.pinv), pc.p);
       nxt[j] = v;
-      row[j] = v;
+      if (keep) row[j] = v;
     }
     __syncthreads();
     uint32_t* t = cur; cur = nxt; nxt = t;
@@ -216,7 +229,7 @@ __global__ __launch_bounds__(256) void k_interp_stir_group(const DevProblem* pro
 hipError_t launch_stir_group(const DevProblem* probs, const StirGroup* groups, const StirMember* members,
                              const WorkItem* items, int nitems, size_t lds, const DevTables& T, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_interp_stir_group, dim3(nitems), dim3(64 * kStirGroupWaves), lds, st, probs, groups, members,
+  hipLaunchKernelGGL(k_interp_stir_group, dim3(nitems), dim3(256), lds, st, probs, groups, members,
                      items, T);
   return hipGetLastError();
 }

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(64) void k_persistent(const DevProblem* probs, Queu
         break;
       case kTaskEval: stage_eval<false>(P, T, w, lds); break;
       case kTaskConv: stage_interp_conv(P, T, w, lds); break;
-      case kTaskStir: stage_interp_stir(P, T, w, lds); break;
+      case kTaskStir: stage_interp_stir<false>(P, T, w, lds); break;
       case kTaskNewton: stage_interp_newton(P, T, w, lds); break;
       case kTaskCrt: stage_crt<NS>(P, T, w, lds, kCrtPerTask); break;
       default: break;
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(64) void k_persistent(const DevProblem* probs, Queu
         }
         case kTaskConv:
           if (atomicSub(&C->conv_left[t.slot], 1) == 1) {
-            const int nj = (P.D + 64) / 64;
+            const int nj = (P.D + 64) / 64;  // one wave: 64 columns per task
             enqueue(Q, probs, nj * P.nchunk, [&](int i) { return mk(kTaskStir, prob, t.slot, i / P.nchunk, i % P.nchunk); });
           }
           break;

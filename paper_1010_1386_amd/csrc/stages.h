@@ -1116,12 +1116,6 @@ __device__ inline bool fast_prime(const DevProblem& P, int slot) {
   return __builtin_amdgcn_readfirstlane(P.status[2 + P.np + slot]) == 0;
 }
 
-// Column j of Stirling rows k..k+7 (zero above the diagonal j <= k + u).
-__device__ __forceinline__ void stir_rows8(const uint32_t* S, int k, int j, uint32_t* v) {
-#pragma unroll
-  for (int u = 0; u < 8; ++u) v[u] = (j <= k + u) ? S[stir_rowoff(k + u) + j] : 0u;
-}
-
 // Newton forward differences at 0..D as a convolution, one i-chunk of it:
 //   a_k = Delta^k z_0 / k! = sum_{i<=k} (z_i / i!) ((-1)^(k-i) / (k-i)!)
 // Each thread owns one k; the chunk's partial sum is stored unreduced
@@ -1187,169 +1181,222 @@ __device__ inline void stage_interp_conv(const DevProblem& P, const DevTables& T
 
 // Falling-factorial basis -> monomials, one k-chunk of the sum
 //   c_j = sum_{k >= j} a_k s(k, j)
-// written as a partial sum (REDC of the sum over chunks is c_j).
+// written as partial sums per chunk (REDC of the sum over the chunks that
+// reach j is c_j).  The context keeps only every kCkpt-th row of the Stirling
+// triangle.  The rows k0 .. k0 + kCkpt - 1 after a checkpoint row k0 follow
+// from it by x^(k0 + t) = x^(k0) (x - k0)^(t) (falling factorials), so their
+// contribution to c_j is a short convolution with that row:
+//   sum_t a_{k0+t} s(k0 + t, j) = sum_{i < kCkpt} h_i s(k0, j - i),
+// h = the monomial coefficients of sum_t a_{k0+t} (x - k0)^(t).  A segment's h
+// is expanded once by Horner's rule (h <- h (x - k0 - t) + a_{k0+t}, one
+// coefficient per lane of a half wave) into `hseg`; the basis change then
+// streams only checkpoint rows: one column per thread, the row's window and
+// the members' h in LDS.
+
+// a_k = REDC(sum of the convolution chunks that reach k) for k in [kb, ke]
+// (0 beyond the problem's degree bound), into dst[k - kb].
+__device__ inline void load_newton_coeffs(const DevProblem& P, int slot, const PrimeConst& pc, int kb, int ke,
+                                          uint32_t* dst) {
+  const uint32_t p = pc.p;
+  const uint64_t* ap = P.aconv + static_cast<size_t>(slot) * (P.D + 1);
+  const size_t astride = static_cast<size_t>(P.np) * (P.D + 1);
+  for (int k = kb + static_cast<int>(threadIdx.x); k <= ke; k += blockDim.x) {
+    uint32_t v = 0u;
+    if (k <= P.D) {
+      const int nch = k / P.cchunk + 1;
+      uint64_t q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) q[u] = ap[(u < nch ? u : nch - 1) * astride + k];
+      uint64_t sacc = 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (u < nch) sacc = add_fold(sacc, q[u], p);
+      for (int ch = 8; ch < nch; ++ch) sacc = add_fold(sacc, ap[ch * astride + k], p);
+      v = redc(sacc, p, pc.pinv);
+    }
+    dst[k - kb] = v;
+  }
+}
+
+// h of the segment starting at k0 (rows k0 .. min(k0 + kCkpt - 1, ke), a_k at
+// a[k - kb]) by one half wave: lane i of the half gets h_i.
+__device__ inline uint32_t segment_h(const uint32_t* a, int kb, int k0, int ke, const PrimeConst& pc) {
+  const uint32_t p = pc.p, pinv = pc.pinv;
+  const int i = threadIdx.x & (kCkpt - 1);
+  uint32_t h = 0u;
+  uint32_t ct = mmul(static_cast<uint32_t>(k0 + kCkpt - 1), pc.r2, p, pinv);  // (k0 + t) R mod p
+  for (int t = kCkpt - 1; t >= 0; --t) {
+    const int k = k0 + t;
+    const uint32_t av = (k <= ke) ? a[k - kb] : 0u;
+    const uint32_t prev = static_cast<uint32_t>(__shfl_up(static_cast<int>(h), 1, kCkpt));
+    h = msubm(i > 0 ? prev : 0u, mmul(h, ct, p, pinv), p);
+    if (i == 0) h = maddm(h, av, p);
+    ct = msubm(ct, pc.r1, p);
+  }
+  return h;
+}
+
+// The segments' h of one problem and prime: item (problem, slot, block of
+// kHsegRows rows), one segment per half wave.
+constexpr int kHsegRows = 256;
+__device__ inline void stage_interp_hseg(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
+  if (!fast_prime(P, w.slot)) return;
+  const PrimeConst pc = T.pc[P.pidx[w.slot]];
+  const int kb = w.blk * kHsegRows;
+  const int ke = (kb + kHsegRows - 1 < P.D) ? kb + kHsegRows - 1 : P.D;
+  load_newton_coeffs(P, w.slot, pc, kb, ke, lds);
+  __syncthreads();
+  const int k0 = kb + kCkpt * (static_cast<int>(threadIdx.x) / kCkpt);
+  if (k0 > ke) return;
+  const uint32_t h = segment_h(lds, kb, k0, ke, pc);
+  P.hseg[static_cast<size_t>(w.slot) * P.hstride + k0 + (threadIdx.x & (kCkpt - 1))] = h;
+}
+
+// Rows [k1, ke] (k1 a multiple of kCkpt) into the partial sums acc[m] of
+// column j0 + threadIdx.x for G members; the block's threads are its columns.
+// h of member m for the segment at k0: hsrc[m][k0 + i] (HG), or expanded here
+// from a_k at lds_a[k - kb] (G = 1).  LDS: lh (G kCkpt words), lw (blockDim + kCkpt - 1).
+template <int GM, bool HG>
+__device__ inline void basis_block(const uint32_t* S, int j0, int k1, int ke, int kb, int G,
+                                   const uint32_t* const* hsrc, const int* hmax, const uint32_t* lds_a,
+                                   const PrimeConst& pc, uint32_t* lh, uint32_t* lw, uint64_t (&acc)[GM]) {
+  const int nt = blockDim.x, tid = threadIdx.x;
+  const uint32_t p = pc.p;
+  // the next segment's h (HG: one value per thread, nt >= GM kCkpt) and row
+  // window (two values per thread, nt >= kCkpt - 1) are loaded into registers
+  // while the current segment is convolved
+  uint32_t nh = 0u, nw0 = 0u, nw1 = 0u;
+  auto fetch = [&](int k0) {
+    if constexpr (HG) {
+      const int m = tid / kCkpt, u = tid & (kCkpt - 1);
+      nh = 0u;
+#pragma unroll
+      for (int mm = 0; mm < GM; ++mm)
+        if (mm == m && mm < G && k0 <= hmax[mm]) nh = hsrc[mm][k0 + u];  // beyond a member's bound: h = 0
+    }
+    const uint32_t* row = S + ckpt_rowoff(k0 / kCkpt);
+    const int ja = j0 - (kCkpt - 1) + tid, jb = ja + nt;
+    nw0 = (ja >= 0 && ja <= k0) ? row[ja] : 0u;
+    nw1 = (tid < kCkpt - 1 && jb >= 0 && jb <= k0) ? row[jb] : 0u;
+  };
+  if (k1 <= ke) fetch(k1);
+  for (int k0 = k1; k0 <= ke; k0 += kCkpt) {
+    if constexpr (HG) {
+      if (tid < GM * kCkpt) lh[tid] = nh;
+    } else {
+      if (tid < kCkpt) lh[tid] = segment_h(lds_a, kb, k0, ke, pc);
+    }
+    lw[tid] = nw0;
+    if (tid < kCkpt - 1) lw[nt + tid] = nw1;
+    __syncthreads();
+    if (k0 + kCkpt <= ke) fetch(k0 + kCkpt);
+#pragma unroll 8
+    for (int i = 0; i < kCkpt; ++i) {
+      const uint32_t w = lw[tid + kCkpt - 1 - i];  // s(k0, j - i)
+#pragma unroll
+      for (int m = 0; m < GM; ++m)
+        if (m < G) acc[m] = mac_fold(acc[m], lh[m * kCkpt + i], w, p);
+    }
+    __syncthreads();  // the next segment overwrites lh and lw
+  }
+}
+
+// LDS words of a basis-change block: members' h, the row window, and (when h
+// is expanded in the block) the chunk's a_k.
+__host__ __device__ inline int basis_lds_words(int members, int nthreads, int K_or_0) {
+  return kCkpt * members + nthreads + kCkpt - 1 + K_or_0;
+}
+
+// One problem: item (problem, slot, block of blockDim columns, chunk).  With
+// h_global the segments' h come from hseg (staged and plain schedules, after
+// stage_interp_hseg); otherwise the block expands them itself (the persistent
+// schedule's single-wave tasks).
+template <bool h_global>
 __device__ inline void stage_interp_stir(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
   if (!fast_prime(P, w.slot)) return;
   const int g = P.pidx[w.slot];
   const PrimeConst pc = T.pc[g];
-  const uint32_t p = pc.p;
   const int nt = blockDim.x;
-  const int j0 = w.blk * nt;
-  const int j = j0 + threadIdx.x;
   const int kb = w.sub * P.kchunk;
   const int ke = (kb + P.kchunk - 1 < P.D) ? kb + P.kchunk - 1 : P.D;
-  const int ks = kb > j0 ? kb : j0;
-  // a_k = REDC(sum of the convolution chunks that reach k)
-  const uint64_t* ap = P.aconv + static_cast<size_t>(w.slot) * (P.D + 1);
-  const size_t astride = static_cast<size_t>(P.np) * (P.D + 1);
-  for (int k = ks + threadIdx.x; k <= ke; k += nt) {
-    const int nch = k / P.cchunk + 1;
-    uint64_t q[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) q[u] = ap[(u < nch ? u : nch - 1) * astride + k];
-    uint64_t s = 0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (u < nch) s = add_fold(s, q[u], p);
-    for (int ch = 8; ch < nch; ++ch) s = add_fold(s, ap[ch * astride + k], p);
-    lds[k - ks] = redc(s, p, pc.pinv);
+  const int j0 = w.blk * nt;
+  uint32_t* lh = lds;
+  uint32_t* lw = lds + kCkpt;
+  uint32_t* la = lw + nt + kCkpt - 1;
+  if constexpr (!h_global) {
+    load_newton_coeffs(P, w.slot, pc, kb, ke, la);
+    __syncthreads();
   }
-  __syncthreads();
-  const uint32_t* S = T.stir + static_cast<int64_t>(g) * T.sstride;
-  uint64_t c0 = 0, c1 = 0;
-  int k = ks;
-  // eight table rows per pass: their loads are in flight together (the
-  // table streams from memory; j <= k masks the upper triangle)
-  const int jc = j <= P.D ? j : P.D;
-  uint32_t sv[8];
-  if (k + 7 <= ke) stir_rows8(S, k, jc, sv);
-  for (; k + 7 <= ke; k += 8) {
-    uint32_t nv[8];
-    if (k + 15 <= ke) stir_rows8(S, k + 8, jc, nv);
-#pragma unroll
-    for (int u = 0; u < 8; u += 2) {
-      c0 = mac_fold(c0, lds[k + u - ks], sv[u], p);
-      c1 = mac_fold(c1, lds[k + u + 1 - ks], sv[u + 1], p);
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) sv[u] = nv[u];
-  }
-  for (; k <= ke; ++k) {
-    const int64_t o = stir_rowoff(k);
-    if (j <= k) c0 = mac_fold(c0, lds[k - ks], S[o + j], p);
-  }
-  if (j <= P.D) P.cpart[(static_cast<size_t>(w.sub) * P.np + w.slot) * (P.D + 1) + j] = add_fold(c0, c1, p);
+  if (j0 > ke || j0 > P.D) return;  // block-uniform: no row of the chunk reaches these columns
+  // rows below j0 contribute nothing to them: start at j0's checkpoint
+  const int jc = (j0 / kCkpt) * kCkpt;
+  const int k1 = kb > jc ? kb : jc;
+  uint64_t acc[1] = {0u};
+  const uint32_t* hrow = P.hseg + static_cast<size_t>(w.slot) * P.hstride;
+  const int hmax[1] = {P.D};
+  basis_block<1, h_global>(T.stir + static_cast<int64_t>(g) * T.sstride, j0, k1, ke, kb, 1, &hrow, hmax, la, pc, lh,
+                           lw, acc);
+  const int j = j0 + static_cast<int>(threadIdx.x);
+  if (j <= P.D) P.cpart[(static_cast<size_t>(w.sub) * P.np + w.slot) * (P.D + 1) + j] = acc[0];
 }
 
 // The same basis change for every member of a prime group (problems that use
-// one prime): each table row is read once and multiplied into every member's
-// partial sums.  Item: (group, -, 64-column block, k-chunk); all members share
-// the chunk length (kchunk) and their rows k > D_m contribute zeros.  The four
-// waves of a block split the chunk's rows into four runs (short dependent
-// chains of table loads) and their partial sums are added in LDS.
-constexpr int kStirGroupCols = 64;
-constexpr int kStirGroupWaves = 4;
-__host__ __device__ inline int stir_group_lds_words(int K, int count) {
-  return count * K + 1 + kStirGroupWaves * count * kStirGroupCols * 2;
+// one prime): each checkpoint row is read once and convolved into every
+// member's partial sums.  Item: (group, -, block of blockDim columns, k-chunk);
+// all members share the chunk length (kchunk) and their rows k > D_m have h = 0.
+__host__ __device__ inline int stir_group_lds_words(int count, int nthreads) {
+  return basis_lds_words(count, nthreads, 0);
 }
 
 __device__ inline void stage_interp_stir_group(const DevProblem* probs, const StirGroup* groups,
                                                const StirMember* members, const DevTables& T, const WorkItem& w,
                                                uint32_t* lds) {
   const StirGroup G = groups[w.prob];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int j0 = w.blk * kStirGroupCols;
-  const int j = j0 + lane;
+  const int nt = blockDim.x;
+  const int j0 = w.blk * nt;
   const PrimeConst pc = T.pc[G.g];
-  const uint32_t p = pc.p;
   const int K = probs[members[G.first].prob].kchunk;
   const int kb = w.sub * K;
-  const int ks = kb > j0 ? kb : j0;
   const int ke = (kb + K - 1 < G.maxD) ? kb + K - 1 : G.maxD;
-  if (ks > ke) return;
-  // per member: its a_k for k in [ks, ke] (0 beyond its degree bound), or inactive
-  bool act[kStirGroupMax];
+  if (j0 > ke) return;
+  // the active members (degree bound reaching the chunk and the block,
+  // consecutive points), compacted
+  int na = 0, which[kStirGroupMax];
+  for (int m = 0; m < G.count; ++m) {
+    const StirMember M = members[G.first + m];
+    const DevProblem& P = probs[M.prob];
+    if (P.D >= kb && P.D >= j0 && fast_prime(P, M.slot)) which[na++] = m;
+  }
+  if (na == 0) return;  // block-uniform
+  const uint32_t* hsrc[kStirGroupMax];
+  int hmax[kStirGroupMax];
 #pragma unroll
-  for (int m = 0; m < kStirGroupMax; ++m) {
-    act[m] = false;
-    if (m < G.count) {
-      const StirMember M = members[G.first + m];
-      const DevProblem& P = probs[M.prob];
-      act[m] = P.D >= ks && fast_prime(P, M.slot);
-      if (!act[m]) continue;
-      uint32_t* am = lds + m * K;
-      const uint64_t* ap = P.aconv + static_cast<size_t>(M.slot) * (P.D + 1);
-      const size_t astride = static_cast<size_t>(P.np) * (P.D + 1);
-      for (int k = ks + static_cast<int>(threadIdx.x); k <= ke; k += blockDim.x) {
-        uint32_t v = 0u;
-        if (k <= P.D) {
-          const int nch = k / P.cchunk + 1;
-          uint64_t q[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) q[u] = ap[(u < nch ? u : nch - 1) * astride + k];
-          uint64_t sacc = 0;
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (u < nch) sacc = add_fold(sacc, q[u], p);
-          for (int ch = 8; ch < nch; ++ch) sacc = add_fold(sacc, ap[ch * astride + k], p);
-          v = redc(sacc, p, pc.pinv);
-        }
-        am[k - ks] = v;
-      }
+  for (int q = 0; q < kStirGroupMax; ++q) {
+    hsrc[q] = nullptr;
+    hmax[q] = -1;
+    if (q < na) {
+      const StirMember M = members[G.first + which[q]];
+      hsrc[q] = probs[M.prob].hseg + static_cast<size_t>(M.slot) * probs[M.prob].hstride;
+      hmax[q] = probs[M.prob].D;
     }
   }
-  __syncthreads();
-  // this wave's run of rows
-  const int nk = ke - ks + 1;
-  const int per = (nk + kStirGroupWaves - 1) / kStirGroupWaves;
-  const int rb = ks + wave * per;
-  const int re = (rb + per - 1 < ke) ? rb + per - 1 : ke;
-  const uint32_t* S = T.stir + static_cast<int64_t>(G.g) * T.sstride;
+  const int jc = (j0 / kCkpt) * kCkpt;
+  const int k1 = kb > jc ? kb : jc;
   uint64_t acc[kStirGroupMax];
 #pragma unroll
   for (int m = 0; m < kStirGroupMax; ++m) acc[m] = 0u;
-  const int jc = j <= G.maxD ? j : G.maxD;
-  int k = rb;
-  uint32_t sv[8];
-  if (k + 7 <= re) stir_rows8(S, k, jc, sv);
-  for (; k + 7 <= re; k += 8) {
-    uint32_t nv[8];
-    if (k + 15 <= re) stir_rows8(S, k + 8, jc, nv);
+  // rows k > D_m of a member are zero in its h (its a_k vanish there), and the
+  // h of a member is read only for segments at or below its degree bound
+  basis_block<kStirGroupMax, true>(T.stir + static_cast<int64_t>(G.g) * T.sstride, j0, k1, ke, kb, na, hsrc, hmax,
+                                   nullptr, pc, lds, lds + kCkpt * kStirGroupMax, acc);
 #pragma unroll
-    for (int m = 0; m < kStirGroupMax; ++m)
-      if (act[m]) {
-        const uint32_t* am = lds + m * K + (k - ks);
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc[m] = mac_fold(acc[m], am[u], sv[u], p);
-      }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) sv[u] = nv[u];
-  }
-  for (; k <= re; ++k) {
-    const int64_t o = stir_rowoff(k);
-    const uint32_t s1 = (jc <= k) ? S[o + jc] : 0u;
-#pragma unroll
-    for (int m = 0; m < kStirGroupMax; ++m)
-      if (act[m]) acc[m] = mac_fold(acc[m], lds[m * K + (k - ks)], s1, p);
-  }
-  // add the four waves' partial sums
-  uint64_t* red = reinterpret_cast<uint64_t*>(lds + G.count * K + ((G.count * K) & 1));
-#pragma unroll
-  for (int m = 0; m < kStirGroupMax; ++m)
-    if (m < G.count) red[(wave * G.count + m) * kStirGroupCols + lane] = acc[m];
-  __syncthreads();
-  if (wave == 0) {
-#pragma unroll
-    for (int m = 0; m < kStirGroupMax; ++m)
-      if (act[m]) {
-        uint64_t t = red[m * kStirGroupCols + lane];
-#pragma unroll
-        for (int ww = 1; ww < kStirGroupWaves; ++ww) t = add_fold(t, red[(ww * G.count + m) * kStirGroupCols + lane], p);
-        const StirMember M = members[G.first + m];
-        const DevProblem& P = probs[M.prob];
-        if (j <= P.D) P.cpart[(static_cast<size_t>(w.sub) * P.np + M.slot) * (P.D + 1) + j] = t;
-      }
-  }
+  for (int q = 0; q < kStirGroupMax; ++q)
+    if (q < na) {
+      const StirMember M = members[G.first + which[q]];
+      const DevProblem& P = probs[M.prob];
+      const int j = j0 + static_cast<int>(threadIdx.x);
+      if (j <= P.D) P.cpart[(static_cast<size_t>(w.sub) * P.np + M.slot) * (P.D + 1) + j] = acc[q];
+    }
 }
 
 // LDS words of the gapped-interpolation block.
