@@ -121,6 +121,9 @@ typedef struct {
   int32_t my, ny;       /* actual degrees in the eliminated variable */
   int32_t bad_primes;   /* primes skipped because they divide a leading coefficient */
   size_t footprint_bytes; /* device workspace one rsl_res call needs */
+  size_t table_bytes;     /* bytes of the context's constant tables that cover this problem
+                             (primes, factorials, checkpoint rows of the Stirling triangle,
+                             CRT constants), rounded up as the context grows them */
 } rsl_info;
 
 /* Per-call options (zero-initialise for the defaults). */
@@ -162,15 +165,24 @@ typedef struct {
 typedef struct rsl_ctx rsl_ctx;
 
 /*
- * Create a context on HIP device `device`.  d_workspace/ws_bytes: device
- * memory owned by the caller (e.g. a torch uint8 tensor) used for all
- * per-call scratch; it must stay alive until rsl_ctx_destroy.  stream: the
- * hipStream_t all work is ordered on (NULL = the null stream).  The context
- * also keeps its own constant tables (primes, Montgomery constants, CRT
- * tables, factorials, Stirling numbers mod p) in device memory that it
- * allocates and frees itself.
+ * Create a context on HIP device `device`.  All device memory the library
+ * uses is the caller's (e.g. torch uint8 tensors); it must stay alive until
+ * rsl_ctx_destroy.
+ *   d_workspace / ws_bytes: per-call scratch (the job of rsl_res, rsl_batch,
+ *     rsl_gcd ... and the server's arena).
+ *   d_tables / table_bytes: the region of the context's constant tables
+ *     (primes, Montgomery constants, factorials, every 32nd row of the
+ *     Stirling triangle, CRT tables).  With d_tables = NULL the top
+ *     table_bytes of the workspace are used instead (and the rest is scratch).
+ *     rsl_query's table_bytes gives what a problem needs; a call whose
+ *     problems need more gets RSL_ENOMEM.  The tables grow on demand inside
+ *     the region (after waiting for this context's streams only).
+ *   stream: the hipStream_t all work is ordered on (NULL = the null stream).
+ * The library allocates no device memory of its own besides rsl_res_static's
+ * fixed array; pinned host staging is allocated with hipHostMalloc.
  */
-int rsl_ctx_create(int device, void *d_workspace, size_t ws_bytes, void *stream, rsl_ctx **out);
+int rsl_ctx_create(int device, void *d_workspace, size_t ws_bytes, void *d_tables, size_t table_bytes,
+                   void *stream, rsl_ctx **out);
 int rsl_ctx_destroy(rsl_ctx *ctx);
 
 /* Sizing only; no device work, no context needed.  var = RSL_Y or RSL_X. */
@@ -289,9 +301,11 @@ int rsl_last_counters(rsl_ctx *ctx, rsl_counters *c);
 /*
  * A job is a planned batch whose inputs stay resident in device memory, so
  * that the device pipeline can be run repeatedly without host work (used for
- * throughput measurement and by the server).  The job owns its device buffers
- * (allocated with hipMalloc at creation, freed by rsl_job_destroy) and must be
- * used with the context it was created on.
+ * throughput measurement and by the autotuner).  rsl_job_create plans and lays
+ * the job out on the host only; rsl_job_bind then points it at device memory
+ * owned by the caller (at least rsl_job_info.device_bytes, alive until
+ * rsl_job_destroy or the next bind) and uploads the inputs.  A job must be used
+ * with the context it was created on.
  */
 typedef struct rsl_job rsl_job;
 
@@ -300,7 +314,7 @@ typedef struct {
   int32_t n_live;         /* problems with device work (non-zero inputs) */
   int64_t pairs;          /* (prime, point) univariate resultants per run */
   int64_t mulmods;        /* algorithmic multiply-adds of evaluation + remainder sequences per run */
-  size_t device_bytes;    /* device memory held by the job */
+  size_t device_bytes;    /* device memory the job's current layout needs */
   size_t upload_bytes;    /* host -> device bytes at creation */
   size_t download_bytes;  /* device -> host bytes per rsl_job_results */
   int32_t layout_mode;    /* schedule the layout was tuned for (RSL_STAGED or RSL_BATCHED) */
@@ -316,9 +330,14 @@ typedef struct {
   int64_t interp_mulmods;     /* interpolation products per run: N_p (D+1)(D+2) over problems */
 } rsl_job_info;
 
-/* Plan n problems and upload their inputs (status per problem in `status`, may be NULL). */
+/* Plan and lay out n problems (status per problem in `status`, may be NULL); host work only.
+ * The context's constant tables are grown to cover the job. */
 int rsl_job_create(rsl_ctx *ctx, int n, const rsl_poly *f, const rsl_poly *g, const int *var,
                    const rsl_opts *opts, int *status, rsl_job **out);
+/* Bind `bytes` of caller-owned device memory at d_mem (256-byte aligned) and upload the inputs
+ * (synchronous).  RSL_ENOMEM when the layout needs more; rsl_job_run, rsl_job_results and
+ * rsl_job_tune return RSL_EINVAL until a bind succeeds. */
+int rsl_job_bind(rsl_ctx *ctx, rsl_job *job, void *d_mem, size_t bytes);
 /* Run the device pipeline on the resident inputs; asynchronous on the context stream. */
 int rsl_job_run(rsl_ctx *ctx, rsl_job *job, int mode);
 /* Wait for the last run, copy the results back and decode them. */
@@ -332,7 +351,8 @@ int rsl_job_destroy(rsl_job *job);
  * launch, interpolation chunking (blocks kept in flight), persistent grid size
  * -- on the job itself, checks that every candidate produces the same output
  * bytes as the first (a candidate that differs is an error, RSL_EDEVICE), keeps
- * the fastest, re-lays the job out with it, and records it in the context's
+ * the fastest, re-lays the job out with it (candidates whose layout needs more
+ * than the bound memory are skipped), and records it in the context's
  * cache under the job's shape bucket (problems, max degree bound, max primes,
  * max degree, all rounded to powers of two).  Jobs created later with the
  * same bucket are laid out with the cached choice; RSL_AUTO runs it.
@@ -379,13 +399,16 @@ typedef struct {
 } rsl_stats;
 
 /*
- * Start a server on a context (the server owns the context's stream and
- * workspace until rsl_server_destroy).  Requests are admitted in FIFO order
- * while slots are free and the sum of their device footprints stays within
- * budget_bytes (<= workspace size); admitted requests run together in one
- * batched device iteration, and requests arriving while an iteration runs
- * join the next one (continuous batching).  max_queue bounds the host queue
- * (RSL_EAGAIN beyond it).
+ * Start a server on a context (the server owns the context's workspace until
+ * rsl_server_destroy: meanwhile rsl_res, rsl_res_xy, rsl_batch and the gcd
+ * calls on that context return RSL_EINVAL, and a second server is refused).
+ * Requests are admitted in FIFO order while slots are free and the sum of
+ * their device footprints stays within budget_bytes (<= workspace size);
+ * admitted requests run together in one batched device iteration, and
+ * requests arriving while an iteration runs join the next one (continuous
+ * batching).  max_queue bounds the host queue (RSL_EAGAIN beyond it).  A
+ * request whose constant tables would not fit the context's table region is
+ * refused at submit with RSL_ENOMEM.
  */
 int rsl_server_create(rsl_ctx *ctx, size_t budget_bytes, int max_slots, int max_queue,
                       rsl_server **out);

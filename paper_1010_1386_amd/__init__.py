@@ -56,7 +56,8 @@ class rsl_result(ctypes.Structure):
 class rsl_info(ctypes.Structure):
     _fields_ = [("D", ctypes.c_int32), ("bound_bits", ctypes.c_int32), ("n_primes", ctypes.c_int32),
                 ("n_points", ctypes.c_int32), ("out_limbs", ctypes.c_int32), ("my", ctypes.c_int32),
-                ("ny", ctypes.c_int32), ("bad_primes", ctypes.c_int32), ("footprint_bytes", ctypes.c_size_t)]
+                ("ny", ctypes.c_int32), ("bad_primes", ctypes.c_int32), ("footprint_bytes", ctypes.c_size_t),
+                ("table_bytes", ctypes.c_size_t)]
 
 
 class rsl_opts(ctypes.Structure):
@@ -107,7 +108,7 @@ STAGES = ("reduce", "eval_ures", "interp_conv", "interp_stir", "interp_newton", 
 _P = ctypes.POINTER
 _vp = ctypes.c_void_p
 _SIGS = {
-    "rsl_ctx_create": (ctypes.c_int, [ctypes.c_int, _vp, ctypes.c_size_t, _vp, _P(_vp)]),
+    "rsl_ctx_create": (ctypes.c_int, [ctypes.c_int, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp, _P(_vp)]),
     "rsl_ctx_destroy": (ctypes.c_int, [_vp]),
     "rsl_query": (ctypes.c_int, [_P(rsl_poly), _P(rsl_poly), ctypes.c_int, _P(rsl_info)]),
     "rsl_res": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), ctypes.c_int, _P(rsl_opts), _P(rsl_result)]),
@@ -130,6 +131,7 @@ _SIGS = {
     "rsl_server_destroy": (ctypes.c_int, [_vp]),
     "rsl_job_create": (ctypes.c_int, [_vp, ctypes.c_int, _P(rsl_poly), _P(rsl_poly), _P(ctypes.c_int),
                                       _P(rsl_opts), _P(ctypes.c_int), _P(_vp)]),
+    "rsl_job_bind": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_size_t]),
     "rsl_job_run": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
     "rsl_job_results": (ctypes.c_int, [_vp, _vp, _P(rsl_result), _P(ctypes.c_int)]),
     "rsl_job_info_get": (ctypes.c_int, [_vp, _P(rsl_job_info)]),
@@ -272,19 +274,26 @@ def _opts(points="replace", prime_start=0, extra_primes=0, point_origin=0, extra
 
 
 class Context:
-    """A device context: a torch workspace tensor on ``cuda:device`` plus a HIP stream."""
+    """A device context: torch uint8 tensors on ``cuda:device`` for the per-call
+    workspace and the constant tables, plus a HIP stream.  The library allocates
+    no device memory of its own (rsl_res_static's fixed array aside)."""
 
-    def __init__(self, device=0, workspace_bytes=256 << 20, stream=None):
+    def __init__(self, device=0, workspace_bytes=256 << 20, stream=None, table_bytes=256 << 20,
+                 tables_in_workspace=False):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: librsl runs only on the device")
         self.device = device
         self.workspace = torch.empty(workspace_bytes, dtype=torch.uint8, device=f"cuda:{device}")
+        # tables_in_workspace: the top table_bytes of the workspace hold the tables
+        self.tables = None if tables_in_workspace else torch.empty(table_bytes, dtype=torch.uint8,
+                                                                    device=f"cuda:{device}")
         self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         h = _vp()
+        tab = ctypes.c_void_p(self.tables.data_ptr()) if self.tables is not None else None
         rc = _lib.rsl_ctx_create(device, ctypes.c_void_p(self.workspace.data_ptr()), workspace_bytes,
-                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+                                 tab, table_bytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         if rc:
             raise RSLError(rc, "rsl_ctx_create")
         self.h = h
@@ -494,9 +503,13 @@ def _modecode(mode):
 
 
 class Job:
-    """Problems planned once with inputs resident on the device; run() repeats the device pipeline."""
+    """Problems planned once with inputs resident on the device; run() repeats the device pipeline.
 
-    def __init__(self, ctx, problems, **opts):
+    The job's device memory is a torch uint8 tensor of ``device_bytes`` (default:
+    the planned layout's size plus ``headroom``, so that the autotuner can try
+    layouts that need a little more)."""
+
+    def __init__(self, ctx, problems, device_bytes=None, headroom=0.5, **opts):
         self.ctx = ctx
         ctx._owned.add(self)
         n = len(problems)
@@ -523,6 +536,20 @@ class Job:
             rc = _lib.rsl_job_create(ctx.h, n, self.fa, self.ga, self.va, ctypes.byref(o), st, ctypes.byref(h))
         ctx._check(rc, "rsl_job_create")
         self.h = h
+        if device_bytes is None:
+            need = self.info()["device_bytes"]
+            device_bytes = max(int(need * (1.0 + headroom)), 1 << 20)
+        self.bind(device_bytes)
+
+    def bind(self, device_bytes):
+        """Give the job a fresh device buffer of ``device_bytes`` and upload its inputs."""
+        import torch
+
+        mem = torch.empty(int(device_bytes), dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
+        with self.ctx.lock:
+            rc = _lib.rsl_job_bind(self.ctx.h, self.h, ctypes.c_void_p(mem.data_ptr()), int(device_bytes))
+        self.ctx._check(rc, "rsl_job_bind")
+        self.mem = mem  # released after the job (close() drops it last)
 
     def run(self, mode="batched", graph=False):
         """One device run of the whole pipeline; graph=True replays it as a captured HIP graph."""
@@ -561,8 +588,9 @@ class Job:
 
     def close(self):
         if getattr(self, "h", None):
-            _lib.rsl_job_destroy(self.h)
+            _lib.rsl_job_destroy(self.h)  # waits for the job's work on the context stream
             self.h = None
+        self.mem = None
 
     def __del__(self):
         try:

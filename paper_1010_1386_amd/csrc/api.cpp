@@ -37,12 +37,7 @@ int hip_check(rsl_ctx* ctx, hipError_t e, const char* what) {
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-static void free_tables(rsl_ctx* c) {
-  for (void* p : {static_cast<void*>(c->d_pc), static_cast<void*>(c->d_fact),
-                  static_cast<void*>(c->d_ifact), static_cast<void*>(c->d_stir),
-                  static_cast<void*>(c->d_Tg), static_cast<void*>(c->d_invM),
-                  static_cast<void*>(c->d_Plimb)})
-    if (p) (void)hipFree(p);
+static void reset_tables(rsl_ctx* c) {
   c->d_pc = nullptr;
   c->d_fact = c->d_ifact = c->d_stir = c->d_Tg = c->d_invM = c->d_Plimb = nullptr;
   c->npcap = 0;
@@ -50,26 +45,75 @@ static void free_tables(rsl_ctx* c) {
   c->kcap = c->scap = -1;
 }
 
+TableLayout table_layout(int np_cap, int kcap, int scap) {
+  TableLayout L{};
+  const size_t A = 256;
+  L.ks = kcap + 1;
+  L.gnp = std::min(np_cap, kSlotCrtPrimes);
+  L.LPg = (31 * L.gnp + 31) / 32 + 1;
+  L.sstride = static_cast<int64_t>(align_up(static_cast<size_t>(ckpt_rowoff(scap / kCkpt + 1)), 64));
+  size_t o = 0;
+  L.pc = o;    o = align_up(o + sizeof(PrimeConst) * np_cap, A);
+  L.fact = o;  o = align_up(o + static_cast<size_t>(np_cap) * L.ks * 4, A);
+  L.ifact = o; o = align_up(o + static_cast<size_t>(np_cap) * L.ks * 4, A);
+  L.stir = o;  o = align_up(o + static_cast<size_t>(np_cap) * L.sstride * 4, A);
+  L.Tg = o;    o = align_up(o + static_cast<size_t>(L.gnp) * L.gnp * 4, A);
+  L.invM = o;  o = align_up(o + static_cast<size_t>(L.gnp) * 4, A);
+  L.Plimb = o; o = align_up(o + static_cast<size_t>(L.gnp) * L.LPg * 4, A);
+  L.total = o;
+  return L;
+}
+
+void table_caps(int np, int kneed, int sneed, int* np_cap, int* kcap, int* scap) {
+  *np_cap = static_cast<int>(align_up(std::max(np, 1), 64));
+  *kcap = static_cast<int>(align_up(std::max(kneed, 0) + 1, 256)) - 1;
+  *scap = static_cast<int>(align_up(std::max(sneed, 0) + 1, 256)) - 1;
+}
+
+int workspace_taken(rsl_ctx* ctx) {
+  return fail(ctx, RSL_EINVAL,
+              "a server runs on this context and owns its workspace: submit the call to the server, "
+              "use another context, or destroy the server first");
+}
+
+int wait_table_readers(rsl_ctx* ctx) {
+  // every launch that reads the tables was issued on one of these streams
+  int rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+  for (hipStream_t s : {ctx->s_up, ctx->s_comp2, ctx->s_down})
+    if (!rc && s) rc = hip_check(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");
+  for (hipStream_t s : ctx->reader_streams)
+    if (!rc) rc = hip_check(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");
+  return rc;
+}
+
 int ensure_tables(rsl_ctx* ctx, int np, int kneed, int sneed) {
   if (np <= ctx->npcap && kneed <= ctx->kcap && sneed <= ctx->scap) return RSL_OK;
-  const int new_np = std::max(ctx->npcap, static_cast<int>(align_up(std::max(np, 1), 64)));
-  const int new_k = std::max(ctx->kcap, static_cast<int>(align_up(kneed + 1, 256)) - 1);
-  const int new_s = std::max(ctx->scap, static_cast<int>(align_up(sneed + 1, 256)) - 1);
-  // the old tables may still be read by work in flight on any stream
-  int rc = hip_check(ctx, hipDeviceSynchronize(), "hipDeviceSynchronize");
+  int cap_np, cap_k, cap_s;
+  table_caps(np, kneed, sneed, &cap_np, &cap_k, &cap_s);
+  const int new_np = std::max(ctx->npcap, cap_np);
+  const int new_k = std::max(ctx->kcap, cap_k);
+  const int new_s = std::max(ctx->scap, cap_s);
+  const TableLayout L = table_layout(new_np, new_k, new_s);
+  if (L.total > ctx->tab_bytes)
+    return fail(ctx, RSL_ENOMEM, "the constant tables need " + std::to_string(L.total) + " bytes, the table region has " +
+                                     std::to_string(ctx->tab_bytes));
+  // the old tables (in the same region) may still be read by this context's
+  // work in flight: wait for its streams, not for the whole device
+  int rc = wait_table_readers(ctx);
   if (rc) return rc;
-  free_tables(ctx);
+  reset_tables(ctx);
 
-  const std::vector<uint32_t>& tab = prime_table(new_np);
-  if (static_cast<int>(tab.size()) < new_np) return fail(ctx, RSL_EPRIMES, "prime table exhausted");
-  std::vector<uint32_t> primes(tab.begin(), tab.begin() + new_np);
+  size_t have = 0;
+  const uint32_t* tab = prime_table(new_np, &have);
+  if (static_cast<int>(have) < new_np) return fail(ctx, RSL_EPRIMES, "prime table exhausted");
+  std::vector<uint32_t> primes(tab, tab + new_np);
   std::vector<PrimeConst> pc(new_np);
   for (int g = 0; g < new_np; ++g) pc[g] = make_prime_const(primes[g]);
 
   // factorials and inverse factorials, Montgomery form
-  const int ks = new_k + 1;
+  const int ks = L.ks;
   std::vector<uint32_t> fact(static_cast<size_t>(new_np) * ks), ifact(fact.size());
-  for (int g = 0; g < new_np; ++g) {
+  parallel_for(new_np, 8, [&](int g) {
     const uint64_t p = primes[g];
     std::vector<uint64_t> f(ks);
     f[0] = 1;
@@ -87,47 +131,41 @@ int ensure_tables(rsl_ctx* ctx, int np, int kneed, int sneed) {
       fact[static_cast<size_t>(g) * ks + t] = static_cast<uint32_t>((f[t] << 32) % p);
       ifact[static_cast<size_t>(g) * ks + t] = static_cast<uint32_t>((fi[t] << 32) % p);
     }
-  }
+  });
   // canonical CRT tables (Garner's digits serve only the per-lane-slot CRT, so
   // they cover at most kSlotCrtPrimes primes)
-  const int gnp = std::min(new_np, kSlotCrtPrimes);
-  const int LPg = (31 * gnp + 31) / 32 + 1;
   std::vector<uint32_t> Tg, invM, Plimb;
-  crt_tables(std::vector<uint32_t>(primes.begin(), primes.begin() + gnp), LPg, &Tg, &invM, &Plimb);
+  crt_tables(std::vector<uint32_t>(primes.begin(), primes.begin() + L.gnp), L.LPg, &Tg, &invM, &Plimb);
 
-  const int64_t sstride = static_cast<int64_t>(align_up(static_cast<size_t>(ckpt_rowoff(new_s / kCkpt + 1)), 64));
-  auto dmalloc = [&](void** p, size_t bytes) { return hip_check(ctx, hipMalloc(p, bytes), "hipMalloc(tables)"); };
-  if ((rc = dmalloc(reinterpret_cast<void**>(&ctx->d_pc), sizeof(PrimeConst) * new_np)) ||
-      (rc = dmalloc(reinterpret_cast<void**>(&ctx->d_fact), fact.size() * 4)) ||
-      (rc = dmalloc(reinterpret_cast<void**>(&ctx->d_ifact), ifact.size() * 4)) ||
-      (rc = dmalloc(reinterpret_cast<void**>(&ctx->d_stir), static_cast<size_t>(new_np) * sstride * 4)) ||
-      (rc = dmalloc(reinterpret_cast<void**>(&ctx->d_Tg), Tg.size() * 4)) ||
-      (rc = dmalloc(reinterpret_cast<void**>(&ctx->d_invM), invM.size() * 4)) ||
-      (rc = dmalloc(reinterpret_cast<void**>(&ctx->d_Plimb), Plimb.size() * 4))) {
-    free_tables(ctx);
+  uint8_t* base = ctx->tab;
+  auto up = [&](size_t off, const void* h, size_t bytes) {
+    return hip_check(ctx, hipMemcpy(base + off, h, bytes, hipMemcpyHostToDevice), "hipMemcpy(tables)");
+  };
+  if ((rc = up(L.pc, pc.data(), sizeof(PrimeConst) * new_np)) || (rc = up(L.fact, fact.data(), fact.size() * 4)) ||
+      (rc = up(L.ifact, ifact.data(), ifact.size() * 4)) || (rc = up(L.Tg, Tg.data(), Tg.size() * 4)) ||
+      (rc = up(L.invM, invM.data(), invM.size() * 4)) || (rc = up(L.Plimb, Plimb.data(), Plimb.size() * 4)))
+    return rc;
+  ctx->d_pc = reinterpret_cast<PrimeConst*>(base + L.pc);
+  ctx->d_fact = reinterpret_cast<uint32_t*>(base + L.fact);
+  ctx->d_ifact = reinterpret_cast<uint32_t*>(base + L.ifact);
+  ctx->d_stir = reinterpret_cast<uint32_t*>(base + L.stir);
+  ctx->d_Tg = reinterpret_cast<uint32_t*>(base + L.Tg);
+  ctx->d_invM = reinterpret_cast<uint32_t*>(base + L.invM);
+  ctx->d_Plimb = reinterpret_cast<uint32_t*>(base + L.Plimb);
+  if ((rc = hip_check(ctx, launch_stirling_build(ctx->d_stir, L.sstride, ctx->d_pc, 0, new_np, new_s, ctx->stream),
+                      "stirling build")) ||
+      (rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "stirling build sync"))) {
+    reset_tables(ctx);
     return rc;
   }
-  auto up = [&](void* d, const void* h, size_t bytes) {
-    return hip_check(ctx, hipMemcpy(d, h, bytes, hipMemcpyHostToDevice), "hipMemcpy(tables)");
-  };
-  if ((rc = up(ctx->d_pc, pc.data(), sizeof(PrimeConst) * new_np)) ||
-      (rc = up(ctx->d_fact, fact.data(), fact.size() * 4)) ||
-      (rc = up(ctx->d_ifact, ifact.data(), ifact.size() * 4)) ||
-      (rc = up(ctx->d_Tg, Tg.data(), Tg.size() * 4)) ||
-      (rc = up(ctx->d_invM, invM.data(), invM.size() * 4)) ||
-      (rc = up(ctx->d_Plimb, Plimb.data(), Plimb.size() * 4)))
-    return rc;
-  if ((rc = hip_check(ctx, launch_stirling_build(ctx->d_stir, sstride, ctx->d_pc, 0, new_np, new_s, ctx->stream),
-                      "stirling build")) ||
-      (rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "stirling build sync")))
-    return rc;
   ctx->npcap = new_np;
   ctx->kcap = new_k;
   ctx->scap = new_s;
   ctx->kstride = ks;
-  ctx->sstride = sstride;
-  ctx->LPg = LPg;
-  ctx->garner_np = gnp;
+  ctx->sstride = L.sstride;
+  ctx->LPg = L.LPg;
+  ctx->garner_np = L.gnp;
+  ctx->tab_used = L.total;
   ctx->table_gen += 1;
   return RSL_OK;
 }
@@ -253,7 +291,7 @@ static std::vector<std::pair<int, int>> chunk_ranges(const std::vector<ShapeEst>
 static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var,
                        const rsl_opts* opts, rsl_result* out, int* status, int mode, const TuneConfig* tc,
                        const std::vector<std::pair<int, int>>& ranges, const std::vector<ShapeEst>& est,
-                       std::string* err, rsl_counters* cnt, double t_entry) {
+                       std::string* err, rsl_counters* cnt) {
   const int S = static_cast<int>(ranges.size());
   if (static_cast<int>(ctx->chunk_stage.size()) < S) ctx->chunk_stage.resize(S);
   for (int c = 0; c < S; ++c) {
@@ -296,26 +334,26 @@ static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g
         nD = std::max(nD, e.D);
       }
     int rc0 = ng ? ensure_tables(ctx, std::min(ng, kMaxPrimes), nE, nD) : RSL_OK;
-    if (rc0) return rc0;
+    if (rc0 == RSL_ENOMEM) {  // the estimate overshoots the region: each chunk grows what it needs
+      ctx->err.clear();
+      rc0 = RSL_OK;
+    }
+    if (rc0) {
+      if (status)
+        for (int k = 0; k < n; ++k) status[k] = rc0;
+      return rc0;
+    }
   }
   // producer: plans and lays out one chunk after the other (host only; the
   // tables are grown below, on this thread)
-  const bool trace = std::getenv("RSL_TRACE_CHUNKS") != nullptr;
-  const double tz = now_ms();
-  if (trace) fprintf(stderr, "before the pipeline %.2f ms\n", tz - t_entry);
-  std::vector<double> t_ready(S), t_enq(S), t_done(S), t_dec(S), t_plan(S), t_lay(S), t_bind(S), t_dcd(S);
   std::thread producer([&]() {
     const double tb = now_ms();
     for (int c = 0; c < S; ++c) {
       const int lo = ranges[c].first, hi = ranges[c].second;
       Job& J = jobs[c];
-      const double tp0 = now_ms();
       job_plan(hi - lo, f + lo, g + lo, var + lo, opts, &J, &errs[c]);
-      t_plan[c] = now_ms() - tp0;
       brc[c] = job_build(ctx, J.n, f + lo, g + lo, var + lo, opts, &J, &errs[c], tc, true, true);
-      t_lay[c] = now_ms() - tp0 - t_plan[c];
       std::lock_guard<std::mutex> lk(mu);
-      t_ready[c] = now_ms() - tz;
       ready[c] = 1;
       cv.notify_all();
     }
@@ -351,7 +389,6 @@ static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g
       break;
     const double t1 = now_ms();
     job_bind(&J, ctx->ws + off, cs.up, mode == RSL_BATCHED);
-    t_bind[c] = now_ms() - t1;
     bind_ms += now_ms() - t1;
     off = align_up(off + J.total, 256);
     // upload on the copy stream; the kernels wait for it on a compute stream
@@ -367,7 +404,6 @@ static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g
         (rc = job_download(ctx, &J, cs.down, ctx->s_down)) ||
         (rc = hip_check(ctx, hipEventRecord(cs.e2, ctx->s_down), "event")))
       break;
-    t_enq[c] = now_ms() - tz;
     ++launched;
   }
   // decode each launched chunk as soon as its copies are done
@@ -378,7 +414,6 @@ static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g
     if (!J.live.empty()) {
       const int e = hip_check(ctx, hipEventSynchronize(ctx->chunk_stage[c].e2), "hipEventSynchronize");
       if (e) { rc = rc ? rc : e; break; }
-      t_done[c] = now_ms() - tz;
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, ctx->chunk_stage[c].e0, ctx->chunk_stage[c].e1);
       cnt->ms_device += ms;
@@ -387,27 +422,14 @@ static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g
     std::vector<int> stc(J.n);
     const int r = job_decode(ctx, J, J.live.empty() ? nullptr : ctx->chunk_stage[c].down, out + lo, stc.data(), cnt);
     dec_ms += now_ms() - t3;
-    t_dcd[c] = now_ms() - t3;
-    t_dec[c] = now_ms() - tz;
     if (status)
       for (int k = 0; k < J.n; ++k) status[lo + k] = stc[k];
     if (r && !rc) rc = r;
     J = Job();  // free the chunk's host state while later chunks still run
   }
-  const double tj0 = now_ms();
   producer.join();
   (void)sync_all();
-  const double tj1 = now_ms();
   std::vector<Job>().swap(jobs);
-  if (trace) fprintf(stderr, "join+sync %.2f free %.2f\n", tj1 - tj0, now_ms() - tj1);
-  if (trace) {
-    for (int c = 0; c < S; ++c) {
-      float dev = 0.f;
-      (void)hipEventElapsedTime(&dev, ctx->chunk_stage[c].e0, ctx->chunk_stage[c].e1);
-      fprintf(stderr, "chunk %d [%d,%d): plan %.2f layout %.2f ready %.2f bind %.2f enq %.2f done %.2f decode %.2f dec %.2f dev %.2f\n", c, ranges[c].first,
-              ranges[c].second, t_plan[c], t_lay[c], t_ready[c], t_bind[c], t_enq[c], t_done[c], t_dcd[c], t_dec[c], dev);
-    }
-  }
   cnt->ms_build += build_ms;
   cnt->ms_bind += bind_ms;
   cnt->ms_decode += dec_ms;
@@ -422,6 +444,7 @@ static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g
 // Run a job laid out in the context workspace, synchronously.
 static int run_in_workspace(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const int* var,
                             const rsl_opts* opts, rsl_result* out, int* status, int mode, rsl_counters* cnt) {
+  if (ctx->server) return workspace_taken(ctx);
   const double t0 = now_ms();
   std::string err;
   // shapes from the inputs alone: the schedule lookup and the chunking need no plans
@@ -449,7 +472,7 @@ static int run_in_workspace(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_po
       std::vector<std::pair<int, int>> ranges = chunk_ranges(est, var, S);
       if (ranges.size() > 1) {
         cnt->ms_build += now_ms() - t0;
-        int rc = run_chunked(ctx, n, f, g, var, opts, out, status, mode, tc, ranges, est, &err, cnt, t0);
+        int rc = run_chunked(ctx, n, f, g, var, opts, out, status, mode, tc, ranges, est, &err, cnt);
         if (rc && !err.empty() && ctx->err.empty()) ctx->err = err;
         return rc;
       }
@@ -458,7 +481,12 @@ static int run_in_workspace(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_po
   Job J;
   job_plan(n, f, g, var, opts, &J, &err);
   int rc = job_build(ctx, n, f, g, var, opts, &J, &err, tc, true);
-  if (rc == RSL_EDEVICE) return rc;
+  if (rc) {  // no layout (tables, options or LDS): nothing ran
+    if (status)
+      for (int k = 0; k < n; ++k) status[k] = J.pstatus[k] ? J.pstatus[k] : rc;
+    if (!err.empty()) ctx->err = err;
+    return rc;
+  }
   const double t1 = now_ms();
   cnt->ms_build += t1 - t0;
   if (!J.live.empty()) {
@@ -501,8 +529,10 @@ using namespace rsl;
 
 extern "C" {
 
-int rsl_ctx_create(int device, void* d_workspace, size_t ws_bytes, void* stream, rsl_ctx** out) {
-  if (!out || (ws_bytes && !d_workspace)) return RSL_EINVAL;
+int rsl_ctx_create(int device, void* d_workspace, size_t ws_bytes, void* d_tables, size_t table_bytes, void* stream,
+                   rsl_ctx** out) {
+  if (!out || (ws_bytes && !d_workspace) || (d_tables && !table_bytes)) return RSL_EINVAL;
+  if (!d_tables && table_bytes > ws_bytes) return RSL_EINVAL;
   *out = nullptr;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return RSL_EDEVICE;
@@ -512,6 +542,15 @@ int rsl_ctx_create(int device, void* d_workspace, size_t ws_bytes, void* stream,
   c->device = device;
   c->ws = static_cast<uint8_t*>(d_workspace);
   c->ws_bytes = ws_bytes;
+  if (d_tables) {  // a region of its own for the constant tables
+    c->tab = static_cast<uint8_t*>(d_tables);
+    c->tab_bytes = table_bytes;
+  } else {  // the top table_bytes of the workspace, 256-byte aligned
+    const size_t jb = (ws_bytes - table_bytes) & ~static_cast<size_t>(255);
+    c->tab = c->ws + jb;
+    c->tab_bytes = ws_bytes - jb;
+    c->ws_bytes = jb;
+  }
   c->stream = static_cast<hipStream_t>(stream);
   bool ok = hipEventCreate(&c->e0) == hipSuccess && hipEventCreate(&c->e1) == hipSuccess;
   for (int s = 0; s <= kNumStages && ok; ++s) ok = hipEventCreate(&c->ev[s]) == hipSuccess;
@@ -535,8 +574,8 @@ int rsl_ctx_create(int device, void* d_workspace, size_t ws_bytes, void* stream,
 int rsl_ctx_destroy(rsl_ctx* ctx) {
   if (!ctx) return RSL_EINVAL;
   (void)hipSetDevice(ctx->device);
-  (void)hipStreamSynchronize(ctx->stream);
-  free_tables(ctx);
+  (void)wait_table_readers(ctx);
+  reset_tables(ctx);
   if (ctx->h_up) (void)hipHostFree(ctx->h_up);
   if (ctx->h_down) (void)hipHostFree(ctx->h_down);
   for (rsl_ctx::ChunkStage& cs : ctx->chunk_stage) {
@@ -584,7 +623,12 @@ int rsl_query(const rsl_poly* f, const rsl_poly* g, int var, rsl_info* info) {
   info->bad_primes = P.bad_primes;
   Job J;
   std::string e2;
-  if (job_build(nullptr, 1, f, g, &var, nullptr, &J, &e2) == RSL_OK) info->footprint_bytes = J.total;
+  if (job_build(nullptr, 1, f, g, &var, nullptr, &J, &e2) == RSL_OK) {
+    info->footprint_bytes = J.total;
+    int cn, ck, cs;
+    table_caps(J.need_g, J.need_E, J.need_D, &cn, &ck, &cs);
+    info->table_bytes = table_layout(cn, ck, cs).total;
+  }
   return RSL_OK;
 }
 

@@ -38,7 +38,12 @@ struct rsl_ctx {
   bool poisoned = false;
   std::string err;
 
-  // constant tables (device), indexed by global prime index
+  // constant tables (device, in the caller's table region), indexed by global prime index
+  uint8_t* tab = nullptr;
+  size_t tab_bytes = 0;   // size of the table region
+  size_t tab_used = 0;    // bytes the current tables take
+  std::vector<hipStream_t> reader_streams;  // other streams reading the tables (server lanes)
+  struct rsl_server* server = nullptr;      // the server whose arena is the workspace, if any
   int npcap = 0, kcap = -1, scap = -1;
   rsl::PrimeConst* d_pc = nullptr;
   uint32_t* d_fact = nullptr;
@@ -100,8 +105,22 @@ int fail(rsl_ctx* ctx, int code, const std::string& msg);
 int hip_check(rsl_ctx* ctx, hipError_t e, const char* what);
 
 // Make sure the constant tables cover global prime indices < np, factorials up
-// to kneed and Stirling rows up to sneed.
+// to kneed and Stirling rows up to sneed (RSL_ENOMEM when the table region is
+// too small; a growth first waits for the context's streams).
 int ensure_tables(rsl_ctx* ctx, int np, int kneed, int sneed);
+// Layout of the constant tables in their region, for the given capacities.
+struct TableLayout {
+  size_t pc, fact, ifact, stir, Tg, invM, Plimb, total;
+  int64_t sstride;
+  int ks, gnp, LPg;
+};
+TableLayout table_layout(int np_cap, int kcap, int scap);
+// Capacities ensure_tables rounds a need up to.
+void table_caps(int np, int kneed, int sneed, int* np_cap, int* kcap, int* scap);
+// Wait for every stream of the context that may read the tables.
+int wait_table_readers(rsl_ctx* ctx);
+// The error of a call that needs the workspace while a server owns it.
+int workspace_taken(rsl_ctx* ctx);
 DevTables tables_of(const rsl_ctx* ctx);
 
 // Grow the pinned staging buffers.

@@ -437,8 +437,9 @@ int gcd_core(rsl_ctx* ctx, const UPoly& u, const UPoly& v, UPoly* gout, UPoly* u
     {
       int bits = 0;
       for (size_t k = 0; static_cast<int>(pidx.size()) < kMaxPrimes * 4; ++k) {
-        const std::vector<uint32_t>& tab = prime_table(k + 1);
-        if (k >= tab.size()) return fail(ctx, RSL_EPRIMES, "prime table exhausted");
+        size_t have = 0;
+        const uint32_t* tab = prime_table(k + 1, &have);
+        if (k >= have) return fail(ctx, RSL_EPRIMES, "prime table exhausted");
         const uint32_t p = tab[k];
         if (lcu.mod_small(p) == 0 || (nv >= 0 && lcv.mod_small(p) == 0)) continue;
         pidx.push_back(static_cast<int>(k));
@@ -449,6 +450,7 @@ int gcd_core(rsl_ctx* ctx, const UPoly& u, const UPoly& v, UPoly* gout, UPoly* u
     }
     const int np = static_cast<int>(pidx.size());
     if (np > kMaxPrimes) return fail(ctx, RSL_EINVAL, "gcd needs more than 4096 primes (inputs too large)");
+    if (ctx->server) return workspace_taken(ctx);
     int rc = ensure_tables(ctx, pidx.back() + 1, std::max(ctx->kcap, 0), std::max(ctx->scap, 0));
     if (rc) return rc;
     const DevTables T = tables_of(ctx);
@@ -495,7 +497,7 @@ int gcd_core(rsl_ctx* ctx, const UPoly& u, const UPoly& v, UPoly* gout, UPoly* u
     const int dg = *std::min_element(gdeg.begin(), gdeg.end());
     std::vector<int> kept, kpidx;
     BigU M(1);
-    const std::vector<uint32_t>& tab = prime_table(0);
+    const uint32_t* tab = prime_table(0);
     for (int s = 0; s < np; ++s)
       if (gdeg[s] == dg) {
         kept.push_back(s);

@@ -59,15 +59,19 @@ bool is_prime_u32(uint32_t n) {
   return true;
 }
 
-const std::vector<uint32_t>& prime_table(size_t at_least) {
+const uint32_t* prime_table(size_t at_least, size_t* avail) {
   std::lock_guard<std::mutex> lk(g_prime_mu);
+  // the storage is reserved once, so the table never moves: a pointer taken by
+  // one planning thread stays valid while another thread extends the table
+  if (g_primes.capacity() < kPrimeTableMax) g_primes.reserve(kPrimeTableMax);
   at_least = std::min(at_least, kPrimeTableMax);
   while (g_primes.size() < at_least) {
     uint32_t c = g_next_candidate;
     g_next_candidate -= 2;
     if (is_prime_u32(c)) g_primes.push_back(c);
   }
-  return g_primes;
+  if (avail) *avail = g_primes.size();
+  return g_primes.data();
 }
 
 int make_view(const rsl_poly* f, int var, View* v, std::string* err) {
@@ -246,7 +250,7 @@ size_t crt_bytes(const CrtConst& C) {
 }  // namespace
 
 void plan_crt(Plan* P) {
-  const std::vector<uint32_t>& tab = prime_table(0);
+  const uint32_t* tab = prime_table(0);
   P->np = static_cast<int>(P->pidx.size());
   P->canonical = true;
   for (int i = 0; i < P->np; ++i)
@@ -283,8 +287,10 @@ namespace {
 struct RowScan {
   int dy = -1, dx = -1, tdeg = -1, lcdeg = -1, L = 1;
   int64_t nterms = 0;
-  double sq = 0.0;  // sum_j ||f_j||_1^2
+  double sq = 0.0;  // sum_j ||f_j||_1^2, scaled by 2^-(2 * shift)
+  int shift = 0;    // values are scaled by 2^-shift so that no sum overflows a double
   bool ok = false;
+  double log2_sq() const { return std::log2(std::max(sq, 1e-300)) + 2.0 * shift; }
 };
 
 RowScan scan_rows(const rsl_poly* f, int var) {
@@ -295,6 +301,10 @@ RowScan scan_rows(const rsl_poly* f, int var) {
   r.L = L;
   const int Ydim = (var == RSL_Y) ? f->dy : f->dx;
   const int Xdim = (var == RSL_Y) ? f->dx : f->dy;
+  // a value is at most 2^(32 L); scaled by 2^-shift it stays below 2^96, a row
+  // sum below 2^123 and the sum of squares far from the double range's end
+  r.shift = 32 * std::max(0, L - 3);
+  const double one = std::ldexp(1.0, -r.shift);
   for (int j = 0; j <= Ydim; ++j) {
     double l1 = 0.0;
     int rd = -1;
@@ -305,14 +315,14 @@ RowScan scan_rows(const rsl_poly* f, int var) {
       for (int l = 0; l < L; ++l) nz |= w[l] != 0u;
       if (!nz) continue;
       rd = i;
-      // |value| from its top two limbs (two's complement)
+      // |value| from its top three limbs (two's complement), scaled
       const bool neg = (w[L - 1] >> 31) != 0;
       double v = 0.0;
       for (int l = L - 1; l >= 0 && l >= L - 3; --l) {
         const uint32_t x = neg ? ~w[l] : w[l];
-        v += std::ldexp(static_cast<double>(x), 32 * l);
+        v += std::ldexp(static_cast<double>(x), 32 * l - r.shift);
       }
-      l1 += v + 1.0;
+      l1 += v + one;
     }
     if (rd >= 0) {
       r.dy = j;
@@ -345,7 +355,7 @@ ShapeEst estimate_shape(const rsl_poly* f, const rsl_poly* g, int var) {
                      static_cast<int64_t>(a.dy) * b.dy;
   e.D = static_cast<int>(std::min<int64_t>(std::min(d1, d2), 1 << 20));
   e.E = e.D + a.lcdeg + b.lcdeg;
-  const double lb2 = b.dy * std::log2(std::max(a.sq, 1.0)) + a.dy * std::log2(std::max(b.sq, 1.0));
+  const double lb2 = b.dy * std::max(a.log2_sq(), 0.0) + a.dy * std::max(b.log2_sq(), 0.0);
   e.np_est = static_cast<int>(std::ceil((lb2 / 2.0 + 1.0) / 30.99)) + 1;
   e.cost = (static_cast<double>(a.nterms + b.nterms) + static_cast<double>(a.dy) * b.dy) * e.np_est * (e.E + 1) +
            static_cast<double>(e.np_est) * (e.D + 1) * (e.D + 1);
@@ -542,8 +552,9 @@ int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opt
       *err = "prime table exhausted";
       return RSL_EPRIMES;
     }
-    const std::vector<uint32_t>& tab = prime_table(k + 1);
-    if (k >= tab.size()) {
+    size_t have = 0;
+    const uint32_t* tab = prime_table(k + 1, &have);
+    if (k >= have) {
       *err = "prime table exhausted";
       return RSL_EPRIMES;
     }

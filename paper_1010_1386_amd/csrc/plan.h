@@ -17,7 +17,11 @@
 namespace rsl {
 
 // Descending 31-bit primes below 2^31 (index 0 = largest); grows on demand.
-const std::vector<uint32_t>& prime_table(size_t at_least);
+// The table of 31-bit primes (descending from 2^31 - 1), extended to at least
+// `at_least` entries (capped at its maximum; *avail = entries present).  The
+// pointer stays valid for the life of the process; entries below *avail, or
+// below an index a previous call reported, may be read without a lock.
+const uint32_t* prime_table(size_t at_least, size_t* avail = nullptr);
 bool is_prime_u32(uint32_t n);
 
 // One input polynomial viewed in the eliminated variable ("y"): rows j are the

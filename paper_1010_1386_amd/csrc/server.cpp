@@ -31,6 +31,7 @@ namespace rsl {
 namespace {
 
 constexpr int kLanes = 3;  // batches in flight at once, one HIP stream each
+constexpr int kTablesFull = -1000;  // launch(): the table region cannot cover the group
 
 struct Request {
   uint64_t ticket = 0;
@@ -197,7 +198,7 @@ int launch(rsl_server* S, Lane& ln, std::vector<std::shared_ptr<Request>>& grp) 
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     rc = job_build(ctx, n, f.data(), g.data(), var.data(), nullptr, &J, &err);
   }
-  if (rc == RSL_EDEVICE) return rc;
+  if (rc) return rc == RSL_ENOMEM ? kTablesFull : rc;  // waiting frees no table room
   size_t off = 0;
   const size_t bytes = std::max<size_t>(J.total, 256);
   if (!S->arena.alloc(bytes, &off)) return RSL_ENOMEM;
@@ -278,6 +279,7 @@ void scheduler(rsl_server* S) {
       for (auto it = back.rbegin(); it != back.rend(); ++it) S->pending.push_front(*it);
       if (grp.empty()) break;
       if (rc) {
+        if (rc == kTablesFull) rc = RSL_ENOMEM;
         for (auto& r : grp) finish(S, *r, rc);
         S->cv_done.notify_all();
         continue;
@@ -302,6 +304,8 @@ extern "C" {
 
 int rsl_server_create(rsl_ctx* ctx, size_t budget_bytes, int max_slots, int max_queue, rsl_server** out) {
   if (!ctx || !out || max_slots < 1 || max_queue < 1 || budget_bytes == 0) return RSL_EINVAL;
+  std::lock_guard<std::recursive_mutex> ctx_lk(ctx->mu);
+  if (ctx->server) return fail(ctx, RSL_EINVAL, "a server already runs on this context");
   if (budget_bytes > ctx->ws_bytes) return fail(ctx, RSL_ENOMEM, "server budget exceeds the workspace");
   *out = nullptr;
   rsl_server* S = new (std::nothrow) rsl_server();
@@ -324,6 +328,9 @@ int rsl_server_create(rsl_ctx* ctx, size_t budget_bytes, int max_slots, int max_
       return RSL_EDEVICE;
     }
   }
+  // the lanes read the constant tables: a table growth waits for them too
+  for (Lane& ln : S->lanes) ctx->reader_streams.push_back(ln.stream);
+  ctx->server = S;
   S->th = std::thread(scheduler, S);
   *out = S;
   return RSL_OK;
@@ -350,6 +357,20 @@ int rsl_server_submit(rsl_server* S, const rsl_poly* f, const rsl_poly* g, int v
   if (rc) return rc;
   if (J.pstatus[0]) return J.pstatus[0];
   r->footprint = std::max<size_t>(J.total, 256);
+  {
+    // the constant tables this request needs (with what the context holds) must fit the table region
+    rsl_ctx* ctx = S->ctx;
+    std::lock_guard<std::recursive_mutex> ctx_lk(ctx->mu);
+    int cn, ck, cs;
+    table_caps(J.need_g, J.need_E, J.need_D, &cn, &ck, &cs);
+    const size_t tb = table_layout(std::max(cn, ctx->npcap), std::max(ck, ctx->kcap), std::max(cs, ctx->scap)).total;
+    if (tb > ctx->tab_bytes) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->rejected += 1;
+      return fail(ctx, RSL_ENOMEM, "the request's constant tables need " + std::to_string(tb) +
+                                       " bytes, the table region has " + std::to_string(ctx->tab_bytes));
+    }
+  }
   std::lock_guard<std::mutex> lk(S->mu);
   if (r->footprint > S->budget) {
     S->rejected += 1;
@@ -425,6 +446,12 @@ int rsl_server_destroy(rsl_server* S) {
   S->cv_sched.notify_all();
   if (S->th.joinable()) S->th.join();  // drains pending and in-flight requests
   (void)hipSetDevice(S->ctx->device);
+  {
+    std::lock_guard<std::recursive_mutex> ctx_lk(S->ctx->mu);
+    std::vector<hipStream_t>& rs = S->ctx->reader_streams;
+    for (Lane& ln : S->lanes) rs.erase(std::remove(rs.begin(), rs.end(), ln.stream), rs.end());
+    S->ctx->server = nullptr;
+  }
   for (Lane& ln : S->lanes) {
     if (ln.stream) (void)hipStreamSynchronize(ln.stream);
     if (ln.stream) (void)hipStreamDestroy(ln.stream);

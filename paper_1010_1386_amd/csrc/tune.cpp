@@ -16,8 +16,10 @@
 
 struct rsl_job {
   rsl::Job J;
-  uint8_t* dmem = nullptr;
+  uint8_t* dmem = nullptr;  // the caller's device memory (rsl_job_bind), nullptr until bound
+  size_t dmem_bytes = 0;
   uint8_t* hdown = nullptr;
+  rsl::TuneConfig tc;       // schedule of the current layout
   int gen = -1;
   rsl_ctx* ctx = nullptr;
   // inputs, kept so that the autotuner can lay the job out again
@@ -74,30 +76,22 @@ static void release_graphs(rsl_job* j) {
 
 static void release_mem(rsl_job* j) {
   release_graphs(j);
-  if (j->dmem) (void)hipFree(j->dmem);
   if (j->hdown) (void)hipHostFree(j->hdown);
-  j->dmem = nullptr;
   j->hdown = nullptr;
+  j->gen = -1;
 }
 
-// Lay the job out with `tc`, allocate its device buffers and upload the inputs.
-static int materialize(rsl_ctx* ctx, rsl_job* j, const TuneConfig& tc) {
+// Point the laid-out job at the caller's memory and upload its inputs.
+static int bind_and_upload(rsl_ctx* ctx, rsl_job* j) {
   release_mem(j);
-  j->J = Job();
-  std::string err;
-  const int n = static_cast<int>(j->f.size());
-  int rc = job_build(ctx, n, j->f.data(), j->g.data(), j->var.data(), j->has_opts ? &j->opts : nullptr, &j->J,
-                     &err, &tc);
-  if (rc == RSL_EDEVICE) return rc;
-  if (!err.empty()) ctx->err = err;
-  const size_t bytes = std::max<size_t>(j->J.total, 256);
-  if ((rc = hip_check(ctx, hipMalloc(reinterpret_cast<void**>(&j->dmem), bytes), "hipMalloc(job)")) ||
-      (rc = hip_check(ctx, hipHostMalloc(reinterpret_cast<void**>(&j->hdown),
+  if (j->J.total > j->dmem_bytes)
+    return fail(ctx, RSL_ENOMEM, "the job needs " + std::to_string(j->J.total) + " device bytes, " +
+                                     std::to_string(j->dmem_bytes) + " are bound");
+  int rc;
+  if ((rc = hip_check(ctx, hipHostMalloc(reinterpret_cast<void**>(&j->hdown),
                                          std::max<size_t>(j->J.down_bytes, 256), hipHostMallocDefault),
-                      "hipHostMalloc(job)"))) {
-    release_mem(j);
+                      "hipHostMalloc(job)")))
     return rc;
-  }
   job_bind(&j->J, j->dmem);
   if ((rc = job_upload(ctx, &j->J, ctx->stream)) ||
       (rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize"))) {
@@ -106,6 +100,24 @@ static int materialize(rsl_ctx* ctx, rsl_job* j, const TuneConfig& tc) {
   }
   j->gen = ctx->table_gen;
   return RSL_OK;
+}
+
+// Lay the job out with `tc` and, when memory is bound, upload the inputs.
+static int materialize(rsl_ctx* ctx, rsl_job* j, const TuneConfig& tc) {
+  release_mem(j);
+  j->J = Job();
+  j->tc = tc;
+  std::string err;
+  const int n = static_cast<int>(j->f.size());
+  int rc = job_build(ctx, n, j->f.data(), j->g.data(), j->var.data(), j->has_opts ? &j->opts : nullptr, &j->J,
+                     &err, &tc);
+  if (!err.empty()) ctx->err = err;
+  if (rc) return rc;
+  return j->dmem ? bind_and_upload(ctx, j) : RSL_OK;
+}
+
+static int require_bound(rsl_ctx* ctx, const rsl_job* j) {
+  return j->dmem ? RSL_OK : fail(ctx, RSL_EINVAL, "the job has no device memory yet (rsl_job_bind)");
 }
 
 // Re-point the job's problems at the current constant tables if they moved.
@@ -158,7 +170,7 @@ static int run_job(rsl_ctx* ctx, rsl_job* j, int mode) {
   mode &= ~RSL_GRAPH;
   if (mode == RSL_AUTO) mode = j->J.tune.mode;
   int rc;
-  if ((rc = job_refresh(ctx, j))) return rc;
+  if ((rc = require_bound(ctx, j)) || (rc = job_refresh(ctx, j))) return rc;
   if (graph && !ctx->profiling && !j->J.live.empty()) {
     if (j->graph_gen[mode] != ctx->table_gen && (rc = capture(ctx, j, mode))) return rc;
     return hip_check(ctx, hipGraphLaunch(j->graph[mode], ctx->stream), "graph launch");
@@ -227,6 +239,23 @@ int rsl_job_create(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, co
   return RSL_OK;
 }
 
+int rsl_job_bind(rsl_ctx* ctx, rsl_job* j, void* d_mem, size_t bytes) {
+  if (!ctx || !j || j->ctx != ctx || !d_mem) return RSL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  if (ctx->poisoned) return RSL_EDEVICE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, RSL_EDEVICE, "hipSetDevice");
+  // work of this job on the old memory may still be in flight
+  int rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+  if (rc) return rc;
+  j->dmem = static_cast<uint8_t*>(d_mem);
+  j->dmem_bytes = bytes;
+  if ((rc = bind_and_upload(ctx, j))) {
+    j->dmem = nullptr;
+    j->dmem_bytes = 0;
+  }
+  return rc;
+}
+
 int rsl_job_run(rsl_ctx* ctx, rsl_job* j, int mode) {
   if (!ctx || !j || j->ctx != ctx) return RSL_EINVAL;
   const int base = mode & ~RSL_GRAPH;
@@ -242,7 +271,7 @@ int rsl_job_results(rsl_ctx* ctx, rsl_job* j, rsl_result* out, int* status) {
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   if (ctx->poisoned) return RSL_EDEVICE;
   int rc;
-  if ((rc = job_download(ctx, &j->J, j->hdown, ctx->stream)) ||
+  if ((rc = require_bound(ctx, j)) || (rc = job_download(ctx, &j->J, j->hdown, ctx->stream)) ||
       (rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize")))
     return rc;
   rsl_counters cnt{};
@@ -292,6 +321,8 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
   if (!ctx || !j || j->ctx != ctx || reps < 1) return RSL_EINVAL;
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   if (ctx->poisoned) return RSL_EDEVICE;
+  int rc;
+  if ((rc = require_bound(ctx, j))) return rc;
   if (j->J.live.empty()) {
     if (best) *best = rsl_tune_result{RSL_STAGED, j->J.tune.chunk_target, 1, 1, 0, 0, 0, 0.0, 0.0};
     return RSL_OK;
@@ -315,10 +346,22 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
   std::vector<uint8_t> ref;
   TuneConfig win = cands[0];
   double win_ms = 1e300, worst_ms = 0.0;
-  int rc;
-  for (size_t ci = 0; ci < cands.size(); ++ci) {
+  bool any = false;
+  int timed = 0;
+  for (size_t ci = 0;; ++ci) {
+    if (ci == phase1) {  // phase two around the winner of phase one
+      if (!any) return fail(ctx, RSL_ENOMEM, "no schedule's layout fits the job's bound device memory");
+      for (int target : {1024, 16384}) cands.push_back(TuneConfig{win.mode, target, 1, win.evk, 0, win.schur});
+      cands.push_back(TuneConfig{win.mode, 4096, 1, win.evk, 1, win.schur});
+      if (win.mode == RSL_BATCHED) cands.push_back(TuneConfig{RSL_BATCHED, 4096, 2, win.evk, 0, 0});
+    }
+    if (ci >= cands.size()) break;
     const TuneConfig tc = cands[ci];
-    if ((rc = materialize(ctx, j, tc))) return rc;
+    rc = materialize(ctx, j, tc);
+    if (rc == RSL_ENOMEM) continue;  // this layout does not fit the bound memory
+    if (rc) return rc;
+    any = true;
+    ++timed;
     // warm-up run (also the correctness check), then `reps` timed runs
     if ((rc = run_job(ctx, j, tc.mode)) || (rc = job_download(ctx, &j->J, j->hdown, ctx->stream)) ||
         (rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize")))
@@ -360,16 +403,11 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
       win_ms = per;
       win = tc;
     }
-    if (ci + 1 == phase1) {  // phase two around the winner of phase one
-      for (int target : {1024, 16384}) cands.push_back(TuneConfig{win.mode, target, 1, win.evk, 0, win.schur});
-      cands.push_back(TuneConfig{win.mode, 4096, 1, win.evk, 1, win.schur});
-      if (win.mode == RSL_BATCHED) cands.push_back(TuneConfig{RSL_BATCHED, 4096, 2, win.evk, 0, 0});
-    }
   }
   if ((rc = materialize(ctx, j, win))) return rc;
   ctx->tune_cache[tune_key(j->J.n, j->f.data(), j->g.data(), j->var.data())] = TuneEntry{win, win_ms};
   if (best) *best = rsl_tune_result{win.mode, win.chunk_target, win.grid_mult, win.evk, win.conv_whole, win.schur,
-                                    static_cast<int32_t>(cands.size()), win_ms, worst_ms};
+                                    timed, win_ms, worst_ms};
   return RSL_OK;
 }
 
