@@ -641,6 +641,61 @@ def verify_batch(results, prefix="cfg4", full_cfg=4, modq_cfg=40, var="y"):
     return {"full_oracle_digests": n_full, "modq_checks": n_modq}
 
 
+def profile_batch(a):
+    """Only the device pipeline of the 512-pair batch, resident, a.profile_batch
+    runs of the layout a saved tuning choice picks: the launches a kernel trace or
+    counter run of this command sees are exactly those runs (plus the uploads)."""
+    import torch
+    import paper_1010_1386_amd as rsl
+    import workloads
+
+    probs = [(f, g, "y") for f, g in workloads.config4()]
+    ctx = rsl.Context(0, workspace_bytes=1 << 30)
+    if a.tune_load:
+        ctx.tune_load(a.tune_load)
+    job = ctx.job(probs)
+    info = job.info()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.profile_batch):
+        job.run("auto")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    job.close()
+    ctx.close()
+    return {"profile_batch_runs": a.profile_batch, "ms_per_run": dt / a.profile_batch * 1e3,
+            "layout_mode": info["layout_mode"], "eval_lanes": info["eval_lanes"],
+            "chunk_target": info["chunk_target"]}
+
+
+def profile_h2h(a):
+    """Only host-to-host batch calls of the 512-pair batch (a.profile_h2h of them,
+    after one warm-up call), laid out with a saved tuning choice: the timeline of
+    a kernel and copy trace of this command shows how host work and device work
+    of the chunk pipeline overlap."""
+    import torch
+    import paper_1010_1386_amd as rsl
+    import workloads
+
+    probs = [(f, g, "y") for f, g in workloads.config4()]
+    pb = rsl.PreparedBatch(probs)
+    ctx = rsl.Context(0, workspace_bytes=1 << 30)
+    if a.tune_load:
+        ctx.tune_load(a.tune_load)
+    pb.run(ctx, "auto")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    splits = []
+    for _ in range(a.profile_h2h):
+        pb.run(ctx, "auto")
+        splits.append(ctx.counters())
+    dt = time.perf_counter() - t0
+    ctx.close()
+    keys = ("ms_total", "ms_build", "ms_bind", "ms_device", "ms_decode")
+    return {"profile_h2h_calls": a.profile_h2h, "ms_per_call": dt / a.profile_h2h * 1e3,
+            "split_ms": {k: sum(c[k] for c in splits) / len(splits) for k in keys}}
+
+
 def batch_headline(a):
     import numpy as np
     import torch
@@ -657,6 +712,8 @@ def batch_headline(a):
     job = ctx.job(probs)
     tune = job.tune(reps=2)
     info = job.info()
+    if a.tune_save:  # the choice, for a profiled run of the same layout (--profile-batch)
+        ctx.tune_save(a.tune_save)
 
     def counters_sum(acc, c):
         for k in ("ms_total", "ms_build", "ms_bind", "ms_transfer", "ms_device", "ms_decode"):
@@ -830,6 +887,14 @@ def main():
                     help="square-free part of resultants by the modular gcd instead")
     ap.add_argument("--table3-only", default="", metavar="DEG:K[,DEG:K]",
                     help="with --table3: only these sets (e.g. 15:2048)")
+    ap.add_argument("--tune-save", default="", metavar="FILE",
+                    help="batch headline: save the autotuner's choice (rsl_tune_save) to FILE")
+    ap.add_argument("--tune-load", default="", metavar="FILE",
+                    help="--profile-batch: lay the batch out with the choice saved in FILE")
+    ap.add_argument("--profile-batch", type=int, default=0, metavar="K",
+                    help="only K device runs of the resident 512-pair batch (for kernel traces and counters)")
+    ap.add_argument("--profile-h2h", type=int, default=0, metavar="K",
+                    help="only K host-to-host batch calls of the 512-pair batch (for timeline traces)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
     a = ap.parse_args()
@@ -867,6 +932,12 @@ def main():
 
     if a.pair:
         print(json.dumps(pair_bench(a)))
+        return
+    if a.profile_batch:
+        print(json.dumps(profile_batch(a)))
+        return
+    if a.profile_h2h:
+        print(json.dumps(profile_h2h(a)))
         return
     out = batch_headline(a)
     print(json.dumps(out))

@@ -315,7 +315,9 @@ static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g
     if (!e) e = hip_check(ctx, hipStreamSynchronize(ctx->s_down), "hipStreamSynchronize");
     return e;
   };
-  std::vector<Job> jobs(S);
+  while (static_cast<int>(ctx->chunk_jobs.size()) < S) ctx->chunk_jobs.push_back(std::make_shared<Job>());
+  std::vector<Job*> jobs(S);
+  for (int c = 0; c < S; ++c) jobs[c] = ctx->chunk_jobs[c].get();
   std::vector<std::string> errs(S);
   std::vector<int> brc(S, RSL_OK);
   std::vector<char> ready(S, 0);
@@ -350,7 +352,7 @@ static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g
     const double tb = now_ms();
     for (int c = 0; c < S; ++c) {
       const int lo = ranges[c].first, hi = ranges[c].second;
-      Job& J = jobs[c];
+      Job& J = *jobs[c];
       job_plan(hi - lo, f + lo, g + lo, var + lo, opts, &J, &errs[c]);
       brc[c] = job_build(ctx, J.n, f + lo, g + lo, var + lo, opts, &J, &errs[c], tc, true, true);
       std::lock_guard<std::mutex> lk(mu);
@@ -369,7 +371,7 @@ static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g
       std::unique_lock<std::mutex> lk(mu);
       cv.wait(lk, [&] { return ready[c] != 0; });
     }
-    Job& J = jobs[c];
+    Job& J = *jobs[c];
     if (brc[c]) { rc = brc[c]; break; }
     if (J.live.empty()) { ++launched; continue; }
     if (J.total > ctx->ws_bytes) {
@@ -409,7 +411,7 @@ static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g
   // decode each launched chunk as soon as its copies are done
   double dec_ms = 0.0;
   for (int c = 0; c < launched; ++c) {
-    Job& J = jobs[c];
+    Job& J = *jobs[c];
     const int lo = ranges[c].first;
     if (!J.live.empty()) {
       const int e = hip_check(ctx, hipEventSynchronize(ctx->chunk_stage[c].e2), "hipEventSynchronize");
@@ -425,11 +427,9 @@ static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g
     if (status)
       for (int k = 0; k < J.n; ++k) status[lo + k] = stc[k];
     if (r && !rc) rc = r;
-    J = Job();  // free the chunk's host state while later chunks still run
   }
   producer.join();
   (void)sync_all();
-  std::vector<Job>().swap(jobs);
   cnt->ms_build += build_ms;
   cnt->ms_bind += bind_ms;
   cnt->ms_decode += dec_ms;
@@ -478,7 +478,8 @@ static int run_in_workspace(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_po
       }
     }
   }
-  Job J;
+  if (ctx->chunk_jobs.empty()) ctx->chunk_jobs.push_back(std::make_shared<Job>());
+  Job& J = *ctx->chunk_jobs[0];
   job_plan(n, f, g, var, opts, &J, &err);
   int rc = job_build(ctx, n, f, g, var, opts, &J, &err, tc, true);
   if (rc) {  // no layout (tables, options or LDS): nothing ran

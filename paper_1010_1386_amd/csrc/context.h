@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -28,6 +29,7 @@ struct TuneEntry {
   TuneConfig cfg;
   double ms = 0.0;            // measured time per run of the winning schedule
 };
+struct Job;
 }  // namespace rsl
 
 struct rsl_ctx {
@@ -75,6 +77,9 @@ struct rsl_ctx {
     hipEvent_t e3 = nullptr;                // after the upload
   };
   std::vector<ChunkStage> chunk_stage;
+  // host state of the batch calls' jobs (one per chunk), reused from call to
+  // call so that their large arrays keep their memory
+  std::vector<std::shared_ptr<rsl::Job>> chunk_jobs;
   // copy streams of the pipelined batch call (created on first use, default
   // priority): uploads and downloads of one chunk overlap the kernels of another
   hipStream_t s_up = nullptr, s_down = nullptr;

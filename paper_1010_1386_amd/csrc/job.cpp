@@ -279,53 +279,103 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       a.pdfr = b.dfr;
     }
 
-  // work items, problem by problem (so that each problem's items are contiguous)
-  J->hseg_items.clear();
-  for (int li = 0; li < nl; ++li) {
+  // work items, problem by problem (so that each problem's items are
+  // contiguous): each problem's items of each stage are counted, the lists
+  // sized, and every problem writes its own ranges (in parallel)
+  constexpr int kHsegList = kNumStages;  // the segment polynomials' list after the stage lists
+  auto emit = [&](int li, int s, WorkItem* out) -> int {
     const Plan& P = J->plans[J->live[li]];
     const DevProblem& d = J->dev[li];
-    ProbLayout& L = J->lay[li];
-    for (int s = 0; s < kNumStages; ++s) L.item_begin[s] = static_cast<int>(J->items[s].size());
-    // slots below skip_reduce are reduced by the partner (the same system in y);
-    // item slot 0 of block 0 also clears the statuses, so a problem whose
-    // slots are all shared keeps one such item
-    const int s0 = J->skip_reduce[li];
-    if (d.L_in > 2) {  // long limb chains: staged limbs, eight primes per thread
-      const int first = (s0 / kReduceMlSlots) * kReduceMlSlots;
-      for (int sl = first; sl < P.np; sl += kReduceMlSlots)
-        for (int b = 0; b < blocks_of(d.CS, kReduceMlCoeffs); ++b) J->items[kStageReduce].push_back({li, sl, b, 1});
-      // the item of (slot 0, block 0) clears the statuses: keep one whenever the
-      // partner reduces the leading slots (it recomputes the same values)
-      if (first > 0) J->items[kStageReduce].push_back({li, 0, 0, 1});
-    } else {
-      for (int sl = s0; sl < P.np; ++sl)
-        for (int b = 0; b < blocks_of(d.CS, 256); ++b) J->items[kStageReduce].push_back({li, sl, b, 0});
-      if (s0 > 0) J->items[kStageReduce].push_back({li, 0, 0, 0});
-    }
-    for (int sl = 0; sl < P.np; ++sl)
-      for (int b = 0; b < blocks_of(P.E + 1, d.evpb); ++b) J->items[kStageEval].push_back({li, sl, b, 0});
-    for (int sl = 0; sl < P.np; ++sl)
-      for (int b = 0; b < blocks_of(P.D + 1, 256); ++b)
-        for (int ch = 0; ch < d.ncchunk; ++ch)
-          if (ch * d.cchunk <= std::min(P.D, b * 256 + 255)) J->items[kStageConv].push_back({li, sl, b, ch});
-    // basis change: blocks of 256 columns
-    for (int sl = 0; sl < P.np; ++sl)
-      for (int b = 0; b < blocks_of(P.D + 1, 256); ++b)
-        for (int ch = 0; ch < d.nchunk; ++ch) {
-          const int ke = std::min(P.D, (ch + 1) * d.kchunk - 1);
-          if (ke >= b * 256) J->items[kStageStir].push_back({li, sl, b, ch});
+    int c = 0;
+    auto put = [&](int slot, int blk, int sub) {
+      if (out) out[c] = WorkItem{li, slot, blk, sub};
+      ++c;
+    };
+    switch (s) {
+      case kStageReduce: {
+        // slots below skip_reduce are reduced by the partner (the same system
+        // in y); item slot 0 of block 0 also clears the statuses, so a problem
+        // whose slots are all shared keeps one such item
+        const int s0 = J->skip_reduce[li];
+        if (d.L_in > 2) {  // long limb chains: staged limbs, eight primes per thread
+          const int first = (s0 / kReduceMlSlots) * kReduceMlSlots;
+          for (int sl = first; sl < P.np; sl += kReduceMlSlots)
+            for (int b = 0; b < blocks_of(d.CS, kReduceMlCoeffs); ++b) put(sl, b, 1);
+          if (first > 0) put(0, 0, 1);
+        } else {
+          for (int sl = s0; sl < P.np; ++sl)
+            for (int b = 0; b < blocks_of(d.CS, 256); ++b) put(sl, b, 0);
+          if (s0 > 0) put(0, 0, 0);
         }
-    L.hseg_begin = static_cast<int>(J->hseg_items.size());
-    for (int sl = 0; sl < P.np; ++sl)
-      for (int b = 0; b < blocks_of(P.D + 1, kHsegRows); ++b) J->hseg_items.push_back({li, sl, b, 0});
-    L.hseg_end = static_cast<int>(J->hseg_items.size());
-    // gapped interpolation is possible only with a non-constant leading
-    // coefficient (bad points) or a shifted origin
-    if (P.origin != 0 || (!P.formal && P.s > 0))
-      for (int sl = 0; sl < P.np; ++sl) J->items[kStageNewton].push_back({li, sl, 0, 0});
-    if (!P.wide)
-      for (int b = 0; b < blocks_of(P.D + 1, kCrtWaves); ++b) J->items[kStageCrt].push_back({li, -1, b, 0});
-    for (int s = 0; s < kNumStages; ++s) L.item_end[s] = static_cast<int>(J->items[s].size());
+        break;
+      }
+      case kStageEval:
+        for (int sl = 0; sl < P.np; ++sl)
+          for (int b = 0; b < blocks_of(P.E + 1, d.evpb); ++b) put(sl, b, 0);
+        break;
+      case kStageConv:
+        for (int sl = 0; sl < P.np; ++sl)
+          for (int b = 0; b < blocks_of(P.D + 1, 256); ++b)
+            for (int ch = 0; ch < d.ncchunk; ++ch)
+              if (ch * d.cchunk <= std::min(P.D, b * 256 + 255)) put(sl, b, ch);
+        break;
+      case kStageStir:  // basis change: blocks of 256 columns
+        for (int sl = 0; sl < P.np; ++sl)
+          for (int b = 0; b < blocks_of(P.D + 1, 256); ++b)
+            for (int ch = 0; ch < d.nchunk; ++ch)
+              if (std::min(P.D, (ch + 1) * d.kchunk - 1) >= b * 256) put(sl, b, ch);
+        break;
+      case kStageNewton:
+        // gapped interpolation is possible only with a non-constant leading
+        // coefficient (bad points) or a shifted origin
+        if (P.origin != 0 || (!P.formal && P.s > 0))
+          for (int sl = 0; sl < P.np; ++sl) put(sl, 0, 0);
+        break;
+      case kStageCrt:
+        if (!P.wide)
+          for (int b = 0; b < blocks_of(P.D + 1, kCrtWaves); ++b) put(-1, b, 0);
+        break;
+      case kHsegList:
+        for (int sl = 0; sl < P.np; ++sl)
+          for (int b = 0; b < blocks_of(P.D + 1, kHsegRows); ++b) put(sl, b, 0);
+        break;
+    }
+    return c;
+  };
+  {
+    constexpr int kLists = kNumStages + 1;
+    std::vector<int>& cnt = J->tmp_a;
+    cnt.assign(static_cast<size_t>(nl) * kLists, 0);
+    parallel_for(nl, 16, [&](int li) {
+      for (int s = 0; s < kLists; ++s) cnt[static_cast<size_t>(li) * kLists + s] = emit(li, s, nullptr);
+    });
+    std::vector<int>& off = J->tmp_b;
+    off.assign(cnt.size(), 0);
+    for (int s = 0; s < kLists; ++s) {
+      int o = 0;
+      for (int li = 0; li < nl; ++li) {
+        off[static_cast<size_t>(li) * kLists + s] = o;
+        o += cnt[static_cast<size_t>(li) * kLists + s];
+      }
+      std::vector<WorkItem>& v = s < kNumStages ? J->items[s] : J->hseg_items;
+      v.clear();
+      v.resize(o);
+    }
+    parallel_for(nl, 16, [&](int li) {
+      ProbLayout& L = J->lay[li];
+      for (int s = 0; s < kLists; ++s) {
+        const size_t at = static_cast<size_t>(li) * kLists + s;
+        std::vector<WorkItem>& v = s < kNumStages ? J->items[s] : J->hseg_items;
+        emit(li, s, v.data() + off[at]);
+        if (s < kNumStages) {
+          L.item_begin[s] = off[at];
+          L.item_end[s] = off[at] + cnt[at];
+        } else {
+          L.hseg_begin = off[at];
+          L.hseg_end = off[at] + cnt[at];
+        }
+      }
+    });
   }
 
   // wide CRT items, problem by problem
@@ -382,7 +432,8 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       std::vector<size_t> start(nv + 1, 0);
       for (const WorkItem& w : ev) ++start[var_of[w.prob] + 1];
       for (int v = 0; v < nv; ++v) start[v + 1] += start[v];
-      std::vector<WorkItem> sorted(ev.size());
+      std::vector<WorkItem>& sorted = J->tmp_items;
+      sorted.resize(ev.size());
       for (const WorkItem& w : ev) sorted[start[var_of[w.prob]]++] = w;
       ev.swap(sorted);
     }
@@ -397,16 +448,22 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     // the staged launches take the same items dealt so that all blocks of one
     // (problem, prime) run on the same XCD: workgroup i of a launch goes to
     // XCD i mod 8, so the prime's coefficient tile is fetched into one L2
-    // instead of eight
+    // instead of eight.  Per variant range: the g-th (problem, prime) of the
+    // range goes to bin g mod 8, and launch position t takes the next item of
+    // bin t mod 8 (of the bin with the most items left once that one is empty).
     constexpr int kXcds = 8;
-    J->eval_staged.clear();
+    J->eval_staged.resize(ev.size());
     J->eval_ranges.clear();
+    std::vector<int>& bin = J->tmp_a;
+    std::vector<int>& order = J->tmp_b;  // items of the range by bin, stable
+    bin.resize(ev.size());
+    order.resize(ev.size());
     size_t b0 = 0;
     while (b0 < ev.size()) {
       size_t b1 = b0;
       const int v = eval_variant(J->dev[ev[b0].prob]);
       while (b1 < ev.size() && eval_variant(J->dev[ev[b1].prob]) == v) ++b1;
-      std::vector<std::vector<WorkItem>> bins(kXcds);
+      size_t bsize[kXcds] = {}, bstart[kXcds + 1] = {}, pos[kXcds] = {};
       int pairs_seen = -1, last_prob = -1, last_slot = -1;
       for (size_t t = b0; t < b1; ++t) {
         if (ev[t].prob != last_prob || ev[t].slot != last_slot) {
@@ -414,20 +471,26 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
           last_prob = ev[t].prob;
           last_slot = ev[t].slot;
         }
-        bins[pairs_seen % kXcds].push_back(ev[t]);
+        bin[t] = pairs_seen % kXcds;
+        ++bsize[bin[t]];
       }
-      std::vector<size_t> pos(kXcds, 0);
+      for (int x = 0; x < kXcds; ++x) bstart[x + 1] = bstart[x] + bsize[x];
+      {
+        size_t fill[kXcds];
+        for (int x = 0; x < kXcds; ++x) fill[x] = bstart[x];
+        for (size_t t = b0; t < b1; ++t) order[b0 + fill[bin[t]]++] = static_cast<int>(t);
+      }
       for (size_t t = b0; t < b1; ++t) {
         int x = static_cast<int>((t - b0) % kXcds);
-        if (pos[x] >= bins[x].size()) {  // bin x is empty: take from the fullest
+        if (pos[x] >= bsize[x]) {  // bin x is empty: take from the fullest
           size_t best = 0;
           for (int y = 0; y < kXcds; ++y)
-            if (bins[y].size() - pos[y] > best) {
-              best = bins[y].size() - pos[y];
+            if (bsize[y] - pos[y] > best) {
+              best = bsize[y] - pos[y];
               x = y;
             }
         }
-        J->eval_staged.push_back(bins[x][pos[x]++]);
+        J->eval_staged[t] = ev[order[b0 + bstart[x] + pos[x]++]];
       }
       J->eval_ranges.push_back({v, static_cast<int>(b0), static_cast<int>(b1)});
       b0 = b1;
@@ -441,18 +504,37 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   J->sg_items.clear();
   J->sg_lds = 0;
   {
-    std::map<int, std::vector<StirMember>> by_prime;
+    // (problem, slot) members by global prime index: a stable counting sort
+    int gidx = 0;
     for (int li = 0; li < nl; ++li) {
       const Plan& P = J->plans[J->live[li]];
-      if (P.origin != 0) continue;
-      for (int sl = 0; sl < P.np; ++sl) by_prime[P.pidx[sl]].push_back(StirMember{li, sl});
+      if (P.origin == 0)
+        for (int sl = 0; sl < P.np; ++sl) gidx = std::max(gidx, P.pidx[sl] + 1);
+    }
+    std::vector<int> pstart(static_cast<size_t>(gidx) + 1, 0);
+    for (int li = 0; li < nl; ++li) {
+      const Plan& P = J->plans[J->live[li]];
+      if (P.origin == 0)
+        for (int sl = 0; sl < P.np; ++sl) ++pstart[P.pidx[sl] + 1];
+    }
+    for (int gi = 0; gi < gidx; ++gi) pstart[gi + 1] += pstart[gi];
+    std::vector<StirMember> by_prime(pstart[gidx]);
+    {
+      std::vector<int> fill(pstart.begin(), pstart.end() - 1);
+      for (int li = 0; li < nl; ++li) {
+        const Plan& P = J->plans[J->live[li]];
+        if (P.origin == 0)
+          for (int sl = 0; sl < P.np; ++sl) by_prime[fill[P.pidx[sl]]++] = StirMember{li, sl};
+      }
     }
     int gmax = kStirGroupMax;
     while (gmax > 1 && stir_group_lds_words(gmax, 256) > kLdsWords) --gmax;
-    for (const auto& kv : by_prime) {
-      const std::vector<StirMember>& mem = kv.second;
-      for (size_t b = 0; b < mem.size(); b += gmax) {
-        StirGroup G{kv.first, static_cast<int>(J->smembers.size()), static_cast<int>(std::min<size_t>(gmax, mem.size() - b)),
+    J->smembers.reserve(by_prime.size());
+    for (int prime = 0; prime < gidx; ++prime) {
+      const StirMember* mem = by_prime.data() + pstart[prime];
+      const size_t msize = static_cast<size_t>(pstart[prime + 1] - pstart[prime]);
+      for (size_t b = 0; b < msize; b += gmax) {
+        StirGroup G{prime, static_cast<int>(J->smembers.size()), static_cast<int>(std::min<size_t>(gmax, msize - b)),
                     0};
         for (int m = 0; m < G.count; ++m) {
           J->smembers.push_back(mem[b + m]);
@@ -493,6 +575,11 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     J->wide_off[pass] = o;
     o = align_up(o + sizeof(WorkItem) * J->wide_items[pass].size(), A);
   }
+  J->nclr = 0;
+  for (int li = 0; li < nl; ++li)
+    J->nclr += (J->dev[li].wide ? 1 : 0) + (J->dev[li].evmf ? 1 : 0) + (J->skip_reduce[li] > 0 ? 1 : 0);
+  J->clr_off = o;
+  o = align_up(o + sizeof(ClearRange) * J->nclr, A);
   // CRT constants are laid out once per prime list (problems with the same
   // canonical list share them)
   std::map<const CrtConst*, int> crt_owner;
@@ -753,6 +840,20 @@ void job_bind(Job* J, uint8_t* base, uint8_t* image, bool with_queue) {
     J->dev[li].presid = (pa >= 0) ? reinterpret_cast<uint32_t*>(base + J->lay[pa].resid) : nullptr;
     J->dev[li].pdig = (pa >= 0 && J->dev[pa].evmf) ? reinterpret_cast<uint64_t*>(base + J->lay[pa].dig) : nullptr;
   }
+  // the clear table: the t rows of the wide CRT (their padding stays zero),
+  // the digit tiles (only the coefficient positions are written) and the
+  // residue tiles a partner fills (its padding)
+  {
+    ClearRange* cr = reinterpret_cast<ClearRange*>(blob + J->clr_off);
+    int c = 0;
+    for (int li = 0; li < nl; ++li) {
+      const DevProblem& d = J->dev[li];
+      if (d.wide) cr[c++] = ClearRange{d.wT, static_cast<uint64_t>(d.wdpad) * d.wnpad};
+      if (d.evmf) cr[c++] = ClearRange{reinterpret_cast<uint32_t*>(d.dig), static_cast<uint64_t>(d.np) * d.dfr * 128};
+      if (J->skip_reduce[li] > 0)
+        cr[c++] = ClearRange{d.resid, static_cast<uint64_t>(J->skip_reduce[li]) * d.CS};
+    }
+  }
   // initial queue image: one REDUCE task per (problem, prime slot), largest problems first
   // (none when a problem has more primes than the persistent schedule takes)
   if (with_queue && J->max_np <= kMaxSlots) {
@@ -848,25 +949,9 @@ int job_upload(rsl_ctx* ctx, Job* J, hipStream_t st, uint8_t* pinned) {
 }
 
 int job_upload_clear(rsl_ctx* ctx, Job* J, hipStream_t st) {
-  int rc = RSL_OK;
-  // the residue tiles a partner fills get their padding cleared once (the
-  // partner writes only the coefficient positions)
-  for (size_t li = 0; !rc && li < J->live.size(); ++li)
-    if (J->dev[li].wide)  // padding of the t rows stays zero (pass 1 writes the rest)
-      rc = hip_check(ctx, launch_copy_words(J->dev[li].wT, nullptr,
-                                            static_cast<size_t>(J->dev[li].wdpad) * J->dev[li].wnpad, st),
-                     "clear t rows");
-  for (size_t li = 0; !rc && li < J->live.size(); ++li)
-    if (J->dev[li].evmf)  // digit tiles: only the coefficient positions are written
-      rc = hip_check(ctx, launch_copy_words(reinterpret_cast<uint32_t*>(J->dev[li].dig), nullptr,
-                                            static_cast<size_t>(J->dev[li].np) * J->dev[li].dfr * 128, st),
-                     "clear digit tiles");
-  for (size_t li = 0; !rc && li < J->live.size(); ++li)
-    if (J->skip_reduce[li] > 0)
-      rc = hip_check(ctx, launch_copy_words(J->dev[li].resid, nullptr,
-                                            static_cast<size_t>(J->skip_reduce[li]) * J->dev[li].CS, st),
-                     "clear shared tiles");
-  return rc;
+  // one launch over the clear table the upload brought (ordered after it)
+  return hip_check(ctx, launch_clear_ranges(reinterpret_cast<const ClearRange*>(J->base + J->clr_off), J->nclr, st),
+                   "clear ranges");
 }
 
 int job_reset(rsl_ctx* ctx, Job* J, hipStream_t st) {

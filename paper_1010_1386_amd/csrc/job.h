@@ -55,6 +55,10 @@ struct Job {
   // segment polynomials of the basis change (before the stir stage)
   std::vector<WorkItem> hseg_items;
   size_t hseg_off = 0;
+  // the ranges the kernels expect zeroed (a table in the upload image, cleared
+  // by one launch after the upload)
+  size_t clr_off = 0;
+  int nclr = 0;
   // wide CRT (problems with more primes than the per-lane slots cover): items of
   // its three passes
   std::vector<WorkItem> wide_items[3];
@@ -94,6 +98,10 @@ struct Job {
   int64_t mfma_macs = 0;           // int8 multiply-adds issued on the matrix cores for those sums
   int64_t interp_mm = 0;           // interpolation products: N_p (D+1)(D+2) over problems
   TuneConfig tune;                 // schedule parameters the job was laid out with
+  // scratch of job_build, kept with the job so that a job object reused for
+  // the next batch reuses its host memory (no fresh pages per call)
+  std::vector<WorkItem> tmp_items;
+  std::vector<int> tmp_a, tmp_b, tmp_c;
 };
 
 // Autotuner cache key of a batch (its shape bucket), from the inputs alone.

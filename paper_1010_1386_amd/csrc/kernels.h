@@ -38,5 +38,7 @@ hipError_t launch_stirling_build(uint32_t* stir, int64_t sstride, const PrimeCon
 
 // dst[t] = src[t] (or 0 when src is null) for t < n words.
 hipError_t launch_copy_words(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t st);
+// Zero every range of a device table of n ClearRanges in one launch.
+hipError_t launch_clear_ranges(const ClearRange* ranges, int n, hipStream_t st);
 
 }  // namespace rsl

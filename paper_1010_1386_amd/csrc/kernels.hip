@@ -275,6 +275,21 @@ hipError_t launch_copy_words(uint32_t* dst, const uint32_t* src, size_t n, hipSt
   return hipGetLastError();
 }
 
+// Workgroup b clears part (b mod kClearSplit) of range b / kClearSplit.
+constexpr int kClearSplit = 16;
+__global__ __launch_bounds__(256) void k_clear_ranges(const ClearRange* ranges) {
+  const ClearRange r = ranges[blockIdx.x / kClearSplit];
+  const size_t stride = static_cast<size_t>(kClearSplit) * 256;
+  for (size_t t = static_cast<size_t>(blockIdx.x % kClearSplit) * 256 + threadIdx.x; t < r.words; t += stride)
+    r.dst[t] = 0u;
+}
+
+hipError_t launch_clear_ranges(const ClearRange* ranges, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_clear_ranges, dim3(static_cast<unsigned>(n) * kClearSplit), dim3(256), 0, st, ranges);
+  return hipGetLastError();
+}
+
 hipError_t launch_stirling_build(uint32_t* stir, int64_t sstride, const PrimeConst* pcs, int g0,
                                  int count, int scap, hipStream_t st) {
   if (count <= 0) return hipSuccess;

@@ -272,7 +272,11 @@ void plan_crt(Plan* P) {
         g_crt.clear();
         g_crt_bytes = 0;
       }
-      if (g_crt.emplace(P->np, C).second) g_crt_bytes += b;
+      // a planner on another thread may have built the same list meanwhile:
+      // every plan takes the cached object, so that jobs share one block
+      auto ins = g_crt.emplace(P->np, C);
+      if (ins.second) g_crt_bytes += b;
+      else C = ins.first->second;
     }
   }
   P->crt = C;

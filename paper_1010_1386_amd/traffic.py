@@ -17,9 +17,12 @@ peak (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz; a wave64 VALU instruction
 takes four cycles of one SIMD).
 
 Usage:
-    python -m paper_1010_1386_amd.traffic FETCH_DIR WRITE_DIR COPYF_DIR COPYW_DIR \\
+    python -m paper_1010_1386_amd.traffic [--per-run K] FETCH_DIR WRITE_DIR COPYF_DIR COPYW_DIR \\
         KERNEL_PREFIX GRID COPY_BYTES OUT.json
-    python -m paper_1010_1386_amd.traffic --insts SQ_DIR MFMA_DIR KERNEL_PREFIX GRID OUT.json
+    python -m paper_1010_1386_amd.traffic [--per-run K] --insts SQ_DIR MFMA_DIR KERNEL_PREFIX GRID OUT.json
+
+GRID "any" takes every grid size; --per-run K sums the matching dispatches and
+divides by K (a stage of several launches, K pipeline runs profiled).
 """
 
 from __future__ import annotations
@@ -46,7 +49,10 @@ def sources_sha256():
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9  # lane operations per second
 
 
-def _per_dispatch(directory, prefix, grid=None, counter=None):
+def _per_dispatch(directory, prefix, grid=None, counter=None, steps=None):
+    """Mean counter value per dispatch of the matching kernels; with `steps`,
+    the sum over all matching dispatches divided by `steps` (per pipeline run,
+    when a stage is several launches)."""
     paths = glob.glob(os.path.join(directory, "*counter_collection.csv"))
     if not paths:
         raise FileNotFoundError(f"no counter_collection.csv under {directory}")
@@ -60,17 +66,18 @@ def _per_dispatch(directory, prefix, grid=None, counter=None):
                 vals.append(float(row["Counter_Value"]))
     if not vals:
         raise ValueError(f"no dispatch of {prefix!r} (grid {grid}) in {paths[0]}")
-    return sum(vals) / len(vals)
+    return sum(vals) / (steps if steps else len(vals))
 
 
-def summarize(fetch_dir, write_dir, copyf_dir, copyw_dir, prefix, grid, copy_bytes):
-    fetch_kib = _per_dispatch(fetch_dir, prefix, grid)
-    write_kib = _per_dispatch(write_dir, prefix, grid)
+def summarize(fetch_dir, write_dir, copyf_dir, copyw_dir, prefix, grid, copy_bytes, steps=None):
+    fetch_kib = _per_dispatch(fetch_dir, prefix, grid, steps=steps)
+    write_kib = _per_dispatch(write_dir, prefix, grid, steps=steps)
     copy_fetch_kib = _per_dispatch(copyf_dir, "__amd_rocclr_copyBuffer")
     copy_write_kib = _per_dispatch(copyw_dir, "__amd_rocclr_copyBuffer")
     return {
         "kernel_prefix": prefix,
         "grid_size": grid,
+        "per": "pipeline run (all matching launches)" if steps else "dispatch",
         "fetch_kib_per_dispatch": fetch_kib,
         "write_kib_per_dispatch": write_kib,
         "copy_bytes": copy_bytes,
@@ -91,12 +98,13 @@ def traffic_bytes(record):
                      record["write_kib_per_dispatch"] * record["write_factor"])
 
 
-def summarize_insts(sq_dir, mfma_dir, prefix, grid):
-    rec = {"kernel_prefix": prefix, "grid_size": grid}
+def summarize_insts(sq_dir, mfma_dir, prefix, grid, steps=None):
+    rec = {"kernel_prefix": prefix, "grid_size": grid,
+           "per": "pipeline run (all matching launches)" if steps else "dispatch"}
     for key, counter in (("waves", "SQ_WAVES"), ("valu_insts", "SQ_INSTS_VALU"), ("salu_insts", "SQ_INSTS_SALU"),
                          ("lds_insts", "SQ_INSTS_LDS")):
-        rec[key] = _per_dispatch(sq_dir, prefix, grid, counter)
-    rec["mfma_insts"] = _per_dispatch(mfma_dir, prefix, grid, "SQ_INSTS_MFMA")
+        rec[key] = _per_dispatch(sq_dir, prefix, grid, counter, steps)
+    rec["mfma_insts"] = _per_dispatch(mfma_dir, prefix, grid, "SQ_INSTS_MFMA", steps)
     rec["sources_sha256"] = sources_sha256()
     return rec
 
@@ -111,8 +119,12 @@ def valu_issue(record, launch_s):
 
 
 def main(argv):
+    steps = None
+    if len(argv) > 2 and argv[1] == "--per-run":  # --per-run K: sums over K pipeline runs, all grids
+        steps = int(argv[2])
+        argv = argv[:1] + argv[3:]
     if len(argv) == 7 and argv[1] == "--insts":
-        rec = summarize_insts(argv[2], argv[3], argv[4], argv[5])
+        rec = summarize_insts(argv[2], argv[3], argv[4], None if argv[5] == "any" else argv[5], steps)
         with open(argv[6], "w") as fh:
             json.dump(rec, fh, indent=1)
             fh.write("\n")
@@ -121,7 +133,8 @@ def main(argv):
     if len(argv) != 9:
         print(__doc__, file=sys.stderr)
         return 2
-    rec = summarize(argv[1], argv[2], argv[3], argv[4], argv[5], argv[6], int(argv[7]))
+    rec = summarize(argv[1], argv[2], argv[3], argv[4], argv[5], None if argv[6] == "any" else argv[6],
+                    int(argv[7]), steps)
     with open(argv[8], "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
