@@ -696,6 +696,13 @@ def profile_h2h(a):
             "split_ms": {k: sum(c[k] for c in splits) / len(splits) for k in keys}}
 
 
+def tune_line(t):
+    """The autotuner's choice as it is saved (mode, chunking, grid, lanes, convolution, Schur)."""
+    names = {"staged": 2, "batched": 1}
+    return [names.get(t["mode"], t["mode"]), t["chunk_target"], t["grid_mult"], t["lanes_per_pair"],
+            t["conv_whole"], t["schur"]]
+
+
 def batch_headline(a):
     import numpy as np
     import torch
@@ -811,6 +818,41 @@ def batch_headline(a):
                          "padded 16x16x32 tiles"},
         "all_products_frac": info["mulmods"] / t_eval / 1e12 / PEAK_TMULMOD,
     }
+    # the same launches against the measured issue rates of the units
+    # (paper_1010_1386_amd.peak: eight chains per lane, 4 or 8 waves per SIMD)
+    try:
+        from paper_1010_1386_amd import peak as peakmod
+        rates = peakmod.measure()
+        mont = rates["montgomery_mul"] / 1e12
+        roofline["measured_peak"] = {
+            "montgomery_tmulmod_s": mont, "fused_update_t_s": rates["fused_update_3_products"] / 1e12,
+            "mfma_int8_top_s": 2.0 * rates["mfma_i32_16x16x32_i8_macs"] / 1e12,
+            "valu_frac_of_measured": valu_mm / t_eval / 1e12 / mont,
+            "mfma_frac_of_measured": macs / t_eval / rates["mfma_i32_16x16x32_i8_macs"],
+            "rates": rates, "source": "paper_1010_1386_amd/peak.py (csrc/peak.hip)"}
+    except Exception as e:  # measurement is auxiliary: report, never fail the line
+        roofline["measured_peak"] = {"error": str(e)}
+    # HBM bytes and VALU instructions of the evaluation stage per run, from the
+    # committed counter summaries of the same kernel sources and layout choice
+    for key, fname in (("traffic", "traffic_eval_ures_cfg4_batch.json"), ("insts", "insts_eval_ures_cfg4_batch.json")):
+        path = os.path.join(ROOT, "profiles", fname)
+        if not os.path.exists(path):
+            continue
+        from paper_1010_1386_amd import traffic as tr
+        with open(path) as fh:
+            rec = json.load(fh)
+        if rec.get("tune_line") != tune_line(tune):
+            continue
+        if key == "traffic":
+            b = tr.traffic_bytes(rec)
+            if b is not None:
+                roofline["traffic"] = b
+                roofline["traffic_gbs"] = b / t_eval / 1e9
+        else:
+            vi = tr.valu_issue(rec, t_eval)
+            if vi is not None:
+                roofline["valu_issue"] = {"lane_ops_per_run": vi[0], "frac_of_issue_peak": vi[1],
+                                          "mfma_insts_per_run": rec["mfma_insts"]}
     out = {
         "metric": METRIC,
         "value": value,

@@ -115,7 +115,7 @@ typedef struct {
 typedef struct {
   int32_t D;            /* degree bound used for interpolation (paper Sec. 3.1: deg R <= m n) */
   int32_t bound_bits;   /* bits of the Hadamard bound B with |coeff of R| <= B */
-  int32_t n_primes;     /* number of 31-bit primes, prod p > 2B */
+  int32_t n_primes;     /* number of primes (2^30 < p < 2^32/3), prod p > 2B */
   int32_t n_points;     /* evaluation points per prime: D + 1 + s */
   int32_t out_limbs;    /* limbs that always suffice for every coefficient */
   int32_t my, ny;       /* actual degrees in the eliminated variable */

@@ -20,6 +20,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librsl.so")
+PEAK_LIB = os.path.join(PKG, "libpeak.so")
 
 SOURCES = ["kernels.hip", "api.cpp", "plan.cpp", "job.cpp", "tune.cpp", "server.cpp", "persistent.hip", "gcd.cpp",
            "noalloc.cpp"]
@@ -66,6 +67,13 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
+    # issue-rate microbenchmarks of the units the kernels use (measurement only)
+    pk_obj, _ = _compile("peak.hip")
+    r = subprocess.run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", PEAK_LIB + ".tmp", pk_obj],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("peak library link failed:\n" + r.stdout + r.stderr)
+    os.replace(PEAK_LIB + ".tmp", PEAK_LIB)
     # host build of the per-lane arithmetic, used only by CPU tests
     hs_src = os.path.join(ROOT, "tests", "hostsim", "hostsim.cpp")
     if os.path.exists(hs_src):

@@ -1,4 +1,4 @@
-// Arithmetic modulo 31-bit primes p < 2^31 in Montgomery form, R = 2^32.
+// Arithmetic modulo primes 2^30 < p < 2^32 / 3 in Montgomery form, R = 2^32.
 //
 // Shared by the device kernels and the host planner (all functions are
 // __host__ __device__).  On gfx950 the 32x32->64 multiply (v_mad_u64_u32) and
@@ -15,7 +15,7 @@ namespace rsl {
 #define RSL_HD __host__ __device__ __forceinline__
 
 struct PrimeConst {
-  uint32_t p;     // the prime, 2^30 < p < 2^31
+  uint32_t p;     // the prime, 2^30 < p < 2^32 / 3
   uint32_t pinv;  // -p^{-1} mod 2^32
   uint32_t r1;    // R mod p        (Montgomery form of 1)
   uint32_t r2;    // R^2 mod p      (to enter Montgomery form)
@@ -44,16 +44,13 @@ RSL_HD uint32_t mmulsub(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t
   return redc(t, p, pinv);
 }
 
-// (a b + c d + e f) / R mod p for all operands <= p: the sum is < 3 p^2 + 3p < 2^64
-// and its high word is below 1.5 p, so one conditional subtraction of p R on
-// the high word brings it below p R.
+// (a b + c d + e f) / R mod p for all operands <= p: the sum is at most 3 p^2,
+// below p R because 3p < 2^32 for every prime of the table, so it goes to REDC
+// as it is (three multiply-adds and one reduction).
 RSL_HD uint32_t mmad3(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t e, uint32_t f,
                       uint32_t p, uint32_t pinv) {
-  uint64_t t = static_cast<uint64_t>(a) * b + static_cast<uint64_t>(c) * d +
-               static_cast<uint64_t>(e) * f;
-  uint32_t hi = static_cast<uint32_t>(t >> 32);
-  hi = umin32(hi, hi - p);
-  t = (static_cast<uint64_t>(hi) << 32) | static_cast<uint32_t>(t);
+  const uint64_t t = static_cast<uint64_t>(a) * b + static_cast<uint64_t>(c) * d +
+                     static_cast<uint64_t>(e) * f;
   return redc(t, p, pinv);
 }
 

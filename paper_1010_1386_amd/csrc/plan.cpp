@@ -32,7 +32,7 @@ uint64_t powmod64(uint64_t a, uint64_t e, uint64_t m) {
 
 std::mutex g_prime_mu;
 std::vector<uint32_t> g_primes;
-uint32_t g_next_candidate = 0x7FFFFFFFu;  // 2^31 - 1
+uint32_t g_next_candidate = 1431655765u;  // floor(2^32 / 3): every prime p of the table has 3p < 2^32
 
 constexpr size_t kPrimeTableMax = 1u << 16;
 

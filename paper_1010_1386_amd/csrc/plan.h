@@ -16,8 +16,8 @@
 
 namespace rsl {
 
-// Descending 31-bit primes below 2^31 (index 0 = largest); grows on demand.
-// The table of 31-bit primes (descending from 2^31 - 1), extended to at least
+// Descending primes below 2^32 / 3 (index 0 = largest; all above 2^30); grows on demand.
+// The table of primes p with 2^30 < p < 2^32 / 3 (descending), extended to at least
 // `at_least` entries (capped at its maximum; *avail = entries present).  The
 // pointer stays valid for the life of the process; entries below *avail, or
 // below an index a previous call reported, may be read without a lock.

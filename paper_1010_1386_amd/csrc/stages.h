@@ -116,7 +116,7 @@ __device__ __forceinline__ void horner_step2x2(uint32_t* a, uint32_t* b, uint32_
 // With zero_status, the block of (slot 0, block 0) also clears the problem's
 // status words (a launch that runs before every other stage of the problem).
 // A two's complement value of L limbs mod p, without divisions: the signed top
-// limb plus 2p lies in (0, 4p) since 2^30 < p < 2^31; each lower limb w (< 4p)
+// limb plus 2p lies in (0, 4p) since p > 2^30; each lower limb w (< 2^32 < 4p)
 // enters as r <- r 2^32 + w, with r 2^32 mod p = mmul(r, R^2).
 __device__ inline uint32_t limbs_mod_p(const uint32_t* wd, int L, const PrimeConst& pc) {
   const uint32_t p = pc.p;
@@ -262,7 +262,7 @@ __device__ inline void stage_reduce_ml(const DevProblem& P, const DevTables& T, 
     for (int l = nl - 1; l >= 0; --l) {
       const uint32_t wd = lds[l * (kReduceMlCoeffs + 1) + c];
       if (l0 + l == L - 1) {
-        // the signed top limb plus 2p lies in (0, 4p) since 2^30 < p < 2^31
+        // the signed top limb plus 2p lies in (0, 4p) since p > 2^30
 #pragma unroll
         for (int r = 0; r < kPer; ++r) {
           uint64_t x = static_cast<uint64_t>(static_cast<int64_t>(static_cast<int32_t>(wd)) + 2 * static_cast<int64_t>(p[r]));
@@ -720,7 +720,7 @@ __device__ inline void stage_eval_ures_regs2(const DevProblem& P, const DevTable
 // matrix cores into the nine anti-diagonal sums S_s = sum_{a+b=s} V_a C_b,
 // each below 5 * 32 * 127^2 < 2^22, and
 //   f_j(x_k) R mod p = REDC(sum_s S_s (2^{7s} R^2 mod p))
-// (a sum below 9 * 2^22 * 2^31 < p 2^32).  Tiles of 16 points x 16 rows;
+// (a sum below 9 * 2^22 * p < p 2^32).  Tiles of 16 points x 16 rows;
 // lane l of a 16x16x32 product holds A row l mod 16 (a point) and B column
 // l mod 16 (a row) for the K slice 8 (l / 16) .. 8 (l / 16) + 7, and gets the
 // outputs [4 (l / 16) + r][l mod 16], r < 4.  The values go through LDS into

@@ -41,8 +41,9 @@ def test_version_and_strerror(rsl):
     assert rsl._lib.rsl_strerror(0) == b"ok"
 
 
-def _primes_below_2_31(n):
-    return oracle.next_check_primes(n, below=1 << 31)
+def _table_primes(n):
+    # the library's table: the primes below 2^32 / 3, descending
+    return oracle.next_check_primes(n, below=(1 << 32) // 3 + 1)
 
 
 @pytest.mark.parametrize("seed", range(12))
@@ -57,7 +58,7 @@ def test_query_matches_oracle_bounds(rsl, seed):
         assert q["D"] == oracle.degree_bound(F, G, var)
         B2 = oracle.hadamard_bound_sq(F, G, var)
         assert abs(q["bound_bits"] - (B2.bit_length() + 1) // 2) <= 1
-        ps = _primes_below_2_31(q["n_primes"])  # no bad primes for these inputs
+        ps = _table_primes(q["n_primes"])  # no bad primes for these inputs
         M = math.prod(ps)
         assert M * M > 4 * B2
         assert (M // ps[-1]) ** 2 <= 4 * B2
@@ -88,7 +89,7 @@ def test_query_rejects_bad_arguments(rsl):
 
 
 def test_bad_prime_detected_by_planner(rsl):
-    p0 = 2147483647
+    p0 = 1431655751  # the first prime of the table
     F = [[1, 2, 3], [5, 0, 1], [p0 * 3, p0 * 2]]
     G = [[2, 1], [1, 1, 1], [3]]
     assert rsl.query(F, G, "y")["bad_primes"] == 1

@@ -114,7 +114,7 @@ def test_self_consistency_primes_and_points(ctx):
 def test_bad_prime_is_skipped(ctx):
     """lc_y f = p_0 * c: the largest prime divides the leading coefficient."""
     import paper_1010_1386_amd as rsl
-    p0 = 2147483647  # largest prime below 2^31, first in the table
+    p0 = 1431655751  # largest prime below 2^32 / 3, first in the table
     F = [[1, 2, 3], [5, 0, 1], [p0 * 3, p0 * 2]]
     G = [[2, 1], [1, 1, 1], [3]]
     info = rsl.query(F, G, "y")
