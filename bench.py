@@ -108,23 +108,41 @@ def serve_bench(n):
 
     Saturated throughput T of the server (all requests submitted at once), then
     Poisson arrivals at 0.5 T, 0.8 T and 1.0 T with p50/p99 latency, against the
-    serial plain path (one rsl_res call after the other)."""
+    serial plain path (one rsl_res call after the other).  Both sides go from
+    the callers' prepared inputs to result limbs (the conversion to Python ints
+    is left out of both), and every server result is compared with the plain
+    path's, limb for limb."""
+    import ctypes
     import threading
     import numpy as np
     import paper_1010_1386_amd as rsl
     import workloads
 
     reqs = workloads.config5(n)
-    polys = [(rsl.Poly(f), rsl.Poly(g), v) for f, g, v in reqs]
-    ctx = rsl.Context(0, workspace_bytes=1 << 30)
-    # serial plain path (also warms the constant tables for the largest shapes)
-    lat_plain = []
-    t0 = time.perf_counter()
+    polys = [(rsl.Poly(f), rsl.Poly(g), rsl._var_code(v)) for f, g, v in reqs]
+    outs = []
     for f, g, v in polys:
-        t1 = time.perf_counter()
-        ctx.res(f, g, v)
-        lat_plain.append((time.perf_counter() - t1) * 1e3)
-    plain_rate = n / (time.perf_counter() - t0)
+        info = rsl.rsl_info()
+        rsl._lib.rsl_query(ctypes.byref(f.c), ctypes.byref(g.c), v, ctypes.byref(info))
+        outs.append(rsl._Result(max(info.D, 0), info.out_limbs))
+    ctx = rsl.Context(0, workspace_bytes=1 << 30)
+    opts = rsl.rsl_opts()
+
+    def plain_pass():
+        lat = []
+        t0 = time.perf_counter()
+        for (f, g, v), o in zip(polys, outs):
+            t1 = time.perf_counter()
+            rc = rsl._lib.rsl_res(ctx.h, ctypes.byref(f.c), ctypes.byref(g.c), v, ctypes.byref(opts),
+                                  ctypes.byref(o.c))
+            if rc:
+                raise rsl.RSLError(rc, "rsl_res")
+            lat.append((time.perf_counter() - t1) * 1e3)
+        return n / (time.perf_counter() - t0), lat
+
+    plain_pass()  # warms the constant tables for the largest shapes
+    plain_rate, lat_plain = plain_pass()
+    want = [o.raw() for o in outs]
 
     def run(rate, budget=64 << 20):
         srv = rsl.Server(ctx, budget_bytes=budget, max_slots=256, max_queue=1 << 20)
@@ -143,15 +161,18 @@ def serve_bench(n):
         th = threading.Thread(target=producer)
         th.start()
         th.join()
-        for t in tickets:
-            srv.wait(t)
+        got = [srv.wait(t, raw=True) for t in tickets]
         wall = time.perf_counter() - t_start
         st = srv.stats()
         srv.close()
+        if [o.raw() for o in got] != want:
+            print("bench: a served result differs from the plain path", file=sys.stderr)
+            sys.exit(1)
         return {"offered_rps": rate, "completed": st["completed"], "resultants_per_s": n / wall,
                 "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
                 "device_iterations": st["launches"], "max_batch": st["max_batch"],
-                "admitted_bytes_peak": st["admitted_bytes_peak"], "budget_bytes": budget}
+                "admitted_bytes_peak": st["admitted_bytes_peak"], "budget_bytes": budget,
+                "verified_vs_plain": True}
 
     sat = run(None)
     T = sat["resultants_per_s"]
@@ -159,7 +180,8 @@ def serve_bench(n):
     ctx.close()
     return {"metric": "serving: resultants/s and latency, continuous batching vs serial plain path",
             "requests": n, "workload": "degrees U{8..48}, signed U{8..48}-bit, dense, res_y/res_x w.p. 1/2",
-            "saturated": sat, "poisson": loads,
+            "boundary": "prepared inputs to result limbs on both sides",
+            "saturated": sat, "poisson": loads, "saturated_vs_serial": T / plain_rate,
             "serial_plain": {"resultants_per_s": plain_rate, "p50_ms": float(np.percentile(lat_plain, 50)),
                              "p99_ms": float(np.percentile(lat_plain, 99))}}
 

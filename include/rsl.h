@@ -412,9 +412,17 @@ typedef struct {
  */
 int rsl_server_create(rsl_ctx *ctx, size_t budget_bytes, int max_slots, int max_queue,
                       rsl_server **out);
-/* Copy the inputs and enqueue; `out` must stay valid until completion. */
+/* Copy the inputs, plan and enqueue; `out` must stay valid until completion. */
 int rsl_server_submit(rsl_server *s, const rsl_poly *f, const rsl_poly *g, int var,
                       rsl_result *out, uint64_t *ticket);
+/* The same in two steps, for a caller that sizes `out` from the plan: copy the
+ * inputs and plan the request (info as rsl_query's; RSL_ENOMEM when its tables
+ * would not fit the context's table region), then queue it under `handle`
+ * with its result buffer.  The request is planned once; the scheduler lays
+ * out its batches from those plans.  A handle is used by one enqueue. */
+int rsl_server_plan(rsl_server *s, const rsl_poly *f, const rsl_poly *g, int var, rsl_info *info,
+                    uint64_t *handle);
+int rsl_server_enqueue(rsl_server *s, uint64_t handle, rsl_result *out, uint64_t *ticket);
 /* 1 if done (status in *status), 0 if still in flight. */
 int rsl_server_poll(rsl_server *s, uint64_t ticket, int *status);
 /* Wait up to timeout_ms (< 0: forever); returns the request status or RSL_ETIMEDOUT. */

@@ -125,6 +125,9 @@ _SIGS = {
     "rsl_server_create": (ctypes.c_int, [_vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, _P(_vp)]),
     "rsl_server_submit": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), ctypes.c_int, _P(rsl_result),
                                          _P(ctypes.c_uint64)]),
+    "rsl_server_plan": (ctypes.c_int, [_vp, _P(rsl_poly), _P(rsl_poly), ctypes.c_int, _P(rsl_info),
+                                       _P(ctypes.c_uint64)]),
+    "rsl_server_enqueue": (ctypes.c_int, [_vp, ctypes.c_uint64, _P(rsl_result), _P(ctypes.c_uint64)]),
     "rsl_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, _P(ctypes.c_int)]),
     "rsl_server_wait": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_int]),
     "rsl_server_stats": (ctypes.c_int, [_vp, _P(rsl_stats)]),
@@ -233,6 +236,11 @@ class _Result:
     def __init__(self, cap_deg, limbs):
         self.buf = np.zeros(max(1, (cap_deg + 1) * limbs), dtype=np.uint32)
         self.c = rsl_result(cap_deg, limbs, self.buf.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), 0, 0)
+
+    def raw(self):
+        """(degree, limbs, the used limb words as bytes): the result without conversion."""
+        deg, L = self.c.deg, self.c.limbs
+        return deg, L, self.buf[:max(deg + 1, 0) * L].tobytes()
 
     def value(self):
         deg, L = self.c.deg, self.c.limbs

@@ -31,6 +31,11 @@ namespace rsl {
 namespace {
 
 constexpr int kLanes = 3;  // batches in flight at once, one HIP stream each
+// Layout of the server's batches: the interpolation sums taken whole (one
+// chunk), which keeps each request's footprint -- and so the budget's share
+// per request -- a few times smaller than the throughput layout of large
+// batch calls; a batch of many requests has enough blocks in flight anyway.
+const TuneConfig kServeLayout{RSL_STAGED, 64, 1, 0, 1, 0};
 constexpr int kTablesFull = -1000;  // launch(): the table region cannot cover the group
 
 struct Request {
@@ -39,6 +44,7 @@ struct Request {
   rsl_poly f{}, g{};
   int var = RSL_Y;
   rsl_result* out = nullptr;
+  Plan plan;                 // planned once, at submit; the batch layout reuses it
   size_t footprint = 0;
   double t_submit = 0.0;
   bool done = false;
@@ -132,6 +138,9 @@ struct rsl_server {
   std::deque<std::shared_ptr<rsl::Request>> pending;
   std::unordered_map<uint64_t, std::shared_ptr<rsl::Request>> tickets;
   uint64_t next_ticket = 1;
+  // planned requests not queued yet (rsl_server_plan -> rsl_server_enqueue)
+  std::unordered_map<uint64_t, std::shared_ptr<rsl::Request>> planned;
+  uint64_t next_handle = 1;
   bool stop = false;
   std::thread th;
   rsl::Arena arena;
@@ -191,12 +200,21 @@ int launch(rsl_server* S, Lane& ln, std::vector<std::shared_ptr<Request>>& grp) 
     g[k] = grp[k]->g;
     var[k] = grp[k]->var;
   }
+  // the requests' plans from submit: only the layout of the group is new
   Job J;
+  J.n = n;
+  J.plans.resize(n);
+  J.pstatus.assign(n, 0);
+  J.live.clear();
+  for (int k = 0; k < n; ++k) {
+    J.plans[k] = grp[k]->plan;
+    if (!J.plans[k].zero) J.live.push_back(k);
+  }
   std::string err;
   int rc;
   {
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-    rc = job_build(ctx, n, f.data(), g.data(), var.data(), nullptr, &J, &err);
+    rc = job_build(ctx, n, f.data(), g.data(), var.data(), nullptr, &J, &err, &kServeLayout, /*planned=*/true);
   }
   if (rc) return rc == RSL_ENOMEM ? kTablesFull : rc;  // waiting frees no table room
   size_t off = 0;
@@ -336,9 +354,10 @@ int rsl_server_create(rsl_ctx* ctx, size_t budget_bytes, int max_slots, int max_
   return RSL_OK;
 }
 
-int rsl_server_submit(rsl_server* S, const rsl_poly* f, const rsl_poly* g, int var, rsl_result* out,
-                      uint64_t* ticket) {
-  if (!S || !f || !g || !out || !ticket) return RSL_EINVAL;
+// Plan the request (host only): sizes, footprint, admission against the
+// table region.  On success *rp holds the request, not yet queued.
+static int plan_request(rsl_server* S, const rsl_poly* f, const rsl_poly* g, int var,
+                        std::shared_ptr<Request>* rp, rsl_info* info) {
   auto r = std::make_shared<Request>();
   auto copy = [](const rsl_poly* p, std::vector<uint32_t>* buf, rsl_poly* dst) {
     if (!p->coeff || p->dx < 0 || p->dy < 0 || p->limbs < 1) return false;
@@ -349,14 +368,33 @@ int rsl_server_submit(rsl_server* S, const rsl_poly* f, const rsl_poly* g, int v
   };
   if (!copy(f, &r->fc, &r->f) || !copy(g, &r->gc, &r->g) || (var != RSL_Y && var != RSL_X)) return RSL_EINVAL;
   r->var = var;
-  r->out = out;
-  // footprint from the host plan of this request alone
+  // the one plan of this request, and its footprint from the layout of it alone
   Job J;
   std::string err;
-  int rc = job_build(nullptr, 1, &r->f, &r->g, &r->var, nullptr, &J, &err);
+  int rc = job_build(nullptr, 1, &r->f, &r->g, &r->var, nullptr, &J, &err, &kServeLayout);
   if (rc) return rc;
   if (J.pstatus[0]) return J.pstatus[0];
   r->footprint = std::max<size_t>(J.total, 256);
+  if (info) {
+    const Plan& P = J.plans[0];
+    *info = rsl_info{};
+    if (P.zero) {  // as rsl_query: R = 0
+      info->D = -1;
+      info->my = P.f.dy;
+      info->ny = P.g.dy;
+      info->out_limbs = 1;
+    } else {
+      info->D = P.D;
+      info->bound_bits = P.bound_bits;
+      info->n_primes = P.np;
+      info->n_points = P.E + 1;
+      info->out_limbs = P.L_out;
+      info->my = P.my;
+      info->ny = P.ny;
+      info->bad_primes = P.bad_primes;
+    }
+    info->footprint_bytes = J.total;
+  }
   {
     // the constant tables this request needs (with what the context holds) must fit the table region
     rsl_ctx* ctx = S->ctx;
@@ -364,6 +402,7 @@ int rsl_server_submit(rsl_server* S, const rsl_poly* f, const rsl_poly* g, int v
     int cn, ck, cs;
     table_caps(J.need_g, J.need_E, J.need_D, &cn, &ck, &cs);
     const size_t tb = table_layout(std::max(cn, ctx->npcap), std::max(ck, ctx->kcap), std::max(cs, ctx->scap)).total;
+    if (info) info->table_bytes = tb;
     if (tb > ctx->tab_bytes) {
       std::lock_guard<std::mutex> lk(S->mu);
       S->rejected += 1;
@@ -371,6 +410,14 @@ int rsl_server_submit(rsl_server* S, const rsl_poly* f, const rsl_poly* g, int v
                                        " bytes, the table region has " + std::to_string(ctx->tab_bytes));
     }
   }
+  r->plan = std::move(J.plans[0]);
+  *rp = std::move(r);
+  return RSL_OK;
+}
+
+// Queue a planned request with its result buffer (server lock not held).
+static int enqueue(rsl_server* S, std::shared_ptr<Request> r, rsl_result* out, uint64_t* ticket) {
+  r->out = out;
   std::lock_guard<std::mutex> lk(S->mu);
   if (r->footprint > S->budget) {
     S->rejected += 1;
@@ -388,6 +435,41 @@ int rsl_server_submit(rsl_server* S, const rsl_poly* f, const rsl_poly* g, int v
   *ticket = r->ticket;
   S->cv_sched.notify_one();
   return RSL_OK;
+}
+
+int rsl_server_submit(rsl_server* S, const rsl_poly* f, const rsl_poly* g, int var, rsl_result* out,
+                      uint64_t* ticket) {
+  if (!S || !f || !g || !out || !ticket) return RSL_EINVAL;
+  std::shared_ptr<Request> r;
+  int rc = plan_request(S, f, g, var, &r, nullptr);
+  if (rc) return rc;
+  return enqueue(S, std::move(r), out, ticket);
+}
+
+int rsl_server_plan(rsl_server* S, const rsl_poly* f, const rsl_poly* g, int var, rsl_info* info,
+                    uint64_t* handle) {
+  if (!S || !f || !g || !info || !handle) return RSL_EINVAL;
+  std::shared_ptr<Request> r;
+  int rc = plan_request(S, f, g, var, &r, info);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(S->mu);
+  const uint64_t h = S->next_handle++;
+  S->planned[h] = std::move(r);
+  *handle = h;
+  return RSL_OK;
+}
+
+int rsl_server_enqueue(rsl_server* S, uint64_t handle, rsl_result* out, uint64_t* ticket) {
+  if (!S || !out || !ticket) return RSL_EINVAL;
+  std::shared_ptr<Request> r;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->planned.find(handle);
+    if (it == S->planned.end()) return RSL_EINVAL;
+    r = std::move(it->second);
+    S->planned.erase(it);
+  }
+  return enqueue(S, std::move(r), out, ticket);
 }
 
 int rsl_server_poll(rsl_server* S, uint64_t ticket, int* status) {

@@ -29,16 +29,19 @@ class Server:
     def submit(self, f, g, var="y"):
         pf, pg = _as_poly(f), _as_poly(g)
         v = _var_code(var)
+        # planned once in the library: the plan sizes the result buffer and the
+        # scheduler lays the request's batch out from the same plan
         info = rsl_info()
-        rc = _lib.rsl_query(ctypes.byref(pf.c), ctypes.byref(pg.c), v, ctypes.byref(info))
+        handle = ctypes.c_uint64()
+        rc = _lib.rsl_server_plan(self.h, ctypes.byref(pf.c), ctypes.byref(pg.c), v, ctypes.byref(info),
+                                  ctypes.byref(handle))
         if rc:
-            raise RSLError(rc, "rsl_query")
+            raise RSLError(rc, "rsl_server_plan: " + self.ctx.last_error())
         out = _Result(max(info.D, 0), info.out_limbs)
         t = ctypes.c_uint64()
-        rc = _lib.rsl_server_submit(self.h, ctypes.byref(pf.c), ctypes.byref(pg.c), v, ctypes.byref(out.c),
-                                    ctypes.byref(t))
+        rc = _lib.rsl_server_enqueue(self.h, handle.value, ctypes.byref(out.c), ctypes.byref(t))
         if rc:
-            raise RSLError(rc, "rsl_server_submit")
+            raise RSLError(rc, "rsl_server_enqueue")
         self._outs[t.value] = out
         return t.value
 
@@ -63,14 +66,16 @@ class Server:
             raise RSLError(st.value, "request failed")
         return out.value()
 
-    def wait(self, ticket, timeout_ms=-1):
+    def wait(self, ticket, timeout_ms=-1, raw=False):
+        """The resultant as a list of ints, or with raw=True its limb buffer (a
+        result object: .deg, .c.limbs, .raw()) without the conversion to ints."""
         rc = _lib.rsl_server_wait(self.h, ticket, timeout_ms)
         if rc == RSL_ETIMEDOUT:
             return None
         out = self._outs.pop(ticket)
         if rc:
             raise RSLError(rc, "request failed")
-        return out.value()
+        return out if raw else out.value()
 
     def stats(self):
         s = rsl_stats()
