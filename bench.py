@@ -719,10 +719,11 @@ def profile_h2h(a):
 
 
 def tune_line(t):
-    """The autotuner's choice as it is saved (mode, chunking, grid, lanes, convolution, Schur)."""
+    """The autotuner's choice as it is saved (mode, chunking, grid, lanes, convolution, Schur,
+    matrix-core interpolation)."""
     names = {"staged": 2, "batched": 1}
     return [names.get(t["mode"], t["mode"]), t["chunk_target"], t["grid_mult"], t["lanes_per_pair"],
-            t["conv_whole"], t["schur"]]
+            t["conv_whole"], t["schur"], t.get("interp_mm", 0)]
 
 
 def batch_headline(a):

@@ -145,6 +145,12 @@ typedef struct {
                           m_y, n_y >= 1 and m_y + n_y <= 64 (others keep the remainder
                           sequence); staged and plain schedules only; 0 = remainder
                           sequence unless the autotuner chose Schur */
+  int32_t interp_mm;   /* 1: interpolation on the matrix cores -- the columns of all problems
+                          sharing a prime as two matrix products with the Vandermonde
+                          system's triangular factors (forward differences, Stirling
+                          basis change); staged schedule (plain runs take the vector
+                          path on the same layout); 0 = vector path unless the
+                          autotuner chose the matrix cores */
 } rsl_opts;
 
 /* Counters of the last call on a context (or of a server). */
@@ -364,6 +370,7 @@ typedef struct {
   int32_t evk;           /* lanes per (prime, point) pair in evaluation: 1, 2 or 4 */
   int32_t conv_whole;    /* 1: convolution sums taken whole, 0: split like the basis change */
   int32_t schur;         /* 1: evaluation by the Schur algorithm (see rsl_opts.eval_schur) */
+  int32_t interp_mm;     /* 1: interpolation on the matrix cores (see rsl_opts.interp_mm) */
   int32_t candidates;    /* candidates timed */
   double ms;             /* device time of one run of the chosen schedule */
   double ms_worst;       /* device time of the slowest candidate */
@@ -371,7 +378,8 @@ typedef struct {
 
 int rsl_job_tune(rsl_ctx *ctx, rsl_job *job, int reps, rsl_tune_result *best);
 /* Save / load the tuning cache as text lines
- * "key mode chunk_target grid_mult evk conv_whole schur ms". */
+ * "key mode chunk_target grid_mult evk conv_whole schur interp_mm ms" (lines without
+ * interp_mm are read as 0). */
 int rsl_tune_save(rsl_ctx *ctx, const char *path);
 int rsl_tune_load(rsl_ctx *ctx, const char *path);
 

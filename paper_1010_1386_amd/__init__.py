@@ -64,7 +64,7 @@ class rsl_opts(ctypes.Structure):
     _fields_ = [("points", ctypes.c_int32), ("prime_start", ctypes.c_int32), ("extra_primes", ctypes.c_int32),
                 ("point_origin", ctypes.c_int32), ("extra_points", ctypes.c_int32),
                 ("prime_limit", ctypes.c_int32), ("eval_lanes", ctypes.c_int32), ("eval_regs", ctypes.c_int32),
-                ("eval_schur", ctypes.c_int32)]
+                ("eval_schur", ctypes.c_int32), ("interp_mm", ctypes.c_int32)]
 
 
 class rsl_counters(ctypes.Structure):
@@ -98,6 +98,7 @@ class rsl_upoly(ctypes.Structure):
 class rsl_tune_result(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("chunk_target", ctypes.c_int32), ("grid_mult", ctypes.c_int32),
                 ("evk", ctypes.c_int32), ("conv_whole", ctypes.c_int32), ("schur", ctypes.c_int32),
+                ("interp_mm", ctypes.c_int32),
                 ("candidates", ctypes.c_int32),
                 ("ms", ctypes.c_double),
                 ("ms_worst", ctypes.c_double)]
@@ -265,13 +266,14 @@ def query(f, g, var="y"):
 
 
 def _opts(points="replace", prime_start=0, extra_primes=0, point_origin=0, extra_points=0, prime_limit=0,
-          eval_lanes=0, eval_regs=True, eval_schur=False):
+          eval_lanes=0, eval_regs=True, eval_schur=False, interp_mm=False):
     if eval_lanes not in (0, 1, 2, 4):
         raise ValueError("eval_lanes must be 0, 1, 2 or 4")
     o = rsl_opts()
     o.eval_lanes = eval_lanes
     o.eval_regs = 0 if eval_regs else -1
     o.eval_schur = 1 if eval_schur else 0
+    o.interp_mm = 1 if interp_mm else 0
     o.points = RSL_POINTS_FORMAL if points in ("formal", RSL_POINTS_FORMAL) else RSL_POINTS_REPLACE
     o.prime_start, o.extra_primes = prime_start, extra_primes
     o.point_origin, o.extra_points, o.prime_limit = point_origin, extra_points, prime_limit
@@ -586,7 +588,8 @@ class Job:
         self.ctx._check(rc, "rsl_job_tune")
         names = {RSL_STAGED: "staged", RSL_BATCHED: "batched"}
         return {"mode": names.get(r.mode, r.mode), "chunk_target": r.chunk_target, "grid_mult": r.grid_mult,
-                "lanes_per_pair": r.evk, "conv_whole": r.conv_whole, "schur": r.schur, "candidates": r.candidates, "ms": r.ms,
+                "lanes_per_pair": r.evk, "conv_whole": r.conv_whole, "schur": r.schur, "interp_mm": r.interp_mm,
+                "candidates": r.candidates, "ms": r.ms,
                 "ms_worst": r.ms_worst}
 
     def info(self):

@@ -24,6 +24,7 @@ struct TuneConfig {
   int evk = 0;                // lanes per (prime, point) pair in evaluation; 0 = from the job size
   int conv_whole = 0;         // 1: the convolution sums each coefficient whole (no i-chunks)
   int schur = 0;              // 1: evaluation by the Schur algorithm where the shape allows
+  int interp_mm = 0;          // 1: interpolation on the matrix cores (staged schedule)
 };
 struct TuneEntry {
   TuneConfig cfg;

@@ -177,6 +177,10 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     else if (all_pairs < 2LL * 256 * 4 * 64)
       evk = 2;  // one wave can issue only about half a SIMD's rate: give each SIMD two
   }
+  // interpolation on the matrix cores (staged schedule; the layout keeps the
+  // vector items too, for plain runs of the same job)
+  const bool mm_req = (opts && opts->interp_mm > 0) || J->tune.interp_mm != 0;
+  J->mm_interp = mm_req;
   // one chunk length K for the basis change of every problem, so that problems
   // sharing a prime can share the checkpoint rows; a multiple of the checkpoint
   // spacing, enough chunks for the target number of blocks in flight
@@ -187,6 +191,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     int dmax = 0;
     for (int k : J->live) dmax = std::max(dmax, J->plans[k].D + 1);
     Kc = std::max<int>(kCkpt, static_cast<int>((dmax + nch - 1) / nch));
+    if (mm_req) Kc = dmax;  // the matrix-core interpolation writes each sum whole: one chunk
     Kc = (Kc + kCkpt - 1) / kCkpt * kCkpt;  // chunks start at checkpoint rows
   }
   J->crt_ns = 1;
@@ -242,7 +247,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     d.wlpad = static_cast<int>(align_up(static_cast<size_t>(P.Lw), kWideMfmaTT));
     d.wnpad = static_cast<int>(align_up(static_cast<size_t>(P.np), kWideMfmaK));
     // the convolution's input range: the basis change's chunking, or whole
-    d.cchunk = J->tune.conv_whole ? P.D + 1 : d.kchunk;
+    d.cchunk = (J->tune.conv_whole || mm_req) ? P.D + 1 : d.kchunk;
     d.ncchunk = (P.D + 1 + d.cchunk - 1) / d.cchunk;
     if (!P.wide) J->crt_ns = std::max(J->crt_ns, (P.np + 63) / 64);
     J->max_np = std::max(J->max_np, P.np);
@@ -552,6 +557,58 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     }
   }
 
+  // matrix-core interpolation: every origin-0 (problem, slot) by global prime
+  // index (a stable counting sort), groups of all members of a prime
+  J->mgroups.clear();
+  J->mmembers.clear();
+  J->dig_items.clear();
+  J->mm_items.clear();
+  if (mm_req) {
+    int gidx = 0;
+    for (int li = 0; li < nl; ++li) {
+      const Plan& P = J->plans[J->live[li]];
+      if (P.origin == 0)
+        for (int sl = 0; sl < P.np; ++sl) gidx = std::max(gidx, P.pidx[sl] + 1);
+    }
+    std::vector<int> pstart(static_cast<size_t>(gidx) + 1, 0);
+    for (int li = 0; li < nl; ++li) {
+      const Plan& P = J->plans[J->live[li]];
+      if (P.origin == 0)
+        for (int sl = 0; sl < P.np; ++sl) ++pstart[P.pidx[sl] + 1];
+    }
+    for (int gi = 0; gi < gidx; ++gi) pstart[gi + 1] += pstart[gi];
+    J->mmembers.resize(pstart[gidx]);
+    {
+      std::vector<int> fill(pstart.begin(), pstart.end() - 1);
+      for (int li = 0; li < nl; ++li) {
+        const Plan& P = J->plans[J->live[li]];
+        if (P.origin == 0)
+          for (int sl = 0; sl < P.np; ++sl) J->mmembers[fill[P.pidx[sl]]++] = StirMember{li, sl};
+      }
+    }
+    for (int prime = 0; prime < gidx; ++prime) {
+      const int first = pstart[prime], count = pstart[prime + 1] - first;
+      if (count == 0) continue;
+      // largest degree bound first: each 16-column tile is bounded by its first column
+      std::stable_sort(J->mmembers.begin() + first, J->mmembers.begin() + first + count,
+                       [&](const StirMember& a, const StirMember& b) { return J->dev[a.prob].D > J->dev[b.prob].D; });
+      StirGroup G{prime, first, count, 0};
+      for (int m = first; m < first + count; ++m) G.maxD = std::max(G.maxD, J->dev[J->mmembers[m].prob].D);
+      const int gi = static_cast<int>(J->mgroups.size());
+      J->mgroups.push_back(G);
+      // items: (group, 64 rows, 16 columns)
+      for (int rs = 0; rs < blocks_of(G.maxD + 1, 64); ++rs)
+        for (int ct = 0; ct < blocks_of(count, 16); ++ct) J->mm_items.push_back({gi, rs, ct, 0});
+    }
+    for (int li = 0; li < nl; ++li) {
+      const Plan& P = J->plans[J->live[li]];
+      if (P.origin != 0) continue;
+      const int Dp = static_cast<int>(align_up(static_cast<size_t>(P.D + 1), kCkpt));
+      for (int sl = 0; sl < P.np; ++sl)
+        for (int b = 0; b < blocks_of(Dp, 256); ++b) J->dig_items.push_back({li, sl, b, 0});
+    }
+  }
+
   // device layout: [problems | items | inputs | statuses][outputs][intermediates]
   const size_t A = 256;
   size_t o = 0;
@@ -571,6 +628,14 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   o = align_up(o + sizeof(WorkItem) * J->sg_items.size(), A);
   J->hseg_off = o;
   o = align_up(o + sizeof(WorkItem) * J->hseg_items.size(), A);
+  J->mg_off = o;
+  o = align_up(o + sizeof(StirGroup) * J->mgroups.size(), A);
+  J->mm_off = o;
+  o = align_up(o + sizeof(StirMember) * J->mmembers.size(), A);
+  J->digi_off = o;
+  o = align_up(o + sizeof(WorkItem) * J->dig_items.size(), A);
+  J->mmi_off = o;
+  o = align_up(o + sizeof(WorkItem) * J->mm_items.size(), A);
   for (int pass = 0; pass < 3; ++pass) {
     J->wide_off[pass] = o;
     o = align_up(o + sizeof(WorkItem) * J->wide_items[pass].size(), A);
@@ -679,6 +744,12 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     L.aconv = o; o = align_up(o + static_cast<size_t>(d.ncchunk) * np * (P.D + 1) * 8, A);
     L.cpart = o; o = align_up(o + static_cast<size_t>(d.nchunk) * np * (P.D + 1) * 8, A);
     L.hseg = o;  o = align_up(o + np * align_up(static_cast<size_t>(P.D + 1), kCkpt) * 4, A);
+    L.ydig = L.hdig = 0;
+    if (mm_req && P.origin == 0) {  // digit planes of the matrix-core interpolation
+      const size_t planes = np * kDigits * align_up(static_cast<size_t>(P.D + 1), kCkpt);
+      L.ydig = o; o = align_up(o + planes, A);
+      L.hdig = o; o = align_up(o + planes, A);
+    }
     L.wT = L.wq = L.wS = 0;
     if (P.wide) {
       L.wT = o; o = align_up(o + static_cast<size_t>(d.wdpad) * d.wnpad * 4, A);
@@ -831,6 +902,8 @@ void job_bind(Job* J, uint8_t* base, uint8_t* image, bool with_queue) {
     d.aconv = reinterpret_cast<uint64_t*>(base + L.aconv);
     d.cpart = reinterpret_cast<uint64_t*>(base + L.cpart);
     d.hseg = reinterpret_cast<uint32_t*>(base + L.hseg);
+    d.ydig = L.ydig ? base + L.ydig : nullptr;
+    d.hdig = L.hdig ? base + L.hdig : nullptr;
     d.hstride = static_cast<int>(align_up(static_cast<size_t>(P.D + 1), kCkpt));
     d.out = reinterpret_cast<uint32_t*>(base + L.out);
     d.status = reinterpret_cast<int*>(base + L.status);
@@ -894,6 +967,12 @@ void job_bind(Job* J, uint8_t* base, uint8_t* image, bool with_queue) {
       std::memcpy(blob + J->wide_off[pass], J->wide_items[pass].data(), sizeof(WorkItem) * J->wide_items[pass].size());
   if (!J->hseg_items.empty())
     std::memcpy(blob + J->hseg_off, J->hseg_items.data(), sizeof(WorkItem) * J->hseg_items.size());
+  if (!J->mgroups.empty()) {
+    std::memcpy(blob + J->mg_off, J->mgroups.data(), sizeof(StirGroup) * J->mgroups.size());
+    std::memcpy(blob + J->mm_off, J->mmembers.data(), sizeof(StirMember) * J->mmembers.size());
+    std::memcpy(blob + J->digi_off, J->dig_items.data(), sizeof(WorkItem) * J->dig_items.size());
+    std::memcpy(blob + J->mmi_off, J->mm_items.data(), sizeof(WorkItem) * J->mm_items.size());
+  }
   if (!J->sgroups.empty()) {
     std::memcpy(blob + J->sg_off, J->sgroups.data(), sizeof(StirGroup) * J->sgroups.size());
     std::memcpy(blob + J->sm_off, J->smembers.data(), sizeof(StirMember) * J->smembers.size());
@@ -1042,6 +1121,23 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
         if ((rc = hip_check(ctx, launch_eval(r.variant, probs, evs + r.begin, r.end - r.begin, J->stage_lds[s], T, st),
                             "launch")))
           return rc;
+      continue;
+    }
+    if (J->mm_interp && (s == kStageConv || s == kStageStir)) {
+      // the interpolation's two products on the matrix cores (the segments'
+      // polynomials between them, from the Newton coefficients)
+      const StirGroup* mg = reinterpret_cast<const StirGroup*>(J->base + J->mg_off);
+      const StirMember* mm = reinterpret_cast<const StirMember*>(J->base + J->mm_off);
+      const WorkItem* di = reinterpret_cast<const WorkItem*>(J->base + J->digi_off);
+      const WorkItem* mi = reinterpret_cast<const WorkItem*>(J->base + J->mmi_off);
+      const int nd = static_cast<int>(J->dig_items.size()), nm = static_cast<int>(J->mm_items.size());
+      if (s == kStageStir &&
+          (rc = hip_check(ctx, launch_hseg(probs, hseg_items, static_cast<int>(J->hseg_items.size()), T, st),
+                          "launch")))
+        return rc;
+      if ((rc = hip_check(ctx, launch_interp_mm(s == kStageConv ? 1 : 2, probs, mg, mm, di, nd, mi, nm, T, st),
+                          "launch")))
+        return rc;
       continue;
     }
     if (s == kStageStir &&

@@ -23,7 +23,7 @@ namespace rsl {
 struct ProbLayout {
   // offsets from the job base
   size_t coeff, gdeg, pidx, Hm, NH, Tg, invM, Plimb, Mi, wdir, rinv, negM, Mw, NHM, wMd, status;
-  size_t out, resid, dig, zval, zbad, aconv, cpart, hseg, wT, wq, wS;
+  size_t out, resid, dig, zval, zbad, aconv, cpart, hseg, ydig, hdig, wT, wq, wS;
   int hseg_begin, hseg_end;        // range of Job::hseg_items
   int L_in;
   bool crt_own;  // this problem's layout holds the CRT constant block it shares
@@ -55,6 +55,14 @@ struct Job {
   // segment polynomials of the basis change (before the stir stage)
   std::vector<WorkItem> hseg_items;
   size_t hseg_off = 0;
+  // interpolation on the matrix cores: prime groups of (problem, slot) columns
+  // (all members of a prime), the digit-plane items (problem, slot, block of
+  // 256 positions) and the product items (group, row tile, column-tile set)
+  bool mm_interp = false;
+  std::vector<StirGroup> mgroups;
+  std::vector<StirMember> mmembers;
+  std::vector<WorkItem> dig_items, mm_items;
+  size_t mg_off = 0, mm_off = 0, digi_off = 0, mmi_off = 0;
   // the ranges the kernels expect zeroed (a table in the upload image, cleared
   // by one launch after the upload)
   size_t clr_off = 0;

@@ -33,6 +33,13 @@ hipError_t launch_stir_group(const DevProblem* probs, const StirGroup* groups, c
 // Stirling numbers of the first kind mod p_g for g in [g0, g0+count), rows 0..scap.
 // Segment polynomials of the basis change (stage_interp_hseg), before the stir stage.
 hipError_t launch_hseg(const DevProblem* probs, const WorkItem* items, int nitems, const DevTables& T, hipStream_t st);
+// Interpolation on the matrix cores: the digit planes of each (problem, slot)
+// (items: problem, slot, block of 256 positions), then the product of one
+// group's columns (items: group, row tile, set of four column tiles).
+// which = 1: Newton coefficients into aconv; 2: the basis change into cpart.
+hipError_t launch_interp_mm(int which, const DevProblem* probs, const StirGroup* groups, const StirMember* members,
+                            const WorkItem* digit_items, int ndigit, const WorkItem* mm_items, int nmm,
+                            const DevTables& T, hipStream_t st);
 hipError_t launch_stirling_build(uint32_t* stir, int64_t sstride, const PrimeConst* pcs, int g0,
                                  int count, int scap, hipStream_t st);
 

@@ -100,6 +100,35 @@ hipError_t launch_hseg(const DevProblem* probs, const WorkItem* items, int nitem
   return hipGetLastError();
 }
 
+template <int WHICH>
+__global__ __launch_bounds__(256) void k_interp_digits(const DevProblem* probs, const WorkItem* items, DevTables T) {
+  const WorkItem w = items[blockIdx.x];
+  stage_interp_digits<WHICH>(probs[w.prob], T, w);
+}
+
+template <int WHICH>
+__global__ __launch_bounds__(256) void k_interp_mm(const DevProblem* probs, const StirGroup* groups,
+                                                   const StirMember* members, const WorkItem* items, DevTables T) {
+  __shared__ uint64_t lds8[kInterpMmLdsBytes / 8];
+  const WorkItem w = items[blockIdx.x];
+  stage_interp_mm<WHICH>(probs, groups[w.prob], members, w, T, reinterpret_cast<uint8_t*>(lds8));
+}
+
+hipError_t launch_interp_mm(int which, const DevProblem* probs, const StirGroup* groups, const StirMember* members,
+                            const WorkItem* digit_items, int ndigit, const WorkItem* mm_items, int nmm,
+                            const DevTables& T, hipStream_t st) {
+  if (ndigit > 0) {
+    if (which == 1) hipLaunchKernelGGL(k_interp_digits<1>, dim3(ndigit), dim3(256), 0, st, probs, digit_items, T);
+    else hipLaunchKernelGGL(k_interp_digits<2>, dim3(ndigit), dim3(256), 0, st, probs, digit_items, T);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (nmm <= 0) return hipSuccess;
+  if (which == 1) hipLaunchKernelGGL(k_interp_mm<1>, dim3(nmm), dim3(256), 0, st, probs, groups, members, mm_items, T);
+  else hipLaunchKernelGGL(k_interp_mm<2>, dim3(nmm), dim3(256), 0, st, probs, groups, members, mm_items, T);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(1024) void k_interp_newton(const DevProblem* probs, const WorkItem* items, DevTables T) {
   extern __shared__ uint32_t lds[];
   const WorkItem w = items[blockIdx.x];

@@ -1301,6 +1301,190 @@ __device__ inline void basis_block(const uint32_t* S, int j0, int k1, int ke, in
   }
 }
 
+// ------------------------------------- interpolation on the matrix cores
+// For the problems of one prime the two triangular factors of the
+// interpolation are shared matrices, so the columns of all those problems
+// (and of the x and y problems alike) form one matrix product each:
+//   Newton coefficients  a_k = sum_{i <= k} T(k - i) y_i,   T(d) = (-1)^d / d!,
+//                        y_i = z_i / i!   (the forward differences of Sec. 4.1's
+//                        consecutive points, a Toeplitz factor),
+//   basis change         c_j = sum_{segments k0} sum_{i < kCkpt} s(k0, j - i) h_{k0,i}
+//                        (the checkpoint rows of the Stirling triangle and the
+//                        segments' polynomials h of stage_interp_hseg).
+// Both have a Toeplitz operand A[row][K] = v(row - K + const); the data
+// operand B holds the problems' columns as 7-bit digit planes (five digits of
+// each residue), and the 16x16x32 int8 products of the five digits of each
+// side accumulate the nine anti-diagonal sums S_s over the whole K range
+// (each below 5 * 3808 * 127^2 < 2^31), recombined as in the evaluation:
+//   out = sum_s S_s (2^{7s} mod p), below 9 * 2^29 p < p 2^32,
+// whose REDC is the coefficient in Montgomery form (the operands are
+// Montgomery representatives), written as the single chunk of aconv / cpart.
+
+// Digit planes of one problem slot: WHICH 1, y_n = z_n ifact_n; WHICH 2, hseg
+// (zero beyond D and, for the basis change, for a prime with bad points).
+template <int WHICH>
+__device__ inline void stage_interp_digits(const DevProblem& P, const DevTables& T, const WorkItem& w) {
+  const int n = w.blk * blockDim.x + threadIdx.x;
+  const int Dp = P.hstride;
+  if (n >= Dp) return;
+  const int g = P.pidx[w.slot];
+  uint32_t v = 0u;
+  if (n <= P.D) {
+    if constexpr (WHICH == 1) {
+      const PrimeConst pc = T.pc[g];
+      const uint32_t z = P.zval[static_cast<size_t>(w.slot) * (P.E + 1) + n];
+      v = mmul(z, T.ifact[static_cast<size_t>(g) * T.kstride + n], pc.p, pc.pinv);
+    } else {
+      if (fast_prime(P, w.slot)) v = P.hseg[static_cast<size_t>(w.slot) * P.hstride + n];
+    }
+  }
+  uint8_t* dst = (WHICH == 1 ? P.ydig : P.hdig) + static_cast<size_t>(w.slot) * kDigits * Dp + n;
+#pragma unroll
+  for (int b = 0; b < kDigits; ++b) dst[static_cast<size_t>(b) * Dp] = static_cast<uint8_t>((v >> (7 * b)) & 127u);
+}
+
+// Item (group, set of four row tiles = 64 rows, column tile of 16 members);
+// wave w of the block takes row tile 4 blk + w of that column tile.  Per K
+// slice the block stages in LDS the Toeplitz operand's window for its 64 rows
+// (96 values, reversed, as digit planes) and the column tile's B fragments
+// (loaded once for the four row tiles); lane l's A fragment -- row l mod 16
+// of its tile, K entries 8 (l / 16) .. + 7 -- is eight consecutive bytes of
+// each plane.  Slices alternate between two buffers (one barrier per slice),
+// and the next slice's loads are issued before the current products.
+constexpr int kMmPlane = 128;  // bytes per window digit plane (96 used)
+constexpr int kInterpMmLdsBytes = 2 * (kDigits * kMmPlane + kDigits * 64 * 8);
+
+template <int WHICH>
+__device__ inline void stage_interp_mm(const DevProblem* probs, const StirGroup& G, const StirMember* members,
+                                       const WorkItem& w, const DevTables& T, uint8_t* lds) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const PrimeConst pc = T.pc[G.g];
+  const uint32_t p = pc.p;
+  const int rs0 = 64 * w.slot;          // first row of the block
+  const int rw0 = rs0 + 16 * wave;      // first row of this wave's tile
+  const int Dmax = G.maxD;
+  const int q = lane >> 4, r = lane & 15;
+  // the column tile (members sorted by degree bound, largest first)
+  const int mi = 16 * w.blk + r;
+  const bool valid = mi < G.count;
+  const StirMember M = members[G.first + (valid ? mi : 0)];
+  const DevProblem& Pm = probs[M.prob];
+  const int Dm = valid ? Pm.D : -1;
+  const int Dp = Pm.hstride;
+  const uint8_t* bsrc = (WHICH == 1 ? Pm.ydig : Pm.hdig) + static_cast<size_t>(M.slot) * kDigits * Dp;
+  const int tileD = __builtin_amdgcn_readfirstlane(Dm);  // the tile's largest degree bound
+  const int n0 = 64 - 16 * wave - r + 8 * q;  // first byte of the fragment in the reversed window
+
+  uint8_t* winb[2] = {lds, lds + kDigits * kMmPlane};
+  uint64_t* bfr[2] = {reinterpret_cast<uint64_t*>(lds + 2 * kDigits * kMmPlane),
+                      reinterpret_cast<uint64_t*>(lds + 2 * kDigits * kMmPlane + kDigits * 64 * 8)};
+  for (int t = tid; t < 2 * kDigits * kMmPlane / 8; t += blockDim.x) reinterpret_cast<uint64_t*>(lds)[t] = 0u;
+
+  int s_first, s_last;
+  if constexpr (WHICH == 1) {
+    s_first = 0;
+    s_last = ((rs0 + 63 < Dmax) ? rs0 + 63 : Dmax) / 32;
+  } else {
+    s_first = rs0 >= 31 ? (rs0 - 31) / 32 : 0;
+    s_last = Dmax / 32;
+  }
+  if (tileD < s_last * 32) s_last = tileD >= 0 ? tileD / 32 : -1;  // no column of the tile reaches beyond
+  const uint32_t* ifact = T.ifact + static_cast<size_t>(G.g) * T.kstride;
+  const uint32_t* srow_base = T.stir + static_cast<size_t>(G.g) * T.sstride;
+  // window value t < 96 of a slice: v(xb + t)
+  auto window_value = [&](int sl) -> uint32_t {
+    uint32_t v = 0u;
+    if (tid < 96) {
+      if constexpr (WHICH == 1) {
+        const int x = rs0 - 32 * sl - 31 + tid;  // T(k - i), k in the block's rows, i in the slice
+        if (x >= 0 && x <= Dmax) {
+          const uint32_t f = ifact[x];
+          v = (x & 1) ? p - f : f;
+        }
+      } else {
+        const int x = rs0 - 31 + tid;  // s(k0, j - i), j in the block's rows, i < kCkpt
+        if (x >= 0 && x <= 32 * sl) v = srow_base[ckpt_rowoff(sl) + x];
+      }
+    }
+    return v;
+  };
+  // wave 0 loads the column tile's B fragments of a slice (zero beyond a column's problem)
+  auto b_frags = [&](int sl, uint64_t (&Bf)[kDigits]) {
+    const int k0 = 32 * sl, pos = k0 + 8 * q;
+    const bool have = wave == 0 && valid && (WHICH == 1 ? pos <= Dm : k0 <= Dm);
+#pragma unroll
+    for (int b = 0; b < kDigits; ++b)
+      Bf[b] = have ? *reinterpret_cast<const uint64_t*>(bsrc + static_cast<size_t>(b) * Dp + pos) : 0u;
+  };
+  ev_v4i S[2 * kDigits - 1];
+#pragma unroll
+  for (int s = 0; s < 2 * kDigits - 1; ++s) S[s] = ev_v4i{0, 0, 0, 0};
+  uint32_t vn = 0u;
+  uint64_t Bn[kDigits] = {0u, 0u, 0u, 0u, 0u};
+  if (s_first <= s_last) {
+    vn = window_value(s_first);
+    b_frags(s_first, Bn);
+  }
+  __syncthreads();  // the zeroed planes
+  for (int sl = s_first; sl <= s_last; ++sl) {
+    const int buf = (sl - s_first) & 1;
+    uint8_t* win = winb[buf];
+    if (tid < 96) {
+#pragma unroll
+      for (int b = 0; b < kDigits; ++b) win[b * kMmPlane + 95 - tid] = static_cast<uint8_t>((vn >> (7 * b)) & 127u);
+    }
+    if (wave == 0) {
+#pragma unroll
+      for (int b = 0; b < kDigits; ++b) bfr[buf][b * 64 + lane] = Bn[b];
+    }
+    __syncthreads();  // one barrier per slice: a buffer is rewritten only after the next one
+    if (sl < s_last) {
+      vn = window_value(sl + 1);
+      b_frags(sl + 1, Bn);
+    }
+    // wave-uniform: this row tile has nothing in the slice
+    const int k0 = 32 * sl;
+    if (rw0 > tileD) continue;
+    if constexpr (WHICH == 1) {
+      if (k0 > rw0 + 15) continue;  // T(k - i) = 0 for i > k
+    } else {
+      if (k0 + 31 < rw0) continue;  // s(k0, j - i) = 0 for j - i > k0
+    }
+    const uint64_t* pl = reinterpret_cast<const uint64_t*>(win);
+    uint64_t A[kDigits], B[kDigits];
+    const int sh = (n0 & 7) * 8, wi = n0 >> 3;
+#pragma unroll
+    for (int b = 0; b < kDigits; ++b) {
+      const uint64_t lo = pl[b * (kMmPlane / 8) + wi], hi = pl[b * (kMmPlane / 8) + wi + 1];
+      A[b] = sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
+      B[b] = bfr[buf][b * 64 + lane];
+    }
+#pragma unroll
+    for (int a = 0; a < kDigits; ++a)
+#pragma unroll
+      for (int b = 0; b < kDigits; ++b)
+        S[a + b] = __builtin_amdgcn_mfma_i32_16x16x32_i8(static_cast<long>(A[a]), static_cast<long>(B[b]), S[a + b],
+                                                         0, 0, 0);
+  }
+  if (!valid || rw0 > Dm) return;
+  uint32_t wgt[2 * kDigits - 1];  // 2^(7 s) mod p
+  wgt[0] = 1u;
+#pragma unroll
+  for (int s = 1; s < 2 * kDigits - 1; ++s) {
+    const uint64_t t = static_cast<uint64_t>(wgt[s - 1]) << 7;
+    wgt[s] = static_cast<uint32_t>(t % p);
+  }
+  uint64_t* out = (WHICH == 1 ? Pm.aconv : Pm.cpart) + static_cast<size_t>(M.slot) * (Dm + 1);
+#pragma unroll
+  for (int r4 = 0; r4 < 4; ++r4) {
+    const int row = rw0 + 4 * q + r4;
+    uint64_t t = 0;
+#pragma unroll
+    for (int s = 0; s < 2 * kDigits - 1; ++s) t += static_cast<uint64_t>(static_cast<uint32_t>(S[s][r4])) * wgt[s];
+    if (row <= Dm) out[row] = t;
+  }
+}
+
 // LDS words of a basis-change block: members' h, the row window, and (when h
 // is expanded in the block) the chunk's a_k.
 __host__ __device__ inline int basis_lds_words(int members, int nthreads, int K_or_0) {

@@ -324,7 +324,7 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
   int rc;
   if ((rc = require_bound(ctx, j))) return rc;
   if (j->J.live.empty()) {
-    if (best) *best = rsl_tune_result{RSL_STAGED, j->J.tune.chunk_target, 1, 1, 0, 0, 0, 0.0, 0.0};
+    if (best) *best = rsl_tune_result{RSL_STAGED, j->J.tune.chunk_target, 1, 1, 0, 0, 0, 0, 0.0, 0.0};
     return RSL_OK;
   }
   // coordinate search: schedule x lanes per pair at the default chunking, then
@@ -354,6 +354,8 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
       for (int target : {1024, 16384}) cands.push_back(TuneConfig{win.mode, target, 1, win.evk, 0, win.schur});
       cands.push_back(TuneConfig{win.mode, 4096, 1, win.evk, 1, win.schur});
       if (win.mode == RSL_BATCHED) cands.push_back(TuneConfig{RSL_BATCHED, 4096, 2, win.evk, 0, 0});
+      // the interpolation on the matrix cores (staged schedule)
+      if (win.mode == RSL_STAGED) cands.push_back(TuneConfig{RSL_STAGED, 4096, 1, win.evk, 1, win.schur, 1});
     }
     if (ci >= cands.size()) break;
     const TuneConfig tc = cands[ci];
@@ -386,6 +388,7 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
                   "autotuner: candidate (mode " + std::to_string(tc.mode) + ", chunk target " +
                       std::to_string(tc.chunk_target) + ", grid x" + std::to_string(tc.grid_mult) +
                       ", lanes per pair " + std::to_string(tc.evk) + ", Schur " + std::to_string(tc.schur) +
+                      ", matrix-core interpolation " + std::to_string(tc.interp_mm) +
                       ") differs from the first candidate in its statuses or outputs (byte " + std::to_string(at) +
                       " of the compared image)");
     }
@@ -407,7 +410,7 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
   if ((rc = materialize(ctx, j, win))) return rc;
   ctx->tune_cache[tune_key(j->J.n, j->f.data(), j->g.data(), j->var.data())] = TuneEntry{win, win_ms};
   if (best) *best = rsl_tune_result{win.mode, win.chunk_target, win.grid_mult, win.evk, win.conv_whole, win.schur,
-                                    timed, win_ms, worst_ms};
+                                    win.interp_mm, timed, win_ms, worst_ms};
   return RSL_OK;
 }
 
@@ -419,7 +422,7 @@ int rsl_tune_save(rsl_ctx* ctx, const char* path) {
   for (const auto& kv : ctx->tune_cache)
     os << kv.first << " " << kv.second.cfg.mode << " " << kv.second.cfg.chunk_target << " "
        << kv.second.cfg.grid_mult << " " << kv.second.cfg.evk << " " << kv.second.cfg.conv_whole << " "
-       << kv.second.cfg.schur << " " << kv.second.ms << "\n";
+       << kv.second.cfg.schur << " " << kv.second.cfg.interp_mm << " " << kv.second.ms << "\n";
   return RSL_OK;
 }
 
@@ -428,14 +431,30 @@ int rsl_tune_load(rsl_ctx* ctx, const char* path) {
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   std::ifstream is(path);
   if (!is) return fail(ctx, RSL_EINVAL, std::string("cannot read ") + path);
-  std::string key;
-  TuneEntry e;
-  while (is >> key >> e.cfg.mode >> e.cfg.chunk_target >> e.cfg.grid_mult >> e.cfg.evk >> e.cfg.conv_whole >>
-         e.cfg.schur >> e.ms) {
+  std::string line;
+  while (std::getline(is, line)) {
+    std::istringstream ls(line);
+    std::string key;
+    if (!(ls >> key)) continue;
+    // key mode chunk grid evk conv_whole schur [interp_mm] ms
+    std::vector<double> v;
+    double x;
+    while (ls >> x) v.push_back(x);
+    TuneEntry e;
+    if (v.size() != 7 && v.size() != 8) return fail(ctx, RSL_EINVAL, "malformed tuning cache line for " + key);
+    e.cfg.mode = static_cast<int>(v[0]);
+    e.cfg.chunk_target = static_cast<int>(v[1]);
+    e.cfg.grid_mult = static_cast<int>(v[2]);
+    e.cfg.evk = static_cast<int>(v[3]);
+    e.cfg.conv_whole = static_cast<int>(v[4]);
+    e.cfg.schur = static_cast<int>(v[5]);
+    e.cfg.interp_mm = v.size() == 8 ? static_cast<int>(v[6]) : 0;
+    e.ms = v.back();
     if ((e.cfg.mode != RSL_STAGED && e.cfg.mode != RSL_BATCHED) || e.cfg.chunk_target < 64 || e.cfg.grid_mult < 1 ||
         e.cfg.grid_mult > 8 || (e.cfg.evk != 1 && e.cfg.evk != 2 && e.cfg.evk != 4) ||
         (e.cfg.conv_whole != 0 && e.cfg.conv_whole != 1) || (e.cfg.schur != 0 && e.cfg.schur != 1) ||
-        (e.cfg.schur && e.cfg.mode != RSL_STAGED))
+        (e.cfg.schur && e.cfg.mode != RSL_STAGED) || (e.cfg.interp_mm != 0 && e.cfg.interp_mm != 1) ||
+        (e.cfg.interp_mm && e.cfg.mode != RSL_STAGED))
       return fail(ctx, RSL_EINVAL, "malformed tuning cache line for " + key);
     ctx->tune_cache[key] = e;
   }

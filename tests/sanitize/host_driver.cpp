@@ -208,7 +208,7 @@ int main(int argc, char** argv) {
   const TuneConfig cfgs[] = {
       TuneConfig{RSL_STAGED, 4096, 1, 1, 0, 0}, TuneConfig{RSL_STAGED, 1024, 1, 2, 0, 0},
       TuneConfig{RSL_STAGED, 16384, 1, 4, 1, 0}, TuneConfig{RSL_BATCHED, 4096, 2, 1, 0, 0},
-      TuneConfig{RSL_STAGED, 4096, 1, 1, 0, 1},
+      TuneConfig{RSL_STAGED, 4096, 1, 1, 0, 1}, TuneConfig{RSL_STAGED, 4096, 1, 1, 1, 0, 1},
   };
   const int C = static_cast<int>(sizeof(cfgs) / sizeof(cfgs[0]));
   std::vector<size_t> totals(static_cast<size_t>(T) * C, 0);

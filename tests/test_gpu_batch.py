@@ -93,9 +93,9 @@ def test_autotuner_keeps_bits_and_caches_choice(ctx, tmp_path):
     ctx.tune_save(str(path))
     lines = path.read_text().split("\n")
     assert len([l for l in lines if l.strip()]) == 1
-    key, mode, target, gm, evk, cw, sch, ms = lines[0].split()
+    key, mode, target, gm, evk, cw, sch, imm, ms = lines[0].split()
     assert int(mode) in (1, 2) and int(target) >= 64 and int(gm) >= 1 and int(evk) in (1, 2, 4)
-    assert int(sch) in (0, 1)
+    assert int(sch) in (0, 1) and int(imm) in (0, 1)
     import paper_1010_1386_amd as rsl
     c2 = rsl.Context(device=0, workspace_bytes=256 << 20)
     c2.tune_load(str(path))
@@ -104,7 +104,10 @@ def test_autotuner_keeps_bits_and_caches_choice(ctx, tmp_path):
     assert j2.results() == want
     j2.close()
     bad = tmp_path / "bad.txt"
-    bad.write_text(key + " 7 4096 1 1 0 0 1.0\n")
+    bad.write_text(key + " 7 4096 1 1 0 0 0 1.0\n")
+    with pytest.raises(rsl.RSLError):
+        c2.tune_load(str(bad))
+    bad.write_text(key + " 1 4096 1 1 0 0 1 1.0\n")  # matrix-core interpolation: staged schedule only
     with pytest.raises(rsl.RSLError):
         c2.tune_load(str(bad))
     c2.close()
