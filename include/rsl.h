@@ -124,6 +124,7 @@ typedef struct {
   size_t table_bytes;     /* bytes of the context's constant tables that cover this problem
                              (primes, factorials, checkpoint rows of the Stirling triangle,
                              CRT constants), rounded up as the context grows them */
+  int32_t origin;         /* first evaluation point (default options: see point_origin) */
 } rsl_info;
 
 /* Per-call options (zero-initialise for the defaults). */
@@ -131,7 +132,12 @@ typedef struct {
   int32_t points;      /* RSL_POINTS_REPLACE (default) or RSL_POINTS_FORMAL */
   int32_t prime_start; /* skip this many primes of the table (self-consistency tests) */
   int32_t extra_primes;/* use this many primes beyond the bound (self-consistency tests) */
-  int32_t point_origin;/* evaluate at origin, origin+1, ... instead of 0, 1, ... */
+  int32_t point_origin;/* > 0: evaluate at origin, origin+1, ... instead of 0, 1, ...;
+                          0 (default): 0, unless a leading coefficient in the eliminated
+                          variable vanishes at 0 over Z (point 0 bad for every prime) --
+                          then the first origin in 1..16 where neither vanishes, so that
+                          the primes keep the consecutive-point interpolation (followed by
+                          a Taylor shift back to x); -1: 0 regardless (the gapped path) */
   int32_t extra_points;/* evaluate at this many points beyond D + s */
   int32_t prime_limit; /* test hook: treat the prime table as having only this many entries */
   int32_t eval_lanes;  /* lanes per (prime, point) pair in evaluation: 1, 2 or 4 (an upper

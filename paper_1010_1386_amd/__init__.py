@@ -57,7 +57,7 @@ class rsl_info(ctypes.Structure):
     _fields_ = [("D", ctypes.c_int32), ("bound_bits", ctypes.c_int32), ("n_primes", ctypes.c_int32),
                 ("n_points", ctypes.c_int32), ("out_limbs", ctypes.c_int32), ("my", ctypes.c_int32),
                 ("ny", ctypes.c_int32), ("bad_primes", ctypes.c_int32), ("footprint_bytes", ctypes.c_size_t),
-                ("table_bytes", ctypes.c_size_t)]
+                ("table_bytes", ctypes.c_size_t), ("origin", ctypes.c_int32)]
 
 
 class rsl_opts(ctypes.Structure):

@@ -622,6 +622,7 @@ int rsl_query(const rsl_poly* f, const rsl_poly* g, int var, rsl_info* info) {
   info->my = P.my;
   info->ny = P.ny;
   info->bad_primes = P.bad_primes;
+  info->origin = P.origin;
   Job J;
   std::string e2;
   if (job_build(nullptr, 1, f, g, &var, nullptr, &J, &e2) == RSL_OK) {

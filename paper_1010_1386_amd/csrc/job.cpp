@@ -179,7 +179,10 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   }
   // interpolation on the matrix cores (staged schedule; the layout keeps the
   // vector items too, for plain runs of the same job)
-  const bool mm_req = (opts && opts->interp_mm > 0) || J->tune.interp_mm != 0;
+  // (degree bounds up to kMmMaxD: the operand of a block stays within 64 KB of LDS)
+  int dmax = 0;
+  for (int k : J->live) dmax = std::max(dmax, J->plans[k].D + 1);
+  const bool mm_req = ((opts && opts->interp_mm > 0) || J->tune.interp_mm != 0) && dmax - 1 <= kMmMaxD;
   J->mm_interp = mm_req;
   // one chunk length K for the basis change of every problem, so that problems
   // sharing a prime can share the checkpoint rows; a multiple of the checkpoint
@@ -188,8 +191,6 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   {
     int64_t nch = 1;
     if (stir_base < target) nch = (target + stir_base - 1) / std::max<int64_t>(stir_base, 1);
-    int dmax = 0;
-    for (int k : J->live) dmax = std::max(dmax, J->plans[k].D + 1);
     Kc = std::max<int>(kCkpt, static_cast<int>((dmax + nch - 1) / nch));
     if (mm_req) Kc = dmax;  // the matrix-core interpolation writes each sum whole: one chunk
     Kc = (Kc + kCkpt - 1) / kCkpt * kCkpt;  // chunks start at checkpoint rows
@@ -502,8 +503,8 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     }
   }
 
-  // prime groups for the basis change: the problems whose interpolation can take
-  // the consecutive-point path (origin 0), by global prime index
+  // prime groups for the basis change: every (problem, slot) by global prime
+  // index (slots whose points turn out gapped skip their share)
   J->sgroups.clear();
   J->smembers.clear();
   J->sg_items.clear();
@@ -513,14 +514,12 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     int gidx = 0;
     for (int li = 0; li < nl; ++li) {
       const Plan& P = J->plans[J->live[li]];
-      if (P.origin == 0)
-        for (int sl = 0; sl < P.np; ++sl) gidx = std::max(gidx, P.pidx[sl] + 1);
+      for (int sl = 0; sl < P.np; ++sl) gidx = std::max(gidx, P.pidx[sl] + 1);
     }
     std::vector<int> pstart(static_cast<size_t>(gidx) + 1, 0);
     for (int li = 0; li < nl; ++li) {
       const Plan& P = J->plans[J->live[li]];
-      if (P.origin == 0)
-        for (int sl = 0; sl < P.np; ++sl) ++pstart[P.pidx[sl] + 1];
+      for (int sl = 0; sl < P.np; ++sl) ++pstart[P.pidx[sl] + 1];
     }
     for (int gi = 0; gi < gidx; ++gi) pstart[gi + 1] += pstart[gi];
     std::vector<StirMember> by_prime(pstart[gidx]);
@@ -528,8 +527,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       std::vector<int> fill(pstart.begin(), pstart.end() - 1);
       for (int li = 0; li < nl; ++li) {
         const Plan& P = J->plans[J->live[li]];
-        if (P.origin == 0)
-          for (int sl = 0; sl < P.np; ++sl) by_prime[fill[P.pidx[sl]]++] = StirMember{li, sl};
+        for (int sl = 0; sl < P.np; ++sl) by_prime[fill[P.pidx[sl]]++] = StirMember{li, sl};
       }
     }
     int gmax = kStirGroupMax;
@@ -557,24 +555,23 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     }
   }
 
-  // matrix-core interpolation: every origin-0 (problem, slot) by global prime
+  // matrix-core interpolation: every (problem, slot) by global prime
   // index (a stable counting sort), groups of all members of a prime
   J->mgroups.clear();
   J->mmembers.clear();
   J->dig_items.clear();
   J->mm_items.clear();
+  J->mm_lds[0] = J->mm_lds[1] = 0;
   if (mm_req) {
     int gidx = 0;
     for (int li = 0; li < nl; ++li) {
       const Plan& P = J->plans[J->live[li]];
-      if (P.origin == 0)
-        for (int sl = 0; sl < P.np; ++sl) gidx = std::max(gidx, P.pidx[sl] + 1);
+      for (int sl = 0; sl < P.np; ++sl) gidx = std::max(gidx, P.pidx[sl] + 1);
     }
     std::vector<int> pstart(static_cast<size_t>(gidx) + 1, 0);
     for (int li = 0; li < nl; ++li) {
       const Plan& P = J->plans[J->live[li]];
-      if (P.origin == 0)
-        for (int sl = 0; sl < P.np; ++sl) ++pstart[P.pidx[sl] + 1];
+      for (int sl = 0; sl < P.np; ++sl) ++pstart[P.pidx[sl] + 1];
     }
     for (int gi = 0; gi < gidx; ++gi) pstart[gi + 1] += pstart[gi];
     J->mmembers.resize(pstart[gidx]);
@@ -582,8 +579,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       std::vector<int> fill(pstart.begin(), pstart.end() - 1);
       for (int li = 0; li < nl; ++li) {
         const Plan& P = J->plans[J->live[li]];
-        if (P.origin == 0)
-          for (int sl = 0; sl < P.np; ++sl) J->mmembers[fill[P.pidx[sl]]++] = StirMember{li, sl};
+        for (int sl = 0; sl < P.np; ++sl) J->mmembers[fill[P.pidx[sl]]++] = StirMember{li, sl};
       }
     }
     for (int prime = 0; prime < gidx; ++prime) {
@@ -596,16 +592,37 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       for (int m = first; m < first + count; ++m) G.maxD = std::max(G.maxD, J->dev[J->mmembers[m].prob].D);
       const int gi = static_cast<int>(J->mgroups.size());
       J->mgroups.push_back(G);
-      // items: (group, 64 rows, 16 columns)
-      for (int rs = 0; rs < blocks_of(G.maxD + 1, 64); ++rs)
-        for (int ct = 0; ct < blocks_of(count, 16); ++ct) J->mm_items.push_back({gi, rs, ct, 0});
+      // items: (group, 64 rows, a run of 16-column tiles whose slices add up to
+      // about kMmRunSlices); a tile whose largest bound is below the rows has
+      // nothing there, and neither have the tiles after it
+      const int ntile = blocks_of(count, 16);
+      for (int rs = 0; rs < blocks_of(G.maxD + 1, 64); ++rs) {
+        const int rs0 = 64 * rs;
+        int ct = 0;
+        while (ct < ntile) {
+          const int tileD0 = J->dev[J->mmembers[first + 16 * ct].prob].D;
+          if (tileD0 < rs0) break;
+          for (int which = 1; which <= 2; ++which)
+            J->mm_lds[which - 1] = std::max(J->mm_lds[which - 1], kMmColBytes + mm_operand_bytes(which, rs0, tileD0));
+          int n = 0, cost = 0;
+          while (ct + n < ntile && n < kMmTilesMax && cost < kMmRunSlices) {
+            const int tD = J->dev[J->mmembers[first + 16 * (ct + n)].prob].D;
+            if (tD < rs0) break;
+            const int c1 = mm_slices_hi(1, rs0, tD) - mm_slices_lo(1, rs0) + 1;
+            const int c2 = mm_slices_hi(2, rs0, tD) - mm_slices_lo(2, rs0) + 1;
+            cost += std::max(c1, c2);
+            ++n;
+          }
+          J->mm_items.push_back({gi, rs, ct, n + 32 * tileD0});
+          ct += n;
+        }
+      }
     }
     for (int li = 0; li < nl; ++li) {
       const Plan& P = J->plans[J->live[li]];
-      if (P.origin != 0) continue;
       const int Dp = static_cast<int>(align_up(static_cast<size_t>(P.D + 1), kCkpt));
       for (int sl = 0; sl < P.np; ++sl)
-        for (int b = 0; b < blocks_of(Dp, 256); ++b) J->dig_items.push_back({li, sl, b, 0});
+        for (int b = 0; b < blocks_of(Dp, kDigitsPerBlock); ++b) J->dig_items.push_back({li, sl, b, 0});
     }
   }
 
@@ -693,7 +710,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       const DevProblem& d = J->dev[li];
       const int64_t ne = blocks_of(P.E + 1, d.evpb), nc = blocks_of(P.D + 1, 64);
       const int64_t ns = blocks_of(P.D + 1, 64) * d.nchunk;
-      cap += static_cast<int64_t>(P.np) * (1 + ne + std::max<int64_t>(nc * d.ncchunk + ns, 1));
+      cap += static_cast<int64_t>(P.np) * (1 + ne + std::max<int64_t>(nc * d.ncchunk + ns + (P.origin != 0), 1));
       const int64_t ncrt = blocks_of(P.D + 1, kCrtPerTask);
       cap += ncrt;
       crt_total += ncrt;
@@ -745,7 +762,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     L.cpart = o; o = align_up(o + static_cast<size_t>(d.nchunk) * np * (P.D + 1) * 8, A);
     L.hseg = o;  o = align_up(o + np * align_up(static_cast<size_t>(P.D + 1), kCkpt) * 4, A);
     L.ydig = L.hdig = 0;
-    if (mm_req && P.origin == 0) {  // digit planes of the matrix-core interpolation
+    if (mm_req) {  // digit planes of the matrix-core interpolation
       const size_t planes = np * kDigits * align_up(static_cast<size_t>(P.D + 1), kCkpt);
       L.ydig = o; o = align_up(o + planes, A);
       L.hdig = o; o = align_up(o + planes, A);
@@ -1135,7 +1152,8 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
           (rc = hip_check(ctx, launch_hseg(probs, hseg_items, static_cast<int>(J->hseg_items.size()), T, st),
                           "launch")))
         return rc;
-      if ((rc = hip_check(ctx, launch_interp_mm(s == kStageConv ? 1 : 2, probs, mg, mm, di, nd, mi, nm, T, st),
+      const int which = s == kStageConv ? 1 : 2;
+      if ((rc = hip_check(ctx, launch_interp_mm(which, probs, mg, mm, di, nd, mi, nm, J->mm_lds[which - 1], T, st),
                           "launch")))
         return rc;
       continue;

@@ -62,6 +62,7 @@ struct Job {
   std::vector<StirGroup> mgroups;
   std::vector<StirMember> mmembers;
   std::vector<WorkItem> dig_items, mm_items;
+  int mm_lds[2] = {0, 0};  // dynamic LDS bytes of the two matrix-core interpolation launches
   size_t mg_off = 0, mm_off = 0, digi_off = 0, mmi_off = 0;
   // the ranges the kernels expect zeroed (a table in the upload image, cleared
   // by one launch after the upload)

@@ -34,12 +34,14 @@ hipError_t launch_stir_group(const DevProblem* probs, const StirGroup* groups, c
 // Segment polynomials of the basis change (stage_interp_hseg), before the stir stage.
 hipError_t launch_hseg(const DevProblem* probs, const WorkItem* items, int nitems, const DevTables& T, hipStream_t st);
 // Interpolation on the matrix cores: the digit planes of each (problem, slot)
-// (items: problem, slot, block of 256 positions), then the product of one
-// group's columns (items: group, row tile, set of four column tiles).
+// (items: problem, slot, block of 2048 positions), then the products of one
+// group's columns (items: group, 64-row set, run of 16-column tiles; sub =
+// tiles + 32 x the first tile's largest degree bound).  lds_bytes: the
+// largest kMmColBytes + mm_operand_bytes of the items.
 // which = 1: Newton coefficients into aconv; 2: the basis change into cpart.
 hipError_t launch_interp_mm(int which, const DevProblem* probs, const StirGroup* groups, const StirMember* members,
                             const WorkItem* digit_items, int ndigit, const WorkItem* mm_items, int nmm,
-                            const DevTables& T, hipStream_t st);
+                            int lds_bytes, const DevTables& T, hipStream_t st);
 hipError_t launch_stirling_build(uint32_t* stir, int64_t sstride, const PrimeConst* pcs, int g0,
                                  int count, int scap, hipStream_t st);
 

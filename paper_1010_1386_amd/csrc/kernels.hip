@@ -109,14 +109,14 @@ __global__ __launch_bounds__(256) void k_interp_digits(const DevProblem* probs, 
 template <int WHICH>
 __global__ __launch_bounds__(256) void k_interp_mm(const DevProblem* probs, const StirGroup* groups,
                                                    const StirMember* members, const WorkItem* items, DevTables T) {
-  __shared__ uint64_t lds8[kInterpMmLdsBytes / 8];
+  extern __shared__ uint64_t lds8[];
   const WorkItem w = items[blockIdx.x];
   stage_interp_mm<WHICH>(probs, groups[w.prob], members, w, T, reinterpret_cast<uint8_t*>(lds8));
 }
 
 hipError_t launch_interp_mm(int which, const DevProblem* probs, const StirGroup* groups, const StirMember* members,
                             const WorkItem* digit_items, int ndigit, const WorkItem* mm_items, int nmm,
-                            const DevTables& T, hipStream_t st) {
+                            int lds_bytes, const DevTables& T, hipStream_t st) {
   if (ndigit > 0) {
     if (which == 1) hipLaunchKernelGGL(k_interp_digits<1>, dim3(ndigit), dim3(256), 0, st, probs, digit_items, T);
     else hipLaunchKernelGGL(k_interp_digits<2>, dim3(ndigit), dim3(256), 0, st, probs, digit_items, T);
@@ -124,8 +124,11 @@ hipError_t launch_interp_mm(int which, const DevProblem* probs, const StirGroup*
     if (e != hipSuccess) return e;
   }
   if (nmm <= 0) return hipSuccess;
-  if (which == 1) hipLaunchKernelGGL(k_interp_mm<1>, dim3(nmm), dim3(256), 0, st, probs, groups, members, mm_items, T);
-  else hipLaunchKernelGGL(k_interp_mm<2>, dim3(nmm), dim3(256), 0, st, probs, groups, members, mm_items, T);
+  if (lds_bytes < kMmColBytes || lds_bytes > 65536) return hipErrorInvalidValue;
+  if (which == 1)
+    hipLaunchKernelGGL(k_interp_mm<1>, dim3(nmm), dim3(256), lds_bytes, st, probs, groups, members, mm_items, T);
+  else
+    hipLaunchKernelGGL(k_interp_mm<2>, dim3(nmm), dim3(256), lds_bytes, st, probs, groups, members, mm_items, T);
   return hipGetLastError();
 }
 

@@ -5,10 +5,11 @@
 // finishing the last task of a group enqueues the next stage's tasks:
 //
 //   REDUCE(p, s) -> EVAL(p, s, *)            per (problem, prime slot)
-//   last EVAL(p, s, *) -> CONV(p, s, *)  if the points 0..D are all usable
+//   last EVAL(p, s, *) -> CONV(p, s, *)  if the points origin..origin+D are all usable
 //                      -> NEWTON(p, s)    otherwise (gapped point set)
 //   last CONV(p, s, *) -> STIR(p, s, *)
-//   last STIR(p, s, *) or NEWTON(p, s) -> slot done; last slot of p -> CRT(p, *)
+//   last STIR(p, s, *) -> NEWTON(p, s)  for a shifted origin (the shift back)
+//   last STIR(p, s, *) otherwise, or NEWTON(p, s) -> slot done; last slot of p -> CRT(p, *)
 //   last CRT task of the batch -> done
 //
 // Termination: every wave exits once the done flag is set (or on an error),
@@ -157,7 +158,13 @@ __global__ __launch_bounds__(64) void k_persistent(const DevProblem* probs, Queu
         case kTaskStir:
         case kTaskNewton: {
           bool slot_done = true;
-          if (type == kTaskStir) slot_done = (atomicSub(&C->stir_left[t.slot], 1) == 1);
+          if (type == kTaskStir) {
+            slot_done = (atomicSub(&C->stir_left[t.slot], 1) == 1);
+            if (slot_done && P.origin != 0) {  // the shift back from the origin first
+              enqueue(Q, probs, 1, [&](int) { return mk(kTaskNewton, prob, t.slot, 0, 0); });
+              slot_done = false;
+            }
+          }
           if (slot_done && atomicSub(&C->slots_left, 1) == 1) {
             const int nc = (P.D + kCrtPerTask) / kCrtPerTask;
             enqueue(Q, probs, nc, [&](int i) { return mk(kTaskCrt, prob, -1, i, 0); });

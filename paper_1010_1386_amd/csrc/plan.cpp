@@ -162,9 +162,26 @@ int make_view(const rsl_poly* f, int var, View* v, std::string* err) {
     }
   }
   v->lc_abs.assign(v->rdeg[v->dy] + 1, BigU());
-  for (int i = 0; i <= v->rdeg[v->dy]; ++i)
-    v->lc_abs[i] = abs_limbs(&v->c[(static_cast<size_t>(v->dy) * row + i) * L], L, nullptr);
+  v->lc_neg.assign(v->rdeg[v->dy] + 1, 0);
+  for (int i = 0; i <= v->rdeg[v->dy]; ++i) {
+    bool neg = false;
+    v->lc_abs[i] = abs_limbs(&v->c[(static_cast<size_t>(v->dy) * row + i) * L], L, &neg);
+    v->lc_neg[i] = neg;
+  }
   return RSL_OK;
+}
+
+// The leading coefficient (a polynomial in the other variable) of V at x0,
+// modulo q = 2^31 - 1: zero when x0 is a root over Z (and, rarely, when q
+// divides the value).
+static bool lc_zero_mod_q(const View& V, uint32_t x0) {
+  const uint64_t q = 2147483647u;
+  uint64_t acc = 0;
+  for (size_t i = V.lc_abs.size(); i-- > 0;) {
+    const uint64_t a = V.lc_abs[i].mod_small(static_cast<uint32_t>(q));
+    acc = (acc * (x0 % q) + (V.lc_neg[i] ? (q - a) % q : a)) % q;
+  }
+  return acc == 0;
 }
 
 void crt_tables(const std::vector<uint32_t>& primes, int LP, std::vector<uint32_t>* Tg,
@@ -477,7 +494,7 @@ int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opt
     *err = "opts.points must be RSL_POINTS_REPLACE or RSL_POINTS_FORMAL";
     return RSL_EINVAL;
   }
-  if (o.prime_start < 0 || o.extra_primes < 0 || o.extra_points < 0 || o.point_origin < 0 ||
+  if (o.prime_start < 0 || o.extra_primes < 0 || o.extra_points < 0 || o.point_origin < -1 ||
       o.point_origin > (1 << 24) || o.prime_limit < 0) {
     *err = "invalid options";
     return RSL_EINVAL;
@@ -488,7 +505,7 @@ int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opt
   if (rc) return rc;
   P->zero = (P->f.dy < 0 || P->g.dy < 0);
   P->formal = o.points;
-  P->origin = o.point_origin;
+  P->origin = o.point_origin > 0 ? o.point_origin : 0;
   if (P->zero) return RSL_OK;
 
   const View &F = P->f, &G = P->g;
@@ -505,6 +522,18 @@ int make_plan(const rsl_poly* f, const rsl_poly* g, int var, const rsl_opts* opt
   P->D = static_cast<int>(D);
   P->s = F.rdeg[my] + G.rdeg[ny];
   P->E = P->D + P->s + o.extra_points;
+  // Automatic origin (option 0): a leading coefficient that vanishes at x = 0
+  // over Z makes point 0 bad for every prime, and every prime would take the
+  // gapped interpolation; start instead at the first x0 in 1 .. kAutoOriginMax
+  // where neither leading coefficient vanishes (the consecutive path then
+  // interpolates in x - x0 and shifts back).
+  constexpr uint32_t kAutoOriginMax = 16;
+  if (o.point_origin == 0 && !P->formal && P->s > 0 && (lc_zero_mod_q(F, 0) || lc_zero_mod_q(G, 0)))
+    for (uint32_t x0 = 1; x0 <= kAutoOriginMax; ++x0)
+      if (!lc_zero_mod_q(F, x0) && !lc_zero_mod_q(G, x0)) {
+        P->origin = static_cast<int>(x0);
+        break;
+      }
 
   // Hadamard bound: B^2 = (sum_j ||f_j||_1^2)^{n_y} (sum_j ||g_j||_1^2)^{m_y}.
   // Primes are taken until M^2 > 4 B^2 (M their product).  The comparison runs

@@ -35,6 +35,7 @@ struct View {
   std::vector<uint32_t> c;  // rows 0..dy, cols 0..dx, L limbs each (two's complement)
   std::vector<BigU> row_l1; // per row j: ||f_j||_1, the sum of |coefficient| (planning only)
   std::vector<BigU> lc_abs; // |coefficient| of the leading row (bad-prime screen)
+  std::vector<uint8_t> lc_neg;  // its signs
 };
 
 // CRT constants of one ordered prime list with product M (Sec. 4.1: the
@@ -66,7 +67,7 @@ struct Plan {
   int D = 0;                // degree bound
   int s = 0;                // spare points: deg lc_y f + deg lc_y g
   int E = 0;                // points 0..E are evaluated (E = D + s + extra)
-  int origin = 0;           // first evaluation point
+  int origin = 0;           // first evaluation point (chosen when the option is 0)
   int formal = 0;           // RSL_POINTS_FORMAL
   int np = 0;               // primes used
   std::vector<int> pidx;    // indices into prime_table()

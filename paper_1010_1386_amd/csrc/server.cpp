@@ -392,6 +392,7 @@ static int plan_request(rsl_server* S, const rsl_poly* f, const rsl_poly* g, int
       info->my = P.my;
       info->ny = P.ny;
       info->bad_primes = P.bad_primes;
+      info->origin = P.origin;
     }
     info->footprint_bytes = J.total;
   }

@@ -1107,11 +1107,12 @@ __device__ inline void stage_eval(const DevProblem& P, const DevTables& T, const
 
 // ------------------------------------------------------------ interpolation
 
-// The consecutive fast path applies when the D+1 points used are 0..D: always
-// with formal-degree values at origin 0, otherwise when none of the points
-// 0..D was flagged bad (the evaluation stage sets a per-prime flag).
+// The consecutive fast path applies when the D+1 points used are origin ..
+// origin + D: always with formal-degree values, otherwise when none of them
+// was flagged bad (the evaluation stage sets a per-prime flag).  It
+// interpolates in t = x - origin; for a shifted origin the Newton stage takes
+// the result back to x.
 __device__ inline bool fast_prime(const DevProblem& P, int slot) {
-  if (P.origin != 0) return false;
   if (P.formal) return true;
   return __builtin_amdgcn_readfirstlane(P.status[2 + P.np + slot]) == 0;
 }
@@ -1315,44 +1316,78 @@ __device__ inline void basis_block(const uint32_t* S, int j0, int k1, int ke, in
 // operand B holds the problems' columns as 7-bit digit planes (five digits of
 // each residue), and the 16x16x32 int8 products of the five digits of each
 // side accumulate the nine anti-diagonal sums S_s over the whole K range
-// (each below 5 * 3808 * 127^2 < 2^31), recombined as in the evaluation:
+// (each below 5 (kMmMaxD + 32) 127^2 < 2^31), recombined as in the evaluation:
 //   out = sum_s S_s (2^{7s} mod p), below 9 * 2^29 p < p 2^32,
 // whose REDC is the coefficient in Montgomery form (the operands are
 // Montgomery representatives), written as the single chunk of aconv / cpart.
 
 // Digit planes of one problem slot: WHICH 1, y_n = z_n ifact_n; WHICH 2, hseg
 // (zero beyond D and, for the basis change, for a prime with bad points).
+// Each thread writes eight consecutive entries of every plane (one 64-bit
+// store per plane); item (problem, slot, block of 2048 entries).
+constexpr int kDigitsPerBlock = 2048;
 template <int WHICH>
 __device__ inline void stage_interp_digits(const DevProblem& P, const DevTables& T, const WorkItem& w) {
-  const int n = w.blk * blockDim.x + threadIdx.x;
+  const int n0 = 8 * (w.blk * blockDim.x + threadIdx.x);
   const int Dp = P.hstride;
-  if (n >= Dp) return;
+  if (n0 >= Dp) return;
   const int g = P.pidx[w.slot];
-  uint32_t v = 0u;
-  if (n <= P.D) {
-    if constexpr (WHICH == 1) {
-      const PrimeConst pc = T.pc[g];
-      const uint32_t z = P.zval[static_cast<size_t>(w.slot) * (P.E + 1) + n];
-      v = mmul(z, T.ifact[static_cast<size_t>(g) * T.kstride + n], pc.p, pc.pinv);
-    } else {
-      if (fast_prime(P, w.slot)) v = P.hseg[static_cast<size_t>(w.slot) * P.hstride + n];
-    }
-  }
-  uint8_t* dst = (WHICH == 1 ? P.ydig : P.hdig) + static_cast<size_t>(w.slot) * kDigits * Dp + n;
+  uint32_t v[8];
+  if constexpr (WHICH == 1) {
+    const PrimeConst pc = T.pc[g];
+    const uint32_t* z = P.zval + static_cast<size_t>(w.slot) * (P.E + 1);
+    const uint32_t* fi = T.ifact + static_cast<size_t>(g) * T.kstride;
 #pragma unroll
-  for (int b = 0; b < kDigits; ++b) dst[static_cast<size_t>(b) * Dp] = static_cast<uint8_t>((v >> (7 * b)) & 127u);
+    for (int e = 0; e < 8; ++e) v[e] = (n0 + e <= P.D) ? mmul(z[n0 + e], fi[n0 + e], pc.p, pc.pinv) : 0u;
+  } else {
+    const bool fast = fast_prime(P, w.slot);
+    const uint32_t* h = P.hseg + static_cast<size_t>(w.slot) * P.hstride;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (fast && n0 + e <= P.D) ? h[n0 + e] : 0u;
+  }
+  uint64_t* dst = reinterpret_cast<uint64_t*>((WHICH == 1 ? P.ydig : P.hdig) +
+                                              static_cast<size_t>(w.slot) * kDigits * Dp + n0);
+#pragma unroll
+  for (int b = 0; b < kDigits; ++b) {
+    uint64_t word = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) word |= static_cast<uint64_t>((v[e] >> (7 * b)) & 127u) << (8 * e);
+    dst[static_cast<size_t>(b) * (Dp / 8)] = word;
+  }
 }
 
-// Item (group, set of four row tiles = 64 rows, column tile of 16 members);
-// wave w of the block takes row tile 4 blk + w of that column tile.  Per K
-// slice the block stages in LDS the Toeplitz operand's window for its 64 rows
-// (96 values, reversed, as digit planes) and the column tile's B fragments
-// (loaded once for the four row tiles); lane l's A fragment -- row l mod 16
-// of its tile, K entries 8 (l / 16) .. + 7 -- is eight consecutive bytes of
-// each plane.  Slices alternate between two buffers (one barrier per slice),
-// and the next slice's loads are issued before the current products.
-constexpr int kMmPlane = 128;  // bytes per window digit plane (96 used)
-constexpr int kInterpMmLdsBytes = 2 * (kDigits * kMmPlane + kDigits * 64 * 8);
+// Item (group, 64-row set rs, column tiles ct0 .. ct0 + nct - 1 of 16 members
+// each; members sorted by degree bound, largest first).  The block stages
+// once, in LDS, the Toeplitz operand of its 64 rows over every K slice its
+// tiles reach -- as 7-bit digit planes, reversed so that a lane's eight K
+// entries are eight consecutive bytes -- and the tiles' column descriptors.
+// Then wave w runs row tile rs0 + 16 w against each column tile in turn with
+// no further barrier: B fragments come from the members' digit planes in
+// global memory, the next slice's loads issued before the current slice's 25
+// products.  Lane l's fragments: row / column l mod 16, K entries 8 (l / 16)
+// .. + 7; its outputs are rows 4 (l / 16) .. + 3 of column l mod 16.
+constexpr int kMmTilesMax = 16;  // column tiles per item
+constexpr int kMmRunSlices = 48; // K slices per item (over its tiles), about
+constexpr int kMmMaxD = 2880;    // the basis change stages 640 bytes per slice: LDS below 64 KB
+struct MmCol {
+  const uint8_t* b;  // the member's digit planes (plane stride Dp bytes)
+  uint64_t* out;     // its sums: aconv or cpart of the slot
+  int D, Dp;         // degree bound (-1: no member), plane stride
+};
+constexpr int kMmColBytes = kMmTilesMax * 16 * static_cast<int>(sizeof(MmCol));
+
+// LDS bytes of the Toeplitz operand of an item: rows rs0 .. rs0 + 63, columns
+// of degree bound at most tileD.
+__host__ __device__ inline int mm_slices_lo(int which, int rs0) {
+  return which == 1 ? 0 : (rs0 >= 31 ? (rs0 - 31) / 32 : 0);
+}
+__host__ __device__ inline int mm_slices_hi(int which, int rs0, int tileD) {
+  return which == 1 ? ((rs0 + 63 < tileD) ? rs0 + 63 : tileD) / 32 : tileD / 32;
+}
+__host__ __device__ inline int mm_operand_bytes(int which, int rs0, int tileD) {
+  const int lo = mm_slices_lo(which, rs0), hi = mm_slices_hi(which, rs0, tileD);
+  return which == 1 ? kDigits * (32 * hi + 104) : kDigits * 128 * (hi - lo + 1);
+}
 
 template <int WHICH>
 __device__ inline void stage_interp_mm(const DevProblem* probs, const StirGroup& G, const StirMember* members,
@@ -1360,113 +1395,55 @@ __device__ inline void stage_interp_mm(const DevProblem* probs, const StirGroup&
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const PrimeConst pc = T.pc[G.g];
   const uint32_t p = pc.p;
-  const int rs0 = 64 * w.slot;          // first row of the block
-  const int rw0 = rs0 + 16 * wave;      // first row of this wave's tile
-  const int Dmax = G.maxD;
+  const int rs0 = 64 * w.slot;      // first row of the block
+  const int rw0 = rs0 + 16 * wave;  // first row of this wave's tile
+  const int ct0 = w.blk, nct = w.sub & 31, tileD0 = w.sub >> 5;  // tileD0: the first tile's largest bound
   const int q = lane >> 4, r = lane & 15;
-  // the column tile (members sorted by degree bound, largest first)
-  const int mi = 16 * w.blk + r;
-  const bool valid = mi < G.count;
-  const StirMember M = members[G.first + (valid ? mi : 0)];
-  const DevProblem& Pm = probs[M.prob];
-  const int Dm = valid ? Pm.D : -1;
-  const int Dp = Pm.hstride;
-  const uint8_t* bsrc = (WHICH == 1 ? Pm.ydig : Pm.hdig) + static_cast<size_t>(M.slot) * kDigits * Dp;
-  const int tileD = __builtin_amdgcn_readfirstlane(Dm);  // the tile's largest degree bound
-  const int n0 = 64 - 16 * wave - r + 8 * q;  // first byte of the fragment in the reversed window
+  MmCol* cols = reinterpret_cast<MmCol*>(lds);
+  uint8_t* opnd = lds + kMmColBytes;
+  const int s_lo = mm_slices_lo(WHICH, rs0), s_hi = mm_slices_hi(WHICH, rs0, tileD0);
 
-  uint8_t* winb[2] = {lds, lds + kDigits * kMmPlane};
-  uint64_t* bfr[2] = {reinterpret_cast<uint64_t*>(lds + 2 * kDigits * kMmPlane),
-                      reinterpret_cast<uint64_t*>(lds + 2 * kDigits * kMmPlane + kDigits * 64 * 8)};
-  for (int t = tid; t < 2 * kDigits * kMmPlane / 8; t += blockDim.x) reinterpret_cast<uint64_t*>(lds)[t] = 0u;
-
-  int s_first, s_last;
+  // column descriptors
+  for (int t = tid; t < 16 * nct; t += blockDim.x) {
+    const int mi = 16 * ct0 + t;
+    MmCol c{nullptr, nullptr, -1, 0};
+    if (mi < G.count) {
+      const StirMember M = members[G.first + mi];
+      const DevProblem& Pm = probs[M.prob];
+      c.D = Pm.D;
+      c.Dp = Pm.hstride;
+      c.b = (WHICH == 1 ? Pm.ydig : Pm.hdig) + static_cast<size_t>(M.slot) * kDigits * Pm.hstride;
+      c.out = (WHICH == 1 ? Pm.aconv : Pm.cpart) + static_cast<size_t>(M.slot) * (Pm.D + 1);
+    }
+    cols[t] = c;
+  }
+  // the Toeplitz operand: WHICH 1, one reversed vector R[y] = T(rs0 + 63 - y),
+  // T(x) = (-1)^x / x! for 0 <= x <= maxD; WHICH 2, per slice s a window
+  // W_s[y] = s(32 s, rs0 + 63 - y) for y < 128 (zero outside 0 .. 32 s)
   if constexpr (WHICH == 1) {
-    s_first = 0;
-    s_last = ((rs0 + 63 < Dmax) ? rs0 + 63 : Dmax) / 32;
-  } else {
-    s_first = rs0 >= 31 ? (rs0 - 31) / 32 : 0;
-    s_last = Dmax / 32;
-  }
-  if (tileD < s_last * 32) s_last = tileD >= 0 ? tileD / 32 : -1;  // no column of the tile reaches beyond
-  const uint32_t* ifact = T.ifact + static_cast<size_t>(G.g) * T.kstride;
-  const uint32_t* srow_base = T.stir + static_cast<size_t>(G.g) * T.sstride;
-  // window value t < 96 of a slice: v(xb + t)
-  auto window_value = [&](int sl) -> uint32_t {
-    uint32_t v = 0u;
-    if (tid < 96) {
-      if constexpr (WHICH == 1) {
-        const int x = rs0 - 32 * sl - 31 + tid;  // T(k - i), k in the block's rows, i in the slice
-        if (x >= 0 && x <= Dmax) {
-          const uint32_t f = ifact[x];
-          v = (x & 1) ? p - f : f;
-        }
-      } else {
-        const int x = rs0 - 31 + tid;  // s(k0, j - i), j in the block's rows, i < kCkpt
-        if (x >= 0 && x <= 32 * sl) v = srow_base[ckpt_rowoff(sl) + x];
+    const int Lr = 32 * s_hi + 104;
+    const uint32_t* ifact = T.ifact + static_cast<size_t>(G.g) * T.kstride;
+    for (int y = tid; y < Lr; y += blockDim.x) {
+      const int x = rs0 + 63 - y;
+      uint32_t v = 0u;
+      if (x >= 0 && x <= G.maxD) {
+        const uint32_t f = ifact[x];
+        v = (x & 1) ? p - f : f;
       }
+#pragma unroll
+      for (int b = 0; b < kDigits; ++b) opnd[b * Lr + y] = static_cast<uint8_t>((v >> (7 * b)) & 127u);
     }
-    return v;
-  };
-  // wave 0 loads the column tile's B fragments of a slice (zero beyond a column's problem)
-  auto b_frags = [&](int sl, uint64_t (&Bf)[kDigits]) {
-    const int k0 = 32 * sl, pos = k0 + 8 * q;
-    const bool have = wave == 0 && valid && (WHICH == 1 ? pos <= Dm : k0 <= Dm);
+  } else {
+    const uint32_t* srow = T.stir + static_cast<size_t>(G.g) * T.sstride;
+    const int n = (s_hi - s_lo + 1) * 128;
+    for (int t = tid; t < n; t += blockDim.x) {
+      const int s = s_lo + (t >> 7), y = t & 127, x = rs0 + 63 - y;
+      const uint32_t v = (x >= 0 && x <= 32 * s) ? srow[ckpt_rowoff(s) + x] : 0u;
+      uint8_t* pl = opnd + (s - s_lo) * kDigits * 128 + y;
 #pragma unroll
-    for (int b = 0; b < kDigits; ++b)
-      Bf[b] = have ? *reinterpret_cast<const uint64_t*>(bsrc + static_cast<size_t>(b) * Dp + pos) : 0u;
-  };
-  ev_v4i S[2 * kDigits - 1];
-#pragma unroll
-  for (int s = 0; s < 2 * kDigits - 1; ++s) S[s] = ev_v4i{0, 0, 0, 0};
-  uint32_t vn = 0u;
-  uint64_t Bn[kDigits] = {0u, 0u, 0u, 0u, 0u};
-  if (s_first <= s_last) {
-    vn = window_value(s_first);
-    b_frags(s_first, Bn);
+      for (int b = 0; b < kDigits; ++b) pl[b * 128] = static_cast<uint8_t>((v >> (7 * b)) & 127u);
+    }
   }
-  __syncthreads();  // the zeroed planes
-  for (int sl = s_first; sl <= s_last; ++sl) {
-    const int buf = (sl - s_first) & 1;
-    uint8_t* win = winb[buf];
-    if (tid < 96) {
-#pragma unroll
-      for (int b = 0; b < kDigits; ++b) win[b * kMmPlane + 95 - tid] = static_cast<uint8_t>((vn >> (7 * b)) & 127u);
-    }
-    if (wave == 0) {
-#pragma unroll
-      for (int b = 0; b < kDigits; ++b) bfr[buf][b * 64 + lane] = Bn[b];
-    }
-    __syncthreads();  // one barrier per slice: a buffer is rewritten only after the next one
-    if (sl < s_last) {
-      vn = window_value(sl + 1);
-      b_frags(sl + 1, Bn);
-    }
-    // wave-uniform: this row tile has nothing in the slice
-    const int k0 = 32 * sl;
-    if (rw0 > tileD) continue;
-    if constexpr (WHICH == 1) {
-      if (k0 > rw0 + 15) continue;  // T(k - i) = 0 for i > k
-    } else {
-      if (k0 + 31 < rw0) continue;  // s(k0, j - i) = 0 for j - i > k0
-    }
-    const uint64_t* pl = reinterpret_cast<const uint64_t*>(win);
-    uint64_t A[kDigits], B[kDigits];
-    const int sh = (n0 & 7) * 8, wi = n0 >> 3;
-#pragma unroll
-    for (int b = 0; b < kDigits; ++b) {
-      const uint64_t lo = pl[b * (kMmPlane / 8) + wi], hi = pl[b * (kMmPlane / 8) + wi + 1];
-      A[b] = sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
-      B[b] = bfr[buf][b * 64 + lane];
-    }
-#pragma unroll
-    for (int a = 0; a < kDigits; ++a)
-#pragma unroll
-      for (int b = 0; b < kDigits; ++b)
-        S[a + b] = __builtin_amdgcn_mfma_i32_16x16x32_i8(static_cast<long>(A[a]), static_cast<long>(B[b]), S[a + b],
-                                                         0, 0, 0);
-  }
-  if (!valid || rw0 > Dm) return;
   uint32_t wgt[2 * kDigits - 1];  // 2^(7 s) mod p
   wgt[0] = 1u;
 #pragma unroll
@@ -1474,14 +1451,67 @@ __device__ inline void stage_interp_mm(const DevProblem* probs, const StirGroup&
     const uint64_t t = static_cast<uint64_t>(wgt[s - 1]) << 7;
     wgt[s] = static_cast<uint32_t>(t % p);
   }
-  uint64_t* out = (WHICH == 1 ? Pm.aconv : Pm.cpart) + static_cast<size_t>(M.slot) * (Dm + 1);
+  __syncthreads();
+
+  // lane's first byte of its A fragment in the operand (plus 32 s for WHICH 1)
+  const int y0 = 63 - 16 * wave - r + 8 * q;
+  const int sh = (y0 & 7) * 8;
+  const uint64_t* op64 = reinterpret_cast<const uint64_t*>(opnd);
+  const int Lr8 = (32 * s_hi + 104) / 8;  // WHICH 1 plane stride in words
+  for (int ct = 0; ct < nct; ++ct) {
+    const MmCol C = cols[16 * ct + r];
+    const int tileD = __builtin_amdgcn_readfirstlane(cols[16 * ct].D);  // the tile's largest degree bound
+    if (rw0 > tileD) break;             // wave-uniform; later tiles have smaller bounds
+    int sa, sb;
+    if constexpr (WHICH == 1) {
+      sa = 0;
+      sb = ((rw0 + 15 < tileD) ? rw0 + 15 : tileD) / 32;  // T(k - i) = 0 for i > k
+    } else {
+      sa = rw0 / 32;  // s(k0, j - i) = 0 for j - i > k0: slices with k0 + 31 >= rw0
+      sb = tileD / 32;
+    }
+    auto load_b = [&](int s, uint64_t (&Bf)[kDigits]) {
+      const bool have = 32 * s <= C.D;
+      const uint8_t* src = C.b + 32 * s + 8 * q;
 #pragma unroll
-  for (int r4 = 0; r4 < 4; ++r4) {
-    const int row = rw0 + 4 * q + r4;
-    uint64_t t = 0;
+      for (int b = 0; b < kDigits; ++b)
+        Bf[b] = have ? *reinterpret_cast<const uint64_t*>(src + static_cast<size_t>(b) * C.Dp) : 0u;
+    };
+    ev_v4i S[2 * kDigits - 1];
 #pragma unroll
-    for (int s = 0; s < 2 * kDigits - 1; ++s) t += static_cast<uint64_t>(static_cast<uint32_t>(S[s][r4])) * wgt[s];
-    if (row <= Dm) out[row] = t;
+    for (int s = 0; s < 2 * kDigits - 1; ++s) S[s] = ev_v4i{0, 0, 0, 0};
+    uint64_t Bn[kDigits];
+    load_b(sa, Bn);
+    for (int s = sa; s <= sb; ++s) {
+      uint64_t B[kDigits];
+#pragma unroll
+      for (int b = 0; b < kDigits; ++b) B[b] = Bn[b];
+      if (s < sb) load_b(s + 1, Bn);
+      uint64_t A[kDigits];
+#pragma unroll
+      for (int b = 0; b < kDigits; ++b) {
+        int wi;
+        if constexpr (WHICH == 1) wi = b * Lr8 + ((y0 + 32 * s) >> 3);
+        else wi = ((s - s_lo) * kDigits + b) * 16 + (y0 >> 3);
+        const uint64_t lo = op64[wi], hi = op64[wi + 1];
+        A[b] = sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
+      }
+#pragma unroll
+      for (int a = 0; a < kDigits; ++a)
+#pragma unroll
+        for (int b = 0; b < kDigits; ++b)
+          S[a + b] = __builtin_amdgcn_mfma_i32_16x16x32_i8(static_cast<long>(A[a]), static_cast<long>(B[b]),
+                                                           S[a + b], 0, 0, 0);
+    }
+    if (rw0 > C.D) continue;
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4) {
+      const int row = rw0 + 4 * q + r4;
+      uint64_t t = 0;
+#pragma unroll
+      for (int s = 0; s < 2 * kDigits - 1; ++s) t += static_cast<uint64_t>(static_cast<uint32_t>(S[s][r4])) * wgt[s];
+      if (row <= C.D) C.out[row] = t;
+    }
   }
 }
 
@@ -1589,15 +1619,60 @@ __host__ __device__ inline int newton_lds_words(const DevProblem& P, int nthread
   return 3 * e1 + (e1 > nthreads ? e1 : nthreads);
 }
 
-// Gapped point sets (bad points replaced, or a shifted origin): one block per
-// prime; select the first D+1 usable points, Newton divided differences, then
-// the Newton form expanded in the monomial basis by Horner.
+// Consecutive points from a shifted origin o: the fast path left the
+// coefficients ct_k of R(t + o) in the slot's partial sums; R(x) has
+//   c_j = sum_{k >= j} C(k, j) (-o)^(k-j) ct_k,
+// a correlation j! c_j = sum_d u_{j+d} v_d with u_k = k! ct_k and
+// v_d = (-o)^d / d! (a Taylor shift), one thread per j.  Written as the
+// Newton stage writes its result: c_j 2^32 in the first chunk the CRT reads
+// for j, zero in the later ones.  LDS: 2 (D+1) words.
+__device__ inline void shift_origin(const DevProblem& P, const DevTables& T, int slot, uint32_t* lds) {
+  const int tid = threadIdx.x, nt = blockDim.x, D = P.D;
+  const int g = P.pidx[slot];
+  const PrimeConst pc = T.pc[g];
+  const uint32_t p = pc.p, pinv = pc.pinv;
+  const uint32_t* fact = T.fact + static_cast<size_t>(g) * T.kstride;
+  const uint32_t* ifact = T.ifact + static_cast<size_t>(g) * T.kstride;
+  const size_t cstride = static_cast<size_t>(P.np) * (D + 1);
+  uint64_t* cp = P.cpart + static_cast<size_t>(slot) * (D + 1);
+  uint32_t* u = lds;
+  uint32_t* v = lds + (D + 1);
+  const uint32_t mo = mmul(p - static_cast<uint32_t>(P.origin), pc.r2, p, pinv);  // -o R (o < 2^24 < p)
+  for (int k = tid; k <= D; k += nt) {
+    uint64_t cs = 0;
+    for (int ch = k / P.kchunk; ch < P.nchunk; ++ch) cs = add_fold(cs, cp[ch * cstride + k], p);
+    u[k] = mmul(redc(cs, p, pinv), fact[k], p, pinv);  // k! ct_k
+    uint32_t pw = pc.r1, base = mo;                     // (-o)^k R by squaring
+    for (int e = k; e; e >>= 1) {
+      if (e & 1) pw = mmul(pw, base, p, pinv);
+      base = mmul(base, base, p, pinv);
+    }
+    v[k] = mmul(pw, ifact[k], p, pinv);  // (-o)^k / k! R
+  }
+  __syncthreads();  // every partial sum is read before any is overwritten
+  for (int j = tid; j <= D; j += nt) {
+    uint64_t acc = 0;
+    for (int d = 0; d <= D - j; ++d) acc = mac_fold(acc, u[j + d], v[d], p);
+    const uint32_t c = mmul(redc(acc, p, pinv), ifact[j], p, pinv);
+    const int ch0 = j / P.kchunk;
+    cp[ch0 * cstride + j] = static_cast<uint64_t>(c) << 32;
+    for (int ch = ch0 + 1; ch < P.nchunk; ++ch) cp[ch * cstride + j] = 0;
+  }
+}
+
+// Gapped point sets (bad points replaced): one block per prime; select the
+// first D+1 usable points, Newton divided differences, then the Newton form
+// expanded in the monomial basis by Horner.  Slots that took the consecutive
+// path need only the shift back from a nonzero origin.
 __device__ inline void stage_interp_newton(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int slot = w.slot;
   const bool fast = fast_prime(P, slot);
   if (tid == 0) P.status[1 + slot] = fast ? 0 : 1;
-  if (fast) return;
+  if (fast) {
+    if (P.origin != 0) shift_origin(P, T, slot, lds);
+    return;
+  }
   const int g = P.pidx[slot];
   const PrimeConst pc = T.pc[g];
   const uint32_t p = pc.p, pinv = pc.pinv;

@@ -72,6 +72,7 @@ def test_query_degrees_and_points(rsl):
     q = rsl.query(F, G, "y")
     assert (q["my"], q["ny"]) == (2, 2)
     assert q["n_points"] == q["D"] + 1 + 2 + 3  # s = deg lc_y f + deg lc_y g = 2 + 3
+    assert q["origin"] == 1  # lc_y f (0) = 0: every prime's point 0 is bad; lc_y f (1) = -2
     z = rsl.query([[0]], G, "y")
     assert z["D"] == -1
 
@@ -138,3 +139,21 @@ def test_factorisation_identity_for_curve_workload():
         assert rFQ == res(F, Q)
         rhs = pmul([4 * sign], pmul(h, pmul(res(F, Fy), pmul(rFQ, rFQ))))
         assert R == rhs
+
+
+@pytest.mark.parametrize("lc, origin", [([1, 1], 0), ([0, 1], 1), ([0, -1, 1], 2), ([0, 0, 1], 1),
+                                        ([0, 2, -3, 1], 3), ([7], 0), ([0, 1 << 40], 1)])
+def test_automatic_origin(rsl, lc, origin):
+    """Default options: origin 0 unless a leading coefficient vanishes at 0 over Z,
+    then the first x0 >= 1 where neither does (here lc_y f = the given row)."""
+    F = [[3, 1, -2], [1, 4], lc]
+    G = [[5, -1], [2, 2, 1], [1, 0, 2]]
+    assert rsl.query(F, G, "y")["origin"] == origin
+    assert rsl.query(G, F, "y")["origin"] == origin  # either polynomial's coefficient
+
+
+def test_automatic_origin_needs_a_root_shared_by_every_prime(rsl):
+    # constant leading coefficients: no bad point anywhere, origin 0
+    F = [[1, 2], [3], [5]]
+    G = [[2], [1, 1], [4]]
+    assert rsl.query(F, G, "y")["origin"] == 0

@@ -78,15 +78,38 @@ def test_degenerate_inputs(ctx):
 
 
 def test_planted_bad_point_every_prime(ctx):
-    """lc_y f = (x - a): point a is bad for every prime and must be replaced."""
+    """lc_y f = (x - a): point a is bad for every prime and must be replaced
+    (origin 0 kept, so that a = 0 takes the gapped path too)."""
     for a in (0, 1, 5):
         F = [[3, 1, -2], [1, 4], [-a, 1]]
         G = [[5, -1], [2, 2, 1], [1]]
         R = oracle.res(F, G)
         assert ctx.res(F, G) == R
         assert ctx.res(F, G, points="formal") == R
+        assert ctx.res(F, G, point_origin=-1) == R
         c = ctx.counters()
         assert c["bad_pairs"] >= 1
+
+
+def test_automatic_origin_when_zero_is_bad_everywhere(ctx):
+    """Leading coefficients vanishing at x = 0 over Z move the default origin:
+    x (x - 1) (x - 3) to 2 (point 3 still bad: the gapped path from there),
+    x^2 (x - 1) to 2 and 5 x to 1 (no bad point: the consecutive path and the
+    shift back).  Every result agrees with the oracle and with origin 0."""
+    import paper_1010_1386_amd as rsl
+    rng = rng_for(706, 0)
+    G = dense_total(rng, 5, 20)
+    for lc, origin, bad in (([0, 3, -4, 1], 2, True), ([0, 0, -1, 1], 2, False), ([0, 5], 1, False)):
+        F = dense_total(rng, 4, 20)
+        F.append(lc)
+        for var in "yx":
+            R = oracle.res(F, G, var)
+            q = rsl.query(F, G, var)
+            assert ctx.res(F, G, var) == R
+            if var == "y":
+                assert q["origin"] == origin
+                assert (ctx.counters()["bad_pairs"] > 0) == bad
+            assert ctx.res(F, G, var, point_origin=-1) == R
 
 
 def test_linear_substitution_closed_form(ctx):
