@@ -346,27 +346,63 @@ static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g
       return rc0;
     }
   }
-  // producer: plans and lays out one chunk after the other (host only; the
-  // tables are grown below, on this thread)
-  std::thread producer([&]() {
-    const double tb = now_ms();
-    for (int c = 0; c < S; ++c) {
-      const int lo = ranges[c].first, hi = ranges[c].second;
-      Job& J = *jobs[c];
-      job_plan(hi - lo, f + lo, g + lo, var + lo, opts, &J, &errs[c]);
-      brc[c] = job_build(ctx, J.n, f + lo, g + lo, var + lo, opts, &J, &errs[c], tc, true, true);
-      std::lock_guard<std::mutex> lk(mu);
-      ready[c] = 1;
-      cv.notify_all();
-    }
-    build_ms = now_ms() - tb;
-  });
+  // producers: kProducers host threads plan and lay out the chunks, producer
+  // q taking chunks q, q + kProducers, ... in order (host only; the tables
+  // are grown below, on this thread).  build_ms: the time until the last
+  // chunk was laid out.
+  constexpr int kProducers = 2;
+  const int nprod = std::min(S, kProducers);
+  const double tb = now_ms();
+  std::vector<std::thread> producers;
+  for (int q = 0; q < nprod; ++q)
+    producers.emplace_back([&, q]() {
+      for (int c = q; c < S; c += nprod) {
+        const int lo = ranges[c].first, hi = ranges[c].second;
+        Job& J = *jobs[c];
+        job_plan(hi - lo, f + lo, g + lo, var + lo, opts, &J, &errs[c]);
+        brc[c] = job_build(ctx, J.n, f + lo, g + lo, var + lo, opts, &J, &errs[c], tc, true, true);
+        std::lock_guard<std::mutex> lk(mu);
+        ready[c] = 1;
+        build_ms = std::max(build_ms, now_ms() - tb);
+        cv.notify_all();
+      }
+    });
   hipStream_t st = ctx->stream;
   int rc = RSL_OK;
   size_t off = 0;
-  int launched = 0;
-  double bind_ms = 0.0;
+  int launched = 0, decoded = 0;
+  double bind_ms = 0.0, dec_ms = 0.0;
+  // decode launched chunks in order: those whose copies are done (block =
+  // false), or all of them
+  auto decode = [&](bool block) {
+    while (decoded < launched) {
+      const int c = decoded;
+      Job& J = *jobs[c];
+      const int lo = ranges[c].first;
+      if (!J.live.empty()) {
+        if (!block && hipEventQuery(ctx->chunk_stage[c].e2) != hipSuccess) return;
+        const int e = hip_check(ctx, hipEventSynchronize(ctx->chunk_stage[c].e2), "hipEventSynchronize");
+        if (e) {
+          rc = rc ? rc : e;
+          decoded = launched;
+          return;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ctx->chunk_stage[c].e0, ctx->chunk_stage[c].e1);
+        cnt->ms_device += ms;
+      }
+      const double t3 = now_ms();
+      std::vector<int> stc(J.n);
+      const int r = job_decode(ctx, J, J.live.empty() ? nullptr : ctx->chunk_stage[c].down, out + lo, stc.data(), cnt);
+      dec_ms += now_ms() - t3;
+      if (status)
+        for (int k = 0; k < J.n; ++k) status[lo + k] = stc[k];
+      if (r && !rc) rc = r;
+      ++decoded;
+    }
+  };
   for (int c = 0; c < S && !rc; ++c) {
+    decode(false);  // while the next chunk is still being laid out
     {
       std::unique_lock<std::mutex> lk(mu);
       cv.wait(lk, [&] { return ready[c] != 0; });
@@ -408,27 +444,9 @@ static int run_chunked(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g
       break;
     ++launched;
   }
-  // decode each launched chunk as soon as its copies are done
-  double dec_ms = 0.0;
-  for (int c = 0; c < launched; ++c) {
-    Job& J = *jobs[c];
-    const int lo = ranges[c].first;
-    if (!J.live.empty()) {
-      const int e = hip_check(ctx, hipEventSynchronize(ctx->chunk_stage[c].e2), "hipEventSynchronize");
-      if (e) { rc = rc ? rc : e; break; }
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, ctx->chunk_stage[c].e0, ctx->chunk_stage[c].e1);
-      cnt->ms_device += ms;
-    }
-    const double t3 = now_ms();
-    std::vector<int> stc(J.n);
-    const int r = job_decode(ctx, J, J.live.empty() ? nullptr : ctx->chunk_stage[c].down, out + lo, stc.data(), cnt);
-    dec_ms += now_ms() - t3;
-    if (status)
-      for (int k = 0; k < J.n; ++k) status[lo + k] = stc[k];
-    if (r && !rc) rc = r;
-  }
-  producer.join();
+  // the remaining chunks, each as soon as its copies are done
+  decode(true);
+  for (std::thread& t : producers) t.join();
   (void)sync_all();
   cnt->ms_build += build_ms;
   cnt->ms_bind += bind_ms;
@@ -466,7 +484,7 @@ static int run_in_workspace(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_po
   if (mode != RSL_BATCHED) {
     int live = 0;
     for (const ShapeEst& e : est) live += (!e.zero && !e.bad) ? 1 : 0;
-    int S = live >= 384 ? 6 : live >= 192 ? 4 : live >= 96 ? 2 : 1;
+    int S = live >= 384 ? 5 : live >= 192 ? 4 : live >= 96 ? 2 : 1;
     if (const char* env = std::getenv("RSL_BATCH_CHUNKS")) S = std::max(1, std::min(16, std::atoi(env)));
     if (S > 1) {
       std::vector<std::pair<int, int>> ranges = chunk_ranges(est, var, S);

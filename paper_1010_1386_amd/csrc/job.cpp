@@ -357,12 +357,27 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     });
     std::vector<int>& off = J->tmp_b;
     off.assign(cnt.size(), 0);
+    // the evaluation items grouped by layout variant (problem order within a
+    // variant): each variant is one launch of the staged schedule
+    std::vector<int>& var_of = J->tmp_c;
+    var_of.resize(nl);
+    int nv = 1;
+    for (int li = 0; li < nl; ++li) {
+      var_of[li] = eval_variant(J->dev[li]);
+      nv = std::max(nv, var_of[li] + 1);
+    }
+    J->eval_vstart.assign(static_cast<size_t>(nv) + 1, 0);
     for (int s = 0; s < kLists; ++s) {
       int o = 0;
-      for (int li = 0; li < nl; ++li) {
-        off[static_cast<size_t>(li) * kLists + s] = o;
-        o += cnt[static_cast<size_t>(li) * kLists + s];
+      for (int v = 0; v < (s == kStageEval ? nv : 1); ++v) {
+        if (s == kStageEval) J->eval_vstart[v] = o;
+        for (int li = 0; li < nl; ++li) {
+          if (s == kStageEval && var_of[li] != v) continue;
+          off[static_cast<size_t>(li) * kLists + s] = o;
+          o += cnt[static_cast<size_t>(li) * kLists + s];
+        }
       }
+      if (s == kStageEval) J->eval_vstart[nv] = o;
       std::vector<WorkItem>& v = s < kNumStages ? J->items[s] : J->hseg_items;
       v.clear();
       v.resize(o);
@@ -424,51 +439,31 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     for (int pass = 0; pass < 3; ++pass) L.wide_end[pass] = static_cast<int>(J->wide_items[pass].size());
   }
 
-  // evaluation items by layout (stable: a problem's items stay together, as
-  // the one-pipeline-per-problem schedule needs)
+  // evaluation items: grouped by layout variant as they were written (a
+  // problem's items stay together, as the one-pipeline-per-problem schedule needs)
   {
-    std::vector<WorkItem>& ev = J->items[kStageEval];
-    {  // stable counting sort by layout variant
-      std::vector<int> var_of(nl);
-      int nv = 1;
-      for (int li = 0; li < nl; ++li) {
-        var_of[li] = eval_variant(J->dev[li]);
-        nv = std::max(nv, var_of[li] + 1);
-      }
-      std::vector<size_t> start(nv + 1, 0);
-      for (const WorkItem& w : ev) ++start[var_of[w.prob] + 1];
-      for (int v = 0; v < nv; ++v) start[v + 1] += start[v];
-      std::vector<WorkItem>& sorted = J->tmp_items;
-      sorted.resize(ev.size());
-      for (const WorkItem& w : ev) sorted[start[var_of[w.prob]]++] = w;
-      ev.swap(sorted);
-    }
-    for (int li = 0; li < nl; ++li) J->lay[li].item_begin[kStageEval] = J->lay[li].item_end[kStageEval] = -1;
-    for (int t = 0; t < static_cast<int>(ev.size()); ++t) {
-      ProbLayout& L = J->lay[ev[t].prob];
-      if (L.item_begin[kStageEval] < 0) L.item_begin[kStageEval] = t;
-      L.item_end[kStageEval] = t + 1;
-    }
-    for (int li = 0; li < nl; ++li)
-      if (J->lay[li].item_begin[kStageEval] < 0) J->lay[li].item_begin[kStageEval] = J->lay[li].item_end[kStageEval] = 0;
+    const std::vector<WorkItem>& ev = J->items[kStageEval];
+    const std::vector<int>& vstart = J->eval_vstart;
+    const int nv = static_cast<int>(vstart.size()) - 1;
+    J->eval_ranges.clear();
+    for (int v = 0; v < nv; ++v)
+      if (vstart[v] < vstart[v + 1])
+        J->eval_ranges.push_back({v, static_cast<int>(vstart[v]), static_cast<int>(vstart[v + 1])});
     // the staged launches take the same items dealt so that all blocks of one
     // (problem, prime) run on the same XCD: workgroup i of a launch goes to
     // XCD i mod 8, so the prime's coefficient tile is fetched into one L2
     // instead of eight.  Per variant range: the g-th (problem, prime) of the
     // range goes to bin g mod 8, and launch position t takes the next item of
     // bin t mod 8 (of the bin with the most items left once that one is empty).
+    // The ranges are independent: one host thread each.
     constexpr int kXcds = 8;
     J->eval_staged.resize(ev.size());
-    J->eval_ranges.clear();
     std::vector<int>& bin = J->tmp_a;
     std::vector<int>& order = J->tmp_b;  // items of the range by bin, stable
     bin.resize(ev.size());
     order.resize(ev.size());
-    size_t b0 = 0;
-    while (b0 < ev.size()) {
-      size_t b1 = b0;
-      const int v = eval_variant(J->dev[ev[b0].prob]);
-      while (b1 < ev.size() && eval_variant(J->dev[ev[b1].prob]) == v) ++b1;
+    parallel_for(static_cast<int>(J->eval_ranges.size()), 1, [&](int ri) {
+      const size_t b0 = static_cast<size_t>(J->eval_ranges[ri].begin), b1 = static_cast<size_t>(J->eval_ranges[ri].end);
       size_t bsize[kXcds] = {}, bstart[kXcds + 1] = {}, pos[kXcds] = {};
       int pairs_seen = -1, last_prob = -1, last_slot = -1;
       for (size_t t = b0; t < b1; ++t) {
@@ -498,9 +493,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
         }
         J->eval_staged[t] = ev[order[b0 + bstart[x] + pos[x]++]];
       }
-      J->eval_ranges.push_back({v, static_cast<int>(b0), static_cast<int>(b1)});
-      b0 = b1;
-    }
+    });
   }
 
   // prime groups for the basis change: every (problem, slot) by global prime

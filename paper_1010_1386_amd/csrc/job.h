@@ -45,6 +45,7 @@ struct Job {
     int variant, begin, end;
   };
   std::vector<EvalRange> eval_ranges;  // ranges of eval_staged
+  std::vector<int> eval_vstart;        // first evaluation item of each layout variant (and the end)
   std::vector<WorkItem> eval_staged;   // evaluation items dealt across XCDs
   size_t evs_off = 0;
   // basis change over prime groups (staged schedule)
@@ -57,7 +58,7 @@ struct Job {
   size_t hseg_off = 0;
   // interpolation on the matrix cores: prime groups of (problem, slot) columns
   // (all members of a prime), the digit-plane items (problem, slot, block of
-  // 256 positions) and the product items (group, row tile, column-tile set)
+  // 2048 positions) and the product items (group, 64-row set, run of column tiles)
   bool mm_interp = false;
   std::vector<StirGroup> mgroups;
   std::vector<StirMember> mmembers;

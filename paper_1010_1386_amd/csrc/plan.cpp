@@ -32,6 +32,7 @@ uint64_t powmod64(uint64_t a, uint64_t e, uint64_t m) {
 
 std::mutex g_prime_mu;
 std::vector<uint32_t> g_primes;
+std::atomic<size_t> g_prime_count{0};  // entries published (written before the count)
 uint32_t g_next_candidate = 1431655765u;  // floor(2^32 / 3): every prime p of the table has 3p < 2^32
 
 constexpr size_t kPrimeTableMax = 1u << 16;
@@ -60,16 +61,23 @@ bool is_prime_u32(uint32_t n) {
 }
 
 const uint32_t* prime_table(size_t at_least, size_t* avail) {
+  at_least = std::min(at_least, kPrimeTableMax);
+  // fast path (no lock): the entries below the published count are final
+  const size_t have = g_prime_count.load(std::memory_order_acquire);
+  if (have > 0 && have >= at_least) {
+    if (avail) *avail = have;
+    return g_primes.data();
+  }
   std::lock_guard<std::mutex> lk(g_prime_mu);
   // the storage is reserved once, so the table never moves: a pointer taken by
   // one planning thread stays valid while another thread extends the table
   if (g_primes.capacity() < kPrimeTableMax) g_primes.reserve(kPrimeTableMax);
-  at_least = std::min(at_least, kPrimeTableMax);
   while (g_primes.size() < at_least) {
     uint32_t c = g_next_candidate;
     g_next_candidate -= 2;
     if (is_prime_u32(c)) g_primes.push_back(c);
   }
+  g_prime_count.store(g_primes.size(), std::memory_order_release);
   if (avail) *avail = g_primes.size();
   return g_primes.data();
 }
