@@ -157,6 +157,11 @@ typedef struct {
                           basis change); staged schedule (plain runs take the vector
                           path on the same layout); 0 = vector path unless the
                           autotuner chose the matrix cores */
+  int32_t interp_newton;/* 1: every prime interpolates by the Vandermonde solve of the gapped
+                          path -- divided differences, then the Newton form expanded to
+                          monomials (the triangular factors of the Vandermonde matrix,
+                          paper Sec. 4.1), D + 1 parallel steps per prime -- instead of the
+                          consecutive-point products; 0 = only primes with a bad point */
 } rsl_opts;
 
 /* Counters of the last call on a context (or of a server). */

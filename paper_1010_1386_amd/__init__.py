@@ -64,7 +64,8 @@ class rsl_opts(ctypes.Structure):
     _fields_ = [("points", ctypes.c_int32), ("prime_start", ctypes.c_int32), ("extra_primes", ctypes.c_int32),
                 ("point_origin", ctypes.c_int32), ("extra_points", ctypes.c_int32),
                 ("prime_limit", ctypes.c_int32), ("eval_lanes", ctypes.c_int32), ("eval_regs", ctypes.c_int32),
-                ("eval_schur", ctypes.c_int32), ("interp_mm", ctypes.c_int32)]
+                ("eval_schur", ctypes.c_int32), ("interp_mm", ctypes.c_int32),
+                ("interp_newton", ctypes.c_int32)]
 
 
 class rsl_counters(ctypes.Structure):
@@ -266,13 +267,14 @@ def query(f, g, var="y"):
 
 
 def _opts(points="replace", prime_start=0, extra_primes=0, point_origin=0, extra_points=0, prime_limit=0,
-          eval_lanes=0, eval_regs=True, eval_schur=False, interp_mm=False):
+          eval_lanes=0, eval_regs=True, eval_schur=False, interp_mm=False, interp_newton=False):
     if eval_lanes not in (0, 1, 2, 4):
         raise ValueError("eval_lanes must be 0, 1, 2 or 4")
     o = rsl_opts()
     o.eval_lanes = eval_lanes
     o.eval_regs = 0 if eval_regs else -1
     o.eval_schur = 1 if eval_schur else 0
+    o.interp_newton = 1 if interp_newton else 0
     o.interp_mm = 1 if interp_mm else 0
     o.points = RSL_POINTS_FORMAL if points in ("formal", RSL_POINTS_FORMAL) else RSL_POINTS_REPLACE
     o.prime_start, o.extra_primes = prime_start, extra_primes

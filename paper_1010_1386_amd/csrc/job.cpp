@@ -199,6 +199,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
   J->max_np = 0;
   J->any_schur = false;
   const bool schur_req = (opts && opts->eval_schur > 0) || J->tune.schur != 0;
+  const bool newton_req = opts && opts->interp_newton > 0;
   for (int li = 0; li < nl; ++li) {
     const Plan& P = J->plans[J->live[li]];
     DevProblem& d = J->dev[li];
@@ -227,6 +228,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     const bool long_ok = d.evk == 1;
     d.regn = (d.evk <= 2) ? regn_of(P, long_ok) : 0;
     d.schur = (schur_req && P.my >= 1 && P.ny >= 1 && P.my + P.ny <= kSchurMaxR) ? 1 : 0;
+    d.newton_all = newton_req ? 1 : 0;
     if (d.schur) {  // one wave per pair, kSchurPts points per block
       d.evk = 1;
       d.evpb = kSchurPts;
@@ -334,7 +336,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       case kStageNewton:
         // gapped interpolation is possible only with a non-constant leading
         // coefficient (bad points) or a shifted origin
-        if (P.origin != 0 || (!P.formal && P.s > 0))
+        if (P.origin != 0 || (!P.formal && P.s > 0) || d.newton_all)
           for (int sl = 0; sl < P.np; ++sl) put(sl, 0, 0);
         break;
       case kStageCrt:

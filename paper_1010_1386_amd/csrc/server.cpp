@@ -223,12 +223,14 @@ int launch(rsl_server* S, Lane& ln, std::vector<std::shared_ptr<Request>>& grp) 
   ln.job = std::move(J);
   ln.off = off;
   ln.bytes = bytes;
-  job_bind(&ln.job, ctx->ws + off);
   if (grow_pinned(&ln.h_up, &ln.h_up_bytes, ln.job.up_bytes) ||
       grow_pinned(&ln.h_down, &ln.h_down_bytes, ln.job.down_bytes)) {
     S->arena.release(off, bytes);
     return RSL_EDEVICE;
   }
+  // the upload image written straight into the lane's pinned staging, without
+  // the persistent queue (the lane's previous upload is complete: it retired)
+  job_bind(&ln.job, ctx->ws + off, ln.h_up, false);
   {
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     if ((rc = job_upload(ctx, &ln.job, ln.stream, ln.h_up)) ||

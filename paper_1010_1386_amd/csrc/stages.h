@@ -1113,6 +1113,7 @@ __device__ inline void stage_eval(const DevProblem& P, const DevTables& T, const
 // interpolates in t = x - origin; for a shifted origin the Newton stage takes
 // the result back to x.
 __device__ inline bool fast_prime(const DevProblem& P, int slot) {
+  if (P.newton_all) return false;
   if (P.formal) return true;
   return __builtin_amdgcn_readfirstlane(P.status[2 + P.np + slot]) == 0;
 }

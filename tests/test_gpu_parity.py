@@ -169,3 +169,32 @@ def test_config2_matches_golden_digest(ctx, var):
     for i, v in rec["samples"].items():
         assert got[int(i)] == int(v)
     assert _digest(got) == rec["sha256"]
+
+
+def test_vandermonde_solve_for_every_prime(ctx):
+    """interp_newton: every prime through the divided-difference solve (the
+    triangular factors of the Vandermonde matrix, Sec. 4.1) gives the same
+    result as the consecutive-point products, for single problems (with and
+    without bad points, shifted origin) and a job in both schedules."""
+    import paper_1010_1386_amd as rsl
+    rng = rng_for(707, 0)
+    probs = []
+    for k in range(6):
+        F = dense_total(rng, 3 + k, 20)
+        G = dense_total(rng, 2 + k, 20)
+        if k % 3 == 1:
+            F.append([0, -2, 1])  # lc_y f = x (x - 2): shifted origin, point 2 bad
+        probs.append((F, G, "yx"[k % 2]))
+    for F, G, var in probs[:4]:
+        want = oracle.res(F, G, var)
+        assert ctx.res(F, G, var, interp_newton=True) == want
+        assert ctx.res(F, G, var, interp_newton=True, points="formal") == want
+    base = ctx.job(probs)
+    base.run("staged")
+    want = base.results()
+    base.close()
+    job = ctx.job(probs, interp_newton=True)
+    for mode in ("staged", "plain"):
+        job.run(mode)
+        assert job.results() == want
+    job.close()
