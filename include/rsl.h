@@ -438,7 +438,9 @@ int rsl_server_submit(rsl_server *s, const rsl_poly *f, const rsl_poly *g, int v
  * inputs and plan the request (info as rsl_query's; RSL_ENOMEM when its tables
  * would not fit the context's table region), then queue it under `handle`
  * with its result buffer.  The request is planned once; the scheduler lays
- * out its batches from those plans.  A handle is used by one enqueue. */
+ * out its batches from those plans.  A handle is used by one successful
+ * enqueue; after RSL_EAGAIN (queue full) it stays valid for a later one, after
+ * any other error it is spent.  Handles never enqueued are freed with the server. */
 int rsl_server_plan(rsl_server *s, const rsl_poly *f, const rsl_poly *g, int var, rsl_info *info,
                     uint64_t *handle);
 int rsl_server_enqueue(rsl_server *s, uint64_t handle, rsl_result *out, uint64_t *ticket);

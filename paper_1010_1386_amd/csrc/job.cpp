@@ -236,8 +236,9 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       J->any_schur = true;
     }
     // the Horner sums on the matrix cores: the register form (one lane or a
-    // lane pair per (prime, point)), at most 32 x-powers (one K slice of the products)
-    d.evmf = (d.evk <= 2 && d.regn > 0 && !d.schur && P.rowf <= 32 && P.rowg <= 32 && !(ctx && ctx->eval_horner))
+    // lane pair per (prime, point)), x-powers 0..31 in one K slice of the
+    // products and x-power 32, if any, on the vector ALUs
+    d.evmf = (d.evk <= 2 && d.regn > 0 && !d.schur && P.rowf <= 33 && P.rowg <= 33 && !(ctx && ctx->eval_horner))
                  ? 1 : 0;
     d.dRTf = d.evmf ? dig_rt(P.my + 1) : 0;
     d.dRTg = d.evmf ? dig_rt(P.ny + 1) : 0;
@@ -260,8 +261,11 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
       const int64_t pts = static_cast<int64_t>(P.np) * (P.E + 1);
       const int64_t sums = pair_mulmods(P) - static_cast<int64_t>(P.my) * P.ny;  // N_f + N_g
       if (d.evmf) {
-        J->mm_sums_mfma += sums * pts;
-        J->mm_valu += static_cast<int64_t>(P.my) * P.ny * pts;
+        int64_t top = 0;  // terms of x-power 32 (vector ALUs)
+        for (int r : P.f.rdeg) top += (r == 32);
+        for (int r : P.g.rdeg) top += (r == 32);
+        J->mm_sums_mfma += (sums - top) * pts;
+        J->mm_valu += (static_cast<int64_t>(P.my) * P.ny + top) * pts;
         // 25 int8 16x16x32 products per 16-point tile and 16-row tile
         const int64_t tiles = static_cast<int64_t>(P.np) * blocks_of(P.E + 1, d.evpb) * (d.evpb / 16);
         J->mfma_macs += tiles * (d.dRTf + d.dRTg) * kDigits * kDigits * 16 * 16 * 32;

@@ -472,7 +472,12 @@ int rsl_server_enqueue(rsl_server* S, uint64_t handle, rsl_result* out, uint64_t
     r = std::move(it->second);
     S->planned.erase(it);
   }
-  return enqueue(S, std::move(r), out, ticket);
+  const int rc = enqueue(S, r, out, ticket);
+  if (rc == RSL_EAGAIN) {  // queue full: the handle stays valid for a later enqueue
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->planned[handle] = std::move(r);
+  }
+  return rc;
 }
 
 int rsl_server_poll(rsl_server* S, uint64_t ticket, int* status) {

@@ -165,7 +165,8 @@ __device__ inline int tile_coord(const DevProblem& P, int t, int* gp, int* i, in
 }
 
 // Digit tiles (evaluation on the matrix cores).  The residue c mod p of the
-// coefficient at x-power i (< 32) and row j of f (gp = 0) or g (gp = 1) is
+// coefficient at x-power i (< 32; x-power 32, the one beyond the products' K
+// range, stays in the residue tile) and row j of f (gp = 0) or g (gp = 1) is
 // kept as five 7-bit digits: digit b lies in operand fragment b RT + j / 16 of
 // its polynomial (RT = its 16-row tiles; g's fragments follow f's), lane
 // (j mod 16) + 16 (i / 8), byte i mod 8 -- the B operand order of
@@ -176,6 +177,7 @@ __host__ __device__ inline int dig_rt(int rows) { return (rows + 15) / 16; }
 constexpr int kDigits = 5;
 __device__ inline void write_digits(uint64_t* dig, int fr, int rtf, int rtg, int slot, int gp, int i, int j,
                                     uint32_t r) {
+  if (i >= 32) return;  // x-power 32: added on the vector ALUs from the residue tile
   const int rt = gp ? rtg : rtf;
   uint8_t* base = reinterpret_cast<uint8_t*>(dig + (static_cast<size_t>(slot) * fr + (gp ? kDigits * rtf : 0)) * 64);
   const size_t at = (static_cast<size_t>(j >> 4) * 64 + (j & 15) + 16 * (i >> 3)) * 8 + (i & 7);
@@ -186,7 +188,8 @@ __device__ inline void write_digits(uint64_t* dig, int fr, int rtf, int rtg, int
 
 // staged = true (the reduction launched as its own kernel): the residue tiles
 // are written only for problems whose staged evaluation reads them (Horner
-// forms); the persistent schedule evaluates by Horner and writes them all.
+// forms; of a matrix-core form only x-power 32, which it adds on the vector
+// ALUs); the persistent schedule evaluates by Horner and writes them all.
 __device__ inline void stage_reduce(const DevProblem& P, const DevTables& T, const WorkItem& w,
                                     bool zero_status = false, bool staged = false) {
   if (zero_status && w.slot == 0 && w.blk == 0)
@@ -202,11 +205,12 @@ __device__ inline void stage_reduce(const DevProblem& P, const DevTables& T, con
     const uint32_t p = pc.p;
     const uint32_t r = limbs_mod_p(P.coeff + static_cast<size_t>(in) * P.L_in, P.L_in, pc);
     v = mmul(r, pc.r3, p, pc.pinv);
-    if (w.slot < P.pshared && partner_tile) P.presid[static_cast<size_t>(w.slot) * P.pCS + partner_pos(P, t)] = v;
+    if (w.slot < P.pshared && (partner_tile || cj == 32))
+      P.presid[static_cast<size_t>(w.slot) * P.pCS + partner_pos(P, t)] = v;
     if (P.dig) write_digits(P.dig, P.dfr, P.dRTf, P.dRTg, w.slot, gp, ci, cj, r);
     if (P.pdig && w.slot < P.pshared) write_digits(P.pdig, P.pdfr, P.pdRTf, P.pdRTg, w.slot, gp, cj, ci, r);
   }
-  if (own_tile) P.resid[static_cast<size_t>(w.slot) * P.CS + t] = v;
+  if (own_tile || ci == 32) P.resid[static_cast<size_t>(w.slot) * P.CS + t] = v;
 }
 
 // Multi-limb inputs: a block takes 64 transposed positions and 32 prime slots
@@ -291,8 +295,8 @@ __device__ inline void stage_reduce_ml(const DevProblem& P, const DevTables& T, 
     const int sl = w.slot + q + 4 * r;
     if (sl < P.np) {
       const uint32_t v = (in >= 0) ? mmul(acc[r], r3[r], p[r], pinv[r]) : 0u;
-      if (own_tile) P.resid[static_cast<size_t>(sl) * P.CS + t] = v;
-      if (in >= 0 && sl < P.pshared && partner_tile) P.presid[static_cast<size_t>(sl) * P.pCS + tp] = v;
+      if (own_tile || ci == 32) P.resid[static_cast<size_t>(sl) * P.CS + t] = v;
+      if (in >= 0 && sl < P.pshared && (partner_tile || cj == 32)) P.presid[static_cast<size_t>(sl) * P.pCS + tp] = v;
       if (in >= 0 && P.dig) write_digits(P.dig, P.dfr, P.dRTf, P.dRTg, sl, gp, ci, cj, acc[r]);
       if (in >= 0 && P.pdig && sl < P.pshared)
         write_digits(P.pdig, P.pdfr, P.pdRTf, P.pdRTg, sl, gp, cj, ci, acc[r]);
@@ -838,6 +842,34 @@ __device__ inline void stage_eval_ures_mfma(const DevProblem& P, const DevTables
     }
   }
   WaveSync()();
+  // x-degree 32: the products cover x-powers 0..31; f_j(x) R += c_{32,j} x^32 R
+  // on the vector ALUs, from the residue tile (c R^2) and x^32 in normal form
+  if (P.rowf > 32 || P.rowg > 32) {
+    const int ptq = w.blk * PTS + (lane < PTS ? lane : 0);
+    const uint32_t xq = static_cast<uint32_t>(P.origin + (ptq < P.E ? ptq : P.E));
+    uint32_t x32 = mmul(xq, pc.r2, p, pinv);
+#pragma unroll
+    for (int s = 0; s < 5; ++s) x32 = mmul(x32, x32, p, pinv);
+    x32 = redc(x32, p, pinv);  // x^32 of local point `lane`, normal form
+    const uint32_t* rs = P.resid + static_cast<size_t>(w.slot) * P.CS;
+    for (int gp = 0; gp < 2; ++gp) {
+      if ((gp ? P.rowg : P.rowf) <= 32) continue;
+      const int rows = gp ? P.ny + 1 : P.my + 1;
+      const uint32_t* top = rs + (gp ? P.goff + 32 * P.nyp : 32 * P.myp);
+      const int n = PTS * rows;
+      for (int t0 = 0; t0 < n; t0 += 64) {  // every lane takes part in each shuffle
+        const int t = t0 + lane;
+        const int q = (t < n) ? t / rows : 0;
+        const uint32_t xv = static_cast<uint32_t>(__shfl(static_cast<int>(x32), q, 64));
+        if (t < n) {
+          const int j = t - q * rows;
+          uint32_t* v = Fv[gp] + q * SR + j;
+          *v = maddm(*v, mmul(top[j], xv, p, pinv), p);
+        }
+      }
+    }
+    WaveSync()();
+  }
 
   bool ok, bad;
   uint32_t r;

@@ -26,24 +26,31 @@ class Server:
         self.h = h
         self._outs = {}
 
-    def submit(self, f, g, var="y"):
+    def plan(self, f, g, var="y"):
+        """Plan a request without queueing it: (handle, result buffer) for enqueue()."""
         pf, pg = _as_poly(f), _as_poly(g)
-        v = _var_code(var)
         # planned once in the library: the plan sizes the result buffer and the
         # scheduler lays the request's batch out from the same plan
         info = rsl_info()
         handle = ctypes.c_uint64()
-        rc = _lib.rsl_server_plan(self.h, ctypes.byref(pf.c), ctypes.byref(pg.c), v, ctypes.byref(info),
-                                  ctypes.byref(handle))
+        rc = _lib.rsl_server_plan(self.h, ctypes.byref(pf.c), ctypes.byref(pg.c), _var_code(var),
+                                  ctypes.byref(info), ctypes.byref(handle))
         if rc:
             raise RSLError(rc, "rsl_server_plan: " + self.ctx.last_error())
-        out = _Result(max(info.D, 0), info.out_limbs)
+        return handle.value, _Result(max(info.D, 0), info.out_limbs)
+
+    def enqueue(self, planned):
+        """Queue a planned request; the ticket (RSLError RSL_EAGAIN when the queue is full)."""
+        handle, out = planned
         t = ctypes.c_uint64()
-        rc = _lib.rsl_server_enqueue(self.h, handle.value, ctypes.byref(out.c), ctypes.byref(t))
+        rc = _lib.rsl_server_enqueue(self.h, handle, ctypes.byref(out.c), ctypes.byref(t))
         if rc:
             raise RSLError(rc, "rsl_server_enqueue")
         self._outs[t.value] = out
         return t.value
+
+    def submit(self, f, g, var="y"):
+        return self.enqueue(self.plan(f, g, var))
 
     def try_submit(self, f, g, var="y"):
         """Like submit() but returns None when the server queue is full."""

@@ -111,14 +111,19 @@ def test_small_shapes_match_oracle(ctx, lanes):
 
 @pytest.mark.parametrize("lanes", [1, 2])
 def test_register_bounds_equal_horner(ctx, horner, lanes):
-    """Degrees up to the 32 bound and x-degrees up to the 32-power limit give
-    the same bits as Horner's rule; an x-degree past the limit keeps Horner."""
+    """Degrees up to the 32 bound and x-degrees up to 32 (x-powers 0..31 on the
+    matrix cores, x-power 32 added on the vector ALUs) give the same bits as
+    Horner's rule; an x-degree past 32 keeps Horner."""
     rng = rng_for(731, 0)
     probs = []
     for dy, dyg, dx in [(16, 16, 16), (17, 16, 12), (24, 24, 24), (25, 24, 20), (31, 32, 6), (32, 32, 8),
                         (8, 9, 31), (12, 12, 31)]:
         probs.append((small_random(rng, dy, dx, 16), small_random(rng, dyg, max(dx - 3, 1), 16), "y"))
-    past = (small_random(rng, 9, 32, 16), small_random(rng, 9, 5, 16), "y")  # 33 x-powers: Horner
+    # 33 x-powers in f, in g, in both (the last with y-degrees 32)
+    probs.append((small_random(rng, 9, 32, 16), small_random(rng, 9, 5, 16), "y"))
+    probs.append((small_random(rng, 12, 7, 16), small_random(rng, 11, 32, 16), "y"))
+    probs.append((small_random(rng, 32, 32, 12), small_random(rng, 31, 32, 12), "y"))
+    past = (small_random(rng, 9, 33, 16), small_random(rng, 9, 5, 16), "y")  # 34 x-powers: Horner
     probs.append(past)
     got, info = run(ctx, probs, lanes=lanes)
     assert info["eval_mfma"] == len(probs) - 1
@@ -144,6 +149,14 @@ def test_multi_limb_joint_projections(ctx, horner, lanes):
     assert info["eval_mfma"] == 2
     assert got == run(horner, big, lanes=3 - lanes)[0]
     modq(big, got, 732)
+    # total degree 32: x-power 32 in both projections, the y problem writing the
+    # x problem's x-power-32 residues (its row 32) with its digit tiles
+    f32, g32 = dense_total(rng, 32, 8), dense_total(rng, 31, 8)
+    pair = [(f32, g32, "y"), (f32, g32, "x")]
+    got, info = run(ctx, pair, lanes=lanes)
+    assert info["eval_mfma"] == 2
+    assert got == run(horner, pair, lanes=3 - lanes)[0]
+    modq(pair, got, 733)
 
 
 def test_repeated_runs_and_relayout(ctx):

@@ -90,13 +90,16 @@ def test_admission_limits(rsl):
     with pytest.raises(rsl.RSLError) as ei:
         srv.submit(big, big, "y")  # footprint above the whole budget
     assert ei.value.code == rsl.RSL_ENOMEM
+    # planned first, then queued back to back: the queue (3) fills faster than
+    # the device serves the requests
+    planned = [srv.plan(*small) for _ in range(40)]
     tickets, refused = [], 0
-    for _ in range(40):
-        t = srv.try_submit(*small)
-        if t is None:
+    for pl in planned:
+        try:
+            tickets.append(srv.enqueue(pl))
+        except rsl.RSLError as e:
+            assert e.code == rsl.RSL_EAGAIN
             refused += 1
-        else:
-            tickets.append(t)
     outs = [srv.wait(t) for t in tickets]
     assert refused > 0 and all(o == outs[0] for o in outs)
     st = srv.stats()
