@@ -309,7 +309,11 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
         // in y); item slot 0 of block 0 also clears the statuses, so a problem
         // whose slots are all shared keeps one such item
         const int s0 = J->skip_reduce[li];
-        if (d.L_in > 2) {  // long limb chains: staged limbs, eight primes per thread
+        if (d.evmf && d.L_in <= 2 && J->partner[li] < 0 && s0 == 0) {  // digit planes a word at a time
+          const int nb = blocks_of(reduce_words(d.my, d.ny, d.rowf, d.rowg), 256);
+          for (int sl = 0; sl < P.np; ++sl)
+            for (int b = 0; b < nb; ++b) put(sl, b, 2);
+        } else if (d.L_in > 2) {  // long limb chains: staged limbs, eight primes per thread
           const int first = (s0 / kReduceMlSlots) * kReduceMlSlots;
           for (int sl = first; sl < P.np; sl += kReduceMlSlots)
             for (int b = 0; b < blocks_of(d.CS, kReduceMlCoeffs); ++b) put(sl, b, 1);

@@ -32,7 +32,9 @@ static_assert(kCrtWaves == kCrtBlockCoeffs, "one coefficient per wave of a CRT b
 __global__ __launch_bounds__(256) void k_reduce(const DevProblem* probs, const WorkItem* items, DevTables T) {
   extern __shared__ uint32_t lds[];
   const WorkItem w = items[blockIdx.x];
-  if (w.sub)
+  if (w.sub == 2)
+    stage_reduce_words(probs[w.prob], T, w);
+  else if (w.sub)
     stage_reduce_ml(probs[w.prob], T, w, lds, true);
   else
     stage_reduce(probs[w.prob], T, w, true, true);

@@ -213,6 +213,53 @@ __device__ inline void stage_reduce(const DevProblem& P, const DevTables& T, con
   if (own_tile || ci == 32) P.resid[static_cast<size_t>(w.slot) * P.CS + t] = v;
 }
 
+// Problems whose evaluation takes its sums from the matrix cores and that
+// share no reduction with a partner (inputs of at most two limbs): one thread
+// per (row, 8 consecutive x-powers) of a prime slot, which writes each of the
+// five digit planes' 8 bytes of that row and K slice as one word (eight
+// separate byte stores per plane otherwise); x-power 32, beyond the products'
+// K range, goes to the residue tile.  Consecutive threads take consecutive
+// rows.  Item (slot, block of 256 words, sub = 2).
+__host__ __device__ inline int reduce_words(int my, int ny, int rowf, int rowg) {
+  return (my + 1) * ((rowf + 7) / 8) + (ny + 1) * ((rowg + 7) / 8);
+}
+__device__ inline void stage_reduce_words(const DevProblem& P, const DevTables& T, const WorkItem& w) {
+  if (w.slot == 0 && w.blk == 0)
+    for (int i = threadIdx.x; i < 2 * P.np + 2; i += blockDim.x) P.status[i] = 0;
+  const int t = w.blk * blockDim.x + threadIdx.x;
+  const int nwf = (P.my + 1) * ((P.rowf + 7) / 8);
+  if (t >= reduce_words(P.my, P.ny, P.rowf, P.rowg)) return;
+  const int gp = t >= nwf ? 1 : 0;
+  const int u = gp ? t - nwf : t;
+  const int rows = gp ? P.ny + 1 : P.my + 1;
+  const int k = u / rows, j = u - k * rows;
+  const int len = gp ? P.rowg : P.rowf;
+  const uint32_t* src =
+      P.coeff + (static_cast<size_t>(gp ? (P.my + 1) * P.rowf : 0) + static_cast<size_t>(j) * len) * P.L_in;
+  const PrimeConst pc = T.pc[P.pidx[w.slot]];
+  uint32_t r[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int i = 8 * k + e;
+    r[e] = (i < len) ? limbs_mod_p(src + static_cast<size_t>(i) * P.L_in, P.L_in, pc) : 0u;
+  }
+  if (k < 4) {
+    const int rt = gp ? P.dRTg : P.dRTf;
+    uint64_t* base = P.dig + (static_cast<size_t>(w.slot) * P.dfr + (gp ? kDigits * P.dRTf : 0)) * 64 +
+                     static_cast<size_t>(j >> 4) * 64 + (j & 15) + 16 * k;
+#pragma unroll
+    for (int b = 0; b < kDigits; ++b) {
+      uint64_t word = 0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) word |= static_cast<uint64_t>((r[e] >> (7 * b)) & 127u) << (8 * e);
+      base[static_cast<size_t>(b) * rt * 64] = word;
+    }
+  } else {  // x-power 32 (rowf or rowg = 33): the residue tile, c R^2 mod p
+    const int at = (gp ? P.goff + 32 * P.nyp : 32 * P.myp) + j;
+    P.resid[static_cast<size_t>(w.slot) * P.CS + at] = mmul(r[0], pc.r3, pc.p, pc.pinv);
+  }
+}
+
 // Multi-limb inputs: a block takes 64 transposed positions and 32 prime slots
 // (item: slot = first slot, blk = position block, sub = 1).  The 64
 // coefficients' limbs are staged in LDS 64 limbs at a time (coalesced reads of
