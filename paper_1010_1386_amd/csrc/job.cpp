@@ -349,7 +349,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
         break;
       case kStageCrt:
         if (!P.wide)
-          for (int b = 0; b < blocks_of(P.D + 1, kCrtWaves); ++b) put(-1, b, 0);
+          for (int b = 0; b < blocks_of(P.D + 1, kCrtWaves * kCrtBatches); ++b) put(-1, b, 0);
         break;
       case kHsegList:
         for (int sl = 0; sl < P.np; ++sl)

@@ -144,7 +144,7 @@ template <int NS>
 __global__ __launch_bounds__(512) void k_crt(const DevProblem* probs, const WorkItem* items, DevTables T) {
   extern __shared__ uint32_t lds[];
   const WorkItem w = items[blockIdx.x];
-  stage_crt<NS>(probs[w.prob], T, w, lds, kCrtBlockCoeffs / static_cast<int>(blockDim.x >> 6));
+  stage_crt<NS>(probs[w.prob], T, w, lds, kCrtBlockCoeffs / static_cast<int>(blockDim.x >> 6), kCrtBatches);
 }
 
 __global__ __launch_bounds__(256) void k_crt_wide_t(const DevProblem* probs, const WorkItem* items, DevTables T) {

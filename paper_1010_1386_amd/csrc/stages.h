@@ -2110,14 +2110,16 @@ __device__ inline void crt_one(const DevProblem& P, int k_raw, const uint32_t* m
 }
 
 // One block: the per-prime constants and (when it fits) the M / p_j limb
-// table staged in LDS once, then `cpw` coefficients per wave,
-// k = (blk * waves + wave) * cpw + c (waves * cpw = kCrtBlockCoeffs).  The
-// residues u_i of the block's coefficients are summed from the basis-change
-// partial sums first, with the block's threads reading kCrtBlockCoeffs
-// consecutive coefficients of one prime together.
+// table staged in LDS once, then `batches` runs of kCrtBlockCoeffs
+// coefficients, `cpw` per wave: k = ((blk * batches + b) * waves + wave) * cpw
+// + c (waves * cpw = kCrtBlockCoeffs).  The residues u_i of a batch's
+// coefficients are summed from the basis-change partial sums first, with the
+// block's threads reading kCrtBlockCoeffs consecutive coefficients of one
+// prime together.  More batches per block stage the limb table fewer times.
+constexpr int kCrtBatches = 4;  // batches per block of the staged and plain launches
 template <int NS>
 __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds,
-                                 int cpw = 1) {
+                                 int cpw = 1, int batches = 1) {
   const int nw = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6;
   const int np = P.np;
@@ -2128,45 +2130,49 @@ __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const 
   uint32_t* wb = wbase + wave * crt_wave_words(NS);
   uint32_t* ures = wbase + nw * crt_wave_words(NS);  // [kCrtBlockCoeffs][np]
   uint32_t* pconst = ures + kCrtBlockCoeffs * np;     // [kCrtConsts][np]
-  const int kbase = w.blk * kCrtBlockCoeffs;
   const size_t cstride = static_cast<size_t>(np) * (P.D + 1);
   if (staged_mi)
     block_stage(mis, np * L, [&](int t) {
       const int j = t / L, l = t - j * L;
       return P.Mi[static_cast<size_t>(j) * L + l];
     });
-  for (int t = threadIdx.x; t < np * kCrtBlockCoeffs; t += blockDim.x) {
-    const int i = t / kCrtBlockCoeffs, c = t - i * kCrtBlockCoeffs;
-    const int k = (kbase + c <= P.D) ? kbase + c : P.D;
-    const uint64_t* cpp = P.cpart + static_cast<size_t>(i) * (P.D + 1) + k;
-    const int ch0 = k / P.kchunk;
-    uint64_t q[8];
+  for (int bt = 0; bt < batches; ++bt) {
+    const int kbase = (w.blk * batches + bt) * kCrtBlockCoeffs;
+    if (kbase > P.D) break;  // block-uniform
+    if (bt > 0) __syncthreads();  // the previous batch is done with ures
+    for (int t = threadIdx.x; t < np * kCrtBlockCoeffs; t += blockDim.x) {
+      const int i = t / kCrtBlockCoeffs, c = t - i * kCrtBlockCoeffs;
+      const int k = (kbase + c <= P.D) ? kbase + c : P.D;
+      const uint64_t* cpp = P.cpart + static_cast<size_t>(i) * (P.D + 1) + k;
+      const int ch0 = k / P.kchunk;
+      uint64_t q[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int ch = ch0 + u < P.nchunk ? ch0 + u : P.nchunk - 1;
-      q[u] = cpp[ch * cstride];
-    }
-    const PrimeConst pc = T.pc[P.pidx[i]];
-    const uint32_t hm = P.Hm[i];
-    uint64_t cs = 0;
+      for (int u = 0; u < 8; ++u) {
+        const int ch = ch0 + u < P.nchunk ? ch0 + u : P.nchunk - 1;
+        q[u] = cpp[ch * cstride];
+      }
+      const PrimeConst pc = T.pc[P.pidx[i]];
+      const uint32_t hm = P.Hm[i];
+      uint64_t cs = 0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (ch0 + u < P.nchunk) cs = add_fold(cs, q[u], pc.p);
-    for (int ch = ch0 + 8; ch < P.nchunk; ++ch) cs = add_fold(cs, cpp[ch * cstride], pc.p);
-    ures[c * np + i] = maddm(redc(cs, pc.p, pc.pinv), hm, pc.p);
-    if (c == 0) {
-      pconst[i] = pc.p;
-      pconst[np + i] = pc.pinv;
-      pconst[2 * np + i] = P.invM[i];
-      pconst[3 * np + i] = P.wdir[i];
-      pconst[4 * np + i] = P.rinv[2 * i];
-      pconst[5 * np + i] = P.rinv[2 * i + 1];
+      for (int u = 0; u < 8; ++u)
+        if (ch0 + u < P.nchunk) cs = add_fold(cs, q[u], pc.p);
+      for (int ch = ch0 + 8; ch < P.nchunk; ++ch) cs = add_fold(cs, cpp[ch * cstride], pc.p);
+      ures[c * np + i] = maddm(redc(cs, pc.p, pc.pinv), hm, pc.p);
+      if (c == 0 && bt == 0) {
+        pconst[i] = pc.p;
+        pconst[np + i] = pc.pinv;
+        pconst[2 * np + i] = P.invM[i];
+        pconst[3 * np + i] = P.wdir[i];
+        pconst[4 * np + i] = P.rinv[2 * i];
+        pconst[5 * np + i] = P.rinv[2 * i + 1];
+      }
     }
-  }
-  __syncthreads();
-  for (int c = 0; c < cpw; ++c) {
-    const int local = wave * cpw + c;
-    crt_one<NS>(P, kbase + local, staged_mi ? mis : P.Mi, L, wb, ures + local * np, pconst);
+    __syncthreads();
+    for (int c = 0; c < cpw; ++c) {
+      const int local = wave * cpw + c;
+      crt_one<NS>(P, kbase + local, staged_mi ? mis : P.Mi, L, wb, ures + local * np, pconst);
+    }
   }
 }
 
