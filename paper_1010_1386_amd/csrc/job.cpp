@@ -349,7 +349,7 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
         break;
       case kStageCrt:
         if (!P.wide)
-          for (int b = 0; b < blocks_of(P.D + 1, kCrtWaves * kCrtBatches); ++b) put(-1, b, 0);
+          for (int b = 0; b < blocks_of(P.D + 1, kCrtWaves); ++b) put(-1, b, 0);
         break;
       case kHsegList:
         for (int sl = 0; sl < P.np; ++sl)
@@ -1174,7 +1174,7 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
       continue;
     }
     if ((rc = hip_check(ctx, launch_stage(s, probs, items(s), static_cast<int>(J->items[s].size()),
-                                          J->stage_lds[s], J->crt_ns, T, st), "launch")))
+                                          J->stage_lds[s], J->crt_ns, T, st, kCrtItemsPerBlock), "launch")))
       return rc;
     if (s == kStageCrt)
       for (int pass = 0; pass < 3; ++pass)

@@ -8,9 +8,10 @@ namespace rsl {
 
 // One launch of stage `stage` (see stages.h) over `nitems` work items, one
 // block per item.  lds: dynamic LDS bytes; crt_ns: prime slots per lane of the
-// CRT kernel (ceil(max primes / 64)).
+// CRT kernel (ceil(max primes / 64)); crt_per_block: CRT items per block
+// (consecutive items of one problem share the staged constants).
 hipError_t launch_stage(int stage, const DevProblem* probs, const WorkItem* items, int nitems, size_t lds,
-                        int crt_ns, const DevTables& T, hipStream_t st);
+                        int crt_ns, const DevTables& T, hipStream_t st, int crt_per_block = 1);
 
 // Evaluation + univariate resultants of items that all have layout `variant`.
 hipError_t launch_eval(int variant, const DevProblem* probs, const WorkItem* items, int nitems, size_t lds,

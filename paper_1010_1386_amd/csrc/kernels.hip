@@ -141,10 +141,19 @@ __global__ __launch_bounds__(1024) void k_interp_newton(const DevProblem* probs,
 }
 
 template <int NS>
-__global__ __launch_bounds__(512) void k_crt(const DevProblem* probs, const WorkItem* items, DevTables T) {
+__global__ __launch_bounds__(512) void k_crt(const DevProblem* probs, const WorkItem* items, int nitems, int per,
+                                             DevTables T) {
   extern __shared__ uint32_t lds[];
-  const WorkItem w = items[blockIdx.x];
-  stage_crt<NS>(probs[w.prob], T, w, lds, kCrtBlockCoeffs / static_cast<int>(blockDim.x >> 6), kCrtBatches);
+  // items blockIdx.x * per .. + per - 1 (one problem's items are consecutive:
+  // the constants and limb table are staged again only when the problem changes)
+  for (int b = 0; b < per; ++b) {
+    const int idx = blockIdx.x * per + b;
+    if (idx >= nitems) break;  // block-uniform
+    const WorkItem w = items[idx];
+    const bool fresh = b == 0 || items[idx - 1].prob != w.prob;
+    if (b > 0) __syncthreads();  // the previous item's waves are done with the LDS
+    stage_crt<NS>(probs[w.prob], T, w, lds, kCrtBlockCoeffs / static_cast<int>(blockDim.x >> 6), fresh);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_crt_wide_t(const DevProblem* probs, const WorkItem* items, DevTables T) {
@@ -269,9 +278,11 @@ hipError_t launch_stir_group(const DevProblem* probs, const StirGroup* groups, c
 }
 
 hipError_t launch_stage(int stage, const DevProblem* probs, const WorkItem* items, int nitems, size_t lds,
-                        int crt_ns, const DevTables& T, hipStream_t st) {
+                        int crt_ns, const DevTables& T, hipStream_t st, int crt_per_block) {
   if (nitems <= 0) return hipSuccess;
   const dim3 g(nitems);
+  const int per = crt_per_block > 1 ? crt_per_block : 1;
+  const dim3 gc((nitems + per - 1) / per);
   switch (stage) {
     case kStageReduce: hipLaunchKernelGGL(k_reduce, g, dim3(256), lds, st, probs, items, T); break;
     case kStageEval: return hipErrorInvalidValue;  // launch_eval: one kernel per layout
@@ -280,12 +291,16 @@ hipError_t launch_stage(int stage, const DevProblem* probs, const WorkItem* item
     case kStageNewton: hipLaunchKernelGGL(k_interp_newton, g, dim3(1024), lds, st, probs, items, T); break;
     case kStageCrt:
       switch (crt_ns) {
-        case 1: hipLaunchKernelGGL(k_crt<1>, g, dim3(kCrtWaves * 64), lds, st, probs, items, T); break;
-        case 2: hipLaunchKernelGGL(k_crt<2>, g, dim3(kCrtWaves * 64), lds, st, probs, items, T); break;
-        case 3: hipLaunchKernelGGL(k_crt<3>, g, dim3(kCrtWaves * 64), lds, st, probs, items, T); break;
-        case 4: hipLaunchKernelGGL(k_crt<4>, g, dim3(kCrtWaves * 64), lds, st, probs, items, T); break;
-        case 6: hipLaunchKernelGGL(k_crt<6>, g, dim3(crt_block_waves(6) * 64), lds, st, probs, items, T); break;
-        case 8: hipLaunchKernelGGL(k_crt<8>, g, dim3(crt_block_waves(8) * 64), lds, st, probs, items, T); break;
+        case 1: hipLaunchKernelGGL(k_crt<1>, gc, dim3(kCrtWaves * 64), lds, st, probs, items, nitems, per, T); break;
+        case 2: hipLaunchKernelGGL(k_crt<2>, gc, dim3(kCrtWaves * 64), lds, st, probs, items, nitems, per, T); break;
+        case 3: hipLaunchKernelGGL(k_crt<3>, gc, dim3(kCrtWaves * 64), lds, st, probs, items, nitems, per, T); break;
+        case 4: hipLaunchKernelGGL(k_crt<4>, gc, dim3(kCrtWaves * 64), lds, st, probs, items, nitems, per, T); break;
+        case 6:
+          hipLaunchKernelGGL(k_crt<6>, gc, dim3(crt_block_waves(6) * 64), lds, st, probs, items, nitems, per, T);
+          break;
+        case 8:
+          hipLaunchKernelGGL(k_crt<8>, gc, dim3(crt_block_waves(8) * 64), lds, st, probs, items, nitems, per, T);
+          break;
         default: return hipErrorInvalidValue;
       }
       break;

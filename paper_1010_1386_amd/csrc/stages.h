@@ -2109,17 +2109,18 @@ __device__ inline void crt_one(const DevProblem& P, int k_raw, const uint32_t* m
   crt_radix<NS>(P, k, valid, vbuf, P.Plimb, P.LP, init, sb, sc);
 }
 
-// One block: the per-prime constants and (when it fits) the M / p_j limb
-// table staged in LDS once, then `batches` runs of kCrtBlockCoeffs
-// coefficients, `cpw` per wave: k = ((blk * batches + b) * waves + wave) * cpw
-// + c (waves * cpw = kCrtBlockCoeffs).  The residues u_i of a batch's
-// coefficients are summed from the basis-change partial sums first, with the
+// One item: kCrtBlockCoeffs coefficients, `cpw` per wave,
+// k = (blk * waves + wave) * cpw + c (waves * cpw = kCrtBlockCoeffs).  With
+// `fresh` the per-prime constants and (when it fits) the M / p_j limb table
+// are staged in LDS first; a block that takes several items of one problem
+// in a row (the staged launch) stages them once.  The residues u_i of the
+// item's coefficients are summed from the basis-change partial sums, with the
 // block's threads reading kCrtBlockCoeffs consecutive coefficients of one
-// prime together.  More batches per block stage the limb table fewer times.
-constexpr int kCrtBatches = 4;  // batches per block of the staged and plain launches
+// prime together.
+constexpr int kCrtItemsPerBlock = 4;  // items per block of the staged launch
 template <int NS>
 __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const WorkItem& w, uint32_t* lds,
-                                 int cpw = 1, int batches = 1) {
+                                 int cpw = 1, bool fresh = true) {
   const int nw = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6;
   const int np = P.np;
@@ -2131,15 +2132,13 @@ __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const 
   uint32_t* ures = wbase + nw * crt_wave_words(NS);  // [kCrtBlockCoeffs][np]
   uint32_t* pconst = ures + kCrtBlockCoeffs * np;     // [kCrtConsts][np]
   const size_t cstride = static_cast<size_t>(np) * (P.D + 1);
-  if (staged_mi)
+  const int kbase = w.blk * kCrtBlockCoeffs;
+  if (fresh && staged_mi)
     block_stage(mis, np * L, [&](int t) {
       const int j = t / L, l = t - j * L;
       return P.Mi[static_cast<size_t>(j) * L + l];
     });
-  for (int bt = 0; bt < batches; ++bt) {
-    const int kbase = (w.blk * batches + bt) * kCrtBlockCoeffs;
-    if (kbase > P.D) break;  // block-uniform
-    if (bt > 0) __syncthreads();  // the previous batch is done with ures
+  {
     for (int t = threadIdx.x; t < np * kCrtBlockCoeffs; t += blockDim.x) {
       const int i = t / kCrtBlockCoeffs, c = t - i * kCrtBlockCoeffs;
       const int k = (kbase + c <= P.D) ? kbase + c : P.D;
@@ -2159,7 +2158,7 @@ __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const 
         if (ch0 + u < P.nchunk) cs = add_fold(cs, q[u], pc.p);
       for (int ch = ch0 + 8; ch < P.nchunk; ++ch) cs = add_fold(cs, cpp[ch * cstride], pc.p);
       ures[c * np + i] = maddm(redc(cs, pc.p, pc.pinv), hm, pc.p);
-      if (c == 0 && bt == 0) {
+      if (c == 0 && fresh) {
         pconst[i] = pc.p;
         pconst[np + i] = pc.pinv;
         pconst[2 * np + i] = P.invM[i];
