@@ -1173,8 +1173,9 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
         return rc;
       continue;
     }
-    // CRT: several items per block once there are enough blocks to fill the chip anyway
-    const int crt_per = J->items[kStageCrt].size() >= 4096 ? kCrtItemsPerBlock : 1;
+    // CRT: several items per block once the launch still has a block per CU
+    // or more (the degree-24 pair, 146 items, keeps one per block)
+    const int crt_per = J->items[kStageCrt].size() >= 1024 ? kCrtItemsPerBlock : 1;
     if ((rc = hip_check(ctx, launch_stage(s, probs, items(s), static_cast<int>(J->items[s].size()),
                                           J->stage_lds[s], J->crt_ns, T, st, crt_per), "launch")))
       return rc;
