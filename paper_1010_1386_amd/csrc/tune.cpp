@@ -330,9 +330,21 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
   // coordinate search: schedule x lanes per pair at the default chunking, then
   // the chunking (and the persistent grid) around the best of those
   std::vector<TuneConfig> cands;
+  auto same = [](const TuneConfig& a, const TuneConfig& b) {
+    return a.mode == b.mode && a.chunk_target == b.chunk_target && a.grid_mult == b.grid_mult && a.evk == b.evk &&
+           a.conv_whole == b.conv_whole && a.schur == b.schur && a.interp_mm == b.interp_mm;
+  };
+  auto add = [&](const TuneConfig& c) {
+    for (const TuneConfig& d : cands)
+      if (same(c, d)) return;
+    cands.push_back(c);
+  };
+  // first the layout the job has (a cached choice can need less memory than
+  // the default layouts: it fits the bound memory by construction)
+  add(j->tc);
   for (int evk : {1, 2, 4})
     for (int mode : {RSL_STAGED, RSL_BATCHED})
-      if (mode == RSL_STAGED || j->J.max_np <= kMaxSlots) cands.push_back(TuneConfig{mode, 4096, 1, evk, 0, 0});
+      if (mode == RSL_STAGED || j->J.max_np <= kMaxSlots) add(TuneConfig{mode, 4096, 1, evk, 0, 0});
   // the Schur evaluation (one wave per pair) when every problem's shape allows
   // it and the job is small: its O(r) depth can only pay when the remainder
   // sequence's one or two lanes per pair leave most of the chip idle
@@ -341,7 +353,7 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
     const Plan& P = j->J.plans[k];
     schur_ok = schur_ok && P.my >= 1 && P.ny >= 1 && P.my + P.ny <= kSchurMaxR;
   }
-  if (schur_ok) cands.push_back(TuneConfig{RSL_STAGED, 4096, 1, 1, 0, 1});
+  if (schur_ok) add(TuneConfig{RSL_STAGED, 4096, 1, 1, 0, 1});
   const size_t phase1 = cands.size();
   std::vector<uint8_t> ref;
   TuneConfig win = cands[0];
@@ -351,11 +363,11 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
   for (size_t ci = 0;; ++ci) {
     if (ci == phase1) {  // phase two around the winner of phase one
       if (!any) return fail(ctx, RSL_ENOMEM, "no schedule's layout fits the job's bound device memory");
-      for (int target : {1024, 16384}) cands.push_back(TuneConfig{win.mode, target, 1, win.evk, 0, win.schur});
-      cands.push_back(TuneConfig{win.mode, 4096, 1, win.evk, 1, win.schur});
-      if (win.mode == RSL_BATCHED) cands.push_back(TuneConfig{RSL_BATCHED, 4096, 2, win.evk, 0, 0});
+      for (int target : {1024, 16384}) add(TuneConfig{win.mode, target, 1, win.evk, 0, win.schur});
+      add(TuneConfig{win.mode, 4096, 1, win.evk, 1, win.schur});
+      if (win.mode == RSL_BATCHED) add(TuneConfig{RSL_BATCHED, 4096, 2, win.evk, 0, 0});
       // the interpolation on the matrix cores (staged schedule)
-      if (win.mode == RSL_STAGED) cands.push_back(TuneConfig{RSL_STAGED, 4096, 1, win.evk, 1, win.schur, 1});
+      if (win.mode == RSL_STAGED) add(TuneConfig{RSL_STAGED, 4096, 1, win.evk, 1, win.schur, 1});
     }
     if (ci >= cands.size()) break;
     const TuneConfig tc = cands[ci];

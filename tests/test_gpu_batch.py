@@ -291,3 +291,33 @@ def test_context_close_closes_its_jobs_first():
     for j in jobs:
         j.close()
     del jobs
+
+
+def test_tune_starts_from_the_jobs_own_layout(tmp_path):
+    """A job laid out with a cached choice whose footprint is small (sums taken
+    whole, matrix-core interpolation) and bound to exactly that size: the
+    default layouts do not fit it, the tuner still times the job's own layout
+    (it fits by construction) and the results stay exact."""
+    import paper_1010_1386_amd as rsl
+    rng = rng_for(760, 0)
+    probs = [(dense_total(rng, 16, 40), dense_total(rng, 15, 40), "y") for _ in range(8)]
+    ctx = rsl.Context(device=0, workspace_bytes=256 << 20)
+    job = ctx.job(probs)
+    job.run("staged")
+    want = job.results()
+    job.tune(reps=1)
+    job.close()
+    path = tmp_path / "tune.txt"
+    ctx.tune_save(str(path))
+    key = path.read_text().split()[0]
+    path.write_text(key + " 2 4096 1 1 1 0 1 1.0\n")
+    c2 = rsl.Context(device=0, workspace_bytes=256 << 20)
+    c2.tune_load(str(path))
+    j2 = c2.job(probs, headroom=0.0)
+    t = j2.tune(reps=1)
+    assert t["candidates"] >= 1
+    j2.run("auto")
+    assert j2.results() == want
+    j2.close()
+    c2.close()
+    ctx.close()
