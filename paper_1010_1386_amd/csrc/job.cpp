@@ -456,9 +456,14 @@ int job_build(rsl_ctx* ctx, int n, const rsl_poly* f, const rsl_poly* g, const i
     const std::vector<int>& vstart = J->eval_vstart;
     const int nv = static_cast<int>(vstart.size()) - 1;
     J->eval_ranges.clear();
+    // each variant's launch sized for its own problems (a small register
+    // form keeps more waves per CU than the largest problem's LDS would allow)
+    std::vector<size_t> vlds(static_cast<size_t>(nv), 0);
+    for (int li = 0; li < nl; ++li)
+      vlds[J->tmp_c[li]] = std::max(vlds[J->tmp_c[li]], static_cast<size_t>(eval_stage_lds_words(J->dev[li])) * 4);
     for (int v = 0; v < nv; ++v)
       if (vstart[v] < vstart[v + 1])
-        J->eval_ranges.push_back({v, static_cast<int>(vstart[v]), static_cast<int>(vstart[v + 1])});
+        J->eval_ranges.push_back({v, static_cast<int>(vstart[v]), static_cast<int>(vstart[v + 1]), vlds[v]});
     // the staged launches take the same items dealt so that all blocks of one
     // (problem, prime) run on the same XCD: workgroup i of a launch goes to
     // XCD i mod 8, so the prime's coefficient tile is fetched into one L2
@@ -1080,7 +1085,8 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
                             "launch")))
           return rc;
         const hipError_t e = (s == kStageEval)
-            ? launch_eval(eval_variant(J->dev[li]), probs, items(s) + L.item_begin[s], cnt, J->stage_lds[s], T, st)
+            ? launch_eval(eval_variant(J->dev[li]), probs, items(s) + L.item_begin[s], cnt,
+                          static_cast<size_t>(eval_stage_lds_words(J->dev[li])) * 4, T, st)
             : launch_stage(s, probs, items(s) + L.item_begin[s], cnt, J->stage_lds[s], ns, T, st);
         if ((rc = hip_check(ctx, e, "launch"))) return rc;
       }
@@ -1138,7 +1144,7 @@ int job_launch(rsl_ctx* ctx, Job* J, int mode, hipStream_t st, bool stage_events
     if (s == kStageEval) {
       const WorkItem* evs = reinterpret_cast<const WorkItem*>(J->base + J->evs_off);
       for (const Job::EvalRange& r : J->eval_ranges)
-        if ((rc = hip_check(ctx, launch_eval(r.variant, probs, evs + r.begin, r.end - r.begin, J->stage_lds[s], T, st),
+        if ((rc = hip_check(ctx, launch_eval(r.variant, probs, evs + r.begin, r.end - r.begin, r.lds, T, st),
                             "launch")))
           return rc;
       continue;

@@ -43,6 +43,7 @@ struct Job {
   // evaluation items are ordered by layout: one launch per (variant, range)
   struct EvalRange {
     int variant, begin, end;
+    size_t lds;  // dynamic LDS bytes of its launch: the most any of its problems needs
   };
   std::vector<EvalRange> eval_ranges;  // ranges of eval_staged
   std::vector<int> eval_vstart;        // first evaluation item of each layout variant (and the end)
