@@ -339,9 +339,11 @@ int rsl_job_tune(rsl_ctx* ctx, rsl_job* j, int reps, rsl_tune_result* best) {
       if (same(c, d)) return;
     cands.push_back(c);
   };
-  // first the layout the job has (a cached choice can need less memory than
-  // the default layouts: it fits the bound memory by construction)
-  add(j->tc);
+  // first the layout the job has when it came from a cached choice (it can
+  // need less memory than the default layouts, and it fits the bound memory
+  // by construction); a job laid out with the defaults starts from the
+  // explicit lane counts below
+  if (!same(j->tc, TuneConfig{})) add(j->tc);
   for (int evk : {1, 2, 4})
     for (int mode : {RSL_STAGED, RSL_BATCHED})
       if (mode == RSL_STAGED || j->J.max_np <= kMaxSlots) add(TuneConfig{mode, 4096, 1, evk, 0, 0});
