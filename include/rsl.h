@@ -339,7 +339,8 @@ typedef struct {
   int32_t grid_mult;      /* persistent grid multiplier */
   int32_t eval_lanes;     /* most lanes per (prime, point) pair used by any problem */
   int32_t eval_mfma;      /* problems whose evaluation sums run on the matrix cores (register form,
-                             two lanes per pair, x-degrees below 32) */
+                             one lane or a lane pair per pair, x-degrees up to 32: x-powers
+                             0..31 on the matrix cores, x-power 32 on the vector ALUs) */
   int64_t mulmods_sums_mfma;  /* of mulmods: evaluation sums taken on the matrix cores */
   int64_t mulmods_valu;       /* of mulmods: the rest (remainder sequences, Horner sums) on the vector ALUs */
   int64_t mfma_int8_macs;     /* int8 multiply-adds the matrix cores issue per run for those sums
