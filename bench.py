@@ -429,6 +429,24 @@ def pair_bench(a):
                 sys.exit(1)
             alt_jobs.append(j)
         inflight_sets.append((alt, alt_jobs))
+    # the autotuner times one launch at a time; when it kept a layout other than
+    # the default interpolation form (whole convolution sums, matrix-core
+    # products, other chunking), the default layout is timed in flight too, on
+    # contexts of its own (no cached choice), in each lane layout
+    dctx = []
+    if extra and mode == "staged" and not a.eval_schur and any(
+            tune.get(k, d) != d for k, d in (("conv_whole", 0), ("interp_mm", 0), ("chunk_target", 4096))):
+        dctx = [rsl.Context(0, workspace_bytes=256 << 20) for _ in all_jobs]
+        for lanes in sorted({s[0] for s in inflight_sets}):
+            djobs = []
+            for c in dctx:
+                j = c.job(problems, eval_lanes=lanes)
+                j.run(mode)
+                if j.results() != res:
+                    print("bench: a resident job of the default layout differs from the first", file=sys.stderr)
+                    sys.exit(1)
+                djobs.append(j)
+            inflight_sets.append((f"{lanes}, default interpolation layout", djobs))
 
     def timed(mode, steps, warmup, graph=False):
         for _ in range(warmup):
@@ -475,6 +493,7 @@ def pair_bench(a):
         return time.perf_counter() - t0
 
     inflight_lanes = None
+    inflight_ms = {}
     if extra:
         best = None
         for lanes, jobs in inflight_sets:
@@ -485,6 +504,7 @@ def pair_bench(a):
                     sys.exit(1)
             for graph in (True, False):
                 t = timed_inflight(jobs, a.pair_steps, a.pair_warmup, graph)
+                inflight_ms[f"lanes {lanes}, {'graph' if graph else 'eager'}"] = t / a.pair_steps * 1e3
                 if best is None or t < best[0]:
                     best = (t, graph, lanes)
         dt, use_graph, inflight_lanes = best
@@ -624,6 +644,7 @@ def pair_bench(a):
         "serial_batched_vs_plain": serial_value / plain_value,
         "host_to_host_resultants_per_s": h2h,
         "schedule_ms_per_step": schedules,
+        "in_flight_ms_per_step": inflight_ms,
         "tune": tune,
         "stage_ms_per_step": staged_split,
         "dominant_stage": dominant,
@@ -634,6 +655,8 @@ def pair_bench(a):
             j.close()
     for c, j in extra:
         j.close()
+        c.close()
+    for c in dctx:
         c.close()
     job.close()
     ctx.close()
@@ -937,7 +960,7 @@ def batch_headline(a):
         pa.no_cpu_baseline = True
         pr = pair_bench(pa)
         out["pair"] = {k: pr[k] for k in ("value", "ms_per_step", "serial_value", "plain_value", "config",
-                                          "verified_bit_exact", "roofline")}
+                                          "tune", "in_flight_ms_per_step", "verified_bit_exact", "roofline")}
         out["pair"]["unit"] = "bivariate resultants/s, device only (inputs resident), steps in flight"
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(probs)

@@ -397,13 +397,15 @@ int rsl_tune_load(rsl_ctx *ctx, const char *path);
 
 /* --------------------------------------------------------------- profiling */
 /* Stages: 0 reduce, 1 eval+ures, 2 interp (convolution), 3 interp (basis
- * change), 4 interp (gapped points), 5 CRT. */
+ * change), 4 interp (gapped points, shifted origin), 5 CRT. */
 #define RSL_NUM_STAGES 6
 /* While enabled, every batched launch records HIP events on the context
  * stream at each stage boundary. */
 int rsl_profile_enable(rsl_ctx *ctx, int on);
 /* Synchronise, add up the stage durations of all launches recorded since the
- * last call into stage_ms[RSL_NUM_STAGES], and reset. */
+ * last call into stage_ms[RSL_NUM_STAGES], and reset.  A stage that launched
+ * no kernel for a job reads 0; the time of its boundary markers is counted in
+ * the stage before it.  A persistent launch is reported as stage 0. */
 int rsl_profile_take(rsl_ctx *ctx, double *stage_ms, int *runs);
 
 /* ---------------------------------------------------------------- serving */

@@ -752,9 +752,16 @@ int rsl_profile_take(rsl_ctx* ctx, double* stage_ms, int* runs) {
   for (int s = 0; s < kNumStages; ++s) stage_ms[s] = 0.0;
   for (int r = 0; r < ctx->evused; ++r) {
     const std::vector<hipEvent_t>& ev = ctx->evsets[r];
+    // the events as the run recorded them: an empty stage's end boundary is
+    // its start event, recorded again where the next stage began, so the
+    // stage itself reads zero and the marker time goes to the stage before
+    const unsigned empty = ctx->evempty[r];
+    hipEvent_t at[kNumStages + 1];
+    for (int s = 0; s <= kNumStages; ++s) at[s] = (s > 0 && (empty >> (s - 1) & 1u)) ? at[s - 1] : ev[s];
     for (int s = 0; s < kNumStages; ++s) {
+      if (empty >> s & 1u) continue;
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ev[s], ev[s + 1]) == hipSuccess) stage_ms[s] += ms;
+      if (hipEventElapsedTime(&ms, at[s], at[s + 1]) == hipSuccess) stage_ms[s] += ms;
     }
   }
   if (runs) *runs = ctx->evused;

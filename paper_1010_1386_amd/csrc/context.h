@@ -91,6 +91,7 @@ struct rsl_ctx {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipEvent_t ev[rsl::kNumStages + 1] = {};   // stage boundaries of the last batched launch
   std::vector<std::vector<hipEvent_t>> evsets; // per-run stage events while profiling
+  std::vector<unsigned> evempty;               // per set: bit s = stage s launched nothing in that run
   int evused = 0;
   bool profiling = false;
   int table_gen = 0;                          // bumped whenever the constant tables move

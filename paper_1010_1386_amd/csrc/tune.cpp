@@ -138,8 +138,28 @@ static hipEvent_t* next_evset(rsl_ctx* ctx) {
     for (auto& e : set)
       if (hipEventCreate(&e) != hipSuccess) return nullptr;
     ctx->evsets.push_back(set);
+    ctx->evempty.push_back(0u);
   }
   return ctx->evsets[ctx->evused++].data();
+}
+
+// Stages of the staged schedule that launch no kernel for this job.  Their
+// boundary events would only time the event markers themselves, so the
+// profiler folds them into the stage before (see rsl_profile_take).
+static unsigned empty_stages(const Job& J) {
+  unsigned m = 0u;
+  if (J.items[kStageReduce].empty()) m |= 1u << kStageReduce;
+  if (J.eval_ranges.empty()) m |= 1u << kStageEval;
+  if (J.mm_interp) {
+    if (J.dig_items.empty() && J.mm_items.empty()) m |= (1u << kStageConv) | (1u << kStageStir);
+  } else {
+    if (J.items[kStageConv].empty()) m |= 1u << kStageConv;
+    if (J.items[kStageStir].empty() && J.sg_items.empty() && J.hseg_items.empty()) m |= 1u << kStageStir;
+  }
+  if (J.items[kStageNewton].empty()) m |= 1u << kStageNewton;
+  if (J.items[kStageCrt].empty() && J.wide_items[0].empty() && J.wide_items[1].empty() && J.wide_items[2].empty())
+    m |= 1u << kStageCrt;
+  return m;
 }
 
 // Capture reset + launches of `mode` into a graph on the context stream.
@@ -179,7 +199,13 @@ static int run_job(rsl_ctx* ctx, rsl_job* j, int mode) {
   if (ctx->profiling && mode != RSL_PLAIN) {
     hipEvent_t* ev = next_evset(ctx);
     if (!ev) return fail(ctx, RSL_EDEVICE, "hipEventCreate");
-    for (int s = 0; s <= kNumStages; ++s) ctx->ev[s] = ev[s];
+    // an empty stage's end boundary reuses its start event, which is then
+    // recorded again where the next stage begins (one persistent launch
+    // records every boundary after its kernel: nothing to fold)
+    const unsigned empty = mode == RSL_STAGED ? empty_stages(j->J) : 0u;
+    ctx->evempty[ctx->evused - 1] = empty;
+    for (int s = 0; s <= kNumStages; ++s)
+      ctx->ev[s] = (s > 0 && (empty >> (s - 1) & 1u)) ? ctx->ev[s - 1] : ev[s];
     return job_launch(ctx, &j->J, mode, ctx->stream, true);
   }
   return job_launch(ctx, &j->J, mode, ctx->stream, false);

@@ -321,3 +321,28 @@ def test_tune_starts_from_the_jobs_own_layout(tmp_path):
     j2.close()
     c2.close()
     ctx.close()
+
+
+def test_stage_profile_times_only_the_stages_that_launch(ctx):
+    """Per-stage device times: a stage that launches nothing for a job reads
+    zero (its boundary markers go to the stage before), the others are timed."""
+    rng = rng_for(733, 0)
+    F, G = dense_total(rng, 6, 20), dense_total(rng, 5, 20)
+    H = small_random(rng, 3, 4, 20)
+    H[3] = [0, -2, 1, 0, 0]  # leading coefficient x (x - 2): the points start at x = 1
+    K = small_random(rng, 2, 3, 20)
+    for probs, newton in (([(F, G, "y")], False), ([(H, K, "y")], True)):
+        job = ctx.job(probs)
+        job.run("staged")
+        want = job.results()
+        ctx.profile_enable(True)
+        for _ in range(3):
+            job.run("staged")
+        stages, runs = ctx.profile_take()
+        ctx.profile_enable(False)
+        assert job.results() == want
+        assert runs == 3
+        for k in ("reduce", "eval_ures", "interp_conv", "interp_stir", "crt"):
+            assert stages[k] > 0.0, (k, stages)
+        assert (stages["interp_newton"] > 0.0) == newton, stages
+        job.close()
