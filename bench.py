@@ -489,8 +489,9 @@ def pair_bench(a):
         t0 = time.perf_counter()
         for s in range(steps):
             jobs[s % len(jobs)].run(mode, graph=graph)
+        t_issue = time.perf_counter() - t0  # host time to enqueue every step
         torch.cuda.synchronize()
-        return time.perf_counter() - t0
+        return time.perf_counter() - t0, t_issue
 
     inflight_lanes = None
     inflight_ms = {}
@@ -503,8 +504,10 @@ def pair_bench(a):
                     print("bench: graph replay differs from the eager run", file=sys.stderr)
                     sys.exit(1)
             for graph in (True, False):
-                t = timed_inflight(jobs, a.pair_steps, a.pair_warmup, graph)
+                t, t_issue = timed_inflight(jobs, a.pair_steps, a.pair_warmup, graph)
                 inflight_ms[f"lanes {lanes}, {'graph' if graph else 'eager'}"] = t / a.pair_steps * 1e3
+                inflight_ms[f"lanes {lanes}, {'graph' if graph else 'eager'}, host enqueue"] = \
+                    t_issue / a.pair_steps * 1e3
                 if best is None or t < best[0]:
                     best = (t, graph, lanes)
         dt, use_graph, inflight_lanes = best

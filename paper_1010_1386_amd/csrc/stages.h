@@ -1898,72 +1898,68 @@ __device__ inline uint32_t wave_sum32(uint32_t v) {
 // Radix conversion of one coefficient (lanes own output limbs t = lane + 64 r):
 //   Z_t = init_t + sum_j v_j tab[j][t]   (96-bit column sums),
 // carries resolved with wave ballots; writes Z mod 2^(32 L_out).
+// Each v_j < 2^32 comes in 16-bit halves -- the caller leaves lo16(v_j) in
+// vbuf[j] and hi16(v_j) in sb[j] (sb is free until the carry phase) -- so that
+// the column sums
+//   A_t = sum_j lo16(v_j) tab[j][t],  B_t = sum_j hi16(v_j) tab[j][t]
+// take one 64-bit multiply-add per term with no carry handling: every term is
+// below 2^48 and at most 512 primes come here, so both sums stay below 2^57.
+// Then Z_t = init_t + A_t + 2^16 B_t, formed once per limb in 96 bits.
 template <int NS>
 __device__ inline void crt_radix(const DevProblem& P, int k, bool valid, const uint32_t* vbuf, const uint32_t* tab,
                                  int tstride, const uint64_t* init, uint32_t* sb, uint32_t* sc) {
   const int lane = threadIdx.x & 63;
   const int np = P.np, L = P.L_out;
-  uint64_t lo[NS];
-  uint32_t hc[NS];
+  // two independent accumulator pairs per limb (short dependency chains)
+  uint64_t A0[NS], B0[NS], A1[NS], B1[NS];
 #pragma unroll
-  for (int r = 0; r < NS; ++r) {
-    lo[r] = init[r];
-    hc[r] = 0u;
-  }
+  for (int r = 0; r < NS; ++r) A0[r] = B0[r] = A1[r] = B1[r] = 0u;
   int j = 0;
-  {
-    // four independent 96-bit accumulators per limb (short dependency chains),
-    // added together afterwards
-    uint64_t lo4[NS][3];
-    uint32_t hc4[NS][3];
-#pragma unroll
-    for (int r = 0; r < NS; ++r)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        lo4[r][a] = 0u;
-        hc4[r][a] = 0u;
-      }
-    for (; j + 4 <= np; j += 4) {
-      const uint32_t v0 = vbuf[j], v1 = vbuf[j + 1], v2 = vbuf[j + 2], v3 = vbuf[j + 3];
-      const uint32_t* p0 = tab + static_cast<size_t>(j) * tstride;
-#pragma unroll
-      for (int r = 0; r < NS; ++r) {
-        const int t = lane + 64 * r;
-        if (t < L) {
-          const uint32_t w0 = p0[t], w1 = p0[tstride + t], w2 = p0[2 * tstride + t], w3 = p0[3 * tstride + t];
-          const uint64_t q0 = static_cast<uint64_t>(v0) * w0, q1 = static_cast<uint64_t>(v1) * w1;
-          const uint64_t q2 = static_cast<uint64_t>(v2) * w2, q3 = static_cast<uint64_t>(v3) * w3;
-          lo[r] += q0;
-          hc[r] += (lo[r] < q0) ? 1u : 0u;
-          lo4[r][0] += q1;
-          hc4[r][0] += (lo4[r][0] < q1) ? 1u : 0u;
-          lo4[r][1] += q2;
-          hc4[r][1] += (lo4[r][1] < q2) ? 1u : 0u;
-          lo4[r][2] += q3;
-          hc4[r][2] += (lo4[r][2] < q3) ? 1u : 0u;
-        }
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < NS; ++r)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        lo[r] += lo4[r][a];
-        hc[r] += hc4[r][a] + ((lo[r] < lo4[r][a]) ? 1u : 0u);
-      }
-  }
-  for (; j < np; ++j) {
-    const uint32_t vj = vbuf[j];
-    const uint32_t* pl = tab + static_cast<size_t>(j) * tstride;
+  for (; j + 4 <= np; j += 4) {
+    const uint64_t l0 = vbuf[j], l1 = vbuf[j + 1], l2 = vbuf[j + 2], l3 = vbuf[j + 3];
+    const uint64_t h0 = sb[j], h1 = sb[j + 1], h2 = sb[j + 2], h3 = sb[j + 3];
+    const uint32_t* p0 = tab + static_cast<size_t>(j) * tstride;
 #pragma unroll
     for (int r = 0; r < NS; ++r) {
       const int t = lane + 64 * r;
       if (t < L) {
-        const uint64_t prod = static_cast<uint64_t>(vj) * pl[t];
-        lo[r] += prod;
-        hc[r] += (lo[r] < prod) ? 1u : 0u;
+        const uint64_t w0 = p0[t], w1 = p0[tstride + t], w2 = p0[2 * tstride + t], w3 = p0[3 * tstride + t];
+        A0[r] += l0 * w0;
+        B0[r] += h0 * w0;
+        A1[r] += l1 * w1;
+        B1[r] += h1 * w1;
+        A0[r] += l2 * w2;
+        B0[r] += h2 * w2;
+        A1[r] += l3 * w3;
+        B1[r] += h3 * w3;
       }
     }
+  }
+  for (; j < np; ++j) {
+    const uint64_t l0 = vbuf[j], h0 = sb[j];
+    const uint32_t* p0 = tab + static_cast<size_t>(j) * tstride;
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      const int t = lane + 64 * r;
+      if (t < L) {
+        const uint64_t w0 = p0[t];
+        A0[r] += l0 * w0;
+        B0[r] += h0 * w0;
+      }
+    }
+  }
+  uint64_t lo[NS];
+  uint32_t hc[NS];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    const uint64_t A = A0[r] + A1[r], B = B0[r] + B1[r];  // each < 2^58
+    uint64_t z = init[r] + A;
+    uint32_t h = z < A ? 1u : 0u;
+    const uint64_t Bs = B << 16;
+    z += Bs;
+    h += (z < Bs ? 1u : 0u) + static_cast<uint32_t>(B >> 48);
+    lo[r] = z;
+    hc[r] = h;
   }
   // limb t receives lo32(S_t) + hi32(S_{t-1}) + top32(S_{t-2})
   WaveSync sync;
@@ -2055,7 +2051,8 @@ __device__ inline void crt_one(const DevProblem& P, int k_raw, const uint32_t* m
       u[r] = ures[i];
       const uint32_t p = cp[i];
       const uint32_t t = mmul(u[r], cw[i], p, cpinv[i]);
-      vbuf[i] = t;
+      vbuf[i] = t & 0xFFFFu;  // the halves crt_radix multiplies with
+      sb[i] = t >> 16;
       const uint64_t f = static_cast<uint64_t>(t) * crhi[i] + __umulhi(t, crlo[i]);
       fa += static_cast<uint32_t>(f) & 0xFFFFu;
       fb += static_cast<uint32_t>(f >> 16);
@@ -2089,7 +2086,10 @@ __device__ inline void crt_one(const DevProblem& P, int k_raw, const uint32_t* m
       const uint32_t im = i0 < np ? cinvm[i0] : 0u;
       const uint32_t vloc = mmul(msubm(u[r], acc[r], pr), im, pr, pir);
       const uint32_t vj = __builtin_amdgcn_readlane(vloc, jj);
-      if (lane == 0) vbuf[j] = vj;
+      if (lane == 0) {
+        vbuf[j] = vj & 0xFFFFu;
+        sb[j] = vj >> 16;
+      }
 #pragma unroll
       for (int rr = r; rr < NS; ++rr) {
         const int i = lane + 64 * rr;
@@ -2168,9 +2168,14 @@ __device__ inline void stage_crt(const DevProblem& P, const DevTables& T, const 
       }
     }
     __syncthreads();
+    // two calls rather than one with a selected pointer: with the table in
+    // LDS the compiler then reads it with LDS instructions, not flat loads
     for (int c = 0; c < cpw; ++c) {
       const int local = wave * cpw + c;
-      crt_one<NS>(P, kbase + local, staged_mi ? mis : P.Mi, L, wb, ures + local * np, pconst);
+      if (staged_mi)
+        crt_one<NS>(P, kbase + local, mis, L, wb, ures + local * np, pconst);
+      else
+        crt_one<NS>(P, kbase + local, P.Mi, L, wb, ures + local * np, pconst);
     }
   }
 }
